@@ -1,0 +1,222 @@
+"""Encoder, decoders and locator quantities of the FNT-based RS code (Sec. II-B).
+
+Layout: a codeword block is an int64 array [symbols, lanes...]; every lane is
+an independent codeword (the code is applied to each 16-bit lane of a packet).
+
+Readings of the paper taken here (the paper is terse or garbled at these
+points):
+
+* the root has order n (not n-1): r_n = 3^(65536/n) (Sec. II-B root choice);
+* encoding is e_i = s(r^i) in natural order i = 0..n-1 (Sec. II-B);
+* the decoder uses the first k received positions in ascending order
+  (Sec. II-B, "the first k evaluation points received");
+* step 5 forms the power series S_j = -N'(r^(-j-1)), j = 0..k-1, which is the
+  unscaled evaluation of N'(y) = sum_i n_i y^(z_i) at the inverse roots, and
+  step 6 keeps P(x) = (A(x) S(x)) mod x^k.  P has degree < k and equals
+  A(x) * sum_i n_i/(x - x_i) exactly, so truncating A*S at x^k recovers it.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import poly
+from .field import P, inverse, inverse_array, powers, root
+from .transform import fnt, ifnt
+
+
+def _rows(a) -> np.ndarray:
+    return np.asarray(a, dtype=np.int64) % P
+
+
+def _check_nk(n: int, k: int) -> None:
+    if n < 1 or n > 65536 or (n & (n - 1)):
+        raise ValueError(f"n must be a power of two in [1, 65536], got {n}")
+    if k < 1 or k > n:
+        raise ValueError(f"need 1 <= k <= n, got k={k}, n={n}")
+
+
+def eval_points(n: int, positions) -> np.ndarray:
+    """x_i = r^(z_i) for received positions z_i (Sec. II-B, x_i = r^(z_i))."""
+    r = root(n)
+    tab = powers(r, n)
+    return tab[np.asarray(positions, dtype=np.int64)]
+
+
+# ---------------------------------------------------------------------------
+# Encoder (Sec. II-B): e = FNT_n(s_0..s_(k-1), 0..0), i.e. e_i = s(r^i).
+# ---------------------------------------------------------------------------
+
+def encode(s, n: int, rows=None) -> np.ndarray:
+    """e_i = s(r^i) = sum_{j<k} s_j r^(i j), by Horner's rule in x = r^i.
+
+    This is the Vandermonde / generator-matrix view of the encoder: the first k
+    rows of the FNT matrix form the generator matrix (Sec. II-A), and the
+    encoder applies the FNT to the zero-padded source (Sec. II-B).  ``rows``
+    restricts the output to the listed indices i (for sampled checks).
+    """
+    s = _rows(s)
+    k = s.shape[0]
+    _check_nk(n, k)
+    r = root(n)
+    idx = np.arange(n, dtype=np.int64) if rows is None else np.asarray(rows, dtype=np.int64)
+    x = powers(r, n)[idx].reshape((idx.size,) + (1,) * (s.ndim - 1))
+    acc = np.zeros((idx.size,) + s.shape[1:], dtype=np.int64)
+    for j in range(k - 1, -1, -1):
+        acc = (acc * x + s[j]) % P
+    return acc
+
+
+# ---------------------------------------------------------------------------
+# Decoders.  Both solve sum_{j<k} s_j x_i^j = v_i for the received points.
+# ---------------------------------------------------------------------------
+
+def _first_k(positions, k: int, n: int) -> np.ndarray:
+    z = np.asarray(positions, dtype=np.int64)
+    if z.size < k:
+        raise ValueError(f"need at least k={k} received positions, got {z.size}")
+    z = np.sort(z)
+    if np.any(np.diff(z) == 0) or z[0] < 0 or z[-1] >= n:
+        raise ValueError("positions must be distinct and in [0, n)")
+    return z[:k]
+
+
+def decode_gauss(n: int, positions, v) -> np.ndarray:
+    """Solve the k x k Vandermonde system V_R s = v by Gauss-Jordan elimination mod p.
+
+    V_R[i][j] = x_i^j is the generator matrix restricted to the received rows;
+    it is invertible because the x_i are pairwise distinct (Sec. II-A), which
+    is the MDS property.  Pivot: the first nonzero entry of the column.
+    Cost k^3, meant for small k.
+    """
+    v = _rows(v)
+    k = v.shape[0]
+    z = _first_k(positions, k, n)
+    x = eval_points(n, z)
+    M = np.empty((k, k), dtype=np.int64)
+    M[:, 0] = 1
+    for j in range(1, k):
+        M[:, j] = (M[:, j - 1] * x) % P
+    B = v.reshape(k, -1).copy()
+    for c in range(k):
+        nz = np.nonzero(M[c:, c])[0]
+        piv = c + int(nz[0])
+        if piv != c:
+            M[[c, piv]] = M[[piv, c]]
+            B[[c, piv]] = B[[piv, c]]
+        inv = inverse(int(M[c, c]))
+        M[c] = (M[c] * inv) % P
+        B[c] = (B[c] * inv) % P
+        f = M[:, c].copy()
+        f[c] = 0
+        M = (M - f[:, None] * M[c][None, :]) % P
+        B = (B - f[:, None] * B[c][None, :]) % P
+    return B.reshape(v.shape)
+
+
+def lagrange_denominators(x) -> np.ndarray:
+    """d_i = prod_{j != i} (x_i - x_j), the Lagrange denominators (Sec. II-B)."""
+    x = np.asarray(x, dtype=np.int64) % P
+    k = x.size
+    d = np.ones(k, dtype=np.int64)
+    for j in range(k):
+        f = (x - x[j]) % P
+        f[j] = 1
+        d = (d * f) % P
+    return d
+
+
+def decode_lagrange(n: int, positions, v) -> np.ndarray:
+    """P(x) = sum_i v_i prod_{j != i} (x - x_j)/(x_i - x_j) (Sec. II-B, Lagrange form).
+
+    The numerator prod_{j != i}(x - x_j) = A(x)/(x - x_i) is obtained by
+    synthetic division of A(x) = prod_j (x - x_j); coefficient m of P is
+    sum_i (v_i / d_i) q_i[m].  Quadratic in k per lane.
+    """
+    v = _rows(v)
+    k = v.shape[0]
+    z = _first_k(positions, k, n)
+    x = eval_points(n, z)
+    A = poly.from_roots(x)                      # degree k, monic
+    c = (inverse_array(lagrange_denominators(x))[:, None] * v.reshape(k, -1)) % P
+    out = np.zeros_like(c)
+    q = np.zeros(k, dtype=np.int64)             # q_i[m] for the current m, all i
+    for m in range(k - 1, -1, -1):
+        # A(x)/(x - x_i): q[k-1] = a_k, q[m-1] = a_m + x_i q[m]
+        q = (A[m + 1] + x * q) % P
+        out[m] = (q @ c) % P
+    return out.reshape(v.shape)
+
+
+def decode_erasure_free(e) -> np.ndarray:
+    """All n symbols received: s = first k of FNT_n^(-1)(e) (Sec. II-B)."""
+    return ifnt(e)
+
+
+# ---------------------------------------------------------------------------
+# Locator quantities and the six-step interpolation (Sec. II-B, steps 1-6).
+# ---------------------------------------------------------------------------
+
+def locator(n: int, positions, with_w: bool = True) -> dict:
+    """Quantities that depend only on the received positions (steps 1-3).
+
+    A     -- A(x) = prod_i (x - x_i), k+1 coefficients, monic (step 1)
+    dA    -- A'(x), k coefficients (step 2)
+    w     -- w_i = 1 / A'(x_i) = 1 / prod_{j != i}(x_i - x_j) (step 3 and
+             the identity A_i(x_i) = A'(x_i))
+    Ahat  -- FNT_(2k) of (a_0 .. a_(k-1), 0 .. 0), used for the low product
+             of step 6 (requires 2k <= 65536)
+    """
+    z = np.asarray(positions, dtype=np.int64)
+    k = z.size
+    x = eval_points(n, z)
+    A = poly.from_roots(x)
+    dA = poly.derivative(A)
+    out = {"x": x, "A": A, "dA": dA}
+    if with_w:
+        out["w"] = inverse_array(lagrange_denominators(x))
+    if 2 * k <= 65536:
+        pad = np.zeros(2 * k, dtype=np.int64)
+        pad[:k] = A[:k]
+        out["Ahat"] = fnt(pad)
+    return out
+
+
+def step5_series(n: int, positions, nvals, count: int) -> np.ndarray:
+    """S_j = -N'(r^(-j-1)), j < count, with N'(y) = sum_i n_i y^(z_i) (Sec. II-B, step 5).
+
+    This is the power series of sum_i n_i / (x - x_i) modulo x^count, written
+    as one evaluation of N' per coefficient.
+    """
+    z = np.asarray(positions, dtype=np.int64)
+    nv = _rows(nvals).reshape(z.size, -1)
+    rinv = inverse(root(n))
+    tab = powers(rinv, n)
+    j = np.arange(1, count + 1, dtype=np.int64)
+    E = (j[:, None] * z[None, :]) % n           # exponent of r^(-1)
+    out = np.zeros((count, nv.shape[1]), dtype=np.int64)
+    for c0 in range(0, count, 512):
+        blk = tab[E[c0:c0 + 512]]               # [rows, k]
+        out[c0:c0 + 512] = (P - (blk @ nv) % P) % P
+    return out.reshape((count,) + np.asarray(nvals).shape[1:])
+
+
+def decode_six_step(n: int, positions, v) -> np.ndarray:
+    """The interpolation of Sec. II-B in the paper's six steps, quadratic building blocks.
+
+    1. A(x) = prod (x - x_i);  2. A'(x);  3. A'(x_i);  4. n_i = v_i / A'(x_i);
+    5. S(x) = sum_i n_i/(x - x_i) mod x^k = -sum_j N'(r^(-j-1)) x^j;
+    6. P(x) = A(x) S(x) truncated to degree < k.
+    """
+    v = _rows(v)
+    k = v.shape[0]
+    z = _first_k(positions, k, n)
+    x = eval_points(n, z)
+    A = poly.from_roots(x)                                   # step 1
+    dA = poly.derivative(A)                                  # step 2
+    dAx = poly.evaluate(dA, x)                               # step 3
+    nvals = (inverse_array(dAx)[:, None] * v.reshape(k, -1)) % P   # step 4
+    S = step5_series(n, z, nvals, k)                         # step 5
+    out = np.zeros_like(S)
+    for i in range(k):                                       # step 6, mod x^k
+        out[i:] = (out[i:] + A[i] * S[: k - i]) % P
+    return out.reshape(v.shape)

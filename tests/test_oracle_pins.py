@@ -1,0 +1,341 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test names the passage of Soro & Lacan, "FNT-based Reed-Solomon Erasure
+Codes", that fixes the checked fact.  The pins are chosen so that a plausible
+slip in the oracle (a dropped term, a wrong sign or index, a transposed
+operand, a wrong root) breaks at least one of them:
+
+P1  3 has multiplicative order 2^16 (Sec. II-A example)            -- brute force
+P2  r_n is a primitive n-th root and r_n = r_(2n)^2 (Sec. II-B)    -- brute force
+P3  inverse transform of the transform is the identity (Sec. II-A) -- invariant
+P3b divide and conquer equals the definition (Sec. II-A)           -- two algorithms
+P4  transform product equals the schoolbook product (Sec. II-B)    -- numpy.convolve
+P5  encoder equals the transform of the zero-padded source         -- two algorithms
+P6  every k-subset decodes (MDS, Sec. I / II-A)                    -- brute force
+P7  A'(x_i) = prod_{j!=i}(x_i - x_j) (Sec. II-B)                   -- two formulas
+P8  sum_i x_i^m / A'(x_i) = [m = k-1]                              -- Lagrange identity
+P9  A_R(x) * Lambda_E(x) = x^n - 1                                  -- all n-th roots
+P10 coset pattern: A = x^k - r^(ck) and decode = twisted IDFT_k     -- closed form
+P11 k = n, k = 1 and unit vectors (Sec. II-B)                       -- closed forms
+P12 hand-worked n = 4 example containing the residue 65536          -- by hand
+P13 linearity over GF(p)                                            -- definition
+P14 decode(encode(s) restricted to R) = s, three decoders           -- uniqueness
+P15 (A * S mod x^n) has zero coefficients k .. n-1 (Sec. II-B, step 5/6)
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+from oracle import codec, field, poly, transform
+from paper_0907_1788_amd import synth
+
+P = 65537
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+# --------------------------------------------------------------------- P1, P2
+def test_p1_three_is_primitive_root():
+    """Sec. II-A: 3^65536 = 1 and 3^i != 1 for 0 < i < 65536."""
+    x, first_one = 1, None
+    for i in range(1, 65537):
+        x = (x * 3) % P
+        if x == 1:
+            first_one = i
+            break
+    assert first_one == 65536
+    # 3^(2^15) = -1 forces the order to be exactly 2^16 (it divides 2^16 and is not 2^15)
+    c = 3
+    for _ in range(15):
+        c = c * c % P
+    assert c == P - 1
+    assert field.order(3) == 65536
+
+
+def test_p2_roots_table():
+    """Sec. II-B: r = 3^(2^(16-i)) is a root of order n = 2^i; stored table matches."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "roots.txt")) if not l.startswith("#")]
+    assert len(rows) == 17
+    prev = None
+    for i, (n, r, rinv, ninv) in enumerate(rows):
+        n, r, rinv, ninv = int(n), int(r), int(rinv), int(ninv)
+        assert n == 1 << i
+        assert field.root(n) == r
+        # order of r is exactly n, by iterated multiplication (not by pow)
+        x, e = r, 1
+        while x != 1:
+            x = x * r % P
+            e += 1
+        assert e == n
+        assert r * rinv % P == 1 and n * ninv % P == 1
+        if prev is not None:
+            assert r * r % P == prev       # r_(2n)^2 = r_n
+        prev = r
+    # the small roots are signed powers of two, since 2^16 = -1 (mod p)
+    tab = {int(a[0]): int(a[1]) for a in rows}
+    assert tab[2] == P - 1
+    assert tab[4] in (256, P - 256)
+    assert tab[8] in {pow(2, e, P) for e in range(32)}
+    assert tab[16] in {pow(2, e, P) for e in range(32)}
+    assert tab[32] in {pow(2, e, P) for e in range(32)}
+
+
+def test_inverse_array_exhaustive():
+    a = np.arange(1, P, dtype=np.int64)
+    assert np.all(a * field.inverse_array(a) % P == 1)
+
+
+# --------------------------------------------------------------------- P3
+@pytest.mark.parametrize("logn", range(0, 17))
+def test_p3_inverse_of_transform_is_identity(logn):
+    n = 1 << logn
+    lanes = 3 if n <= 4096 else 1
+    a = synth.residues(100 + logn, (n, lanes)).astype(np.int64)
+    A = transform.fnt(a)
+    assert np.array_equal(transform.ifnt(A), a)
+
+
+@pytest.mark.parametrize("logn", range(0, 10))
+def test_p3b_divide_and_conquer_equals_definition(logn):
+    n = 1 << logn
+    a = synth.residues(200 + logn, (n, 4)).astype(np.int64)
+    assert np.array_equal(transform.fnt(a), transform.dft(a))
+    assert np.array_equal(transform.idft(transform.dft(a)), a)
+
+
+def test_p3c_transform_of_delta_and_constant():
+    """DFT of a unit impulse at i is (r^(i j))_j; DFT of the all-ones vector is n e_0."""
+    n = 64
+    r = field.root(n)
+    for i in (0, 1, 5, 63):
+        d = np.zeros(n, dtype=np.int64)
+        d[i] = 1
+        assert np.array_equal(transform.fnt(d), np.array([pow(r, i * j, P) for j in range(n)]))
+    ones = np.ones(n, dtype=np.int64)
+    exp = np.zeros(n, dtype=np.int64)
+    exp[0] = n
+    assert np.array_equal(transform.fnt(ones), exp)
+
+
+# --------------------------------------------------------------------- P4
+@pytest.mark.parametrize("la,lb", [(1, 1), (3, 5), (17, 32), (64, 64), (100, 27)])
+def test_p4_convolution_theorem(la, lb):
+    """Sec. II-B: a product costs three transforms; it equals the schoolbook product."""
+    rng = np.random.default_rng(la * 1000 + lb)
+    a = rng.integers(0, P, la)
+    b = rng.integers(0, P, lb)
+    a[0] = P - 1
+    ref = np.convolve(a.astype(object), b.astype(object))
+    ref = np.array([int(x) % P for x in ref], dtype=np.int64)
+    assert np.array_equal(poly.mul(a, b), ref)
+    m = 1
+    while m < la + lb - 1:
+        m *= 2
+    pa = np.zeros(m, dtype=np.int64)
+    pb = np.zeros(m, dtype=np.int64)
+    pa[:la], pb[:lb] = a, b
+    prod = transform.ifnt(transform.fnt(pa) * transform.fnt(pb) % P)
+    assert np.array_equal(prod[: la + lb - 1], ref)
+    assert not np.any(prod[la + lb - 1:])
+
+
+# --------------------------------------------------------------------- P5
+@pytest.mark.parametrize("n,k", [(2, 1), (4, 2), (8, 8), (64, 16), (512, 256), (1024, 1)])
+def test_p5_encoder_is_transform_of_padded_source(n, k):
+    """Sec. II-B: e = FNT_n(s_0..s_(k-1), 0..0)."""
+    s = synth.residues(300 + n + k, (k, 5)).astype(np.int64)
+    pad = np.zeros((n, 5), dtype=np.int64)
+    pad[:k] = s
+    assert np.array_equal(codec.encode(s, n), transform.fnt(pad))
+    rows = np.array([0, n - 1, n // 2])
+    assert np.array_equal(codec.encode(s, n, rows=rows), transform.fnt(pad)[rows])
+
+
+# --------------------------------------------------------------------- P6
+@pytest.mark.parametrize("n,k", [(8, 3), (8, 4), (16, 4), (16, 8)])
+def test_p6_mds_every_subset(n, k):
+    """Sec. I/II-A: any k of the n encoded symbols recover the source."""
+    s = synth.residues(400 + n * 100 + k, (k, 2)).astype(np.int64)
+    e = codec.encode(s, n)
+    count = 0
+    for sub in itertools.combinations(range(n), k):
+        z = np.array(sub)
+        assert np.array_equal(codec.decode_gauss(n, z, e[z]), s)
+        count += 1
+    assert count == len(list(itertools.combinations(range(n), k)))
+
+
+def test_p6_lagrange_and_six_step_on_subsets():
+    n, k = 16, 8
+    s = synth.residues(411, (k, 3)).astype(np.int64)
+    e = codec.encode(s, n)
+    for sub in list(itertools.combinations(range(n), k))[::97]:
+        z = np.array(sub)
+        assert np.array_equal(codec.decode_lagrange(n, z, e[z]), s)
+        assert np.array_equal(codec.decode_six_step(n, z, e[z]), s)
+
+
+# --------------------------------------------------------------------- P7-P10
+@pytest.mark.parametrize("n,k,seed", [(16, 8, 1), (64, 16, 2), (256, 128, 3), (512, 256, 4)])
+def test_p7_derivative_at_points_is_product(n, k, seed):
+    z = synth.received_positions(seed, n, k)
+    loc = codec.locator(n, z)
+    x = loc["x"]
+    direct = np.array([np.prod([(xi - xj) % P for xj in x if xj != xi], dtype=object) % P
+                       for xi in x[:8]], dtype=np.int64)
+    assert np.array_equal(poly.evaluate(loc["dA"], x[:8]), direct)
+    assert np.array_equal(loc["w"] * poly.evaluate(loc["dA"], x) % P, np.ones(k, dtype=np.int64))
+    assert loc["A"][k] == 1 and np.all(poly.evaluate(loc["A"], x) == 0)
+
+
+@pytest.mark.parametrize("n,k,seed", [(16, 8, 5), (128, 32, 6), (1024, 512, 7)])
+def test_p8_weight_moments(n, k, seed):
+    """sum_i x_i^m w_i = [m = k-1]: the interpolant of x^m (m < k) is x^m itself."""
+    z = synth.received_positions(seed, n, k)
+    loc = codec.locator(n, z)
+    x, w = loc["x"], loc["w"]
+    xm = np.ones(k, dtype=np.int64)
+    for m in range(k):
+        val = int((xm * w % P).sum() % P)
+        assert val == (1 if m == k - 1 else 0), m
+        xm = xm * x % P
+
+
+@pytest.mark.parametrize("n,k,seed", [(8, 3, 8), (64, 32, 9), (256, 64, 10)])
+def test_p9_received_times_erased_locator(n, k, seed):
+    z = synth.received_positions(seed, n, k)
+    erased = np.setdiff1d(np.arange(n), z)
+    ar = poly.from_roots(codec.eval_points(n, z))
+    le = poly.from_roots(codec.eval_points(n, erased))
+    prod = poly.mul(ar, le)
+    exp = np.zeros(n + 1, dtype=np.int64)
+    exp[0], exp[n] = P - 1, 1
+    assert np.array_equal(prod, exp)
+
+
+@pytest.mark.parametrize("n,k,c", [(16, 4, 0), (16, 4, 3), (64, 16, 1), (256, 64, 2)])
+def test_p10_coset_pattern(n, k, c):
+    """R = {c + j n/k}: A = x^k - r^(ck), and s_j = r^(-cj) IDFT_k(v)_j with root r^(n/k)."""
+    z = np.array([c + j * (n // k) for j in range(k)])
+    r = field.root(n)
+    loc = codec.locator(n, z)
+    exp = np.zeros(k + 1, dtype=np.int64)
+    exp[0] = (-pow(r, c * k, P)) % P
+    exp[k] = 1
+    assert np.array_equal(loc["A"], exp)
+    s = synth.residues(500 + n + c, (k, 3)).astype(np.int64)
+    v = codec.encode(s, n)[z]
+    rk = pow(r, n // k, P)
+    idft = transform.idft(v, rk)
+    twist = np.array([pow(r, (-c * j) % n, P) for j in range(k)], dtype=np.int64)[:, None]
+    assert np.array_equal(idft * twist % P, s)
+    assert np.array_equal(codec.decode_lagrange(n, z, v), s)
+
+
+# --------------------------------------------------------------------- P11, P12, P13
+def test_p11_special_cases():
+    n = 32
+    r = field.root(n)
+    # k = 1: every encoded symbol equals s_0
+    s0 = np.array([[65536, 7, 0]])
+    assert np.array_equal(codec.encode(s0, n), np.repeat(s0, n, axis=0))
+    # unit source delta_j gives e_i = r^(i j)
+    for j in (0, 1, 7):
+        d = np.zeros((8, 1), dtype=np.int64)
+        d[j] = 1
+        exp = np.array([[pow(r, i * j, P)] for i in range(n)])
+        assert np.array_equal(codec.encode(d, n), exp)
+    # k = n: decoding is the inverse transform (Sec. II-B, erasure-free case)
+    s = synth.residues(601, (n, 2)).astype(np.int64)
+    e = codec.encode(s, n)
+    assert np.array_equal(codec.decode_erasure_free(e), s)
+    assert np.array_equal(codec.decode_lagrange(n, np.arange(n), e), s)
+
+
+def test_p12_hand_worked_example():
+    vals = [int(x) for l in open(os.path.join(GOLDEN, "worked_n4.txt")) if not l.startswith("#")
+            for x in l.split()]
+    r4 = field.root(4)
+    assert r4 * r4 % P == P - 1
+    hand = [(1 - 2) % P, (1 - 2 * r4) % P, (1 + 2) % P, (1 + 2 * r4) % P]
+    assert vals == hand == [65536, 513, 3, 65026]
+    assert list(codec.encode([1, 65535], 4)) == hand
+    # the residue 65536 appears as decoder input and is handled
+    assert list(codec.decode_gauss(4, [0, 1], np.array(vals)[[0, 1]])) == [1, 65535]
+    assert list(codec.decode_lagrange(4, [0, 3], np.array(vals)[[0, 3]])) == [1, 65535]
+
+
+def test_p13_linearity():
+    n, k = 64, 16
+    a = synth.residues(701, (k, 2)).astype(np.int64)
+    b = synth.residues(702, (k, 2)).astype(np.int64)
+    c = 12345
+    assert np.array_equal(codec.encode((a + c * b) % P, n),
+                          (codec.encode(a, n) + c * codec.encode(b, n)) % P)
+    z = synth.received_positions(703, n, k)
+    va, vb = codec.encode(a, n)[z], codec.encode(b, n)[z]
+    assert np.array_equal(codec.decode_lagrange(n, z, (va + c * vb) % P),
+                          (codec.decode_lagrange(n, z, va) + c * codec.decode_lagrange(n, z, vb)) % P)
+
+
+# --------------------------------------------------------------------- P14, P15
+@pytest.mark.parametrize("n,k,seed", [(64, 32, 11), (256, 64, 12), (512, 256, 13), (1024, 512, 14)])
+def test_p14_roundtrip_three_decoders(n, k, seed):
+    s = synth.source(seed, 1, k, 4)[0].astype(np.int64)
+    e = codec.encode(s, n)
+    for z in (synth.received_positions(seed + 1, n, k), synth.erased_first_k(n, k)):
+        v = e[z]
+        assert np.array_equal(codec.decode_lagrange(n, z, v), s)
+        assert np.array_equal(codec.decode_six_step(n, z, v), s)
+        if k <= 64:
+            assert np.array_equal(codec.decode_gauss(n, z, v), s)
+
+
+@pytest.mark.parametrize("n,k,seed", [(16, 8, 21), (64, 16, 22), (256, 128, 23)])
+def test_p15_series_times_locator_truncates(n, k, seed):
+    """With S the length-n series of step 5, A*S mod x^n vanishes at degrees k..n-1."""
+    z = synth.received_positions(seed, n, k)
+    loc = codec.locator(n, z)
+    nv = synth.residues(seed, (k,)).astype(np.int64)
+    S = codec.step5_series(n, z, nv, n)
+    prod = poly.mul(loc["A"], S)[:n]
+    assert not np.any(prod[k:])
+    # and the low part is the interpolant through v_i = n_i A'(x_i)
+    v = nv * poly.evaluate(loc["dA"], loc["x"]) % P
+    assert np.array_equal(prod[:k], codec.decode_gauss(n, z, v) if k <= 64 else codec.decode_lagrange(n, z, v))
+
+
+def test_step5_series_is_taylor_expansion():
+    """S_j = -sum_i n_i x_i^(-j-1): the Taylor series of 1/(x - x_i), term by term."""
+    n, k = 32, 5
+    z = synth.received_positions(31, n, k)
+    x = codec.eval_points(n, z)
+    nv = synth.residues(32, (k,)).astype(np.int64)
+    S = codec.step5_series(n, z, nv, 12)
+    for j in range(12):
+        ref = 0
+        for i in range(k):
+            ref = (ref - int(nv[i]) * pow(field.inverse(int(x[i])), j + 1, P)) % P
+        assert S[j] == ref
+
+
+def test_locator_ahat_definition():
+    n, k = 64, 16
+    z = synth.received_positions(41, n, k)
+    loc = codec.locator(n, z)
+    r2k = field.root(2 * k)
+    for m in (0, 1, 17, 31):
+        ref = sum(int(loc["A"][j]) * pow(r2k, j * m, P) for j in range(k)) % P
+        assert loc["Ahat"][m] == ref
+
+
+def test_rejects_bad_arguments():
+    with pytest.raises(ValueError):
+        codec.encode(np.zeros((3, 1)), 6)
+    with pytest.raises(ValueError):
+        codec.encode(np.zeros((9, 1)), 8)
+    with pytest.raises(ValueError):
+        codec.decode_lagrange(8, [0, 1], np.zeros((3, 1)))
+    with pytest.raises(ValueError):
+        codec.decode_lagrange(8, [0, 0, 1], np.zeros((3, 1)))
