@@ -1,0 +1,491 @@
+// libfntrs: host side of the C ABI declared in include/fntrs.h.
+//
+// Validation happens here, synchronously, before anything is enqueued; the
+// coding work itself runs in the kernels of codec_kernels.hpp and
+// locator_kernels.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/fntrs.h"
+#include "codec_kernels.hpp"
+#include "locator_kernels.hpp"
+
+using namespace fntrs;
+
+namespace {
+
+constexpr size_t kDefaultCap = size_t(4) << 30;
+constexpr int kThreads = 256;
+
+bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+int ilog2(uint64_t x) { int r = 0; while ((1ull << r) < x) ++r; return r; }
+
+}  // namespace
+
+struct fntrs_locator_s {
+  uint32_t n = 0, k = 0;
+  int logn = 0, logk = 0;
+  std::vector<uint32_t> positions;   // the k positions used
+  uint64_t key = 0;
+  uint32_t* mem = nullptr;           // one device allocation, views below
+  size_t bytes = 0;
+  uint32_t *pos = nullptr, *wp = nullptr, *ahat_br = nullptr;
+  uint32_t *A = nullptr, *w = nullptr, *ahat = nullptr;
+  hipEvent_t ready = nullptr;        // recorded after the build on its stream
+  int refs = 0;
+  uint64_t last_use = 0;
+};
+
+struct fntrs_ctx {
+  int device = 0;
+  size_t cap = kDefaultCap, used = 0;
+  uint32_t* tw = nullptr;            // tw[e] = 3^e mod p, e < 65536
+  size_t lds_max = 65536;
+  std::mutex mu;
+  std::string err;
+  std::unordered_multimap<uint64_t, fntrs_locator_t*> cache;
+  uint64_t tick = 0;
+};
+
+namespace {
+
+int fail(fntrs_ctx* c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(fntrs_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                              \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(ctx, FNTRS_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));  \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+uint64_t hash_positions(uint32_t n, uint32_t k, const uint32_t* z) {
+  uint64_t h = 0xcbf29ce484222325ull ^ ((uint64_t)n << 32) ^ k;
+  for (uint32_t i = 0; i < k; ++i) {
+    h ^= z[i];
+    h *= 0x100000001b3ull;
+  }
+  return h;
+}
+
+// Lanes per workgroup tile: the widest power of two (<= 32) whose tile of
+// `rows` rows fits the LDS budget.
+int pick_tile(size_t rows, size_t lds_budget) {
+  int t = 32;
+  while (t > 1 && rows * (size_t)t * 4 > lds_budget) t >>= 1;
+  return t;
+}
+
+hipError_t set_lds_attr(const void* fn, size_t bytes) {
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int T>
+hipError_t launch_encode(const EncodeArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
+  (void)set_lds_attr((const void*)k_encode<T>, lds);
+  hipLaunchKernelGGL(k_encode<T>, dim3(blocks), dim3(kThreads), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int T>
+hipError_t launch_decode(const DecodeArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
+  (void)set_lds_attr((const void*)k_decode<T>, lds);
+  hipLaunchKernelGGL(k_decode<T>, dim3(blocks), dim3(kThreads), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t encode_dispatch(int T, const EncodeArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
+  switch (T) {
+    case 1: return launch_encode<1>(a, blocks, lds, s);
+    case 2: return launch_encode<2>(a, blocks, lds, s);
+    case 4: return launch_encode<4>(a, blocks, lds, s);
+    case 8: return launch_encode<8>(a, blocks, lds, s);
+    case 16: return launch_encode<16>(a, blocks, lds, s);
+    default: return launch_encode<32>(a, blocks, lds, s);
+  }
+}
+
+hipError_t decode_dispatch(int T, const DecodeArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
+  switch (T) {
+    case 1: return launch_decode<1>(a, blocks, lds, s);
+    case 2: return launch_decode<2>(a, blocks, lds, s);
+    case 4: return launch_decode<4>(a, blocks, lds, s);
+    case 8: return launch_decode<8>(a, blocks, lds, s);
+    case 16: return launch_decode<16>(a, blocks, lds, s);
+    default: return launch_decode<32>(a, blocks, lds, s);
+  }
+}
+
+bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  auto pa = (uintptr_t)a, pb = (uintptr_t)b;
+  return pa < pb + bbytes && pb < pa + abytes;
+}
+
+size_t span_elems(uint32_t batch, size_t stride, uint32_t rows, size_t ld, uint32_t lanes) {
+  return (size_t)(batch - 1) * stride + (size_t)(rows - 1) * ld + lanes;
+}
+
+// Reads a strided device region back and checks every residue <= 65536.
+int validate_range(fntrs_ctx* c, const uint32_t* p, uint32_t batch, size_t stride, uint32_t rows,
+                   size_t ld, uint32_t lanes, hipStream_t s) {
+  const size_t cnt = span_elems(batch, stride, rows, ld, lanes);
+  std::vector<uint32_t> h(cnt);
+  HIP_TRY(c, hipStreamSynchronize(s));
+  HIP_TRY(c, hipMemcpy(h.data(), p, cnt * 4, hipMemcpyDeviceToHost));
+  for (uint32_t b = 0; b < batch; ++b)
+    for (uint32_t r = 0; r < rows; ++r)
+      for (uint32_t l = 0; l < lanes; ++l) {
+        const uint32_t v = h[b * stride + r * ld + l];
+        if (v > 65536u)
+          return fail(c, FNTRS_E_RANGE, "input residue %u > 65536 at block %u row %u lane %u", v, b, r, l);
+      }
+  return FNTRS_OK;
+}
+
+void free_locator(fntrs_ctx* c, fntrs_locator_t* L) {
+  if (L->ready) (void)hipEventDestroy(L->ready);
+  if (L->mem) {
+    (void)hipFree(L->mem);
+    c->used -= L->bytes;
+  }
+  delete L;
+}
+
+// Evicts unreferenced cached locators, least recently used first, until
+// `need` more bytes fit under the cap.
+bool make_room(fntrs_ctx* c, size_t need) {
+  while (c->used + need > c->cap) {
+    auto victim = c->cache.end();
+    for (auto it = c->cache.begin(); it != c->cache.end(); ++it)
+      if (it->second->refs == 0 && (victim == c->cache.end() || it->second->last_use < victim->second->last_use))
+        victim = it;
+    if (victim == c->cache.end()) return false;
+    fntrs_locator_t* L = victim->second;
+    c->cache.erase(victim);
+    free_locator(c, L);
+  }
+  return true;
+}
+
+int build_locator(fntrs_ctx* c, fntrs_locator_t* L, hipStream_t s) {
+  const uint32_t n = L->n, k = L->k;
+  const int logn = L->logn, logk = L->logk;
+  const size_t k2 = 2ull * k;
+  // device layout: pos[k] wp[k] ahat_br[2k] A[k+1] w[k] ahat[2k] | scratch: t0[k] t1[k] spec[k] vals[max(n,2k)]
+  const size_t state = k + k + k2 + (k + 1) + k + k2;
+  const size_t scratch = 3ull * k + std::max<size_t>(n, k2);
+  L->bytes = (state + scratch) * 4;
+  if (!make_room(c, L->bytes))
+    return fail(c, FNTRS_E_NOMEM, "locator of %zu bytes exceeds the context cap (%zu used of %zu)", L->bytes,
+                c->used, c->cap);
+  hipError_t e = hipMalloc((void**)&L->mem, L->bytes);
+  if (e != hipSuccess) {
+    L->mem = nullptr;
+    return fail(c, FNTRS_E_NOMEM, "hipMalloc(%zu) for locator failed: %s", L->bytes, hipGetErrorString(e));
+  }
+  c->used += L->bytes;
+  uint32_t* p = L->mem;
+  L->pos = p; p += k;
+  L->wp = p; p += k;
+  L->ahat_br = p; p += k2;
+  L->A = p; p += k + 1;
+  L->w = p; p += k;
+  L->ahat = p; p += k2;
+  uint32_t* t0 = p; p += k;
+  uint32_t* t1 = p; p += k;
+  uint32_t* spec = p; p += k;
+  uint32_t* vals = p;
+
+  HIP_TRY(c, hipMemcpyAsync(L->pos, L->positions.data(), k * 4ull, hipMemcpyHostToDevice, s));
+  if (k == n) {
+    // Nothing erased: the decoder is the inverse FNT_n with factor n^-1.
+    const uint32_t ninv = 65537u - (65536u >> logn);
+    hipLaunchKernelGGL(k_loc_fill, dim3((k + 255) / 256), dim3(256), 0, s, L->wp, k, ninv);
+    HIP_TRY(c, hipGetLastError());
+    // A = x^n - 1 for export
+    hipLaunchKernelGGL(k_loc_fill, dim3((k + 256) / 256), dim3(256), 0, s, L->A, k + 1, 0u);
+    hipLaunchKernelGGL(k_loc_fill, dim3(1), dim3(1), 0, s, L->A, 1u, 65536u);
+    hipLaunchKernelGGL(k_loc_fill, dim3(1), dim3(1), 0, s, L->A + k, 1u, 1u);
+    HIP_TRY(c, hipGetLastError());
+  } else {
+    // Step 1: product tree.  Leaves of G points, then FNT products up to degree k.
+    const int G = (int)std::min<uint32_t>(k, 64);
+    hipLaunchKernelGGL(k_loc_leaves, dim3(k / G), dim3(64), 0, s, L->pos, logn, G, c->tw, t0);
+    HIP_TRY(c, hipGetLastError());
+    uint32_t* cur = t0;
+    uint32_t* nxt = t1;
+    for (uint32_t d = G; d < k; d *= 2) {
+      const size_t lds = 2ull * d * 4;
+      (void)set_lds_attr((const void*)k_loc_mul_level, lds);
+      const int nt = (int)std::min<uint32_t>(1024, std::max<uint32_t>(64, d / 2));
+      hipLaunchKernelGGL(k_loc_mul_level, dim3(k / (2 * d)), dim3(nt), lds, s, cur, ilog2(d), c->tw, spec, nxt);
+      HIP_TRY(c, hipGetLastError());
+      std::swap(cur, nxt);
+    }
+    // cur holds a_0..a_(k-1); A = x^k + ...
+    HIP_TRY(c, hipMemcpyAsync(L->A, cur, k * 4ull, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_loc_fill, dim3(1), dim3(1), 0, s, L->A + k, 1u, 1u);
+    HIP_TRY(c, hipGetLastError());
+    // Step 2: A'.
+    hipLaunchKernelGGL(k_loc_derivative, dim3((k + 255) / 256), dim3(256), 0, s, cur, k, spec);
+    HIP_TRY(c, hipGetLastError());
+    // Step 3: A' at every n-th root (n/k twisted FNT_k), then w and wp.
+    const size_t ldsk = (size_t)k * 4;
+    (void)set_lds_attr((const void*)k_loc_eval, ldsk);
+    const int ntk = (int)std::min<uint32_t>(1024, std::max<uint32_t>(64, k / 4));
+    hipLaunchKernelGGL(k_loc_eval, dim3(n / k), dim3(ntk), ldsk, s, spec, logk, logn, c->tw, vals);
+    HIP_TRY(c, hipGetLastError());
+    hipLaunchKernelGGL(k_loc_weights, dim3((k + 255) / 256), dim3(256), 0, s, L->pos, vals, k, logn, c->tw, L->w,
+                       L->wp);
+    HIP_TRY(c, hipGetLastError());
+    // FNT_2k of (a_0..a_(k-1), 0..0): two twisted FNT_k.
+    hipLaunchKernelGGL(k_loc_eval, dim3(2), dim3(ntk), ldsk, s, cur, logk, logk + 1, c->tw, L->ahat);
+    HIP_TRY(c, hipGetLastError());
+    hipLaunchKernelGGL(k_loc_ahat, dim3((k2 + 255) / 256), dim3(256), 0, s, L->ahat, logk + 1, L->ahat_br);
+    HIP_TRY(c, hipGetLastError());
+  }
+  HIP_TRY(c, hipEventCreateWithFlags(&L->ready, hipEventDisableTiming));
+  HIP_TRY(c, hipEventRecord(L->ready, s));
+  return FNTRS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fntrs_version(void) { return "fntrs 0.1 (gfx950)"; }
+
+int fntrs_create(int device, size_t cap, fntrs_ctx** out) {
+  if (!out) return FNTRS_E_INVAL;
+  *out = nullptr;
+  if (device == FNTRS_HOST_ONLY) {
+    auto* c = new fntrs_ctx();
+    c->device = FNTRS_HOST_ONLY;
+    c->cap = cap ? cap : kDefaultCap;
+    c->lds_max = 163840;
+    *out = c;
+    return FNTRS_OK;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return FNTRS_E_DEVICE;
+  if (device < 0 || device >= ndev) return FNTRS_E_INVAL;
+  auto* c = new fntrs_ctx();
+  c->device = device;
+  c->cap = cap ? cap : kDefaultCap;
+  DeviceGuard g(device);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete c; return FNTRS_E_DEVICE; }
+  c->lds_max = prop.sharedMemPerBlock;
+  std::vector<uint32_t> h(65536);
+  uint64_t x = 1;
+  for (int e = 0; e < 65536; ++e) { h[e] = (uint32_t)x; x = x * 3 % 65537; }
+  if (hipMalloc((void**)&c->tw, 65536 * 4) != hipSuccess) { delete c; return FNTRS_E_NOMEM; }
+  c->used += 65536 * 4;
+  if (hipMemcpy(c->tw, h.data(), 65536 * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(c->tw);
+    delete c;
+    return FNTRS_E_DEVICE;
+  }
+  *out = c;
+  return FNTRS_OK;
+}
+
+void fntrs_destroy(fntrs_ctx* c) {
+  if (!c) return;
+  if (c->device == FNTRS_HOST_ONLY) { delete c; return; }
+  DeviceGuard g(c->device);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : c->cache) free_locator(c, kv.second);
+  c->cache.clear();
+  if (c->tw) (void)hipFree(c->tw);
+  delete c;
+}
+
+const char* fntrs_last_error(const fntrs_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int fntrs_encode(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uint32_t* src, size_t ld_src,
+                 size_t stride_src, uint32_t* dst, size_t ld_dst, size_t stride_dst, uint32_t batch, uint32_t flags,
+                 void* stream) {
+  if (!c) return FNTRS_E_INVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->err.clear();
+  if (!is_pow2(n) || n > 65536) return fail(c, FNTRS_E_INVAL, "n=%u must be a power of two in [1, 65536]", n);
+  if (k < 1 || k > n) return fail(c, FNTRS_E_INVAL, "k=%u must satisfy 1 <= k <= n=%u", k, n);
+  if (lanes < 1 || batch < 1) return fail(c, FNTRS_E_INVAL, "lanes=%u and batch=%u must be >= 1", lanes, batch);
+  if (!src || !dst) return fail(c, FNTRS_E_INVAL, "null src or dst");
+  if (ld_src < lanes || ld_dst < lanes) return fail(c, FNTRS_E_INVAL, "ld_src/ld_dst smaller than lanes");
+  if (batch > 1 && (stride_src < (size_t)(k - 1) * ld_src + lanes || stride_dst < (size_t)(n - 1) * ld_dst + lanes))
+    return fail(c, FNTRS_E_INVAL, "block strides overlap consecutive blocks");
+  if (flags & ~FNTRS_FLAG_VALIDATE) return fail(c, FNTRS_E_INVAL, "unknown flags 0x%x", flags);
+  const size_t sb = span_elems(batch, stride_src, k, ld_src, lanes) * 4;
+  const size_t db = span_elems(batch, stride_dst, n, ld_dst, lanes) * 4;
+  if (ranges_overlap(src, sb, dst, db)) return fail(c, FNTRS_E_INVAL, "src and dst overlap");
+  if (c->device == FNTRS_HOST_ONLY) return fail(c, FNTRS_E_DEVICE, "host-only context: arguments valid, no device");
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  if (flags & FNTRS_FLAG_VALIDATE) {
+    int rc = validate_range(c, src, batch, stride_src, k, ld_src, lanes, s);
+    if (rc) return rc;
+  }
+  EncodeArgs a;
+  a.src = src; a.ld_src = ld_src; a.stride_src = stride_src;
+  a.dst = dst; a.ld_dst = ld_dst; a.stride_dst = stride_dst;
+  a.tw = c->tw; a.n = n; a.k = k; a.lanes = lanes;
+  a.logn = ilog2(n);
+  a.logK = ilog2(k);                     // K = smallest power of two >= k
+  const uint32_t K = 1u << a.logK;
+  const size_t budget = std::min<size_t>(c->lds_max, K >= 8192 ? 131072 : 65536);
+  const int T = pick_tile(K, budget);
+  if ((size_t)K * T * 4 > c->lds_max)
+    return fail(c, FNTRS_E_UNSUPPORTED, "encode with k=%u needs a multi-pass transform (not built)", k);
+  a.tiles = (lanes + T - 1) / T;
+  a.cosets = n / K;
+  const uint64_t blocks = (uint64_t)a.tiles * a.cosets * batch;
+  if (blocks > 0x7fffffffull) return fail(c, FNTRS_E_INVAL, "grid too large");
+  HIP_TRY(c, encode_dispatch(T, a, (uint32_t)blocks, (size_t)K * T * 4, s));
+  return FNTRS_OK;
+}
+
+int fntrs_locator(fntrs_ctx* c, uint32_t n, uint32_t k, const uint32_t* positions, uint32_t npos, void* stream,
+                  fntrs_locator_t** out) {
+  if (!c) return FNTRS_E_INVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->err.clear();
+  if (!out) return fail(c, FNTRS_E_INVAL, "null out");
+  *out = nullptr;
+  if (!is_pow2(n) || n > 65536) return fail(c, FNTRS_E_INVAL, "n=%u must be a power of two in [1, 65536]", n);
+  if (k < 1 || k > n) return fail(c, FNTRS_E_INVAL, "k=%u must satisfy 1 <= k <= n=%u", k, n);
+  if (!positions) return fail(c, FNTRS_E_INVAL, "null positions");
+  if (npos < k) return fail(c, FNTRS_E_TOOFEW, "%u positions received, k=%u needed", npos, k);
+  for (uint32_t i = 0; i < k; ++i) {
+    if (positions[i] >= n) return fail(c, FNTRS_E_POSITIONS, "position %u at index %u is >= n=%u", positions[i], i, n);
+    if (i && positions[i] <= positions[i - 1])
+      return fail(c, FNTRS_E_POSITIONS, "positions must be strictly ascending (index %u)", i);
+  }
+  if (!is_pow2(k)) return fail(c, FNTRS_E_UNSUPPORTED, "decoding needs k a power of two, got %u", k);
+  if (k != n && (size_t)k * 4 > c->lds_max)
+    return fail(c, FNTRS_E_UNSUPPORTED, "locator for k=%u exceeds the on-chip transform size", k);
+  const uint64_t key = hash_positions(n, k, positions);
+  auto range = c->cache.equal_range(key);
+  for (auto it = range.first; it != range.second; ++it) {
+    fntrs_locator_t* L = it->second;
+    if (L->n == n && L->k == k && std::equal(L->positions.begin(), L->positions.end(), positions)) {
+      L->refs++;
+      L->last_use = ++c->tick;
+      *out = L;
+      return FNTRS_OK;
+    }
+  }
+  if (c->device == FNTRS_HOST_ONLY) return fail(c, FNTRS_E_DEVICE, "host-only context: arguments valid, no device");
+  DeviceGuard g(c->device);
+  auto* L = new fntrs_locator_t();
+  L->n = n; L->k = k; L->logn = ilog2(n); L->logk = ilog2(k);
+  L->positions.assign(positions, positions + k);
+  L->key = key;
+  int rc = build_locator(c, L, (hipStream_t)stream);
+  if (rc) {
+    free_locator(c, L);
+    return rc;
+  }
+  L->refs = 1;
+  L->last_use = ++c->tick;
+  c->cache.emplace(key, L);
+  *out = L;
+  return FNTRS_OK;
+}
+
+int fntrs_locator_release(fntrs_ctx* c, fntrs_locator_t* L) {
+  if (!c || !L) return FNTRS_E_INVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (L->refs <= 0) return fail(c, FNTRS_E_INVAL, "locator released more often than acquired");
+  L->refs--;
+  return FNTRS_OK;
+}
+
+int fntrs_locator_export(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t* A, uint32_t* w, uint32_t* ahat) {
+  if (!c || !L) return FNTRS_E_INVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->device == FNTRS_HOST_ONLY) return fail(c, FNTRS_E_DEVICE, "host-only context");
+  DeviceGuard g(c->device);
+  HIP_TRY(c, hipEventSynchronize(L->ready));
+  if (A) HIP_TRY(c, hipMemcpy(A, L->A, (L->k + 1) * 4ull, hipMemcpyDeviceToHost));
+  if (w) HIP_TRY(c, hipMemcpy(w, L->w, L->k * 4ull, hipMemcpyDeviceToHost));
+  if (ahat && L->k != L->n) HIP_TRY(c, hipMemcpy(ahat, L->ahat, 2ull * L->k * 4, hipMemcpyDeviceToHost));
+  return FNTRS_OK;
+}
+
+int fntrs_decode(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, uint32_t flags, const uint32_t* recv,
+                 size_t ld_recv, size_t stride_recv, uint32_t* dst, size_t ld_dst, size_t stride_dst, uint32_t batch,
+                 void* stream) {
+  if (!c) return FNTRS_E_INVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->err.clear();
+  if (!L) return fail(c, FNTRS_E_INVAL, "null locator");
+  if (L->refs <= 0) return fail(c, FNTRS_E_INVAL, "locator was released");
+  if (lanes < 1 || batch < 1) return fail(c, FNTRS_E_INVAL, "lanes=%u and batch=%u must be >= 1", lanes, batch);
+  if (!recv || !dst) return fail(c, FNTRS_E_INVAL, "null recv or dst");
+  if (flags & ~(FNTRS_RECV_FULL | FNTRS_FLAG_VALIDATE)) return fail(c, FNTRS_E_INVAL, "unknown flags 0x%x", flags);
+  const bool full = flags & FNTRS_RECV_FULL;
+  const uint32_t n = L->n, k = L->k;
+  const uint32_t rrows = full ? n : k;
+  if (ld_recv < lanes || ld_dst < lanes) return fail(c, FNTRS_E_INVAL, "ld_recv/ld_dst smaller than lanes");
+  if (batch > 1 && (stride_recv < (size_t)(rrows - 1) * ld_recv + lanes || stride_dst < (size_t)(k - 1) * ld_dst + lanes))
+    return fail(c, FNTRS_E_INVAL, "block strides overlap consecutive blocks");
+  const size_t rb = span_elems(batch, stride_recv, rrows, ld_recv, lanes) * 4;
+  const size_t db = span_elems(batch, stride_dst, k, ld_dst, lanes) * 4;
+  if (ranges_overlap(recv, rb, dst, db)) return fail(c, FNTRS_E_INVAL, "recv and dst overlap");
+  if (c->device == FNTRS_HOST_ONLY) return fail(c, FNTRS_E_DEVICE, "host-only context: arguments valid, no device");
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  if (flags & FNTRS_FLAG_VALIDATE) {
+    int rc = validate_range(c, recv, batch, stride_recv, rrows, ld_recv, lanes, s);
+    if (rc) return rc;
+  }
+  HIP_TRY(c, hipStreamWaitEvent(s, L->ready, 0));
+  DecodeArgs a;
+  a.recv = recv; a.ld_recv = ld_recv; a.stride_recv = stride_recv;
+  a.dst = dst; a.ld_dst = ld_dst; a.stride_dst = stride_dst;
+  a.tw = c->tw; a.pos = L->pos; a.wp = L->wp; a.ahat_br = L->ahat_br;
+  a.n = n; a.k = k; a.lanes = lanes; a.logn = L->logn; a.logk = L->logk;
+  a.full = full ? 1u : 0u;
+  const size_t rows = (k == n) ? n : std::max<size_t>(n, 2ull * k);
+  const size_t budget = std::min<size_t>(c->lds_max, rows >= 8192 ? 131072 : 65536);
+  const int T = pick_tile(rows, budget);
+  if (rows * T * 4 > c->lds_max)
+    return fail(c, FNTRS_E_UNSUPPORTED, "decode with n=%u needs a multi-pass transform (not built)", n);
+  a.tiles = (lanes + T - 1) / T;
+  const uint64_t blocks = (uint64_t)a.tiles * batch;
+  if (blocks > 0x7fffffffull) return fail(c, FNTRS_E_INVAL, "grid too large");
+  HIP_TRY(c, decode_dispatch(T, a, (uint32_t)blocks, rows * T * 4, s));
+  return FNTRS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,234 @@
+"""Python binding of libfntrs (the C ABI in include/fntrs.h).
+
+Argument marshalling only: every step of encoding and decoding runs in the
+HIP library.  Loading fails loudly when the shared object is missing; there
+is no fallback path.
+
+Two layers:
+* ``fntrs_*`` module functions mirror the C entry points one to one and take
+  raw device pointers (ints), strides in uint32 elements and a raw
+  hipStream_t handle (int, 0 = null stream);
+* ``Context`` wraps them for torch tensors of dtype int32 holding residues
+  (torch has no full uint32 arithmetic; residues <= 65536 have the same bit
+  pattern either way).  Tensors are [batch, rows, lanes] (or [rows, lanes])
+  with unit lane stride.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfntrs.so")
+
+FNTRS_OK = 0
+FNTRS_E_INVAL = -1
+FNTRS_E_TOOFEW = -2
+FNTRS_E_POSITIONS = -3
+FNTRS_E_RANGE = -4
+FNTRS_E_NOMEM = -5
+FNTRS_E_DEVICE = -6
+FNTRS_E_UNSUPPORTED = -7
+ERROR_NAMES = {
+    FNTRS_E_INVAL: "FNTRS_E_INVAL", FNTRS_E_TOOFEW: "FNTRS_E_TOOFEW",
+    FNTRS_E_POSITIONS: "FNTRS_E_POSITIONS", FNTRS_E_RANGE: "FNTRS_E_RANGE",
+    FNTRS_E_NOMEM: "FNTRS_E_NOMEM", FNTRS_E_DEVICE: "FNTRS_E_DEVICE",
+    FNTRS_E_UNSUPPORTED: "FNTRS_E_UNSUPPORTED",
+}
+
+FNTRS_RECV_COMPACT = 0
+FNTRS_RECV_FULL = 1
+FNTRS_FLAG_VALIDATE = 2
+
+# every symbol the header declares, with (restype, argtypes)
+_u32, _sz, _vp, _int = ctypes.c_uint32, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int
+_pu32 = ctypes.POINTER(ctypes.c_uint32)
+SIGNATURES = {
+    "fntrs_create": (_int, [_int, _sz, ctypes.POINTER(_vp)]),
+    "fntrs_destroy": (None, [_vp]),
+    "fntrs_last_error": (ctypes.c_char_p, [_vp]),
+    "fntrs_encode": (_int, [_vp, _u32, _u32, _u32, _vp, _sz, _sz, _vp, _sz, _sz, _u32, _u32, _vp]),
+    "fntrs_locator": (_int, [_vp, _u32, _u32, _pu32, _u32, _vp, ctypes.POINTER(_vp)]),
+    "fntrs_locator_release": (_int, [_vp, _vp]),
+    "fntrs_locator_export": (_int, [_vp, _vp, _pu32, _pu32, _pu32]),
+    "fntrs_decode": (_int, [_vp, _vp, _u32, _u32, _vp, _sz, _sz, _vp, _sz, _sz, _u32, _vp]),
+    "fntrs_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+class FntrsError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {message}")
+        self.code = code
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libfntrs.so (built in-tree by ``paper_0907_1788_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_0907_1788_amd.build`")
+        # torch ships its own HIP runtime under the same soname; loading torch
+        # first makes libfntrs bind to that copy, so the process holds one HIP
+        # runtime and torch's device pointers and streams are valid here.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(ctx, rc: int) -> None:
+    if rc != FNTRS_OK:
+        msg = lib().fntrs_last_error(ctx)
+        raise FntrsError(rc, msg.decode() if msg else "")
+
+
+# ------------------------------------------------------------------ raw ABI
+def fntrs_create(device: int = 0, workspace_cap_bytes: int = 0) -> int:
+    out = _vp()
+    rc = lib().fntrs_create(device, workspace_cap_bytes, ctypes.byref(out))
+    if rc != FNTRS_OK:
+        raise FntrsError(rc, f"fntrs_create(device={device}) failed")
+    return out.value
+
+
+def fntrs_destroy(ctx: int) -> None:
+    lib().fntrs_destroy(ctx)
+
+
+def fntrs_last_error(ctx: int) -> str:
+    return lib().fntrs_last_error(ctx).decode()
+
+
+def fntrs_encode(ctx, n, k, lanes, src, ld_src, stride_src, dst, ld_dst, stride_dst, batch, flags=0, stream=0):
+    return lib().fntrs_encode(ctx, n, k, lanes, src, ld_src, stride_src, dst, ld_dst, stride_dst,
+                              batch, flags, stream)
+
+
+def fntrs_locator(ctx, n, k, positions, stream=0):
+    """Returns (rc, handle); positions: host sequence of received positions."""
+    pos = np.ascontiguousarray(np.asarray(positions, dtype=np.uint32))
+    out = _vp()
+    rc = lib().fntrs_locator(ctx, n, k, pos.ctypes.data_as(_pu32), pos.size, stream, ctypes.byref(out))
+    return rc, out.value
+
+
+def fntrs_locator_release(ctx, loc):
+    return lib().fntrs_locator_release(ctx, loc)
+
+
+def fntrs_locator_export(ctx, loc, k):
+    A = np.zeros(k + 1, dtype=np.uint32)
+    w = np.zeros(k, dtype=np.uint32)
+    ahat = np.zeros(2 * k, dtype=np.uint32)
+    rc = lib().fntrs_locator_export(ctx, loc, A.ctypes.data_as(_pu32), w.ctypes.data_as(_pu32),
+                                    ahat.ctypes.data_as(_pu32))
+    return rc, A, w, ahat
+
+
+def fntrs_decode(ctx, loc, lanes, flags, recv, ld_recv, stride_recv, dst, ld_dst, stride_dst, batch, stream=0):
+    return lib().fntrs_decode(ctx, loc, lanes, flags, recv, ld_recv, stride_recv, dst, ld_dst, stride_dst,
+                              batch, stream)
+
+
+def fntrs_version() -> str:
+    return lib().fntrs_version().decode()
+
+
+# ------------------------------------------------------------------ tensor layer
+def _geom(t, rows_expected=None):
+    """(batch, rows, lanes, ld, stride) of a [batch, rows, lanes] or [rows, lanes] tensor."""
+    if t.dim() == 2:
+        t3 = t.unsqueeze(0)
+    elif t.dim() == 3:
+        t3 = t
+    else:
+        raise ValueError("expected a [rows, lanes] or [batch, rows, lanes] tensor")
+    if t3.stride(2) != 1:
+        raise ValueError("lanes must be contiguous (unit stride)")
+    b, r, l = t3.shape
+    if rows_expected is not None and r != rows_expected:
+        raise ValueError(f"expected {rows_expected} rows, got {r}")
+    stride = t3.stride(0) if b > 1 else r * t3.stride(1)
+    return b, r, l, t3.stride(1), stride
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Locator:
+    """A reference to the device-resident state of one erasure pattern."""
+
+    def __init__(self, ctx: "Context", handle: int, n: int, k: int, positions):
+        self.ctx, self.handle, self.n, self.k = ctx, handle, n, k
+        self.positions = np.asarray(positions, dtype=np.uint32)[:k]
+
+    def release(self) -> None:
+        if self.handle:
+            _check(self.ctx.handle, fntrs_locator_release(self.ctx.handle, self.handle))
+            self.handle = None
+
+    def export(self):
+        rc, A, w, ahat = fntrs_locator_export(self.ctx.handle, self.handle, self.k)
+        _check(self.ctx.handle, rc)
+        return A, w, ahat
+
+
+class Context:
+    """Owns an fntrs context on one device."""
+
+    def __init__(self, device: int = 0, workspace_cap_bytes: int = 0):
+        self.device = device
+        self.handle = fntrs_create(device, workspace_cap_bytes)
+
+    def close(self) -> None:
+        if self.handle:
+            fntrs_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def encode(self, src, dst, n: int, flags: int = 0, stream=None) -> None:
+        """dst[b, i, l] = sum_j src[b, j, l] r_n^(i j); src has k rows, dst n rows."""
+        b, k, lanes, ld_s, st_s = _geom(src)
+        b2, _, lanes2, ld_d, st_d = _geom(dst, n)
+        if b2 != b or lanes2 != lanes:
+            raise ValueError("src and dst disagree on batch or lanes")
+        _check(self.handle, fntrs_encode(self.handle, n, k, lanes, src.data_ptr(), ld_s, st_s,
+                                         dst.data_ptr(), ld_d, st_d, b, flags, _stream_handle(stream)))
+
+    def locator(self, n: int, k: int, positions, stream=None) -> Locator:
+        rc, h = fntrs_locator(self.handle, n, k, positions, _stream_handle(stream))
+        _check(self.handle, rc)
+        return Locator(self, h, n, k, positions)
+
+    def decode(self, loc: Locator, recv, dst, flags: int = FNTRS_RECV_COMPACT, stream=None) -> None:
+        """dst [b, k, lanes] <- source recovered from recv ([b, k, lanes] or, FULL, [b, n, lanes])."""
+        rows = loc.n if flags & FNTRS_RECV_FULL else loc.k
+        b, _, lanes, ld_r, st_r = _geom(recv, rows)
+        b2, _, lanes2, ld_d, st_d = _geom(dst, loc.k)
+        if b2 != b or lanes2 != lanes:
+            raise ValueError("recv and dst disagree on batch or lanes")
+        _check(self.handle, fntrs_decode(self.handle, loc.handle, lanes, flags, recv.data_ptr(), ld_r, st_r,
+                                         dst.data_ptr(), ld_d, st_d, b, _stream_handle(stream)))

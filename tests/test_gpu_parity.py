@@ -1,0 +1,216 @@
+"""Bit-exact parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Every comparison is element by element and exact: the code is integer
+arithmetic modulo 65537 and has a unique result (Sec. II-B).  Inputs come
+from the seeded generators shared with the oracle; expected values come from
+the oracle only.  Large configurations are checked on sampled rows / lanes
+that the oracle computes one by one, plus the implementation-free property
+decode(encode(s) restricted to R) == s on every lane.
+"""
+import numpy as np
+import pytest
+
+from oracle import codec
+from paper_0907_1788_amd import fntrs, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+P = 65537
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = fntrs.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a).astype(np.int32)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy().astype(np.int64)
+
+
+def gpu_encode(ctx, src, n, pad=0):
+    """src: numpy [batch, k, lanes]; optional row padding (ld = lanes + pad)."""
+    b, k, lanes = src.shape
+    s = torch.zeros((b, k, lanes + pad), dtype=torch.int32, device="cuda")
+    s[:, :, :lanes] = dev(src)
+    e = torch.full((b, n, lanes + pad), -7, dtype=torch.int32, device="cuda")
+    ctx.encode(s[:, :, :lanes], e[:, :, :lanes], n)
+    torch.cuda.synchronize()
+    out = host(e)
+    if pad:
+        assert np.all(out[:, :, lanes:] == -7), "encode wrote outside its lanes"
+    return out[:, :, :lanes]
+
+
+def gpu_decode(ctx, loc, recv, flags=fntrs.FNTRS_RECV_COMPACT):
+    b, _, lanes = recv.shape
+    d = torch.full((b, loc.k, lanes), -7, dtype=torch.int32, device="cuda")
+    ctx.decode(loc, dev(recv), d, flags)
+    torch.cuda.synchronize()
+    return host(d)
+
+
+# ------------------------------------------------------------------ encode
+ENC_CASES = [
+    (1, 1, 3, 1), (2, 1, 5, 1), (2, 2, 7, 2), (4, 2, 1, 1), (8, 3, 33, 1), (16, 16, 40, 1),
+    (64, 5, 17, 2), (128, 64, 100, 1), (256, 256, 9, 1), (512, 256, 512, 1), (512, 100, 65, 3),
+    (1024, 1, 31, 1), (2048, 1024, 70, 1), (4096, 4096, 5, 1), (8192, 4096, 16, 1),
+    (8192, 8192, 3, 1), (16384, 2048, 4, 1), (32768, 32768, 2, 1),
+]
+
+
+@pytest.mark.parametrize("n,k,lanes,batch", ENC_CASES)
+def test_encode_matches_oracle(ctx, n, k, lanes, batch):
+    say("encode", n, k, lanes, batch)
+    src = synth.residues(1000 + n + k + lanes, (batch, k, lanes))
+    out = gpu_encode(ctx, src, n, pad=3)
+    if n * k * lanes * batch <= 2 ** 28:
+        for b in range(batch):
+            assert np.array_equal(out[b], codec.encode(src[b], n)), b
+    else:
+        rows = np.unique(np.concatenate([[0, 1, n - 1, n // 2], synth.stream(n, 12) % np.uint64(n)]).astype(np.int64))
+        for b in range(batch):
+            assert np.array_equal(out[b][rows], codec.encode(src[b], n, rows=rows)), b
+
+
+def test_encode_all_top_residue(ctx):
+    say("encode all-65536")
+    n, k, lanes = 64, 32, 8
+    src = np.full((1, k, lanes), 65536, dtype=np.uint32)
+    assert np.array_equal(gpu_encode(ctx, src, n)[0], codec.encode(src[0], n))
+
+
+def test_encode_worked_example(ctx):
+    say("encode n=4 worked example")
+    out = gpu_encode(ctx, np.array([[[1], [65535]]], dtype=np.uint32), 4)
+    assert list(out[0, :, 0]) == [65536, 513, 3, 65026]
+
+
+# ------------------------------------------------------------------ locator
+@pytest.mark.parametrize("n,k,seed", [(2, 1, 1), (8, 4, 2), (64, 32, 3), (128, 64, 4), (512, 256, 5),
+                                      (512, 128, 6), (1024, 64, 7), (4096, 1024, 8), (8192, 4096, 9)])
+def test_locator_state_matches_oracle(ctx, n, k, seed):
+    say("locator", n, k, seed)
+    z = synth.received_positions(seed, n, k)
+    loc = ctx.locator(n, k, z)
+    A, w, ahat = loc.export()
+    ref = codec.locator(n, z, with_w=k <= 4096)
+    assert np.array_equal(A.astype(np.int64), ref["A"])
+    if "w" in ref:
+        assert np.array_equal(w.astype(np.int64), ref["w"])
+    assert np.array_equal(ahat.astype(np.int64), ref["Ahat"])
+    loc.release()
+
+
+def test_locator_cache_returns_same_state(ctx):
+    say("locator cache")
+    z = synth.received_positions(77, 256, 64)
+    a = ctx.locator(256, 64, z)
+    b = ctx.locator(256, 64, z)
+    assert a.handle == b.handle
+    c = ctx.locator(256, 64, synth.received_positions(78, 256, 64))
+    assert c.handle != a.handle
+    for x in (a, b, c):
+        x.release()
+
+
+# ------------------------------------------------------------------ decode
+DEC_CASES = [
+    # n, k, lanes, batch, pattern
+    (2, 1, 3, 1, "random"), (4, 2, 5, 1, "random"), (8, 4, 9, 2, "random"), (16, 8, 33, 1, "first"),
+    (64, 32, 40, 1, "random"), (64, 16, 7, 1, "random"), (128, 128, 6, 1, "all"), (256, 128, 65, 2, "random"),
+    (512, 256, 512, 1, "random"), (512, 256, 100, 1, "first"), (512, 128, 17, 1, "random"),
+    (1024, 512, 31, 1, "random"), (2048, 1024, 9, 1, "random"), (4096, 2048, 8, 1, "first"),
+    (8192, 4096, 8, 1, "random"), (8192, 2048, 5, 1, "random"), (16384, 8192, 3, 1, "random"),
+]
+
+
+def pattern(kind, n, k, seed):
+    if kind == "random":
+        return synth.received_positions(seed, n, k)
+    if kind == "first":
+        return synth.erased_first_k(n, k)
+    return np.arange(n, dtype=np.uint32)
+
+
+@pytest.mark.parametrize("n,k,lanes,batch,kind", DEC_CASES)
+def test_decode_matches_oracle(ctx, n, k, lanes, batch, kind):
+    say("decode", n, k, lanes, batch, kind)
+    src = synth.source(2000 + n + k, batch, k, lanes)
+    z = pattern(kind, n, k, 3000 + n + k)
+    e = np.stack([codec.encode(src[b], n) for b in range(batch)]) if n * k * lanes <= 2 ** 27 else None
+    if e is None:
+        e = gpu_encode(ctx, src, n)
+    loc = ctx.locator(n, k, z)
+    got = gpu_decode(ctx, loc, e[:, z, :])
+    assert np.array_equal(got, src.astype(np.int64))                  # P14: every lane
+    got_full = gpu_decode(ctx, loc, e, fntrs.FNTRS_RECV_FULL)
+    assert np.array_equal(got_full, src.astype(np.int64))
+    # oracle decode of arbitrary (non-codeword) received values: exact interpolant
+    rnd = synth.residues(4000 + n, (1, k, min(lanes, 4)))
+    got_rnd = gpu_decode(ctx, loc, rnd)[0]
+    ref = codec.decode_lagrange(n, z, rnd[0]) if k <= 4096 else None
+    if ref is not None:
+        assert np.array_equal(got_rnd, ref)
+    loc.release()
+
+
+def test_decode_top_residue_inputs(ctx):
+    say("decode with 65536 inputs")
+    n, k = 64, 32
+    z = synth.received_positions(91, n, k)
+    recv = np.full((1, k, 4), 65536, dtype=np.uint32)
+    recv[0, ::3, 1] = 0
+    loc = ctx.locator(n, k, z)
+    assert np.array_equal(gpu_decode(ctx, loc, recv)[0], codec.decode_lagrange(n, z, recv[0]))
+    loc.release()
+
+
+def test_decode_gauss_crosscheck(ctx):
+    say("decode vs gauss")
+    n, k = 32, 8
+    z = synth.received_positions(92, n, k)
+    v = synth.residues(93, (1, k, 6))
+    loc = ctx.locator(n, k, z)
+    assert np.array_equal(gpu_decode(ctx, loc, v)[0], codec.decode_gauss(n, z, v[0]))
+    loc.release()
+
+
+def test_batch_composition_is_irrelevant(ctx):
+    """P16: a block decodes to the same result alone and inside a batch."""
+    say("batch composition")
+    n, k, lanes = 1024, 512, 48
+    z = synth.received_positions(94, n, k)
+    v = synth.residues(95, (5, k, lanes))
+    loc = ctx.locator(n, k, z)
+    together = gpu_decode(ctx, loc, v)
+    for b in range(5):
+        assert np.array_equal(gpu_decode(ctx, loc, v[b:b + 1])[0], together[b])
+    again = gpu_decode(ctx, loc, v)
+    assert np.array_equal(again, together)
+    loc.release()
+
+
+def test_validation_with_device(ctx):
+    say("validation with device")
+    rc, _ = fntrs.fntrs_locator(ctx.handle, 16, 4, [1, 2, 2, 5])
+    assert rc == fntrs.FNTRS_E_POSITIONS
+    src = dev(np.full((1, 4, 4), 70000, dtype=np.uint32))
+    dst = torch.zeros((1, 8, 4), dtype=torch.int32, device="cuda")
+    with pytest.raises(fntrs.FntrsError) as ei:
+        ctx.encode(src, dst, 8, flags=fntrs.FNTRS_FLAG_VALIDATE)
+    assert ei.value.code == fntrs.FNTRS_E_RANGE
+    ok = dev(np.full((1, 4, 4), 65536, dtype=np.uint32))
+    ctx.encode(ok, dst, 8, flags=fntrs.FNTRS_FLAG_VALIDATE)
+    torch.cuda.synchronize()
