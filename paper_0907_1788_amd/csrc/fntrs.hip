@@ -23,7 +23,6 @@ using namespace fntrs;
 namespace {
 
 constexpr size_t kDefaultCap = size_t(4) << 30;
-constexpr int kThreads = 256;
 
 bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
 int ilog2(uint64_t x) { int r = 0; while ((1ull << r) < x) ++r; return r; }
@@ -37,7 +36,7 @@ struct fntrs_locator_s {
   uint64_t key = 0;
   uint32_t* mem = nullptr;           // one device allocation, views below
   size_t bytes = 0;
-  uint32_t *pos = nullptr, *wp = nullptr, *ahat_br = nullptr;
+  uint32_t *pos = nullptr, *wfull = nullptr, *ridx = nullptr, *ahat_s = nullptr;
   uint32_t *A = nullptr, *w = nullptr, *ahat = nullptr;
   hipEvent_t ready = nullptr;        // recorded after the build on its stream
   int refs = 0;
@@ -96,10 +95,10 @@ uint64_t hash_positions(uint32_t n, uint32_t k, const uint32_t* z) {
   return h;
 }
 
-// Lanes per workgroup tile: the widest power of two (<= 32) whose tile of
+// Lanes per workgroup tile: the widest power of two (<= 64) whose tile of
 // `rows` rows fits the LDS budget.
 int pick_tile(size_t rows, size_t lds_budget) {
-  int t = 32;
+  int t = 64;
   while (t > 1 && rows * (size_t)t * 4 > lds_budget) t >>= 1;
   return t;
 }
@@ -108,40 +107,62 @@ hipError_t set_lds_attr(const void* fn, size_t bytes) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int T>
-hipError_t launch_encode(const EncodeArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
-  (void)set_lds_attr((const void*)k_encode<T>, lds);
-  hipLaunchKernelGGL(k_encode<T>, dim3(blocks), dim3(kThreads), lds, s, a);
+// Codec tile geometry: T lanes per workgroup, V lanes per thread, G = T/V
+// lane groups, BMAX the largest radix-2^B pass (bounded by registers).
+struct Tile {
+  int T = 1, V = 1, G = 1, bmax = 6;
+};
+
+Tile make_tile(int T) {
+  Tile t;
+  t.T = T;
+  t.V = T >= 4 ? 4 : T;
+  t.G = T / t.V;
+  t.bmax = t.V == 4 ? 4 : (t.V == 2 ? 5 : 6);
+  return t;
+}
+
+// Items of the last pass of a size-2^logm transform must fit one per thread
+// when that pass is synchronised.
+bool last_pass_fits(const Tile& t, int logm) {
+  int bs[8];
+  const int np = plan_passes(logm, pass_bmax(logm, t.G, kCodecThreads, t.bmax), bs);
+  if (np == 0) return true;
+  return ((size_t)t.G << (logm - bs[np - 1])) <= (size_t)kCodecThreads;
+}
+
+template <int V, int BMAX>
+hipError_t launch_encode_v(const EncodeArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
+  (void)set_lds_attr((const void*)k_encode<V, BMAX>, lds);
+  hipLaunchKernelGGL((k_encode<V, BMAX>), dim3(blocks), dim3(kCodecThreads), lds, s, a);
   return hipGetLastError();
 }
 
-template <int T>
-hipError_t launch_decode(const DecodeArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
-  (void)set_lds_attr((const void*)k_decode<T>, lds);
-  hipLaunchKernelGGL(k_decode<T>, dim3(blocks), dim3(kThreads), lds, s, a);
+template <int V, int BMAX>
+hipError_t launch_decode_v(const DecodeArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
+  (void)set_lds_attr((const void*)k_decode<V, BMAX>, lds);
+  hipLaunchKernelGGL((k_decode<V, BMAX>), dim3(blocks), dim3(kCodecThreads), lds, s, a);
   return hipGetLastError();
 }
 
-hipError_t encode_dispatch(int T, const EncodeArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
-  switch (T) {
-    case 1: return launch_encode<1>(a, blocks, lds, s);
-    case 2: return launch_encode<2>(a, blocks, lds, s);
-    case 4: return launch_encode<4>(a, blocks, lds, s);
-    case 8: return launch_encode<8>(a, blocks, lds, s);
-    case 16: return launch_encode<16>(a, blocks, lds, s);
-    default: return launch_encode<32>(a, blocks, lds, s);
+hipError_t encode_dispatch(const Tile& t, const EncodeArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
+  switch (t.V) {
+    case 4: return launch_encode_v<4, 4>(a, blocks, lds, s);
+    case 2: return launch_encode_v<2, 5>(a, blocks, lds, s);
+    default: return launch_encode_v<1, 6>(a, blocks, lds, s);
   }
 }
 
-hipError_t decode_dispatch(int T, const DecodeArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
-  switch (T) {
-    case 1: return launch_decode<1>(a, blocks, lds, s);
-    case 2: return launch_decode<2>(a, blocks, lds, s);
-    case 4: return launch_decode<4>(a, blocks, lds, s);
-    case 8: return launch_decode<8>(a, blocks, lds, s);
-    case 16: return launch_decode<16>(a, blocks, lds, s);
-    default: return launch_decode<32>(a, blocks, lds, s);
+hipError_t decode_dispatch(const Tile& t, const DecodeArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
+  switch (t.V) {
+    case 4: return launch_decode_v<4, 4>(a, blocks, lds, s);
+    case 2: return launch_decode_v<2, 5>(a, blocks, lds, s);
+    default: return launch_decode_v<1, 6>(a, blocks, lds, s);
   }
+}
+
+bool aligned16(const void* p, size_t ld, size_t stride) {
+  return ((uintptr_t)p % 16 == 0) && (ld % 4 == 0) && (stride % 4 == 0);
 }
 
 bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
@@ -199,8 +220,8 @@ int build_locator(fntrs_ctx* c, fntrs_locator_t* L, hipStream_t s) {
   const uint32_t n = L->n, k = L->k;
   const int logn = L->logn, logk = L->logk;
   const size_t k2 = 2ull * k;
-  // device layout: pos[k] wp[k] ahat_br[2k] A[k+1] w[k] ahat[2k] | scratch: t0[k] t1[k] spec[k] vals[max(n,2k)]
-  const size_t state = k + k + k2 + (k + 1) + k + k2;
+  // device layout: pos[k] wfull[n] ridx[n] ahat_s[2k] A[k+1] w[k] ahat[2k] | scratch: t0[k] t1[k] spec[k] vals[max(n,2k)]
+  const size_t state = k + 2ull * n + k2 + (k + 1) + k + k2;
   const size_t scratch = 3ull * k + std::max<size_t>(n, k2);
   L->bytes = (state + scratch) * 4;
   if (!make_room(c, L->bytes))
@@ -214,8 +235,9 @@ int build_locator(fntrs_ctx* c, fntrs_locator_t* L, hipStream_t s) {
   c->used += L->bytes;
   uint32_t* p = L->mem;
   L->pos = p; p += k;
-  L->wp = p; p += k;
-  L->ahat_br = p; p += k2;
+  L->wfull = p; p += n;
+  L->ridx = p; p += n;
+  L->ahat_s = p; p += k2;
   L->A = p; p += k + 1;
   L->w = p; p += k;
   L->ahat = p; p += k2;
@@ -228,7 +250,7 @@ int build_locator(fntrs_ctx* c, fntrs_locator_t* L, hipStream_t s) {
   if (k == n) {
     // Nothing erased: the decoder is the inverse FNT_n with factor n^-1.
     const uint32_t ninv = 65537u - (65536u >> logn);
-    hipLaunchKernelGGL(k_loc_fill, dim3((k + 255) / 256), dim3(256), 0, s, L->wp, k, ninv);
+    hipLaunchKernelGGL(k_loc_identity, dim3((n + 255) / 256), dim3(256), 0, s, L->wfull, L->ridx, n, ninv);
     HIP_TRY(c, hipGetLastError());
     // A = x^n - 1 for export
     hipLaunchKernelGGL(k_loc_fill, dim3((k + 256) / 256), dim3(256), 0, s, L->A, k + 1, 0u);
@@ -257,19 +279,20 @@ int build_locator(fntrs_ctx* c, fntrs_locator_t* L, hipStream_t s) {
     // Step 2: A'.
     hipLaunchKernelGGL(k_loc_derivative, dim3((k + 255) / 256), dim3(256), 0, s, cur, k, spec);
     HIP_TRY(c, hipGetLastError());
-    // Step 3: A' at every n-th root (n/k twisted FNT_k), then w and wp.
+    // Step 3: A' at every n-th root (n/k twisted FNT_k), then the weights.
     const size_t ldsk = (size_t)k * 4;
     (void)set_lds_attr((const void*)k_loc_eval, ldsk);
     const int ntk = (int)std::min<uint32_t>(1024, std::max<uint32_t>(64, k / 4));
     hipLaunchKernelGGL(k_loc_eval, dim3(n / k), dim3(ntk), ldsk, s, spec, logk, logn, c->tw, vals);
     HIP_TRY(c, hipGetLastError());
+    hipLaunchKernelGGL(k_loc_fill, dim3((n + 255) / 256), dim3(256), 0, s, L->wfull, n, 0u);
     hipLaunchKernelGGL(k_loc_weights, dim3((k + 255) / 256), dim3(256), 0, s, L->pos, vals, k, logn, c->tw, L->w,
-                       L->wp);
+                       L->wfull, L->ridx);
     HIP_TRY(c, hipGetLastError());
     // FNT_2k of (a_0..a_(k-1), 0..0): two twisted FNT_k.
     hipLaunchKernelGGL(k_loc_eval, dim3(2), dim3(ntk), ldsk, s, cur, logk, logk + 1, c->tw, L->ahat);
     HIP_TRY(c, hipGetLastError());
-    hipLaunchKernelGGL(k_loc_ahat, dim3((k2 + 255) / 256), dim3(256), 0, s, L->ahat, logk + 1, L->ahat_br);
+    hipLaunchKernelGGL(k_loc_ahat, dim3((k2 + 255) / 256), dim3(256), 0, s, L->ahat, logk + 1, L->ahat_s);
     HIP_TRY(c, hipGetLastError());
   }
   HIP_TRY(c, hipEventCreateWithFlags(&L->ready, hipEventDisableTiming));
@@ -363,14 +386,16 @@ int fntrs_encode(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uin
   a.logK = ilog2(k);                     // K = smallest power of two >= k
   const uint32_t K = 1u << a.logK;
   const size_t budget = std::min<size_t>(c->lds_max, K >= 8192 ? 131072 : 65536);
-  const int T = pick_tile(K, budget);
-  if ((size_t)K * T * 4 > c->lds_max)
+  const Tile tl = make_tile(pick_tile(K, budget));
+  if ((size_t)K * tl.T * 4 > c->lds_max)
     return fail(c, FNTRS_E_UNSUPPORTED, "encode with k=%u needs a multi-pass transform (not built)", k);
-  a.tiles = (lanes + T - 1) / T;
+  a.G = tl.G;
+  a.vec = aligned16(src, ld_src, stride_src) && aligned16(dst, ld_dst, stride_dst);
+  a.tiles = (lanes + tl.T - 1) / tl.T;
   a.cosets = n / K;
   const uint64_t blocks = (uint64_t)a.tiles * a.cosets * batch;
   if (blocks > 0x7fffffffull) return fail(c, FNTRS_E_INVAL, "grid too large");
-  HIP_TRY(c, encode_dispatch(T, a, (uint32_t)blocks, (size_t)K * T * 4, s));
+  HIP_TRY(c, encode_dispatch(tl, a, (uint32_t)blocks, (size_t)K * tl.T * 4, s));
   return FNTRS_OK;
 }
 
@@ -473,18 +498,22 @@ int fntrs_decode(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, uint32_
   DecodeArgs a;
   a.recv = recv; a.ld_recv = ld_recv; a.stride_recv = stride_recv;
   a.dst = dst; a.ld_dst = ld_dst; a.stride_dst = stride_dst;
-  a.tw = c->tw; a.pos = L->pos; a.wp = L->wp; a.ahat_br = L->ahat_br;
+  a.tw = c->tw; a.wfull = L->wfull; a.ridx = L->ridx; a.ahat = L->ahat_s;
   a.n = n; a.k = k; a.lanes = lanes; a.logn = L->logn; a.logk = L->logk;
   a.full = full ? 1u : 0u;
-  const size_t rows = (k == n) ? n : std::max<size_t>(n, 2ull * k);
+  const size_t rows = n;                 // 2k <= n whenever k < n (both powers of two)
   const size_t budget = std::min<size_t>(c->lds_max, rows >= 8192 ? 131072 : 65536);
-  const int T = pick_tile(rows, budget);
-  if (rows * T * 4 > c->lds_max)
+  Tile tl = make_tile(pick_tile(rows, budget));
+  while (tl.T > 1 && (!last_pass_fits(tl, L->logn) || (k != n && !last_pass_fits(tl, L->logk + 1))))
+    tl = make_tile(tl.T / 2);
+  if (rows * tl.T * 4 > c->lds_max || !last_pass_fits(tl, L->logn))
     return fail(c, FNTRS_E_UNSUPPORTED, "decode with n=%u needs a multi-pass transform (not built)", n);
-  a.tiles = (lanes + T - 1) / T;
+  a.G = tl.G;
+  a.vec = aligned16(recv, ld_recv, stride_recv) && aligned16(dst, ld_dst, stride_dst);
+  a.tiles = (lanes + tl.T - 1) / tl.T;
   const uint64_t blocks = (uint64_t)a.tiles * batch;
   if (blocks > 0x7fffffffull) return fail(c, FNTRS_E_INVAL, "grid too large");
-  HIP_TRY(c, decode_dispatch(T, a, (uint32_t)blocks, rows * T * 4, s));
+  HIP_TRY(c, decode_dispatch(tl, a, (uint32_t)blocks, rows * tl.T * 4, s));
   return FNTRS_OK;
 }
 

@@ -102,29 +102,42 @@ __global__ void __launch_bounds__(1024) k_loc_eval(const uint32_t* __restrict__ 
   for (uint32_t m = threadIdx.x; m < K; m += blockDim.x) vals[t + cosets * m] = lds[m];
 }
 
-// Step 3 and the weights of step 4: w_i = 1/A'(x_i) and
-// wp_i = -w_i x_i^(-1) (the sign and shift of step 5 folded in).
+// Step 3 and the weights of step 4: w_i = 1/A'(x_i), and the decoder weight
+// -w_i x_i^(-1) (sign and index shift of step 5 folded in) scattered to the
+// per-position tables: wfull[z_i] = -w_i x_i^(-1), ridx[z_i] = i.  wfull
+// must be zero beforehand so that erased positions read as 0.
 __global__ void k_loc_weights(const uint32_t* __restrict__ pos, const uint32_t* __restrict__ vals,
                               uint32_t k, int logn, const uint32_t* __restrict__ tw,
-                              uint32_t* __restrict__ w, uint32_t* __restrict__ wp) {
+                              uint32_t* __restrict__ w, uint32_t* __restrict__ wfull,
+                              uint32_t* __restrict__ ridx) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= k) return;
   const uint32_t z = pos[i];
   const uint32_t wi = finv(vals[z]);
   const uint32_t xinv = tw[(65536u - ((z << (16 - logn)) & 0xFFFFu)) & 0xFFFFu];
   w[i] = wi;
-  wp[i] = fsub(0u, fmul(wi, xinv));
+  wfull[z] = fsub(0u, fmul(wi, xinv));
+  ridx[z] = i;
 }
 
-// Â for step 6 in bit-reversed order with the inverse-transform factor (2k)^-1.
-__global__ void k_loc_ahat(const uint32_t* __restrict__ ahat, int log2k, uint32_t* __restrict__ ahat_br) {
+// Â for step 6 with the inverse-transform factor (2k)^-1 folded in.
+__global__ void k_loc_ahat(const uint32_t* __restrict__ ahat, int log2k, uint32_t* __restrict__ ahat_s) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (1u << log2k)) return;
   const uint32_t inv = 65537u - (65536u >> log2k);          // (2^log2k)^-1 = -2^(16-log2k)
-  ahat_br[i] = fmul(ahat[bitrev(i, log2k)], inv);
+  ahat_s[i] = fmul(ahat[i], inv);
 }
 
-// Fill n^-1 as the decoder weights when nothing is erased (k = n).
+// Decoder tables when nothing is erased (k = n): weight n^-1, row z.
+__global__ void k_loc_identity(uint32_t* __restrict__ wfull, uint32_t* __restrict__ ridx, uint32_t n,
+                               uint32_t ninv) {
+  const uint32_t z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= n) return;
+  wfull[z] = ninv;
+  ridx[z] = z;
+}
+
+// Fill k words with v.
 __global__ void k_loc_fill(uint32_t* __restrict__ w, uint32_t k, uint32_t v) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < k) w[i] = v;

@@ -133,6 +133,7 @@ DEC_CASES = [
     (512, 256, 512, 1, "random"), (512, 256, 100, 1, "first"), (512, 128, 17, 1, "random"),
     (1024, 512, 31, 1, "random"), (2048, 1024, 9, 1, "random"), (4096, 2048, 8, 1, "first"),
     (8192, 4096, 8, 1, "random"), (8192, 2048, 5, 1, "random"), (16384, 8192, 3, 1, "random"),
+    (16384, 4096, 6, 2, "first"), (32768, 16384, 2, 1, "random"), (32768, 32768, 2, 1, "all"),
 ]
 
 
