@@ -1,20 +1,28 @@
 """Builds libfntrs.so in-tree with hipcc for gfx950.
 
+The library is one host translation unit (fntrs.hip: C ABI, locator,
+runtime-plan kernels) plus one translation unit per transform size for the
+compile-time kernels (ct_inst.hip with -DFNTRS_L=1..15).  They compile in
+parallel into paper_0907_1788_amd/_build/ and link into libfntrs.so.
+
 Usage: python -m paper_0907_1788_amd.build   (or call build()).
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "fntrs.hip")
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "libfntrs.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+SIZES = range(1, 16)
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "-fPIC",
     "--offload-arch=gfx950",
     # keep the compiler from forming packed fp32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -23,15 +31,31 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile the HIP library; returns the path of the shared object."""
-    tmp = OUT + ".tmp"
-    cmd = [HIPCC, *FLAGS, SRC, "-o", tmp]
+def _run(cmd):
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed ({res.returncode}):\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
-    if verbose and res.stderr.strip():
-        print(res.stderr)
+    return res.stderr
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    """Compile every HIP translation unit and link the shared library."""
+    os.makedirs(BUILD, exist_ok=True)
+    units = [(os.path.join(CSRC, "fntrs.hip"), os.path.join(BUILD, "fntrs.o"), [])]
+    for L in SIZES:
+        units.append((os.path.join(CSRC, "ct_inst.hip"), os.path.join(BUILD, f"ct_{L}.o"), [f"-DFNTRS_L={L}"]))
+    jobs = jobs or min(16, os.cpu_count() or 4)
+    # the large sizes take longest: start them first
+    order = sorted(units, key=lambda u: -int(u[2][0].split("=")[1]) if u[2] else 0)
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        futs = [ex.submit(_run, [HIPCC, *FLAGS, *extra, "-c", src, "-o", obj]) for src, obj, extra in order]
+        logs = [f.result() for f in futs]
+    tmp = OUT + ".tmp"
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *[u[1] for u in units], "-o", tmp])
+    if verbose:
+        for l in logs:
+            if l.strip():
+                print(l)
     os.replace(tmp, OUT)
     return OUT
 

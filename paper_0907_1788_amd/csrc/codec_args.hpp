@@ -1,0 +1,67 @@
+// Kernel arguments of the encoder and decoder, and the helpers that move V
+// lanes of one row between global memory and registers.
+#pragma once
+#include "field.hpp"
+
+namespace fntrs {
+
+struct EncodeArgs {
+  const uint32_t* src;
+  uint64_t ld_src, stride_src;
+  uint32_t* dst;
+  uint64_t ld_dst, stride_dst;
+  const uint32_t* tw;        // tw[e] = 3^e
+  const uint32_t* twi;       // twi[e] = 3^-e
+  uint32_t n, k, lanes;
+  int logn, logK;            // transform size K = 2^logK >= k, K <= n
+  uint32_t tiles, cosets;    // lane tiles per block, n / K
+  uint32_t vec;              // src/dst rows are 16-byte aligned (vector access allowed)
+};
+
+// Moves V lanes of one row between global memory and registers; lanes at or
+// beyond `lanes` read as 0 and are not written.
+template <int V>
+__device__ __forceinline__ void gload(const uint32_t* p, uint32_t lane, uint32_t lanes, bool vec,
+                                      uint32_t (&x)[V]) {
+  if constexpr (V == 4) {
+    if (vec && lane + 4 <= lanes) {
+      const uint4 t = *reinterpret_cast<const uint4*>(p);
+      x[0] = t.x; x[1] = t.y; x[2] = t.z; x[3] = t.w;
+      return;
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < V; ++v) x[v] = (lane + v < lanes) ? p[v] : 0u;
+}
+
+template <int V>
+__device__ __forceinline__ void gstore(uint32_t* p, uint32_t lane, uint32_t lanes, bool vec,
+                                       const uint32_t (&x)[V]) {
+  if constexpr (V == 4) {
+    if (vec && lane + 4 <= lanes) {
+      *reinterpret_cast<uint4*>(p) = make_uint4(x[0], x[1], x[2], x[3]);
+      return;
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < V; ++v)
+    if (lane + v < lanes) p[v] = x[v];
+}
+
+struct DecodeArgs {
+  const uint32_t* recv;
+  uint64_t ld_recv, stride_recv;
+  uint32_t* dst;
+  uint64_t ld_dst, stride_dst;
+  const uint32_t* tw;
+  const uint32_t* twi;
+  const uint32_t* wfull;    // per position z < n: decoder weight (0 if z is erased)
+  const uint32_t* ridx;     // per position z < n: row of z in a compact recv
+  const uint32_t* ahat_br;  // FNT_M of A's low part, bit-reversed order, times M^-1
+  uint32_t n, k, lanes;
+  int logn, logk;
+  uint32_t full;            // recv holds n rows indexed by position
+  uint32_t tiles, vec;
+};
+
+}  // namespace fntrs

@@ -1,0 +1,80 @@
+// One transform size of the compile-time kernels; built once per L with
+// -DFNTRS_L=L (see build.py).
+#include "ct_kernels.hpp"
+#include "ct_launch.hpp"
+
+#ifndef FNTRS_L
+#error "FNTRS_L must be defined"
+#endif
+
+namespace fntrs {
+namespace {
+
+template <int L, int T, int NT>
+hipError_t enc_one(const EncodeArgs& a, uint32_t blocks, hipStream_t s) {
+  constexpr size_t lds = ct::Geo<L, T, NT>::LDS_BYTES;
+  static_assert(lds <= 163840, "tile exceeds LDS");
+  (void)hipFuncSetAttribute((const void*)ct::k_enc<L, T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+  hipLaunchKernelGGL((ct::k_enc<L, T, NT>), dim3(blocks), dim3(NT), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int L, int D, int T, int NT>
+hipError_t dec_one(const DecodeArgs& a, uint32_t blocks, hipStream_t s) {
+  constexpr size_t lds = ct::Geo<L, T, NT>::LDS_BYTES;
+  static_assert(lds <= 163840, "tile exceeds LDS");
+  (void)hipFuncSetAttribute((const void*)ct::k_dec<L, D, T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+  hipLaunchKernelGGL((ct::k_dec<L, D, T, NT>), dim3(blocks), dim3(NT), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int L, int T, int NT>
+hipError_t dec_t(int D, const DecodeArgs& a, uint32_t blocks, hipStream_t s) {
+  if (D == -1) return dec_one<L, -1, T, NT>(a, blocks, s);
+  if (D == 0) return dec_one<L, 0, T, NT>(a, blocks, s);
+  if constexpr (L > 1) {
+    if (D == 1) return dec_one<L, 1, T, NT>(a, blocks, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+constexpr CtVariants kVar = ct_variants(FNTRS_L);
+
+template <int I>
+hipError_t enc_pick(CtCfg c, const EncodeArgs& a, uint32_t blocks, hipStream_t s) {
+  if constexpr (I < 4 && kVar.enc[I < 4 ? I : 0].T != 0) {
+    if (c.T == kVar.enc[I].T && c.NT == kVar.enc[I].NT)
+      return enc_one<FNTRS_L, kVar.enc[I].T, kVar.enc[I].NT>(a, blocks, s);
+    return enc_pick<I + 1>(c, a, blocks, s);
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int I>
+hipError_t dec_pick(CtCfg c, int D, const DecodeArgs& a, uint32_t blocks, hipStream_t s) {
+  if constexpr (I < 4 && kVar.dec[I < 4 ? I : 0].T != 0) {
+    if (c.T == kVar.dec[I].T && c.NT == kVar.dec[I].NT)
+      return dec_t<FNTRS_L, kVar.dec[I].T, kVar.dec[I].NT>(D, a, blocks, s);
+    return dec_pick<I + 1>(c, D, a, blocks, s);
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+#define FNTRS_CAT2(a, b) a##b
+#define FNTRS_CAT(a, b) FNTRS_CAT2(a, b)
+
+hipError_t FNTRS_CAT(ct_enc_launch_, FNTRS_L)(CtCfg c, const EncodeArgs& a, uint32_t blocks, hipStream_t s) {
+  return enc_pick<0>(c, a, blocks, s);
+}
+
+hipError_t FNTRS_CAT(ct_dec_launch_, FNTRS_L)(CtCfg c, int D, const DecodeArgs& a, uint32_t blocks, hipStream_t s) {
+  return dec_pick<0>(c, D, a, blocks, s);
+}
+
+}  // namespace fntrs

@@ -1,0 +1,48 @@
+// Launch entry points of the compile-time kernels.  Each transform size L
+// lives in its own translation unit (ct_inst.hip built with -DFNTRS_L=L), so
+// the sizes compile in parallel; the host reaches them through these tables.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "codec_args.hpp"
+
+namespace fntrs {
+
+// Kernel configurations instantiated for encode / decode at size 2^L: lane
+// tile width T and threads per workgroup NT (T = 0 ends a list).  The first
+// entry is the default; the autotuner may pick another.
+struct CtCfg {
+  int T, NT;
+};
+struct CtVariants {
+  CtCfg enc[4];
+  CtCfg dec[4];
+};
+
+constexpr CtVariants ct_variants(int L) {
+  switch (L) {
+    case 9: return {{{32, 512}}, {{32, 512}}};
+    case 10: return {{{16, 512}}, {{16, 512}}};
+    case 11: return {{{8, 512}, {16, 512}}, {{8, 512}}};
+    case 12: return {{{8, 512}, {4, 512}, {8, 1024}}, {{4, 512}, {8, 512}}};
+    case 13: return {{{4, 512}}, {{4, 512}, {4, 1024}, {2, 512}}};
+    case 14: return {{{2, 512}}, {{2, 512}}};
+    case 15: return {{{1, 512}}, {{1, 512}}};
+    default: return {{{64, 512}}, {{64, 512}}};   // L <= 8
+  }
+}
+
+// Launches k_enc<L, T, NT> / k_dec<L, D, T, NT>; D in {-1 (k = n), 0, 1}.
+// Returns hipErrorInvalidValue for a configuration that is not instantiated.
+using CtEncLaunch = hipError_t (*)(CtCfg cfg, const EncodeArgs& a, uint32_t blocks, hipStream_t s);
+using CtDecLaunch = hipError_t (*)(CtCfg cfg, int D, const DecodeArgs& a, uint32_t blocks, hipStream_t s);
+
+#define FNTRS_CT_DECL(L)                                                                        \
+  hipError_t ct_enc_launch_##L(CtCfg cfg, const EncodeArgs& a, uint32_t blocks, hipStream_t s);     \
+  hipError_t ct_dec_launch_##L(CtCfg cfg, int D, const DecodeArgs& a, uint32_t blocks, hipStream_t s);
+FNTRS_CT_DECL(1) FNTRS_CT_DECL(2) FNTRS_CT_DECL(3) FNTRS_CT_DECL(4) FNTRS_CT_DECL(5)
+FNTRS_CT_DECL(6) FNTRS_CT_DECL(7) FNTRS_CT_DECL(8) FNTRS_CT_DECL(9) FNTRS_CT_DECL(10)
+FNTRS_CT_DECL(11) FNTRS_CT_DECL(12) FNTRS_CT_DECL(13) FNTRS_CT_DECL(14) FNTRS_CT_DECL(15)
+#undef FNTRS_CT_DECL
+
+}  // namespace fntrs

@@ -1,0 +1,366 @@
+// FNT passes over GF(65537) with compile-time plans, for gfx950.
+//
+// A transform of size 2^L runs along the rows of a tile of T = V*G lanes
+// (V lanes per thread, G lane groups); every lane is an independent
+// transform (Sec. II-B).  The L radix-2 stages of the divide-and-conquer FNT
+// (Sec. II-A) are grouped into passes of B stages; a thread loads one item
+// -- the 2^B positions base + c*2^S0 of V lanes -- into registers, runs the
+// B stages there and writes it back.  Pass radices, strides and twiddle
+// strides are template constants, so every LDS offset inside an item is an
+// immediate.
+//
+// Orders: dit_*: input bit-reversed, output natural;
+//         dif_*: input natural, output bit-reversed.
+//
+// Lazy arithmetic.  Values are int32 congruent to the residue and kept below
+// 2^23 in magnitude.  Since p = 2^16 + 1, 2^16 = -1 and 2^32 = 1, so a
+// product y*w (|y| < 2^23, w < 2^16) split into its low 32-bit word and the
+// bits above is congruent to hi + lo16 - hi16(lo): a twiddle product costs
+// two 24-bit multiplies and two adds with no reduction of y, and lands in
+// [-65663, 65662].  A DIT butterfly x +- w*y grows ranges only additively
+// (x +- t); a trivial butterfly (w = 1) or a DIF sum x + y doubles them, so
+// the stages that double are few per pass and values are folded
+// (lo16 - (v >> 16), one SDWA subtract) when a pass that doubles stores them.
+// fold(fold(v)) lies in [-1, 65536] and an unsigned min maps -1 to 65536,
+// which gives the canonical residue stored to global memory.
+#pragma once
+#include "field.hpp"
+
+namespace fntrs {
+namespace ct {
+
+// ---------------------------------------------------------------- arithmetic
+__device__ __forceinline__ int32_t fold1(int32_t a) { return (int32_t)(a & 0xFFFF) - (a >> 16); }
+
+__device__ __forceinline__ uint32_t canon(int32_t a) { return min((uint32_t)fold1(fold1(a)), 65536u); }
+
+// y * w mod p for loose y with |y| < 2^23 and a residue w in [0, 65536].
+// The signed 24-bit multiplier gives the 48-bit product as a low word and a
+// high part h (|h| <= 128); 2^32 = 1 mod p, so y w = h + lo16 - hi16(lo).
+// Result in [-65663, 65663].  Two multiplies and two adds, no reduction of y.
+__device__ __forceinline__ int32_t mulw(int32_t y, uint32_t w) {
+  const int32_t ys = (y << 8) >> 8;            // states |y| < 2^23 (the multiplier reads 24 bits)
+  const int32_t wsx = (int32_t)(w << 8) >> 8;  // and w < 2^23
+  const int64_t m = (int64_t)ys * (int64_t)wsx;
+  const uint32_t lo = (uint32_t)m;
+  const int32_t hi = (int32_t)(m >> 32);
+  return (int32_t)(lo & 0xFFFFu) - (int32_t)(lo >> 16) + hi;
+}
+
+// y * c mod p for canonical y and any residue c in [0, 65536] (65536*65536 =
+// 2^32 wraps to 0 in 32 bits; 2^32 = 1 mod p, added back through the top bits).
+__device__ __forceinline__ int32_t mulc(uint32_t yc, uint32_t c) {
+  const uint32_t m = __umul24(yc, c);
+  return (int32_t)(m & 0xFFFFu) - (int32_t)(m >> 16) + (int32_t)((yc & c) >> 16);
+}
+
+// Small roots for passes whose twiddles are compile-time constants:
+// root(lg, j) = omega_(2^lg)^j = 3^(j * 2^(16-lg)).
+struct RootTable {
+  uint32_t f[64], i[64];   // 3^(1024 j), 3^(-1024 j), j < 64
+};
+__host__ __device__ constexpr uint32_t cmul(uint32_t a, uint32_t b) {
+  return (uint32_t)((uint64_t)a * b % 65537u);
+}
+__host__ __device__ constexpr RootTable make_roots() {
+  RootTable t{};
+  uint32_t g = 1;
+  for (int e = 0; e < 1024; ++e) g = cmul(g, 3);           // 3^1024
+  uint32_t ginv = 1;
+  for (int e = 0; e < 65536 - 1024; ++e) ginv = cmul(ginv, 3);  // 3^-1024
+  uint32_t a = 1, b = 1;
+  for (int j = 0; j < 64; ++j) {
+    t.f[j] = a;
+    t.i[j] = b;
+    a = cmul(a, g);
+    b = cmul(b, ginv);
+  }
+  return t;
+}
+constexpr RootTable kRoots = make_roots();
+
+template <bool INV>
+__device__ __forceinline__ constexpr uint32_t small_root(int lg, int j) {
+  // lg <= 6: omega_(2^lg)^j = 3^(1024 * j * 2^(6-lg))
+  return INV ? kRoots.i[(j << (6 - lg)) & 63] : kRoots.f[(j << (6 - lg)) & 63];
+}
+
+// ---------------------------------------------------------------- LDS tile
+// Vector index u = pos*G + g (V words each); one padding vector every 16
+// vectors: phys(u) = u + u/16.  For an item (positions base + c*H, B >= 4
+// or H*G >= 16) phys(u0 + c*H*G) = phys(u0) + c*H*G + (c*H*G)/16, a constant
+// offset, and the strided accesses of a pass fall in distinct banks.
+__device__ __forceinline__ uint32_t phys(uint32_t u) { return u + (u >> 4); }
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Renumber them so that consecutive logical ids run on the same XCD:
+// neighbouring lane tiles, which share cache lines of every row, then meet
+// in one L2 instead of each fetching whole lines from HBM.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nb) {
+  const uint32_t xcd = bid & 7u, local = bid >> 3;
+  const uint32_t per = nb >> 3, rem = nb & 7u;
+  return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+__host__ __device__ constexpr uint32_t lds_vectors(uint32_t rows, uint32_t G) {
+  return rows * G + (rows * G) / 16;
+}
+
+template <int V>
+struct Vec;
+template <>
+struct Vec<4> {
+  __device__ static void get(const uint32_t* p, int32_t (&x)[4]) {
+    const uint4 t = *reinterpret_cast<const uint4*>(p);
+    x[0] = t.x; x[1] = t.y; x[2] = t.z; x[3] = t.w;
+  }
+  __device__ static void put(uint32_t* p, const int32_t (&x)[4]) {
+    *reinterpret_cast<uint4*>(p) = make_uint4(x[0], x[1], x[2], x[3]);
+  }
+};
+template <>
+struct Vec<2> {
+  __device__ static void get(const uint32_t* p, int32_t (&x)[2]) {
+    const uint2 t = *reinterpret_cast<const uint2*>(p);
+    x[0] = t.x; x[1] = t.y;
+  }
+  __device__ static void put(uint32_t* p, const int32_t (&x)[2]) {
+    *reinterpret_cast<uint2*>(p) = make_uint2(x[0], x[1]);
+  }
+};
+template <>
+struct Vec<1> {
+  __device__ static void get(const uint32_t* p, int32_t (&x)[1]) { x[0] = (int32_t)p[0]; }
+  __device__ static void put(uint32_t* p, const int32_t (&x)[1]) { p[0] = (uint32_t)x[0]; }
+};
+
+// Item I/O on the LDS tile: 2^B positions base + c*H of lane group g.
+template <int B, int V, int G, uint32_t H>
+__device__ __forceinline__ void lds_item_get(const uint32_t* lds, uint32_t base, uint32_t g,
+                                             int32_t (&x)[1 << B][V]) {
+  const uint32_t* p = lds + phys(base * G + g) * V;
+#pragma unroll
+  for (int c = 0; c < (1 << B); ++c) {
+    constexpr uint32_t step = H * G;
+    const uint32_t off = c * step + (c * step) / 16;
+    Vec<V>::get(p + off * V, x[c]);
+  }
+}
+template <int B, int V, int G, uint32_t H>
+__device__ __forceinline__ void lds_item_put(uint32_t* lds, uint32_t base, uint32_t g,
+                                             const int32_t (&x)[1 << B][V]) {
+  uint32_t* p = lds + phys(base * G + g) * V;
+#pragma unroll
+  for (int c = 0; c < (1 << B); ++c) {
+    constexpr uint32_t step = H * G;
+    const uint32_t off = c * step + (c * step) / 16;
+    Vec<V>::put(p + off * V, x[c]);
+  }
+}
+
+// ---------------------------------------------------------------- twiddles
+// A twiddle source yields w = omega_(2^lg)^j (j < 2^(lg-1)) for the forward
+// root, or for the inverse root possibly as its negative (NEG): the
+// butterflies then swap their +/- outputs, which costs nothing.
+//
+// TwGlobal: the 3^e and 3^-e tables in global memory (any size).
+// TwLds<L>: tab[u] = omega_(2^L)^u, u <= 2^(L-1), in LDS; omega_(2^lg)^j =
+//   tab[j 2^(L-lg)], and since omega_(2^L)^(2^(L-1)) = -1 the inverse is
+//   omega^-u = -tab[2^(L-1) - u].
+struct TwGlobal {
+  const uint32_t* fwd;
+  const uint32_t* inv;
+  static constexpr bool NEG = false;
+  __device__ __forceinline__ uint32_t get(bool inverse, uint32_t j, int lg) const {
+    return (inverse ? inv : fwd)[j << (16 - lg)];
+  }
+};
+
+// TwLds<L, LO, TOP>: per-stage tables in LDS.  For LO <= lg <= TOP the table
+// of stage lg holds omega_(2^lg)^j for j <= 2^(lg-1), contiguous in j, so the
+// items of a pass (consecutive j) read consecutive words; the inverse root is
+// omega^-j = -omega^(2^(lg-1) - j), read mirrored with NEG.  Stages above TOP
+// read the table of stage L (omega_(2^L)^u, u <= 2^(L-1)) at stride
+// 2^(L-lg).  Stages below LO are never looked up (the first pass of a
+// transform uses compile-time roots).
+template <int L, int LO, int TOP>
+struct TwLds {
+  const uint32_t* tab;
+  static constexpr bool NEG = true;
+  // word offset of the table of stage lg (LO <= lg <= TOP), then stage L
+  __host__ __device__ static constexpr uint32_t off(int lg) {
+    uint32_t o = 0;
+    for (int g = LO; g < lg; ++g) o += (1u << (g - 1)) + 1;
+    return o;
+  }
+  __host__ __device__ static constexpr uint32_t words() {
+    return off(TOP + 1) + (TOP < L ? (1u << (L - 1)) + 1 : 0);
+  }
+  __device__ __forceinline__ uint32_t get(bool inverse, uint32_t j, int lg) const {
+    if (lg <= TOP) return tab[off(lg) + (inverse ? (1u << (lg - 1)) - j : j)];
+    const uint32_t u = j << (L - lg);
+    return tab[off(TOP + 1) + (inverse ? (1u << (L - 1)) - u : u)];
+  }
+  // fills the tables from the global table tw[e] = 3^e: omega_(2^lg)^j = 3^(j 2^(16-lg))
+  __device__ __forceinline__ void fill(uint32_t* t, const uint32_t* __restrict__ tw) const {
+    for (int lg = LO; lg <= TOP; ++lg)
+      for (uint32_t j = threadIdx.x; j <= (1u << (lg - 1)); j += blockDim.x) t[off(lg) + j] = tw[j << (16 - lg)];
+    if (TOP < L)
+      for (uint32_t u = threadIdx.x; u <= (1u << (L - 1)); u += blockDim.x) t[off(TOP + 1) + u] = tw[u << (16 - L)];
+  }
+};
+
+// ---------------------------------------------------------------- butterflies
+template <int B, int V, int S0, bool INV, class TW>
+__device__ __forceinline__ void dit_stages(int32_t (&x)[1 << B][V], uint32_t jp, const TW& tws) {
+#pragma unroll
+  for (int i = 0; i < B; ++i) {
+    const int lg = S0 + i + 1;
+#pragma unroll
+    for (int cc = 0; cc < (1 << i); ++cc) {
+      // twiddle omega_(2^lg)^(jp + cc 2^S0)
+      uint32_t w = 1;
+      bool triv = false, neg = false;
+      if constexpr (S0 == 0) {
+        triv = cc == 0;
+        w = small_root<INV>(lg, cc);
+      } else {
+        w = tws.get(INV, jp + ((uint32_t)cc << S0), lg);
+        neg = INV && TW::NEG;
+      }
+#pragma unroll
+      for (int c0 = 0; c0 < (1 << B); c0 += 2 << i) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const int32_t a = x[c0 + cc][v];
+          const int32_t t = triv ? x[c0 + cc + (1 << i)][v] : mulw(x[c0 + cc + (1 << i)][v], w);
+          x[c0 + cc][v] = neg ? a - t : a + t;
+          x[c0 + cc + (1 << i)][v] = neg ? a + t : a - t;
+        }
+      }
+    }
+  }
+}
+
+// DIF stages with spans 2^(S1-1) down to 2^(S1-B), S1 = top stage index + 1.
+template <int B, int V, int S1, bool INV, class TW>
+__device__ __forceinline__ void dif_stages(int32_t (&x)[1 << B][V], uint32_t jp, const TW& tws) {
+  constexpr int S0 = S1 - B;    // log2 of the item stride
+#pragma unroll
+  for (int i = B - 1; i >= 0; --i) {
+    const int lg = S0 + i + 1;  // pairs at distance 2^(S0+i), block 2^lg
+#pragma unroll
+    for (int cc = 0; cc < (1 << i); ++cc) {
+      uint32_t w = 1;
+      bool triv = false, neg = false;
+      if constexpr (S0 == 0) {
+        triv = cc == 0;
+        w = small_root<INV>(lg, cc);
+      } else {
+        w = tws.get(INV, jp + ((uint32_t)cc << S0), lg);
+        neg = INV && TW::NEG;
+      }
+#pragma unroll
+      for (int c0 = 0; c0 < (1 << B); c0 += 2 << i) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const int32_t a = x[c0 + cc][v], b = x[c0 + cc + (1 << i)][v];
+          x[c0 + cc][v] = a + b;
+          x[c0 + cc + (1 << i)][v] = triv ? a - b : mulw(neg ? b - a : a - b, w);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- plans
+// An L-stage transform with radix bound BM takes NP = ceil(L/BM) passes with
+// radices as equal as possible.  DIT passes run bottom-up (pass 0 has stride
+// 1) and put the larger radices first; DIF passes run top-down and put them
+// last.  Either way the stride-1 pass gets the largest radix, which keeps the
+// padded layout conflict-free when H*G < 16.
+__host__ __device__ constexpr int plan_np(int L, int BM) { return L == 0 ? 0 : (L + BM - 1) / BM; }
+__host__ __device__ constexpr int plan_b(int L, int BM, int p) {
+  return L / plan_np(L, BM) + (p < L % plan_np(L, BM) ? 1 : 0);
+}
+// DIT pass p covers stages [dit_s0, dit_s0 + B).
+__host__ __device__ constexpr int dit_s0(int L, int BM, int p) {
+  int s = 0;
+  for (int q = 0; q < p; ++q) s += plan_b(L, BM, q);
+  return s;
+}
+// DIF pass p has radix plan_b(L, BM, NP-1-p) and covers stages [top - B, top).
+__host__ __device__ constexpr int dif_top(int L, int BM, int p) {
+  int t = L;
+  for (int q = 0; q < p; ++q) t -= plan_b(L, BM, plan_np(L, BM) - 1 - q);
+  return t;
+}
+
+// Loaders / storers are objects with a member template
+//   item<B, H>(base, g, x)  that moves the 2^B positions base + c*H of lane
+// group g between their home (global memory or the LDS tile) and registers.
+template <int L, int BM, int P, int V, int G, bool INV, class TW, class Ld, class St>
+__device__ __forceinline__ void dit_pass(const TW& tw, Ld& ld, St& st) {
+  constexpr int B = plan_b(L, BM, P);
+  constexpr int S0 = dit_s0(L, BM, P);
+  constexpr uint32_t H = 1u << S0;
+  constexpr uint32_t ITEMS = (1u << (L - B)) * G;
+  for (uint32_t q = threadIdx.x; q < ITEMS; q += blockDim.x) {
+    const uint32_t g = q % G, it = q / G;
+    const uint32_t jp = it % H, blk = it / H;
+    const uint32_t base = blk * (H << B) + jp;
+    int32_t x[1 << B][V];
+    ld.template item<B, H>(base, g, x);
+    dit_stages<B, V, S0, INV>(x, jp, tw);
+    st.template item<B, H>(base, g, x);
+  }
+}
+
+template <int L, int BM, int P, int V, int G, bool INV, class TW, class Ld, class St>
+__device__ __forceinline__ void dif_pass(const TW& tw, Ld& ld, St& st) {
+  constexpr int B = plan_b(L, BM, plan_np(L, BM) - 1 - P);
+  constexpr int TOP = dif_top(L, BM, P);
+  constexpr int S0 = TOP - B;
+  constexpr uint32_t H = 1u << S0;
+  constexpr uint32_t ITEMS = (1u << (L - B)) * G;
+  for (uint32_t q = threadIdx.x; q < ITEMS; q += blockDim.x) {
+    const uint32_t g = q % G, it = q / G;
+    const uint32_t jp = it % H, blk = it / H;
+    const uint32_t base = blk * (H << B) + jp;
+    int32_t x[1 << B][V];
+    ld.template item<B, H>(base, g, x);
+    dif_stages<B, V, TOP, INV>(x, jp, tw);
+    st.template item<B, H>(base, g, x);
+  }
+}
+
+// Whole transforms: pass 0 uses (first-loader, mid-storer) ... the last pass
+// (mid-loader, last-storer); a single-pass transform uses (first, last).
+// A barrier follows every pass.
+template <int L, int BM, int V, int G, bool INV, int P = 0, class TW, class L0, class LM, class SM, class SL>
+__device__ __forceinline__ void dit(const TW& tw, L0& l0, LM& lm, SM& sm, SL& sl) {
+  constexpr int NP = plan_np(L, BM);
+  if constexpr (P < NP) {
+    if constexpr (P == 0 && NP == 1) dit_pass<L, BM, P, V, G, INV>(tw, l0, sl);
+    else if constexpr (P == 0) dit_pass<L, BM, P, V, G, INV>(tw, l0, sm);
+    else if constexpr (P == NP - 1) dit_pass<L, BM, P, V, G, INV>(tw, lm, sl);
+    else dit_pass<L, BM, P, V, G, INV>(tw, lm, sm);
+    __syncthreads();
+    dit<L, BM, V, G, INV, P + 1>(tw, l0, lm, sm, sl);
+  }
+}
+
+template <int L, int BM, int V, int G, bool INV, int P = 0, class TW, class L0, class LM, class SM, class SL>
+__device__ __forceinline__ void dif(const TW& tw, L0& l0, LM& lm, SM& sm, SL& sl) {
+  constexpr int NP = plan_np(L, BM);
+  if constexpr (P < NP) {
+    if constexpr (P == 0 && NP == 1) dif_pass<L, BM, P, V, G, INV>(tw, l0, sl);
+    else if constexpr (P == 0) dif_pass<L, BM, P, V, G, INV>(tw, l0, sm);
+    else if constexpr (P == NP - 1) dif_pass<L, BM, P, V, G, INV>(tw, lm, sl);
+    else dif_pass<L, BM, P, V, G, INV>(tw, lm, sm);
+    __syncthreads();
+    dif<L, BM, V, G, INV, P + 1>(tw, l0, lm, sm, sl);
+  }
+}
+
+}  // namespace ct
+}  // namespace fntrs

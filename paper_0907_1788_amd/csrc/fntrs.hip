@@ -1,8 +1,9 @@
 // libfntrs: host side of the C ABI declared in include/fntrs.h.
 //
 // Validation happens here, synchronously, before anything is enqueued; the
-// coding work itself runs in the kernels of codec_kernels.hpp and
-// locator_kernels.hpp.
+// coding work itself runs in the compile-time kernels (ct_kernels.hpp, one
+// translation unit per transform size) and the locator kernels
+// (locator_kernels.hpp).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -15,8 +16,8 @@
 #include <vector>
 
 #include "../../include/fntrs.h"
-#include "codec_kernels.hpp"
 #include "locator_kernels.hpp"
+#include "ct_launch.hpp"
 
 using namespace fntrs;
 
@@ -32,11 +33,12 @@ int ilog2(uint64_t x) { int r = 0; while ((1ull << r) < x) ++r; return r; }
 struct fntrs_locator_s {
   uint32_t n = 0, k = 0;
   int logn = 0, logk = 0;
+  int logm = 0;                      // low-product length M = 2^logm >= 2k (k < n)
   std::vector<uint32_t> positions;   // the k positions used
   uint64_t key = 0;
   uint32_t* mem = nullptr;           // one device allocation, views below
   size_t bytes = 0;
-  uint32_t *pos = nullptr, *wfull = nullptr, *ridx = nullptr, *ahat_s = nullptr;
+  uint32_t *pos = nullptr, *wfull = nullptr, *ridx = nullptr, *ahat_br = nullptr;
   uint32_t *A = nullptr, *w = nullptr, *ahat = nullptr;
   hipEvent_t ready = nullptr;        // recorded after the build on its stream
   int refs = 0;
@@ -47,7 +49,10 @@ struct fntrs_ctx {
   int device = 0;
   size_t cap = kDefaultCap, used = 0;
   uint32_t* tw = nullptr;            // tw[e] = 3^e mod p, e < 65536
+  uint32_t* twi = nullptr;           // twi[e] = 3^-e mod p
   size_t lds_max = 65536;
+  CtCfg enc_cfg[16] = {};            // kernel configuration per log2 transform size
+  CtCfg dec_cfg[16] = {};
   std::mutex mu;
   std::string err;
   std::unordered_multimap<uint64_t, fntrs_locator_t*> cache;
@@ -95,71 +100,18 @@ uint64_t hash_positions(uint32_t n, uint32_t k, const uint32_t* z) {
   return h;
 }
 
-// Lanes per workgroup tile: the widest power of two (<= 64) whose tile of
-// `rows` rows fits the LDS budget.
-int pick_tile(size_t rows, size_t lds_budget) {
-  int t = 64;
-  while (t > 1 && rows * (size_t)t * 4 > lds_budget) t >>= 1;
-  return t;
-}
-
 hipError_t set_lds_attr(const void* fn, size_t bytes) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-// Codec tile geometry: T lanes per workgroup, V lanes per thread, G = T/V
-// lane groups, BMAX the largest radix-2^B pass (bounded by registers).
-struct Tile {
-  int T = 1, V = 1, G = 1, bmax = 6;
-};
-
-Tile make_tile(int T) {
-  Tile t;
-  t.T = T;
-  t.V = T >= 4 ? 4 : T;
-  t.G = T / t.V;
-  t.bmax = t.V == 4 ? 4 : (t.V == 2 ? 5 : 6);
-  return t;
-}
-
-// Items of the last pass of a size-2^logm transform must fit one per thread
-// when that pass is synchronised.
-bool last_pass_fits(const Tile& t, int logm) {
-  int bs[8];
-  const int np = plan_passes(logm, pass_bmax(logm, t.G, kCodecThreads, t.bmax), bs);
-  if (np == 0) return true;
-  return ((size_t)t.G << (logm - bs[np - 1])) <= (size_t)kCodecThreads;
-}
-
-template <int V, int BMAX>
-hipError_t launch_encode_v(const EncodeArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
-  (void)set_lds_attr((const void*)k_encode<V, BMAX>, lds);
-  hipLaunchKernelGGL((k_encode<V, BMAX>), dim3(blocks), dim3(kCodecThreads), lds, s, a);
-  return hipGetLastError();
-}
-
-template <int V, int BMAX>
-hipError_t launch_decode_v(const DecodeArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
-  (void)set_lds_attr((const void*)k_decode<V, BMAX>, lds);
-  hipLaunchKernelGGL((k_decode<V, BMAX>), dim3(blocks), dim3(kCodecThreads), lds, s, a);
-  return hipGetLastError();
-}
-
-hipError_t encode_dispatch(const Tile& t, const EncodeArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
-  switch (t.V) {
-    case 4: return launch_encode_v<4, 4>(a, blocks, lds, s);
-    case 2: return launch_encode_v<2, 5>(a, blocks, lds, s);
-    default: return launch_encode_v<1, 6>(a, blocks, lds, s);
-  }
-}
-
-hipError_t decode_dispatch(const Tile& t, const DecodeArgs& a, uint32_t blocks, size_t lds, hipStream_t s) {
-  switch (t.V) {
-    case 4: return launch_decode_v<4, 4>(a, blocks, lds, s);
-    case 2: return launch_decode_v<2, 5>(a, blocks, lds, s);
-    default: return launch_decode_v<1, 6>(a, blocks, lds, s);
-  }
-}
+const CtEncLaunch kCtEnc[16] = {nullptr, ct_enc_launch_1, ct_enc_launch_2, ct_enc_launch_3, ct_enc_launch_4,
+                                 ct_enc_launch_5, ct_enc_launch_6, ct_enc_launch_7, ct_enc_launch_8,
+                                 ct_enc_launch_9, ct_enc_launch_10, ct_enc_launch_11, ct_enc_launch_12,
+                                 ct_enc_launch_13, ct_enc_launch_14, ct_enc_launch_15};
+const CtDecLaunch kCtDec[16] = {nullptr, ct_dec_launch_1, ct_dec_launch_2, ct_dec_launch_3, ct_dec_launch_4,
+                                 ct_dec_launch_5, ct_dec_launch_6, ct_dec_launch_7, ct_dec_launch_8,
+                                 ct_dec_launch_9, ct_dec_launch_10, ct_dec_launch_11, ct_dec_launch_12,
+                                 ct_dec_launch_13, ct_dec_launch_14, ct_dec_launch_15};
 
 bool aligned16(const void* p, size_t ld, size_t stride) {
   return ((uintptr_t)p % 16 == 0) && (ld % 4 == 0) && (stride % 4 == 0);
@@ -219,10 +171,11 @@ bool make_room(fntrs_ctx* c, size_t need) {
 int build_locator(fntrs_ctx* c, fntrs_locator_t* L, hipStream_t s) {
   const uint32_t n = L->n, k = L->k;
   const int logn = L->logn, logk = L->logk;
-  const size_t k2 = 2ull * k;
-  // device layout: pos[k] wfull[n] ridx[n] ahat_s[2k] A[k+1] w[k] ahat[2k] | scratch: t0[k] t1[k] spec[k] vals[max(n,2k)]
-  const size_t state = k + 2ull * n + k2 + (k + 1) + k + k2;
-  const size_t scratch = 3ull * k + std::max<size_t>(n, k2);
+  const size_t M = (k < n) ? (size_t)1 << L->logm : 0;
+  // device layout: pos[k] wfull[n] ridx[n] ahat_br[M] A[k+1] w[k] ahat[M]
+  //                | scratch: t0[k] t1[k] spec[k] vals[n]
+  const size_t state = k + 2ull * n + M + (k + 1) + k + M;
+  const size_t scratch = (k < n) ? 3ull * k + n : 0;
   L->bytes = (state + scratch) * 4;
   if (!make_room(c, L->bytes))
     return fail(c, FNTRS_E_NOMEM, "locator of %zu bytes exceeds the context cap (%zu used of %zu)", L->bytes,
@@ -237,13 +190,13 @@ int build_locator(fntrs_ctx* c, fntrs_locator_t* L, hipStream_t s) {
   L->pos = p; p += k;
   L->wfull = p; p += n;
   L->ridx = p; p += n;
-  L->ahat_s = p; p += k2;
+  L->ahat_br = p; p += M;
   L->A = p; p += k + 1;
   L->w = p; p += k;
-  L->ahat = p; p += k2;
-  uint32_t* t0 = p; p += k;
-  uint32_t* t1 = p; p += k;
-  uint32_t* spec = p; p += k;
+  L->ahat = p; p += M;
+  uint32_t* t0 = p; p += (k < n) ? k : 0;
+  uint32_t* t1 = p; p += (k < n) ? k : 0;
+  uint32_t* spec = p; p += (k < n) ? k : 0;
   uint32_t* vals = p;
 
   HIP_TRY(c, hipMemcpyAsync(L->pos, L->positions.data(), k * 4ull, hipMemcpyHostToDevice, s));
@@ -251,7 +204,6 @@ int build_locator(fntrs_ctx* c, fntrs_locator_t* L, hipStream_t s) {
     // Nothing erased: the decoder is the inverse FNT_n with factor n^-1.
     const uint32_t ninv = 65537u - (65536u >> logn);
     hipLaunchKernelGGL(k_loc_identity, dim3((n + 255) / 256), dim3(256), 0, s, L->wfull, L->ridx, n, ninv);
-    HIP_TRY(c, hipGetLastError());
     // A = x^n - 1 for export
     hipLaunchKernelGGL(k_loc_fill, dim3((k + 256) / 256), dim3(256), 0, s, L->A, k + 1, 0u);
     hipLaunchKernelGGL(k_loc_fill, dim3(1), dim3(1), 0, s, L->A, 1u, 65536u);
@@ -289,15 +241,24 @@ int build_locator(fntrs_ctx* c, fntrs_locator_t* L, hipStream_t s) {
     hipLaunchKernelGGL(k_loc_weights, dim3((k + 255) / 256), dim3(256), 0, s, L->pos, vals, k, logn, c->tw, L->w,
                        L->wfull, L->ridx);
     HIP_TRY(c, hipGetLastError());
-    // FNT_2k of (a_0..a_(k-1), 0..0): two twisted FNT_k.
-    hipLaunchKernelGGL(k_loc_eval, dim3(2), dim3(ntk), ldsk, s, cur, logk, logk + 1, c->tw, L->ahat);
+    // FNT_M of (a_0..a_(k-1), 0..0): M/k twisted FNT_k; then the decoder's
+    // copy, bit-reversed and scaled by M^-1.
+    hipLaunchKernelGGL(k_loc_eval, dim3((uint32_t)(M / k)), dim3(ntk), ldsk, s, cur, logk, L->logm, c->tw, L->ahat);
     HIP_TRY(c, hipGetLastError());
-    hipLaunchKernelGGL(k_loc_ahat, dim3((k2 + 255) / 256), dim3(256), 0, s, L->ahat, logk + 1, L->ahat_s);
+    hipLaunchKernelGGL(k_loc_ahat, dim3((uint32_t)((M + 255) / 256)), dim3(256), 0, s, L->ahat, L->logm, L->ahat_br);
     HIP_TRY(c, hipGetLastError());
   }
   HIP_TRY(c, hipEventCreateWithFlags(&L->ready, hipEventDisableTiming));
   HIP_TRY(c, hipEventRecord(L->ready, s));
   return FNTRS_OK;
+}
+
+hipError_t launch_copy(const uint32_t* src, size_t stride_src, uint32_t* dst, size_t stride_dst, uint32_t lanes,
+                       uint32_t batch, hipStream_t s) {
+  const uint64_t total = (uint64_t)lanes * batch;
+  hipLaunchKernelGGL(k_copy_rows, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, s, src, (uint64_t)stride_src,
+                     dst, (uint64_t)stride_dst, lanes, batch, (const uint32_t*)nullptr);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -327,12 +288,36 @@ int fntrs_create(int device, size_t cap, fntrs_ctx** out) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete c; return FNTRS_E_DEVICE; }
   c->lds_max = prop.sharedMemPerBlock;
-  std::vector<uint32_t> h(65536);
+  for (int L = 1; L <= 15; ++L) {
+    c->enc_cfg[L] = ct_variants(L).enc[0];
+    c->dec_cfg[L] = ct_variants(L).dec[0];
+  }
+  // FNTRS_TILES="e12=8x512,d13=4x1024,...": override the configuration per size
+  if (const char* t = getenv("FNTRS_TILES")) {
+    std::string spec(t);
+    size_t pos = 0;
+    while (pos < spec.size()) {
+      size_t end = spec.find(',', pos);
+      if (end == std::string::npos) end = spec.size();
+      const std::string item = spec.substr(pos, end - pos);
+      int L = 0, T = 0, NT = 512;
+      char kind = 0;
+      if (sscanf(item.c_str(), "%c%d=%dx%d", &kind, &L, &T, &NT) >= 3 && L >= 1 && L <= 15) {
+        if (kind == 'e') c->enc_cfg[L] = CtCfg{T, NT};
+        if (kind == 'd') c->dec_cfg[L] = CtCfg{T, NT};
+      }
+      pos = end + 1;
+    }
+  }
+  // twiddle tables: tw[e] = 3^e and twi[e] = 3^-e = 3^(65536-e), e < 65536
+  std::vector<uint32_t> h(2 * 65536);
   uint64_t x = 1;
   for (int e = 0; e < 65536; ++e) { h[e] = (uint32_t)x; x = x * 3 % 65537; }
-  if (hipMalloc((void**)&c->tw, 65536 * 4) != hipSuccess) { delete c; return FNTRS_E_NOMEM; }
-  c->used += 65536 * 4;
-  if (hipMemcpy(c->tw, h.data(), 65536 * 4, hipMemcpyHostToDevice) != hipSuccess) {
+  for (int e = 0; e < 65536; ++e) h[65536 + e] = h[(65536 - e) & 0xFFFF];
+  if (hipMalloc((void**)&c->tw, 2 * 65536 * 4) != hipSuccess) { delete c; return FNTRS_E_NOMEM; }
+  c->twi = c->tw + 65536;
+  c->used += 2 * 65536 * 4;
+  if (hipMemcpy(c->tw, h.data(), 2 * 65536 * 4, hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipFree(c->tw);
     delete c;
     return FNTRS_E_DEVICE;
@@ -378,24 +363,26 @@ int fntrs_encode(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uin
     int rc = validate_range(c, src, batch, stride_src, k, ld_src, lanes, s);
     if (rc) return rc;
   }
+  if (n == 1) {  // k = 1: e_0 = s_0
+    HIP_TRY(c, launch_copy(src, stride_src, dst, stride_dst, lanes, batch, s));
+    return FNTRS_OK;
+  }
   EncodeArgs a;
   a.src = src; a.ld_src = ld_src; a.stride_src = stride_src;
   a.dst = dst; a.ld_dst = ld_dst; a.stride_dst = stride_dst;
-  a.tw = c->tw; a.n = n; a.k = k; a.lanes = lanes;
+  a.tw = c->tw; a.twi = c->twi;
+  a.n = n; a.k = k; a.lanes = lanes;
   a.logn = ilog2(n);
-  a.logK = ilog2(k);                     // K = smallest power of two >= k
-  const uint32_t K = 1u << a.logK;
-  const size_t budget = std::min<size_t>(c->lds_max, K >= 8192 ? 131072 : 65536);
-  const Tile tl = make_tile(pick_tile(K, budget));
-  if ((size_t)K * tl.T * 4 > c->lds_max)
-    return fail(c, FNTRS_E_UNSUPPORTED, "encode with k=%u needs a multi-pass transform (not built)", k);
-  a.G = tl.G;
+  a.logK = std::max(1, ilog2(k));        // transform size K: smallest power of two >= k, at least 2
+  if (a.logK > 15)
+    return fail(c, FNTRS_E_UNSUPPORTED, "encode with k=%u > 32768 needs a transform larger than one tile", k);
+  const CtCfg cfg = c->enc_cfg[a.logK];
   a.vec = aligned16(src, ld_src, stride_src) && aligned16(dst, ld_dst, stride_dst);
-  a.tiles = (lanes + tl.T - 1) / tl.T;
-  a.cosets = n / K;
+  a.tiles = (lanes + cfg.T - 1) / cfg.T;
+  a.cosets = n >> a.logK;
   const uint64_t blocks = (uint64_t)a.tiles * a.cosets * batch;
   if (blocks > 0x7fffffffull) return fail(c, FNTRS_E_INVAL, "grid too large");
-  HIP_TRY(c, encode_dispatch(tl, a, (uint32_t)blocks, (size_t)K * tl.T * 4, s));
+  HIP_TRY(c, kCtEnc[a.logK](cfg, a, (uint32_t)blocks, s));
   return FNTRS_OK;
 }
 
@@ -416,8 +403,8 @@ int fntrs_locator(fntrs_ctx* c, uint32_t n, uint32_t k, const uint32_t* position
       return fail(c, FNTRS_E_POSITIONS, "positions must be strictly ascending (index %u)", i);
   }
   if (!is_pow2(k)) return fail(c, FNTRS_E_UNSUPPORTED, "decoding needs k a power of two, got %u", k);
-  if (k != n && (size_t)k * 4 > c->lds_max)
-    return fail(c, FNTRS_E_UNSUPPORTED, "locator for k=%u exceeds the on-chip transform size", k);
+  if (n > 32768)
+    return fail(c, FNTRS_E_UNSUPPORTED, "decoding n=%u needs a transform larger than one tile (n <= 32768)", n);
   const uint64_t key = hash_positions(n, k, positions);
   auto range = c->cache.equal_range(key);
   for (auto it = range.first; it != range.second; ++it) {
@@ -433,6 +420,7 @@ int fntrs_locator(fntrs_ctx* c, uint32_t n, uint32_t k, const uint32_t* position
   DeviceGuard g(c->device);
   auto* L = new fntrs_locator_t();
   L->n = n; L->k = k; L->logn = ilog2(n); L->logk = ilog2(k);
+  L->logm = std::max(L->logk + 1, L->logn - 1);   // low-product length M >= 2k, M >= n/2
   L->positions.assign(positions, positions + k);
   L->key = key;
   int rc = build_locator(c, L, (hipStream_t)stream);
@@ -463,7 +451,13 @@ int fntrs_locator_export(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t* A, ui
   HIP_TRY(c, hipEventSynchronize(L->ready));
   if (A) HIP_TRY(c, hipMemcpy(A, L->A, (L->k + 1) * 4ull, hipMemcpyDeviceToHost));
   if (w) HIP_TRY(c, hipMemcpy(w, L->w, L->k * 4ull, hipMemcpyDeviceToHost));
-  if (ahat && L->k != L->n) HIP_TRY(c, hipMemcpy(ahat, L->ahat, 2ull * L->k * 4, hipMemcpyDeviceToHost));
+  if (ahat && L->k != L->n) {
+    // FNT_2k values are the FNT_M values at multiples of M/2k
+    const size_t M = (size_t)1 << L->logm, step = M / (2ull * L->k);
+    std::vector<uint32_t> h(M);
+    HIP_TRY(c, hipMemcpy(h.data(), L->ahat, M * 4, hipMemcpyDeviceToHost));
+    for (size_t m = 0; m < 2ull * L->k; ++m) ahat[m] = h[m * step];
+  }
   return FNTRS_OK;
 }
 
@@ -495,25 +489,23 @@ int fntrs_decode(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, uint32_
     if (rc) return rc;
   }
   HIP_TRY(c, hipStreamWaitEvent(s, L->ready, 0));
+  if (n == 1) {  // k = n = 1: s_0 = e_0
+    HIP_TRY(c, launch_copy(recv, stride_recv, dst, stride_dst, lanes, batch, s));
+    return FNTRS_OK;
+  }
   DecodeArgs a;
   a.recv = recv; a.ld_recv = ld_recv; a.stride_recv = stride_recv;
   a.dst = dst; a.ld_dst = ld_dst; a.stride_dst = stride_dst;
-  a.tw = c->tw; a.wfull = L->wfull; a.ridx = L->ridx; a.ahat = L->ahat_s;
+  a.tw = c->tw; a.twi = c->twi; a.wfull = L->wfull; a.ridx = L->ridx; a.ahat_br = L->ahat_br;
   a.n = n; a.k = k; a.lanes = lanes; a.logn = L->logn; a.logk = L->logk;
   a.full = full ? 1u : 0u;
-  const size_t rows = n;                 // 2k <= n whenever k < n (both powers of two)
-  const size_t budget = std::min<size_t>(c->lds_max, rows >= 8192 ? 131072 : 65536);
-  Tile tl = make_tile(pick_tile(rows, budget));
-  while (tl.T > 1 && (!last_pass_fits(tl, L->logn) || (k != n && !last_pass_fits(tl, L->logk + 1))))
-    tl = make_tile(tl.T / 2);
-  if (rows * tl.T * 4 > c->lds_max || !last_pass_fits(tl, L->logn))
-    return fail(c, FNTRS_E_UNSUPPORTED, "decode with n=%u needs a multi-pass transform (not built)", n);
-  a.G = tl.G;
+  const int D = (k == n) ? -1 : L->logn - L->logm;
+  const CtCfg cfg = c->dec_cfg[L->logn];
   a.vec = aligned16(recv, ld_recv, stride_recv) && aligned16(dst, ld_dst, stride_dst);
-  a.tiles = (lanes + tl.T - 1) / tl.T;
+  a.tiles = (lanes + cfg.T - 1) / cfg.T;
   const uint64_t blocks = (uint64_t)a.tiles * batch;
   if (blocks > 0x7fffffffull) return fail(c, FNTRS_E_INVAL, "grid too large");
-  HIP_TRY(c, decode_dispatch(tl, a, (uint32_t)blocks, rows * tl.T * 4, s));
+  HIP_TRY(c, kCtDec[L->logn](cfg, D, a, (uint32_t)blocks, s));
   return FNTRS_OK;
 }
 

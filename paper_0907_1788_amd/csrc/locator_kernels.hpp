@@ -120,12 +120,13 @@ __global__ void k_loc_weights(const uint32_t* __restrict__ pos, const uint32_t* 
   ridx[z] = i;
 }
 
-// Â for step 6 with the inverse-transform factor (2k)^-1 folded in.
-__global__ void k_loc_ahat(const uint32_t* __restrict__ ahat, int log2k, uint32_t* __restrict__ ahat_s) {
+// Â for step 6 in bit-reversed order with the inverse-transform factor
+// M^-1 folded in (M = 2^logm is the cyclic length of the low product).
+__global__ void k_loc_ahat(const uint32_t* __restrict__ ahat, int logm, uint32_t* __restrict__ ahat_br) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (1u << log2k)) return;
-  const uint32_t inv = 65537u - (65536u >> log2k);          // (2^log2k)^-1 = -2^(16-log2k)
-  ahat_s[i] = fmul(ahat[i], inv);
+  if (i >= (1u << logm)) return;
+  const uint32_t inv = 65537u - (65536u >> logm);           // (2^logm)^-1 = -2^(16-logm)
+  ahat_br[bitrev(i, logm)] = fmul(ahat[i], inv);
 }
 
 // Decoder tables when nothing is erased (k = n): weight n^-1, row z.
@@ -141,6 +142,16 @@ __global__ void k_loc_identity(uint32_t* __restrict__ wfull, uint32_t* __restric
 __global__ void k_loc_fill(uint32_t* __restrict__ w, uint32_t k, uint32_t v) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < k) w[i] = v;
+}
+
+// n = 1 (and k = 1): encoding and decoding both copy the single symbol.
+__global__ void k_copy_rows(const uint32_t* __restrict__ src, uint64_t stride_src, uint32_t* __restrict__ dst,
+                            uint64_t stride_dst, uint32_t lanes, uint32_t batch, const uint32_t* __restrict__ scale) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (uint64_t)lanes * batch) return;
+  const uint64_t b = i / lanes, l = i % lanes;
+  const uint32_t v = src[b * stride_src + l];
+  dst[b * stride_dst + l] = scale ? fmul(v, scale[0]) : v;
 }
 
 }  // namespace fntrs

@@ -63,7 +63,7 @@ def gpu_decode(ctx, loc, recv, flags=fntrs.FNTRS_RECV_COMPACT):
 
 # ------------------------------------------------------------------ encode
 ENC_CASES = [
-    (1, 1, 3, 1), (2, 1, 5, 1), (2, 2, 7, 2), (4, 2, 1, 1), (8, 3, 33, 1), (16, 16, 40, 1),
+    (1, 1, 3, 2), (4, 1, 3, 1), (65536, 1, 2, 1), (2, 1, 5, 1), (2, 2, 7, 2), (4, 2, 1, 1), (8, 3, 33, 1), (16, 16, 40, 1),
     (64, 5, 17, 2), (128, 64, 100, 1), (256, 256, 9, 1), (512, 256, 512, 1), (512, 100, 65, 3),
     (1024, 1, 31, 1), (2048, 1024, 70, 1), (4096, 4096, 5, 1), (8192, 4096, 16, 1),
     (8192, 8192, 3, 1), (16384, 2048, 4, 1), (32768, 32768, 2, 1),
@@ -133,6 +133,9 @@ DEC_CASES = [
     (512, 256, 512, 1, "random"), (512, 256, 100, 1, "first"), (512, 128, 17, 1, "random"),
     (1024, 512, 31, 1, "random"), (2048, 1024, 9, 1, "random"), (4096, 2048, 8, 1, "first"),
     (8192, 4096, 8, 1, "random"), (8192, 2048, 5, 1, "random"), (16384, 8192, 3, 1, "random"),
+    (1024, 128, 8, 1, "random"), (2048, 256, 5, 1, "first"), (128, 1, 3, 1, "random"),
+    (1, 1, 3, 2, "all"), (2, 2, 5, 1, "all"), (8192, 8192, 3, 1, "all"), (4096, 64, 9, 1, "random"),
+    (32768, 1024, 2, 1, "random"), (16384, 16384, 2, 1, "all"),
     (16384, 4096, 6, 2, "first"), (32768, 16384, 2, 1, "random"), (32768, 32768, 2, 1, "all"),
 ]
 
@@ -215,3 +218,53 @@ def test_validation_with_device(ctx):
     ok = dev(np.full((1, 4, 4), 65536, dtype=np.uint32))
     ctx.encode(ok, dst, 8, flags=fntrs.FNTRS_FLAG_VALIDATE)
     torch.cuda.synchronize()
+
+
+# every lane-tile width instantiated for a size, forced through FNTRS_TILES
+TILE_CASES = [("e12=4x512", 4096, 4096, 40), ("e12=8x1024", 8192, 4096, 24), ("e11=16x512", 2048, 1024, 33),
+              ("d12=8x512", 4096, 2048, 40), ("d13=4x1024", 8192, 4096, 9), ("d13=2x512", 8192, 4096, 6),
+              ("d13=2x512", 8192, 2048, 6), ("d13=4x1024", 8192, 8192, 5)]
+
+
+@pytest.mark.parametrize("spec,n,k,lanes", TILE_CASES)
+def test_tile_variants(spec, n, k, lanes, monkeypatch):
+    say("tile variant", spec, n, k, lanes)
+    monkeypatch.setenv("FNTRS_TILES", spec)
+    c = fntrs.Context(0)
+    try:
+        src = synth.source(7000 + n + k, 2, k, lanes)
+        out = gpu_encode(c, src, n, pad=1)
+        rows = np.arange(0, n, max(1, n // 128))
+        for b in range(2):
+            assert np.array_equal(out[b][rows], codec.encode(src[b], n, rows=rows))
+        z = pattern("random" if k < n else "all", n, k, 7001 + n)
+        loc = c.locator(n, k, z)
+        got = gpu_decode(c, loc, out[:, z, :])
+        assert np.array_equal(got, src.astype(np.int64))
+        loc.release()
+    finally:
+        torch.cuda.synchronize()
+        c.close()
+
+
+@pytest.mark.parametrize("n,k", [(8192, 4096), (4096, 1024), (16384, 8192)])
+def test_extreme_inputs(ctx, n, k):
+    """All inputs at the largest residue 65536 (or alternating with 0): the
+    largest magnitudes the lazy arithmetic meets."""
+    say("extreme inputs", n, k)
+    src = np.full((1, k, 8), 65536, dtype=np.uint32)
+    src[0, 1::2, ::2] = 0
+    out = gpu_encode(ctx, src, n)
+    rows = np.arange(0, n, 61)
+    assert np.array_equal(out[0][rows], codec.encode(src[0], n, rows=rows))
+    z = synth.received_positions(n + 5, n, k)
+    recv = np.full((1, k, 4), 65536, dtype=np.uint32)
+    recv[0, ::2, 1] = 0
+    loc = ctx.locator(n, k, z)
+    got = gpu_decode(ctx, loc, recv)[0]
+    if k <= 4096:
+        assert np.array_equal(got, codec.decode_lagrange(n, z, recv[0]))
+    # re-encoding the decoded polynomial reproduces the received values
+    re = gpu_encode(ctx, got[None].astype(np.uint32), n)[0]
+    assert np.array_equal(re[z.astype(np.int64)], recv[0].astype(np.int64))
+    loc.release()
