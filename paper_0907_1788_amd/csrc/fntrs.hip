@@ -18,6 +18,7 @@
 #include "../../include/fntrs.h"
 #include "locator_kernels.hpp"
 #include "ct_launch.hpp"
+#include "fourstep_launch.hpp"
 
 using namespace fntrs;
 
@@ -38,7 +39,7 @@ struct fntrs_locator_s {
   uint64_t key = 0;
   uint32_t* mem = nullptr;           // one device allocation, views below
   size_t bytes = 0;
-  uint32_t *pos = nullptr, *wfull = nullptr, *ridx = nullptr, *ahat_br = nullptr;
+  uint32_t *pos = nullptr, *wfull = nullptr, *ridx = nullptr, *ahat_br = nullptr, *ahat_s = nullptr;
   uint32_t *A = nullptr, *w = nullptr, *ahat = nullptr;
   hipEvent_t ready = nullptr;        // recorded after the build on its stream
   int refs = 0;
@@ -172,9 +173,9 @@ int build_locator(fntrs_ctx* c, fntrs_locator_t* L, hipStream_t s) {
   const uint32_t n = L->n, k = L->k;
   const int logn = L->logn, logk = L->logk;
   const size_t M = (k < n) ? (size_t)1 << L->logm : 0;
-  // device layout: pos[k] wfull[n] ridx[n] ahat_br[M] A[k+1] w[k] ahat[M]
+  // device layout: pos[k] wfull[n] ridx[n] ahat_br[M] ahat_s[M] A[k+1] w[k] ahat[M]
   //                | scratch: t0[k] t1[k] spec[k] vals[n]
-  const size_t state = k + 2ull * n + M + (k + 1) + k + M;
+  const size_t state = k + 2ull * n + 2 * M + (k + 1) + k + M;
   const size_t scratch = (k < n) ? 3ull * k + n : 0;
   L->bytes = (state + scratch) * 4;
   if (!make_room(c, L->bytes))
@@ -191,6 +192,7 @@ int build_locator(fntrs_ctx* c, fntrs_locator_t* L, hipStream_t s) {
   L->wfull = p; p += n;
   L->ridx = p; p += n;
   L->ahat_br = p; p += M;
+  L->ahat_s = p; p += M;
   L->A = p; p += k + 1;
   L->w = p; p += k;
   L->ahat = p; p += M;
@@ -245,7 +247,8 @@ int build_locator(fntrs_ctx* c, fntrs_locator_t* L, hipStream_t s) {
     // copy, bit-reversed and scaled by M^-1.
     hipLaunchKernelGGL(k_loc_eval, dim3((uint32_t)(M / k)), dim3(ntk), ldsk, s, cur, logk, L->logm, c->tw, L->ahat);
     HIP_TRY(c, hipGetLastError());
-    hipLaunchKernelGGL(k_loc_ahat, dim3((uint32_t)((M + 255) / 256)), dim3(256), 0, s, L->ahat, L->logm, L->ahat_br);
+    hipLaunchKernelGGL(k_loc_ahat, dim3((uint32_t)((M + 255) / 256)), dim3(256), 0, s, L->ahat, L->logm, L->ahat_br,
+                       L->ahat_s);
     HIP_TRY(c, hipGetLastError());
   }
   HIP_TRY(c, hipEventCreateWithFlags(&L->ready, hipEventDisableTiming));
@@ -374,8 +377,25 @@ int fntrs_encode(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uin
   a.n = n; a.k = k; a.lanes = lanes;
   a.logn = ilog2(n);
   a.logK = std::max(1, ilog2(k));        // transform size K: smallest power of two >= k, at least 2
-  if (a.logK > 15)
-    return fail(c, FNTRS_E_UNSUPPORTED, "encode with k=%u > 32768 needs a transform larger than one tile", k);
+  if (a.logK == 16) {
+    // K = n = 65536: four-step transform through a scratch buffer
+    FourStepArgs f{};
+    f.in = src; f.ld_in = ld_src; f.stride_in = stride_src;
+    f.out = dst; f.ld_out = ld_dst; f.stride_out = stride_dst;
+    f.tw = c->tw; f.twi = c->twi;
+    f.n = n; f.k = k; f.M = n; f.lanes = lanes; f.logn = 16; f.logm = 16;
+    f.tiles = (lanes + kFourStepTile - 1) / kFourStepTile;
+    const uint64_t lds = (uint64_t)f.tiles * kFourStepTile;
+    f.vec = aligned16(src, ld_src, stride_src) && aligned16(dst, ld_dst, stride_dst);
+    uint32_t* sa = nullptr;
+    const size_t bytes = (size_t)batch * n * lds * 4;
+    hipError_t e = hipMallocAsync((void**)&sa, bytes, s);
+    if (e != hipSuccess) return fail(c, FNTRS_E_NOMEM, "scratch of %zu bytes: %s", bytes, hipGetErrorString(e));
+    e = fourstep_encode(f, batch, sa, lds, s);
+    (void)hipFreeAsync(sa, s);
+    HIP_TRY(c, e);
+    return FNTRS_OK;
+  }
   const CtCfg cfg = c->enc_cfg[a.logK];
   a.vec = aligned16(src, ld_src, stride_src) && aligned16(dst, ld_dst, stride_dst);
   a.tiles = (lanes + cfg.T - 1) / cfg.T;
@@ -403,8 +423,6 @@ int fntrs_locator(fntrs_ctx* c, uint32_t n, uint32_t k, const uint32_t* position
       return fail(c, FNTRS_E_POSITIONS, "positions must be strictly ascending (index %u)", i);
   }
   if (!is_pow2(k)) return fail(c, FNTRS_E_UNSUPPORTED, "decoding needs k a power of two, got %u", k);
-  if (n > 32768)
-    return fail(c, FNTRS_E_UNSUPPORTED, "decoding n=%u needs a transform larger than one tile (n <= 32768)", n);
   const uint64_t key = hash_positions(n, k, positions);
   auto range = c->cache.equal_range(key);
   for (auto it = range.first; it != range.second; ++it) {
@@ -491,6 +509,27 @@ int fntrs_decode(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, uint32_
   HIP_TRY(c, hipStreamWaitEvent(s, L->ready, 0));
   if (n == 1) {  // k = n = 1: s_0 = e_0
     HIP_TRY(c, launch_copy(recv, stride_recv, dst, stride_dst, lanes, batch, s));
+    return FNTRS_OK;
+  }
+  if (L->logn == 16) {
+    FourStepArgs f{};
+    f.in = recv; f.ld_in = ld_recv; f.stride_in = stride_recv;
+    f.out = dst; f.ld_out = ld_dst; f.stride_out = stride_dst;
+    f.tw = c->tw; f.twi = c->twi; f.wfull = L->wfull; f.ridx = L->ridx; f.ahat = L->ahat_s;
+    f.n = n; f.k = k; f.lanes = lanes; f.logn = 16;
+    f.logm = (k == n) ? 16 : L->logm;
+    f.M = 1u << f.logm;
+    f.full = full ? 1u : 0u;
+    f.tiles = (lanes + kFourStepTile - 1) / kFourStepTile;
+    const uint64_t lds = (uint64_t)f.tiles * kFourStepTile;
+    f.vec = aligned16(recv, ld_recv, stride_recv) && aligned16(dst, ld_dst, stride_dst);
+    uint32_t* sa = nullptr;
+    const size_t bytes = (size_t)batch * (n + f.M) * lds * 4;
+    hipError_t e = hipMallocAsync((void**)&sa, bytes, s);
+    if (e != hipSuccess) return fail(c, FNTRS_E_NOMEM, "scratch of %zu bytes: %s", bytes, hipGetErrorString(e));
+    e = fourstep_decode(f, batch, sa, sa + (size_t)batch * n * lds, lds, s);
+    (void)hipFreeAsync(sa, s);
+    HIP_TRY(c, e);
     return FNTRS_OK;
   }
   DecodeArgs a;

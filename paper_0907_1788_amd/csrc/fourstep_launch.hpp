@@ -1,0 +1,37 @@
+// Host entry points of the four-step (n = 65536) kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "codec_args.hpp"
+
+namespace fntrs {
+
+struct FourStepArgs {
+  const uint32_t* in;       // first-pass input (recv / src) or scratch
+  uint64_t ld_in, stride_in;
+  uint32_t* out;            // scratch or final output
+  uint64_t ld_out, stride_out;
+  const uint32_t* tw;       // 3^e
+  const uint32_t* twi;      // 3^-e
+  const uint32_t* wfull;    // decoder weights per position
+  const uint32_t* ridx;     // compact recv row per position
+  const uint32_t* ahat;     // FNT_M(A mod x^k) / M, natural order
+  uint32_t n, k, M, lanes;
+  int logn, logm;
+  uint32_t full, tiles, subs, vec;   // subs: sub-transforms per block
+};
+
+// Lanes per tile of the four-step kernels.
+constexpr int kFourStepTile = 32;
+
+// Decoder for n = 65536: `base` carries recv (in), dst (out), the tables and
+// sizes (n, k, M, logn, logm, lanes, full, tiles, vec); sa (n rows) and sb
+// (M rows) are scratch buffers [batch][rows][ld_scratch].
+hipError_t fourstep_decode(const FourStepArgs& base, uint32_t batch, uint32_t* sa, uint32_t* sb,
+                           uint64_t ld_scratch, hipStream_t s);
+// Encoder for K = n = 65536: `base` carries src (in) and dst (out); sa is a
+// scratch buffer of n rows per block.
+hipError_t fourstep_encode(const FourStepArgs& base, uint32_t batch, uint32_t* sa, uint64_t ld_scratch,
+                           hipStream_t s);
+
+}  // namespace fntrs

@@ -120,13 +120,17 @@ __global__ void k_loc_weights(const uint32_t* __restrict__ pos, const uint32_t* 
   ridx[z] = i;
 }
 
-// Â for step 6 in bit-reversed order with the inverse-transform factor
-// M^-1 folded in (M = 2^logm is the cyclic length of the low product).
-__global__ void k_loc_ahat(const uint32_t* __restrict__ ahat, int logm, uint32_t* __restrict__ ahat_br) {
+// Â for step 6 with the inverse-transform factor M^-1 folded in (M = 2^logm
+// is the cyclic length of the low product), in bit-reversed and in natural
+// order.
+__global__ void k_loc_ahat(const uint32_t* __restrict__ ahat, int logm, uint32_t* __restrict__ ahat_br,
+                           uint32_t* __restrict__ ahat_s) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (1u << logm)) return;
   const uint32_t inv = 65537u - (65536u >> logm);           // (2^logm)^-1 = -2^(16-logm)
-  ahat_br[bitrev(i, logm)] = fmul(ahat[i], inv);
+  const uint32_t v = fmul(ahat[i], inv);
+  ahat_br[bitrev(i, logm)] = v;
+  ahat_s[i] = v;
 }
 
 // Decoder tables when nothing is erased (k = n): weight n^-1, row z.

@@ -268,3 +268,59 @@ def test_extreme_inputs(ctx, n, k):
     re = gpu_encode(ctx, got[None].astype(np.uint32), n)[0]
     assert np.array_equal(re[z.astype(np.int64)], recv[0].astype(np.int64))
     loc.release()
+
+
+# ------------------------------------------------------------------ n = 65536 (four-step path)
+@pytest.mark.parametrize("k,lanes", [(40000, 33), (65536, 8)])
+def test_encode_max_length_fourstep(ctx, k, lanes):
+    say("encode four-step", 65536, k, lanes)
+    n = 65536
+    src = synth.residues(8100 + k, (1, k, lanes))
+    out = gpu_encode(ctx, src, n, pad=3)
+    rows = np.unique(np.concatenate([[0, 1, 255, 256, n - 1], synth.stream(k, 16) % np.uint64(n)]).astype(np.int64))
+    assert np.array_equal(out[0][rows], codec.encode(src[0], n, rows=rows))
+
+
+@pytest.mark.parametrize("kind", ["random", "first"])
+def test_max_length_config(ctx, kind):
+    """k = 32768, n = 65536, 512 lanes, with a uniform random erasure pattern and
+    with every erasure among the first k positions."""
+    say("max-length config", kind)
+    n, k, lanes = 65536, 32768, 512
+    src = synth.source(8200, 1, k, lanes)
+    e = gpu_encode(ctx, src, n)
+    rows = np.unique(np.concatenate([[0, n // 2, n - 1], synth.stream(8201, 13) % np.uint64(n)]).astype(np.int64))
+    assert np.array_equal(e[0][rows], codec.encode(src[0], n, rows=rows))
+    z = pattern(kind, n, k, 8202)
+    loc = ctx.locator(n, k, z)
+    got = gpu_decode(ctx, loc, e[:, z, :])
+    assert np.array_equal(got, src.astype(np.int64))                  # every lane
+    got_full = gpu_decode(ctx, loc, e, fntrs.FNTRS_RECV_FULL)
+    assert np.array_equal(got_full, src.astype(np.int64))
+    loc.release()
+
+
+@pytest.mark.parametrize("k", [16384, 65536, 2048])
+def test_max_length_other_rates(ctx, k):
+    say("max-length rate", k)
+    n, lanes = 65536, 40
+    src = synth.source(8300 + k, 2, k, lanes)
+    e = gpu_encode(ctx, src, n)
+    z = synth.received_positions(8301 + k, n, k) if k < n else np.arange(n, dtype=np.uint32)
+    loc = ctx.locator(n, k, z)
+    got = gpu_decode(ctx, loc, e[:, z, :])
+    assert np.array_equal(got, src.astype(np.int64))
+    loc.release()
+
+
+@pytest.mark.slow
+def test_max_length_decode_matches_oracle(ctx):
+    """Decode of non-codeword received values equals the Lagrange interpolant (one lane)."""
+    say("max-length decode vs oracle")
+    n, k = 65536, 32768
+    z = synth.received_positions(8400, n, k)
+    v = synth.residues(8401, (1, k, 1))
+    loc = ctx.locator(n, k, z)
+    got = gpu_decode(ctx, loc, v)[0]
+    loc.release()
+    assert np.array_equal(got, codec.decode_lagrange(n, z, v[0]))
