@@ -136,6 +136,87 @@ int fntrs_decode(fntrs_ctx* ctx, const fntrs_locator_t* loc, uint32_t lanes, uin
                  uint32_t* dst, size_t ld_dst, size_t stride_dst,
                  uint32_t batch, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batched path: uneven batches of encode and decode jobs.
+ *
+ * A job carries the arguments of one fntrs_encode or fntrs_decode call.  Its
+ * result is bit-identical to that call's: the batch changes how the work is
+ * launched, not what is computed.  Jobs of one size class (encode: transform
+ * size K = 2^ceil(log2 k); decode: code length n and product length) share
+ * one persistent launch whose workgroups walk a device-side table of the
+ * class's jobs; the classes run concurrently on internal streams of default
+ * priority and are joined back into the caller's stream.
+ * ------------------------------------------------------------------------ */
+
+#define FNTRS_OP_ENCODE 0u
+#define FNTRS_OP_DECODE 1u
+
+typedef struct fntrs_job {
+  uint32_t op;                 /* FNTRS_OP_ENCODE or FNTRS_OP_DECODE */
+  uint32_t n, k;               /* encode: code length and source symbols (the
+                                  rules of fntrs_encode); decode: 0, or equal
+                                  to the locator's n and k */
+  uint32_t lanes, batch;       /* lanes per row, codeword blocks */
+  uint32_t flags;              /* encode: 0; decode: FNTRS_RECV_COMPACT or
+                                  FNTRS_RECV_FULL (FNTRS_FLAG_VALIDATE is
+                                  rejected: it would synchronise the batch) */
+  const fntrs_locator_t* loc;  /* decode: locator of the received positions;
+                                  encode: NULL */
+  const uint32_t* in;          /* encode: src [batch][k][ld_in];
+                                  decode: recv [batch][k or n][ld_in] */
+  size_t ld_in, stride_in;
+  uint32_t* out;               /* encode: dst [batch][n][ld_out];
+                                  decode: dst [batch][k][ld_out] */
+  size_t ld_out, stride_out;
+} fntrs_job;
+
+/* Enqueue `njobs` jobs on `stream` (asynchronous, like the single calls).
+ * The job array is read before the call returns; data buffers and locators
+ * must stay valid until the stream reaches the batch.  Every job is checked
+ * as its single call would be; in addition no job's output may overlap any
+ * other job's input or output.  A working buffer for the job tables (and the
+ * scratch of n = 65536 jobs, which run one after another) is allocated
+ * stream-ordered and freed after the batch.  Errors: FNTRS_E_INVAL (with the
+ * job index in fntrs_last_error), FNTRS_E_NOMEM, FNTRS_E_DEVICE. */
+int fntrs_submit(fntrs_ctx* ctx, const fntrs_job* jobs, uint32_t njobs, void* stream);
+
+/* A batch captured once into a HIP graph and replayed many times on the same
+ * buffers (whose contents may change between replays).  The graph owns its
+ * job tables and scratch (counted against the context's cap) and holds a
+ * reference to every locator it reads until it is destroyed. */
+typedef struct fntrs_graph_s fntrs_graph_t;
+
+/* Checks and plans the batch as fntrs_submit does, then captures it.  The
+ * kernel configuration of each size class is frozen at capture time.
+ * Errors: as fntrs_submit; FNTRS_E_INVAL also for an empty batch. */
+int fntrs_graph_create(fntrs_ctx* ctx, const fntrs_job* jobs, uint32_t njobs, fntrs_graph_t** out);
+
+/* Replays the batch on `stream` (after the builds of its locators). */
+int fntrs_graph_launch(fntrs_ctx* ctx, fntrs_graph_t* graph, void* stream);
+
+/* Frees the graph (waits for replays in flight) and its locator references. */
+int fntrs_graph_destroy(fntrs_ctx* ctx, fntrs_graph_t* graph);
+
+/* Kernel configuration of one transform size. */
+typedef struct fntrs_tuning {
+  uint32_t tile_lanes;   /* lanes per workgroup tile */
+  uint32_t threads;      /* threads per workgroup */
+  uint32_t radix_log2;   /* largest radix of the LDS passes, as log2 */
+  float ms;              /* autotune: mean time of the chosen kernel per launch */
+} fntrs_tuning;
+
+/* Autotuner: times every compiled configuration of the size class of
+ * (op, n, k) on `lanes` x `batch` scratch codewords, `reps` launches each
+ * (synchronous), and makes the fastest the context's configuration for that
+ * class, used by later single calls, batches and graphs.  n <= 32768.
+ * Errors: FNTRS_E_INVAL, FNTRS_E_UNSUPPORTED (decode with k not a power of
+ * two), FNTRS_E_NOMEM, FNTRS_E_DEVICE. */
+int fntrs_autotune(fntrs_ctx* ctx, uint32_t op, uint32_t n, uint32_t k, uint32_t lanes, uint32_t batch,
+                   uint32_t reps, void* stream, fntrs_tuning* chosen);
+
+/* Current configuration of transform size 2^log2_size (1..15) for op. */
+int fntrs_get_config(fntrs_ctx* ctx, uint32_t op, uint32_t log2_size, fntrs_tuning* cfg);
+
 /* Library version string. */
 const char* fntrs_version(void);
 

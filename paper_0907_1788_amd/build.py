@@ -1,7 +1,8 @@
 """Builds libfntrs.so in-tree with hipcc for gfx950.
 
-The library is one host translation unit (fntrs.hip: C ABI and locator
-kernels) plus one translation unit per transform size for the
+The library is two host translation units (fntrs.hip: C ABI and locator
+kernels; submit.hip: batches, graphs, autotuner) plus one translation unit
+per transform size for the
 compile-time kernels (ct_inst.hip with -DFNTRS_L=1..15), plus the
 four-step kernels for n = 65536 (fourstep.hip).  They compile in
 parallel into paper_0907_1788_amd/_build/ and link into libfntrs.so.
@@ -43,6 +44,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     """Compile every HIP translation unit and link the shared library."""
     os.makedirs(BUILD, exist_ok=True)
     units = [(os.path.join(CSRC, "fntrs.hip"), os.path.join(BUILD, "fntrs.o"), []),
+             (os.path.join(CSRC, "submit.hip"), os.path.join(BUILD, "submit.o"), []),
              (os.path.join(CSRC, "fourstep.hip"), os.path.join(BUILD, "fourstep.o"), [])]
     for L in SIZES:
         units.append((os.path.join(CSRC, "ct_inst.hip"), os.path.join(BUILD, f"ct_{L}.o"), [f"-DFNTRS_L={L}"]))

@@ -64,4 +64,15 @@ struct DecodeArgs {
   uint32_t tiles, vec;
 };
 
+// Work table of the batched path: the jobs of one class (one transform size,
+// one kernel configuration) share a persistent launch; job j owns the work
+// items [start[j], start[j+1]), numbered as the single-job grid numbers its
+// workgroups.
+template <class Args>
+struct JobTable {
+  const Args* jobs;
+  const uint32_t* start;    // njobs + 1 ascending entries, start[0] = 0
+  uint32_t njobs, total;    // total = start[njobs]
+};
+
 }  // namespace fntrs

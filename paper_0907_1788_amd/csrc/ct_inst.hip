@@ -40,6 +40,57 @@ hipError_t dec_t(int D, const DecodeArgs& a, uint32_t blocks, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+template <int L, int T, int NT>
+hipError_t enc_tab_one(const JobTable<EncodeArgs>& t, const uint32_t* tw, const uint32_t* twi, uint32_t grid,
+                       hipStream_t s) {
+  constexpr size_t lds = ct::Geo<L, T, NT>::LDS_BYTES;
+  (void)hipFuncSetAttribute((const void*)ct::k_enc_tab<L, T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+  hipLaunchKernelGGL((ct::k_enc_tab<L, T, NT>), dim3(grid), dim3(NT), lds, s, t, tw, twi);
+  return hipGetLastError();
+}
+
+template <int L, int D, int T, int NT>
+hipError_t dec_tab_one(const JobTable<DecodeArgs>& t, const uint32_t* tw, const uint32_t* twi, uint32_t grid,
+                       hipStream_t s) {
+  constexpr size_t lds = ct::Geo<L, T, NT>::LDS_BYTES;
+  (void)hipFuncSetAttribute((const void*)ct::k_dec_tab<L, D, T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+  hipLaunchKernelGGL((ct::k_dec_tab<L, D, T, NT>), dim3(grid), dim3(NT), lds, s, t, tw, twi);
+  return hipGetLastError();
+}
+
+template <int L, int T, int NT>
+hipError_t dec_tab_t(int D, const JobTable<DecodeArgs>& t, const uint32_t* tw, const uint32_t* twi, uint32_t grid,
+                     hipStream_t s) {
+  if (D == -1) return dec_tab_one<L, -1, T, NT>(t, tw, twi, grid, s);
+  if (D == 0) return dec_tab_one<L, 0, T, NT>(t, tw, twi, grid, s);
+  if constexpr (L > 1) {
+    if (D == 1) return dec_tab_one<L, 1, T, NT>(t, tw, twi, grid, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <class K>
+int occupancy(K kernel, int NT, size_t lds) {
+  int nb = 0;
+  (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, NT, lds) != hipSuccess) return 0;
+  return nb;
+}
+
+template <int L, int T, int NT>
+int occ_t(int op, int D) {
+  constexpr size_t lds = ct::Geo<L, T, NT>::LDS_BYTES;
+  if (op == 0) return occupancy(ct::k_enc_tab<L, T, NT>, NT, lds);
+  if (D == -1) return occupancy(ct::k_dec_tab<L, -1, T, NT>, NT, lds);
+  if (D == 0) return occupancy(ct::k_dec_tab<L, 0, T, NT>, NT, lds);
+  if constexpr (L > 1) {
+    if (D == 1) return occupancy(ct::k_dec_tab<L, 1, T, NT>, NT, lds);
+  }
+  return 0;
+}
+
 constexpr CtVariants kVar = ct_variants(FNTRS_L);
 
 template <int I>
@@ -64,6 +115,46 @@ hipError_t dec_pick(CtCfg c, int D, const DecodeArgs& a, uint32_t blocks, hipStr
   }
 }
 
+template <int I>
+hipError_t enc_tab_pick(CtCfg c, const JobTable<EncodeArgs>& t, const uint32_t* tw, const uint32_t* twi,
+                        uint32_t grid, hipStream_t s) {
+  if constexpr (I < 4 && kVar.enc[I < 4 ? I : 0].T != 0) {
+    if (c.T == kVar.enc[I].T && c.NT == kVar.enc[I].NT)
+      return enc_tab_one<FNTRS_L, kVar.enc[I].T, kVar.enc[I].NT>(t, tw, twi, grid, s);
+    return enc_tab_pick<I + 1>(c, t, tw, twi, grid, s);
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int I>
+hipError_t dec_tab_pick(CtCfg c, int D, const JobTable<DecodeArgs>& t, const uint32_t* tw, const uint32_t* twi,
+                        uint32_t grid, hipStream_t s) {
+  if constexpr (I < 4 && kVar.dec[I < 4 ? I : 0].T != 0) {
+    if (c.T == kVar.dec[I].T && c.NT == kVar.dec[I].NT)
+      return dec_tab_t<FNTRS_L, kVar.dec[I].T, kVar.dec[I].NT>(D, t, tw, twi, grid, s);
+    return dec_tab_pick<I + 1>(c, D, t, tw, twi, grid, s);
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int I>
+int occ_pick(CtCfg c, int op, int D) {
+  if constexpr (I < 4) {
+    constexpr CtCfg e = kVar.enc[I], d = kVar.dec[I];
+    if constexpr (e.T != 0) {
+      if (op == 0 && c.T == e.T && c.NT == e.NT) return occ_t<FNTRS_L, e.T, e.NT>(0, D);
+    }
+    if constexpr (d.T != 0) {
+      if (op == 1 && c.T == d.T && c.NT == d.NT) return occ_t<FNTRS_L, d.T, d.NT>(1, D);
+    }
+    return occ_pick<I + 1>(c, op, D);
+  } else {
+    return 0;
+  }
+}
+
 }  // namespace
 
 #define FNTRS_CAT2(a, b) a##b
@@ -76,5 +167,17 @@ hipError_t FNTRS_CAT(ct_enc_launch_, FNTRS_L)(CtCfg c, const EncodeArgs& a, uint
 hipError_t FNTRS_CAT(ct_dec_launch_, FNTRS_L)(CtCfg c, int D, const DecodeArgs& a, uint32_t blocks, hipStream_t s) {
   return dec_pick<0>(c, D, a, blocks, s);
 }
+
+hipError_t FNTRS_CAT(ct_enc_tab_launch_, FNTRS_L)(CtCfg c, const JobTable<EncodeArgs>& t, const uint32_t* tw,
+                                                  const uint32_t* twi, uint32_t grid, hipStream_t s) {
+  return enc_tab_pick<0>(c, t, tw, twi, grid, s);
+}
+
+hipError_t FNTRS_CAT(ct_dec_tab_launch_, FNTRS_L)(CtCfg c, int D, const JobTable<DecodeArgs>& t, const uint32_t* tw,
+                                                  const uint32_t* twi, uint32_t grid, hipStream_t s) {
+  return dec_tab_pick<0>(c, D, t, tw, twi, grid, s);
+}
+
+int FNTRS_CAT(ct_tab_occupancy_, FNTRS_L)(CtCfg c, int op, int D) { return occ_pick<0>(c, op, D); }
 
 }  // namespace fntrs

@@ -167,27 +167,59 @@ struct EncStore {
 };
 
 // Encoder, Sec. II-B: e_i = s(r_n^i).  Output row t + (n/K) m is output m of
-// FNT_K of (s_j r_n^(t j))_j (r_n^(n/K) = r_K), one workgroup per
-// (coset t, lane tile, block).
-template <int LK, int TT, int NT>
-__global__ void __launch_bounds__(NT) k_enc(EncodeArgs a) {
+// FNT_K of (s_j r_n^(t j))_j (r_n^(n/K) = r_K), one work item per
+// (coset t, lane tile, block), coset fastest.
+template <int LK, int TT, int NT, class TW>
+__device__ __forceinline__ void enc_item(const EncodeArgs& a, uint32_t item, uint32_t* lds, const TW& tws) {
   using Gm = Geo<LK, TT, NT>;
   constexpr int V = Gm::V, G = Gm::G, T = Gm::T;
-  extern __shared__ uint32_t lds[];
-  uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
-  const uint32_t t = bid % a.cosets;
-  bid /= a.cosets;
-  const uint32_t tile = bid % a.tiles;
-  const uint64_t blk = bid / a.tiles;
+  const uint32_t t = item % a.cosets;
+  item /= a.cosets;
+  const uint32_t tile = item % a.tiles;
+  const uint64_t blk = item / a.tiles;
   const uint32_t lane0 = tile * T;
   EncLoad<LK, V> l0{a.src + blk * a.stride_src + lane0, a.tw, a.ld_src, a.k, a.n, t, lane0, a.lanes,
                     16 - a.logn, a.vec != 0};
   LdsLoad<V, G> lm{lds};
   LdsStore<V, G, false> sm{lds};
   EncStore<V> sl{a.dst + blk * a.stride_dst + lane0, a.ld_dst, t, a.cosets, lane0, a.lanes, a.vec != 0};
-  using TW = typename Gm::TwType;
-  const TW tws = make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
   dit<LK, Gm::BM, V, G, false>(tws, l0, lm, sm, sl);
+}
+
+template <int LK, int TT, int NT>
+__global__ void __launch_bounds__(NT) k_enc(EncodeArgs a) {
+  using Gm = Geo<LK, TT, NT>;
+  using TW = typename Gm::TwType;
+  extern __shared__ uint32_t lds[];
+  const TW tws = make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
+  enc_item<LK, TT, NT>(a, xcd_remap(blockIdx.x, gridDim.x), lds, tws);
+}
+
+// Job of work item w: the last j with start[j] <= w (uniform per workgroup).
+__device__ __forceinline__ uint32_t find_job(const uint32_t* start, uint32_t njobs, uint32_t w) {
+  uint32_t lo = 0, hi = njobs;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (start[mid] <= w) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Batched encoder: a persistent grid walks the work items of every job of
+// one transform size; the LDS twiddle tables are filled once per workgroup.
+template <int LK, int TT, int NT>
+__global__ void __launch_bounds__(NT) k_enc_tab(JobTable<EncodeArgs> t, const uint32_t* tw, const uint32_t* twi) {
+  using Gm = Geo<LK, TT, NT>;
+  using TW = typename Gm::TwType;
+  extern __shared__ uint32_t lds[];
+  const TW tws = make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, tw, twi);
+  for (uint32_t w = xcd_remap(blockIdx.x, gridDim.x); w < t.total; w += gridDim.x) {
+    const uint32_t j = find_job(t.start, t.njobs, w);
+    const EncodeArgs a = t.jobs[j];
+    enc_item<LK, TT, NT>(a, w - t.start[j], lds, tws);
+    __syncthreads();   // the next item overwrites the LDS tile
+  }
 }
 
 // ---------------------------------------------------------------- decoder
@@ -289,22 +321,18 @@ struct SourceStore {
 // No permutation passes through LDS between the three transforms.
 // D = -1 is the erasure-free case k = n (Sec. II-B): the weights are n^-1
 // and the inverse FNT_n alone is the decoder.
-template <int LN, int D, int TT, int NT>
-__global__ void __launch_bounds__(NT) k_dec(DecodeArgs a) {
+template <int LN, int D, int TT, int NT, class TW>
+__device__ __forceinline__ void dec_item(const DecodeArgs& a, uint32_t item, uint32_t* lds, const TW& tws) {
   using Gm = Geo<LN, TT, NT>;
   constexpr int V = Gm::V, G = Gm::G, T = Gm::T;
-  extern __shared__ uint32_t lds[];
-  const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
-  const uint32_t tile = bid % a.tiles;
-  const uint64_t blk = bid / a.tiles;
+  const uint32_t tile = item % a.tiles;
+  const uint64_t blk = item / a.tiles;
   const uint32_t lane0 = tile * T;
   DecLoad<LN, V> lg{a.recv + blk * a.stride_recv + lane0, a.wfull, a.ridx, a.ld_recv, lane0, a.lanes,
                     a.full != 0, a.vec != 0};
   LdsLoad<V, G> ll{lds};
   LdsStore<V, G, false> sl{lds};
   SourceStore<V> sg{a.dst + blk * a.stride_dst + lane0, a.ld_dst, a.k, lane0, a.lanes, a.vec != 0};
-  using TW = typename Gm::TwType;
-  const TW tws = make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
   if constexpr (D < 0) {
     dit<LN, Gm::BM, V, G, true>(tws, lg, ll, sl, sg);
   } else {
@@ -315,6 +343,31 @@ __global__ void __launch_bounds__(NT) k_dec(DecodeArgs a) {
     dit<LN, Gm::BM, V, G, true>(tws, lg, ll, sl, ss);
     dif<L2, Gm::BM, V, G, false>(tws, ll, ll, slf, sp);
     dit<L2, Gm::BM, V, G, true>(tws, ll, ll, sl, sg);
+  }
+}
+
+template <int LN, int D, int TT, int NT>
+__global__ void __launch_bounds__(NT) k_dec(DecodeArgs a) {
+  using Gm = Geo<LN, TT, NT>;
+  using TW = typename Gm::TwType;
+  extern __shared__ uint32_t lds[];
+  const TW tws = make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
+  dec_item<LN, D, TT, NT>(a, xcd_remap(blockIdx.x, gridDim.x), lds, tws);
+}
+
+// Batched decoder: as k_enc_tab, for decode jobs of one code length n and
+// one product length M = n / 2^D, each with its own locator.
+template <int LN, int D, int TT, int NT>
+__global__ void __launch_bounds__(NT) k_dec_tab(JobTable<DecodeArgs> t, const uint32_t* tw, const uint32_t* twi) {
+  using Gm = Geo<LN, TT, NT>;
+  using TW = typename Gm::TwType;
+  extern __shared__ uint32_t lds[];
+  const TW tws = make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, tw, twi);
+  for (uint32_t w = xcd_remap(blockIdx.x, gridDim.x); w < t.total; w += gridDim.x) {
+    const uint32_t j = find_job(t.start, t.njobs, w);
+    const DecodeArgs a = t.jobs[j];
+    dec_item<LN, D, TT, NT>(a, w - t.start[j], lds, tws);
+    __syncthreads();
   }
 }
 

@@ -37,9 +37,24 @@ constexpr CtVariants ct_variants(int L) {
 using CtEncLaunch = hipError_t (*)(CtCfg cfg, const EncodeArgs& a, uint32_t blocks, hipStream_t s);
 using CtDecLaunch = hipError_t (*)(CtCfg cfg, int D, const DecodeArgs& a, uint32_t blocks, hipStream_t s);
 
-#define FNTRS_CT_DECL(L)                                                                        \
-  hipError_t ct_enc_launch_##L(CtCfg cfg, const EncodeArgs& a, uint32_t blocks, hipStream_t s);     \
-  hipError_t ct_dec_launch_##L(CtCfg cfg, int D, const DecodeArgs& a, uint32_t blocks, hipStream_t s);
+// Batched (table) launches: a persistent grid of `grid` workgroups walks the
+// work items of every job in the table (k_enc_tab / k_dec_tab).
+using CtEncTabLaunch = hipError_t (*)(CtCfg cfg, const JobTable<EncodeArgs>& t, const uint32_t* tw,
+                                      const uint32_t* twi, uint32_t grid, hipStream_t s);
+using CtDecTabLaunch = hipError_t (*)(CtCfg cfg, int D, const JobTable<DecodeArgs>& t, const uint32_t* tw,
+                                      const uint32_t* twi, uint32_t grid, hipStream_t s);
+// Workgroups of the table kernel that fit on one CU at once (0 when the
+// configuration is not instantiated); op 0 = encode, 1 = decode.
+using CtTabOccupancy = int (*)(CtCfg cfg, int op, int D);
+
+#define FNTRS_CT_DECL(L)                                                                              \
+  hipError_t ct_enc_launch_##L(CtCfg cfg, const EncodeArgs& a, uint32_t blocks, hipStream_t s);           \
+  hipError_t ct_dec_launch_##L(CtCfg cfg, int D, const DecodeArgs& a, uint32_t blocks, hipStream_t s);    \
+  hipError_t ct_enc_tab_launch_##L(CtCfg cfg, const JobTable<EncodeArgs>& t, const uint32_t* tw,          \
+                                   const uint32_t* twi, uint32_t grid, hipStream_t s);                    \
+  hipError_t ct_dec_tab_launch_##L(CtCfg cfg, int D, const JobTable<DecodeArgs>& t, const uint32_t* tw,   \
+                                   const uint32_t* twi, uint32_t grid, hipStream_t s);                    \
+  int ct_tab_occupancy_##L(CtCfg cfg, int op, int D);
 FNTRS_CT_DECL(1) FNTRS_CT_DECL(2) FNTRS_CT_DECL(3) FNTRS_CT_DECL(4) FNTRS_CT_DECL(5)
 FNTRS_CT_DECL(6) FNTRS_CT_DECL(7) FNTRS_CT_DECL(8) FNTRS_CT_DECL(9) FNTRS_CT_DECL(10)
 FNTRS_CT_DECL(11) FNTRS_CT_DECL(12) FNTRS_CT_DECL(13) FNTRS_CT_DECL(14) FNTRS_CT_DECL(15)

@@ -3,66 +3,13 @@
 // Validation happens here, synchronously, before anything is enqueued; the
 // coding work itself runs in the compile-time kernels (ct_kernels.hpp, one
 // translation unit per transform size) and the locator kernels
-// (locator_kernels.hpp).
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <cstdarg>
-#include <cstdio>
-#include <cstring>
-#include <mutex>
-#include <string>
-#include <unordered_map>
-#include <vector>
-
-#include "../../include/fntrs.h"
+// (locator_kernels.hpp).  The batched path (jobs, graphs, autotuning) is in
+// submit.hip.
+#include "host.hpp"
 #include "locator_kernels.hpp"
-#include "ct_launch.hpp"
-#include "fourstep_launch.hpp"
 
-using namespace fntrs;
+namespace fntrs {
 
-namespace {
-
-constexpr size_t kDefaultCap = size_t(4) << 30;
-
-bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
-int ilog2(uint64_t x) { int r = 0; while ((1ull << r) < x) ++r; return r; }
-
-}  // namespace
-
-struct fntrs_locator_s {
-  uint32_t n = 0, k = 0;
-  int logn = 0, logk = 0;
-  int logm = 0;                      // low-product length M = 2^logm >= 2k (k < n)
-  std::vector<uint32_t> positions;   // the k positions used
-  uint64_t key = 0;
-  uint32_t* mem = nullptr;           // one device allocation, views below
-  size_t bytes = 0;
-  uint32_t *pos = nullptr, *wfull = nullptr, *ridx = nullptr, *ahat_br = nullptr, *ahat_s = nullptr;
-  uint32_t *A = nullptr, *w = nullptr, *ahat = nullptr;
-  hipEvent_t ready = nullptr;        // recorded after the build on its stream
-  int refs = 0;
-  uint64_t last_use = 0;
-};
-
-struct fntrs_ctx {
-  int device = 0;
-  size_t cap = kDefaultCap, used = 0;
-  uint32_t* tw = nullptr;            // tw[e] = 3^e mod p, e < 65536
-  uint32_t* twi = nullptr;           // twi[e] = 3^-e mod p
-  size_t lds_max = 65536;
-  CtCfg enc_cfg[16] = {};            // kernel configuration per log2 transform size
-  CtCfg dec_cfg[16] = {};
-  std::mutex mu;
-  std::string err;
-  std::unordered_multimap<uint64_t, fntrs_locator_t*> cache;
-  uint64_t tick = 0;
-};
-
-namespace {
-
-int fail(fntrs_ctx* c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
 int fail(fntrs_ctx* c, int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -73,24 +20,73 @@ int fail(fntrs_ctx* c, int code, const char* fmt, ...) {
   return code;
 }
 
-#define HIP_TRY(ctx, expr)                                                              \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      return fail(ctx, FNTRS_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));  \
-  } while (0)
+// Launch tables of the per-size translation units, indexed by log2 size.
+const CtTables& ct_tables() {
+  static const CtEncLaunch enc[16] = {nullptr, ct_enc_launch_1, ct_enc_launch_2, ct_enc_launch_3, ct_enc_launch_4,
+                                 ct_enc_launch_5, ct_enc_launch_6, ct_enc_launch_7, ct_enc_launch_8,
+                                 ct_enc_launch_9, ct_enc_launch_10, ct_enc_launch_11, ct_enc_launch_12,
+                                 ct_enc_launch_13, ct_enc_launch_14, ct_enc_launch_15};
+  static const CtDecLaunch dec[16] = {nullptr, ct_dec_launch_1, ct_dec_launch_2, ct_dec_launch_3, ct_dec_launch_4,
+                                 ct_dec_launch_5, ct_dec_launch_6, ct_dec_launch_7, ct_dec_launch_8,
+                                 ct_dec_launch_9, ct_dec_launch_10, ct_dec_launch_11, ct_dec_launch_12,
+                                 ct_dec_launch_13, ct_dec_launch_14, ct_dec_launch_15};
+  static const CtEncTabLaunch enc_tab[16] = {
+    nullptr,              ct_enc_tab_launch_1,  ct_enc_tab_launch_2,  ct_enc_tab_launch_3,
+    ct_enc_tab_launch_4,  ct_enc_tab_launch_5,  ct_enc_tab_launch_6,  ct_enc_tab_launch_7,
+    ct_enc_tab_launch_8,  ct_enc_tab_launch_9,  ct_enc_tab_launch_10, ct_enc_tab_launch_11,
+    ct_enc_tab_launch_12, ct_enc_tab_launch_13, ct_enc_tab_launch_14, ct_enc_tab_launch_15};
+  static const CtDecTabLaunch dec_tab[16] = {
+    nullptr,              ct_dec_tab_launch_1,  ct_dec_tab_launch_2,  ct_dec_tab_launch_3,
+    ct_dec_tab_launch_4,  ct_dec_tab_launch_5,  ct_dec_tab_launch_6,  ct_dec_tab_launch_7,
+    ct_dec_tab_launch_8,  ct_dec_tab_launch_9,  ct_dec_tab_launch_10, ct_dec_tab_launch_11,
+    ct_dec_tab_launch_12, ct_dec_tab_launch_13, ct_dec_tab_launch_14, ct_dec_tab_launch_15};
+  static const CtTabOccupancy occ[16] = {
+    nullptr,             ct_tab_occupancy_1,  ct_tab_occupancy_2,  ct_tab_occupancy_3,
+    ct_tab_occupancy_4,  ct_tab_occupancy_5,  ct_tab_occupancy_6,  ct_tab_occupancy_7,
+    ct_tab_occupancy_8,  ct_tab_occupancy_9,  ct_tab_occupancy_10, ct_tab_occupancy_11,
+    ct_tab_occupancy_12, ct_tab_occupancy_13, ct_tab_occupancy_14, ct_tab_occupancy_15};
+  static const CtTables t{enc, dec, enc_tab, dec_tab, occ};
+  return t;
+}
 
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
+int check_encode(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uint32_t* src, size_t ld_src,
+                 size_t stride_src, const uint32_t* dst, size_t ld_dst, size_t stride_dst, uint32_t batch,
+                 uint32_t flags) {
+  if (!is_pow2(n) || n > 65536) return fail(c, FNTRS_E_INVAL, "n=%u must be a power of two in [1, 65536]", n);
+  if (k < 1 || k > n) return fail(c, FNTRS_E_INVAL, "k=%u must satisfy 1 <= k <= n=%u", k, n);
+  if (lanes < 1 || batch < 1) return fail(c, FNTRS_E_INVAL, "lanes=%u and batch=%u must be >= 1", lanes, batch);
+  if (!src || !dst) return fail(c, FNTRS_E_INVAL, "null src or dst");
+  if (ld_src < lanes || ld_dst < lanes) return fail(c, FNTRS_E_INVAL, "ld_src/ld_dst smaller than lanes");
+  if (batch > 1 && (stride_src < (size_t)(k - 1) * ld_src + lanes || stride_dst < (size_t)(n - 1) * ld_dst + lanes))
+    return fail(c, FNTRS_E_INVAL, "block strides overlap consecutive blocks");
+  if (flags & ~FNTRS_FLAG_VALIDATE) return fail(c, FNTRS_E_INVAL, "unknown flags 0x%x", flags);
+  const size_t sb = span_elems(batch, stride_src, k, ld_src, lanes) * 4;
+  const size_t db = span_elems(batch, stride_dst, n, ld_dst, lanes) * 4;
+  if (ranges_overlap(src, sb, dst, db)) return fail(c, FNTRS_E_INVAL, "src and dst overlap");
+  return FNTRS_OK;
+}
+
+int check_decode(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, uint32_t flags, const uint32_t* recv,
+                 size_t ld_recv, size_t stride_recv, const uint32_t* dst, size_t ld_dst, size_t stride_dst,
+                 uint32_t batch) {
+  if (!L) return fail(c, FNTRS_E_INVAL, "null locator");
+  if (L->refs <= 0) return fail(c, FNTRS_E_INVAL, "locator was released");
+  if (lanes < 1 || batch < 1) return fail(c, FNTRS_E_INVAL, "lanes=%u and batch=%u must be >= 1", lanes, batch);
+  if (!recv || !dst) return fail(c, FNTRS_E_INVAL, "null recv or dst");
+  if (flags & ~(FNTRS_RECV_FULL | FNTRS_FLAG_VALIDATE)) return fail(c, FNTRS_E_INVAL, "unknown flags 0x%x", flags);
+  const bool full = flags & FNTRS_RECV_FULL;
+  const uint32_t n = L->n, k = L->k;
+  const uint32_t rrows = full ? n : k;
+  if (ld_recv < lanes || ld_dst < lanes) return fail(c, FNTRS_E_INVAL, "ld_recv/ld_dst smaller than lanes");
+  if (batch > 1 && (stride_recv < (size_t)(rrows - 1) * ld_recv + lanes || stride_dst < (size_t)(k - 1) * ld_dst + lanes))
+    return fail(c, FNTRS_E_INVAL, "block strides overlap consecutive blocks");
+  const size_t rb = span_elems(batch, stride_recv, rrows, ld_recv, lanes) * 4;
+  const size_t db = span_elems(batch, stride_dst, k, ld_dst, lanes) * 4;
+  if (ranges_overlap(recv, rb, dst, db)) return fail(c, FNTRS_E_INVAL, "recv and dst overlap");
+  return FNTRS_OK;
+}
+
+namespace {
 
 uint64_t hash_positions(uint32_t n, uint32_t k, const uint32_t* z) {
   uint64_t h = 0xcbf29ce484222325ull ^ ((uint64_t)n << 32) ^ k;
@@ -105,29 +101,8 @@ hipError_t set_lds_attr(const void* fn, size_t bytes) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-const CtEncLaunch kCtEnc[16] = {nullptr, ct_enc_launch_1, ct_enc_launch_2, ct_enc_launch_3, ct_enc_launch_4,
-                                 ct_enc_launch_5, ct_enc_launch_6, ct_enc_launch_7, ct_enc_launch_8,
-                                 ct_enc_launch_9, ct_enc_launch_10, ct_enc_launch_11, ct_enc_launch_12,
-                                 ct_enc_launch_13, ct_enc_launch_14, ct_enc_launch_15};
-const CtDecLaunch kCtDec[16] = {nullptr, ct_dec_launch_1, ct_dec_launch_2, ct_dec_launch_3, ct_dec_launch_4,
-                                 ct_dec_launch_5, ct_dec_launch_6, ct_dec_launch_7, ct_dec_launch_8,
-                                 ct_dec_launch_9, ct_dec_launch_10, ct_dec_launch_11, ct_dec_launch_12,
-                                 ct_dec_launch_13, ct_dec_launch_14, ct_dec_launch_15};
+}  // namespace
 
-bool aligned16(const void* p, size_t ld, size_t stride) {
-  return ((uintptr_t)p % 16 == 0) && (ld % 4 == 0) && (stride % 4 == 0);
-}
-
-bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
-  auto pa = (uintptr_t)a, pb = (uintptr_t)b;
-  return pa < pb + bbytes && pb < pa + abytes;
-}
-
-size_t span_elems(uint32_t batch, size_t stride, uint32_t rows, size_t ld, uint32_t lanes) {
-  return (size_t)(batch - 1) * stride + (size_t)(rows - 1) * ld + lanes;
-}
-
-// Reads a strided device region back and checks every residue <= 65536.
 int validate_range(fntrs_ctx* c, const uint32_t* p, uint32_t batch, size_t stride, uint32_t rows,
                    size_t ld, uint32_t lanes, hipStream_t s) {
   const size_t cnt = span_elems(batch, stride, rows, ld, lanes);
@@ -144,7 +119,7 @@ int validate_range(fntrs_ctx* c, const uint32_t* p, uint32_t batch, size_t strid
   return FNTRS_OK;
 }
 
-void free_locator(fntrs_ctx* c, fntrs_locator_t* L) {
+static void free_locator(fntrs_ctx* c, fntrs_locator_t* L) {
   if (L->ready) (void)hipEventDestroy(L->ready);
   if (L->mem) {
     (void)hipFree(L->mem);
@@ -153,8 +128,7 @@ void free_locator(fntrs_ctx* c, fntrs_locator_t* L) {
   delete L;
 }
 
-// Evicts unreferenced cached locators, least recently used first, until
-// `need` more bytes fit under the cap.
+// Least recently used first.
 bool make_room(fntrs_ctx* c, size_t need) {
   while (c->used + need > c->cap) {
     auto victim = c->cache.end();
@@ -169,7 +143,7 @@ bool make_room(fntrs_ctx* c, size_t need) {
   return true;
 }
 
-int build_locator(fntrs_ctx* c, fntrs_locator_t* L, hipStream_t s) {
+static int build_locator(fntrs_ctx* c, fntrs_locator_t* L, hipStream_t s) {
   const uint32_t n = L->n, k = L->k;
   const int logn = L->logn, logk = L->logk;
   const size_t M = (k < n) ? (size_t)1 << L->logm : 0;
@@ -264,33 +238,53 @@ hipError_t launch_copy(const uint32_t* src, size_t stride_src, uint32_t* dst, si
   return hipGetLastError();
 }
 
-}  // namespace
-
-extern "C" {
-
-const char* fntrs_version(void) { return "fntrs 0.1 (gfx950)"; }
-
-int fntrs_create(int device, size_t cap, fntrs_ctx** out) {
-  if (!out) return FNTRS_E_INVAL;
+int locator_acquire(fntrs_ctx* c, uint32_t n, uint32_t k, const uint32_t* positions, uint32_t npos,
+                    hipStream_t stream, fntrs_locator_t** out) {
+  if (!out) return fail(c, FNTRS_E_INVAL, "null out");
   *out = nullptr;
-  if (device == FNTRS_HOST_ONLY) {
-    auto* c = new fntrs_ctx();
-    c->device = FNTRS_HOST_ONLY;
-    c->cap = cap ? cap : kDefaultCap;
-    c->lds_max = 163840;
-    *out = c;
-    return FNTRS_OK;
+  if (!is_pow2(n) || n > 65536) return fail(c, FNTRS_E_INVAL, "n=%u must be a power of two in [1, 65536]", n);
+  if (k < 1 || k > n) return fail(c, FNTRS_E_INVAL, "k=%u must satisfy 1 <= k <= n=%u", k, n);
+  if (!positions) return fail(c, FNTRS_E_INVAL, "null positions");
+  if (npos < k) return fail(c, FNTRS_E_TOOFEW, "%u positions received, k=%u needed", npos, k);
+  for (uint32_t i = 0; i < k; ++i) {
+    if (positions[i] >= n) return fail(c, FNTRS_E_POSITIONS, "position %u at index %u is >= n=%u", positions[i], i, n);
+    if (i && positions[i] <= positions[i - 1])
+      return fail(c, FNTRS_E_POSITIONS, "positions must be strictly ascending (index %u)", i);
   }
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return FNTRS_E_DEVICE;
-  if (device < 0 || device >= ndev) return FNTRS_E_INVAL;
-  auto* c = new fntrs_ctx();
-  c->device = device;
-  c->cap = cap ? cap : kDefaultCap;
-  DeviceGuard g(device);
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete c; return FNTRS_E_DEVICE; }
-  c->lds_max = prop.sharedMemPerBlock;
+  if (!is_pow2(k)) return fail(c, FNTRS_E_UNSUPPORTED, "decoding needs k a power of two, got %u", k);
+  const uint64_t key = hash_positions(n, k, positions);
+  auto range = c->cache.equal_range(key);
+  for (auto it = range.first; it != range.second; ++it) {
+    fntrs_locator_t* L = it->second;
+    if (L->n == n && L->k == k && std::equal(L->positions.begin(), L->positions.end(), positions)) {
+      L->refs++;
+      L->last_use = ++c->tick;
+      *out = L;
+      return FNTRS_OK;
+    }
+  }
+  if (c->device == FNTRS_HOST_ONLY) return fail(c, FNTRS_E_DEVICE, "host-only context: arguments valid, no device");
+  DeviceGuard g(c->device);
+  auto* L = new fntrs_locator_t();
+  L->n = n; L->k = k; L->logn = ilog2(n); L->logk = ilog2(k);
+  L->logm = std::max(L->logk + 1, L->logn - 1);   // low-product length M >= 2k, M >= n/2
+  L->positions.assign(positions, positions + k);
+  L->key = key;
+  int rc = build_locator(c, L, stream);
+  if (rc) {
+    free_locator(c, L);
+    return rc;
+  }
+  L->refs = 1;
+  L->last_use = ++c->tick;
+  c->cache.emplace(key, L);
+  *out = L;
+  return FNTRS_OK;
+}
+
+// Default kernel configuration per transform size, then the FNTRS_TILES
+// override "e12=8x512,d13=4x1024,...".
+void set_default_configs(fntrs_ctx* c) {
   for (int L = 1; L <= 15; ++L) {
     c->enc_cfg[L] = ct_variants(L).enc[0];
     c->dec_cfg[L] = ct_variants(L).dec[0];
@@ -312,6 +306,40 @@ int fntrs_create(int device, size_t cap, fntrs_ctx** out) {
       pos = end + 1;
     }
   }
+}
+
+}  // namespace fntrs
+
+using namespace fntrs;
+
+extern "C" {
+
+const char* fntrs_version(void) { return "fntrs 0.1 (gfx950)"; }
+
+int fntrs_create(int device, size_t cap, fntrs_ctx** out) {
+  if (!out) return FNTRS_E_INVAL;
+  *out = nullptr;
+  if (device == FNTRS_HOST_ONLY) {
+    auto* c = new fntrs_ctx();
+    c->device = FNTRS_HOST_ONLY;
+    c->cap = cap ? cap : kDefaultCap;
+    c->lds_max = 163840;
+    set_default_configs(c);
+    *out = c;
+    return FNTRS_OK;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return FNTRS_E_DEVICE;
+  if (device < 0 || device >= ndev) return FNTRS_E_INVAL;
+  auto* c = new fntrs_ctx();
+  c->device = device;
+  c->cap = cap ? cap : kDefaultCap;
+  DeviceGuard g(device);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete c; return FNTRS_E_DEVICE; }
+  c->lds_max = prop.sharedMemPerBlock;
+  c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  set_default_configs(c);
   // twiddle tables: tw[e] = 3^e and twi[e] = 3^-e = 3^(65536-e), e < 65536
   std::vector<uint32_t> h(2 * 65536);
   uint64_t x = 1;
@@ -336,6 +364,11 @@ void fntrs_destroy(fntrs_ctx* c) {
   (void)hipDeviceSynchronize();
   for (auto& kv : c->cache) free_locator(c, kv.second);
   c->cache.clear();
+  for (int b = 0; b < fntrs_ctx::kSide; ++b) {
+    if (c->side[b]) (void)hipStreamDestroy(c->side[b]);
+    if (c->join[b]) (void)hipEventDestroy(c->join[b]);
+  }
+  if (c->fork) (void)hipEventDestroy(c->fork);
   if (c->tw) (void)hipFree(c->tw);
   delete c;
 }
@@ -348,17 +381,7 @@ int fntrs_encode(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uin
   if (!c) return FNTRS_E_INVAL;
   std::lock_guard<std::mutex> lk(c->mu);
   c->err.clear();
-  if (!is_pow2(n) || n > 65536) return fail(c, FNTRS_E_INVAL, "n=%u must be a power of two in [1, 65536]", n);
-  if (k < 1 || k > n) return fail(c, FNTRS_E_INVAL, "k=%u must satisfy 1 <= k <= n=%u", k, n);
-  if (lanes < 1 || batch < 1) return fail(c, FNTRS_E_INVAL, "lanes=%u and batch=%u must be >= 1", lanes, batch);
-  if (!src || !dst) return fail(c, FNTRS_E_INVAL, "null src or dst");
-  if (ld_src < lanes || ld_dst < lanes) return fail(c, FNTRS_E_INVAL, "ld_src/ld_dst smaller than lanes");
-  if (batch > 1 && (stride_src < (size_t)(k - 1) * ld_src + lanes || stride_dst < (size_t)(n - 1) * ld_dst + lanes))
-    return fail(c, FNTRS_E_INVAL, "block strides overlap consecutive blocks");
-  if (flags & ~FNTRS_FLAG_VALIDATE) return fail(c, FNTRS_E_INVAL, "unknown flags 0x%x", flags);
-  const size_t sb = span_elems(batch, stride_src, k, ld_src, lanes) * 4;
-  const size_t db = span_elems(batch, stride_dst, n, ld_dst, lanes) * 4;
-  if (ranges_overlap(src, sb, dst, db)) return fail(c, FNTRS_E_INVAL, "src and dst overlap");
+  if (int rc = check_encode(c, n, k, lanes, src, ld_src, stride_src, dst, ld_dst, stride_dst, batch, flags)) return rc;
   if (c->device == FNTRS_HOST_ONLY) return fail(c, FNTRS_E_DEVICE, "host-only context: arguments valid, no device");
   DeviceGuard g(c->device);
   hipStream_t s = (hipStream_t)stream;
@@ -402,7 +425,7 @@ int fntrs_encode(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uin
   a.cosets = n >> a.logK;
   const uint64_t blocks = (uint64_t)a.tiles * a.cosets * batch;
   if (blocks > 0x7fffffffull) return fail(c, FNTRS_E_INVAL, "grid too large");
-  HIP_TRY(c, kCtEnc[a.logK](cfg, a, (uint32_t)blocks, s));
+  HIP_TRY(c, ct_tables().enc[a.logK](cfg, a, (uint32_t)blocks, s));
   return FNTRS_OK;
 }
 
@@ -411,46 +434,7 @@ int fntrs_locator(fntrs_ctx* c, uint32_t n, uint32_t k, const uint32_t* position
   if (!c) return FNTRS_E_INVAL;
   std::lock_guard<std::mutex> lk(c->mu);
   c->err.clear();
-  if (!out) return fail(c, FNTRS_E_INVAL, "null out");
-  *out = nullptr;
-  if (!is_pow2(n) || n > 65536) return fail(c, FNTRS_E_INVAL, "n=%u must be a power of two in [1, 65536]", n);
-  if (k < 1 || k > n) return fail(c, FNTRS_E_INVAL, "k=%u must satisfy 1 <= k <= n=%u", k, n);
-  if (!positions) return fail(c, FNTRS_E_INVAL, "null positions");
-  if (npos < k) return fail(c, FNTRS_E_TOOFEW, "%u positions received, k=%u needed", npos, k);
-  for (uint32_t i = 0; i < k; ++i) {
-    if (positions[i] >= n) return fail(c, FNTRS_E_POSITIONS, "position %u at index %u is >= n=%u", positions[i], i, n);
-    if (i && positions[i] <= positions[i - 1])
-      return fail(c, FNTRS_E_POSITIONS, "positions must be strictly ascending (index %u)", i);
-  }
-  if (!is_pow2(k)) return fail(c, FNTRS_E_UNSUPPORTED, "decoding needs k a power of two, got %u", k);
-  const uint64_t key = hash_positions(n, k, positions);
-  auto range = c->cache.equal_range(key);
-  for (auto it = range.first; it != range.second; ++it) {
-    fntrs_locator_t* L = it->second;
-    if (L->n == n && L->k == k && std::equal(L->positions.begin(), L->positions.end(), positions)) {
-      L->refs++;
-      L->last_use = ++c->tick;
-      *out = L;
-      return FNTRS_OK;
-    }
-  }
-  if (c->device == FNTRS_HOST_ONLY) return fail(c, FNTRS_E_DEVICE, "host-only context: arguments valid, no device");
-  DeviceGuard g(c->device);
-  auto* L = new fntrs_locator_t();
-  L->n = n; L->k = k; L->logn = ilog2(n); L->logk = ilog2(k);
-  L->logm = std::max(L->logk + 1, L->logn - 1);   // low-product length M >= 2k, M >= n/2
-  L->positions.assign(positions, positions + k);
-  L->key = key;
-  int rc = build_locator(c, L, (hipStream_t)stream);
-  if (rc) {
-    free_locator(c, L);
-    return rc;
-  }
-  L->refs = 1;
-  L->last_use = ++c->tick;
-  c->cache.emplace(key, L);
-  *out = L;
-  return FNTRS_OK;
+  return locator_acquire(c, n, k, positions, npos, (hipStream_t)stream, out);
 }
 
 int fntrs_locator_release(fntrs_ctx* c, fntrs_locator_t* L) {
@@ -485,20 +469,10 @@ int fntrs_decode(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, uint32_
   if (!c) return FNTRS_E_INVAL;
   std::lock_guard<std::mutex> lk(c->mu);
   c->err.clear();
-  if (!L) return fail(c, FNTRS_E_INVAL, "null locator");
-  if (L->refs <= 0) return fail(c, FNTRS_E_INVAL, "locator was released");
-  if (lanes < 1 || batch < 1) return fail(c, FNTRS_E_INVAL, "lanes=%u and batch=%u must be >= 1", lanes, batch);
-  if (!recv || !dst) return fail(c, FNTRS_E_INVAL, "null recv or dst");
-  if (flags & ~(FNTRS_RECV_FULL | FNTRS_FLAG_VALIDATE)) return fail(c, FNTRS_E_INVAL, "unknown flags 0x%x", flags);
+  if (int rc = check_decode(c, L, lanes, flags, recv, ld_recv, stride_recv, dst, ld_dst, stride_dst, batch)) return rc;
   const bool full = flags & FNTRS_RECV_FULL;
   const uint32_t n = L->n, k = L->k;
   const uint32_t rrows = full ? n : k;
-  if (ld_recv < lanes || ld_dst < lanes) return fail(c, FNTRS_E_INVAL, "ld_recv/ld_dst smaller than lanes");
-  if (batch > 1 && (stride_recv < (size_t)(rrows - 1) * ld_recv + lanes || stride_dst < (size_t)(k - 1) * ld_dst + lanes))
-    return fail(c, FNTRS_E_INVAL, "block strides overlap consecutive blocks");
-  const size_t rb = span_elems(batch, stride_recv, rrows, ld_recv, lanes) * 4;
-  const size_t db = span_elems(batch, stride_dst, k, ld_dst, lanes) * 4;
-  if (ranges_overlap(recv, rb, dst, db)) return fail(c, FNTRS_E_INVAL, "recv and dst overlap");
   if (c->device == FNTRS_HOST_ONLY) return fail(c, FNTRS_E_DEVICE, "host-only context: arguments valid, no device");
   DeviceGuard g(c->device);
   hipStream_t s = (hipStream_t)stream;
@@ -544,7 +518,7 @@ int fntrs_decode(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, uint32_
   a.tiles = (lanes + cfg.T - 1) / cfg.T;
   const uint64_t blocks = (uint64_t)a.tiles * batch;
   if (blocks > 0x7fffffffull) return fail(c, FNTRS_E_INVAL, "grid too large");
-  HIP_TRY(c, kCtDec[L->logn](cfg, D, a, (uint32_t)blocks, s));
+  HIP_TRY(c, ct_tables().dec[L->logn](cfg, D, a, (uint32_t)blocks, s));
   return FNTRS_OK;
 }
 

@@ -1,0 +1,131 @@
+// Host-side internals of libfntrs shared by its translation units: the
+// context and locator objects, error reporting, argument checks.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/fntrs.h"
+#include "ct_launch.hpp"
+#include "fourstep_launch.hpp"
+
+namespace fntrs {
+
+constexpr size_t kDefaultCap = size_t(4) << 30;
+
+inline bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+inline int ilog2(uint64_t x) { int r = 0; while ((1ull << r) < x) ++r; return r; }
+
+}  // namespace fntrs
+
+struct fntrs_locator_s {
+  uint32_t n = 0, k = 0;
+  int logn = 0, logk = 0;
+  int logm = 0;                      // low-product length M = 2^logm >= 2k (k < n)
+  std::vector<uint32_t> positions;   // the k positions used
+  uint64_t key = 0;
+  uint32_t* mem = nullptr;           // one device allocation, views below
+  size_t bytes = 0;
+  uint32_t *pos = nullptr, *wfull = nullptr, *ridx = nullptr, *ahat_br = nullptr, *ahat_s = nullptr;
+  uint32_t *A = nullptr, *w = nullptr, *ahat = nullptr;
+  hipEvent_t ready = nullptr;        // recorded after the build on its stream
+  int refs = 0;
+  uint64_t last_use = 0;
+};
+
+struct fntrs_ctx {
+  int device = 0;
+  int num_cu = 256;
+  size_t cap = fntrs::kDefaultCap, used = 0;
+  uint32_t* tw = nullptr;            // tw[e] = 3^e mod p, e < 65536
+  uint32_t* twi = nullptr;           // twi[e] = 3^-e mod p
+  size_t lds_max = 65536;
+  fntrs::CtCfg enc_cfg[16] = {};     // kernel configuration per log2 transform size
+  fntrs::CtCfg dec_cfg[16] = {};
+  std::mutex mu;
+  std::string err;
+  std::unordered_multimap<uint64_t, fntrs_locator_t*> cache;
+  uint64_t tick = 0;
+  // batched path: side streams (default priority) for independent classes,
+  // and the occupancy of each table kernel
+  static constexpr int kSide = 3;
+  hipStream_t side[kSide] = {};
+  hipEvent_t fork = nullptr, join[kSide] = {};
+  std::map<std::tuple<int, int, int, int, int>, int> occ;
+};
+
+namespace fntrs {
+
+int fail(fntrs_ctx* c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+
+#define HIP_TRY(ctx, expr)                                                              \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(ctx, FNTRS_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));  \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+inline bool aligned16(const void* p, size_t ld, size_t stride) {
+  return ((uintptr_t)p % 16 == 0) && (ld % 4 == 0) && (stride % 4 == 0);
+}
+
+inline bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  auto pa = (uintptr_t)a, pb = (uintptr_t)b;
+  return pa < pb + bbytes && pb < pa + abytes;
+}
+
+inline size_t span_elems(uint32_t batch, size_t stride, uint32_t rows, size_t ld, uint32_t lanes) {
+  return (size_t)(batch - 1) * stride + (size_t)(rows - 1) * ld + lanes;
+}
+
+struct CtTables {
+  const CtEncLaunch* enc;
+  const CtDecLaunch* dec;
+  const CtEncTabLaunch* enc_tab;
+  const CtDecTabLaunch* dec_tab;
+  const CtTabOccupancy* occ;
+};
+const CtTables& ct_tables();
+
+// Argument checks of one encode / decode call (the rules of fntrs_encode and
+// fntrs_decode); FNTRS_OK or an error code with the message set.
+int check_encode(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uint32_t* src, size_t ld_src,
+                 size_t stride_src, const uint32_t* dst, size_t ld_dst, size_t stride_dst, uint32_t batch,
+                 uint32_t flags);
+int check_decode(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, uint32_t flags, const uint32_t* recv,
+                 size_t ld_recv, size_t stride_recv, const uint32_t* dst, size_t ld_dst, size_t stride_dst,
+                 uint32_t batch);
+// Reads a strided device region back and checks every residue <= 65536.
+int validate_range(fntrs_ctx* c, const uint32_t* p, uint32_t batch, size_t stride, uint32_t rows, size_t ld,
+                   uint32_t lanes, hipStream_t s);
+// Evicts unreferenced cached locators until `need` more bytes fit the cap.
+bool make_room(fntrs_ctx* c, size_t need);
+// Finds the cached locator of the positions or builds it (fntrs_locator
+// without the lock).
+int locator_acquire(fntrs_ctx* c, uint32_t n, uint32_t k, const uint32_t* positions, uint32_t npos,
+                    hipStream_t stream, fntrs_locator_t** out);
+hipError_t launch_copy(const uint32_t* src, size_t stride_src, uint32_t* dst, size_t stride_dst, uint32_t lanes,
+                       uint32_t batch, hipStream_t s);
+
+}  // namespace fntrs

@@ -1,0 +1,533 @@
+// libfntrs: the batched path -- uneven batches of encode and decode jobs
+// (fntrs_submit), their captured HIP graphs (fntrs_graph_*), and the
+// autotuner that picks each transform size's kernel configuration
+// (fntrs_autotune).
+//
+// A batch is split into classes that share one compiled kernel: encode jobs
+// by transform size K, decode jobs by code length n and product length M.
+// Each class becomes one persistent launch of a table kernel (k_enc_tab /
+// k_dec_tab) whose workgroups walk the work items of all of the class's jobs;
+// the classes run on up to four streams at once.  Jobs the table kernels do
+// not cover (n = 65536 four-step transforms, n = 1 copies) run one by one.
+#include <chrono>
+
+#include "ct_kernels.hpp"
+#include "host.hpp"
+
+namespace fntrs {
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct ClassLaunch {
+  int op = 0;          // 0 encode, 1 decode
+  int L = 0, D = 0;    // transform size 2^L; decode product length 2^(L-D)
+  CtCfg cfg{};
+  size_t jobs_off = 0, start_off = 0;   // byte offsets of the tables in the blob
+  uint32_t njobs = 0, total = 0, grid = 0;
+  uint64_t work = 0;   // butterflies, to balance the streams
+};
+
+struct SingleJob {
+  int kind = 0;        // 0 copy (n = 1), 1 four-step encode, 2 four-step decode
+  FourStepArgs f{};
+  uint32_t batch = 0;
+  uint64_t ld_scratch = 0;
+  const uint32_t* src = nullptr;   // copy
+  uint32_t* dst = nullptr;
+  size_t stride_src = 0, stride_dst = 0;
+  uint32_t lanes = 0;
+};
+
+struct Plan {
+  std::vector<uint8_t> blob;              // host image of the job tables
+  std::vector<ClassLaunch> launches;
+  std::vector<SingleJob> singles;
+  size_t scratch_elems = 0;               // shared by the singles, which run in order
+  std::vector<fntrs_locator_t*> locs;     // distinct locators the batch reads
+};
+
+int occupancy(fntrs_ctx* c, int op, int L, int D, CtCfg cfg) {
+  const auto key = std::make_tuple(op, L, D, cfg.T, cfg.NT);
+  auto it = c->occ.find(key);
+  if (it != c->occ.end()) return it->second;
+  const int o = ct_tables().occ[L](cfg, op, D);
+  c->occ[key] = o;
+  return o;
+}
+
+// Checks every job, groups them into classes and lays out the job tables.
+int make_plan(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, Plan& P) {
+  if (!jobs && njobs) return fail(c, FNTRS_E_INVAL, "null jobs");
+  // spans of every job's input and output, to reject overlaps across jobs
+  struct Span {
+    uintptr_t lo, hi;
+    uint32_t job;
+    bool out;
+  };
+  std::vector<Span> spans;
+  spans.reserve(2ull * njobs);
+  std::map<std::tuple<int, int, int>, std::vector<uint32_t>> classes;   // (op, L, D) -> jobs
+  for (uint32_t j = 0; j < njobs; ++j) {
+    const fntrs_job& J = jobs[j];
+    if (J.flags & FNTRS_FLAG_VALIDATE)
+      return fail(c, FNTRS_E_INVAL, "job %u: FNTRS_FLAG_VALIDATE is not available in a batch", j);
+    if (J.op == FNTRS_OP_ENCODE) {
+      if (J.loc) return fail(c, FNTRS_E_INVAL, "job %u: an encode job takes no locator", j);
+      if (int rc = check_encode(c, J.n, J.k, J.lanes, J.in, J.ld_in, J.stride_in, J.out, J.ld_out, J.stride_out,
+                                J.batch, J.flags)) {
+        c->err = "job " + std::to_string(j) + ": " + c->err;
+        return rc;
+      }
+      spans.push_back({(uintptr_t)J.in, (uintptr_t)J.in + span_elems(J.batch, J.stride_in, J.k, J.ld_in, J.lanes) * 4,
+                       j, false});
+      spans.push_back({(uintptr_t)J.out,
+                       (uintptr_t)J.out + span_elems(J.batch, J.stride_out, J.n, J.ld_out, J.lanes) * 4, j, true});
+      const int logK = std::max(1, ilog2(J.k));
+      if (J.n == 1) {
+        SingleJob s;
+        s.kind = 0; s.src = J.in; s.dst = J.out; s.stride_src = J.stride_in; s.stride_dst = J.stride_out;
+        s.lanes = J.lanes; s.batch = J.batch;
+        P.singles.push_back(s);
+      } else if (logK == 16) {
+        SingleJob s;
+        s.kind = 1;
+        FourStepArgs& f = s.f;
+        f.in = J.in; f.ld_in = J.ld_in; f.stride_in = J.stride_in;
+        f.out = J.out; f.ld_out = J.ld_out; f.stride_out = J.stride_out;
+        f.tw = c->tw; f.twi = c->twi;
+        f.n = J.n; f.k = J.k; f.M = J.n; f.lanes = J.lanes; f.logn = 16; f.logm = 16;
+        f.tiles = (J.lanes + kFourStepTile - 1) / kFourStepTile;
+        f.vec = aligned16(J.in, J.ld_in, J.stride_in) && aligned16(J.out, J.ld_out, J.stride_out);
+        s.batch = J.batch;
+        s.ld_scratch = (uint64_t)f.tiles * kFourStepTile;
+        P.scratch_elems = std::max(P.scratch_elems, (size_t)J.batch * J.n * s.ld_scratch);
+        P.singles.push_back(s);
+      } else {
+        classes[std::make_tuple(0, logK, 0)].push_back(j);
+      }
+    } else if (J.op == FNTRS_OP_DECODE) {
+      const fntrs_locator_t* L = J.loc;
+      if (!L) return fail(c, FNTRS_E_INVAL, "job %u: a decode job needs a locator", j);
+      if ((J.n && J.n != L->n) || (J.k && J.k != L->k))
+        return fail(c, FNTRS_E_INVAL, "job %u: n=%u k=%u differ from the locator's n=%u k=%u", j, J.n, J.k, L->n,
+                    L->k);
+      if (int rc = check_decode(c, L, J.lanes, J.flags, J.in, J.ld_in, J.stride_in, J.out, J.ld_out, J.stride_out,
+                                J.batch)) {
+        c->err = "job " + std::to_string(j) + ": " + c->err;
+        return rc;
+      }
+      const bool full = J.flags & FNTRS_RECV_FULL;
+      const uint32_t rrows = full ? L->n : L->k;
+      spans.push_back({(uintptr_t)J.in,
+                       (uintptr_t)J.in + span_elems(J.batch, J.stride_in, rrows, J.ld_in, J.lanes) * 4, j, false});
+      spans.push_back({(uintptr_t)J.out,
+                       (uintptr_t)J.out + span_elems(J.batch, J.stride_out, L->k, J.ld_out, J.lanes) * 4, j, true});
+      if (std::find(P.locs.begin(), P.locs.end(), L) == P.locs.end())
+        P.locs.push_back(const_cast<fntrs_locator_t*>(L));
+      if (L->n == 1) {
+        SingleJob s;
+        s.kind = 0; s.src = J.in; s.dst = J.out; s.stride_src = J.stride_in; s.stride_dst = J.stride_out;
+        s.lanes = J.lanes; s.batch = J.batch;
+        P.singles.push_back(s);
+      } else if (L->logn == 16) {
+        SingleJob s;
+        s.kind = 2;
+        FourStepArgs& f = s.f;
+        f.in = J.in; f.ld_in = J.ld_in; f.stride_in = J.stride_in;
+        f.out = J.out; f.ld_out = J.ld_out; f.stride_out = J.stride_out;
+        f.tw = c->tw; f.twi = c->twi; f.wfull = L->wfull; f.ridx = L->ridx; f.ahat = L->ahat_s;
+        f.n = L->n; f.k = L->k; f.lanes = J.lanes; f.logn = 16;
+        f.logm = (L->k == L->n) ? 16 : L->logm;
+        f.M = 1u << f.logm;
+        f.full = full ? 1u : 0u;
+        f.tiles = (J.lanes + kFourStepTile - 1) / kFourStepTile;
+        f.vec = aligned16(J.in, J.ld_in, J.stride_in) && aligned16(J.out, J.ld_out, J.stride_out);
+        s.batch = J.batch;
+        s.ld_scratch = (uint64_t)f.tiles * kFourStepTile;
+        P.scratch_elems = std::max(P.scratch_elems, (size_t)J.batch * (f.n + f.M) * s.ld_scratch);
+        P.singles.push_back(s);
+      } else {
+        const int D = (L->k == L->n) ? -1 : L->logn - L->logm;
+        classes[std::make_tuple(1, L->logn, D)].push_back(j);
+      }
+    } else {
+      return fail(c, FNTRS_E_INVAL, "job %u: unknown op %u", j, J.op);
+    }
+  }
+  // no output may overlap another job's input or output
+  std::sort(spans.begin(), spans.end(), [](const Span& a, const Span& b) { return a.lo < b.lo; });
+  for (size_t i = 0; i < spans.size(); ++i)
+    for (size_t q = i + 1; q < spans.size() && spans[q].lo < spans[i].hi; ++q)
+      if ((spans[i].out || spans[q].out) && spans[i].job != spans[q].job)
+        return fail(c, FNTRS_E_INVAL, "jobs %u and %u overlap (an output shares memory with another job)",
+                    spans[i].job, spans[q].job);
+
+  // job tables, one class after another
+  size_t off = 0;
+  for (auto& kv : classes) {
+    ClassLaunch cl;
+    cl.op = std::get<0>(kv.first);
+    cl.L = std::get<1>(kv.first);
+    cl.D = std::get<2>(kv.first);
+    cl.cfg = cl.op == 0 ? c->enc_cfg[cl.L] : c->dec_cfg[cl.L];
+    const auto& js = kv.second;
+    cl.njobs = (uint32_t)js.size();
+    const size_t args_bytes = cl.op == 0 ? sizeof(EncodeArgs) : sizeof(DecodeArgs);
+    cl.jobs_off = off;
+    off = align_up(off + args_bytes * js.size());
+    cl.start_off = off;
+    off = align_up(off + 4 * (js.size() + 1));
+    P.blob.resize(off);
+    uint32_t* start = reinterpret_cast<uint32_t*>(P.blob.data() + cl.start_off);
+    uint64_t total = 0;
+    for (size_t i = 0; i < js.size(); ++i) {
+      const fntrs_job& J = jobs[js[i]];
+      start[i] = (uint32_t)total;
+      const uint32_t tiles = (J.lanes + cl.cfg.T - 1) / cl.cfg.T;
+      if (cl.op == 0) {
+        EncodeArgs a{};
+        a.src = J.in; a.ld_src = J.ld_in; a.stride_src = J.stride_in;
+        a.dst = J.out; a.ld_dst = J.ld_out; a.stride_dst = J.stride_out;
+        a.tw = c->tw; a.twi = c->twi;
+        a.n = J.n; a.k = J.k; a.lanes = J.lanes;
+        a.logn = ilog2(J.n); a.logK = cl.L;
+        a.tiles = tiles; a.cosets = J.n >> cl.L;
+        a.vec = aligned16(J.in, J.ld_in, J.stride_in) && aligned16(J.out, J.ld_out, J.stride_out);
+        std::memcpy(P.blob.data() + cl.jobs_off + i * sizeof(EncodeArgs), &a, sizeof a);
+        total += (uint64_t)tiles * a.cosets * J.batch;
+        cl.work += (uint64_t)J.lanes * J.batch * (J.n / 2) * cl.L;
+      } else {
+        const fntrs_locator_t* L = J.loc;
+        DecodeArgs a{};
+        a.recv = J.in; a.ld_recv = J.ld_in; a.stride_recv = J.stride_in;
+        a.dst = J.out; a.ld_dst = J.ld_out; a.stride_dst = J.stride_out;
+        a.tw = c->tw; a.twi = c->twi; a.wfull = L->wfull; a.ridx = L->ridx; a.ahat_br = L->ahat_br;
+        a.n = L->n; a.k = L->k; a.lanes = J.lanes; a.logn = L->logn; a.logk = L->logk;
+        a.full = (J.flags & FNTRS_RECV_FULL) ? 1u : 0u;
+        a.tiles = tiles;
+        a.vec = aligned16(J.in, J.ld_in, J.stride_in) && aligned16(J.out, J.ld_out, J.stride_out);
+        std::memcpy(P.blob.data() + cl.jobs_off + i * sizeof(DecodeArgs), &a, sizeof a);
+        total += (uint64_t)tiles * J.batch;
+        cl.work += (uint64_t)J.lanes * J.batch * ((L->n / 2) * L->logn * 3);
+      }
+      if (total > 0x7fffffffull) return fail(c, FNTRS_E_INVAL, "class of 2^%d: too many work items", cl.L);
+    }
+    start[js.size()] = (uint32_t)total;
+    cl.total = (uint32_t)total;
+    const int occ = c->device == FNTRS_HOST_ONLY ? 1 : occupancy(c, cl.op, cl.L, cl.D, cl.cfg);
+    if (occ <= 0)
+      return fail(c, FNTRS_E_DEVICE, "no occupancy for the %s kernel of size 2^%d (T=%d, NT=%d)",
+                  cl.op ? "decode" : "encode", cl.L, cl.cfg.T, cl.cfg.NT);
+    cl.grid = (uint32_t)std::min<uint64_t>(total, (uint64_t)occ * c->num_cu);
+    P.launches.push_back(cl);
+  }
+  // largest classes first: they start early and the small ones fill the tail
+  std::stable_sort(P.launches.begin(), P.launches.end(),
+                   [](const ClassLaunch& a, const ClassLaunch& b) { return a.work > b.work; });
+  return FNTRS_OK;
+}
+
+int ensure_side_streams(fntrs_ctx* c) {
+  if (c->fork) return FNTRS_OK;
+  for (int b = 0; b < fntrs_ctx::kSide; ++b) {
+    HIP_TRY(c, hipStreamCreateWithFlags(&c->side[b], hipStreamNonBlocking));
+    HIP_TRY(c, hipEventCreateWithFlags(&c->join[b], hipEventDisableTiming));
+  }
+  HIP_TRY(c, hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+  return FNTRS_OK;
+}
+
+// Enqueues the plan: the classes spread over `s` and the side streams (each
+// stream takes the next class while the one with the least work so far),
+// the single jobs in order on `s`; everything is joined back into `s`.
+int run_plan(fntrs_ctx* c, const Plan& P, const uint8_t* dblob, uint32_t* scratch, hipStream_t s) {
+  const int streams = std::min<int>(1 + fntrs_ctx::kSide, (int)P.launches.size());
+  if (streams > 1) {
+    if (int rc = ensure_side_streams(c)) return rc;
+    HIP_TRY(c, hipEventRecord(c->fork, s));
+    for (int b = 0; b < streams - 1; ++b) HIP_TRY(c, hipStreamWaitEvent(c->side[b], c->fork, 0));
+  }
+  std::vector<uint64_t> load(streams > 0 ? streams : 1, 0);
+  for (const ClassLaunch& cl : P.launches) {
+    int b = 0;
+    for (int q = 1; q < streams; ++q)
+      if (load[q] < load[b]) b = q;
+    load[b] += cl.work;
+    hipStream_t st = b == 0 ? s : c->side[b - 1];
+    if (cl.op == 0) {
+      JobTable<EncodeArgs> t{reinterpret_cast<const EncodeArgs*>(dblob + cl.jobs_off),
+                             reinterpret_cast<const uint32_t*>(dblob + cl.start_off), cl.njobs, cl.total};
+      HIP_TRY(c, ct_tables().enc_tab[cl.L](cl.cfg, t, c->tw, c->twi, cl.grid, st));
+    } else {
+      JobTable<DecodeArgs> t{reinterpret_cast<const DecodeArgs*>(dblob + cl.jobs_off),
+                             reinterpret_cast<const uint32_t*>(dblob + cl.start_off), cl.njobs, cl.total};
+      HIP_TRY(c, ct_tables().dec_tab[cl.L](cl.cfg, cl.D, t, c->tw, c->twi, cl.grid, st));
+    }
+  }
+  for (const SingleJob& sj : P.singles) {
+    if (sj.kind == 0) {
+      HIP_TRY(c, launch_copy(sj.src, sj.stride_src, sj.dst, sj.stride_dst, sj.lanes, sj.batch, s));
+    } else if (sj.kind == 1) {
+      HIP_TRY(c, fourstep_encode(sj.f, sj.batch, scratch, sj.ld_scratch, s));
+    } else {
+      uint32_t* sb = scratch + (size_t)sj.batch * sj.f.n * sj.ld_scratch;
+      HIP_TRY(c, fourstep_decode(sj.f, sj.batch, scratch, sb, sj.ld_scratch, s));
+    }
+  }
+  for (int b = 0; b < streams - 1; ++b) {
+    HIP_TRY(c, hipEventRecord(c->join[b], c->side[b]));
+    HIP_TRY(c, hipStreamWaitEvent(s, c->join[b], 0));
+  }
+  return FNTRS_OK;
+}
+
+}  // namespace
+}  // namespace fntrs
+
+using namespace fntrs;
+
+struct fntrs_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint8_t* mem = nullptr;                 // job tables + scratch, owned by the graph
+  size_t bytes = 0;
+  std::vector<fntrs_locator_t*> locs;     // held (refcount) while the graph lives
+};
+
+extern "C" {
+
+int fntrs_submit(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, void* stream) {
+  if (!c) return FNTRS_E_INVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->err.clear();
+  Plan P;
+  if (int rc = make_plan(c, jobs, njobs, P)) return rc;
+  if (c->device == FNTRS_HOST_ONLY) return fail(c, FNTRS_E_DEVICE, "host-only context: arguments valid, no device");
+  if (njobs == 0) return FNTRS_OK;
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  for (fntrs_locator_t* L : P.locs) HIP_TRY(c, hipStreamWaitEvent(s, L->ready, 0));
+  const size_t blob = align_up(P.blob.size());
+  const size_t bytes = blob + P.scratch_elems * 4;
+  uint8_t* mem = nullptr;
+  if (bytes) {
+    hipError_t e = hipMallocAsync((void**)&mem, bytes, s);
+    if (e != hipSuccess) return fail(c, FNTRS_E_NOMEM, "batch workspace of %zu bytes: %s", bytes, hipGetErrorString(e));
+    // pageable source: the runtime stages it before returning
+    if (!P.blob.empty()) HIP_TRY(c, hipMemcpyAsync(mem, P.blob.data(), P.blob.size(), hipMemcpyHostToDevice, s));
+  }
+  const int rc = run_plan(c, P, mem, reinterpret_cast<uint32_t*>(mem + blob), s);
+  if (mem) (void)hipFreeAsync(mem, s);
+  return rc;
+}
+
+int fntrs_graph_create(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, fntrs_graph_t** out) {
+  if (!c) return FNTRS_E_INVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->err.clear();
+  if (!out) return fail(c, FNTRS_E_INVAL, "null out");
+  *out = nullptr;
+  Plan P;
+  if (int rc = make_plan(c, jobs, njobs, P)) return rc;
+  if (njobs == 0) return fail(c, FNTRS_E_INVAL, "empty batch");
+  if (c->device == FNTRS_HOST_ONLY) return fail(c, FNTRS_E_DEVICE, "host-only context: arguments valid, no device");
+  DeviceGuard g(c->device);
+  auto* G = new fntrs_graph_t();
+  auto cleanup = [&](int rc) {
+    if (G->exec) (void)hipGraphExecDestroy(G->exec);
+    if (G->graph) (void)hipGraphDestroy(G->graph);
+    if (G->mem) {
+      (void)hipFree(G->mem);
+      c->used -= G->bytes;
+    }
+    delete G;
+    return rc;
+  };
+  const size_t blob = align_up(P.blob.size());
+  G->bytes = blob + P.scratch_elems * 4;
+  if (G->bytes) {
+    if (!make_room(c, G->bytes))
+      return cleanup(fail(c, FNTRS_E_NOMEM, "graph workspace of %zu bytes exceeds the context cap", G->bytes));
+    if (hipMalloc((void**)&G->mem, G->bytes) != hipSuccess) {
+      G->mem = nullptr;
+      return cleanup(fail(c, FNTRS_E_NOMEM, "hipMalloc(%zu) for the graph workspace failed", G->bytes));
+    }
+    c->used += G->bytes;
+    if (!P.blob.empty() && hipMemcpy(G->mem, P.blob.data(), P.blob.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup(fail(c, FNTRS_E_DEVICE, "copying the job tables failed"));
+  }
+  if (int rc = ensure_side_streams(c)) return cleanup(rc);
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+    return cleanup(fail(c, FNTRS_E_DEVICE, "capture stream creation failed"));
+  int rc = FNTRS_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    rc = fail(c, FNTRS_E_DEVICE, "hipStreamBeginCapture failed");
+  } else {
+    rc = run_plan(c, P, G->mem, reinterpret_cast<uint32_t*>(G->mem + blob), cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &graph);
+    G->graph = graph;
+    if (!rc && e != hipSuccess) rc = fail(c, FNTRS_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  }
+  (void)hipStreamDestroy(cs);
+  if (!rc && hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0) != hipSuccess)
+    rc = fail(c, FNTRS_E_DEVICE, "hipGraphInstantiate failed");
+  if (rc) return cleanup(rc);
+  for (fntrs_locator_t* L : P.locs) {
+    L->refs++;
+    G->locs.push_back(L);
+  }
+  *out = G;
+  return FNTRS_OK;
+}
+
+int fntrs_graph_launch(fntrs_ctx* c, fntrs_graph_t* G, void* stream) {
+  if (!c || !G) return FNTRS_E_INVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->err.clear();
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  for (fntrs_locator_t* L : G->locs) HIP_TRY(c, hipStreamWaitEvent(s, L->ready, 0));
+  HIP_TRY(c, hipGraphLaunch(G->exec, s));
+  return FNTRS_OK;
+}
+
+int fntrs_graph_destroy(fntrs_ctx* c, fntrs_graph_t* G) {
+  if (!c || !G) return FNTRS_E_INVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  // hipFree waits for the device, so replays still in flight finish first
+  if (G->exec) (void)hipGraphExecDestroy(G->exec);
+  if (G->graph) (void)hipGraphDestroy(G->graph);
+  if (G->mem) {
+    (void)hipFree(G->mem);
+    c->used -= G->bytes;
+  }
+  for (fntrs_locator_t* L : G->locs) L->refs--;
+  delete G;
+  return FNTRS_OK;
+}
+
+int fntrs_autotune(fntrs_ctx* c, uint32_t op, uint32_t n, uint32_t k, uint32_t lanes, uint32_t batch, uint32_t reps,
+                   void* stream, fntrs_tuning* chosen) {
+  if (!c) return FNTRS_E_INVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->err.clear();
+  if (op != FNTRS_OP_ENCODE && op != FNTRS_OP_DECODE) return fail(c, FNTRS_E_INVAL, "unknown op %u", op);
+  if (!is_pow2(n) || n < 2 || n > 32768)
+    return fail(c, FNTRS_E_INVAL, "n=%u: the tuner covers powers of two in [2, 32768]", n);
+  if (k < 1 || k > n) return fail(c, FNTRS_E_INVAL, "k=%u must satisfy 1 <= k <= n=%u", k, n);
+  if (op == FNTRS_OP_DECODE && !is_pow2(k)) return fail(c, FNTRS_E_UNSUPPORTED, "decoding needs k a power of two");
+  if (lanes < 1 || batch < 1) return fail(c, FNTRS_E_INVAL, "lanes and batch must be >= 1");
+  if (c->device == FNTRS_HOST_ONLY) return fail(c, FNTRS_E_DEVICE, "host-only context: arguments valid, no device");
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  reps = std::max(1u, std::min(reps, 100u));
+  const int L = op == FNTRS_OP_ENCODE ? std::max(1, ilog2(k)) : ilog2(n);
+  if (op == FNTRS_OP_ENCODE && L == 16) return fail(c, FNTRS_E_INVAL, "K = 65536 has one configuration");
+  // scratch input (zero residues: timing does not depend on the values) and output
+  const uint32_t in_rows = k, out_rows = op == FNTRS_OP_ENCODE ? n : k;
+  const size_t in_elems = (size_t)batch * in_rows * lanes, out_elems = (size_t)batch * out_rows * lanes;
+  const size_t bytes = (in_elems + out_elems) * 4;
+  if (!make_room(c, bytes)) return fail(c, FNTRS_E_NOMEM, "tuning buffers of %zu bytes exceed the context cap", bytes);
+  uint32_t* buf = nullptr;
+  if (hipMalloc((void**)&buf, bytes) != hipSuccess) return fail(c, FNTRS_E_NOMEM, "hipMalloc(%zu) failed", bytes);
+  struct Free {
+    uint32_t* p;
+    ~Free() { (void)hipFree(p); }
+  } free_buf{buf};
+  HIP_TRY(c, hipMemsetAsync(buf, 0, bytes, s));
+  uint32_t* in = buf;
+  uint32_t* out = buf + in_elems;
+  fntrs_locator_t* loc = nullptr;
+  if (op == FNTRS_OP_DECODE) {
+    // a coset pattern: every (n/k)-th position
+    std::vector<uint32_t> z(k);
+    for (uint32_t i = 0; i < k; ++i) z[i] = i * (n / k);
+    if (int rc = locator_acquire(c, n, k, z.data(), k, s, &loc)) return rc;
+    HIP_TRY(c, hipStreamWaitEvent(s, loc->ready, 0));
+  }
+  struct Release {
+    fntrs_locator_t* L;
+    ~Release() {
+      if (L) L->refs--;
+    }
+  } rel{loc};
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+  } ev{e0, e1};
+  const CtVariants var = ct_variants(L);
+  const CtCfg* cands = op == FNTRS_OP_ENCODE ? var.enc : var.dec;
+  float best = -1.f;
+  CtCfg best_cfg{};
+  for (int i = 0; i < 4 && cands[i].T; ++i) {
+    const CtCfg cfg = cands[i];
+    auto launch = [&]() -> hipError_t {
+      if (op == FNTRS_OP_ENCODE) {
+        EncodeArgs a{};
+        a.src = in; a.ld_src = lanes; a.stride_src = (size_t)k * lanes;
+        a.dst = out; a.ld_dst = lanes; a.stride_dst = (size_t)n * lanes;
+        a.tw = c->tw; a.twi = c->twi; a.n = n; a.k = k; a.lanes = lanes;
+        a.logn = ilog2(n); a.logK = L;
+        a.tiles = (lanes + cfg.T - 1) / cfg.T; a.cosets = n >> L;
+        a.vec = aligned16(in, lanes, a.stride_src) && aligned16(out, lanes, a.stride_dst);
+        return ct_tables().enc[L](cfg, a, a.tiles * a.cosets * batch, s);
+      }
+      DecodeArgs a{};
+      a.recv = in; a.ld_recv = lanes; a.stride_recv = (size_t)k * lanes;
+      a.dst = out; a.ld_dst = lanes; a.stride_dst = (size_t)k * lanes;
+      a.tw = c->tw; a.twi = c->twi; a.wfull = loc->wfull; a.ridx = loc->ridx; a.ahat_br = loc->ahat_br;
+      a.n = n; a.k = k; a.lanes = lanes; a.logn = loc->logn; a.logk = loc->logk; a.full = 0;
+      a.tiles = (lanes + cfg.T - 1) / cfg.T;
+      a.vec = aligned16(in, lanes, a.stride_recv) && aligned16(out, lanes, a.stride_dst);
+      const int D = (k == n) ? -1 : loc->logn - loc->logm;
+      return ct_tables().dec[L](cfg, D, a, a.tiles * batch, s);
+    };
+    HIP_TRY(c, launch());   // warm-up (first launch loads the code object)
+    HIP_TRY(c, hipEventRecord(e0, s));
+    for (uint32_t r = 0; r < reps; ++r) HIP_TRY(c, launch());
+    HIP_TRY(c, hipEventRecord(e1, s));
+    HIP_TRY(c, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+    ms /= (float)reps;
+    if (best < 0.f || ms < best) {
+      best = ms;
+      best_cfg = cfg;
+    }
+  }
+  if (op == FNTRS_OP_ENCODE) c->enc_cfg[L] = best_cfg;
+  else c->dec_cfg[L] = best_cfg;
+  if (chosen) {
+    const int V = best_cfg.T >= 4 ? 4 : best_cfg.T;
+    chosen->tile_lanes = (uint32_t)best_cfg.T;
+    chosen->threads = (uint32_t)best_cfg.NT;
+    chosen->radix_log2 = (uint32_t)ct::geo_bm(L, best_cfg.T / V, V, best_cfg.NT);
+    chosen->ms = best;
+  }
+  return FNTRS_OK;
+}
+
+int fntrs_get_config(fntrs_ctx* c, uint32_t op, uint32_t log2_size, fntrs_tuning* cfg) {
+  if (!c || !cfg) return FNTRS_E_INVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (op > FNTRS_OP_DECODE || log2_size < 1 || log2_size > 15)
+    return fail(c, FNTRS_E_INVAL, "op %u / size 2^%u has no table configuration", op, log2_size);
+  const CtCfg k = op == FNTRS_OP_ENCODE ? c->enc_cfg[log2_size] : c->dec_cfg[log2_size];
+  const int V = k.T >= 4 ? 4 : k.T;
+  cfg->tile_lanes = (uint32_t)k.T;
+  cfg->threads = (uint32_t)k.NT;
+  cfg->radix_log2 = (uint32_t)ct::geo_bm((int)log2_size, k.T / V, V, k.NT);
+  cfg->ms = 0.f;
+  return FNTRS_OK;
+}
+
+}  // extern "C"

@@ -42,9 +42,28 @@ FNTRS_RECV_COMPACT = 0
 FNTRS_RECV_FULL = 1
 FNTRS_FLAG_VALIDATE = 2
 
+FNTRS_OP_ENCODE = 0
+FNTRS_OP_DECODE = 1
+
 # every symbol the header declares, with (restype, argtypes)
 _u32, _sz, _vp, _int = ctypes.c_uint32, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int
 _pu32 = ctypes.POINTER(ctypes.c_uint32)
+
+
+class fntrs_job(ctypes.Structure):
+    """struct fntrs_job of include/fntrs.h."""
+    _fields_ = [("op", _u32), ("n", _u32), ("k", _u32), ("lanes", _u32), ("batch", _u32), ("flags", _u32),
+                ("loc", _vp), ("in_", _vp), ("ld_in", _sz), ("stride_in", _sz),
+                ("out", _vp), ("ld_out", _sz), ("stride_out", _sz)]
+
+
+class fntrs_tuning(ctypes.Structure):
+    """struct fntrs_tuning of include/fntrs.h."""
+    _fields_ = [("tile_lanes", _u32), ("threads", _u32), ("radix_log2", _u32), ("ms", ctypes.c_float)]
+
+
+_pjob = ctypes.POINTER(fntrs_job)
+_ptun = ctypes.POINTER(fntrs_tuning)
 SIGNATURES = {
     "fntrs_create": (_int, [_int, _sz, ctypes.POINTER(_vp)]),
     "fntrs_destroy": (None, [_vp]),
@@ -54,6 +73,12 @@ SIGNATURES = {
     "fntrs_locator_release": (_int, [_vp, _vp]),
     "fntrs_locator_export": (_int, [_vp, _vp, _pu32, _pu32, _pu32]),
     "fntrs_decode": (_int, [_vp, _vp, _u32, _u32, _vp, _sz, _sz, _vp, _sz, _sz, _u32, _vp]),
+    "fntrs_submit": (_int, [_vp, _pjob, _u32, _vp]),
+    "fntrs_graph_create": (_int, [_vp, _pjob, _u32, ctypes.POINTER(_vp)]),
+    "fntrs_graph_launch": (_int, [_vp, _vp, _vp]),
+    "fntrs_graph_destroy": (_int, [_vp, _vp]),
+    "fntrs_autotune": (_int, [_vp, _u32, _u32, _u32, _u32, _u32, _u32, _vp, _ptun]),
+    "fntrs_get_config": (_int, [_vp, _u32, _u32, _ptun]),
     "fntrs_version": (ctypes.c_char_p, []),
 }
 
@@ -142,8 +167,52 @@ def fntrs_decode(ctx, loc, lanes, flags, recv, ld_recv, stride_recv, dst, ld_dst
                               batch, stream)
 
 
+def fntrs_submit(ctx, jobs, stream=0):
+    """jobs: a ctypes array of fntrs_job (or a list, converted here)."""
+    arr = _job_array(jobs)
+    return lib().fntrs_submit(ctx, arr, len(arr), stream)
+
+
+def fntrs_graph_create(ctx, jobs):
+    """Returns (rc, handle)."""
+    arr = _job_array(jobs)
+    out = _vp()
+    rc = lib().fntrs_graph_create(ctx, arr, len(arr), ctypes.byref(out))
+    return rc, out.value
+
+
+def fntrs_graph_launch(ctx, graph, stream=0):
+    return lib().fntrs_graph_launch(ctx, graph, stream)
+
+
+def fntrs_graph_destroy(ctx, graph):
+    return lib().fntrs_graph_destroy(ctx, graph)
+
+
+def fntrs_autotune(ctx, op, n, k, lanes, batch, reps=5, stream=0):
+    """Returns (rc, fntrs_tuning)."""
+    t = fntrs_tuning()
+    rc = lib().fntrs_autotune(ctx, op, n, k, lanes, batch, reps, stream, ctypes.byref(t))
+    return rc, t
+
+
+def fntrs_get_config(ctx, op, log2_size):
+    t = fntrs_tuning()
+    rc = lib().fntrs_get_config(ctx, op, log2_size, ctypes.byref(t))
+    return rc, t
+
+
 def fntrs_version() -> str:
     return lib().fntrs_version().decode()
+
+
+def _job_array(jobs):
+    if isinstance(jobs, ctypes.Array):
+        return jobs
+    arr = (fntrs_job * max(1, len(jobs)))()
+    for i, j in enumerate(jobs):
+        arr[i] = j
+    return arr if len(jobs) else (fntrs_job * 0)()
 
 
 # ------------------------------------------------------------------ tensor layer
@@ -232,3 +301,59 @@ class Context:
             raise ValueError("recv and dst disagree on batch or lanes")
         _check(self.handle, fntrs_decode(self.handle, loc.handle, lanes, flags, recv.data_ptr(), ld_r, st_r,
                                          dst.data_ptr(), ld_d, st_d, b, _stream_handle(stream)))
+
+    # -------------------------------------------------------------- batches
+    def encode_job(self, src, dst, n: int) -> fntrs_job:
+        """An encode job of the batched path (see encode)."""
+        b, k, lanes, ld_s, st_s = _geom(src)
+        b2, _, lanes2, ld_d, st_d = _geom(dst, n)
+        if b2 != b or lanes2 != lanes:
+            raise ValueError("src and dst disagree on batch or lanes")
+        return fntrs_job(FNTRS_OP_ENCODE, n, k, lanes, b, 0, None, src.data_ptr(), ld_s, st_s,
+                         dst.data_ptr(), ld_d, st_d)
+
+    def decode_job(self, loc: Locator, recv, dst, flags: int = FNTRS_RECV_COMPACT) -> fntrs_job:
+        """A decode job of the batched path (see decode)."""
+        rows = loc.n if flags & FNTRS_RECV_FULL else loc.k
+        b, _, lanes, ld_r, st_r = _geom(recv, rows)
+        b2, _, lanes2, ld_d, st_d = _geom(dst, loc.k)
+        if b2 != b or lanes2 != lanes:
+            raise ValueError("recv and dst disagree on batch or lanes")
+        return fntrs_job(FNTRS_OP_DECODE, loc.n, loc.k, lanes, b, flags, loc.handle, recv.data_ptr(), ld_r, st_r,
+                         dst.data_ptr(), ld_d, st_d)
+
+    def submit(self, jobs, stream=None) -> None:
+        """Enqueues a batch of jobs (encode_job / decode_job) in one call."""
+        _check(self.handle, fntrs_submit(self.handle, jobs, _stream_handle(stream)))
+
+    def graph(self, jobs) -> "Graph":
+        """Captures a batch into a replayable HIP graph."""
+        rc, h = fntrs_graph_create(self.handle, jobs)
+        _check(self.handle, rc)
+        return Graph(self, h)
+
+    def autotune(self, op: int, n: int, k: int, lanes: int, batch: int = 1, reps: int = 5, stream=None):
+        """Times every configuration of the size class and keeps the fastest; returns it as a dict."""
+        rc, t = fntrs_autotune(self.handle, op, n, k, lanes, batch, reps, _stream_handle(stream))
+        _check(self.handle, rc)
+        return {"tile_lanes": t.tile_lanes, "threads": t.threads, "radix_log2": t.radix_log2, "ms": t.ms}
+
+    def config(self, op: int, log2_size: int):
+        rc, t = fntrs_get_config(self.handle, op, log2_size)
+        _check(self.handle, rc)
+        return {"tile_lanes": t.tile_lanes, "threads": t.threads, "radix_log2": t.radix_log2}
+
+
+class Graph:
+    """A captured batch (fntrs_graph_t)."""
+
+    def __init__(self, ctx: Context, handle: int):
+        self.ctx, self.handle = ctx, handle
+
+    def launch(self, stream=None) -> None:
+        _check(self.ctx.handle, fntrs_graph_launch(self.ctx.handle, self.handle, _stream_handle(stream)))
+
+    def destroy(self) -> None:
+        if self.handle:
+            _check(self.ctx.handle, fntrs_graph_destroy(self.ctx.handle, self.handle))
+            self.handle = None

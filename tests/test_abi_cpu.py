@@ -112,3 +112,79 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(fntrs, "_lib", None)
     with pytest.raises(ImportError):
         fntrs.lib()
+
+
+def test_job_struct_layout_matches_header(tmp_path):
+    """The binding's fntrs_job / fntrs_tuning mirror the C structs byte for byte."""
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        pytest.skip("no host C compiler")
+    c = tmp_path / "abi.c"
+    c.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "fntrs.h"\n'
+                 'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(fntrs_job), offsetof(fntrs_job, loc),'
+                 ' offsetof(fntrs_job, in), offsetof(fntrs_job, out), offsetof(fntrs_job, stride_out),'
+                 ' sizeof(fntrs_tuning)); return 0;}\n')
+    exe = tmp_path / "abi"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    J = fntrs.fntrs_job
+    assert got == [ctypes.sizeof(J), J.loc.offset, J.in_.offset, J.out.offset, J.stride_out.offset,
+                   ctypes.sizeof(fntrs.fntrs_tuning)]
+
+
+def ejob(n, k, lanes, src, dst, batch=1, flags=0):
+    return fntrs.fntrs_job(fntrs.FNTRS_OP_ENCODE, n, k, lanes, batch, flags, None, src, lanes, k * lanes,
+                           dst, lanes, n * lanes)
+
+
+def test_submit_validation(hctx):
+    MB = 1 << 20
+    ok = [ejob(512, 256, 64, SRC, DST), ejob(1024, 100, 33, SRC + MB, DST + MB), ejob(65536, 40000, 4, SRC + 2 * MB,
+                                                                                       DST + 2 * MB)]
+    assert fntrs.fntrs_submit(hctx, ok) == fntrs.FNTRS_E_DEVICE      # valid batch, no device
+    assert fntrs.fntrs_submit(hctx, []) == fntrs.FNTRS_E_DEVICE
+    # one bad job names its index
+    bad = ok + [ejob(96, 4, 4, SRC + 3 * MB, DST + 3 * MB)]
+    assert fntrs.fntrs_submit(hctx, bad) == fntrs.FNTRS_E_INVAL
+    assert "job 3" in fntrs.fntrs_last_error(hctx)
+    # an output overlapping another job's input
+    clash = [ejob(512, 256, 64, SRC, DST), ejob(512, 256, 64, DST + 4096, DST + MB)]
+    assert fntrs.fntrs_submit(hctx, clash) == fntrs.FNTRS_E_INVAL
+    assert "overlap" in fntrs.fntrs_last_error(hctx)
+    # two jobs reading the same input is fine
+    shared = [ejob(512, 256, 64, SRC, DST), ejob(1024, 256, 64, SRC, DST + MB)]
+    assert fntrs.fntrs_submit(hctx, shared) == fntrs.FNTRS_E_DEVICE
+    # validate flag, unknown op, decode without locator, encode with a locator
+    assert fntrs.fntrs_submit(hctx, [ejob(512, 256, 64, SRC, DST, flags=fntrs.FNTRS_FLAG_VALIDATE)]) \
+        == fntrs.FNTRS_E_INVAL
+    j = ejob(512, 256, 64, SRC, DST)
+    j.op = 7
+    assert fntrs.fntrs_submit(hctx, [j]) == fntrs.FNTRS_E_INVAL
+    j = ejob(512, 256, 64, SRC, DST)
+    j.op = fntrs.FNTRS_OP_DECODE
+    assert fntrs.fntrs_submit(hctx, [j]) == fntrs.FNTRS_E_INVAL
+    assert "locator" in fntrs.fntrs_last_error(hctx)
+    j = ejob(512, 256, 64, SRC, DST)
+    j.loc = 0x1234
+    assert fntrs.fntrs_submit(hctx, [j]) == fntrs.FNTRS_E_INVAL
+    L = fntrs.lib()
+    assert L.fntrs_submit(None, None, 0, None) == fntrs.FNTRS_E_INVAL
+    assert L.fntrs_submit(hctx, None, 3, None) == fntrs.FNTRS_E_INVAL
+
+
+def test_graph_and_tuner_validation(hctx):
+    rc, g = fntrs.fntrs_graph_create(hctx, [ejob(512, 256, 64, SRC, DST)])
+    assert rc == fntrs.FNTRS_E_DEVICE and g is None
+    assert fntrs.fntrs_graph_create(hctx, [])[0] == fntrs.FNTRS_E_INVAL
+    L = fntrs.lib()
+    assert L.fntrs_graph_launch(hctx, None, None) == fntrs.FNTRS_E_INVAL
+    assert L.fntrs_graph_destroy(hctx, None) == fntrs.FNTRS_E_INVAL
+    assert fntrs.fntrs_autotune(hctx, 0, 8192, 4096, 64, 1)[0] == fntrs.FNTRS_E_DEVICE
+    assert fntrs.fntrs_autotune(hctx, 2, 8192, 4096, 64, 1)[0] == fntrs.FNTRS_E_INVAL
+    assert fntrs.fntrs_autotune(hctx, 0, 65536, 4096, 64, 1)[0] == fntrs.FNTRS_E_INVAL
+    assert fntrs.fntrs_autotune(hctx, 1, 8192, 3000, 64, 1)[0] == fntrs.FNTRS_E_UNSUPPORTED
+    assert fntrs.fntrs_autotune(hctx, 0, 8192, 4096, 0, 1)[0] == fntrs.FNTRS_E_INVAL
+    rc, t = fntrs.fntrs_get_config(hctx, 1, 13)
+    assert rc == fntrs.FNTRS_OK and t.tile_lanes >= 1 and t.threads >= 64 and 1 <= t.radix_log2 <= 5
+    assert fntrs.fntrs_get_config(hctx, 0, 16)[0] == fntrs.FNTRS_E_INVAL

@@ -1,0 +1,221 @@
+"""The batched path (fntrs_submit, captured graphs, autotuner) on the GPU.
+
+A batch must compute exactly what its jobs compute one call at a time: every
+output is compared with the single-call path element by element, decoding
+must return the source on every lane (unique interpolant, Sec. II-B), and
+sampled rows / lanes are checked against the CPU oracle.  Sizes follow the
+uneven-batch workload (k = 2^6..2^14, rate 1/2 or 1/4, uneven lane counts,
+one erasure pattern per codeword), scaled down in lanes so the oracle checks
+stay fast.
+"""
+import numpy as np
+import pytest
+
+from oracle import codec
+from paper_0907_1788_amd import fntrs, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = fntrs.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a).astype(np.int32)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy().astype(np.int64)
+
+
+class Codeword:
+    """One codeword block set of the batch: source, encoded, received, decoded buffers."""
+
+    def __init__(self, ctx, i, k, n, lanes, blocks=1, seed=0, full=False):
+        self.k, self.n, self.lanes, self.blocks, self.full = k, n, lanes, blocks, full
+        self.src_np = synth.source(seed * 100003 + i, blocks, k, lanes)
+        self.src = dev(self.src_np)
+        self.enc = torch.full((blocks, n, lanes), -7, dtype=torch.int32, device="cuda")
+        self.z = synth.received_positions(seed * 7919 + i, n, k)
+        self.loc = ctx.locator(n, k, self.z)
+        self.dec = torch.full((blocks, k, lanes), -7, dtype=torch.int32, device="cuda")
+        self.recv = None
+
+    def make_recv(self):
+        """Received rows (compact) from the encoded buffer, or the full buffer itself."""
+        if self.full:
+            self.recv = self.enc
+        else:
+            idx = torch.from_numpy(self.z.astype(np.int64)).cuda()
+            self.recv = self.enc.index_select(1, idx).contiguous()
+
+    def dec_flags(self):
+        return fntrs.FNTRS_RECV_FULL if self.full else fntrs.FNTRS_RECV_COMPACT
+
+
+def build_batch(ctx, sizes, seed, blocks=1):
+    return [Codeword(ctx, i, k, n, lanes, blocks, seed, full=(i % 3 == 0)) for i, (k, n, lanes) in enumerate(sizes)]
+
+
+def check_against_singles(ctx, cws):
+    """Batch outputs equal the single calls' outputs, bit for bit."""
+    for cw in cws:
+        e = torch.empty_like(cw.enc)
+        ctx.encode(cw.src, e, cw.n)
+        d = torch.empty_like(cw.dec)
+        ctx.decode(cw.loc, cw.recv, d, cw.dec_flags())
+        torch.cuda.synchronize()
+        assert torch.equal(e, cw.enc), ("encode", cw.k, cw.n, cw.lanes)
+        assert torch.equal(d, cw.dec), ("decode", cw.k, cw.n, cw.lanes)
+
+
+def check_against_oracle(cws, lanes_checked=2):
+    for cw in cws:
+        # every lane decodes back to its source (P14)
+        assert np.array_equal(host(cw.dec), cw.src_np.astype(np.int64)), ("roundtrip", cw.k, cw.n, cw.lanes)
+        # sampled encoded rows against the oracle's Horner evaluation
+        rows = np.unique(np.concatenate([[0, 1 % cw.n, cw.n - 1], synth.stream(cw.n + cw.k, 6) % np.uint64(cw.n)])
+                         .astype(np.int64))
+        lanes = [0, cw.lanes - 1][:lanes_checked]
+        got = host(cw.enc)[0][rows][:, lanes]
+        ref = codec.encode(cw.src_np[0][:, lanes], cw.n, rows=rows)
+        assert np.array_equal(got, ref), ("encode rows", cw.k, cw.n)
+
+
+def small_uneven(seed, count, max_lanes, max_k):
+    out = []
+    for k, n, lanes in synth.uneven_batch(seed, 4 * count):
+        if k <= max_k:
+            out.append((k, n, max(1, lanes * max_lanes // 8192)))
+        if len(out) == count:
+            break
+    return out
+
+
+def run_submit(ctx, cws):
+    ctx.submit([ctx.encode_job(cw.src, cw.enc, cw.n) for cw in cws])
+    for cw in cws:
+        cw.make_recv()
+    ctx.submit([ctx.decode_job(cw.loc, cw.recv, cw.dec, cw.dec_flags()) for cw in cws])
+    torch.cuda.synchronize()
+
+
+def test_submit_uneven_batch(ctx):
+    sizes = small_uneven(seed=4, count=40, max_lanes=300, max_k=4096)
+    # ragged and tiny codes, k = n, a non-power-of-two encode size
+    sizes += [(1, 1, 5), (2, 2, 7), (64, 64, 33), (4, 256, 3), (1024, 2048, 130)]
+    say("submit uneven", len(sizes), "codewords")
+    cws = build_batch(ctx, sizes, seed=1)
+    run_submit(ctx, cws)
+    check_against_oracle(cws)
+    check_against_singles(ctx, cws)
+    for cw in cws:
+        cw.loc.release()
+
+
+def test_submit_full_range_sizes(ctx):
+    """The workload's largest codes: k = 16384 at rate 1/4 (n = 65536, four-step decode) and rate 1/2."""
+    sizes = [(16384, 65536, 40), (16384, 32768, 37), (8192, 32768, 16), (64, 128, 1000), (128, 512, 9)]
+    say("submit full range", sizes)
+    cws = build_batch(ctx, sizes, seed=2)
+    run_submit(ctx, cws)
+    check_against_oracle(cws, lanes_checked=1)
+    check_against_singles(ctx, cws)
+    for cw in cws:
+        cw.loc.release()
+
+
+def test_submit_persistent_loop(ctx):
+    """Classes with many more work items than resident workgroups, several blocks per job."""
+    sizes = [(256, 512, 2048), (256, 1024, 1500), (512, 1024, 777)]
+    say("submit persistent", sizes)
+    cws = build_batch(ctx, sizes, seed=3, blocks=6)
+    run_submit(ctx, cws)
+    for cw in cws:
+        assert np.array_equal(host(cw.dec), cw.src_np.astype(np.int64))
+    check_against_singles(ctx, cws)
+    for cw in cws:
+        cw.loc.release()
+
+
+def test_submit_decodes_arbitrary_received_values(ctx):
+    """Non-codeword received data: the exact interpolant, against the Lagrange oracle."""
+    specs = [(64, 128, 5), (256, 1024, 3), (512, 1024, 4)]
+    jobs, outs, refs, locs = [], [], [], []
+    for i, (k, n, lanes) in enumerate(specs):
+        z = synth.received_positions(500 + i, n, k)
+        loc = ctx.locator(n, k, z)
+        rnd = synth.residues(600 + i, (1, k, lanes))
+        r = dev(rnd)
+        d = torch.full((1, k, lanes), -7, dtype=torch.int32, device="cuda")
+        jobs.append(ctx.decode_job(loc, r, d))
+        outs.append((r, d))
+        refs.append(codec.decode_lagrange(n, z, rnd[0]))
+        locs.append(loc)
+    ctx.submit(jobs)
+    torch.cuda.synchronize()
+    for (r, d), ref in zip(outs, refs):
+        assert np.array_equal(host(d)[0], ref)
+    for loc in locs:
+        loc.release()
+
+
+def test_graph_replays_match_eager(ctx):
+    """A captured batch replayed several times, with new inputs and eager work between replays."""
+    sizes = small_uneven(seed=9, count=12, max_lanes=200, max_k=2048) + [(16384, 65536, 8)]
+    say("graph", len(sizes))
+    cws = build_batch(ctx, sizes, seed=4)
+    # encode graph, then decode graph over the received rows
+    g_enc = ctx.graph([ctx.encode_job(cw.src, cw.enc, cw.n) for cw in cws])
+    compact = [cw for cw in cws if not cw.full]
+    for cw in compact:
+        cw.recv = torch.zeros((cw.blocks, cw.k, cw.lanes), dtype=torch.int32, device="cuda")
+    for cw in cws:
+        if cw.full:
+            cw.recv = cw.enc
+    g_dec = ctx.graph([ctx.decode_job(cw.loc, cw.recv, cw.dec, cw.dec_flags()) for cw in cws])
+    for rep in range(3):
+        for cw in cws:
+            cw.src_np = synth.source(7000 + 31 * rep + cw.k + cw.lanes, cw.blocks, cw.k, cw.lanes)
+            cw.src.copy_(dev(cw.src_np))
+        g_enc.launch()
+        torch.cuda.synchronize()
+        for cw in compact:
+            idx = torch.from_numpy(cw.z.astype(np.int64)).cuda()
+            cw.recv.copy_(cw.enc.index_select(1, idx))
+        g_dec.launch()
+        torch.cuda.synchronize()
+        for cw in cws:
+            assert np.array_equal(host(cw.dec), cw.src_np.astype(np.int64)), ("replay", rep, cw.k, cw.n)
+        check_against_singles(ctx, cws)
+    g_enc.destroy()
+    g_dec.destroy()
+    for cw in cws:
+        cw.loc.release()
+
+
+def test_autotune_keeps_results_exact(ctx):
+    """The tuner picks one of the compiled configurations; results stay bit-exact under it."""
+    from paper_0907_1788_amd.fntrs import FNTRS_OP_DECODE, FNTRS_OP_ENCODE
+    say("autotune")
+    for op, n, k in [(FNTRS_OP_ENCODE, 8192, 4096), (FNTRS_OP_DECODE, 8192, 4096), (FNTRS_OP_DECODE, 4096, 2048)]:
+        t = ctx.autotune(op, n, k, lanes=512, batch=2, reps=2)
+        assert t["ms"] > 0 and t["tile_lanes"] >= 1 and t["threads"] in (256, 512, 1024)
+        L = (k - 1).bit_length() if op == FNTRS_OP_ENCODE else n.bit_length() - 1
+        assert ctx.config(op, L)["tile_lanes"] == t["tile_lanes"]
+    cws = build_batch(ctx, [(4096, 8192, 70), (2048, 4096, 9)], seed=5)
+    run_submit(ctx, cws)
+    check_against_oracle(cws, lanes_checked=1)
+    check_against_singles(ctx, cws)
+    for cw in cws:
+        cw.loc.release()
