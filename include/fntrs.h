@@ -112,6 +112,19 @@ int fntrs_locator(fntrs_ctx* ctx, uint32_t n, uint32_t k,
                   const uint32_t* positions, uint32_t npos,
                   void* stream, fntrs_locator_t** out);
 
+/* Locators of `count` erasure patterns at once: pattern q has code length
+ * n[q], k[q] source symbols and npos[q] received positions at positions[q]
+ * (host memory, the rules of fntrs_locator).  Patterns not in the cache are
+ * built together, one launch per stage for all of them (O(log k) launches
+ * in total instead of per pattern), and share one device allocation that is
+ * returned when the last of them leaves the cache.  out[q] receives a
+ * reference as from fntrs_locator (release each).  All or nothing: on error
+ * no reference is returned and fntrs_last_error names the pattern.  Errors:
+ * those of fntrs_locator. */
+int fntrs_locator_batch(fntrs_ctx* ctx, uint32_t count, const uint32_t* n, const uint32_t* k,
+                        const uint32_t* const* positions, const uint32_t* npos,
+                        void* stream, fntrs_locator_t** out);
+
 /* Give back a locator reference.  The state stays cached for reuse until the
  * context needs the memory; work already enqueued that uses it is not
  * affected.  Errors: FNTRS_E_INVAL. */

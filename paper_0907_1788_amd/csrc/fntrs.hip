@@ -120,12 +120,8 @@ int validate_range(fntrs_ctx* c, const uint32_t* p, uint32_t batch, size_t strid
 }
 
 static void free_locator(fntrs_ctx* c, fntrs_locator_t* L) {
-  if (L->ready) (void)hipEventDestroy(L->ready);
-  if (L->mem) {
-    (void)hipFree(L->mem);
-    c->used -= L->bytes;
-  }
-  delete L;
+  if (L->slab) c->used -= L->bytes;
+  delete L;   // the slab goes with its last locator
 }
 
 // Least recently used first.
@@ -143,90 +139,189 @@ bool make_room(fntrs_ctx* c, size_t need) {
   return true;
 }
 
-static int build_locator(fntrs_ctx* c, fntrs_locator_t* L, hipStream_t s) {
-  const uint32_t n = L->n, k = L->k;
-  const int logn = L->logn, logk = L->logk;
-  const size_t M = (k < n) ? (size_t)1 << L->logm : 0;
-  // device layout: pos[k] wfull[n] ridx[n] ahat_br[M] ahat_s[M] A[k+1] w[k] ahat[M]
-  //                | scratch: t0[k] t1[k] spec[k] vals[n]
-  const size_t state = k + 2ull * n + 2 * M + (k + 1) + k + M;
-  const size_t scratch = (k < n) ? 3ull * k + n : 0;
-  L->bytes = (state + scratch) * 4;
-  if (!make_room(c, L->bytes))
-    return fail(c, FNTRS_E_NOMEM, "locator of %zu bytes exceeds the context cap (%zu used of %zu)", L->bytes,
-                c->used, c->cap);
-  hipError_t e = hipMalloc((void**)&L->mem, L->bytes);
-  if (e != hipSuccess) {
-    L->mem = nullptr;
-    return fail(c, FNTRS_E_NOMEM, "hipMalloc(%zu) for locator failed: %s", L->bytes, hipGetErrorString(e));
-  }
-  c->used += L->bytes;
-  uint32_t* p = L->mem;
-  L->pos = p; p += k;
-  L->wfull = p; p += n;
-  L->ridx = p; p += n;
-  L->ahat_br = p; p += M;
-  L->ahat_s = p; p += M;
-  L->A = p; p += k + 1;
-  L->w = p; p += k;
-  L->ahat = p; p += M;
-  uint32_t* t0 = p; p += (k < n) ? k : 0;
-  uint32_t* t1 = p; p += (k < n) ? k : 0;
-  uint32_t* spec = p; p += (k < n) ? k : 0;
-  uint32_t* vals = p;
+namespace {
 
-  HIP_TRY(c, hipMemcpyAsync(L->pos, L->positions.data(), k * 4ull, hipMemcpyHostToDevice, s));
-  if (k == n) {
-    // Nothing erased: the decoder is the inverse FNT_n with factor n^-1.
-    const uint32_t ninv = 65537u - (65536u >> logn);
-    hipLaunchKernelGGL(k_loc_identity, dim3((n + 255) / 256), dim3(256), 0, s, L->wfull, L->ridx, n, ninv);
-    // A = x^n - 1 for export
-    hipLaunchKernelGGL(k_loc_fill, dim3((k + 256) / 256), dim3(256), 0, s, L->A, k + 1, 0u);
-    hipLaunchKernelGGL(k_loc_fill, dim3(1), dim3(1), 0, s, L->A, 1u, 65536u);
-    hipLaunchKernelGGL(k_loc_fill, dim3(1), dim3(1), 0, s, L->A + k, 1u, 1u);
-    HIP_TRY(c, hipGetLastError());
-  } else {
-    // Step 1: product tree.  Leaves of G points, then FNT products up to degree k.
-    const int G = (int)std::min<uint32_t>(k, 64);
-    hipLaunchKernelGGL(k_loc_leaves, dim3(k / G), dim3(64), 0, s, L->pos, logn, G, c->tw, t0);
-    HIP_TRY(c, hipGetLastError());
-    uint32_t* cur = t0;
-    uint32_t* nxt = t1;
-    for (uint32_t d = G; d < k; d *= 2) {
-      const size_t lds = 2ull * d * 4;
-      (void)set_lds_attr((const void*)k_loc_mul_level, lds);
-      const int nt = (int)std::min<uint32_t>(1024, std::max<uint32_t>(64, d / 2));
-      hipLaunchKernelGGL(k_loc_mul_level, dim3(k / (2 * d)), dim3(nt), lds, s, cur, ilog2(d), c->tw, spec, nxt);
-      HIP_TRY(c, hipGetLastError());
-      std::swap(cur, nxt);
-    }
-    // cur holds a_0..a_(k-1); A = x^k + ...
-    HIP_TRY(c, hipMemcpyAsync(L->A, cur, k * 4ull, hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_loc_fill, dim3(1), dim3(1), 0, s, L->A + k, 1u, 1u);
-    HIP_TRY(c, hipGetLastError());
-    // Step 2: A'.
-    hipLaunchKernelGGL(k_loc_derivative, dim3((k + 255) / 256), dim3(256), 0, s, cur, k, spec);
-    HIP_TRY(c, hipGetLastError());
-    // Step 3: A' at every n-th root (n/k twisted FNT_k), then the weights.
-    const size_t ldsk = (size_t)k * 4;
-    (void)set_lds_attr((const void*)k_loc_eval, ldsk);
-    const int ntk = (int)std::min<uint32_t>(1024, std::max<uint32_t>(64, k / 4));
-    hipLaunchKernelGGL(k_loc_eval, dim3(n / k), dim3(ntk), ldsk, s, spec, logk, logn, c->tw, vals);
-    HIP_TRY(c, hipGetLastError());
-    hipLaunchKernelGGL(k_loc_fill, dim3((n + 255) / 256), dim3(256), 0, s, L->wfull, n, 0u);
-    hipLaunchKernelGGL(k_loc_weights, dim3((k + 255) / 256), dim3(256), 0, s, L->pos, vals, k, logn, c->tw, L->w,
-                       L->wfull, L->ridx);
-    HIP_TRY(c, hipGetLastError());
-    // FNT_M of (a_0..a_(k-1), 0..0): M/k twisted FNT_k; then the decoder's
-    // copy, bit-reversed and scaled by M^-1.
-    hipLaunchKernelGGL(k_loc_eval, dim3((uint32_t)(M / k)), dim3(ntk), ldsk, s, cur, logk, L->logm, c->tw, L->ahat);
-    HIP_TRY(c, hipGetLastError());
-    hipLaunchKernelGGL(k_loc_ahat, dim3((uint32_t)((M + 255) / 256)), dim3(256), 0, s, L->ahat, L->logm, L->ahat_br,
-                       L->ahat_s);
-    HIP_TRY(c, hipGetLastError());
+size_t round_words(size_t w) { return (w + 63) / 64 * 64; }   // 256-byte aligned views
+
+// Words of device state of a locator: pos[k] wfull[n] ridx[n] ahat_br[M]
+// ahat_s[M] A[k+1] w[k] ahat[M] (M = 0 when nothing is erased).
+size_t state_words(const fntrs_locator_t* L) {
+  const size_t n = L->n, k = L->k, M = (k < n) ? (size_t)1 << L->logm : 0;
+  return round_words(k) + 2 * round_words(n) + 3 * round_words(M) + round_words(k + 1) + round_words(k);
+}
+
+struct Range {
+  uint32_t first = 0, count = 0;
+};
+
+}  // namespace
+
+// Builds the device state of the locators `Ls` (steps 1-3 of Sec. II-B and
+// the tables of steps 4 and 6) with one launch per stage for all of them:
+// patterns sorted by k (nothing-erased patterns last), so that every stage
+// covers a contiguous range of the descriptor table.
+static int build_locators(fntrs_ctx* c, std::vector<fntrs_locator_t*>& Ls, hipStream_t s) {
+  std::stable_sort(Ls.begin(), Ls.end(), [](const fntrs_locator_t* a, const fntrs_locator_t* b) {
+    const bool ia = a->k == a->n, ib = b->k == b->n;
+    return ia != ib ? ib : a->k < b->k;
+  });
+  const uint32_t P = (uint32_t)Ls.size();
+  uint32_t Pn = 0;   // patterns with erasures
+  while (Pn < P && Ls[Pn]->k < Ls[Pn]->n) ++Pn;
+  // persistent state: one slab for the batch
+  size_t words = 0;
+  for (auto* L : Ls) {
+    L->bytes = state_words(L) * 4;
+    words += state_words(L);
   }
-  HIP_TRY(c, hipEventCreateWithFlags(&L->ready, hipEventDisableTiming));
-  HIP_TRY(c, hipEventRecord(L->ready, s));
+  if (!make_room(c, words * 4))
+    return fail(c, FNTRS_E_NOMEM, "locator state of %zu bytes exceeds the context cap (%zu used of %zu)", words * 4,
+                c->used, c->cap);
+  auto slab = std::make_shared<LocSlab>();
+  if (hipMalloc((void**)&slab->mem, words * 4) != hipSuccess) {
+    slab->mem = nullptr;
+    return fail(c, FNTRS_E_NOMEM, "hipMalloc(%zu) for locator state failed", words * 4);
+  }
+  HIP_TRY(c, hipEventCreateWithFlags(&slab->ready, hipEventDisableTiming));
+  // host image: descriptors, positions, stage start tables
+  std::vector<LocDesc> desc(P);
+  std::vector<uint32_t> zall;
+  size_t scratch = 0;
+  uint32_t* p = slab->mem;
+  std::vector<size_t> zoff(P), soff(P);
+  for (uint32_t i = 0; i < P; ++i) {
+    fntrs_locator_t* L = Ls[i];
+    const size_t n = L->n, k = L->k, M = (k < n) ? (size_t)1 << L->logm : 0;
+    L->pos = p; p += round_words(k);
+    L->wfull = p; p += round_words(n);
+    L->ridx = p; p += round_words(n);
+    L->ahat_br = p; p += round_words(M);
+    L->ahat_s = p; p += round_words(M);
+    L->A = p; p += round_words(k + 1);
+    L->w = p; p += round_words(k);
+    L->ahat = p; p += round_words(M);
+    L->slab = slab;
+    L->ready = slab->ready;
+    zoff[i] = zall.size();
+    zall.insert(zall.end(), L->positions.begin(), L->positions.end());
+    soff[i] = scratch;
+    if (k < n) scratch += 3 * round_words(k) + round_words(n);
+    LocDesc& d = desc[i];
+    d = LocDesc{};
+    d.pos = L->pos; d.wfull = L->wfull; d.ridx = L->ridx; d.ahat_br = L->ahat_br; d.ahat_s = L->ahat_s;
+    d.A = L->A; d.w = L->w; d.ahat = L->ahat;
+    d.n = L->n; d.k = L->k; d.G = std::min<uint32_t>(L->k, 64);
+    d.logn = L->logn; d.logk = L->logk; d.logm = L->logm;
+  }
+  // stage tables: (range of descriptors, start offsets relative to the range)
+  std::vector<uint32_t> tab;
+  struct Stage {
+    Range r;
+    size_t start_off;   // in words within tab
+    uint32_t total;
+  };
+  auto add_stage = [&](Range r, auto per) {
+    Stage st{r, tab.size(), 0};
+    uint64_t acc = 0;
+    for (uint32_t q = 0; q < r.count; ++q) {
+      tab.push_back((uint32_t)acc);
+      acc += per(Ls[r.first + q]);
+    }
+    tab.push_back((uint32_t)acc);
+    st.total = (uint32_t)acc;
+    return st;
+  };
+  const Stage prep = add_stage({0, P}, [](const fntrs_locator_t* L) { return (uint64_t)L->k + L->n; });
+  const Stage leaves =
+      add_stage({0, Pn}, [](const fntrs_locator_t* L) { return (uint64_t)L->k / std::min<uint32_t>(L->k, 64); });
+  std::vector<std::pair<int, Stage>> levels;   // (log2 d, stage)
+  for (int logd = 6; logd <= 15; ++logd) {
+    uint32_t first = 0;
+    while (first < Pn && Ls[first]->k <= (1u << logd)) ++first;
+    if (first == Pn) break;
+    levels.emplace_back(logd, add_stage({first, Pn - first}, [logd](const fntrs_locator_t* L) {
+                          return (uint64_t)L->k >> (logd + 1);
+                        }));
+  }
+  const Stage deriv = add_stage({0, Pn}, [](const fntrs_locator_t* L) { return (uint64_t)L->k; });
+  std::vector<std::pair<int, Stage>> evals;   // (log2 k, stage)
+  for (uint32_t first = 0; first < Pn;) {
+    uint32_t last = first;
+    while (last < Pn && Ls[last]->k == Ls[first]->k) ++last;
+    evals.emplace_back(Ls[first]->logk, add_stage({first, last - first}, [](const fntrs_locator_t* L) {
+                         return (uint64_t)(L->n >> L->logk) + ((1ull << L->logm) >> L->logk);
+                       }));
+    first = last;
+  }
+  const Stage weights = add_stage({0, Pn}, [](const fntrs_locator_t* L) { return (uint64_t)L->k; });
+  const Stage ahat = add_stage({0, Pn}, [](const fntrs_locator_t* L) { return 1ull << L->logm; });
+  // one transient allocation: descriptors | positions | tables | scratch
+  const size_t desc_bytes = (P * sizeof(LocDesc) + 255) / 256 * 256;
+  const size_t z_words = round_words(zall.size()), tab_words = round_words(tab.size());
+  const size_t tmp_bytes = desc_bytes + (z_words + tab_words + scratch) * 4;
+  uint8_t* tmp = nullptr;
+  hipError_t e = hipMallocAsync((void**)&tmp, tmp_bytes, s);
+  if (e != hipSuccess) return fail(c, FNTRS_E_NOMEM, "locator build buffer of %zu bytes: %s", tmp_bytes,
+                                   hipGetErrorString(e));
+  uint32_t* dz = reinterpret_cast<uint32_t*>(tmp + desc_bytes);
+  uint32_t* dtab = dz + z_words;
+  uint32_t* dscr = dtab + tab_words;
+  for (uint32_t i = 0; i < P; ++i) {
+    LocDesc& d = desc[i];
+    d.zin = dz + zoff[i];
+    if (d.k < d.n) {
+      uint32_t* q = dscr + soff[i];
+      const size_t kw = round_words(d.k);
+      d.t0 = q; d.t1 = q + kw; d.spec = q + 2 * kw; d.vals = q + 3 * kw;
+      const int nlev = ilog2(d.k / d.G);
+      d.poly = (nlev & 1) ? d.t1 : d.t0;
+    }
+  }
+  std::vector<uint8_t> img(tmp_bytes - scratch * 4, 0);
+  std::memcpy(img.data(), desc.data(), P * sizeof(LocDesc));
+  std::memcpy(img.data() + desc_bytes, zall.data(), zall.size() * 4);
+  std::memcpy(img.data() + desc_bytes + z_words * 4, tab.data(), tab.size() * 4);
+  auto fail_free = [&](int rc) {
+    (void)hipFreeAsync(tmp, s);
+    return rc;
+  };
+  if (hipMemcpyAsync(tmp, img.data(), img.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+    return fail_free(fail(c, FNTRS_E_DEVICE, "locator upload failed"));
+  const LocDesc* D = reinterpret_cast<const LocDesc*>(tmp);
+  auto launch_err = [&]() { return hipGetLastError(); };
+  auto st_ptr = [&](const Stage& st) { return dtab + st.start_off; };
+  const uint32_t* tw = c->tw;
+  hipLaunchKernelGGL(k_locb_prep, dim3((prep.total + 255) / 256), dim3(256), 0, s, D, st_ptr(prep), P);
+  if (Pn) {
+    hipLaunchKernelGGL(k_locb_leaves, dim3(leaves.total), dim3(64), 0, s, D, st_ptr(leaves), Pn, tw);
+    for (size_t j = 0; j < levels.size(); ++j) {
+      const int logd = levels[j].first;
+      const Stage& st = levels[j].second;
+      const uint32_t d = 1u << logd;
+      const size_t lds = 2ull * d * 4;
+      (void)set_lds_attr((const void*)k_locb_level, lds);
+      const int nt = (int)std::min<uint32_t>(1024, std::max<uint32_t>(64, d / 2));
+      hipLaunchKernelGGL(k_locb_level, dim3(st.total), dim3(nt), lds, s, D + st.r.first, st_ptr(st), st.r.count, logd,
+                         (int)j, tw);
+    }
+    hipLaunchKernelGGL(k_locb_derivative, dim3((deriv.total + 255) / 256), dim3(256), 0, s, D, st_ptr(deriv), Pn);
+    for (auto& ev : evals) {
+      const uint32_t K = 1u << ev.first;
+      const size_t lds = (size_t)K * 4;
+      (void)set_lds_attr((const void*)k_locb_eval, lds);
+      const int nt = (int)std::min<uint32_t>(1024, std::max<uint32_t>(64, K / 4));
+      hipLaunchKernelGGL(k_locb_eval, dim3(ev.second.total), dim3(nt), lds, s, D + ev.second.r.first,
+                         st_ptr(ev.second), ev.second.r.count, ev.first, tw);
+    }
+    hipLaunchKernelGGL(k_locb_weights, dim3((weights.total + 255) / 256), dim3(256), 0, s, D, st_ptr(weights), Pn,
+                       tw);
+    hipLaunchKernelGGL(k_locb_ahat, dim3((ahat.total + 255) / 256), dim3(256), 0, s, D, st_ptr(ahat), Pn);
+  }
+  if (hipError_t le = launch_err(); le != hipSuccess)
+    return fail_free(fail(c, FNTRS_E_DEVICE, "locator kernels: %s", hipGetErrorString(le)));
+  if (hipEventRecord(slab->ready, s) != hipSuccess) return fail_free(fail(c, FNTRS_E_DEVICE, "event record failed"));
+  (void)hipFreeAsync(tmp, s);
+  for (auto* L : Ls) c->used += L->bytes;
   return FNTRS_OK;
 }
 
@@ -238,47 +333,75 @@ hipError_t launch_copy(const uint32_t* src, size_t stride_src, uint32_t* dst, si
   return hipGetLastError();
 }
 
-int locator_acquire(fntrs_ctx* c, uint32_t n, uint32_t k, const uint32_t* positions, uint32_t npos,
-                    hipStream_t stream, fntrs_locator_t** out) {
+int locators_acquire(fntrs_ctx* c, uint32_t count, const uint32_t* n_, const uint32_t* k_,
+                     const uint32_t* const* positions_, const uint32_t* npos_, hipStream_t stream,
+                     fntrs_locator_t** out) {
   if (!out) return fail(c, FNTRS_E_INVAL, "null out");
-  *out = nullptr;
-  if (!is_pow2(n) || n > 65536) return fail(c, FNTRS_E_INVAL, "n=%u must be a power of two in [1, 65536]", n);
-  if (k < 1 || k > n) return fail(c, FNTRS_E_INVAL, "k=%u must satisfy 1 <= k <= n=%u", k, n);
-  if (!positions) return fail(c, FNTRS_E_INVAL, "null positions");
-  if (npos < k) return fail(c, FNTRS_E_TOOFEW, "%u positions received, k=%u needed", npos, k);
-  for (uint32_t i = 0; i < k; ++i) {
-    if (positions[i] >= n) return fail(c, FNTRS_E_POSITIONS, "position %u at index %u is >= n=%u", positions[i], i, n);
-    if (i && positions[i] <= positions[i - 1])
-      return fail(c, FNTRS_E_POSITIONS, "positions must be strictly ascending (index %u)", i);
-  }
-  if (!is_pow2(k)) return fail(c, FNTRS_E_UNSUPPORTED, "decoding needs k a power of two, got %u", k);
-  const uint64_t key = hash_positions(n, k, positions);
-  auto range = c->cache.equal_range(key);
-  for (auto it = range.first; it != range.second; ++it) {
-    fntrs_locator_t* L = it->second;
-    if (L->n == n && L->k == k && std::equal(L->positions.begin(), L->positions.end(), positions)) {
-      L->refs++;
-      L->last_use = ++c->tick;
-      *out = L;
-      return FNTRS_OK;
+  if (count && (!n_ || !k_ || !positions_ || !npos_)) return fail(c, FNTRS_E_INVAL, "null argument array");
+  for (uint32_t q = 0; q < count; ++q) out[q] = nullptr;
+  auto give_back = [&](uint32_t upto) {
+    for (uint32_t q = 0; q < upto; ++q)
+      if (out[q]) { out[q]->refs--; out[q] = nullptr; }
+  };
+  std::vector<fntrs_locator_t*> fresh;   // not cached: built below
+  for (uint32_t q = 0; q < count; ++q) {
+    const uint32_t n = n_[q], k = k_[q], npos = npos_[q];
+    const uint32_t* positions = positions_[q];
+    int rc = FNTRS_OK;
+    if (!is_pow2(n) || n > 65536) rc = fail(c, FNTRS_E_INVAL, "n=%u must be a power of two in [1, 65536]", n);
+    else if (k < 1 || k > n) rc = fail(c, FNTRS_E_INVAL, "k=%u must satisfy 1 <= k <= n=%u", k, n);
+    else if (!positions) rc = fail(c, FNTRS_E_INVAL, "null positions");
+    else if (npos < k) rc = fail(c, FNTRS_E_TOOFEW, "%u positions received, k=%u needed", npos, k);
+    for (uint32_t i = 0; !rc && i < k; ++i) {
+      if (positions[i] >= n) rc = fail(c, FNTRS_E_POSITIONS, "position %u at index %u is >= n=%u", positions[i], i, n);
+      else if (i && positions[i] <= positions[i - 1])
+        rc = fail(c, FNTRS_E_POSITIONS, "positions must be strictly ascending (index %u)", i);
     }
+    if (!rc && !is_pow2(k)) rc = fail(c, FNTRS_E_UNSUPPORTED, "decoding needs k a power of two, got %u", k);
+    if (rc) {
+      if (count > 1) c->err = "pattern " + std::to_string(q) + ": " + c->err;
+      give_back(q);
+      for (auto* L : fresh) delete L;
+      return rc;
+    }
+    const uint64_t key = hash_positions(n, k, positions);
+    auto same = [&](const fntrs_locator_t* L) {
+      return L->n == n && L->k == k && std::equal(L->positions.begin(), L->positions.end(), positions);
+    };
+    fntrs_locator_t* hit = nullptr;
+    auto range = c->cache.equal_range(key);
+    for (auto it = range.first; it != range.second && !hit; ++it)
+      if (same(it->second)) hit = it->second;
+    for (auto* L : fresh)
+      if (!hit && L->key == key && same(L)) hit = L;
+    if (!hit) {
+      hit = new fntrs_locator_t();
+      hit->n = n; hit->k = k; hit->logn = ilog2(n); hit->logk = ilog2(k);
+      hit->logm = std::max(hit->logk + 1, hit->logn - 1);   // low-product length M >= 2k, M >= n/2
+      hit->positions.assign(positions, positions + k);
+      hit->key = key;
+      fresh.push_back(hit);
+    }
+    hit->refs++;
+    hit->last_use = ++c->tick;
+    out[q] = hit;
   }
-  if (c->device == FNTRS_HOST_ONLY) return fail(c, FNTRS_E_DEVICE, "host-only context: arguments valid, no device");
-  DeviceGuard g(c->device);
-  auto* L = new fntrs_locator_t();
-  L->n = n; L->k = k; L->logn = ilog2(n); L->logk = ilog2(k);
-  L->logm = std::max(L->logk + 1, L->logn - 1);   // low-product length M >= 2k, M >= n/2
-  L->positions.assign(positions, positions + k);
-  L->key = key;
-  int rc = build_locator(c, L, stream);
-  if (rc) {
-    free_locator(c, L);
-    return rc;
+  if (!fresh.empty()) {
+    int rc = FNTRS_OK;
+    if (c->device == FNTRS_HOST_ONLY) rc = fail(c, FNTRS_E_DEVICE, "host-only context: arguments valid, no device");
+    else {
+      DeviceGuard g(c->device);
+      rc = build_locators(c, fresh, stream);
+    }
+    if (rc) {
+      for (uint32_t q = 0; q < count; ++q)
+        if (out[q] && std::find(fresh.begin(), fresh.end(), out[q]) == fresh.end()) out[q]->refs--;
+      for (uint32_t q = 0; q < count; ++q) out[q] = nullptr;
+      for (auto* L : fresh) delete L;   // not yet counted in c->used
+      return rc;
+    }
+    for (auto* L : fresh) c->cache.emplace(L->key, L);
   }
-  L->refs = 1;
-  L->last_use = ++c->tick;
-  c->cache.emplace(key, L);
-  *out = L;
   return FNTRS_OK;
 }
 
@@ -434,7 +557,17 @@ int fntrs_locator(fntrs_ctx* c, uint32_t n, uint32_t k, const uint32_t* position
   if (!c) return FNTRS_E_INVAL;
   std::lock_guard<std::mutex> lk(c->mu);
   c->err.clear();
-  return locator_acquire(c, n, k, positions, npos, (hipStream_t)stream, out);
+  if (!out) return fail(c, FNTRS_E_INVAL, "null out");
+  return locators_acquire(c, 1, &n, &k, &positions, &npos, (hipStream_t)stream, out);
+}
+
+int fntrs_locator_batch(fntrs_ctx* c, uint32_t count, const uint32_t* n, const uint32_t* k,
+                        const uint32_t* const* positions, const uint32_t* npos, void* stream,
+                        fntrs_locator_t** out) {
+  if (!c) return FNTRS_E_INVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->err.clear();
+  return locators_acquire(c, count, n, k, positions, npos, (hipStream_t)stream, out);
 }
 
 int fntrs_locator_release(fntrs_ctx* c, fntrs_locator_t* L) {

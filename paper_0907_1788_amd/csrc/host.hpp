@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -27,17 +28,31 @@ inline int ilog2(uint64_t x) { int r = 0; while ((1ull << r) < x) ++r; return r;
 
 }  // namespace fntrs
 
+// Device memory and completion event shared by the locators built together
+// in one batch; freed when the last of them is.
+struct LocSlab {
+  uint32_t* mem = nullptr;
+  hipEvent_t ready = nullptr;        // recorded after the build on its stream
+  LocSlab() = default;
+  LocSlab(const LocSlab&) = delete;
+  LocSlab& operator=(const LocSlab&) = delete;
+  ~LocSlab() {
+    if (ready) (void)hipEventDestroy(ready);
+    if (mem) (void)hipFree(mem);   // waits for work still using it
+  }
+};
+
 struct fntrs_locator_s {
   uint32_t n = 0, k = 0;
   int logn = 0, logk = 0;
   int logm = 0;                      // low-product length M = 2^logm >= 2k (k < n)
   std::vector<uint32_t> positions;   // the k positions used
   uint64_t key = 0;
-  uint32_t* mem = nullptr;           // one device allocation, views below
-  size_t bytes = 0;
+  std::shared_ptr<LocSlab> slab;     // holds the views below
+  size_t bytes = 0;                  // this locator's share of the slab
   uint32_t *pos = nullptr, *wfull = nullptr, *ridx = nullptr, *ahat_br = nullptr, *ahat_s = nullptr;
   uint32_t *A = nullptr, *w = nullptr, *ahat = nullptr;
-  hipEvent_t ready = nullptr;        // recorded after the build on its stream
+  hipEvent_t ready = nullptr;        // the slab's event
   int refs = 0;
   uint64_t last_use = 0;
 };
@@ -121,10 +136,11 @@ int validate_range(fntrs_ctx* c, const uint32_t* p, uint32_t batch, size_t strid
                    uint32_t lanes, hipStream_t s);
 // Evicts unreferenced cached locators until `need` more bytes fit the cap.
 bool make_room(fntrs_ctx* c, size_t need);
-// Finds the cached locator of the positions or builds it (fntrs_locator
-// without the lock).
-int locator_acquire(fntrs_ctx* c, uint32_t n, uint32_t k, const uint32_t* positions, uint32_t npos,
-                    hipStream_t stream, fntrs_locator_t** out);
+// Finds the cached locators of `count` patterns or builds the missing ones
+// together (fntrs_locator_batch without the lock); all or nothing.
+int locators_acquire(fntrs_ctx* c, uint32_t count, const uint32_t* n, const uint32_t* k,
+                     const uint32_t* const* positions, const uint32_t* npos, hipStream_t stream,
+                     fntrs_locator_t** out);
 hipError_t launch_copy(const uint32_t* src, size_t stride_src, uint32_t* dst, size_t stride_dst, uint32_t lanes,
                        uint32_t batch, hipStream_t s);
 

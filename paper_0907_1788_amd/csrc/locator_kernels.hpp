@@ -13,45 +13,112 @@ __device__ __forceinline__ uint32_t point_of(const uint32_t* tw, uint32_t z, int
   return tw[(z << (16 - logn)) & 0xFFFFu];
 }
 
-// Step 1, leaves of the product tree: group g multiplies the G linear factors
-// (x - x_i), i in [gG, gG+G), one factor at a time (schoolbook; G <= 64).
-__global__ void __launch_bounds__(64) k_loc_leaves(const uint32_t* __restrict__ pos, int logn, int G,
-                                                   const uint32_t* __restrict__ tw,
-                                                   uint32_t* __restrict__ out) {
+// One erasure pattern of a locator batch: where its positions come from,
+// where its state goes, its scratch, its sizes.
+struct LocDesc {
+  const uint32_t* zin;      // the k received positions (batch upload)
+  uint32_t* pos;            // state: positions, k words
+  uint32_t* wfull;          // state: decoder weight per position, n words
+  uint32_t* ridx;           // state: compact row per position, n words
+  uint32_t* ahat_br;        // state: FNT_M(A mod x^k) / M, bit-reversed, M words
+  uint32_t* ahat_s;         // state: the same in natural order, M words
+  uint32_t* A;              // state: A(x), k+1 coefficients
+  uint32_t* w;              // state: 1/A'(x_i), k words
+  uint32_t* ahat;           // state: FNT_M(A mod x^k), M words
+  uint32_t* t0;             // scratch: product-tree levels, k words each
+  uint32_t* t1;
+  uint32_t* spec;           // scratch: parked transforms, then A', k words
+  uint32_t* vals;           // scratch: A' at every n-th root, n words
+  uint32_t* poly;           // t0 or t1: where the tree leaves A mod x^k
+  uint32_t n, k, G;         // G points per leaf
+  int logn, logk, logm;
+};
+
+// Pattern owning index x of a batch stage: the last i with start[i] <= x.
+__device__ __forceinline__ uint32_t loc_find(const uint32_t* start, uint32_t count, uint32_t x) {
+  uint32_t lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (start[mid] <= x) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Stage 0, one thread per word: copy the positions into the state, clear the
+// weights (an erased position must read weight 0).  Nothing erased (k = n):
+// the decoder is the inverse FNT_n with factor n^-1, weight n^-1 and row z at
+// every position, and A = x^n - 1.
+__global__ void k_locb_prep(const LocDesc* __restrict__ D, const uint32_t* __restrict__ start, uint32_t count) {
+  const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= start[count]) return;
+  const uint32_t i = loc_find(start, count, x);
+  const LocDesc& d = D[i];
+  const uint32_t j = x - start[i];   // j < k + n
+  if (j < d.k) {
+    d.pos[j] = d.zin[j];
+    if (d.k == d.n) {
+      d.A[j] = j == 0 ? 65536u : 0u;
+      if (j == 0) d.A[d.k] = 1u;
+    }
+  } else {
+    const uint32_t z = j - d.k;
+    if (d.k == d.n) {
+      d.wfull[z] = 65537u - (65536u >> d.logn);
+      d.ridx[z] = z;
+    } else {
+      d.wfull[z] = 0u;
+    }
+  }
+}
+
+// Step 1, leaves of the product tree: workgroup g of a pattern multiplies the
+// G linear factors (x - x_i), i in [gG, gG+G), one factor at a time
+// (schoolbook; G <= 64).
+__global__ void __launch_bounds__(64) k_locb_leaves(const LocDesc* __restrict__ D, const uint32_t* __restrict__ start,
+                                                    uint32_t count, const uint32_t* __restrict__ tw) {
   __shared__ uint32_t c[2][66];
-  const int g = blockIdx.x;
+  const uint32_t i = loc_find(start, count, blockIdx.x);
+  const LocDesc& d = D[i];
+  const uint32_t g = blockIdx.x - start[i];
+  const int G = (int)d.G;
   for (int j = threadIdx.x; j < 66; j += blockDim.x) { c[0][j] = (j == 0); c[1][j] = 0; }
   __syncthreads();
   int cur = 0;
-  for (int i = 0; i < G; ++i) {
-    const uint32_t x = point_of(tw, pos[g * G + i], logn);
-    // (sum_j c_j x^j)(x - x_i): new_j = c_(j-1) - x_i c_j, degree i -> i+1
-    for (int j = threadIdx.x; j <= i + 1; j += blockDim.x) {
+  for (int q = 0; q < G; ++q) {
+    const uint32_t x = point_of(tw, d.zin[g * G + q], d.logn);
+    // (sum_j c_j x^j)(x - x_q): new_j = c_(j-1) - x_q c_j, degree q -> q+1
+    for (int j = threadIdx.x; j <= q + 1; j += blockDim.x) {
       const uint32_t lo = j ? c[cur][j - 1] : 0u;
       c[cur ^ 1][j] = fsub(lo, fmul(x, c[cur][j]));
     }
     __syncthreads();
     cur ^= 1;
   }
-  for (int j = threadIdx.x; j < G; j += blockDim.x) out[g * G + j] = c[cur][j];
+  for (int j = threadIdx.x; j < G; j += blockDim.x) d.t0[g * G + j] = c[cur][j];
 }
 
-// Step 1, one level of the product tree: pair p multiplies the monic degree-d
-// polynomials a = x^d + a_lo and b = x^d + b_lo:
+// Step 1, level `lev` of the product tree (degree d = G 2^lev): pair p of a
+// pattern multiplies the monic degree-d polynomials a = x^d + a_lo and
+// b = x^d + b_lo:
 //   a b = x^(2d) + x^d (a_lo + b_lo) + a_lo b_lo,
 // with a_lo b_lo (degree <= 2d-2) from three FNTs of size 2d (the
 // transform-based product of Sec. II-B).  LDS holds one size-2d transform;
-// the transform of a_lo is parked in `spec` (2d words per pair).
-__global__ void __launch_bounds__(1024) k_loc_mul_level(const uint32_t* __restrict__ in, int logd,
-                                                        const uint32_t* __restrict__ tw,
-                                                        uint32_t* __restrict__ spec,
-                                                        uint32_t* __restrict__ out) {
+// the transform of a_lo is parked in `spec` (2d words per pair).  Levels
+// alternate between the t0 and t1 buffers.
+__global__ void __launch_bounds__(1024) k_locb_level(const LocDesc* __restrict__ D, const uint32_t* __restrict__ start,
+                                                     uint32_t count, int logd, int lev,
+                                                     const uint32_t* __restrict__ tw) {
   extern __shared__ uint32_t lds[];
+  const uint32_t i = loc_find(start, count, blockIdx.x);
+  const LocDesc& dd = D[i];
+  const uint32_t p = blockIdx.x - start[i];
   const uint32_t d = 1u << logd, d2 = 2u * d;
-  const uint32_t p = blockIdx.x;
+  const uint32_t* in = (lev & 1) ? dd.t1 : dd.t0;
+  uint32_t* outp = (lev & 1) ? dd.t0 : dd.t1;
   const uint32_t* a = in + (uint64_t)(2 * p) * d;
   const uint32_t* b = a + d;
-  uint32_t* sp = spec + (uint64_t)p * d2;
+  uint32_t* sp = dd.spec + (uint64_t)p * d2;
   const uint32_t inv2d = 65537u - (65536u >> logd >> 1);   // (2d)^-1 = -2^16/(2d)
   for (uint32_t j = threadIdx.x; j < d2; j += blockDim.x) lds[j] = j < d ? a[j] : 0u;
   __syncthreads();
@@ -65,7 +132,7 @@ __global__ void __launch_bounds__(1024) k_loc_mul_level(const uint32_t* __restri
   for (uint32_t j = threadIdx.x; j < d2; j += blockDim.x) lds[j] = fmul(lds[j], sp[j]);
   __syncthreads();
   lds_dit<1>(lds, 1, logd + 1, true, tw);
-  uint32_t* o = out + (uint64_t)p * d2;
+  uint32_t* o = outp + (uint64_t)p * d2;
   for (uint32_t j = threadIdx.x; j < d2; j += blockDim.x) {
     uint32_t v = fmul(lds[j], inv2d);
     if (j >= d) v = fadd(v, fadd(a[j - d], b[j - d]));
@@ -73,25 +140,42 @@ __global__ void __launch_bounds__(1024) k_loc_mul_level(const uint32_t* __restri
   }
 }
 
-// Step 2: A'(x) from the monic degree-k A (low coefficients a_0..a_(k-1)):
-// coefficient j of A' is (j+1) a_(j+1), with a_k = 1.
-__global__ void k_loc_derivative(const uint32_t* __restrict__ a, uint32_t k, uint32_t* __restrict__ da) {
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= k) return;
-  const uint32_t next = (j + 1 < k) ? a[j + 1] : 1u;
-  da[j] = fmul(next, (j + 1) % 65537u);
+// Step 2, one thread per coefficient: A (monic, degree k) into the state and
+// A'(x): coefficient j of A' is (j+1) a_(j+1), with a_k = 1.
+__global__ void k_locb_derivative(const LocDesc* __restrict__ D, const uint32_t* __restrict__ start, uint32_t count) {
+  const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= start[count]) return;
+  const uint32_t i = loc_find(start, count, x);
+  const LocDesc& d = D[i];
+  const uint32_t j = x - start[i];
+  const uint32_t next = (j + 1 < d.k) ? d.poly[j + 1] : 1u;
+  d.A[j] = d.poly[j];
+  if (j == 0) d.A[d.k] = 1u;
+  d.spec[j] = fmul(next, (j + 1) % 65537u);
 }
 
-// Evaluate c (K = 2^logK coefficients) at every N-th root of unity, N = K*cosets:
-// value at r_N^(t + cosets*m) is FNT_K of (c_j r_N^(t j))_j at m (Sec. II-A,
-// polynomial view of the FNT).  One workgroup per coset t.
-__global__ void __launch_bounds__(1024) k_loc_eval(const uint32_t* __restrict__ c, int logK, int logN,
-                                                   const uint32_t* __restrict__ tw,
-                                                   uint32_t* __restrict__ vals) {
+// Evaluate a polynomial with K = 2^logK coefficients at every N-th root of
+// unity, N = K * cosets: the value at r_N^(t + cosets m) is FNT_K of
+// (c_j r_N^(t j))_j at m (Sec. II-A, polynomial view of the FNT).  One
+// workgroup per coset t.  Every pattern of the launch has k = K.  A
+// pattern's first n/k workgroups evaluate A' at the n-th roots (step 3);
+// the next M/k evaluate A mod x^k at the M-th roots (the transform of A used
+// by the low product of step 6).
+__global__ void __launch_bounds__(1024) k_locb_eval(const LocDesc* __restrict__ D, const uint32_t* __restrict__ start,
+                                                    uint32_t count, int logK, const uint32_t* __restrict__ tw) {
   extern __shared__ uint32_t lds[];
-  const uint32_t K = 1u << logK, N = 1u << logN;
-  const uint32_t t = blockIdx.x;
+  const uint32_t i = loc_find(start, count, blockIdx.x);
+  const LocDesc& d = D[i];
+  uint32_t t = blockIdx.x - start[i];
+  const uint32_t K = 1u << logK;
+  const uint32_t ncos = d.n >> logK;
+  const bool deriv = t < ncos;
+  if (!deriv) t -= ncos;
+  const int logN = deriv ? d.logn : d.logm;
+  const uint32_t N = 1u << logN;
   const uint32_t cosets = N >> logK;
+  const uint32_t* c = deriv ? d.spec : d.poly;
+  uint32_t* vals = deriv ? d.vals : d.ahat;
   for (uint32_t j = threadIdx.x; j < K; j += blockDim.x) {
     uint32_t v = c[j];
     if (t) v = fmul(v, tw[((t * j) & (N - 1)) << (16 - logN)]);
@@ -102,50 +186,38 @@ __global__ void __launch_bounds__(1024) k_loc_eval(const uint32_t* __restrict__ 
   for (uint32_t m = threadIdx.x; m < K; m += blockDim.x) vals[t + cosets * m] = lds[m];
 }
 
-// Step 3 and the weights of step 4: w_i = 1/A'(x_i), and the decoder weight
-// -w_i x_i^(-1) (sign and index shift of step 5 folded in) scattered to the
-// per-position tables: wfull[z_i] = -w_i x_i^(-1), ridx[z_i] = i.  wfull
-// must be zero beforehand so that erased positions read as 0.
-__global__ void k_loc_weights(const uint32_t* __restrict__ pos, const uint32_t* __restrict__ vals,
-                              uint32_t k, int logn, const uint32_t* __restrict__ tw,
-                              uint32_t* __restrict__ w, uint32_t* __restrict__ wfull,
-                              uint32_t* __restrict__ ridx) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= k) return;
-  const uint32_t z = pos[i];
-  const uint32_t wi = finv(vals[z]);
-  const uint32_t xinv = tw[(65536u - ((z << (16 - logn)) & 0xFFFFu)) & 0xFFFFu];
-  w[i] = wi;
-  wfull[z] = fsub(0u, fmul(wi, xinv));
-  ridx[z] = i;
+// Step 3 and the weights of step 4, one thread per received position:
+// w_i = 1/A'(x_i), and the decoder weight -w_i x_i^(-1) (sign and index
+// shift of step 5 folded in) scattered to the per-position tables:
+// wfull[z_i] = -w_i x_i^(-1), ridx[z_i] = i.
+__global__ void k_locb_weights(const LocDesc* __restrict__ D, const uint32_t* __restrict__ start, uint32_t count,
+                               const uint32_t* __restrict__ tw) {
+  const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= start[count]) return;
+  const uint32_t i = loc_find(start, count, x);
+  const LocDesc& d = D[i];
+  const uint32_t q = x - start[i];
+  const uint32_t z = d.pos[q];
+  const uint32_t wi = finv(d.vals[z]);
+  const uint32_t xinv = tw[(65536u - ((z << (16 - d.logn)) & 0xFFFFu)) & 0xFFFFu];
+  d.w[q] = wi;
+  d.wfull[z] = fsub(0u, fmul(wi, xinv));
+  d.ridx[z] = q;
 }
 
 // Â for step 6 with the inverse-transform factor M^-1 folded in (M = 2^logm
 // is the cyclic length of the low product), in bit-reversed and in natural
-// order.
-__global__ void k_loc_ahat(const uint32_t* __restrict__ ahat, int logm, uint32_t* __restrict__ ahat_br,
-                           uint32_t* __restrict__ ahat_s) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (1u << logm)) return;
-  const uint32_t inv = 65537u - (65536u >> logm);           // (2^logm)^-1 = -2^(16-logm)
-  const uint32_t v = fmul(ahat[i], inv);
-  ahat_br[bitrev(i, logm)] = v;
-  ahat_s[i] = v;
-}
-
-// Decoder tables when nothing is erased (k = n): weight n^-1, row z.
-__global__ void k_loc_identity(uint32_t* __restrict__ wfull, uint32_t* __restrict__ ridx, uint32_t n,
-                               uint32_t ninv) {
-  const uint32_t z = blockIdx.x * blockDim.x + threadIdx.x;
-  if (z >= n) return;
-  wfull[z] = ninv;
-  ridx[z] = z;
-}
-
-// Fill k words with v.
-__global__ void k_loc_fill(uint32_t* __restrict__ w, uint32_t k, uint32_t v) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < k) w[i] = v;
+// order; one thread per value.
+__global__ void k_locb_ahat(const LocDesc* __restrict__ D, const uint32_t* __restrict__ start, uint32_t count) {
+  const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= start[count]) return;
+  const uint32_t i = loc_find(start, count, x);
+  const LocDesc& d = D[i];
+  const uint32_t q = x - start[i];
+  const uint32_t inv = 65537u - (65536u >> d.logm);   // (2^logm)^-1 = -2^(16-logm)
+  const uint32_t v = fmul(d.ahat[q], inv);
+  d.ahat_br[bitrev(q, d.logm)] = v;
+  d.ahat_s[q] = v;
 }
 
 // n = 1 (and k = 1): encoding and decoding both copy the single symbol.

@@ -448,7 +448,8 @@ int fntrs_autotune(fntrs_ctx* c, uint32_t op, uint32_t n, uint32_t k, uint32_t l
     // a coset pattern: every (n/k)-th position
     std::vector<uint32_t> z(k);
     for (uint32_t i = 0; i < k; ++i) z[i] = i * (n / k);
-    if (int rc = locator_acquire(c, n, k, z.data(), k, s, &loc)) return rc;
+    const uint32_t* zp = z.data();
+    if (int rc = locators_acquire(c, 1, &n, &k, &zp, &k, s, &loc)) return rc;
     HIP_TRY(c, hipStreamWaitEvent(s, loc->ready, 0));
   }
   struct Release {

@@ -70,6 +70,8 @@ SIGNATURES = {
     "fntrs_last_error": (ctypes.c_char_p, [_vp]),
     "fntrs_encode": (_int, [_vp, _u32, _u32, _u32, _vp, _sz, _sz, _vp, _sz, _sz, _u32, _u32, _vp]),
     "fntrs_locator": (_int, [_vp, _u32, _u32, _pu32, _u32, _vp, ctypes.POINTER(_vp)]),
+    "fntrs_locator_batch": (_int, [_vp, _u32, _pu32, _pu32, ctypes.POINTER(_pu32), _pu32, _vp,
+                                   ctypes.POINTER(_vp)]),
     "fntrs_locator_release": (_int, [_vp, _vp]),
     "fntrs_locator_export": (_int, [_vp, _vp, _pu32, _pu32, _pu32]),
     "fntrs_decode": (_int, [_vp, _vp, _u32, _u32, _vp, _sz, _sz, _vp, _sz, _sz, _u32, _vp]),
@@ -147,6 +149,20 @@ def fntrs_locator(ctx, n, k, positions, stream=0):
     out = _vp()
     rc = lib().fntrs_locator(ctx, n, k, pos.ctypes.data_as(_pu32), pos.size, stream, ctypes.byref(out))
     return rc, out.value
+
+
+def fntrs_locator_batch(ctx, ns, ks, positions, stream=0):
+    """Returns (rc, [handles]); positions: one host sequence per pattern."""
+    count = len(ns)
+    arrs = [np.ascontiguousarray(np.asarray(z, dtype=np.uint32)) for z in positions]
+    n_arr = np.ascontiguousarray(np.asarray(ns, dtype=np.uint32))
+    k_arr = np.ascontiguousarray(np.asarray(ks, dtype=np.uint32))
+    npos = np.ascontiguousarray(np.asarray([a.size for a in arrs], dtype=np.uint32))
+    ptrs = (_pu32 * max(1, count))(*[a.ctypes.data_as(_pu32) for a in arrs])
+    out = (_vp * max(1, count))()
+    rc = lib().fntrs_locator_batch(ctx, count, n_arr.ctypes.data_as(_pu32), k_arr.ctypes.data_as(_pu32), ptrs,
+                                   npos.ctypes.data_as(_pu32), stream, out)
+    return rc, [out[i] for i in range(count)]
 
 
 def fntrs_locator_release(ctx, loc):
@@ -291,6 +307,15 @@ class Context:
         rc, h = fntrs_locator(self.handle, n, k, positions, _stream_handle(stream))
         _check(self.handle, rc)
         return Locator(self, h, n, k, positions)
+
+    def locators(self, patterns, stream=None):
+        """Locators of many patterns [(n, k, positions), ...] built together."""
+        ns = [p[0] for p in patterns]
+        ks = [p[1] for p in patterns]
+        zs = [p[2] for p in patterns]
+        rc, hs = fntrs_locator_batch(self.handle, ns, ks, zs, _stream_handle(stream))
+        _check(self.handle, rc)
+        return [Locator(self, h, n, k, z) for h, n, k, z in zip(hs, ns, ks, zs)]
 
     def decode(self, loc: Locator, recv, dst, flags: int = FNTRS_RECV_COMPACT, stream=None) -> None:
         """dst [b, k, lanes] <- source recovered from recv ([b, k, lanes] or, FULL, [b, n, lanes])."""

@@ -188,3 +188,15 @@ def test_graph_and_tuner_validation(hctx):
     rc, t = fntrs.fntrs_get_config(hctx, 1, 13)
     assert rc == fntrs.FNTRS_OK and t.tile_lanes >= 1 and t.threads >= 64 and 1 <= t.radix_log2 <= 5
     assert fntrs.fntrs_get_config(hctx, 0, 16)[0] == fntrs.FNTRS_E_INVAL
+
+
+def test_locator_batch_validation(hctx):
+    rc, hs = fntrs.fntrs_locator_batch(hctx, [16, 8], [4, 2], [[1, 2, 3, 9], [0, 5]])
+    assert rc == fntrs.FNTRS_E_DEVICE and hs == [None, None]
+    rc, hs = fntrs.fntrs_locator_batch(hctx, [16, 8], [4, 2], [[1, 2, 3, 9], [5, 0]])
+    assert rc == fntrs.FNTRS_E_POSITIONS and "pattern 1" in fntrs.fntrs_last_error(hctx)
+    assert fntrs.fntrs_locator_batch(hctx, [16], [4], [[1, 2]])[0] == fntrs.FNTRS_E_TOOFEW
+    assert fntrs.fntrs_locator_batch(hctx, [16], [3], [[1, 2, 4]])[0] == fntrs.FNTRS_E_UNSUPPORTED
+    assert fntrs.fntrs_locator_batch(hctx, [], [], [])[0] == fntrs.FNTRS_OK
+    L = fntrs.lib()
+    assert L.fntrs_locator_batch(hctx, 1, None, None, None, None, None, None) == fntrs.FNTRS_E_INVAL

@@ -219,3 +219,38 @@ def test_autotune_keeps_results_exact(ctx):
     check_against_singles(ctx, cws)
     for cw in cws:
         cw.loc.release()
+
+
+def test_locator_batch_state_matches_oracle(ctx):
+    """Patterns built together (mixed n and k, nothing erased, k = 1, repeats) equal the oracle's locators."""
+    specs = [(16, 4, 1), (64, 64, 0), (128, 1, 2), (256, 64, 3), (512, 256, 4), (1024, 128, 5), (2048, 1024, 6),
+             (256, 64, 3), (4096, 2048, 7), (8192, 4096, 8), (65536, 16384, 9), (64, 32, 10), (2, 1, 11)]
+    pats = []
+    for n, k, seed in specs:
+        z = np.arange(n, dtype=np.uint32) if k == n else synth.received_positions(900 + seed, n, k)
+        pats.append((n, k, z))
+    say("locator batch", len(pats))
+    locs = ctx.locators(pats)
+    assert locs[3].handle == locs[7].handle           # the repeated pattern is built once
+    for (n, k, z), loc in zip(pats, locs):
+        A, w, ahat = loc.export()
+        ref = codec.locator(n, z, with_w=(k <= 4096 and k < n))
+        assert np.array_equal(A.astype(np.int64), ref["A"]), (n, k)
+        if k < n:
+            if "w" in ref:
+                assert np.array_equal(w.astype(np.int64), ref["w"]), (n, k)
+            assert np.array_equal(ahat.astype(np.int64), ref["Ahat"]), (n, k)
+    # cache hits on a second batch, and decoding through batch-built locators
+    again = ctx.locators(pats[:4])
+    assert [a.handle for a in again] == [b.handle for b in locs[:4]]
+    for (n, k, z), loc in zip(pats, locs):
+        lanes = 3
+        src = synth.source(1000 + n + k, 1, k, lanes)
+        e = torch.empty((1, n, lanes), dtype=torch.int32, device="cuda")
+        ctx.encode(dev(src), e, n)
+        d = torch.empty((1, k, lanes), dtype=torch.int32, device="cuda")
+        ctx.decode(loc, e, d, fntrs.FNTRS_RECV_FULL)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(d), src.astype(np.int64)), (n, k)
+    for x in locs + again:
+        x.release()
