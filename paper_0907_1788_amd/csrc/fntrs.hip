@@ -487,11 +487,15 @@ void fntrs_destroy(fntrs_ctx* c) {
   (void)hipDeviceSynchronize();
   for (auto& kv : c->cache) free_locator(c, kv.second);
   c->cache.clear();
-  for (int b = 0; b < fntrs_ctx::kSide; ++b) {
-    if (c->side[b]) (void)hipStreamDestroy(c->side[b]);
-    if (c->join[b]) (void)hipEventDestroy(c->join[b]);
-  }
-  if (c->fork) (void)hipEventDestroy(c->fork);
+  auto drop = [](fntrs_ctx::SideSet& ss) {
+    for (int b = 0; b < fntrs_ctx::kSide; ++b) {
+      if (ss.st[b]) (void)hipStreamDestroy(ss.st[b]);
+      if (ss.join[b]) (void)hipEventDestroy(ss.join[b]);
+    }
+    if (ss.fork) (void)hipEventDestroy(ss.fork);
+  };
+  for (auto& kv : c->sides) drop(kv.second);
+  drop(c->capture_side);
   if (c->tw) (void)hipFree(c->tw);
   delete c;
 }

@@ -70,11 +70,16 @@ struct fntrs_ctx {
   std::string err;
   std::unordered_multimap<uint64_t, fntrs_locator_t*> cache;
   uint64_t tick = 0;
-  // batched path: side streams (default priority) for independent classes,
-  // and the occupancy of each table kernel
+  // batched path: per caller stream, side streams (default priority) that
+  // run a batch's size classes concurrently; one more set for captures
   static constexpr int kSide = 3;
-  hipStream_t side[kSide] = {};
-  hipEvent_t fork = nullptr, join[kSide] = {};
+  struct SideSet {
+    hipStream_t st[kSide] = {};
+    hipEvent_t fork = nullptr, join[kSide] = {};
+  };
+  std::unordered_map<hipStream_t, SideSet> sides;
+  SideSet capture_side;
+  // occupancy of each table kernel
   std::map<std::tuple<int, int, int, int, int>, int> occ;
 };
 

@@ -230,25 +230,26 @@ int make_plan(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, Plan& P) {
   return FNTRS_OK;
 }
 
-int ensure_side_streams(fntrs_ctx* c) {
-  if (c->fork) return FNTRS_OK;
+int init_side_set(fntrs_ctx* c, fntrs_ctx::SideSet& ss) {
+  if (ss.fork) return FNTRS_OK;
   for (int b = 0; b < fntrs_ctx::kSide; ++b) {
-    HIP_TRY(c, hipStreamCreateWithFlags(&c->side[b], hipStreamNonBlocking));
-    HIP_TRY(c, hipEventCreateWithFlags(&c->join[b], hipEventDisableTiming));
+    HIP_TRY(c, hipStreamCreateWithFlags(&ss.st[b], hipStreamNonBlocking));
+    HIP_TRY(c, hipEventCreateWithFlags(&ss.join[b], hipEventDisableTiming));
   }
-  HIP_TRY(c, hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+  HIP_TRY(c, hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming));
   return FNTRS_OK;
 }
 
-// Enqueues the plan: the classes spread over `s` and the side streams (each
-// stream takes the next class while the one with the least work so far),
-// the single jobs in order on `s`; everything is joined back into `s`.
-int run_plan(fntrs_ctx* c, const Plan& P, const uint8_t* dblob, uint32_t* scratch, hipStream_t s) {
+// Enqueues the plan: the classes spread over `s` and the side streams of
+// `side` (the next class goes to the stream with the least work so far), the
+// single jobs in order on `s`; everything is joined back into `s`.
+int run_plan(fntrs_ctx* c, const Plan& P, const uint8_t* dblob, uint32_t* scratch, hipStream_t s,
+             fntrs_ctx::SideSet& side) {
   const int streams = std::min<int>(1 + fntrs_ctx::kSide, (int)P.launches.size());
   if (streams > 1) {
-    if (int rc = ensure_side_streams(c)) return rc;
-    HIP_TRY(c, hipEventRecord(c->fork, s));
-    for (int b = 0; b < streams - 1; ++b) HIP_TRY(c, hipStreamWaitEvent(c->side[b], c->fork, 0));
+    if (int rc = init_side_set(c, side)) return rc;
+    HIP_TRY(c, hipEventRecord(side.fork, s));
+    for (int b = 0; b < streams - 1; ++b) HIP_TRY(c, hipStreamWaitEvent(side.st[b], side.fork, 0));
   }
   std::vector<uint64_t> load(streams > 0 ? streams : 1, 0);
   for (const ClassLaunch& cl : P.launches) {
@@ -256,7 +257,7 @@ int run_plan(fntrs_ctx* c, const Plan& P, const uint8_t* dblob, uint32_t* scratc
     for (int q = 1; q < streams; ++q)
       if (load[q] < load[b]) b = q;
     load[b] += cl.work;
-    hipStream_t st = b == 0 ? s : c->side[b - 1];
+    hipStream_t st = b == 0 ? s : side.st[b - 1];
     if (cl.op == 0) {
       JobTable<EncodeArgs> t{reinterpret_cast<const EncodeArgs*>(dblob + cl.jobs_off),
                              reinterpret_cast<const uint32_t*>(dblob + cl.start_off), cl.njobs, cl.total};
@@ -278,8 +279,8 @@ int run_plan(fntrs_ctx* c, const Plan& P, const uint8_t* dblob, uint32_t* scratc
     }
   }
   for (int b = 0; b < streams - 1; ++b) {
-    HIP_TRY(c, hipEventRecord(c->join[b], c->side[b]));
-    HIP_TRY(c, hipStreamWaitEvent(s, c->join[b], 0));
+    HIP_TRY(c, hipEventRecord(side.join[b], side.st[b]));
+    HIP_TRY(c, hipStreamWaitEvent(s, side.join[b], 0));
   }
   return FNTRS_OK;
 }
@@ -319,7 +320,7 @@ int fntrs_submit(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, void* stre
     // pageable source: the runtime stages it before returning
     if (!P.blob.empty()) HIP_TRY(c, hipMemcpyAsync(mem, P.blob.data(), P.blob.size(), hipMemcpyHostToDevice, s));
   }
-  const int rc = run_plan(c, P, mem, reinterpret_cast<uint32_t*>(mem + blob), s);
+  const int rc = run_plan(c, P, mem, reinterpret_cast<uint32_t*>(mem + blob), s, c->sides[s]);
   if (mem) (void)hipFreeAsync(mem, s);
   return rc;
 }
@@ -359,7 +360,6 @@ int fntrs_graph_create(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, fntr
     if (!P.blob.empty() && hipMemcpy(G->mem, P.blob.data(), P.blob.size(), hipMemcpyHostToDevice) != hipSuccess)
       return cleanup(fail(c, FNTRS_E_DEVICE, "copying the job tables failed"));
   }
-  if (int rc = ensure_side_streams(c)) return cleanup(rc);
   hipStream_t cs = nullptr;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
     return cleanup(fail(c, FNTRS_E_DEVICE, "capture stream creation failed"));
@@ -367,7 +367,7 @@ int fntrs_graph_create(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, fntr
   if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
     rc = fail(c, FNTRS_E_DEVICE, "hipStreamBeginCapture failed");
   } else {
-    rc = run_plan(c, P, G->mem, reinterpret_cast<uint32_t*>(G->mem + blob), cs);
+    rc = run_plan(c, P, G->mem, reinterpret_cast<uint32_t*>(G->mem + blob), cs, c->capture_side);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(cs, &graph);
     G->graph = graph;
