@@ -188,7 +188,8 @@ typedef struct fntrs_job {
  * must stay valid until the stream reaches the batch.  Every job is checked
  * as its single call would be; in addition no job's output may overlap any
  * other job's input or output.  A working buffer for the job tables (and the
- * scratch of n = 65536 jobs, which run one after another) is allocated
+ * scratch of four-step jobs (2^14 points or more), which run one after
+ * another) is allocated
  * stream-ordered and freed after the batch.  Errors: FNTRS_E_INVAL (with the
  * job index in fntrs_last_error), FNTRS_E_NOMEM, FNTRS_E_DEVICE. */
 int fntrs_submit(fntrs_ctx* ctx, const fntrs_job* jobs, uint32_t njobs, void* stream);
@@ -212,10 +213,11 @@ int fntrs_graph_destroy(fntrs_ctx* ctx, fntrs_graph_t* graph);
 
 /* Kernel configuration of one transform size. */
 typedef struct fntrs_tuning {
-  uint32_t tile_lanes;   /* lanes per workgroup tile */
-  uint32_t threads;      /* threads per workgroup */
-  uint32_t radix_log2;   /* largest radix of the LDS passes, as log2 */
-  float ms;              /* autotune: mean time of the chosen kernel per launch */
+  uint32_t tile_lanes;        /* lanes per workgroup tile */
+  uint32_t threads;           /* threads per workgroup */
+  uint32_t lanes_per_thread;  /* lanes one thread carries through a pass */
+  uint32_t radix_log2;        /* largest radix of the LDS passes, as log2 */
+  float ms;                   /* autotune: mean time of the chosen kernel per launch */
 } fntrs_tuning;
 
 /* Autotuner: times every compiled configuration of the size class of

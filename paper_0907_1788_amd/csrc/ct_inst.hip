@@ -10,63 +10,63 @@
 namespace fntrs {
 namespace {
 
-template <int L, int T, int NT>
+template <int L, int T, int NT, int V>
 hipError_t enc_one(const EncodeArgs& a, uint32_t blocks, hipStream_t s) {
-  constexpr size_t lds = ct::Geo<L, T, NT>::LDS_BYTES;
+  constexpr size_t lds = ct::Geo<L, T, NT, V>::LDS_BYTES;
   static_assert(lds <= 163840, "tile exceeds LDS");
-  (void)hipFuncSetAttribute((const void*)ct::k_enc<L, T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  (void)hipFuncSetAttribute((const void*)ct::k_enc<L, T, NT, V>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
-  hipLaunchKernelGGL((ct::k_enc<L, T, NT>), dim3(blocks), dim3(NT), lds, s, a);
+  hipLaunchKernelGGL((ct::k_enc<L, T, NT, V>), dim3(blocks), dim3(NT), lds, s, a);
   return hipGetLastError();
 }
 
-template <int L, int D, int T, int NT>
+template <int L, int D, int T, int NT, int V>
 hipError_t dec_one(const DecodeArgs& a, uint32_t blocks, hipStream_t s) {
-  constexpr size_t lds = ct::Geo<L, T, NT>::LDS_BYTES;
+  constexpr size_t lds = ct::Geo<L, T, NT, V>::LDS_BYTES;
   static_assert(lds <= 163840, "tile exceeds LDS");
-  (void)hipFuncSetAttribute((const void*)ct::k_dec<L, D, T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  (void)hipFuncSetAttribute((const void*)ct::k_dec<L, D, T, NT, V>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
-  hipLaunchKernelGGL((ct::k_dec<L, D, T, NT>), dim3(blocks), dim3(NT), lds, s, a);
+  hipLaunchKernelGGL((ct::k_dec<L, D, T, NT, V>), dim3(blocks), dim3(NT), lds, s, a);
   return hipGetLastError();
 }
 
-template <int L, int T, int NT>
+template <int L, int T, int NT, int V>
 hipError_t dec_t(int D, const DecodeArgs& a, uint32_t blocks, hipStream_t s) {
-  if (D == -1) return dec_one<L, -1, T, NT>(a, blocks, s);
-  if (D == 0) return dec_one<L, 0, T, NT>(a, blocks, s);
+  if (D == -1) return dec_one<L, -1, T, NT, V>(a, blocks, s);
+  if (D == 0) return dec_one<L, 0, T, NT, V>(a, blocks, s);
   if constexpr (L > 1) {
-    if (D == 1) return dec_one<L, 1, T, NT>(a, blocks, s);
+    if (D == 1) return dec_one<L, 1, T, NT, V>(a, blocks, s);
   }
   return hipErrorInvalidValue;
 }
 
-template <int L, int T, int NT>
+template <int L, int T, int NT, int V>
 hipError_t enc_tab_one(const JobTable<EncodeArgs>& t, const uint32_t* tw, const uint32_t* twi, uint32_t grid,
                        hipStream_t s) {
-  constexpr size_t lds = ct::Geo<L, T, NT>::LDS_BYTES;
-  (void)hipFuncSetAttribute((const void*)ct::k_enc_tab<L, T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  constexpr size_t lds = ct::Geo<L, T, NT, V>::LDS_BYTES;
+  (void)hipFuncSetAttribute((const void*)ct::k_enc_tab<L, T, NT, V>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
-  hipLaunchKernelGGL((ct::k_enc_tab<L, T, NT>), dim3(grid), dim3(NT), lds, s, t, tw, twi);
+  hipLaunchKernelGGL((ct::k_enc_tab<L, T, NT, V>), dim3(grid), dim3(NT), lds, s, t, tw, twi);
   return hipGetLastError();
 }
 
-template <int L, int D, int T, int NT>
+template <int L, int D, int T, int NT, int V>
 hipError_t dec_tab_one(const JobTable<DecodeArgs>& t, const uint32_t* tw, const uint32_t* twi, uint32_t grid,
                        hipStream_t s) {
-  constexpr size_t lds = ct::Geo<L, T, NT>::LDS_BYTES;
-  (void)hipFuncSetAttribute((const void*)ct::k_dec_tab<L, D, T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  constexpr size_t lds = ct::Geo<L, T, NT, V>::LDS_BYTES;
+  (void)hipFuncSetAttribute((const void*)ct::k_dec_tab<L, D, T, NT, V>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
-  hipLaunchKernelGGL((ct::k_dec_tab<L, D, T, NT>), dim3(grid), dim3(NT), lds, s, t, tw, twi);
+  hipLaunchKernelGGL((ct::k_dec_tab<L, D, T, NT, V>), dim3(grid), dim3(NT), lds, s, t, tw, twi);
   return hipGetLastError();
 }
 
-template <int L, int T, int NT>
+template <int L, int T, int NT, int V>
 hipError_t dec_tab_t(int D, const JobTable<DecodeArgs>& t, const uint32_t* tw, const uint32_t* twi, uint32_t grid,
                      hipStream_t s) {
-  if (D == -1) return dec_tab_one<L, -1, T, NT>(t, tw, twi, grid, s);
-  if (D == 0) return dec_tab_one<L, 0, T, NT>(t, tw, twi, grid, s);
+  if (D == -1) return dec_tab_one<L, -1, T, NT, V>(t, tw, twi, grid, s);
+  if (D == 0) return dec_tab_one<L, 0, T, NT, V>(t, tw, twi, grid, s);
   if constexpr (L > 1) {
-    if (D == 1) return dec_tab_one<L, 1, T, NT>(t, tw, twi, grid, s);
+    if (D == 1) return dec_tab_one<L, 1, T, NT, V>(t, tw, twi, grid, s);
   }
   return hipErrorInvalidValue;
 }
@@ -79,14 +79,14 @@ int occupancy(K kernel, int NT, size_t lds) {
   return nb;
 }
 
-template <int L, int T, int NT>
+template <int L, int T, int NT, int V>
 int occ_t(int op, int D) {
-  constexpr size_t lds = ct::Geo<L, T, NT>::LDS_BYTES;
-  if (op == 0) return occupancy(ct::k_enc_tab<L, T, NT>, NT, lds);
-  if (D == -1) return occupancy(ct::k_dec_tab<L, -1, T, NT>, NT, lds);
-  if (D == 0) return occupancy(ct::k_dec_tab<L, 0, T, NT>, NT, lds);
+  constexpr size_t lds = ct::Geo<L, T, NT, V>::LDS_BYTES;
+  if (op == 0) return occupancy(ct::k_enc_tab<L, T, NT, V>, NT, lds);
+  if (D == -1) return occupancy(ct::k_dec_tab<L, -1, T, NT, V>, NT, lds);
+  if (D == 0) return occupancy(ct::k_dec_tab<L, 0, T, NT, V>, NT, lds);
   if constexpr (L > 1) {
-    if (D == 1) return occupancy(ct::k_dec_tab<L, 1, T, NT>, NT, lds);
+    if (D == 1) return occupancy(ct::k_dec_tab<L, 1, T, NT, V>, NT, lds);
   }
   return 0;
 }
@@ -96,8 +96,8 @@ constexpr CtVariants kVar = ct_variants(FNTRS_L);
 template <int I>
 hipError_t enc_pick(CtCfg c, const EncodeArgs& a, uint32_t blocks, hipStream_t s) {
   if constexpr (I < 4 && kVar.enc[I < 4 ? I : 0].T != 0) {
-    if (c.T == kVar.enc[I].T && c.NT == kVar.enc[I].NT)
-      return enc_one<FNTRS_L, kVar.enc[I].T, kVar.enc[I].NT>(a, blocks, s);
+    if (c.T == kVar.enc[I].T && c.NT == kVar.enc[I].NT && c.V == kVar.enc[I].V)
+      return enc_one<FNTRS_L, kVar.enc[I].T, kVar.enc[I].NT, kVar.enc[I].V>(a, blocks, s);
     return enc_pick<I + 1>(c, a, blocks, s);
   } else {
     return hipErrorInvalidValue;
@@ -107,8 +107,8 @@ hipError_t enc_pick(CtCfg c, const EncodeArgs& a, uint32_t blocks, hipStream_t s
 template <int I>
 hipError_t dec_pick(CtCfg c, int D, const DecodeArgs& a, uint32_t blocks, hipStream_t s) {
   if constexpr (I < 4 && kVar.dec[I < 4 ? I : 0].T != 0) {
-    if (c.T == kVar.dec[I].T && c.NT == kVar.dec[I].NT)
-      return dec_t<FNTRS_L, kVar.dec[I].T, kVar.dec[I].NT>(D, a, blocks, s);
+    if (c.T == kVar.dec[I].T && c.NT == kVar.dec[I].NT && c.V == kVar.dec[I].V)
+      return dec_t<FNTRS_L, kVar.dec[I].T, kVar.dec[I].NT, kVar.dec[I].V>(D, a, blocks, s);
     return dec_pick<I + 1>(c, D, a, blocks, s);
   } else {
     return hipErrorInvalidValue;
@@ -119,8 +119,8 @@ template <int I>
 hipError_t enc_tab_pick(CtCfg c, const JobTable<EncodeArgs>& t, const uint32_t* tw, const uint32_t* twi,
                         uint32_t grid, hipStream_t s) {
   if constexpr (I < 4 && kVar.enc[I < 4 ? I : 0].T != 0) {
-    if (c.T == kVar.enc[I].T && c.NT == kVar.enc[I].NT)
-      return enc_tab_one<FNTRS_L, kVar.enc[I].T, kVar.enc[I].NT>(t, tw, twi, grid, s);
+    if (c.T == kVar.enc[I].T && c.NT == kVar.enc[I].NT && c.V == kVar.enc[I].V)
+      return enc_tab_one<FNTRS_L, kVar.enc[I].T, kVar.enc[I].NT, kVar.enc[I].V>(t, tw, twi, grid, s);
     return enc_tab_pick<I + 1>(c, t, tw, twi, grid, s);
   } else {
     return hipErrorInvalidValue;
@@ -131,8 +131,8 @@ template <int I>
 hipError_t dec_tab_pick(CtCfg c, int D, const JobTable<DecodeArgs>& t, const uint32_t* tw, const uint32_t* twi,
                         uint32_t grid, hipStream_t s) {
   if constexpr (I < 4 && kVar.dec[I < 4 ? I : 0].T != 0) {
-    if (c.T == kVar.dec[I].T && c.NT == kVar.dec[I].NT)
-      return dec_tab_t<FNTRS_L, kVar.dec[I].T, kVar.dec[I].NT>(D, t, tw, twi, grid, s);
+    if (c.T == kVar.dec[I].T && c.NT == kVar.dec[I].NT && c.V == kVar.dec[I].V)
+      return dec_tab_t<FNTRS_L, kVar.dec[I].T, kVar.dec[I].NT, kVar.dec[I].V>(D, t, tw, twi, grid, s);
     return dec_tab_pick<I + 1>(c, D, t, tw, twi, grid, s);
   } else {
     return hipErrorInvalidValue;
@@ -144,10 +144,10 @@ int occ_pick(CtCfg c, int op, int D) {
   if constexpr (I < 4) {
     constexpr CtCfg e = kVar.enc[I], d = kVar.dec[I];
     if constexpr (e.T != 0) {
-      if (op == 0 && c.T == e.T && c.NT == e.NT) return occ_t<FNTRS_L, e.T, e.NT>(0, D);
+      if (op == 0 && c.T == e.T && c.NT == e.NT && c.V == e.V) return occ_t<FNTRS_L, e.T, e.NT, e.V>(0, D);
     }
     if constexpr (d.T != 0) {
-      if (op == 1 && c.T == d.T && c.NT == d.NT) return occ_t<FNTRS_L, d.T, d.NT>(1, D);
+      if (op == 1 && c.T == d.T && c.NT == d.NT && c.V == d.V) return occ_t<FNTRS_L, d.T, d.NT, d.V>(1, D);
     }
     return occ_pick<I + 1>(c, op, D);
   } else {

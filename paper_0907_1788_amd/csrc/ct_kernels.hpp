@@ -33,13 +33,15 @@ __host__ __device__ constexpr int geo_bm(int L, int G, int V, int NT) {
   return b;
 }
 
-// Tile geometry: T lanes per tile, V lanes per thread, G = T/V lane groups,
-// NT threads, radix bound BM, LDS bytes of the padded tile.
-template <int L, int T_, int NT_>
+// Tile geometry: T lanes per tile, V lanes per thread (VV, or 4 when the
+// tile allows), G = T/V lane groups, NT threads, radix bound BM, LDS bytes of
+// the padded tile.
+template <int L, int T_, int NT_, int VV = 0>
 struct Geo {
   static constexpr int T = T_;
   static constexpr int NT = NT_;
-  static constexpr int V = T >= 4 ? 4 : T;
+  static constexpr int V = VV ? VV : (T >= 4 ? 4 : T);   // lanes per thread (vector width)
+  static_assert(T % V == 0, "the tile must hold whole vectors");
   static constexpr int G = T / V;
   static constexpr int BM = geo_bm(L, G, V, NT);
   static constexpr uint32_t TILE_BYTES = lds_vectors(1u << L, G) * V * 4;
@@ -169,9 +171,9 @@ struct EncStore {
 // Encoder, Sec. II-B: e_i = s(r_n^i).  Output row t + (n/K) m is output m of
 // FNT_K of (s_j r_n^(t j))_j (r_n^(n/K) = r_K), one work item per
 // (coset t, lane tile, block), coset fastest.
-template <int LK, int TT, int NT, class TW>
+template <int LK, int TT, int NT, int VV, class TW>
 __device__ __forceinline__ void enc_item(const EncodeArgs& a, uint32_t item, uint32_t* lds, const TW& tws) {
-  using Gm = Geo<LK, TT, NT>;
+  using Gm = Geo<LK, TT, NT, VV>;
   constexpr int V = Gm::V, G = Gm::G, T = Gm::T;
   const uint32_t t = item % a.cosets;
   item /= a.cosets;
@@ -186,13 +188,13 @@ __device__ __forceinline__ void enc_item(const EncodeArgs& a, uint32_t item, uin
   dit<LK, Gm::BM, V, G, false>(tws, l0, lm, sm, sl);
 }
 
-template <int LK, int TT, int NT>
+template <int LK, int TT, int NT, int VV>
 __global__ void __launch_bounds__(NT) k_enc(EncodeArgs a) {
-  using Gm = Geo<LK, TT, NT>;
+  using Gm = Geo<LK, TT, NT, VV>;
   using TW = typename Gm::TwType;
   extern __shared__ uint32_t lds[];
   const TW tws = make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
-  enc_item<LK, TT, NT>(a, xcd_remap(blockIdx.x, gridDim.x), lds, tws);
+  enc_item<LK, TT, NT, VV>(a, xcd_remap(blockIdx.x, gridDim.x), lds, tws);
 }
 
 // Job of work item w: the last j with start[j] <= w (uniform per workgroup).
@@ -208,16 +210,16 @@ __device__ __forceinline__ uint32_t find_job(const uint32_t* start, uint32_t njo
 
 // Batched encoder: a persistent grid walks the work items of every job of
 // one transform size; the LDS twiddle tables are filled once per workgroup.
-template <int LK, int TT, int NT>
+template <int LK, int TT, int NT, int VV>
 __global__ void __launch_bounds__(NT) k_enc_tab(JobTable<EncodeArgs> t, const uint32_t* tw, const uint32_t* twi) {
-  using Gm = Geo<LK, TT, NT>;
+  using Gm = Geo<LK, TT, NT, VV>;
   using TW = typename Gm::TwType;
   extern __shared__ uint32_t lds[];
   const TW tws = make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, tw, twi);
   for (uint32_t w = xcd_remap(blockIdx.x, gridDim.x); w < t.total; w += gridDim.x) {
     const uint32_t j = find_job(t.start, t.njobs, w);
     const EncodeArgs a = t.jobs[j];
-    enc_item<LK, TT, NT>(a, w - t.start[j], lds, tws);
+    enc_item<LK, TT, NT, VV>(a, w - t.start[j], lds, tws);
     __syncthreads();   // the next item overwrites the LDS tile
   }
 }
@@ -321,9 +323,9 @@ struct SourceStore {
 // No permutation passes through LDS between the three transforms.
 // D = -1 is the erasure-free case k = n (Sec. II-B): the weights are n^-1
 // and the inverse FNT_n alone is the decoder.
-template <int LN, int D, int TT, int NT, class TW>
+template <int LN, int D, int TT, int NT, int VV, class TW>
 __device__ __forceinline__ void dec_item(const DecodeArgs& a, uint32_t item, uint32_t* lds, const TW& tws) {
-  using Gm = Geo<LN, TT, NT>;
+  using Gm = Geo<LN, TT, NT, VV>;
   constexpr int V = Gm::V, G = Gm::G, T = Gm::T;
   const uint32_t tile = item % a.tiles;
   const uint64_t blk = item / a.tiles;
@@ -346,27 +348,27 @@ __device__ __forceinline__ void dec_item(const DecodeArgs& a, uint32_t item, uin
   }
 }
 
-template <int LN, int D, int TT, int NT>
+template <int LN, int D, int TT, int NT, int VV>
 __global__ void __launch_bounds__(NT) k_dec(DecodeArgs a) {
-  using Gm = Geo<LN, TT, NT>;
+  using Gm = Geo<LN, TT, NT, VV>;
   using TW = typename Gm::TwType;
   extern __shared__ uint32_t lds[];
   const TW tws = make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
-  dec_item<LN, D, TT, NT>(a, xcd_remap(blockIdx.x, gridDim.x), lds, tws);
+  dec_item<LN, D, TT, NT, VV>(a, xcd_remap(blockIdx.x, gridDim.x), lds, tws);
 }
 
 // Batched decoder: as k_enc_tab, for decode jobs of one code length n and
 // one product length M = n / 2^D, each with its own locator.
-template <int LN, int D, int TT, int NT>
+template <int LN, int D, int TT, int NT, int VV>
 __global__ void __launch_bounds__(NT) k_dec_tab(JobTable<DecodeArgs> t, const uint32_t* tw, const uint32_t* twi) {
-  using Gm = Geo<LN, TT, NT>;
+  using Gm = Geo<LN, TT, NT, VV>;
   using TW = typename Gm::TwType;
   extern __shared__ uint32_t lds[];
   const TW tws = make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, tw, twi);
   for (uint32_t w = xcd_remap(blockIdx.x, gridDim.x); w < t.total; w += gridDim.x) {
     const uint32_t j = find_job(t.start, t.njobs, w);
     const DecodeArgs a = t.jobs[j];
-    dec_item<LN, D, TT, NT>(a, w - t.start[j], lds, tws);
+    dec_item<LN, D, TT, NT, VV>(a, w - t.start[j], lds, tws);
     __syncthreads();
   }
 }

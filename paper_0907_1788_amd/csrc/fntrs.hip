@@ -406,7 +406,8 @@ int locators_acquire(fntrs_ctx* c, uint32_t count, const uint32_t* n_, const uin
 }
 
 // Default kernel configuration per transform size, then the FNTRS_TILES
-// override "e12=8x512,d13=4x1024,...".
+// override "e12=8x512,d13=4x512v2,..." (tile lanes x threads, optional
+// lanes per thread).
 void set_default_configs(fntrs_ctx* c) {
   for (int L = 1; L <= 15; ++L) {
     c->enc_cfg[L] = ct_variants(L).enc[0];
@@ -420,11 +421,11 @@ void set_default_configs(fntrs_ctx* c) {
       size_t end = spec.find(',', pos);
       if (end == std::string::npos) end = spec.size();
       const std::string item = spec.substr(pos, end - pos);
-      int L = 0, T = 0, NT = 512;
+      int L = 0, T = 0, NT = 512, V = 0;
       char kind = 0;
-      if (sscanf(item.c_str(), "%c%d=%dx%d", &kind, &L, &T, &NT) >= 3 && L >= 1 && L <= 15) {
-        if (kind == 'e') c->enc_cfg[L] = CtCfg{T, NT};
-        if (kind == 'd') c->dec_cfg[L] = CtCfg{T, NT};
+      if (sscanf(item.c_str(), "%c%d=%dx%dv%d", &kind, &L, &T, &NT, &V) >= 3 && L >= 1 && L <= 15) {
+        if (kind == 'e') c->enc_cfg[L] = CtCfg{T, NT, V};
+        if (kind == 'd') c->dec_cfg[L] = CtCfg{T, NT, V};
       }
       pos = end + 1;
     }
@@ -527,13 +528,14 @@ int fntrs_encode(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uin
   a.n = n; a.k = k; a.lanes = lanes;
   a.logn = ilog2(n);
   a.logK = std::max(1, ilog2(k));        // transform size K: smallest power of two >= k, at least 2
-  if (a.logK == 16) {
-    // K = n = 65536: four-step transform through a scratch buffer
+  if (a.logK >= kFourStepMinLog) {
+    // K >= 2^14: one FNT_n of the zero-padded source as four-step passes over
+    // 32-lane tiles, through a scratch buffer
     FourStepArgs f{};
     f.in = src; f.ld_in = ld_src; f.stride_in = stride_src;
     f.out = dst; f.ld_out = ld_dst; f.stride_out = stride_dst;
     f.tw = c->tw; f.twi = c->twi;
-    f.n = n; f.k = k; f.M = n; f.lanes = lanes; f.logn = 16; f.logm = 16;
+    f.n = n; f.k = k; f.M = n; f.lanes = lanes; f.logn = a.logn; f.logm = a.logn;
     f.tiles = (lanes + kFourStepTile - 1) / kFourStepTile;
     const uint64_t lds = (uint64_t)f.tiles * kFourStepTile;
     f.vec = aligned16(src, ld_src, stride_src) && aligned16(dst, ld_dst, stride_dst);
@@ -622,13 +624,13 @@ int fntrs_decode(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, uint32_
     HIP_TRY(c, launch_copy(recv, stride_recv, dst, stride_dst, lanes, batch, s));
     return FNTRS_OK;
   }
-  if (L->logn == 16) {
+  if (L->logn >= kFourStepMinLog) {
     FourStepArgs f{};
     f.in = recv; f.ld_in = ld_recv; f.stride_in = stride_recv;
     f.out = dst; f.ld_out = ld_dst; f.stride_out = stride_dst;
     f.tw = c->tw; f.twi = c->twi; f.wfull = L->wfull; f.ridx = L->ridx; f.ahat = L->ahat_s;
-    f.n = n; f.k = k; f.lanes = lanes; f.logn = 16;
-    f.logm = (k == n) ? 16 : L->logm;
+    f.n = n; f.k = k; f.lanes = lanes; f.logn = L->logn;
+    f.logm = (k == n) ? L->logn : L->logm;
     f.M = 1u << f.logm;
     f.full = full ? 1u : 0u;
     f.tiles = (lanes + kFourStepTile - 1) / kFourStepTile;

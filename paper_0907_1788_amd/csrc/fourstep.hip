@@ -1,4 +1,4 @@
-// Launches of the four-step kernels (fourstep.hpp) for n = 65536.
+// Launches of the four-step kernels (fourstep.hpp) for n = 2^14 .. 2^16.
 #include "fourstep.hpp"
 #include "fourstep_launch.hpp"
 
@@ -19,13 +19,50 @@ hipError_t launch(K kernel, size_t lds, uint32_t blocks, const FourStepArgs& a, 
     if (e_ != hipSuccess) return e_;    \
   } while (0)
 
+template <int LB>
+hipError_t dec4(const FourStepArgs& a, uint32_t blocks, hipStream_t s) {
+  return launch(fs::k4_dec4<LB>, fs::Geo<LB>::LDS_BYTES, blocks, a, s);
+}
+
+hipError_t dec4_any(int LB, const FourStepArgs& a, uint32_t blocks, hipStream_t s) {
+  switch (LB) {
+    case 5: return dec4<5>(a, blocks, s);
+    case 6: return dec4<6>(a, blocks, s);
+    case 7: return dec4<7>(a, blocks, s);
+    case 8: return dec4<8>(a, blocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int LB1, int LB2>
+hipError_t dec2(const FourStepArgs& a, uint32_t blocks, hipStream_t s) {
+  return launch(fs::k4_dec2<LB1, LB2>, fs::Geo<LB1>::LDS_BYTES, blocks, a, s);
+}
+
+// K2 for pass-B size 2^LB1 (n / 256) and FNT_M pass-A size 2^LB2 (M / 256).
+hipError_t dec2_any(int LB1, int LB2, const FourStepArgs& a, uint32_t blocks, hipStream_t s) {
+  if (LB1 == 6 && LB2 == 5) return dec2<6, 5>(a, blocks, s);
+  if (LB1 == 6 && LB2 == 6) return dec2<6, 6>(a, blocks, s);
+  if (LB1 == 7 && LB2 == 6) return dec2<7, 6>(a, blocks, s);
+  if (LB1 == 7 && LB2 == 7) return dec2<7, 7>(a, blocks, s);
+  if (LB1 == 8 && LB2 == 7) return dec2<8, 7>(a, blocks, s);
+  if (LB1 == 8 && LB2 == 8) return dec2<8, 8>(a, blocks, s);
+  return hipErrorInvalidValue;
+}
+
 }  // namespace
 
-// Decoder for n = 65536 (and k = n) through two scratch buffers of n and M rows.
+// Decoder for n = 2^14 .. 2^16 (and k = n) through two scratch buffers of n
+// and M rows.  n = N1 * 256: K1 runs the size-256 passes A of the inverse
+// FNT_n, K2 its size-N1 passes B and the size-M/256 passes A of FNT_M, K3 the
+// size-256 passes B of FNT_M, the product with the locator's transform and
+// the size-256 passes A of the inverse FNT_M, K4 its size-M/256 passes B.
 hipError_t fourstep_decode(const FourStepArgs& base, uint32_t batch, uint32_t* sa, uint32_t* sb, uint64_t lds_,
                            hipStream_t s) {
   const uint32_t tiles = base.tiles;
   const uint64_t ld = lds_;
+  if (base.logn < 14 || base.logn > 16) return hipErrorInvalidValue;
+  const int LB1 = base.logn - 8;
   FourStepArgs a = base;
   // K1: recv -> sa (n rows)
   a.out = sa; a.ld_out = ld; a.stride_out = ld * a.n;
@@ -37,17 +74,15 @@ hipError_t fourstep_decode(const FourStepArgs& base, uint32_t batch, uint32_t* s
     b.in = sa; b.ld_in = ld; b.stride_in = ld * a.n;
     b.subs = 256;
     b.M = base.n;
-    return launch(fs::k4_dec4<8>, fs::Geo<8>::LDS_BYTES, tiles * b.subs * batch, b, s);
+    return dec4_any(LB1, b, tiles * b.subs * batch, s);
   }
+  const int LB2 = base.logm - 8;
   // K2: sa -> sb (M rows)
   FourStepArgs b = base;
   b.in = sa; b.ld_in = ld; b.stride_in = ld * a.n;
   b.out = sb; b.ld_out = ld; b.stride_out = ld * base.M;
   b.subs = 256;
-  if (base.logm == 16)
-    FNTRS_TRY(launch(fs::k4_dec2<8, 8>, fs::Geo<8>::LDS_BYTES, tiles * b.subs * batch, b, s));
-  else
-    FNTRS_TRY(launch(fs::k4_dec2<8, 7>, fs::Geo<8>::LDS_BYTES, tiles * b.subs * batch, b, s));
+  FNTRS_TRY(dec2_any(LB1, LB2, b, tiles * b.subs * batch, s));
   // K3: sb -> sa (M rows)
   FourStepArgs c = base;
   c.in = sb; c.ld_in = ld; c.stride_in = ld * base.M;
@@ -58,20 +93,25 @@ hipError_t fourstep_decode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   FourStepArgs d = base;
   d.in = sa; d.ld_in = ld; d.stride_in = ld * a.n;
   d.subs = 256;
-  if (base.logm == 16) return launch(fs::k4_dec4<8>, fs::Geo<8>::LDS_BYTES, tiles * d.subs * batch, d, s);
-  return launch(fs::k4_dec4<7>, fs::Geo<7>::LDS_BYTES, tiles * d.subs * batch, d, s);
+  return dec4_any(LB2, d, tiles * d.subs * batch, s);
 }
 
-// Encoder for K = n = 65536 through one scratch buffer of n rows.
+// Encoder as one FNT_n of the zero-padded source, n = 2^14 .. 2^16, through
+// one scratch buffer of n rows.
 hipError_t fourstep_encode(const FourStepArgs& base, uint32_t batch, uint32_t* sa, uint64_t lds_, hipStream_t s) {
+  if (base.logn < 14 || base.logn > 16) return hipErrorInvalidValue;
   FourStepArgs a = base;
   a.out = sa; a.ld_out = lds_; a.stride_out = lds_ * a.n;
-  a.subs = 256;
+  a.subs = a.n >> 8;
   FNTRS_TRY(launch(fs::k4_enc1, fs::Geo<8>::LDS_BYTES, base.tiles * a.subs * batch, a, s));
   FourStepArgs b = base;
   b.in = sa; b.ld_in = lds_; b.stride_in = lds_ * a.n;
   b.subs = 256;
-  return launch(fs::k4_enc2, fs::Geo<8>::LDS_BYTES, base.tiles * b.subs * batch, b, s);
+  switch (base.logn) {
+    case 14: return launch(fs::k4_enc2<6>, fs::Geo<6>::LDS_BYTES, base.tiles * b.subs * batch, b, s);
+    case 15: return launch(fs::k4_enc2<7>, fs::Geo<7>::LDS_BYTES, base.tiles * b.subs * batch, b, s);
+    default: return launch(fs::k4_enc2<8>, fs::Geo<8>::LDS_BYTES, base.tiles * b.subs * batch, b, s);
+  }
 }
 
 }  // namespace fntrs

@@ -1,4 +1,5 @@
-// Transforms longer than one tile (n = 65536): four-step FNT passes.
+// Transforms longer than a lane-wide tile (n = 2^14 .. 2^16): four-step FNT
+// passes over 32-lane tiles.
 //
 // A transform of size N = N1*N2 (Sec. II-A, divide and conquer) is split as
 //   X[m2 + N2 m1] = sum_i1 w_N1^(i1 m1) w_N^(i1 m2) sum_i2 x[i1 + N1 i2] w_N2^(i2 m2)
@@ -282,16 +283,17 @@ __global__ void __launch_bounds__(kNT) k4_dec4(FourStepArgs a) {
   ct::dit<LB, Gm::BM, 4, Gm::G, true>(tws, l0, ll, sl, sg);
 }
 
-// Encoder pass A for K = n = 65536: rows i1 + 256 i2 (zero from k on),
-// forward, times w_n^(i1 m2) -> scratch row i1*256 + m2.
+// Encoder as one FNT_n of the zero-padded source, n = N1 * 256.  Pass A:
+// rows i1 + N1 i2 (zero from k on), forward, times w_n^(i1 m2) -> scratch
+// row i1*256 + m2.
 __global__ void __launch_bounds__(kNT) k4_enc1(FourStepArgs a) {
   using Gm = Geo<8>;
   extern __shared__ uint32_t lds[];
   const Work wk = work_of(a);
-  const uint32_t i1 = wk.sub;
+  const uint32_t i1 = wk.sub, N1 = a.n >> 8;
   auto rowf = [&](uint32_t i2, uint32_t& w) -> uint64_t {
     w = 0;
-    const uint32_t j = i1 + 256u * i2;
+    const uint32_t j = i1 + N1 * i2;
     return j < a.k ? (uint64_t)j : ~0ull;
   };
   auto destf = [&](uint32_t m2, uint32_t& w) -> uint64_t {
@@ -308,9 +310,11 @@ __global__ void __launch_bounds__(kNT) k4_enc1(FourStepArgs a) {
   ct::dit<8, Gm::BM, 4, Gm::G, false>(tws, l0, lm, sm, sl);
 }
 
-// Encoder pass B: scratch rows i1*256 + m2 (m2 = sub), forward -> rows m2 + 256 m1.
+// Encoder pass B (size N1 = 2^LB): scratch rows i1*256 + m2 (m2 = sub),
+// forward -> rows m2 + 256 m1.
+template <int LB>
 __global__ void __launch_bounds__(kNT) k4_enc2(FourStepArgs a) {
-  using Gm = Geo<8>;
+  using Gm = Geo<LB>;
   extern __shared__ uint32_t lds[];
   const Work wk = work_of(a);
   const uint32_t m2 = wk.sub;
@@ -322,14 +326,14 @@ __global__ void __launch_bounds__(kNT) k4_enc2(FourStepArgs a) {
     w = 0;
     return (uint64_t)m2 + 256u * m1;
   };
-  GLoad<8, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.lane0, a.ld_in, wk.lane0, a.lanes, a.vec != 0, rowf};
+  GLoad<LB, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.lane0, a.ld_in, wk.lane0, a.lanes, a.vec != 0, rowf};
   ct::LdsLoad<4, Gm::G> lm{lds};
   ct::LdsStore<4, Gm::G, false> sm{lds};
-  GStore<8, false, decltype(destf)> sl{a.out + wk.blk * a.stride_out + wk.lane0, a.ld_out, wk.lane0, a.lanes,
+  GStore<LB, false, decltype(destf)> sl{a.out + wk.blk * a.stride_out + wk.lane0, a.ld_out, wk.lane0, a.lanes,
                                        a.vec != 0, destf};
   using TW = typename Gm::TwType;
   const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
-  ct::dit<8, Gm::BM, 4, Gm::G, false>(tws, l0, lm, sm, sl);
+  ct::dit<LB, Gm::BM, 4, Gm::G, false>(tws, l0, lm, sm, sl);
 }
 
 }  // namespace fs

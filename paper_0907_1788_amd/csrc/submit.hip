@@ -8,7 +8,8 @@
 // Each class becomes one persistent launch of a table kernel (k_enc_tab /
 // k_dec_tab) whose workgroups walk the work items of all of the class's jobs;
 // the classes run on up to four streams at once.  Jobs the table kernels do
-// not cover (n = 65536 four-step transforms, n = 1 copies) run one by one.
+// not cover (four-step transforms of 2^14 points or more, n = 1 copies) run
+// one by one.
 #include <chrono>
 
 #include "ct_kernels.hpp"
@@ -91,14 +92,14 @@ int make_plan(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, Plan& P) {
         s.kind = 0; s.src = J.in; s.dst = J.out; s.stride_src = J.stride_in; s.stride_dst = J.stride_out;
         s.lanes = J.lanes; s.batch = J.batch;
         P.singles.push_back(s);
-      } else if (logK == 16) {
+      } else if (logK >= kFourStepMinLog) {
         SingleJob s;
         s.kind = 1;
         FourStepArgs& f = s.f;
         f.in = J.in; f.ld_in = J.ld_in; f.stride_in = J.stride_in;
         f.out = J.out; f.ld_out = J.ld_out; f.stride_out = J.stride_out;
         f.tw = c->tw; f.twi = c->twi;
-        f.n = J.n; f.k = J.k; f.M = J.n; f.lanes = J.lanes; f.logn = 16; f.logm = 16;
+        f.n = J.n; f.k = J.k; f.M = J.n; f.lanes = J.lanes; f.logn = ilog2(J.n); f.logm = f.logn;
         f.tiles = (J.lanes + kFourStepTile - 1) / kFourStepTile;
         f.vec = aligned16(J.in, J.ld_in, J.stride_in) && aligned16(J.out, J.ld_out, J.stride_out);
         s.batch = J.batch;
@@ -132,15 +133,15 @@ int make_plan(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, Plan& P) {
         s.kind = 0; s.src = J.in; s.dst = J.out; s.stride_src = J.stride_in; s.stride_dst = J.stride_out;
         s.lanes = J.lanes; s.batch = J.batch;
         P.singles.push_back(s);
-      } else if (L->logn == 16) {
+      } else if (L->logn >= kFourStepMinLog) {
         SingleJob s;
         s.kind = 2;
         FourStepArgs& f = s.f;
         f.in = J.in; f.ld_in = J.ld_in; f.stride_in = J.stride_in;
         f.out = J.out; f.ld_out = J.ld_out; f.stride_out = J.stride_out;
         f.tw = c->tw; f.twi = c->twi; f.wfull = L->wfull; f.ridx = L->ridx; f.ahat = L->ahat_s;
-        f.n = L->n; f.k = L->k; f.lanes = J.lanes; f.logn = 16;
-        f.logm = (L->k == L->n) ? 16 : L->logm;
+        f.n = L->n; f.k = L->k; f.lanes = J.lanes; f.logn = L->logn;
+        f.logm = (L->k == L->n) ? L->logn : L->logm;
         f.M = 1u << f.logm;
         f.full = full ? 1u : 0u;
         f.tiles = (J.lanes + kFourStepTile - 1) / kFourStepTile;
@@ -283,6 +284,14 @@ int run_plan(fntrs_ctx* c, const Plan& P, const uint8_t* dblob, uint32_t* scratc
     HIP_TRY(c, hipStreamWaitEvent(s, side.join[b], 0));
   }
   return FNTRS_OK;
+}
+
+void fill_tuning(int L, CtCfg k, fntrs_tuning* t) {
+  const int V = k.V ? k.V : (k.T >= 4 ? 4 : k.T);
+  t->tile_lanes = (uint32_t)k.T;
+  t->threads = (uint32_t)k.NT;
+  t->lanes_per_thread = (uint32_t)V;
+  t->radix_log2 = (uint32_t)ct::geo_bm(L, k.T / V, V, k.NT);
 }
 
 }  // namespace
@@ -508,10 +517,7 @@ int fntrs_autotune(fntrs_ctx* c, uint32_t op, uint32_t n, uint32_t k, uint32_t l
   if (op == FNTRS_OP_ENCODE) c->enc_cfg[L] = best_cfg;
   else c->dec_cfg[L] = best_cfg;
   if (chosen) {
-    const int V = best_cfg.T >= 4 ? 4 : best_cfg.T;
-    chosen->tile_lanes = (uint32_t)best_cfg.T;
-    chosen->threads = (uint32_t)best_cfg.NT;
-    chosen->radix_log2 = (uint32_t)ct::geo_bm(L, best_cfg.T / V, V, best_cfg.NT);
+    fill_tuning(L, best_cfg, chosen);
     chosen->ms = best;
   }
   return FNTRS_OK;
@@ -522,11 +528,7 @@ int fntrs_get_config(fntrs_ctx* c, uint32_t op, uint32_t log2_size, fntrs_tuning
   std::lock_guard<std::mutex> lk(c->mu);
   if (op > FNTRS_OP_DECODE || log2_size < 1 || log2_size > 15)
     return fail(c, FNTRS_E_INVAL, "op %u / size 2^%u has no table configuration", op, log2_size);
-  const CtCfg k = op == FNTRS_OP_ENCODE ? c->enc_cfg[log2_size] : c->dec_cfg[log2_size];
-  const int V = k.T >= 4 ? 4 : k.T;
-  cfg->tile_lanes = (uint32_t)k.T;
-  cfg->threads = (uint32_t)k.NT;
-  cfg->radix_log2 = (uint32_t)ct::geo_bm((int)log2_size, k.T / V, V, k.NT);
+  fill_tuning((int)log2_size, op == FNTRS_OP_ENCODE ? c->enc_cfg[log2_size] : c->dec_cfg[log2_size], cfg);
   cfg->ms = 0.f;
   return FNTRS_OK;
 }

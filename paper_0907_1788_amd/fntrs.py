@@ -59,7 +59,8 @@ class fntrs_job(ctypes.Structure):
 
 class fntrs_tuning(ctypes.Structure):
     """struct fntrs_tuning of include/fntrs.h."""
-    _fields_ = [("tile_lanes", _u32), ("threads", _u32), ("radix_log2", _u32), ("ms", ctypes.c_float)]
+    _fields_ = [("tile_lanes", _u32), ("threads", _u32), ("lanes_per_thread", _u32), ("radix_log2", _u32),
+                ("ms", ctypes.c_float)]
 
 
 _pjob = ctypes.POINTER(fntrs_job)
@@ -361,12 +362,14 @@ class Context:
         """Times every configuration of the size class and keeps the fastest; returns it as a dict."""
         rc, t = fntrs_autotune(self.handle, op, n, k, lanes, batch, reps, _stream_handle(stream))
         _check(self.handle, rc)
-        return {"tile_lanes": t.tile_lanes, "threads": t.threads, "radix_log2": t.radix_log2, "ms": t.ms}
+        return {"tile_lanes": t.tile_lanes, "threads": t.threads, "lanes_per_thread": t.lanes_per_thread,
+                "radix_log2": t.radix_log2, "ms": t.ms}
 
     def config(self, op: int, log2_size: int):
         rc, t = fntrs_get_config(self.handle, op, log2_size)
         _check(self.handle, rc)
-        return {"tile_lanes": t.tile_lanes, "threads": t.threads, "radix_log2": t.radix_log2}
+        return {"tile_lanes": t.tile_lanes, "threads": t.threads, "lanes_per_thread": t.lanes_per_thread,
+                "radix_log2": t.radix_log2}
 
 
 class Graph:

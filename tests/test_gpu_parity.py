@@ -67,6 +67,8 @@ ENC_CASES = [
     (64, 5, 17, 2), (128, 64, 100, 1), (256, 256, 9, 1), (512, 256, 512, 1), (512, 100, 65, 3),
     (1024, 1, 31, 1), (2048, 1024, 70, 1), (4096, 4096, 5, 1), (8192, 4096, 16, 1),
     (8192, 8192, 3, 1), (16384, 2048, 4, 1), (32768, 32768, 2, 1),
+    # four-step FNT_n of the zero-padded source (K >= 2^14)
+    (16384, 16384, 5, 1), (32768, 9000, 37, 1), (32768, 16384, 3, 2), (65536, 20000, 2, 1),
 ]
 
 
@@ -137,6 +139,9 @@ DEC_CASES = [
     (1, 1, 3, 2, "all"), (2, 2, 5, 1, "all"), (8192, 8192, 3, 1, "all"), (4096, 64, 9, 1, "random"),
     (32768, 1024, 2, 1, "random"), (16384, 16384, 2, 1, "all"),
     (16384, 4096, 6, 2, "first"), (32768, 16384, 2, 1, "random"), (32768, 32768, 2, 1, "all"),
+    # four-step decoders at n = 2^14, 2^15: every product length, ragged lanes
+    (16384, 8192, 37, 1, "random"), (16384, 2048, 5, 2, "random"), (32768, 8192, 33, 1, "first"),
+    (32768, 4096, 3, 1, "random"), (16384, 16384, 9, 1, "all"),
 ]
 
 
@@ -223,7 +228,8 @@ def test_validation_with_device(ctx):
 # every lane-tile width instantiated for a size, forced through FNTRS_TILES
 TILE_CASES = [("e12=4x512", 4096, 4096, 40), ("e12=8x1024", 8192, 4096, 24), ("e11=16x512", 2048, 1024, 33),
               ("d12=8x512", 4096, 2048, 40), ("d13=4x1024", 8192, 4096, 9), ("d13=2x512", 8192, 4096, 6),
-              ("d13=2x512", 8192, 2048, 6), ("d13=4x1024", 8192, 8192, 5)]
+              ("d13=2x512", 8192, 2048, 6), ("d13=4x1024", 8192, 8192, 5), ("d13=4x512v2", 8192, 4096, 10),
+              ("d13=4x512v2", 8192, 2048, 7), ("d13=4x512v2", 8192, 8192, 5)]
 
 
 @pytest.mark.parametrize("spec,n,k,lanes", TILE_CASES)
@@ -241,6 +247,28 @@ def test_tile_variants(spec, n, k, lanes, monkeypatch):
         loc = c.locator(n, k, z)
         got = gpu_decode(c, loc, out[:, z, :])
         assert np.array_equal(got, src.astype(np.int64))
+        loc.release()
+    finally:
+        torch.cuda.synchronize()
+        c.close()
+
+
+def test_extreme_inputs_two_lanes_per_thread(monkeypatch):
+    """Largest residues through the radix-32 decoder with two lanes per thread."""
+    say("extreme inputs d13=4x512v2")
+    monkeypatch.setenv("FNTRS_TILES", "d13=4x512v2")
+    c = fntrs.Context(0)
+    try:
+        n, k = 8192, 4096
+        src = np.full((1, k, 8), 65536, dtype=np.uint32)
+        src[0, 1::2, ::2] = 0
+        e = np.stack([codec.encode(src[0], n)])
+        z = pattern("random", n, k, 31)
+        loc = c.locator(n, k, z)
+        assert np.array_equal(gpu_decode(c, loc, e[:, z, :]), src.astype(np.int64))
+        top = np.full((1, k, 4), 65536, dtype=np.uint32)
+        ref = codec.decode_lagrange(n, z, top[0])
+        assert np.array_equal(gpu_decode(c, loc, top)[0], ref)
         loc.release()
     finally:
         torch.cuda.synchronize()
