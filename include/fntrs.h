@@ -187,9 +187,9 @@ typedef struct fntrs_job {
  * The job array is read before the call returns; data buffers and locators
  * must stay valid until the stream reaches the batch.  Every job is checked
  * as its single call would be; in addition no job's output may overlap any
- * other job's input or output.  A working buffer for the job tables (and the
- * scratch of four-step jobs (2^14 points or more), which run one after
- * another) is allocated
+ * other job's input or output.  A working buffer for the job tables and the
+ * scratch of four-step jobs (2^14 points or more; the ones given to one
+ * stream run one after another over that stream's slice) is allocated
  * stream-ordered and freed after the batch.  Errors: FNTRS_E_INVAL (with the
  * job index in fntrs_last_error), FNTRS_E_NOMEM, FNTRS_E_DEVICE. */
 int fntrs_submit(fntrs_ctx* ctx, const fntrs_job* jobs, uint32_t njobs, void* stream);

@@ -29,6 +29,7 @@ struct ClassLaunch {
   size_t jobs_off = 0, start_off = 0;   // byte offsets of the tables in the blob
   uint32_t njobs = 0, total = 0, grid = 0;
   uint64_t work = 0;   // butterflies, to balance the streams
+  int stream = 0;      // 0 = the caller's stream, b > 0 = side stream b-1
 };
 
 struct SingleJob {
@@ -36,6 +37,10 @@ struct SingleJob {
   FourStepArgs f{};
   uint32_t batch = 0;
   uint64_t ld_scratch = 0;
+  size_t scratch_need = 0;    // elements of scratch the job uses
+  uint64_t work = 0;          // butterflies, to balance the streams
+  int stream = 0;             // 0 = the caller's stream, b > 0 = side stream b-1
+  size_t scratch_off = 0;     // start of its stream's scratch slice
   const uint32_t* src = nullptr;   // copy
   uint32_t* dst = nullptr;
   size_t stride_src = 0, stride_dst = 0;
@@ -46,8 +51,9 @@ struct Plan {
   std::vector<uint8_t> blob;              // host image of the job tables
   std::vector<ClassLaunch> launches;
   std::vector<SingleJob> singles;
-  size_t scratch_elems = 0;               // shared by the singles, which run in order
+  size_t scratch_elems = 0;               // one slice per stream; a stream's singles run in order
   std::vector<fntrs_locator_t*> locs;     // distinct locators the batch reads
+  int streams = 0;                        // streams the plan spreads over
 };
 
 int occupancy(fntrs_ctx* c, int op, int L, int D, CtCfg cfg) {
@@ -104,7 +110,8 @@ int make_plan(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, Plan& P) {
         f.vec = aligned16(J.in, J.ld_in, J.stride_in) && aligned16(J.out, J.ld_out, J.stride_out);
         s.batch = J.batch;
         s.ld_scratch = (uint64_t)f.tiles * kFourStepTile;
-        P.scratch_elems = std::max(P.scratch_elems, (size_t)J.batch * J.n * s.ld_scratch);
+        s.scratch_need = (size_t)J.batch * J.n * s.ld_scratch;
+        s.work = (uint64_t)J.lanes * J.batch * (J.n / 2) * f.logn;
         P.singles.push_back(s);
       } else {
         classes[std::make_tuple(0, logK, 0)].push_back(j);
@@ -148,7 +155,8 @@ int make_plan(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, Plan& P) {
         f.vec = aligned16(J.in, J.ld_in, J.stride_in) && aligned16(J.out, J.ld_out, J.stride_out);
         s.batch = J.batch;
         s.ld_scratch = (uint64_t)f.tiles * kFourStepTile;
-        P.scratch_elems = std::max(P.scratch_elems, (size_t)J.batch * (f.n + f.M) * s.ld_scratch);
+        s.scratch_need = (size_t)J.batch * (f.n + f.M) * s.ld_scratch;
+        s.work = (uint64_t)J.lanes * J.batch * ((f.n / 2) * f.logn + f.M * f.logm);
         P.singles.push_back(s);
       } else {
         const int D = (L->k == L->n) ? -1 : L->logn - L->logm;
@@ -228,6 +236,43 @@ int make_plan(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, Plan& P) {
   // largest classes first: they start early and the small ones fill the tail
   std::stable_sort(P.launches.begin(), P.launches.end(),
                    [](const ClassLaunch& a, const ClassLaunch& b) { return a.work > b.work; });
+  // streams: every class launch and single job goes to the stream with the
+  // least work so far, heaviest first; a stream's singles share its slice
+  const int streams = std::min<int>(1 + fntrs_ctx::kSide, (int)(P.launches.size() + P.singles.size()));
+  std::vector<uint64_t> load(std::max(streams, 1), 0);
+  auto pick = [&](uint64_t w) {
+    int b = 0;
+    for (int q = 1; q < streams; ++q)
+      if (load[q] < load[b]) b = q;
+    load[b] += w;
+    return b;
+  };
+  std::vector<size_t> order(P.launches.size() + P.singles.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  auto work_of = [&](size_t i) {
+    return i < P.launches.size() ? P.launches[i].work : P.singles[i - P.launches.size()].work;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return work_of(a) > work_of(b); });
+  std::vector<size_t> slice(std::max(streams, 1), 0);
+  for (size_t i : order) {
+    const int b = pick(work_of(i));
+    if (i < P.launches.size()) {
+      P.launches[i].stream = b;
+    } else {
+      SingleJob& sj = P.singles[i - P.launches.size()];
+      sj.stream = b;
+      slice[b] = std::max(slice[b], sj.scratch_need);
+    }
+  }
+  size_t soff = 0;
+  std::vector<size_t> base(slice.size(), 0);
+  for (size_t b = 0; b < slice.size(); ++b) {
+    base[b] = soff;
+    soff += (slice[b] + 63) / 64 * 64;
+  }
+  for (SingleJob& sj : P.singles) sj.scratch_off = base[sj.stream];
+  P.scratch_elems = soff;
+  P.streams = streams;
   return FNTRS_OK;
 }
 
@@ -241,24 +286,19 @@ int init_side_set(fntrs_ctx* c, fntrs_ctx::SideSet& ss) {
   return FNTRS_OK;
 }
 
-// Enqueues the plan: the classes spread over `s` and the side streams of
-// `side` (the next class goes to the stream with the least work so far), the
-// single jobs in order on `s`; everything is joined back into `s`.
+// Enqueues the plan on `s` and the side streams of `side`, as make_plan
+// assigned them; everything is joined back into `s`.
 int run_plan(fntrs_ctx* c, const Plan& P, const uint8_t* dblob, uint32_t* scratch, hipStream_t s,
              fntrs_ctx::SideSet& side) {
-  const int streams = std::min<int>(1 + fntrs_ctx::kSide, (int)P.launches.size());
+  const int streams = P.streams;
   if (streams > 1) {
     if (int rc = init_side_set(c, side)) return rc;
     HIP_TRY(c, hipEventRecord(side.fork, s));
     for (int b = 0; b < streams - 1; ++b) HIP_TRY(c, hipStreamWaitEvent(side.st[b], side.fork, 0));
   }
-  std::vector<uint64_t> load(streams > 0 ? streams : 1, 0);
+  auto stream_of = [&](int b) { return b == 0 ? s : side.st[b - 1]; };
   for (const ClassLaunch& cl : P.launches) {
-    int b = 0;
-    for (int q = 1; q < streams; ++q)
-      if (load[q] < load[b]) b = q;
-    load[b] += cl.work;
-    hipStream_t st = b == 0 ? s : side.st[b - 1];
+    hipStream_t st = stream_of(cl.stream);
     if (cl.op == 0) {
       JobTable<EncodeArgs> t{reinterpret_cast<const EncodeArgs*>(dblob + cl.jobs_off),
                              reinterpret_cast<const uint32_t*>(dblob + cl.start_off), cl.njobs, cl.total};
@@ -270,13 +310,15 @@ int run_plan(fntrs_ctx* c, const Plan& P, const uint8_t* dblob, uint32_t* scratc
     }
   }
   for (const SingleJob& sj : P.singles) {
+    hipStream_t st = stream_of(sj.stream);
+    uint32_t* sa = scratch + sj.scratch_off;
     if (sj.kind == 0) {
-      HIP_TRY(c, launch_copy(sj.src, sj.stride_src, sj.dst, sj.stride_dst, sj.lanes, sj.batch, s));
+      HIP_TRY(c, launch_copy(sj.src, sj.stride_src, sj.dst, sj.stride_dst, sj.lanes, sj.batch, st));
     } else if (sj.kind == 1) {
-      HIP_TRY(c, fourstep_encode(sj.f, sj.batch, scratch, sj.ld_scratch, s));
+      HIP_TRY(c, fourstep_encode(sj.f, sj.batch, sa, sj.ld_scratch, st));
     } else {
-      uint32_t* sb = scratch + (size_t)sj.batch * sj.f.n * sj.ld_scratch;
-      HIP_TRY(c, fourstep_decode(sj.f, sj.batch, scratch, sb, sj.ld_scratch, s));
+      uint32_t* sb = sa + (size_t)sj.batch * sj.f.n * sj.ld_scratch;
+      HIP_TRY(c, fourstep_decode(sj.f, sj.batch, sa, sb, sj.ld_scratch, st));
     }
   }
   for (int b = 0; b < streams - 1; ++b) {
