@@ -71,6 +71,50 @@ hipError_t dec_tab_t(int D, const JobTable<DecodeArgs>& t, const uint32_t* tw, c
   return hipErrorInvalidValue;
 }
 
+// The pipelined decoder needs whole pass-0 items per thread and two passes.
+template <int L, int T, int NT, int V>
+constexpr bool pipe_ok() {
+  using Gm = ct::Geo<L, T, NT, V>;
+  return ct::pass0_per_thread<L, Gm::BM, Gm::G, NT>() >= 1 && ct::plan_np(L, Gm::BM) >= 2;
+}
+
+template <int L, int D, int T, int NT, int V>
+hipError_t dec_pipe_one(const JobTable<DecodeArgs>& t, const DecodeArgs& one, const uint32_t* tw, const uint32_t* twi,
+                        uint32_t grid, hipStream_t s) {
+  if constexpr (pipe_ok<L, T, NT, V>()) {
+    constexpr size_t lds = ct::Geo<L, T, NT, V>::LDS_BYTES;
+    (void)hipFuncSetAttribute((const void*)ct::k_dec_pipe<L, D, T, NT, V>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((ct::k_dec_pipe<L, D, T, NT, V>), dim3(grid), dim3(NT), lds, s, t, one, tw, twi);
+    return hipGetLastError();
+  } else {
+    return hipErrorNotSupported;
+  }
+}
+
+template <int L, int T, int NT, int V>
+hipError_t dec_pipe_t(int D, const JobTable<DecodeArgs>& t, const DecodeArgs& one, const uint32_t* tw,
+                      const uint32_t* twi, uint32_t grid, hipStream_t s) {
+  if (D == -1) return dec_pipe_one<L, -1, T, NT, V>(t, one, tw, twi, grid, s);
+  if (D == 0) return dec_pipe_one<L, 0, T, NT, V>(t, one, tw, twi, grid, s);
+  if constexpr (L > 1) {
+    if (D == 1) return dec_pipe_one<L, 1, T, NT, V>(t, one, tw, twi, grid, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// A pipelined kernel that spills registers to scratch loses to the plain one:
+// report it as unavailable.
+template <class K>
+int occupancy_no_spill(K kernel, int NT, size_t lds) {
+  hipFuncAttributes at{};
+  if (hipFuncGetAttributes(&at, (const void*)kernel) != hipSuccess || at.localSizeBytes > 0) return 0;
+  int nb = 0;
+  (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, NT, lds) != hipSuccess) return 0;
+  return nb;
+}
+
 template <class K>
 int occupancy(K kernel, int NT, size_t lds) {
   int nb = 0;
@@ -82,6 +126,16 @@ int occupancy(K kernel, int NT, size_t lds) {
 template <int L, int T, int NT, int V>
 int occ_t(int op, int D) {
   constexpr size_t lds = ct::Geo<L, T, NT, V>::LDS_BYTES;
+  if (op >= 2) {
+    if constexpr (pipe_ok<L, T, NT, V>()) {
+      if (D == -1) return occupancy_no_spill(ct::k_dec_pipe<L, -1, T, NT, V>, NT, lds);
+      if (D == 0) return occupancy_no_spill(ct::k_dec_pipe<L, 0, T, NT, V>, NT, lds);
+      if constexpr (L > 1) {
+        if (D == 1) return occupancy_no_spill(ct::k_dec_pipe<L, 1, T, NT, V>, NT, lds);
+      }
+    }
+    return 0;
+  }
   if (op == 0) return occupancy(ct::k_enc_tab<L, T, NT, V>, NT, lds);
   if (D == -1) return occupancy(ct::k_dec_tab<L, -1, T, NT, V>, NT, lds);
   if (D == 0) return occupancy(ct::k_dec_tab<L, 0, T, NT, V>, NT, lds);
@@ -140,14 +194,26 @@ hipError_t dec_tab_pick(CtCfg c, int D, const JobTable<DecodeArgs>& t, const uin
 }
 
 template <int I>
+hipError_t dec_pipe_pick(CtCfg c, int D, const JobTable<DecodeArgs>& t, const DecodeArgs& one, const uint32_t* tw,
+                         const uint32_t* twi, uint32_t grid, hipStream_t s) {
+  if constexpr (I < 4 && kVar.dec[I < 4 ? I : 0].T != 0) {
+    if (c.T == kVar.dec[I].T && c.NT == kVar.dec[I].NT && c.V == kVar.dec[I].V)
+      return dec_pipe_t<FNTRS_L, kVar.dec[I].T, kVar.dec[I].NT, kVar.dec[I].V>(D, t, one, tw, twi, grid, s);
+    return dec_pipe_pick<I + 1>(c, D, t, one, tw, twi, grid, s);
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int I>
 int occ_pick(CtCfg c, int op, int D) {
   if constexpr (I < 4) {
     constexpr CtCfg e = kVar.enc[I], d = kVar.dec[I];
     if constexpr (e.T != 0) {
-      if (op == 0 && c.T == e.T && c.NT == e.NT && c.V == e.V) return occ_t<FNTRS_L, e.T, e.NT, e.V>(0, D);
+      if (op == 0 && c.T == e.T && c.NT == e.NT && c.V == e.V) return occ_t<FNTRS_L, e.T, e.NT, e.V>(op, D);
     }
     if constexpr (d.T != 0) {
-      if (op == 1 && c.T == d.T && c.NT == d.NT && c.V == d.V) return occ_t<FNTRS_L, d.T, d.NT, d.V>(1, D);
+      if ((op == 1 || op == 2) && c.T == d.T && c.NT == d.NT && c.V == d.V) return occ_t<FNTRS_L, d.T, d.NT, d.V>(op, D);
     }
     return occ_pick<I + 1>(c, op, D);
   } else {
@@ -176,6 +242,12 @@ hipError_t FNTRS_CAT(ct_enc_tab_launch_, FNTRS_L)(CtCfg c, const JobTable<Encode
 hipError_t FNTRS_CAT(ct_dec_tab_launch_, FNTRS_L)(CtCfg c, int D, const JobTable<DecodeArgs>& t, const uint32_t* tw,
                                                   const uint32_t* twi, uint32_t grid, hipStream_t s) {
   return dec_tab_pick<0>(c, D, t, tw, twi, grid, s);
+}
+
+hipError_t FNTRS_CAT(ct_dec_pipe_launch_, FNTRS_L)(CtCfg c, int D, const JobTable<DecodeArgs>& t,
+                                                   const DecodeArgs& one, const uint32_t* tw, const uint32_t* twi,
+                                                   uint32_t grid, hipStream_t s) {
+  return dec_pipe_pick<0>(c, D, t, one, tw, twi, grid, s);
 }
 
 int FNTRS_CAT(ct_tab_occupancy_, FNTRS_L)(CtCfg c, int op, int D) { return occ_pick<0>(c, op, D); }

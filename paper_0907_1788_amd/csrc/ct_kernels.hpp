@@ -100,27 +100,30 @@ __device__ __forceinline__ const uint32_t* row_ptr(const uint32_t* p, uint64_t r
   return p + row * ld;
 }
 
-template <int V>
-__device__ __forceinline__ void load_lanes(const uint32_t* p, uint32_t lane, uint32_t lanes, bool vec,
-                                           int32_t (&x)[V]) {
+// One row of V lanes as int32, whole (one access) or part (ragged tail).
+template <int V, bool WHOLE>
+__device__ __forceinline__ void load_lanes(const uint32_t* p, uint32_t lane, uint32_t lanes, int32_t (&x)[V]) {
   uint32_t u[V];
-  gload<V>(p, lane, lanes, vec, u);
+  if constexpr (WHOLE) gload_whole<V>(p, u);
+  else gload_part<V>(p, lane, lanes, u);
 #pragma unroll
   for (int v = 0; v < V; ++v) x[v] = (int32_t)u[v];
 }
 
-template <int V>
-__device__ __forceinline__ void store_lanes(uint32_t* p, uint32_t lane, uint32_t lanes, bool vec,
-                                            const int32_t (&x)[V]) {
+template <int V, bool WHOLE>
+__device__ __forceinline__ void store_lanes(uint32_t* p, uint32_t lane, uint32_t lanes, const int32_t (&x)[V]) {
   uint32_t u[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) u[v] = canon(x[v]);
-  gstore<V>(p, lane, lanes, vec, u);
+  if constexpr (WHOLE) gstore_whole<V>(p, u);
+  else gstore_part<V>(p, lane, lanes, u);
 }
 
 // ---------------------------------------------------------------- encoder
 // First DIT pass of the encoder: position pos holds source row bitrev(pos),
-// twisted by r_n^(t j) (coset t); rows j >= k are zero padding.
+// twisted by r_n^(t j) (coset t); rows j >= k are zero padding.  raw issues
+// all reads of an item -- the rows and their twist factors -- before finish
+// consumes any of them (twist, zero the padding).
 template <int L, int V>
 struct EncLoad {
   const uint32_t* src;
@@ -129,25 +132,42 @@ struct EncLoad {
   uint32_t k, n, t, lane0, lanes;
   int sh;
   bool vec;
-  template <int B, uint32_t H>
-  __device__ __forceinline__ void item(uint32_t base, uint32_t g, int32_t (&x)[1 << B][V]) {
-    static_assert(H == 1, "the first DIT pass has stride 1");
+  template <int B, bool WHOLE>
+  __device__ __forceinline__ void rows(uint32_t jb, uint32_t g, int32_t (&x)[1 << B][V], uint32_t (&wt)[1 << B]) {
+#pragma unroll
+    for (int c = 0; c < (1 << B); ++c) {
+      const uint32_t j = jb | (bitrev((uint32_t)c, B) << (L - B));
+      wt[c] = gptr(tw)[((t * j) & (n - 1)) << sh];   // tw[0] = 1 for coset 0
+      // no branch: a padding row reads row k-1 (finish zeroes it), which
+      // keeps the reads of an item one straight sequence
+      const uint32_t jr = j < k ? j : k - 1;
+      load_lanes<V, WHOLE>(row_ptr(src, jr, ld) + g * V, lane0 + g * V, lanes, x[c]);
+    }
+  }
+  template <int B>
+  __device__ __forceinline__ void raw(uint32_t base, uint32_t g, int32_t (&x)[1 << B][V], uint32_t (&wt)[1 << B],
+                                      uint32_t (&)[1 << B]) {
+    const uint32_t jb = bitrev(base, L);
+    if (whole_vector<V>(lane0 + g * V, lanes, vec)) rows<B, true>(jb, g, x, wt);
+    else rows<B, false>(jb, g, x, wt);
+  }
+  template <int B>
+  __device__ __forceinline__ void finish(uint32_t base, uint32_t, int32_t (&x)[1 << B][V], const uint32_t (&wt)[1 << B],
+                                         const uint32_t (&)[1 << B]) {
     const uint32_t jb = bitrev(base, L);
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c) {
       const uint32_t j = jb | (bitrev((uint32_t)c, B) << (L - B));
-      if (j < k) {
-        load_lanes<V>(row_ptr(src, j, ld) + g * V, lane0 + g * V, lanes, vec, x[c]);
-        if (t) {
-          const uint32_t w = tw[((t * j) & (n - 1)) << sh];
 #pragma unroll
-          for (int v = 0; v < V; ++v) x[c][v] = mulw(x[c][v], w);
-        }
-      } else {
-#pragma unroll
-        for (int v = 0; v < V; ++v) x[c][v] = 0;
-      }
+      for (int v = 0; v < V; ++v) x[c][v] = j < k ? (t ? mulw(x[c][v], wt[c]) : x[c][v]) : 0;
     }
+  }
+  template <int B, uint32_t H>
+  __device__ __forceinline__ void item(uint32_t base, uint32_t g, int32_t (&x)[1 << B][V]) {
+    static_assert(H == 1, "the first DIT pass has stride 1");
+    uint32_t aux[1 << B], aux2[1 << B];
+    raw<B>(base, g, x, aux, aux2);
+    finish<B>(base, g, x, aux, aux2);
   }
 };
 
@@ -158,13 +178,18 @@ struct EncStore {
   uint64_t ld;
   uint32_t t, cosets, lane0, lanes;
   bool vec;
-  template <int B, uint32_t H>
-  __device__ __forceinline__ void item(uint32_t base, uint32_t g, int32_t (&x)[1 << B][V]) {
+  template <int B, uint32_t H, bool WHOLE>
+  __device__ __forceinline__ void rows(uint32_t base, uint32_t g, int32_t (&x)[1 << B][V]) {
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c) {
       const uint64_t row = t + (uint64_t)cosets * (base + c * H);
-      store_lanes<V>(dst + row * ld + g * V, lane0 + g * V, lanes, vec, x[c]);
+      store_lanes<V, WHOLE>(dst + row * ld + g * V, lane0 + g * V, lanes, x[c]);
     }
+  }
+  template <int B, uint32_t H>
+  __device__ __forceinline__ void item(uint32_t base, uint32_t g, int32_t (&x)[1 << B][V]) {
+    if (whole_vector<V>(lane0 + g * V, lanes, vec)) rows<B, H, true>(base, g, x);
+    else rows<B, H, false>(base, g, x);
   }
 };
 
@@ -202,7 +227,7 @@ __device__ __forceinline__ uint32_t find_job(const uint32_t* start, uint32_t njo
   uint32_t lo = 0, hi = njobs;
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
-    if (start[mid] <= w) lo = mid;
+    if (gptr(start)[mid] <= w) lo = mid;
     else hi = mid;
   }
   return lo;
@@ -218,15 +243,34 @@ __global__ void __launch_bounds__(NT) k_enc_tab(JobTable<EncodeArgs> t, const ui
   const TW tws = make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, tw, twi);
   for (uint32_t w = xcd_remap(blockIdx.x, gridDim.x); w < t.total; w += gridDim.x) {
     const uint32_t j = find_job(t.start, t.njobs, w);
-    const EncodeArgs a = t.jobs[j];
-    enc_item<LK, TT, NT, VV>(a, w - t.start[j], lds, tws);
+    const EncodeArgs a = load_global(t.jobs + j);
+    enc_item<LK, TT, NT, VV>(a, w - gptr(t.start)[j], lds, tws);
     __syncthreads();   // the next item overwrites the LDS tile
   }
+}
+
+// The job and local work item of global work item w: from the table, or the
+// single job `one` when the table has none.
+template <class Args>
+__device__ __forceinline__ Args job_at(const JobTable<Args>& t, const Args& one, uint32_t w, uint32_t& local,
+                                       uint32_t& job) {
+  if (!t.jobs) {
+    local = w;
+    job = 0;
+    return one;
+  }
+  const uint32_t j = find_job(t.start, t.njobs, w);
+  local = w - gptr(t.start)[j];
+  job = j;
+  return load_global(t.jobs + j);
 }
 
 // ---------------------------------------------------------------- decoder
 // First DIT pass of step 5: position pos holds u at index z = bitrev(pos):
 // the received symbol v_z times the locator weight of z (0 if z is erased).
+// consts reads the weights and rows of the positions (the same for every
+// tile of a locator), raw issues the row reads of all positions and
+// consumes nothing, finish multiplies and zeroes the erased positions.
 template <int L, int V>
 struct DecLoad {
   const uint32_t* recv;
@@ -235,24 +279,46 @@ struct DecLoad {
   uint64_t ld;
   uint32_t lane0, lanes;
   bool full, vec;
-  template <int B, uint32_t H>
-  __device__ __forceinline__ void item(uint32_t base, uint32_t g, int32_t (&x)[1 << B][V]) {
-    static_assert(H == 1, "the first DIT pass has stride 1");
+  template <int B>
+  __device__ __forceinline__ void consts(uint32_t base, uint32_t (&wv)[1 << B], uint32_t (&rv)[1 << B]) {
     const uint32_t zb = bitrev(base, L);
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c) {
       const uint32_t z = zb | (bitrev((uint32_t)c, B) << (L - B));
-      const uint32_t w = wfull[z];
-      if (w) {
-        const uint32_t row = full ? z : ridx[z];
-        load_lanes<V>(row_ptr(recv, row, ld) + g * V, lane0 + g * V, lanes, vec, x[c]);
-#pragma unroll
-        for (int v = 0; v < V; ++v) x[c][v] = mulc((uint32_t)x[c][v], w);
-      } else {
-#pragma unroll
-        for (int v = 0; v < V; ++v) x[c][v] = 0;
-      }
+      const uint32_t w = gptr(wfull)[z];
+      wv[c] = w;
+      // an erased position reads a row that exists (finish zeroes it)
+      rv[c] = full ? z : (w ? gptr(ridx)[z] : 0u);
     }
+  }
+  template <int B, bool WHOLE>
+  __device__ __forceinline__ void rows(uint32_t g, int32_t (&x)[1 << B][V], const uint32_t (&wv)[1 << B],
+                                       const uint32_t (&rv)[1 << B]) {
+#pragma unroll
+    for (int c = 0; c < (1 << B); ++c)
+      load_lanes<V, WHOLE>(row_ptr(recv, rv[c], ld) + g * V, lane0 + g * V, lanes, x[c]);
+  }
+  template <int B>
+  __device__ __forceinline__ void raw(uint32_t, uint32_t g, int32_t (&x)[1 << B][V], uint32_t (&wv)[1 << B],
+                                      uint32_t (&rv)[1 << B]) {
+    if (whole_vector<V>(lane0 + g * V, lanes, vec)) rows<B, true>(g, x, wv, rv);
+    else rows<B, false>(g, x, wv, rv);
+  }
+  template <int B>
+  __device__ __forceinline__ void finish(uint32_t, uint32_t, int32_t (&x)[1 << B][V], const uint32_t (&wv)[1 << B],
+                                         const uint32_t (&)[1 << B]) {
+#pragma unroll
+    for (int c = 0; c < (1 << B); ++c)
+#pragma unroll
+      for (int v = 0; v < V; ++v) x[c][v] = wv[c] ? mulc((uint32_t)x[c][v], wv[c]) : 0;
+  }
+  template <int B, uint32_t H>
+  __device__ __forceinline__ void item(uint32_t base, uint32_t g, int32_t (&x)[1 << B][V]) {
+    static_assert(H == 1, "the first DIT pass has stride 1");
+    uint32_t wv[1 << B], rv[1 << B];
+    consts<B>(base, wv, rv);
+    raw<B>(base, g, x, wv, rv);
+    finish<B>(base, g, x, wv, rv);
   }
 };
 
@@ -286,7 +352,7 @@ struct ProductStore {
   __device__ __forceinline__ void item(uint32_t base, uint32_t g, int32_t (&x)[1 << B][V]) {
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c) {
-      const uint32_t h = ahat_br[base + c * H];
+      const uint32_t h = gptr(ahat_br)[base + c * H];
 #pragma unroll
       for (int v = 0; v < V; ++v) x[c][v] = mulc(canon(x[c][v]), h);
     }
@@ -301,13 +367,18 @@ struct SourceStore {
   uint64_t ld;
   uint32_t k, lane0, lanes;
   bool vec;
-  template <int B, uint32_t H>
-  __device__ __forceinline__ void item(uint32_t base, uint32_t g, int32_t (&x)[1 << B][V]) {
+  template <int B, uint32_t H, bool WHOLE>
+  __device__ __forceinline__ void rows(uint32_t base, uint32_t g, int32_t (&x)[1 << B][V]) {
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c) {
       const uint32_t m = base + c * H;
-      if (m < k) store_lanes<V>(dst + (uint64_t)m * ld + g * V, lane0 + g * V, lanes, vec, x[c]);
+      if (m < k) store_lanes<V, WHOLE>(dst + (uint64_t)m * ld + g * V, lane0 + g * V, lanes, x[c]);
     }
+  }
+  template <int B, uint32_t H>
+  __device__ __forceinline__ void item(uint32_t base, uint32_t g, int32_t (&x)[1 << B][V]) {
+    if (whole_vector<V>(lane0 + g * V, lanes, vec)) rows<B, H, true>(base, g, x);
+    else rows<B, H, false>(base, g, x);
   }
 };
 
@@ -367,9 +438,85 @@ __global__ void __launch_bounds__(NT) k_dec_tab(JobTable<DecodeArgs> t, const ui
   const TW tws = make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, tw, twi);
   for (uint32_t w = xcd_remap(blockIdx.x, gridDim.x); w < t.total; w += gridDim.x) {
     const uint32_t j = find_job(t.start, t.njobs, w);
-    const DecodeArgs a = t.jobs[j];
-    dec_item<LN, D, TT, NT, VV>(a, w - t.start[j], lds, tws);
+    const DecodeArgs a = load_global(t.jobs + j);
+    dec_item<LN, D, TT, NT, VV>(a, w - gptr(t.start)[j], lds, tws);
     __syncthreads();
+  }
+}
+
+template <int LN, int TT, int NT, int VV>
+__device__ __forceinline__ DecLoad<LN, Geo<LN, TT, NT, VV>::V> dec_loader(const DecodeArgs& a, uint32_t item) {
+  constexpr int T = Geo<LN, TT, NT, VV>::T;
+  const uint32_t lane0 = (item % a.tiles) * T;
+  const uint64_t blk = item / a.tiles;
+  return {a.recv + blk * a.stride_recv + lane0, a.wfull, a.ridx, a.ld_recv, lane0, a.lanes, a.full != 0, a.vec != 0};
+}
+
+// Persistent decoder: a grid of resident size walks the work items (numbered
+// as in k_dec).  The pass-0 reads of a workgroup's next item (received rows
+// and their weights) are issued right before the last pass of the current
+// one, so their latency overlaps that pass and its stores; the next item's
+// pass 0 then starts from registers.
+template <int LN, int D, int TT, int NT, int VV>
+__global__ void __launch_bounds__(NT) k_dec_pipe(JobTable<DecodeArgs> t, DecodeArgs one, const uint32_t* tw,
+                                                 const uint32_t* twi) {
+  using Gm = Geo<LN, TT, NT, VV>;
+  constexpr int V = Gm::V, G = Gm::G, T = Gm::T, BM = Gm::BM;
+  constexpr int B0 = plan_b(LN, BM, 0);
+  constexpr int C0 = pass0_per_thread<LN, BM, G, NT>();
+  static_assert(C0 >= 1 && plan_np(LN, BM) >= 2, "pipelined kernel needs whole pass-0 items and two passes");
+  using TW = typename Gm::TwType;
+  extern __shared__ uint32_t lds[];
+  const TW tws = make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, tw, twi);
+  int32_t pre[C0][1 << B0][V];
+  uint32_t aux[C0][1 << B0], aux2[C0][1 << B0];   // weights and rows of the current job's positions
+  uint32_t w = xcd_remap(blockIdx.x, gridDim.x);
+  if (w >= t.total) return;
+  uint32_t cjob;
+  {
+    uint32_t local;
+    const DecodeArgs a = job_at(t, one, w, local, cjob);
+    auto ld = dec_loader<LN, TT, NT, VV>(a, local);
+    consts0<LN, BM, V, G, NT, C0>(ld, aux, aux2);
+    prefetch0<LN, BM, V, G, NT, C0>(ld, pre, aux, aux2);
+  }
+  LdsLoad<V, G> ll{lds};
+  LdsStore<V, G, false> sl{lds};
+  for (; w < t.total; w += gridDim.x) {
+    uint32_t local, job;
+    const DecodeArgs a = job_at(t, one, w, local, job);
+    auto lg = dec_loader<LN, TT, NT, VV>(a, local);
+    const uint32_t lane0 = (local % a.tiles) * T;
+    const uint64_t blk = local / a.tiles;
+    SourceStore<V> sg{a.dst + blk * a.stride_dst + lane0, a.ld_dst, a.k, lane0, a.lanes, a.vec != 0};
+    const uint32_t wn = w + gridDim.x;
+    auto hook = [&]() {
+      if (wn < t.total) {
+        uint32_t ln, jn;
+        const DecodeArgs an = job_at(t, one, wn, ln, jn);
+        auto ld = dec_loader<LN, TT, NT, VV>(an, ln);
+        if (jn != cjob) {
+          consts0<LN, BM, V, G, NT, C0>(ld, aux, aux2);
+          cjob = jn;
+        }
+        prefetch0<LN, BM, V, G, NT, C0>(ld, pre, aux, aux2);
+      }
+    };
+    dit_pass0_regs<LN, BM, V, G, NT, C0, true>(tws, lg, pre, aux, aux2, sl);
+    __syncthreads();
+    if constexpr (D < 0) {
+      dit_from<LN, BM, V, G, true, 1>(tws, ll, sl, sg, hook);
+    } else {
+      LdsStore<V, G, true> slf{lds};
+      SeriesStore<V, G> ss{lds, a.k};
+      ProductStore<V, G> sp{lds, a.ahat_br};
+      NoHook none;
+      dit_from<LN, BM, V, G, true, 1>(tws, ll, sl, ss, none);
+      __syncthreads();
+      dif<LN - D, BM, V, G, false>(tws, ll, ll, slf, sp);
+      dit_hooked<LN - D, BM, V, G, true>(tws, ll, ll, sl, sg, hook);
+    }
+    __syncthreads();   // the next item overwrites the LDS tile
   }
 }
 

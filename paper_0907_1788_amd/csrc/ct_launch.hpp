@@ -45,8 +45,14 @@ using CtEncTabLaunch = hipError_t (*)(CtCfg cfg, const JobTable<EncodeArgs>& t, 
                                       const uint32_t* twi, uint32_t grid, hipStream_t s);
 using CtDecTabLaunch = hipError_t (*)(CtCfg cfg, int D, const JobTable<DecodeArgs>& t, const uint32_t* tw,
                                       const uint32_t* twi, uint32_t grid, hipStream_t s);
-// Workgroups of the table kernel that fit on one CU at once (0 when the
-// configuration is not instantiated); op 0 = encode, 1 = decode.
+// Pipelined persistent decoder launch (k_dec_pipe): a table of jobs, or
+// (t.jobs == nullptr) the single job `one` with t.total work items.
+// hipErrorNotSupported when the configuration has no pipelined kernel.
+using CtDecPipeLaunch = hipError_t (*)(CtCfg cfg, int D, const JobTable<DecodeArgs>& t, const DecodeArgs& one,
+                                       const uint32_t* tw, const uint32_t* twi, uint32_t grid, hipStream_t s);
+// Workgroups of a persistent kernel that fit on one CU at once (0 when the
+// configuration is not instantiated or has no such kernel); op 0 = encode
+// table, 1 = decode table, 2 = decode pipelined.
 using CtTabOccupancy = int (*)(CtCfg cfg, int op, int D);
 
 #define FNTRS_CT_DECL(L)                                                                              \
@@ -56,6 +62,8 @@ using CtTabOccupancy = int (*)(CtCfg cfg, int op, int D);
                                    const uint32_t* twi, uint32_t grid, hipStream_t s);                    \
   hipError_t ct_dec_tab_launch_##L(CtCfg cfg, int D, const JobTable<DecodeArgs>& t, const uint32_t* tw,   \
                                    const uint32_t* twi, uint32_t grid, hipStream_t s);                    \
+  hipError_t ct_dec_pipe_launch_##L(CtCfg cfg, int D, const JobTable<DecodeArgs>& t, const DecodeArgs& one,\
+                                    const uint32_t* tw, const uint32_t* twi, uint32_t grid, hipStream_t s); \
   int ct_tab_occupancy_##L(CtCfg cfg, int op, int D);
 FNTRS_CT_DECL(1) FNTRS_CT_DECL(2) FNTRS_CT_DECL(3) FNTRS_CT_DECL(4) FNTRS_CT_DECL(5)
 FNTRS_CT_DECL(6) FNTRS_CT_DECL(7) FNTRS_CT_DECL(8) FNTRS_CT_DECL(9) FNTRS_CT_DECL(10)

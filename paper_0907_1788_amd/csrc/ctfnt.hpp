@@ -171,7 +171,7 @@ struct TwGlobal {
   const uint32_t* inv;
   static constexpr bool NEG = false;
   __device__ __forceinline__ uint32_t get(bool inverse, uint32_t j, int lg) const {
-    return (inverse ? inv : fwd)[j << (16 - lg)];
+    return gptr(inverse ? inv : fwd)[j << (16 - lg)];
   }
 };
 
@@ -203,9 +203,9 @@ struct TwLds {
   // fills the tables from the global table tw[e] = 3^e: omega_(2^lg)^j = 3^(j 2^(16-lg))
   __device__ __forceinline__ void fill(uint32_t* t, const uint32_t* __restrict__ tw) const {
     for (int lg = LO; lg <= TOP; ++lg)
-      for (uint32_t j = threadIdx.x; j <= (1u << (lg - 1)); j += blockDim.x) t[off(lg) + j] = tw[j << (16 - lg)];
+      for (uint32_t j = threadIdx.x; j <= (1u << (lg - 1)); j += blockDim.x) t[off(lg) + j] = gptr(tw)[j << (16 - lg)];
     if (TOP < L)
-      for (uint32_t u = threadIdx.x; u <= (1u << (L - 1)); u += blockDim.x) t[off(TOP + 1) + u] = tw[u << (16 - L)];
+      for (uint32_t u = threadIdx.x; u <= (1u << (L - 1)); u += blockDim.x) t[off(TOP + 1) + u] = gptr(tw)[u << (16 - L)];
   }
 };
 
@@ -361,6 +361,103 @@ __device__ __forceinline__ void dif(const TW& tw, L0& l0, LM& lm, SM& sm, SL& sl
     dif<L, BM, V, G, INV, P + 1>(tw, l0, lm, sm, sl);
   }
 }
+
+// ---------------------------------------------------------------- pipeline
+// Persistent kernels overlap the global reads of the next tile with the last
+// pass of the current one: pass 0's inputs are read into registers ahead of
+// time (raw<B>), completed when pass 0 runs (finish<B>: twist, weights), and
+// the stores of the last pass drain while the next tile starts.  This needs
+// every thread to own the same whole number C0 of pass-0 items.
+template <int L, int BM, int G, int NT>
+__host__ __device__ constexpr int pass0_per_thread() {
+  return (((1u << (L - plan_b(L, BM, 0))) * G) % NT == 0) ? (int)(((1u << (L - plan_b(L, BM, 0))) * G) / NT) : 0;
+}
+
+// Reads the per-position values of this thread's pass-0 items that every
+// tile of a job shares (loader member consts<B>).
+template <int L, int BM, int V, int G, int NT, int C0, class Ld>
+__device__ __forceinline__ void consts0(Ld& ld, uint32_t (&aux)[C0][1 << plan_b(L, BM, 0)],
+                                       uint32_t (&aux2)[C0][1 << plan_b(L, BM, 0)]) {
+  constexpr int B = plan_b(L, BM, 0);
+#pragma unroll
+  for (int c = 0; c < C0; ++c) {
+    const uint32_t q = threadIdx.x + (uint32_t)c * NT;
+    ld.template consts<B>((q / G) << B, aux[c], aux2[c]);
+  }
+}
+
+// Issues the reads of this thread's pass-0 items (positions base + c,
+// stride 1) of the loader's tile into x (loader member raw<B>), consuming
+// none of them.
+template <int L, int BM, int V, int G, int NT, int C0, class Ld>
+__device__ __forceinline__ void prefetch0(Ld& ld, int32_t (&x)[C0][1 << plan_b(L, BM, 0)][V],
+                                         uint32_t (&aux)[C0][1 << plan_b(L, BM, 0)],
+                                         uint32_t (&aux2)[C0][1 << plan_b(L, BM, 0)]) {
+  constexpr int B = plan_b(L, BM, 0);
+#pragma unroll
+  for (int c = 0; c < C0; ++c) {
+    const uint32_t q = threadIdx.x + (uint32_t)c * NT;
+    const uint32_t g = q % G, it = q / G;
+    ld.template raw<B>(it << B, g, x[c], aux[c], aux2[c]);
+  }
+}
+
+// Pass 0 of a DIT transform from prefetched registers.
+template <int L, int BM, int V, int G, int NT, int C0, bool INV, class TW, class Ld, class St>
+__device__ __forceinline__ void dit_pass0_regs(const TW& tw, Ld& ld, int32_t (&pre)[C0][1 << plan_b(L, BM, 0)][V],
+                                               uint32_t (&aux)[C0][1 << plan_b(L, BM, 0)],
+                                               uint32_t (&aux2)[C0][1 << plan_b(L, BM, 0)], St& st) {
+  constexpr int B = plan_b(L, BM, 0);
+#pragma unroll
+  for (int c = 0; c < C0; ++c) {
+    const uint32_t q = threadIdx.x + (uint32_t)c * NT;
+    const uint32_t g = q % G, it = q / G;
+    const uint32_t base = it << B;
+    int32_t x[1 << B][V];
+#pragma unroll
+    for (int r = 0; r < (1 << B); ++r)
+#pragma unroll
+      for (int v = 0; v < V; ++v) x[r][v] = pre[c][r][v];
+    ld.template finish<B>(base, g, x, aux[c], aux2[c]);
+    dit_stages<B, V, 0, INV>(x, 0, tw);
+    st.template item<B, 1>(base, g, x);
+  }
+}
+
+// Passes P.. of a DIT transform (pass P reads through lm); hook() runs right
+// before the last pass, and no barrier follows it.
+template <int L, int BM, int V, int G, bool INV, int P, class TW, class LM, class SM, class SL, class Hook>
+__device__ __forceinline__ void dit_from(const TW& tw, LM& lm, SM& sm, SL& sl, Hook& hook) {
+  constexpr int NP = plan_np(L, BM);
+  if constexpr (P < NP) {
+    if constexpr (P == NP - 1) {
+      hook();
+      dit_pass<L, BM, P, V, G, INV>(tw, lm, sl);
+    } else {
+      dit_pass<L, BM, P, V, G, INV>(tw, lm, sm);
+      __syncthreads();
+      dit_from<L, BM, V, G, INV, P + 1>(tw, lm, sm, sl, hook);
+    }
+  }
+}
+
+// A whole DIT transform like dit<>, with hook() right before the last pass
+// and no barrier after it.
+template <int L, int BM, int V, int G, bool INV, class TW, class L0, class LM, class SM, class SL, class Hook>
+__device__ __forceinline__ void dit_hooked(const TW& tw, L0& l0, LM& lm, SM& sm, SL& sl, Hook& hook) {
+  if constexpr (plan_np(L, BM) == 1) {
+    hook();
+    dit_pass<L, BM, 0, V, G, INV>(tw, l0, sl);
+  } else {
+    dit_pass<L, BM, 0, V, G, INV>(tw, l0, sm);
+    __syncthreads();
+    dit_from<L, BM, V, G, INV, 1>(tw, lm, sm, sl, hook);
+  }
+}
+
+struct NoHook {
+  __device__ __forceinline__ void operator()() const {}
+};
 
 }  // namespace ct
 }  // namespace fntrs

@@ -11,6 +11,38 @@
 
 namespace fntrs {
 
+// Global-memory views of generic pointers.  A pointer that reaches a kernel
+// through memory (a job table) rather than as a kernel argument has lost its
+// address space, and flat accesses through it count against the LDS counter
+// too, so that every wait for an LDS result would also wait for all global
+// traffic in flight.  Every global access of the coding kernels goes
+// through these views.
+#define FNTRS_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const FNTRS_GLOBAL T* gptr(const T* p) {
+  return (const FNTRS_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ FNTRS_GLOBAL T* gptr(T* p) {
+  return (FNTRS_GLOBAL T*)p;
+}
+
+// 16-byte vector of the global accesses.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// A trivially copyable struct read from global memory word by word.
+template <class T>
+__device__ __forceinline__ T load_global(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "whole words");
+  T v;
+  const FNTRS_GLOBAL uint32_t* q = gptr(reinterpret_cast<const uint32_t*>(p));
+  uint32_t* d = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+  for (unsigned i = 0; i < sizeof(T) / 4; ++i) d[i] = q[i];
+  return v;
+}
+
+
 constexpr uint32_t kP = 65537u;
 
 // a + b mod p for canonical a, b.

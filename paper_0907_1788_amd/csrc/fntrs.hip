@@ -45,8 +45,40 @@ const CtTables& ct_tables() {
     ct_tab_occupancy_4,  ct_tab_occupancy_5,  ct_tab_occupancy_6,  ct_tab_occupancy_7,
     ct_tab_occupancy_8,  ct_tab_occupancy_9,  ct_tab_occupancy_10, ct_tab_occupancy_11,
     ct_tab_occupancy_12, ct_tab_occupancy_13, ct_tab_occupancy_14, ct_tab_occupancy_15};
-  static const CtTables t{enc, dec, enc_tab, dec_tab, occ};
+  static const CtDecPipeLaunch dec_pipe[16] = {
+      nullptr,               ct_dec_pipe_launch_1,  ct_dec_pipe_launch_2,  ct_dec_pipe_launch_3,
+      ct_dec_pipe_launch_4,  ct_dec_pipe_launch_5,  ct_dec_pipe_launch_6,  ct_dec_pipe_launch_7,
+      ct_dec_pipe_launch_8,  ct_dec_pipe_launch_9,  ct_dec_pipe_launch_10, ct_dec_pipe_launch_11,
+      ct_dec_pipe_launch_12, ct_dec_pipe_launch_13, ct_dec_pipe_launch_14, ct_dec_pipe_launch_15};
+  static const CtTables t{enc, dec, enc_tab, dec_tab, dec_pipe, occ};
   return t;
+}
+
+int kernel_occupancy(fntrs_ctx* c, int op, int L, int D, CtCfg cfg) {
+  const auto key = std::make_tuple(op, L, D, cfg.T * 4096 + cfg.NT, cfg.V);
+  auto it = c->occ.find(key);
+  if (it != c->occ.end()) return it->second;
+  const int o = ct_tables().occ[L](cfg, op, D);
+  c->occ[key] = o;
+  return o;
+}
+
+hipError_t launch_ct_encode(fntrs_ctx* c, int L, CtCfg cfg, const EncodeArgs& a, uint64_t items, hipStream_t s) {
+  (void)c;
+  if (items > 0x7fffffffull) return hipErrorInvalidValue;
+  return ct_tables().enc[L](cfg, a, (uint32_t)items, s);
+}
+
+hipError_t launch_ct_decode(fntrs_ctx* c, int L, CtCfg cfg, int D, const DecodeArgs& a, uint64_t items,
+                            hipStream_t s) {
+  if (items > 0x7fffffffull) return hipErrorInvalidValue;
+  const int occ = kernel_occupancy(c, 2, L, D, cfg);
+  if (occ > 0) {
+    const JobTable<DecodeArgs> t{nullptr, nullptr, 1, (uint32_t)items};
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(items, (uint64_t)occ * c->num_cu);
+    return ct_tables().dec_pipe[L](cfg, D, t, a, c->tw, c->twi, grid, s);
+  }
+  return ct_tables().dec[L](cfg, D, a, (uint32_t)items, s);
 }
 
 int check_encode(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uint32_t* src, size_t ld_src,
@@ -554,7 +586,7 @@ int fntrs_encode(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uin
   a.cosets = n >> a.logK;
   const uint64_t blocks = (uint64_t)a.tiles * a.cosets * batch;
   if (blocks > 0x7fffffffull) return fail(c, FNTRS_E_INVAL, "grid too large");
-  HIP_TRY(c, ct_tables().enc[a.logK](cfg, a, (uint32_t)blocks, s));
+  HIP_TRY(c, launch_ct_encode(c, a.logK, cfg, a, blocks, s));
   return FNTRS_OK;
 }
 
@@ -657,7 +689,7 @@ int fntrs_decode(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, uint32_
   a.tiles = (lanes + cfg.T - 1) / cfg.T;
   const uint64_t blocks = (uint64_t)a.tiles * batch;
   if (blocks > 0x7fffffffull) return fail(c, FNTRS_E_INVAL, "grid too large");
-  HIP_TRY(c, ct_tables().dec[L->logn](cfg, D, a, (uint32_t)blocks, s));
+  HIP_TRY(c, launch_ct_decode(c, L->logn, cfg, D, a, blocks, s));
   return FNTRS_OK;
 }
 

@@ -70,10 +70,8 @@ struct GLoad {
   uint32_t lane0, lanes;
   bool vec;
   RowFn rowf;
-  template <int B, uint32_t H>
-  __device__ __forceinline__ void item(uint32_t pb, uint32_t g, int32_t (&x)[1 << B][4]) {
-    static_assert(H == 1, "the first DIT pass has stride 1");
-    const uint32_t ib = bitrev(pb, L);
+  template <int B, bool WHOLE>
+  __device__ __forceinline__ void rows(uint32_t ib, uint32_t g, int32_t (&x)[1 << B][4]) {
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c) {
       const uint32_t i = ib | (bitrev((uint32_t)c, B) << (L - B));
@@ -83,13 +81,20 @@ struct GLoad {
 #pragma unroll
         for (int v = 0; v < 4; ++v) x[c][v] = 0;
       } else {
-        ct::load_lanes<4>(rowp(base, ld, r, g), lane0 + g * 4, lanes, vec, x[c]);
+        ct::load_lanes<4, WHOLE>(rowp(base, ld, r, g), lane0 + g * 4, lanes, x[c]);
         if (w) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) x[c][v] = ct::mulc((uint32_t)x[c][v], w);
         }
       }
     }
+  }
+  template <int B, uint32_t H>
+  __device__ __forceinline__ void item(uint32_t pb, uint32_t g, int32_t (&x)[1 << B][4]) {
+    static_assert(H == 1, "the first DIT pass has stride 1");
+    const uint32_t ib = bitrev(pb, L);
+    if (whole_vector<4>(lane0 + g * 4, lanes, vec)) rows<B, true>(ib, g, x);
+    else rows<B, false>(ib, g, x);
   }
 };
 
@@ -103,8 +108,8 @@ struct GStore {
   uint32_t lane0, lanes;
   bool vec;
   DestFn destf;
-  template <int B, uint32_t H>
-  __device__ __forceinline__ void item(uint32_t pb, uint32_t g, int32_t (&x)[1 << B][4]) {
+  template <int B, uint32_t H, bool WHOLE>
+  __device__ __forceinline__ void rows(uint32_t pb, uint32_t g, int32_t (&x)[1 << B][4]) {
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c) {
       const uint32_t p = pb + c * H;
@@ -115,8 +120,13 @@ struct GStore {
       int32_t y[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) y[v] = w ? ct::mulc(ct::canon(x[c][v]), w) : x[c][v];
-      ct::store_lanes<4>(const_cast<uint32_t*>(rowp(base, ld, r, g)), lane0 + g * 4, lanes, vec, y);
+      ct::store_lanes<4, WHOLE>(const_cast<uint32_t*>(rowp(base, ld, r, g)), lane0 + g * 4, lanes, y);
     }
+  }
+  template <int B, uint32_t H>
+  __device__ __forceinline__ void item(uint32_t pb, uint32_t g, int32_t (&x)[1 << B][4]) {
+    if (whole_vector<4>(lane0 + g * 4, lanes, vec)) rows<B, H, true>(pb, g, x);
+    else rows<B, H, false>(pb, g, x);
   }
 };
 
@@ -124,7 +134,7 @@ struct GStore {
 // order N = 2^logN, e taken mod N.
 __device__ __forceinline__ uint32_t tw4(const FourStepArgs& a, bool inv, uint32_t e, int logN) {
   const uint32_t idx = (e & ((1u << logN) - 1)) << (16 - logN);
-  return inv ? a.twi[idx] : a.tw[idx];
+  return inv ? gptr(a.twi)[idx] : gptr(a.tw)[idx];
 }
 
 // ------------------------------------------------------------------ kernels
@@ -139,9 +149,9 @@ __global__ void __launch_bounds__(kNT) k4_dec1(FourStepArgs a) {
   const uint32_t i1 = wk.sub, N1 = a.n >> LA;
   auto rowf = [&](uint32_t i2, uint32_t& w) -> uint64_t {
     const uint32_t z = i1 + N1 * i2;
-    w = a.wfull[z];
+    w = gptr(a.wfull)[z];
     if (!w) return ~0ull;
-    return a.full ? z : a.ridx[z];
+    return a.full ? z : gptr(a.ridx)[z];
   };
   auto destf = [&](uint32_t m2, uint32_t& w) -> uint64_t {
     w = tw4(a, true, i1 * m2, a.logn);
@@ -218,7 +228,7 @@ struct AhatStore {
   __device__ __forceinline__ void item(uint32_t pb, uint32_t g, int32_t (&x)[1 << B][4]) {
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c) {
-      const uint32_t h = ahat[m2p + rows2 * (pb + c * H)];
+      const uint32_t h = gptr(ahat)[m2p + rows2 * (pb + c * H)];
 #pragma unroll
       for (int v = 0; v < 4; ++v) x[c][v] = ct::mulc(ct::canon(x[c][v]), h);
     }

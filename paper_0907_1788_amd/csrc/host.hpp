@@ -124,9 +124,22 @@ struct CtTables {
   const CtDecLaunch* dec;
   const CtEncTabLaunch* enc_tab;
   const CtDecTabLaunch* dec_tab;
+  const CtDecPipeLaunch* dec_pipe;
   const CtTabOccupancy* occ;
 };
 const CtTables& ct_tables();
+
+// Resident workgroups per CU of a persistent kernel (cached per context);
+// op 0/1 = encode/decode table kernel, 2 = pipelined decode kernel;
+// 0 = not available.
+int kernel_occupancy(fntrs_ctx* c, int op, int L, int D, CtCfg cfg);
+
+// One encode / decode over `items` work items of the single job `a` with the
+// compile-time kernels of size 2^L: the pipelined persistent kernel when the
+// configuration has one, else one workgroup per work item.
+hipError_t launch_ct_encode(fntrs_ctx* c, int L, CtCfg cfg, const EncodeArgs& a, uint64_t items, hipStream_t s);
+hipError_t launch_ct_decode(fntrs_ctx* c, int L, CtCfg cfg, int D, const DecodeArgs& a, uint64_t items,
+                            hipStream_t s);
 
 // Argument checks of one encode / decode call (the rules of fntrs_encode and
 // fntrs_decode); FNTRS_OK or an error code with the message set.

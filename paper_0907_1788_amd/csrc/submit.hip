@@ -30,6 +30,7 @@ struct ClassLaunch {
   uint32_t njobs = 0, total = 0, grid = 0;
   uint64_t work = 0;   // butterflies, to balance the streams
   int stream = 0;      // 0 = the caller's stream, b > 0 = side stream b-1
+  bool pipe = false;   // pipelined persistent kernel (else the table kernel)
 };
 
 struct SingleJob {
@@ -55,15 +56,6 @@ struct Plan {
   std::vector<fntrs_locator_t*> locs;     // distinct locators the batch reads
   int streams = 0;                        // streams the plan spreads over
 };
-
-int occupancy(fntrs_ctx* c, int op, int L, int D, CtCfg cfg) {
-  const auto key = std::make_tuple(op, L, D, cfg.T, cfg.NT);
-  auto it = c->occ.find(key);
-  if (it != c->occ.end()) return it->second;
-  const int o = ct_tables().occ[L](cfg, op, D);
-  c->occ[key] = o;
-  return o;
-}
 
 // Checks every job, groups them into classes and lays out the job tables.
 int make_plan(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, Plan& P) {
@@ -226,7 +218,12 @@ int make_plan(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, Plan& P) {
     }
     start[js.size()] = (uint32_t)total;
     cl.total = (uint32_t)total;
-    const int occ = c->device == FNTRS_HOST_ONLY ? 1 : occupancy(c, cl.op, cl.L, cl.D, cl.cfg);
+    int occ = 1;
+    if (c->device != FNTRS_HOST_ONLY) {
+      occ = cl.op == 1 ? kernel_occupancy(c, 2, cl.L, cl.D, cl.cfg) : 0;   // pipelined decoder first
+      cl.pipe = occ > 0;
+      if (!cl.pipe) occ = kernel_occupancy(c, cl.op, cl.L, cl.D, cl.cfg);
+    }
     if (occ <= 0)
       return fail(c, FNTRS_E_DEVICE, "no occupancy for the %s kernel of size 2^%d (T=%d, NT=%d)",
                   cl.op ? "decode" : "encode", cl.L, cl.cfg.T, cl.cfg.NT);
@@ -306,7 +303,8 @@ int run_plan(fntrs_ctx* c, const Plan& P, const uint8_t* dblob, uint32_t* scratc
     } else {
       JobTable<DecodeArgs> t{reinterpret_cast<const DecodeArgs*>(dblob + cl.jobs_off),
                              reinterpret_cast<const uint32_t*>(dblob + cl.start_off), cl.njobs, cl.total};
-      HIP_TRY(c, ct_tables().dec_tab[cl.L](cl.cfg, cl.D, t, c->tw, c->twi, cl.grid, st));
+      if (cl.pipe) HIP_TRY(c, ct_tables().dec_pipe[cl.L](cl.cfg, cl.D, t, DecodeArgs{}, c->tw, c->twi, cl.grid, st));
+      else HIP_TRY(c, ct_tables().dec_tab[cl.L](cl.cfg, cl.D, t, c->tw, c->twi, cl.grid, st));
     }
   }
   for (const SingleJob& sj : P.singles) {
@@ -531,7 +529,7 @@ int fntrs_autotune(fntrs_ctx* c, uint32_t op, uint32_t n, uint32_t k, uint32_t l
         a.logn = ilog2(n); a.logK = L;
         a.tiles = (lanes + cfg.T - 1) / cfg.T; a.cosets = n >> L;
         a.vec = aligned16(in, lanes, a.stride_src) && aligned16(out, lanes, a.stride_dst);
-        return ct_tables().enc[L](cfg, a, a.tiles * a.cosets * batch, s);
+        return launch_ct_encode(c, L, cfg, a, (uint64_t)a.tiles * a.cosets * batch, s);
       }
       DecodeArgs a{};
       a.recv = in; a.ld_recv = lanes; a.stride_recv = (size_t)k * lanes;
@@ -541,7 +539,7 @@ int fntrs_autotune(fntrs_ctx* c, uint32_t op, uint32_t n, uint32_t k, uint32_t l
       a.tiles = (lanes + cfg.T - 1) / cfg.T;
       a.vec = aligned16(in, lanes, a.stride_recv) && aligned16(out, lanes, a.stride_dst);
       const int D = (k == n) ? -1 : loc->logn - loc->logm;
-      return ct_tables().dec[L](cfg, D, a, a.tiles * batch, s);
+      return launch_ct_decode(c, L, cfg, D, a, (uint64_t)a.tiles * batch, s);
     };
     HIP_TRY(c, launch());   // warm-up (first launch loads the code object)
     HIP_TRY(c, hipEventRecord(e0, s));
