@@ -82,6 +82,7 @@ struct DecodeArgs {
   int logn, logk;
   uint32_t full;            // recv holds n rows indexed by position
   uint32_t tiles, vec;
+  uint32_t row0;            // a received row of recv: erased positions read it and discard the value
 };
 
 // Work table of the batched path: the jobs of one class (one transform size,

@@ -277,7 +277,7 @@ struct DecLoad {
   const uint32_t* wfull;
   const uint32_t* ridx;
   uint64_t ld;
-  uint32_t lane0, lanes;
+  uint32_t lane0, lanes, row0;
   bool full, vec;
   template <int B>
   __device__ __forceinline__ void consts(uint32_t base, uint32_t (&wv)[1 << B], uint32_t (&rv)[1 << B]) {
@@ -287,8 +287,9 @@ struct DecLoad {
       const uint32_t z = zb | (bitrev((uint32_t)c, B) << (L - B));
       const uint32_t w = gptr(wfull)[z];
       wv[c] = w;
-      // an erased position reads a row that exists (finish zeroes it)
-      rv[c] = full ? z : (w ? gptr(ridx)[z] : 0u);
+      // an erased position reads a received row, which the tile reads
+      // anyway (no extra HBM traffic); finish zeroes it
+      rv[c] = w ? (full ? z : gptr(ridx)[z]) : row0;
     }
   }
   template <int B, bool WHOLE>
@@ -402,7 +403,7 @@ __device__ __forceinline__ void dec_item(const DecodeArgs& a, uint32_t item, uin
   const uint64_t blk = item / a.tiles;
   const uint32_t lane0 = tile * T;
   DecLoad<LN, V> lg{a.recv + blk * a.stride_recv + lane0, a.wfull, a.ridx, a.ld_recv, lane0, a.lanes,
-                    a.full != 0, a.vec != 0};
+                    a.row0, a.full != 0, a.vec != 0};
   LdsLoad<V, G> ll{lds};
   LdsStore<V, G, false> sl{lds};
   SourceStore<V> sg{a.dst + blk * a.stride_dst + lane0, a.ld_dst, a.k, lane0, a.lanes, a.vec != 0};
@@ -449,7 +450,8 @@ __device__ __forceinline__ DecLoad<LN, Geo<LN, TT, NT, VV>::V> dec_loader(const 
   constexpr int T = Geo<LN, TT, NT, VV>::T;
   const uint32_t lane0 = (item % a.tiles) * T;
   const uint64_t blk = item / a.tiles;
-  return {a.recv + blk * a.stride_recv + lane0, a.wfull, a.ridx, a.ld_recv, lane0, a.lanes, a.full != 0, a.vec != 0};
+  return {a.recv + blk * a.stride_recv + lane0, a.wfull, a.ridx, a.ld_recv, lane0, a.lanes, a.row0,
+          a.full != 0, a.vec != 0};
 }
 
 // Persistent decoder: a grid of resident size walks the work items (numbered

@@ -677,12 +677,13 @@ int fntrs_decode(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, uint32_
     HIP_TRY(c, e);
     return FNTRS_OK;
   }
-  DecodeArgs a;
+  DecodeArgs a{};
   a.recv = recv; a.ld_recv = ld_recv; a.stride_recv = stride_recv;
   a.dst = dst; a.ld_dst = ld_dst; a.stride_dst = stride_dst;
   a.tw = c->tw; a.twi = c->twi; a.wfull = L->wfull; a.ridx = L->ridx; a.ahat_br = L->ahat_br;
   a.n = n; a.k = k; a.lanes = lanes; a.logn = L->logn; a.logk = L->logk;
   a.full = full ? 1u : 0u;
+  a.row0 = full ? L->positions[0] : 0u;
   const int D = (k == n) ? -1 : L->logn - L->logm;
   const CtCfg cfg = c->dec_cfg[L->logn];
   a.vec = aligned16(recv, ld_recv, stride_recv) && aligned16(dst, ld_dst, stride_dst);

@@ -208,6 +208,7 @@ int make_plan(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, Plan& P) {
         a.tw = c->tw; a.twi = c->twi; a.wfull = L->wfull; a.ridx = L->ridx; a.ahat_br = L->ahat_br;
         a.n = L->n; a.k = L->k; a.lanes = J.lanes; a.logn = L->logn; a.logk = L->logk;
         a.full = (J.flags & FNTRS_RECV_FULL) ? 1u : 0u;
+        a.row0 = a.full ? L->positions[0] : 0u;
         a.tiles = tiles;
         a.vec = aligned16(J.in, J.ld_in, J.stride_in) && aligned16(J.out, J.ld_out, J.stride_out);
         std::memcpy(P.blob.data() + cl.jobs_off + i * sizeof(DecodeArgs), &a, sizeof a);
