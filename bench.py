@@ -468,11 +468,11 @@ def main():
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
         "phases_ms": {"encode": enc_avg, "locator": float(np.mean(loc_ms)), "decode": dec_avg},
         # dominant kernel: the decoder, bound by the integer vector ALUs
-        "roofline": {"bound": "alu", "kernel": "k_dec_pipe",
+        "roofline": {"bound": "alu", "kernel": "k_dec",
                      "achieved": round(dec_bfly / (dec_avg * 1e-3) / 1e12, 4),
                      "peak": round(ALU_PEAK_BFLY / 1e12, 4), "unit": "Tbutterfly/s",
                      "frac": round(dec_bfly / (dec_avg * 1e-3) / ALU_PEAK_BFLY, 4),
-                     "traffic": stored_traffic("k_dec_pipe", args.workload),
+                     "traffic": stored_traffic("k_dec", args.workload),
                      "algorithmic_hbm_bytes": dec_bytes,
                      "hbm_frac": round(dec_bytes / (dec_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "encode_roofline": {"bound": "alu", "kernel": "k_enc",

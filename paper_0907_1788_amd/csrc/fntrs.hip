@@ -438,7 +438,7 @@ int locators_acquire(fntrs_ctx* c, uint32_t count, const uint32_t* n_, const uin
 }
 
 // Default kernel configuration per transform size, then the FNTRS_TILES
-// override "e12=8x512,d13=4x512v2,..." (tile lanes x threads, optional
+// override "e12=8x512,d13=4x1024,d13=4x512v2,..." (tile lanes x threads, optional
 // lanes per thread).
 void set_default_configs(fntrs_ctx* c) {
   for (int L = 1; L <= 15; ++L) {

@@ -228,7 +228,8 @@ def test_validation_with_device(ctx):
 # every lane-tile width instantiated for a size, forced through FNTRS_TILES
 TILE_CASES = [("e12=4x512", 4096, 4096, 40), ("e12=8x1024", 8192, 4096, 24), ("e11=16x512", 2048, 1024, 33),
               ("d12=8x512", 4096, 2048, 40), ("d13=4x1024", 8192, 4096, 9), ("d13=2x512", 8192, 4096, 6),
-              ("d13=2x512", 8192, 2048, 6), ("d13=4x1024", 8192, 8192, 5), ("d13=4x512v2", 8192, 4096, 10),
+              ("d13=2x512", 8192, 2048, 6), ("d13=4x1024", 8192, 8192, 5), ("d13=4x512", 8192, 4096, 10),
+              ("d13=4x512", 8192, 2048, 7), ("d13=4x512", 8192, 8192, 3), ("d13=4x512v2", 8192, 4096, 10),
               ("d13=4x512v2", 8192, 2048, 7), ("d13=4x512v2", 8192, 8192, 5)]
 
 
@@ -246,6 +247,13 @@ def test_tile_variants(spec, n, k, lanes, monkeypatch):
         z = pattern("random" if k < n else "all", n, k, 7001 + n)
         loc = c.locator(n, k, z)
         got = gpu_decode(c, loc, out[:, z, :])
+        assert np.array_equal(got, src.astype(np.int64))
+        # the same decode reading the received rows out of the full codeword
+        # (erased rows hold garbage; they must not matter)
+        full = out.copy()
+        erased = np.setdiff1d(np.arange(n), z)
+        full[:, erased, :] = synth.residues(7002 + n, (2, erased.size, lanes)) if erased.size else 0
+        got = gpu_decode(c, loc, full, fntrs.FNTRS_RECV_FULL)
         assert np.array_equal(got, src.astype(np.int64))
         loc.release()
     finally:
