@@ -51,11 +51,25 @@ struct Geo {
   // (the decoder's size-2^(L-1) transforms start with their own first pass)
   static constexpr int LO = (L > 1 && plan_b(L - 1, BM, 0) < plan_b(L, BM, 0) ? plan_b(L - 1, BM, 0)
                                                                                 : plan_b(L, BM, 0)) + 1;
-  static constexpr uint32_t WORDS_ALL = TwLds<L, LO, L>::words();
-  static constexpr uint32_t WORDS_TOP2 = TwLds<L, LO, L - 2>::words();
-  static constexpr int TOP = TILE_BYTES + WORDS_ALL * 4 <= 163840 ? L : L - 2;
-  static constexpr bool TW_LDS = TILE_BYTES + (TOP == L ? WORDS_ALL : WORDS_TOP2) * 4 <= 163840 && LO <= L;
-  static constexpr uint32_t LDS_BYTES = TILE_BYTES + (TW_LDS ? (TOP == L ? WORDS_ALL : WORDS_TOP2) * 4 : 0);
+  // Stages up to TOP get their own tables, the stages above read the stage-L
+  // table at a stride.  TOP is the highest stage whose tables still let as
+  // many workgroups share a CU's LDS as the smallest tables would (strided
+  // reads of the small low-stage tables would conflict on LDS banks, so
+  // those keep their own tables whenever that costs no occupancy).
+  static constexpr uint32_t kLds = 163840;
+  static constexpr uint32_t words_at(int top) {
+    return TwLds<L, LO, L>::off(top + 1) + (top < L ? (1u << (L - 1)) + 1 : 0);
+  }
+  static constexpr uint32_t wgs(int top) { return kLds / (TILE_BYTES + words_at(top) * 4); }
+  static constexpr int pick_top() {
+    int t = L;
+    while (t >= LO && wgs(t) < wgs(LO - 1)) --t;
+    return t < LO - 1 ? LO - 1 : t;
+  }
+  static constexpr int TOP = LO <= L ? pick_top() : L;
+  static constexpr uint32_t WORDS = TwLds<L, LO, TOP>::words();
+  static constexpr bool TW_LDS = LO <= L && TILE_BYTES + WORDS * 4 <= kLds;
+  static constexpr uint32_t LDS_BYTES = TILE_BYTES + (TW_LDS ? WORDS * 4 : 0);
   using TwType = typename std::conditional<TW_LDS, TwLds<L, LO, TOP>, TwGlobal>::type;
 };
 
