@@ -63,6 +63,10 @@ __device__ __forceinline__ void zero_item(int32_t (&x)[V]) {
 // Generic global loader for the first DIT pass: position p of the size-2^L
 // sub-transform holds input index i = bitrev(p); `row(i)` gives the row to
 // read (or ~0u for a zero), `scale(i)` a per-row multiplier (0 = none).
+// The reads of an item go out in three rounds -- the row descriptors (which
+// may themselves be reads), then every row with no branch (a zero position
+// reads row 0, which exists in every input, and is discarded), then the
+// scaling -- so each round waits once for the whole item.
 template <int L, class RowFn>
 struct GLoad {
   const uint32_t* base;   // block base + lane0
@@ -72,21 +76,22 @@ struct GLoad {
   RowFn rowf;
   template <int B, bool WHOLE>
   __device__ __forceinline__ void rows(uint32_t ib, uint32_t g, int32_t (&x)[1 << B][4]) {
+    uint64_t r[1 << B];
+    uint32_t w[1 << B];
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c) {
       const uint32_t i = ib | (bitrev((uint32_t)c, B) << (L - B));
-      uint32_t w = 0;
-      const uint64_t r = rowf(i, w);
-      if (r == ~0ull) {
+      w[c] = 0;
+      r[c] = rowf(i, w[c]);
+    }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) x[c][v] = 0;
-      } else {
-        ct::load_lanes<4, WHOLE>(rowp(base, ld, r, g), lane0 + g * 4, lanes, x[c]);
-        if (w) {
+    for (int c = 0; c < (1 << B); ++c)
+      ct::load_lanes<4, WHOLE>(rowp(base, ld, r[c] == ~0ull ? 0 : r[c], g), lane0 + g * 4, lanes, x[c]);
 #pragma unroll
-          for (int v = 0; v < 4; ++v) x[c][v] = ct::mulc((uint32_t)x[c][v], w);
-        }
-      }
+    for (int c = 0; c < (1 << B); ++c) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        x[c][v] = r[c] == ~0ull ? 0 : (w[c] ? (int32_t)ct::mulc((uint32_t)x[c][v], w[c]) : x[c][v]);
     }
   }
   template <int B, uint32_t H>
@@ -100,7 +105,9 @@ struct GLoad {
 
 // Generic global storer: position p holds output index m = p (natural, DIT)
 // or m = bitrev(p) (DIF, REV); `dest(m, w)` gives the row (or ~0 to drop) and
-// a multiplier w (0 = none) applied before the store.
+// a multiplier w (0 = none) applied before the store.  The multipliers of an
+// item (table reads) are all read before its first store: a read placed after
+// a store could not be moved above it, and would wait on every row.
 template <int L, bool REV, class DestFn>
 struct GStore {
   uint32_t* base;
@@ -110,17 +117,21 @@ struct GStore {
   DestFn destf;
   template <int B, uint32_t H, bool WHOLE>
   __device__ __forceinline__ void rows(uint32_t pb, uint32_t g, int32_t (&x)[1 << B][4]) {
+    uint64_t r[1 << B];
+    uint32_t w[1 << B];
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c) {
       const uint32_t p = pb + c * H;
-      const uint32_t m = REV ? bitrev(p, L) : p;
-      uint32_t w = 0;
-      const uint64_t r = destf(m, w);
-      if (r == ~0ull) continue;
+      w[c] = 0;
+      r[c] = destf(REV ? bitrev(p, L) : p, w[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < (1 << B); ++c) {
+      if (r[c] == ~0ull) continue;
       int32_t y[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) y[v] = w ? ct::mulc(ct::canon(x[c][v]), w) : x[c][v];
-      ct::store_lanes<4, WHOLE>(const_cast<uint32_t*>(rowp(base, ld, r, g)), lane0 + g * 4, lanes, y);
+      for (int v = 0; v < 4; ++v) y[v] = w[c] ? ct::mulc(ct::canon(x[c][v]), w[c]) : x[c][v];
+      ct::store_lanes<4, WHOLE>(const_cast<uint32_t*>(rowp(base, ld, r[c], g)), lane0 + g * 4, lanes, y);
     }
   }
   template <int B, uint32_t H>
@@ -150,8 +161,8 @@ __global__ void __launch_bounds__(kNT) k4_dec1(FourStepArgs a) {
   auto rowf = [&](uint32_t i2, uint32_t& w) -> uint64_t {
     const uint32_t z = i1 + N1 * i2;
     w = gptr(a.wfull)[z];
-    if (!w) return ~0ull;
-    return a.full ? z : gptr(a.ridx)[z];
+    const uint32_t r = a.full ? z : gptr(a.ridx)[z];
+    return w ? (uint64_t)r : ~0ull;
   };
   auto destf = [&](uint32_t m2, uint32_t& w) -> uint64_t {
     w = tw4(a, true, i1 * m2, a.logn);
