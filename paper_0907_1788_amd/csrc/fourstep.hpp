@@ -25,9 +25,13 @@ namespace fs {
 
 constexpr int kT = 32;       // lanes per tile
 constexpr int kNT = 256;     // threads per workgroup
+// Two lanes per thread: a 256-point pass then has an item for every thread
+// (with four, half the threads would idle), and a ragged lane tail wastes
+// less of a vector.
+constexpr int kV = 2;
 
 template <int L>
-using Geo = ct::Geo<L, kT, kNT>;
+using Geo = ct::Geo<L, kT, kNT, kV>;
 
 // scratch row stride: every scratch buffer is [block][row][lane], ld = lanes
 // rounded up to the tile, rows = N.
@@ -51,7 +55,7 @@ __device__ __forceinline__ Work work_of(const FourStepArgs& a) {
 
 // Row r of a [block][row][lane] buffer, lane group g (V = 4 lanes).
 __device__ __forceinline__ const uint32_t* rowp(const uint32_t* p, uint64_t ld, uint64_t r, uint32_t g) {
-  return p + r * ld + g * 4;
+  return p + r * ld + g * kV;
 }
 
 template <int L, int V>
@@ -75,7 +79,7 @@ struct GLoad {
   bool vec;
   RowFn rowf;
   template <int B, bool WHOLE>
-  __device__ __forceinline__ void rows(uint32_t ib, uint32_t g, int32_t (&x)[1 << B][4]) {
+  __device__ __forceinline__ void rows(uint32_t ib, uint32_t g, int32_t (&x)[1 << B][kV]) {
     uint64_t r[1 << B];
     uint32_t w[1 << B];
 #pragma unroll
@@ -86,19 +90,19 @@ struct GLoad {
     }
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c)
-      ct::load_lanes<4, WHOLE>(rowp(base, ld, r[c] == ~0ull ? 0 : r[c], g), lane0 + g * 4, lanes, x[c]);
+      ct::load_lanes<kV, WHOLE>(rowp(base, ld, r[c] == ~0ull ? 0 : r[c], g), lane0 + g * kV, lanes, x[c]);
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
+      for (int v = 0; v < kV; ++v)
         x[c][v] = r[c] == ~0ull ? 0 : (w[c] ? (int32_t)ct::mulc((uint32_t)x[c][v], w[c]) : x[c][v]);
     }
   }
   template <int B, uint32_t H>
-  __device__ __forceinline__ void item(uint32_t pb, uint32_t g, int32_t (&x)[1 << B][4]) {
+  __device__ __forceinline__ void item(uint32_t pb, uint32_t g, int32_t (&x)[1 << B][kV]) {
     static_assert(H == 1, "the first DIT pass has stride 1");
     const uint32_t ib = bitrev(pb, L);
-    if (whole_vector<4>(lane0 + g * 4, lanes, vec)) rows<B, true>(ib, g, x);
+    if (whole_vector<kV>(lane0 + g * kV, lanes, vec)) rows<B, true>(ib, g, x);
     else rows<B, false>(ib, g, x);
   }
 };
@@ -116,7 +120,7 @@ struct GStore {
   bool vec;
   DestFn destf;
   template <int B, uint32_t H, bool WHOLE>
-  __device__ __forceinline__ void rows(uint32_t pb, uint32_t g, int32_t (&x)[1 << B][4]) {
+  __device__ __forceinline__ void rows(uint32_t pb, uint32_t g, int32_t (&x)[1 << B][kV]) {
     uint64_t r[1 << B];
     uint32_t w[1 << B];
 #pragma unroll
@@ -128,15 +132,15 @@ struct GStore {
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c) {
       if (r[c] == ~0ull) continue;
-      int32_t y[4];
+      int32_t y[kV];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) y[v] = w[c] ? ct::mulc(ct::canon(x[c][v]), w[c]) : x[c][v];
-      ct::store_lanes<4, WHOLE>(const_cast<uint32_t*>(rowp(base, ld, r[c], g)), lane0 + g * 4, lanes, y);
+      for (int v = 0; v < kV; ++v) y[v] = w[c] ? ct::mulc(ct::canon(x[c][v]), w[c]) : x[c][v];
+      ct::store_lanes<kV, WHOLE>(const_cast<uint32_t*>(rowp(base, ld, r[c], g)), lane0 + g * kV, lanes, y);
     }
   }
   template <int B, uint32_t H>
-  __device__ __forceinline__ void item(uint32_t pb, uint32_t g, int32_t (&x)[1 << B][4]) {
-    if (whole_vector<4>(lane0 + g * 4, lanes, vec)) rows<B, H, true>(pb, g, x);
+  __device__ __forceinline__ void item(uint32_t pb, uint32_t g, int32_t (&x)[1 << B][kV]) {
+    if (whole_vector<kV>(lane0 + g * kV, lanes, vec)) rows<B, H, true>(pb, g, x);
     else rows<B, H, false>(pb, g, x);
   }
 };
@@ -169,13 +173,13 @@ __global__ void __launch_bounds__(kNT) k4_dec1(FourStepArgs a) {
     return (uint64_t)i1 * (1u << LA) + m2;
   };
   GLoad<LA, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.lane0, a.ld_in, wk.lane0, a.lanes, a.vec != 0, rowf};
-  ct::LdsLoad<4, Gm::G> lm{lds};
-  ct::LdsStore<4, Gm::G, false> sm{lds};
+  ct::LdsLoad<kV, Gm::G> lm{lds};
+  ct::LdsStore<kV, Gm::G, false> sm{lds};
   GStore<LA, false, decltype(destf)> sl{a.out + wk.blk * a.stride_out + wk.lane0, a.ld_out, wk.lane0, a.lanes,
                                         a.vec != 0, destf};
   using TW = typename Gm::TwType;
   const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
-  ct::dit<LA, Gm::BM, 4, Gm::G, true>(tws, l0, lm, sm, sl);
+  ct::dit<LA, Gm::BM, kV, Gm::G, true>(tws, l0, lm, sm, sl);
 }
 
 // LDS storer that keeps index m only while index(m) < limit (else zero) and
@@ -185,14 +189,14 @@ struct MaskStore {
   uint32_t* lds;
   uint32_t m2, k;    // series index = m2 + 256 m
   template <int B, uint32_t H>
-  __device__ __forceinline__ void item(uint32_t pb, uint32_t g, int32_t (&x)[1 << B][4]) {
+  __device__ __forceinline__ void item(uint32_t pb, uint32_t g, int32_t (&x)[1 << B][kV]) {
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c) {
       const uint32_t m = pb + c * H;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) x[c][v] = (m2 + 256u * m < k) ? ct::fold1(x[c][v]) : 0;
+      for (int v = 0; v < kV; ++v) x[c][v] = (m2 + 256u * m < k) ? ct::fold1(x[c][v]) : 0;
     }
-    ct::lds_item_put<B, 4, G, H>(lds, pb, g, x);
+    ct::lds_item_put<B, kV, G, H>(lds, pb, g, x);
   }
 };
 
@@ -216,16 +220,16 @@ __global__ void __launch_bounds__(kNT) k4_dec2(FourStepArgs a) {
   };
   GLoad<LB1, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.lane0, a.ld_in, wk.lane0, a.lanes, a.vec != 0,
                                 rowf};
-  ct::LdsLoad<4, Gm::G> ll{lds};
-  ct::LdsStore<4, Gm::G, false> sl{lds};
-  ct::LdsStore<4, Gm::G, true> slf{lds};
+  ct::LdsLoad<kV, Gm::G> ll{lds};
+  ct::LdsStore<kV, Gm::G, false> sl{lds};
+  ct::LdsStore<kV, Gm::G, true> slf{lds};
   MaskStore<Gm::G> ms{lds, m2, a.k};
   GStore<LB2, true, decltype(destf)> sg{a.out + wk.blk * a.stride_out + wk.lane0, a.ld_out, wk.lane0, a.lanes,
                                         a.vec != 0, destf};
   using TW = typename Gm::TwType;
   const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
-  ct::dit<LB1, Gm::BM, 4, Gm::G, true>(tws, l0, ll, sl, ms);
-  ct::dif<LB2, Gm::BM, 4, Gm::G, false>(tws, ll, ll, slf, sg);
+  ct::dit<LB1, Gm::BM, kV, Gm::G, true>(tws, l0, ll, sl, ms);
+  ct::dif<LB2, Gm::BM, kV, Gm::G, false>(tws, ll, ll, slf, sg);
 }
 
 // LDS storer of the product: natural index m1' of FNT_M pass B with
@@ -236,14 +240,14 @@ struct AhatStore {
   const uint32_t* ahat;
   uint32_t m2p, rows2;   // rows2 = M / 256
   template <int B, uint32_t H>
-  __device__ __forceinline__ void item(uint32_t pb, uint32_t g, int32_t (&x)[1 << B][4]) {
+  __device__ __forceinline__ void item(uint32_t pb, uint32_t g, int32_t (&x)[1 << B][kV]) {
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c) {
       const uint32_t h = gptr(ahat)[m2p + rows2 * (pb + c * H)];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) x[c][v] = ct::mulc(ct::canon(x[c][v]), h);
+      for (int v = 0; v < kV; ++v) x[c][v] = ct::mulc(ct::canon(x[c][v]), h);
     }
-    ct::lds_item_put<B, 4, G, H>(lds, pb, g, x);
+    ct::lds_item_put<B, kV, G, H>(lds, pb, g, x);
   }
 };
 
@@ -264,16 +268,16 @@ __global__ void __launch_bounds__(kNT) k4_dec3(FourStepArgs a) {
     return (uint64_t)m2p * 256u + m2pp;
   };
   GLoad<8, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.lane0, a.ld_in, wk.lane0, a.lanes, a.vec != 0, rowf};
-  ct::LdsLoad<4, Gm::G> ll{lds};
-  ct::LdsStore<4, Gm::G, false> sl{lds};
-  ct::LdsStore<4, Gm::G, true> slf{lds};
+  ct::LdsLoad<kV, Gm::G> ll{lds};
+  ct::LdsStore<kV, Gm::G, false> sl{lds};
+  ct::LdsStore<kV, Gm::G, true> slf{lds};
   AhatStore<Gm::G> ah{lds, a.ahat, m2p, rows2};
   GStore<8, true, decltype(destf)> sg{a.out + wk.blk * a.stride_out + wk.lane0, a.ld_out, wk.lane0, a.lanes,
                                       a.vec != 0, destf};
   using TW = typename Gm::TwType;
   const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
-  ct::dit<8, Gm::BM, 4, Gm::G, false>(tws, l0, ll, sl, ah);
-  ct::dif<8, Gm::BM, 4, Gm::G, true>(tws, ll, ll, slf, sg);
+  ct::dit<8, Gm::BM, kV, Gm::G, false>(tws, l0, ll, sl, ah);
+  ct::dif<8, Gm::BM, kV, Gm::G, true>(tws, ll, ll, slf, sg);
 }
 
 // Decoder K4 / last pass of an inverse transform: size 2^LB over scratch rows
@@ -295,13 +299,13 @@ __global__ void __launch_bounds__(kNT) k4_dec4(FourStepArgs a) {
   };
   GLoad<LB, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.lane0, a.ld_in, wk.lane0, a.lanes, a.vec != 0,
                                rowf};
-  ct::LdsLoad<4, Gm::G> ll{lds};
-  ct::LdsStore<4, Gm::G, false> sl{lds};
+  ct::LdsLoad<kV, Gm::G> ll{lds};
+  ct::LdsStore<kV, Gm::G, false> sl{lds};
   GStore<LB, false, decltype(destf)> sg{a.out + wk.blk * a.stride_out + wk.lane0, a.ld_out, wk.lane0, a.lanes,
                                         a.vec != 0, destf};
   using TW = typename Gm::TwType;
   const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
-  ct::dit<LB, Gm::BM, 4, Gm::G, true>(tws, l0, ll, sl, sg);
+  ct::dit<LB, Gm::BM, kV, Gm::G, true>(tws, l0, ll, sl, sg);
 }
 
 // Encoder as one FNT_n of the zero-padded source, n = N1 * 256.  Pass A:
@@ -322,13 +326,13 @@ __global__ void __launch_bounds__(kNT) k4_enc1(FourStepArgs a) {
     return (uint64_t)i1 * 256u + m2;
   };
   GLoad<8, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.lane0, a.ld_in, wk.lane0, a.lanes, a.vec != 0, rowf};
-  ct::LdsLoad<4, Gm::G> lm{lds};
-  ct::LdsStore<4, Gm::G, false> sm{lds};
+  ct::LdsLoad<kV, Gm::G> lm{lds};
+  ct::LdsStore<kV, Gm::G, false> sm{lds};
   GStore<8, false, decltype(destf)> sl{a.out + wk.blk * a.stride_out + wk.lane0, a.ld_out, wk.lane0, a.lanes,
                                        a.vec != 0, destf};
   using TW = typename Gm::TwType;
   const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
-  ct::dit<8, Gm::BM, 4, Gm::G, false>(tws, l0, lm, sm, sl);
+  ct::dit<8, Gm::BM, kV, Gm::G, false>(tws, l0, lm, sm, sl);
 }
 
 // Encoder pass B (size N1 = 2^LB): scratch rows i1*256 + m2 (m2 = sub),
@@ -348,13 +352,13 @@ __global__ void __launch_bounds__(kNT) k4_enc2(FourStepArgs a) {
     return (uint64_t)m2 + 256u * m1;
   };
   GLoad<LB, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.lane0, a.ld_in, wk.lane0, a.lanes, a.vec != 0, rowf};
-  ct::LdsLoad<4, Gm::G> lm{lds};
-  ct::LdsStore<4, Gm::G, false> sm{lds};
+  ct::LdsLoad<kV, Gm::G> lm{lds};
+  ct::LdsStore<kV, Gm::G, false> sm{lds};
   GStore<LB, false, decltype(destf)> sl{a.out + wk.blk * a.stride_out + wk.lane0, a.ld_out, wk.lane0, a.lanes,
                                        a.vec != 0, destf};
   using TW = typename Gm::TwType;
   const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
-  ct::dit<LB, Gm::BM, 4, Gm::G, false>(tws, l0, lm, sm, sl);
+  ct::dit<LB, Gm::BM, kV, Gm::G, false>(tws, l0, lm, sm, sl);
 }
 
 }  // namespace fs
