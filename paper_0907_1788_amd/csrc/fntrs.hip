@@ -54,6 +54,50 @@ const CtTables& ct_tables() {
   return t;
 }
 
+int upload_async(fntrs_ctx* c, void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return FNTRS_OK;
+  constexpr size_t kMaxSlots = 32;
+  fntrs_ctx::StageSlot* slot = nullptr;
+  for (auto& q : c->stage) {   // an idle slot that is large enough
+    if (q.bytes >= bytes && (!q.pending || hipEventQuery(q.ev) == hipSuccess)) { slot = &q; break; }
+  }
+  if (!slot) {                 // else an idle slot to grow, or a new one
+    for (auto& q : c->stage)
+      if (!q.pending || hipEventQuery(q.ev) == hipSuccess) { slot = &q; break; }
+    if (!slot && c->stage.size() < kMaxSlots) {
+      c->stage.emplace_back();
+      slot = &c->stage.back();
+      HIP_TRY(c, hipEventCreateWithFlags(&slot->ev, hipEventDisableTiming));
+    }
+    if (!slot) {               // all busy: wait for the first
+      slot = &c->stage.front();
+      HIP_TRY(c, hipEventSynchronize(slot->ev));
+    }
+    if (slot->bytes < bytes) {
+      if (slot->p) HIP_TRY(c, hipHostFree(slot->p));
+      slot->p = nullptr;
+      slot->bytes = 0;
+      size_t sz = 65536;
+      while (sz < bytes) sz <<= 1;
+      HIP_TRY(c, hipHostMalloc(&slot->p, sz, hipHostMallocDefault));
+      slot->bytes = sz;
+    }
+  }
+  std::memcpy(slot->p, src, bytes);
+  HIP_TRY(c, hipMemcpyAsync(dst, slot->p, bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipEventRecord(slot->ev, s));
+  slot->pending = true;
+  return FNTRS_OK;
+}
+
+void stage_release(fntrs_ctx* c) {
+  for (auto& q : c->stage) {
+    if (q.p) (void)hipHostFree(q.p);
+    if (q.ev) (void)hipEventDestroy(q.ev);
+  }
+  c->stage.clear();
+}
+
 int kernel_occupancy(fntrs_ctx* c, int op, int L, int D, CtCfg cfg) {
   const auto key = std::make_tuple(op, L, D, cfg.T * 4096 + cfg.NT, cfg.V);
   auto it = c->occ.find(key);
@@ -317,8 +361,7 @@ static int build_locators(fntrs_ctx* c, std::vector<fntrs_locator_t*>& Ls, hipSt
     (void)hipFreeAsync(tmp, s);
     return rc;
   };
-  if (hipMemcpyAsync(tmp, img.data(), img.size(), hipMemcpyHostToDevice, s) != hipSuccess)
-    return fail_free(fail(c, FNTRS_E_DEVICE, "locator upload failed"));
+  if (int rc = upload_async(c, tmp, img.data(), img.size(), s)) return fail_free(rc);
   const LocDesc* D = reinterpret_cast<const LocDesc*>(tmp);
   auto launch_err = [&]() { return hipGetLastError(); };
   auto st_ptr = [&](const Stage& st) { return dtab + st.start_off; };
@@ -529,6 +572,7 @@ void fntrs_destroy(fntrs_ctx* c) {
   };
   for (auto& kv : c->sides) drop(kv.second);
   drop(c->capture_side);
+  stage_release(c);
   if (c->tw) (void)hipFree(c->tw);
   delete c;
 }

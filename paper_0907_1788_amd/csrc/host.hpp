@@ -81,6 +81,16 @@ struct fntrs_ctx {
   SideSet capture_side;
   // occupancy of each table kernel
   std::map<std::tuple<int, int, int, int, int>, int> occ;
+  // pinned host staging for table uploads: a copy from pageable memory is
+  // synchronous and would keep the host from running ahead of the device.
+  // A slot is reused once the event recorded after its copy has fired.
+  struct StageSlot {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+  };
+  std::vector<StageSlot> stage;
 };
 
 namespace fntrs {
@@ -128,6 +138,13 @@ struct CtTables {
   const CtTabOccupancy* occ;
 };
 const CtTables& ct_tables();
+
+// Enqueues a host-to-device copy of `bytes` bytes of `src` on `s` through a
+// pinned staging slot (the host returns at once; the slot stays reserved
+// until the copy has run).
+int upload_async(fntrs_ctx* c, void* dst, const void* src, size_t bytes, hipStream_t s);
+// Frees the staging slots (the device must be idle).
+void stage_release(fntrs_ctx* c);
 
 // Resident workgroups per CU of a persistent kernel (cached per context);
 // op 0/1 = encode/decode table kernel, 2 = pipelined decode kernel;

@@ -72,30 +72,39 @@ __global__ void k_locb_prep(const LocDesc* __restrict__ D, const uint32_t* __res
   }
 }
 
-// Step 1, leaves of the product tree: workgroup g of a pattern multiplies the
-// G linear factors (x - x_i), i in [gG, gG+G), one factor at a time
-// (schoolbook; G <= 64).
+// Step 1, leaves of the product tree: workgroup g of a pattern builds the
+// product of the G linear factors (x - x_i), i in [gG, gG+G) (G <= 64), as
+// its own small product tree in LDS: round h pairs monic degree-h
+// polynomials a = x^h + a_lo, b = x^h + b_lo into
+//   a b = x^(2h) + x^h (a_lo + b_lo) + a_lo b_lo,
+// one output coefficient per thread (schoolbook, at most h terms), so the
+// G points are read in one round and the tree takes log2(G) barriers.
 __global__ void __launch_bounds__(64) k_locb_leaves(const LocDesc* __restrict__ D, const uint32_t* __restrict__ start,
                                                     uint32_t count, const uint32_t* __restrict__ tw) {
-  __shared__ uint32_t c[2][66];
+  __shared__ uint32_t c[2][64];
   const uint32_t i = loc_find(start, count, blockIdx.x);
   const LocDesc& d = D[i];
   const uint32_t g = blockIdx.x - start[i];
   const int G = (int)d.G;
-  for (int j = threadIdx.x; j < 66; j += blockDim.x) { c[0][j] = (j == 0); c[1][j] = 0; }
+  const int t = (int)threadIdx.x;
+  // the leaves: monic degree 1, low coefficient -x_i
+  if (t < G) c[0][t] = fsub(0u, point_of(tw, d.zin[g * G + t], d.logn));
   __syncthreads();
   int cur = 0;
-  for (int q = 0; q < G; ++q) {
-    const uint32_t x = point_of(tw, d.zin[g * G + q], d.logn);
-    // (sum_j c_j x^j)(x - x_q): new_j = c_(j-1) - x_q c_j, degree q -> q+1
-    for (int j = threadIdx.x; j <= q + 1; j += blockDim.x) {
-      const uint32_t lo = j ? c[cur][j - 1] : 0u;
-      c[cur ^ 1][j] = fsub(lo, fmul(x, c[cur][j]));
+  for (int h = 1; h < G; h <<= 1) {
+    if (t < G) {
+      const uint32_t* a = &c[cur][(t / (2 * h)) * 2 * h];
+      const uint32_t* b = a + h;
+      const int j = t % (2 * h);
+      uint32_t acc = j >= h ? fadd(a[j - h], b[j - h]) : 0u;
+      const int lo = j - h + 1 > 0 ? j - h + 1 : 0, hi = j < h - 1 ? j : h - 1;
+      for (int s2 = lo; s2 <= hi; ++s2) acc = fadd(acc, fmul(a[s2], b[j - s2]));
+      c[cur ^ 1][t] = acc;
     }
     __syncthreads();
     cur ^= 1;
   }
-  for (int j = threadIdx.x; j < G; j += blockDim.x) d.t0[g * G + j] = c[cur][j];
+  if (t < G) d.t0[g * G + t] = c[cur][t];
 }
 
 // Step 1, level `lev` of the product tree (degree d = G 2^lev): pair p of a

@@ -367,8 +367,10 @@ int fntrs_submit(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, void* stre
   if (bytes) {
     hipError_t e = hipMallocAsync((void**)&mem, bytes, s);
     if (e != hipSuccess) return fail(c, FNTRS_E_NOMEM, "batch workspace of %zu bytes: %s", bytes, hipGetErrorString(e));
-    // pageable source: the runtime stages it before returning
-    if (!P.blob.empty()) HIP_TRY(c, hipMemcpyAsync(mem, P.blob.data(), P.blob.size(), hipMemcpyHostToDevice, s));
+    if (int rc = upload_async(c, mem, P.blob.data(), P.blob.size(), s)) {
+      (void)hipFreeAsync(mem, s);
+      return rc;
+    }
   }
   const int rc = run_plan(c, P, mem, reinterpret_cast<uint32_t*>(mem + blob), s, c->sides[s]);
   if (mem) (void)hipFreeAsync(mem, s);
