@@ -230,7 +230,8 @@ TILE_CASES = [("e12=4x512v2", 4096, 4096, 40), ("e12=8x1024", 8192, 4096, 24), (
               ("d12=8x512", 4096, 2048, 40), ("d13=4x1024", 8192, 4096, 9), ("d13=2x512", 8192, 4096, 6),
               ("d13=2x512", 8192, 2048, 6), ("d13=4x1024", 8192, 8192, 5), ("d13=4x512", 8192, 4096, 10),
               ("d13=4x512", 8192, 2048, 7), ("d13=4x512", 8192, 8192, 3), ("d13=4x512v2", 8192, 4096, 10),
-              ("d13=4x512v2", 8192, 2048, 7), ("d13=4x512v2", 8192, 8192, 5)]
+              ("d13=4x512v2", 8192, 2048, 7), ("d13=4x512v2", 8192, 8192, 5), ("d12=8x512", 4096, 4096, 11),
+              ("e12=8x1024v2", 8192, 4096, 19), ("d12=4x512", 4096, 1024, 9)]
 
 
 @pytest.mark.parametrize("spec,n,k,lanes", TILE_CASES)
