@@ -27,7 +27,7 @@ constexpr CtVariants ct_variants(int L) {
     case 10: return {{{16, 512}, {32, 512}}, {{16, 512}, {32, 512}}};
     case 11: return {{{8, 512}, {16, 512}}, {{8, 512}, {16, 512}}};
     case 12: return {{{8, 512}, {8, 1024}, {4, 512, 2}, {8, 1024, 2}}, {{8, 1024, 2}, {8, 512}, {4, 512}, {8, 1024}}};
-    case 13: return {{{4, 1024}, {4, 512}}, {{4, 1024}, {4, 512}, {4, 512, 2}, {2, 512}}};
+    case 13: return {{{4, 1024}, {4, 512}}, {{4, 1024}, {4, 512}, {4, 512, 2}}};
     case 14: return {{{2, 512}}, {{2, 512}}};
     case 15: return {{{1, 512}}, {{1, 512}}};
     default: return {{{64, 512}, {128, 512}}, {{64, 512}, {128, 512}}};   // L <= 8

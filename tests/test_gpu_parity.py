@@ -227,8 +227,8 @@ def test_validation_with_device(ctx):
 
 # every lane-tile width instantiated for a size, forced through FNTRS_TILES
 TILE_CASES = [("e12=4x512v2", 4096, 4096, 40), ("e12=8x1024", 8192, 4096, 24), ("e11=16x512", 2048, 1024, 33),
-              ("d12=8x512", 4096, 2048, 40), ("d13=4x1024", 8192, 4096, 9), ("d13=2x512", 8192, 4096, 6),
-              ("d13=2x512", 8192, 2048, 6), ("d13=4x1024", 8192, 8192, 5), ("d13=4x512", 8192, 4096, 10),
+              ("d12=8x512", 4096, 2048, 40), ("d13=4x1024", 8192, 4096, 9), ("d13=4x512v2", 8192, 4096, 6),
+              ("d13=4x1024", 8192, 2048, 6), ("d13=4x1024", 8192, 8192, 5), ("d13=4x512", 8192, 4096, 10),
               ("d13=4x512", 8192, 2048, 7), ("d13=4x512", 8192, 8192, 3), ("d13=4x512v2", 8192, 4096, 10),
               ("d13=4x512v2", 8192, 2048, 7), ("d13=4x512v2", 8192, 8192, 5), ("d12=8x512", 4096, 4096, 11),
               ("e12=8x1024v2", 8192, 4096, 19), ("d12=4x512", 4096, 1024, 9)]
