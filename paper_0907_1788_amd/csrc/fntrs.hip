@@ -177,6 +177,48 @@ hipError_t set_lds_attr(const void* fn, size_t bytes) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// One launch of a locator stage on the one-lane ct kernels (transform size
+// 2^L, L >= kLocCtMin).
+template <int L>
+void launch_level_ct(uint32_t grid, const LocDesc* D, const uint32_t* start, uint32_t count, int lev,
+                     const uint32_t* tw, const uint32_t* twi, hipStream_t s) {
+  constexpr size_t lds = LocGeo<L>::LDS_BYTES;
+  (void)set_lds_attr((const void*)k_locb_level_ct<L>, lds);
+  hipLaunchKernelGGL(k_locb_level_ct<L>, dim3(grid), dim3(loc_nt<L>()), lds, s, D, start, count, lev, tw, twi);
+}
+template <int L>
+void launch_eval_ct(uint32_t grid, const LocDesc* D, const uint32_t* start, uint32_t count, const uint32_t* tw,
+                    const uint32_t* twi, hipStream_t s) {
+  constexpr size_t lds = LocGeo<L>::LDS_BYTES;
+  (void)set_lds_attr((const void*)k_locb_eval_ct<L>, lds);
+  hipLaunchKernelGGL(k_locb_eval_ct<L>, dim3(grid), dim3(loc_nt<L>()), lds, s, D, start, count, tw, twi);
+}
+// false when L has no one-lane ct kernel (the caller uses the radix-4 one)
+bool level_ct(int L, uint32_t grid, const LocDesc* D, const uint32_t* start, uint32_t count, int lev,
+              const uint32_t* tw, const uint32_t* twi, hipStream_t s) {
+  if (L < kLocCtMin) return false;
+  switch (L) {
+    case 11: launch_level_ct<11>(grid, D, start, count, lev, tw, twi, s); return true;
+    case 12: launch_level_ct<12>(grid, D, start, count, lev, tw, twi, s); return true;
+    case 13: launch_level_ct<13>(grid, D, start, count, lev, tw, twi, s); return true;
+    case 14: launch_level_ct<14>(grid, D, start, count, lev, tw, twi, s); return true;
+    case 15: launch_level_ct<15>(grid, D, start, count, lev, tw, twi, s); return true;
+    default: return false;
+  }
+}
+bool eval_ct(int L, uint32_t grid, const LocDesc* D, const uint32_t* start, uint32_t count, const uint32_t* tw,
+             const uint32_t* twi, hipStream_t s) {
+  if (L < kLocCtMin) return false;
+  switch (L) {
+    case 11: launch_eval_ct<11>(grid, D, start, count, tw, twi, s); return true;
+    case 12: launch_eval_ct<12>(grid, D, start, count, tw, twi, s); return true;
+    case 13: launch_eval_ct<13>(grid, D, start, count, tw, twi, s); return true;
+    case 14: launch_eval_ct<14>(grid, D, start, count, tw, twi, s); return true;
+    case 15: launch_eval_ct<15>(grid, D, start, count, tw, twi, s); return true;
+    default: return false;
+  }
+}
+
 }  // namespace
 
 int validate_range(fntrs_ctx* c, const uint32_t* p, uint32_t batch, size_t stride, uint32_t rows,
@@ -373,14 +415,19 @@ static int build_locators(fntrs_ctx* c, std::vector<fntrs_locator_t*>& Ls, hipSt
       const int logd = levels[j].first;
       const Stage& st = levels[j].second;
       const uint32_t d = 1u << logd;
-      const size_t lds = 2ull * d * 4;
-      (void)set_lds_attr((const void*)k_locb_level, lds);
-      const int nt = (int)std::min<uint32_t>(1024, std::max<uint32_t>(64, d / 2));
-      hipLaunchKernelGGL(k_locb_level, dim3(st.total), dim3(nt), lds, s, D + st.r.first, st_ptr(st), st.r.count, logd,
-                         (int)j, tw);
+      if (!level_ct(logd + 1, st.total, D + st.r.first, st_ptr(st), st.r.count, (int)j, tw, c->twi, s)) {
+        const size_t lds = 2ull * d * 4;
+        (void)set_lds_attr((const void*)k_locb_level, lds);
+        const int nt = (int)std::min<uint32_t>(1024, std::max<uint32_t>(64, d / 2));
+        hipLaunchKernelGGL(k_locb_level, dim3(st.total), dim3(nt), lds, s, D + st.r.first, st_ptr(st), st.r.count,
+                           logd, (int)j, tw);
+      }
     }
     hipLaunchKernelGGL(k_locb_derivative, dim3((deriv.total + 255) / 256), dim3(256), 0, s, D, st_ptr(deriv), Pn);
     for (auto& ev : evals) {
+      if (eval_ct(ev.first, ev.second.total, D + ev.second.r.first, st_ptr(ev.second), ev.second.r.count, tw, c->twi,
+                  s))
+        continue;
       const uint32_t K = 1u << ev.first;
       const size_t lds = (size_t)K * 4;
       (void)set_lds_attr((const void*)k_locb_eval, lds);

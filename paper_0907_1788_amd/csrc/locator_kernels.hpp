@@ -4,6 +4,7 @@
 // Polynomials here are monic; a degree-d polynomial is stored as its d low
 // coefficients (the leading 1 is implicit).
 #pragma once
+#include "ct_kernels.hpp"
 #include "lds_fnt.hpp"
 
 namespace fntrs {
@@ -129,23 +130,73 @@ __global__ void __launch_bounds__(1024) k_locb_level(const LocDesc* __restrict__
   const uint32_t* b = a + d;
   uint32_t* sp = dd.spec + (uint64_t)p * d2;
   const uint32_t inv2d = 65537u - (65536u >> logd >> 1);   // (2d)^-1 = -2^16/(2d)
-  for (uint32_t j = threadIdx.x; j < d2; j += blockDim.x) lds[j] = j < d ? a[j] : 0u;
-  __syncthreads();
-  lds_dif<1>(lds, 1, logd + 1, false, tw);
-  for (uint32_t j = threadIdx.x; j < d2; j += blockDim.x) {
-    sp[j] = lds[j];
-    lds[j] = j < d ? b[j] : 0u;
+  // The copies between global memory and LDS take kU words per thread at a
+  // time, global reads first (see lds_fnt.hpp).  Word j of a round is
+  // j0 + u*nt; the reads of words past the end are clamped to j0.
+  const uint32_t nt = blockDim.x;
+  for (uint32_t j0 = threadIdx.x; j0 < d2; j0 += kU * nt) {
+    uint32_t v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t j = j0 + u * nt;
+      v[u] = j < d ? gptr(a)[j] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (j0 + u * nt < d2) lds[j0 + u * nt] = v[u];
   }
   __syncthreads();
   lds_dif<1>(lds, 1, logd + 1, false, tw);
-  for (uint32_t j = threadIdx.x; j < d2; j += blockDim.x) lds[j] = fmul(lds[j], sp[j]);
+  for (uint32_t j0 = threadIdx.x; j0 < d2; j0 += kU * nt) {
+    uint32_t v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t j = j0 + u * nt;
+      v[u] = j < d ? gptr(b)[j] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t j = j0 + u * nt;
+      if (j < d2) {
+        gptr(sp)[j] = lds[j];
+        lds[j] = v[u];
+      }
+    }
+  }
+  __syncthreads();
+  lds_dif<1>(lds, 1, logd + 1, false, tw);
+  for (uint32_t j0 = threadIdx.x; j0 < d2; j0 += kU * nt) {
+    uint32_t v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t j = j0 + u * nt;
+      v[u] = gptr(sp)[j < d2 ? j : j0];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t j = j0 + u * nt;
+      if (j < d2) lds[j] = fmul(lds[j], v[u]);
+    }
+  }
   __syncthreads();
   lds_dit<1>(lds, 1, logd + 1, true, tw);
   uint32_t* o = outp + (uint64_t)p * d2;
-  for (uint32_t j = threadIdx.x; j < d2; j += blockDim.x) {
-    uint32_t v = fmul(lds[j], inv2d);
-    if (j >= d) v = fadd(v, fadd(a[j - d], b[j - d]));
-    o[j] = v;
+  for (uint32_t j0 = threadIdx.x; j0 < d2; j0 += kU * nt) {
+    uint32_t hi[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t j = j0 + u * nt;
+      hi[u] = (j < d2 && j >= d) ? fadd(gptr(a)[j - d], gptr(b)[j - d]) : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t j = j0 + u * nt;
+      if (j < d2) {
+        uint32_t v = fmul(lds[j], inv2d);
+        if (j >= d) v = fadd(v, hi[u]);
+        gptr(o)[j] = v;
+      }
+    }
   }
 }
 
@@ -185,10 +236,20 @@ __global__ void __launch_bounds__(1024) k_locb_eval(const LocDesc* __restrict__ 
   const uint32_t cosets = N >> logK;
   const uint32_t* c = deriv ? d.spec : d.poly;
   uint32_t* vals = deriv ? d.vals : d.ahat;
-  for (uint32_t j = threadIdx.x; j < K; j += blockDim.x) {
-    uint32_t v = c[j];
-    if (t) v = fmul(v, tw[((t * j) & (N - 1)) << (16 - logN)]);
-    lds[bitrev(j, logK)] = v;
+  const uint32_t nt = blockDim.x;
+  for (uint32_t j0 = threadIdx.x; j0 < K; j0 += kU * nt) {   // global reads of kU words first
+    uint32_t v[kU], w[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t j = j0 + u * nt < K ? j0 + u * nt : j0;
+      v[u] = gptr(c)[j];
+      w[u] = gptr(tw)[((t * j) & (N - 1)) << (16 - logN)];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t j = j0 + u * nt;
+      if (j < K) lds[bitrev(j, logK)] = t ? fmul(v[u], w[u]) : v[u];
+    }
   }
   __syncthreads();
   lds_dit<1>(lds, 1, logK, false, tw);
@@ -227,6 +288,130 @@ __global__ void k_locb_ahat(const LocDesc* __restrict__ D, const uint32_t* __res
   const uint32_t v = fmul(d.ahat[q], inv);
   d.ahat_br[bitrev(q, d.logm)] = v;
   d.ahat_s[q] = v;
+}
+
+// ---------------------------------------------------------------- large
+// transforms of the locator on the lane-tile engine (ctfnt.hpp) with one
+// lane: radix-32 passes, one item per thread per pass (2^L / 32 threads,
+// 64..1024), in place of the radix-4 LDS loops above, for sizes 2^11 and up.
+constexpr int kLocCtMin = 11;
+
+template <int L>
+__host__ __device__ constexpr int loc_nt() {
+  return (1 << (L - 5)) < 64 ? 64 : ((1 << (L - 5)) > 1024 ? 1024 : (1 << (L - 5)));
+}
+template <int L>
+using LocGeo = ct::Geo<L, 1, loc_nt<L>(), 1>;
+
+// First DIF pass over a monic polynomial's d = 2^(L-1) low coefficients,
+// zero-padded to 2d: positions base + c*H with H = 2^(L-B); the upper half
+// of an item (c >= 2^(B-1)) is exactly the padding.
+struct PolyLoad {
+  const uint32_t* a;
+  template <int B, uint32_t H>
+  __device__ __forceinline__ void item(uint32_t base, uint32_t, int32_t (&x)[1 << B][1]) {
+#pragma unroll
+    for (int c = 0; c < (1 << B); ++c) x[c][0] = c < (1 << (B - 1)) ? (int32_t)gptr(a)[base + c * H] : 0;
+  }
+};
+
+// Last DIF pass of the first factor: its transform, canonical, parked in
+// global scratch at its LDS position (the second factor's last pass has the
+// same item layout, so each thread reads back what it wrote).
+struct ParkStore {
+  uint32_t* sp;
+  template <int B, uint32_t H>
+  __device__ __forceinline__ void item(uint32_t base, uint32_t, int32_t (&x)[1 << B][1]) {
+#pragma unroll
+    for (int c = 0; c < (1 << B); ++c) gptr(sp)[base + c * H] = ct::canon(x[c][0]);
+  }
+};
+
+// Last DIT pass of the product: coefficient m (natural) of a_lo b_lo times
+// (2d)^-1, plus a_(m-d) + b_(m-d) for m >= d (the c >= 2^(B-1) half).
+struct LevelOut {
+  uint32_t* o;
+  const uint32_t* a;
+  const uint32_t* b;
+  uint32_t inv2d;
+  template <int B, uint32_t H>
+  __device__ __forceinline__ void item(uint32_t base, uint32_t, int32_t (&x)[1 << B][1]) {
+    constexpr uint32_t D = H << (B - 1);
+    uint32_t hi[1 << B];
+#pragma unroll
+    for (int c = 0; c < (1 << B); ++c)
+      hi[c] = c < (1 << (B - 1)) ? 0u : fadd(gptr(a)[base + c * H - D], gptr(b)[base + c * H - D]);
+#pragma unroll
+    for (int c = 0; c < (1 << B); ++c)
+      gptr(o)[base + c * H] = fadd(ct::canon(ct::mulc(ct::canon(x[c][0]), inv2d)), hi[c]);
+  }
+};
+
+// k_locb_level for transforms of 2^L = 2d points: DIF of a_lo (parked), DIF
+// of b_lo times the parked transform (in LDS), DIT back to the coefficients.
+template <int L>
+__global__ void __launch_bounds__(loc_nt<L>()) k_locb_level_ct(const LocDesc* __restrict__ D,
+                                                             const uint32_t* __restrict__ start, uint32_t count,
+                                                             int lev, const uint32_t* tw, const uint32_t* twi) {
+  using Gm = LocGeo<L>;
+  using TW = typename Gm::TwType;
+  extern __shared__ uint32_t lds[];
+  const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, tw, twi);
+  __syncthreads();   // the first DIF pass reads the top stages' twiddles at once
+  const uint32_t i = loc_find(start, count, blockIdx.x);
+  const LocDesc& dd = D[i];
+  const uint32_t p = blockIdx.x - start[i];
+  constexpr uint32_t d = 1u << (L - 1), d2 = 2 * d;
+  const uint32_t* in = (lev & 1) ? dd.t1 : dd.t0;
+  uint32_t* outp = (lev & 1) ? dd.t0 : dd.t1;
+  const uint32_t* a = in + (uint64_t)(2 * p) * d;
+  const uint32_t* b = a + d;
+  uint32_t* sp = dd.spec + (uint64_t)p * d2;
+  ct::LdsLoad<1, 1> ll{lds};
+  ct::LdsStore<1, 1, false> sl{lds};
+  ct::LdsStore<1, 1, true> slf{lds};
+  PolyLoad la{a}, lb{b};
+  ParkStore park{sp};
+  ct::ProductStore<1, 1> prod{lds, sp};
+  LevelOut out{outp + (uint64_t)p * d2, a, b, 65537u - (65536u >> (L - 1) >> 1)};
+  ct::dif<L, Gm::BM, 1, 1, false>(tws, la, ll, slf, park);
+  ct::dif<L, Gm::BM, 1, 1, false>(tws, lb, ll, slf, prod);
+  ct::dit<L, Gm::BM, 1, 1, true>(tws, ll, ll, sl, out);
+}
+
+// k_locb_eval for K = 2^LK: the encoder's work item on a one-lane codeword
+// (the polynomial's K coefficients as K source rows, N = 2^logN points, one
+// workgroup per coset t of N / K).
+template <int LK>
+__global__ void __launch_bounds__(loc_nt<LK>()) k_locb_eval_ct(const LocDesc* __restrict__ D,
+                                                             const uint32_t* __restrict__ start, uint32_t count,
+                                                             const uint32_t* tw, const uint32_t* twi) {
+  using Gm = LocGeo<LK>;
+  using TW = typename Gm::TwType;
+  extern __shared__ uint32_t lds[];
+  const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, tw, twi);
+  const uint32_t i = loc_find(start, count, blockIdx.x);
+  const LocDesc& d = D[i];
+  uint32_t t = blockIdx.x - start[i];
+  const uint32_t ncos = d.n >> LK;
+  const bool deriv = t < ncos;
+  if (!deriv) t -= ncos;
+  const int logN = deriv ? d.logn : d.logm;
+  EncodeArgs e{};
+  e.src = deriv ? d.spec : d.poly;
+  e.ld_src = 1;
+  e.dst = deriv ? d.vals : d.ahat;
+  e.ld_dst = 1;
+  e.tw = tw;
+  e.twi = twi;
+  e.n = 1u << logN;
+  e.k = 1u << LK;
+  e.lanes = 1;
+  e.logn = logN;
+  e.logK = LK;
+  e.tiles = 1;
+  e.cosets = e.n >> LK;
+  ct::enc_item<LK, 1, loc_nt<LK>(), 1>(e, t, lds, tws);
 }
 
 // n = 1 (and k = 1): encoding and decoding both copy the single symbol.

@@ -142,6 +142,8 @@ DEC_CASES = [
     # four-step decoders at n = 2^14, 2^15: every product length, ragged lanes
     (16384, 8192, 37, 1, "random"), (16384, 2048, 5, 2, "random"), (32768, 8192, 33, 1, "first"),
     (32768, 4096, 3, 1, "random"), (16384, 16384, 9, 1, "all"),
+    # the largest locator: product-tree transforms of 2^15 points
+    (65536, 32768, 3, 1, "random"), (65536, 32768, 2, 1, "first"),
 ]
 
 
