@@ -96,6 +96,50 @@ void stage_release(fntrs_ctx* c) {
     if (q.ev) (void)hipEventDestroy(q.ev);
   }
   c->stage.clear();
+  for (auto& q : c->dev_slots) {
+    if (q.p) (void)hipFree(q.p);
+    if (q.ev) (void)hipEventDestroy(q.ev);
+  }
+  c->dev_slots.clear();
+}
+
+int dev_slot_acquire(fntrs_ctx* c, size_t bytes, fntrs_ctx::DevSlot*& out) {
+  constexpr size_t kMaxSlots = 8;
+  out = nullptr;
+  auto idle = [](fntrs_ctx::DevSlot& q) { return !q.pending || hipEventQuery(q.ev) == hipSuccess; };
+  for (auto& q : c->dev_slots)   // the smallest idle slot that fits
+    if (q.bytes >= bytes && idle(q) && (!out || q.bytes < out->bytes)) out = &q;
+  if (out) return FNTRS_OK;
+  fntrs_ctx::DevSlot* slot = nullptr;
+  if (c->dev_slots.size() < kMaxSlots) {
+    c->dev_slots.emplace_back();
+    slot = &c->dev_slots.back();
+    HIP_TRY(c, hipEventCreateWithFlags(&slot->ev, hipEventDisableTiming));
+  } else {                       // replace the smallest slot once it is idle
+    slot = &c->dev_slots.front();
+    for (auto& q : c->dev_slots)
+      if (q.bytes < slot->bytes) slot = &q;
+    if (slot->pending) HIP_TRY(c, hipEventSynchronize(slot->ev));
+    HIP_TRY(c, hipFree(slot->p));
+    slot->p = nullptr;
+    slot->bytes = 0;
+  }
+  size_t sz = size_t(1) << 20;
+  while (sz < bytes) sz <<= 1;
+  if (hipMalloc((void**)&slot->p, sz) != hipSuccess) {
+    slot->p = nullptr;
+    return fail(c, FNTRS_E_NOMEM, "device table buffer of %zu bytes", sz);
+  }
+  slot->bytes = sz;
+  slot->pending = false;
+  out = slot;
+  return FNTRS_OK;
+}
+
+int dev_slot_done(fntrs_ctx* c, fntrs_ctx::DevSlot* slot, hipStream_t s) {
+  HIP_TRY(c, hipEventRecord(slot->ev, s));
+  slot->pending = true;
+  return FNTRS_OK;
 }
 
 int kernel_occupancy(fntrs_ctx* c, int op, int L, int D, CtCfg cfg) {
@@ -178,7 +222,7 @@ hipError_t set_lds_attr(const void* fn, size_t bytes) {
 }
 
 // One launch of a locator stage on the one-lane ct kernels (transform size
-// 2^L, L >= kLocCtMin).
+// 2^L).
 template <int L>
 void launch_level_ct(uint32_t grid, const LocDesc* D, const uint32_t* start, uint32_t count, int lev,
                      const uint32_t* tw, const uint32_t* twi, hipStream_t s) {
@@ -196,9 +240,8 @@ void launch_eval_ct(uint32_t grid, const LocDesc* D, const uint32_t* start, uint
 // false when L has no one-lane ct kernel (the caller uses the radix-4 one)
 bool level_ct(int L, uint32_t grid, const LocDesc* D, const uint32_t* start, uint32_t count, int lev,
               const uint32_t* tw, const uint32_t* twi, hipStream_t s) {
-  if (L < kLocCtMin) return false;
+  if (L < kLocLevelCtMin) return false;
   switch (L) {
-    case 11: launch_level_ct<11>(grid, D, start, count, lev, tw, twi, s); return true;
     case 12: launch_level_ct<12>(grid, D, start, count, lev, tw, twi, s); return true;
     case 13: launch_level_ct<13>(grid, D, start, count, lev, tw, twi, s); return true;
     case 14: launch_level_ct<14>(grid, D, start, count, lev, tw, twi, s); return true;
@@ -208,7 +251,7 @@ bool level_ct(int L, uint32_t grid, const LocDesc* D, const uint32_t* start, uin
 }
 bool eval_ct(int L, uint32_t grid, const LocDesc* D, const uint32_t* start, uint32_t count, const uint32_t* tw,
              const uint32_t* twi, hipStream_t s) {
-  if (L < kLocCtMin) return false;
+  if (L < kLocEvalCtMin) return false;
   switch (L) {
     case 11: launch_eval_ct<11>(grid, D, start, count, tw, twi, s); return true;
     case 12: launch_eval_ct<12>(grid, D, start, count, tw, twi, s); return true;
@@ -378,9 +421,15 @@ static int build_locators(fntrs_ctx* c, std::vector<fntrs_locator_t*>& Ls, hipSt
   const size_t z_words = round_words(zall.size()), tab_words = round_words(tab.size());
   const size_t tmp_bytes = desc_bytes + (z_words + tab_words + scratch) * 4;
   uint8_t* tmp = nullptr;
-  hipError_t e = hipMallocAsync((void**)&tmp, tmp_bytes, s);
-  if (e != hipSuccess) return fail(c, FNTRS_E_NOMEM, "locator build buffer of %zu bytes: %s", tmp_bytes,
-                                   hipGetErrorString(e));
+  fntrs_ctx::DevSlot* slot = nullptr;
+  if (tmp_bytes <= kDevSlotMax) {
+    if (int rc = dev_slot_acquire(c, tmp_bytes, slot)) return rc;
+    tmp = slot->p;
+  } else {
+    hipError_t e = hipMallocAsync((void**)&tmp, tmp_bytes, s);
+    if (e != hipSuccess) return fail(c, FNTRS_E_NOMEM, "locator build buffer of %zu bytes: %s", tmp_bytes,
+                                     hipGetErrorString(e));
+  }
   uint32_t* dz = reinterpret_cast<uint32_t*>(tmp + desc_bytes);
   uint32_t* dtab = dz + z_words;
   uint32_t* dscr = dtab + tab_words;
@@ -399,8 +448,12 @@ static int build_locators(fntrs_ctx* c, std::vector<fntrs_locator_t*>& Ls, hipSt
   std::memcpy(img.data(), desc.data(), P * sizeof(LocDesc));
   std::memcpy(img.data() + desc_bytes, zall.data(), zall.size() * 4);
   std::memcpy(img.data() + desc_bytes + z_words * 4, tab.data(), tab.size() * 4);
+  auto release_tmp = [&]() {
+    if (slot) (void)dev_slot_done(c, slot, s);
+    else (void)hipFreeAsync(tmp, s);
+  };
   auto fail_free = [&](int rc) {
-    (void)hipFreeAsync(tmp, s);
+    release_tmp();
     return rc;
   };
   if (int rc = upload_async(c, tmp, img.data(), img.size(), s)) return fail_free(rc);
@@ -442,7 +495,7 @@ static int build_locators(fntrs_ctx* c, std::vector<fntrs_locator_t*>& Ls, hipSt
   if (hipError_t le = launch_err(); le != hipSuccess)
     return fail_free(fail(c, FNTRS_E_DEVICE, "locator kernels: %s", hipGetErrorString(le)));
   if (hipEventRecord(slab->ready, s) != hipSuccess) return fail_free(fail(c, FNTRS_E_DEVICE, "event record failed"));
-  (void)hipFreeAsync(tmp, s);
+  release_tmp();
   for (auto* L : Ls) c->used += L->bytes;
   return FNTRS_OK;
 }
@@ -586,6 +639,17 @@ int fntrs_create(int device, size_t cap, fntrs_ctx** out) {
   c->lds_max = prop.sharedMemPerBlock;
   c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   set_default_configs(c);
+  // Stream-ordered scratch (locator builds, batch tables, four-step passes)
+  // is allocated and freed per call.  With the pool's default release
+  // threshold of 0 every free hands the memory back to the driver (~15 us a
+  // call); keep up to the workspace cap reserved in the device's pool.
+  hipMemPool_t pool = nullptr;
+  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess && pool) {
+    uint64_t keep = c->cap;
+    uint64_t cur = 0;
+    if (hipMemPoolGetAttribute(pool, hipMemPoolAttrReleaseThreshold, &cur) == hipSuccess && cur < keep)
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
   // twiddle tables: tw[e] = 3^e and twi[e] = 3^-e = 3^(65536-e), e < 65536
   std::vector<uint32_t> h(2 * 65536);
   uint64_t x = 1;

@@ -91,6 +91,17 @@ struct fntrs_ctx {
     bool pending = false;
   };
   std::vector<StageSlot> stage;
+  // device buffers for small per-call tables (locator builds, batch job
+  // tables): allocating and freeing stream-ordered memory costs ~15 us of
+  // host time a call.  A slot is reused once the event recorded after its
+  // last use has fired.
+  struct DevSlot {
+    uint8_t* p = nullptr;
+    size_t bytes = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+  };
+  std::vector<DevSlot> dev_slots;
 };
 
 namespace fntrs {
@@ -145,6 +156,14 @@ const CtTables& ct_tables();
 int upload_async(fntrs_ctx* c, void* dst, const void* src, size_t bytes, hipStream_t s);
 // Frees the staging slots (the device must be idle).
 void stage_release(fntrs_ctx* c);
+
+// Largest per-call table served from the device slots; larger buffers are
+// allocated stream-ordered.
+constexpr size_t kDevSlotMax = size_t(64) << 20;
+// A device buffer of at least `bytes` (<= kDevSlotMax) idle on every stream;
+// dev_slot_done must follow its last use on stream s.
+int dev_slot_acquire(fntrs_ctx* c, size_t bytes, fntrs_ctx::DevSlot*& out);
+int dev_slot_done(fntrs_ctx* c, fntrs_ctx::DevSlot* slot, hipStream_t s);
 
 // Resident workgroups per CU of a persistent kernel (cached per context);
 // op 0/1 = encode/decode table kernel, 2 = pipelined decode kernel;

@@ -293,8 +293,11 @@ __global__ void k_locb_ahat(const LocDesc* __restrict__ D, const uint32_t* __res
 // ---------------------------------------------------------------- large
 // transforms of the locator on the lane-tile engine (ctfnt.hpp) with one
 // lane: radix-32 passes, one item per thread per pass (2^L / 32 threads,
-// 64..1024), in place of the radix-4 LDS loops above, for sizes 2^11 and up.
-constexpr int kLocCtMin = 11;
+// 64..1024), in place of the radix-4 LDS loops above: product-tree levels
+// with transforms of 2^12 points and up (at 2^11 the radix-4 kernel is as
+// fast), evaluations with K >= 2^11.
+constexpr int kLocLevelCtMin = 12;
+constexpr int kLocEvalCtMin = 11;
 
 template <int L>
 __host__ __device__ constexpr int loc_nt() {

@@ -364,16 +364,26 @@ int fntrs_submit(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, void* stre
   const size_t blob = align_up(P.blob.size());
   const size_t bytes = blob + P.scratch_elems * 4;
   uint8_t* mem = nullptr;
-  if (bytes) {
+  fntrs_ctx::DevSlot* slot = nullptr;
+  if (bytes && bytes <= kDevSlotMax) {
+    if (int rc = dev_slot_acquire(c, bytes, slot)) return rc;
+    mem = slot->p;
+  } else if (bytes) {
     hipError_t e = hipMallocAsync((void**)&mem, bytes, s);
     if (e != hipSuccess) return fail(c, FNTRS_E_NOMEM, "batch workspace of %zu bytes: %s", bytes, hipGetErrorString(e));
+  }
+  auto release = [&]() {
+    if (slot) (void)dev_slot_done(c, slot, s);
+    else if (mem) (void)hipFreeAsync(mem, s);
+  };
+  if (bytes) {
     if (int rc = upload_async(c, mem, P.blob.data(), P.blob.size(), s)) {
-      (void)hipFreeAsync(mem, s);
+      release();
       return rc;
     }
   }
   const int rc = run_plan(c, P, mem, reinterpret_cast<uint32_t*>(mem + blob), s, c->sides[s]);
-  if (mem) (void)hipFreeAsync(mem, s);
+  release();
   return rc;
 }
 
