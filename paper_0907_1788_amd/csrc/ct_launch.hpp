@@ -23,15 +23,22 @@ struct CtVariants {
 
 constexpr CtVariants ct_variants(int L) {
   switch (L) {
-    case 9: return {{{32, 512}, {64, 512}}, {{32, 512}, {64, 512}}};
+    case 9: return {{{32, 512}, {64, 512}, {8, 128}}, {{32, 512}, {64, 512}, {8, 128}}};
     case 10: return {{{16, 512}, {32, 512}}, {{16, 512}, {32, 512}}};
     case 11: return {{{8, 512}, {16, 512}}, {{8, 512}, {16, 512}}};
     case 12: return {{{8, 512}, {8, 1024}, {4, 512, 2}, {8, 1024, 2}}, {{8, 1024, 2}, {8, 512}, {4, 512}, {8, 1024}}};
     case 13: return {{{4, 1024}, {4, 512}}, {{4, 1024}, {4, 512}, {4, 512, 2}}};
     case 14: return {{{2, 512}}, {{2, 512}}};
     case 15: return {{{1, 512}}, {{1, 512}}};
-    default: return {{{64, 512}, {128, 512}}, {{64, 512}, {128, 512}}};   // L <= 8
+    default: return {{{64, 512}, {128, 512}, {16, 128}}, {{64, 512}, {128, 512}, {16, 128}}};   // L <= 8
   }
+}
+
+// Narrow tile for calls too small to fill the device with the default one
+// (one codeword of a few hundred lanes): more, shorter workgroups.  T = 0
+// when the size has none.  Each is also listed in ct_variants.
+constexpr CtCfg ct_small(int L) {
+  return L <= 8 ? CtCfg{16, 128} : (L == 9 ? CtCfg{8, 128} : CtCfg{0, 0});
 }
 
 // Launches k_enc<L, T, NT> / k_dec<L, D, T, NT>; D in {-1 (k = n), 0, 1}.

@@ -142,6 +142,16 @@ int dev_slot_done(fntrs_ctx* c, fntrs_ctx::DevSlot* slot, hipStream_t s) {
   return FNTRS_OK;
 }
 
+// The configuration of one single call: the size's configuration, or its
+// narrow tile when the call would otherwise give fewer work items than half
+// the CUs (per = work items per lane tile).
+CtCfg call_cfg(const fntrs_ctx* c, CtCfg cfg, int L, uint32_t lanes, uint64_t per) {
+  const CtCfg sm = ct_small(L);
+  if (sm.T == 0 || sm.T >= cfg.T) return cfg;
+  const uint64_t items = (uint64_t)((lanes + cfg.T - 1) / cfg.T) * per;
+  return items * 2 < (uint64_t)c->num_cu ? sm : cfg;
+}
+
 int kernel_occupancy(fntrs_ctx* c, int op, int L, int D, CtCfg cfg) {
   const auto key = std::make_tuple(op, L, D, cfg.T * 4096 + cfg.NT, cfg.V);
   auto it = c->occ.find(key);
@@ -735,10 +745,10 @@ int fntrs_encode(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uin
     HIP_TRY(c, e);
     return FNTRS_OK;
   }
-  const CtCfg cfg = c->enc_cfg[a.logK];
+  a.cosets = n >> a.logK;
+  const CtCfg cfg = call_cfg(c, c->enc_cfg[a.logK], a.logK, lanes, (uint64_t)a.cosets * batch);
   a.vec = aligned16(src, ld_src, stride_src) && aligned16(dst, ld_dst, stride_dst);
   a.tiles = (lanes + cfg.T - 1) / cfg.T;
-  a.cosets = n >> a.logK;
   const uint64_t blocks = (uint64_t)a.tiles * a.cosets * batch;
   if (blocks > 0x7fffffffull) return fail(c, FNTRS_E_INVAL, "grid too large");
   HIP_TRY(c, launch_ct_encode(c, a.logK, cfg, a, blocks, s));
@@ -840,7 +850,7 @@ int fntrs_decode(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, uint32_
   a.full = full ? 1u : 0u;
   a.row0 = full ? L->positions[0] : 0u;
   const int D = (k == n) ? -1 : L->logn - L->logm;
-  const CtCfg cfg = c->dec_cfg[L->logn];
+  const CtCfg cfg = call_cfg(c, c->dec_cfg[L->logn], L->logn, lanes, batch);
   a.vec = aligned16(recv, ld_recv, stride_recv) && aligned16(dst, ld_dst, stride_dst);
   a.tiles = (lanes + cfg.T - 1) / cfg.T;
   const uint64_t blocks = (uint64_t)a.tiles * batch;

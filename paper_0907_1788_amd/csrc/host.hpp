@@ -165,6 +165,9 @@ constexpr size_t kDevSlotMax = size_t(64) << 20;
 int dev_slot_acquire(fntrs_ctx* c, size_t bytes, fntrs_ctx::DevSlot*& out);
 int dev_slot_done(fntrs_ctx* c, fntrs_ctx::DevSlot* slot, hipStream_t s);
 
+// The configuration of one single call of size 2^L (see ct_small).
+CtCfg call_cfg(const fntrs_ctx* c, CtCfg cfg, int L, uint32_t lanes, uint64_t per);
+
 // Resident workgroups per CU of a persistent kernel (cached per context);
 // op 0/1 = encode/decode table kernel, 2 = pipelined decode kernel;
 // 0 = not available.

@@ -233,7 +233,9 @@ TILE_CASES = [("e12=4x512v2", 4096, 4096, 40), ("e12=8x1024", 8192, 4096, 24), (
               ("d13=4x1024", 8192, 2048, 6), ("d13=4x1024", 8192, 8192, 5), ("d13=4x512", 8192, 4096, 10),
               ("d13=4x512", 8192, 2048, 7), ("d13=4x512", 8192, 8192, 3), ("d13=4x512v2", 8192, 4096, 10),
               ("d13=4x512v2", 8192, 2048, 7), ("d13=4x512v2", 8192, 8192, 5), ("d12=8x512", 4096, 4096, 11),
-              ("e12=8x1024v2", 8192, 4096, 19), ("d12=4x512", 4096, 1024, 9)]
+              ("e12=8x1024v2", 8192, 4096, 19), ("d12=4x512", 4096, 1024, 9),
+              # narrow tiles (chosen by small single calls), forced at many lanes
+              ("e8=16x128,d9=8x128", 512, 256, 300), ("e5=16x128,d6=16x128", 64, 32, 70)]
 
 
 @pytest.mark.parametrize("spec,n,k,lanes", TILE_CASES)
