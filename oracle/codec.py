@@ -220,3 +220,35 @@ def decode_six_step(n: int, positions, v) -> np.ndarray:
     for i in range(k):                                       # step 6, mod x^k
         out[i:] = (out[i:] + A[i] * S[: k - i]) % P
     return out.reshape(v.shape)
+
+
+# ---------------------------------------------------------------------------
+# Systematic code (Sec. II-C): the source vector, interpolated on the first k
+# positions, gives k intermediate symbols; the codeword is the same transform
+# of the intermediate symbols, so its first k symbols are the source.
+# ---------------------------------------------------------------------------
+
+def systematic_intermediate(s, n: int) -> np.ndarray:
+    """The intermediate symbols: coefficients of the degree < k polynomial
+    taking the value s_j at x = r^j, j < k (Sec. II-C, interpolation on the
+    first k positions)."""
+    s = _rows(s)
+    k = s.shape[0]
+    _check_nk(n, k)
+    return decode_lagrange(n, np.arange(k, dtype=np.int64), s)
+
+
+def systematic_encode(s, n: int, rows=None) -> np.ndarray:
+    """e = FNT_n of the zero-padded intermediate symbols (Sec. II-C);
+    ``rows`` restricts the output as in ``encode``."""
+    return encode(systematic_intermediate(s, n), n, rows=rows)
+
+
+def systematic_decode(n: int, positions, v) -> np.ndarray:
+    """The source from k received symbols (Sec. II-C): the intermediate
+    symbols by the interpolation of Sec. II-B, then their transform at the
+    first k positions."""
+    v = _rows(v)
+    k = v.shape[0]
+    inter = decode_lagrange(n, positions, v)
+    return encode(inter, n, rows=np.arange(k, dtype=np.int64))

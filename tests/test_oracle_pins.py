@@ -21,6 +21,10 @@ P12 hand-worked n = 4 example containing the residue 65536          -- by hand
 P13 linearity over GF(p)                                            -- definition
 P14 decode(encode(s) restricted to R) = s, three decoders           -- uniqueness
 P15 (A * S mod x^n) has zero coefficients k .. n-1 (Sec. II-B, step 5/6)
+P16 systematic code: the first k codeword symbols are the source (Sec. II-C)
+P17 systematic code, k = n is the identity and k = 1 a constant     -- closed forms
+P18 systematic codewords are codewords; every k-subset decodes      -- brute force
+P19 systematic n = 4, k = 2 worked by Cramer's rule                 -- by hand
 """
 import itertools
 import os
@@ -339,3 +343,49 @@ def test_rejects_bad_arguments():
         codec.decode_lagrange(8, [0, 1], np.zeros((3, 1)))
     with pytest.raises(ValueError):
         codec.decode_lagrange(8, [0, 0, 1], np.zeros((3, 1)))
+
+
+# --------------------------------------------------------------- P16 .. P19
+@pytest.mark.parametrize("n,k,lanes", [(2, 1, 3), (8, 4, 2), (16, 5, 3), (64, 32, 4), (256, 64, 2), (512, 256, 1)])
+def test_p16_systematic_positions_hold_the_source(n, k, lanes):
+    """Sec. II-C: the first k positions of the encoded vector are the source."""
+    s = synth.residues(800 + n + k, (k, lanes))
+    e = codec.systematic_encode(s, n)
+    assert np.array_equal(e[:k], s.astype(np.int64))
+    # and the source comes back from the last k positions alone
+    z = np.arange(n - k, n)
+    assert np.array_equal(codec.systematic_decode(n, z, e[z]), s.astype(np.int64))
+
+
+def test_p17_systematic_special_cases():
+    """k = n: interpolating on all n positions and transforming back is the
+    identity.  k = 1: the interpolant of one value is that constant, so every
+    symbol equals s_0."""
+    s = synth.residues(811, (16, 2))
+    assert np.array_equal(codec.systematic_encode(s, 16), s.astype(np.int64))
+    one = np.array([[65536, 7]])
+    assert np.array_equal(codec.systematic_encode(one, 32), np.repeat(one, 32, axis=0))
+
+
+@pytest.mark.parametrize("n,k", [(8, 3), (16, 4)])
+def test_p18_systematic_codewords_are_codewords_and_decode_from_every_subset(n, k):
+    """A systematic codeword is the transform of k intermediate symbols, i.e. a
+    codeword of the code of Sec. II-B: any k of its symbols determine all n.
+    Every k-subset recovers the source (MDS)."""
+    s = synth.residues(820 + n, (k, 2))
+    e = codec.systematic_encode(s, n)
+    for z in itertools.combinations(range(n), k):
+        z = np.array(z)
+        assert np.array_equal(codec.encode(codec.decode_gauss(n, z, e[z]), n), e), z
+        assert np.array_equal(codec.systematic_decode(n, z, e[z]), s.astype(np.int64)), z
+
+
+def test_p19_systematic_n4_worked_example():
+    """n = 4 (r = -256), k = 2, s = (1, 65535 = -2): the intermediate symbols
+    solve i0 + i1 = 1 and i0 - 256 i1 = -2; by Cramer's rule (det = -257)
+    i0 = 254/257 and i1 = 3/257, so e2 = i(r^2 = -1) = 251/257 and
+    e3 = i(r^3 = 256) = 1022/257."""
+    inv257 = pow(257, P - 2, P)
+    want = [1, 65535, 251 * inv257 % P, 1022 * inv257 % P]
+    got = codec.systematic_encode(np.array([[1], [65535]]), 4)[:, 0]
+    assert list(got) == want
