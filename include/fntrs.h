@@ -61,6 +61,9 @@ enum {
 #define FNTRS_RECV_COMPACT 0u   /* recv holds k rows: row i is the symbol received at positions[i] */
 #define FNTRS_RECV_FULL 1u      /* recv holds n rows indexed by position; only the k received rows are read */
 #define FNTRS_FLAG_VALIDATE 2u  /* check input residues <= 65536 first (synchronous) */
+/* encode and decode flag: the systematic code of Sec. II-C (single calls
+ * only; a batched job with this flag is rejected with FNTRS_E_UNSUPPORTED) */
+#define FNTRS_SYSTEMATIC 4u
 
 /* Pseudo-device for fntrs_create: a context that touches no GPU.  Every call
  * on it runs the full host-side argument validation and, if the arguments
@@ -87,8 +90,17 @@ const char* fntrs_last_error(const fntrs_ctx* ctx);
  * the FNT of size n of the zero-padded source.  src holds k rows, dst n rows.
  * n: power of two in [1, 65536]; 1 <= k <= n (any k, zero padding covers a k
  * that is not a power of two, Sec. II-B); lanes >= 1; batch >= 1 blocks.
- * src and dst must not overlap.  Errors: FNTRS_E_INVAL, FNTRS_E_DEVICE,
- * FNTRS_E_RANGE (validate flag). */
+ * src and dst must not overlap.
+ * flags: 0, FNTRS_FLAG_VALIDATE, and/or FNTRS_SYSTEMATIC.  With
+ * FNTRS_SYSTEMATIC the systematic code of Sec. II-C: the source is
+ * interpolated on positions 0..k-1 into k intermediate symbols (the decoder,
+ * with the locator of that pattern, which the context builds once and
+ * caches), and dst is the transform above of the intermediate symbols, so
+ * that dst rows 0..k-1 equal src; k must then be a power of two
+ * (FNTRS_E_UNSUPPORTED otherwise), and the call holds a scratch of
+ * batch*k*lanes words of device memory, allocated and freed on `stream`.
+ * Errors: FNTRS_E_INVAL, FNTRS_E_DEVICE, FNTRS_E_RANGE (validate flag),
+ * FNTRS_E_NOMEM, FNTRS_E_UNSUPPORTED. */
 int fntrs_encode(fntrs_ctx* ctx, uint32_t n, uint32_t k, uint32_t lanes,
                  const uint32_t* src, size_t ld_src, size_t stride_src,
                  uint32_t* dst, size_t ld_dst, size_t stride_dst,
@@ -143,7 +155,12 @@ int fntrs_locator_export(fntrs_ctx* ctx, const fntrs_locator_t* loc,
  * recv layout (FNTRS_RECV_COMPACT: k rows in position order; FNTRS_RECV_FULL:
  * n rows, row z read for each received position z) and may add
  * FNTRS_FLAG_VALIDATE.  dst receives k rows per block.  recv and dst must not
- * overlap.  Errors: FNTRS_E_INVAL, FNTRS_E_DEVICE, FNTRS_E_RANGE. */
+ * overlap.  With FNTRS_SYSTEMATIC (Sec. II-C) the received symbols are those
+ * of a systematic codeword (fntrs_encode with FNTRS_SYSTEMATIC): the decoder
+ * recovers the k intermediate symbols and transforms them at positions
+ * 0..k-1, so dst receives the source; the call holds a scratch of
+ * batch*k*lanes words of device memory, allocated and freed on `stream`.
+ * Errors: FNTRS_E_INVAL, FNTRS_E_DEVICE, FNTRS_E_RANGE, FNTRS_E_NOMEM. */
 int fntrs_decode(fntrs_ctx* ctx, const fntrs_locator_t* loc, uint32_t lanes, uint32_t flags,
                  const uint32_t* recv, size_t ld_recv, size_t stride_recv,
                  uint32_t* dst, size_t ld_dst, size_t stride_dst,
@@ -172,7 +189,8 @@ typedef struct fntrs_job {
   uint32_t lanes, batch;       /* lanes per row, codeword blocks */
   uint32_t flags;              /* encode: 0; decode: FNTRS_RECV_COMPACT or
                                   FNTRS_RECV_FULL (FNTRS_FLAG_VALIDATE is
-                                  rejected: it would synchronise the batch) */
+                                  rejected: it would synchronise the batch;
+                                  FNTRS_SYSTEMATIC is not batched) */
   const fntrs_locator_t* loc;  /* decode: locator of the received positions;
                                   encode: NULL */
   const uint32_t* in;          /* encode: src [batch][k][ld_in];

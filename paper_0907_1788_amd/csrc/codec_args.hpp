@@ -16,6 +16,7 @@ struct EncodeArgs {
   int logn, logK;            // transform size K = 2^logK >= k, K <= n
   uint32_t tiles, cosets;    // lane tiles per block, n / K
   uint32_t vec;              // src/dst rows are 16-byte aligned (vector access allowed)
+  uint32_t rows_out;         // only rows i < rows_out of dst are written (0: all n)
 };
 
 // Moves V lanes of one row between global memory and registers.  The

@@ -192,11 +192,13 @@ struct EncStore {
   uint64_t ld;
   uint32_t t, cosets, lane0, lanes;
   bool vec;
+  uint32_t rows_out;   // rows at or beyond are not written (0: none skipped)
   template <int B, uint32_t H, bool WHOLE>
   __device__ __forceinline__ void rows(uint32_t base, uint32_t g, int32_t (&x)[1 << B][V]) {
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c) {
       const uint64_t row = t + (uint64_t)cosets * (base + c * H);
+      if (rows_out && row >= rows_out) continue;
       store_lanes<V, WHOLE>(dst + row * ld + g * V, lane0 + g * V, lanes, x[c]);
     }
   }
@@ -223,7 +225,7 @@ __device__ __forceinline__ void enc_item(const EncodeArgs& a, uint32_t item, uin
                     16 - a.logn, a.vec != 0};
   LdsLoad<V, G> lm{lds};
   LdsStore<V, G, false> sm{lds};
-  EncStore<V> sl{a.dst + blk * a.stride_dst + lane0, a.ld_dst, t, a.cosets, lane0, a.lanes, a.vec != 0};
+  EncStore<V> sl{a.dst + blk * a.stride_dst + lane0, a.ld_dst, t, a.cosets, lane0, a.lanes, a.vec != 0, a.rows_out};
   dit<LK, Gm::BM, V, G, false>(tws, l0, lm, sm, sl);
 }
 

@@ -189,7 +189,7 @@ int check_encode(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uin
   if (ld_src < lanes || ld_dst < lanes) return fail(c, FNTRS_E_INVAL, "ld_src/ld_dst smaller than lanes");
   if (batch > 1 && (stride_src < (size_t)(k - 1) * ld_src + lanes || stride_dst < (size_t)(n - 1) * ld_dst + lanes))
     return fail(c, FNTRS_E_INVAL, "block strides overlap consecutive blocks");
-  if (flags & ~FNTRS_FLAG_VALIDATE) return fail(c, FNTRS_E_INVAL, "unknown flags 0x%x", flags);
+  if (flags & ~(FNTRS_FLAG_VALIDATE | FNTRS_SYSTEMATIC)) return fail(c, FNTRS_E_INVAL, "unknown flags 0x%x", flags);
   const size_t sb = span_elems(batch, stride_src, k, ld_src, lanes) * 4;
   const size_t db = span_elems(batch, stride_dst, n, ld_dst, lanes) * 4;
   if (ranges_overlap(src, sb, dst, db)) return fail(c, FNTRS_E_INVAL, "src and dst overlap");
@@ -203,7 +203,8 @@ int check_decode(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, uint32_
   if (L->refs <= 0) return fail(c, FNTRS_E_INVAL, "locator was released");
   if (lanes < 1 || batch < 1) return fail(c, FNTRS_E_INVAL, "lanes=%u and batch=%u must be >= 1", lanes, batch);
   if (!recv || !dst) return fail(c, FNTRS_E_INVAL, "null recv or dst");
-  if (flags & ~(FNTRS_RECV_FULL | FNTRS_FLAG_VALIDATE)) return fail(c, FNTRS_E_INVAL, "unknown flags 0x%x", flags);
+  if (flags & ~(FNTRS_RECV_FULL | FNTRS_FLAG_VALIDATE | FNTRS_SYSTEMATIC))
+    return fail(c, FNTRS_E_INVAL, "unknown flags 0x%x", flags);
   const bool full = flags & FNTRS_RECV_FULL;
   const uint32_t n = L->n, k = L->k;
   const uint32_t rrows = full ? n : k;
@@ -621,6 +622,148 @@ void set_default_configs(fntrs_ctx* c) {
 
 using namespace fntrs;
 
+// Encoder on validated arguments, enqueued on s; rows_out > 0 writes only
+// the rows i < rows_out of dst.
+static int encode_run(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uint32_t* src, size_t ld_src,
+                      size_t stride_src, uint32_t* dst, size_t ld_dst, size_t stride_dst, uint32_t batch,
+                      uint32_t rows_out, hipStream_t s) {
+  if (n == 1) {  // k = 1: e_0 = s_0
+    HIP_TRY(c, launch_copy(src, stride_src, dst, stride_dst, lanes, batch, s));
+    return FNTRS_OK;
+  }
+  EncodeArgs a{};
+  a.rows_out = rows_out;
+  a.src = src; a.ld_src = ld_src; a.stride_src = stride_src;
+  a.dst = dst; a.ld_dst = ld_dst; a.stride_dst = stride_dst;
+  a.tw = c->tw; a.twi = c->twi;
+  a.n = n; a.k = k; a.lanes = lanes;
+  a.logn = ilog2(n);
+  a.logK = std::max(1, ilog2(k));        // transform size K: smallest power of two >= k, at least 2
+  if (a.logK >= kFourStepMinLog) {
+    // K >= 2^14: one FNT_n of the zero-padded source as four-step passes over
+    // 32-lane tiles, through a scratch buffer
+    FourStepArgs f{};
+    f.in = src; f.ld_in = ld_src; f.stride_in = stride_src;
+    f.out = dst; f.ld_out = ld_dst; f.stride_out = stride_dst;
+    f.tw = c->tw; f.twi = c->twi;
+    f.n = n; f.k = k; f.M = n; f.lanes = lanes; f.logn = a.logn; f.logm = a.logn;
+    f.tiles = (lanes + kFourStepTile - 1) / kFourStepTile;
+    f.rows_out = rows_out;
+    const uint64_t lds = (uint64_t)f.tiles * kFourStepTile;
+    f.vec = aligned16(src, ld_src, stride_src) && aligned16(dst, ld_dst, stride_dst);
+    uint32_t* sa = nullptr;
+    const size_t bytes = (size_t)batch * n * lds * 4;
+    hipError_t e = hipMallocAsync((void**)&sa, bytes, s);
+    if (e != hipSuccess) return fail(c, FNTRS_E_NOMEM, "scratch of %zu bytes: %s", bytes, hipGetErrorString(e));
+    e = fourstep_encode(f, batch, sa, lds, s);
+    (void)hipFreeAsync(sa, s);
+    HIP_TRY(c, e);
+    return FNTRS_OK;
+  }
+  a.cosets = n >> a.logK;
+  const CtCfg cfg = call_cfg(c, c->enc_cfg[a.logK], a.logK, lanes, (uint64_t)a.cosets * batch);
+  a.vec = aligned16(src, ld_src, stride_src) && aligned16(dst, ld_dst, stride_dst);
+  a.tiles = (lanes + cfg.T - 1) / cfg.T;
+  const uint64_t blocks = (uint64_t)a.tiles * a.cosets * batch;
+  if (blocks > 0x7fffffffull) return fail(c, FNTRS_E_INVAL, "grid too large");
+  HIP_TRY(c, launch_ct_encode(c, a.logK, cfg, a, blocks, s));
+  return FNTRS_OK;
+}
+
+
+// Decoder on validated arguments, enqueued on s.
+static int decode_run(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, bool full, const uint32_t* recv,
+                      size_t ld_recv, size_t stride_recv, uint32_t* dst, size_t ld_dst, size_t stride_dst,
+                      uint32_t batch, hipStream_t s) {
+  const uint32_t n = L->n, k = L->k;
+  HIP_TRY(c, hipStreamWaitEvent(s, L->ready, 0));
+  if (n == 1) {  // k = n = 1: s_0 = e_0
+    HIP_TRY(c, launch_copy(recv, stride_recv, dst, stride_dst, lanes, batch, s));
+    return FNTRS_OK;
+  }
+  if (L->logn >= kFourStepMinLog) {
+    FourStepArgs f{};
+    f.in = recv; f.ld_in = ld_recv; f.stride_in = stride_recv;
+    f.out = dst; f.ld_out = ld_dst; f.stride_out = stride_dst;
+    f.tw = c->tw; f.twi = c->twi; f.wfull = L->wfull; f.ridx = L->ridx; f.ahat = L->ahat_s;
+    f.n = n; f.k = k; f.lanes = lanes; f.logn = L->logn;
+    f.logm = (k == n) ? L->logn : L->logm;
+    f.M = 1u << f.logm;
+    f.full = full ? 1u : 0u;
+    f.tiles = (lanes + kFourStepTile - 1) / kFourStepTile;
+    const uint64_t lds = (uint64_t)f.tiles * kFourStepTile;
+    f.vec = aligned16(recv, ld_recv, stride_recv) && aligned16(dst, ld_dst, stride_dst);
+    uint32_t* sa = nullptr;
+    const size_t bytes = (size_t)batch * (n + f.M) * lds * 4;
+    hipError_t e = hipMallocAsync((void**)&sa, bytes, s);
+    if (e != hipSuccess) return fail(c, FNTRS_E_NOMEM, "scratch of %zu bytes: %s", bytes, hipGetErrorString(e));
+    e = fourstep_decode(f, batch, sa, sa + (size_t)batch * n * lds, lds, s);
+    (void)hipFreeAsync(sa, s);
+    HIP_TRY(c, e);
+    return FNTRS_OK;
+  }
+  DecodeArgs a{};
+  a.recv = recv; a.ld_recv = ld_recv; a.stride_recv = stride_recv;
+  a.dst = dst; a.ld_dst = ld_dst; a.stride_dst = stride_dst;
+  a.tw = c->tw; a.twi = c->twi; a.wfull = L->wfull; a.ridx = L->ridx; a.ahat_br = L->ahat_br;
+  a.n = n; a.k = k; a.lanes = lanes; a.logn = L->logn; a.logk = L->logk;
+  a.full = full ? 1u : 0u;
+  a.row0 = full ? L->positions[0] : 0u;
+  const int D = (k == n) ? -1 : L->logn - L->logm;
+  const CtCfg cfg = call_cfg(c, c->dec_cfg[L->logn], L->logn, lanes, batch);
+  a.vec = aligned16(recv, ld_recv, stride_recv) && aligned16(dst, ld_dst, stride_dst);
+  a.tiles = (lanes + cfg.T - 1) / cfg.T;
+  const uint64_t blocks = (uint64_t)a.tiles * batch;
+  if (blocks > 0x7fffffffull) return fail(c, FNTRS_E_INVAL, "grid too large");
+  HIP_TRY(c, launch_ct_decode(c, L->logn, cfg, D, a, blocks, s));
+  return FNTRS_OK;
+}
+
+
+// Systematic code (Sec. II-C), encoder: the source, read as the symbols
+// received at positions 0..k-1, is interpolated into k intermediate symbols
+// (the decoder with the locator of that pattern, cached in the context),
+// whose transform is the codeword; its first k rows are the source.
+static int systematic_encode_run(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uint32_t* src,
+                                 size_t ld_src, size_t stride_src, uint32_t* dst, size_t ld_dst, size_t stride_dst,
+                                 uint32_t batch, hipStream_t s) {
+  std::vector<uint32_t> first(k);
+  for (uint32_t i = 0; i < k; ++i) first[i] = i;
+  const uint32_t* fp = first.data();
+  fntrs_locator_t* L = nullptr;
+  if (int rc = locators_acquire(c, 1, &n, &k, &fp, &k, s, &L)) return rc;
+  uint32_t* mid = nullptr;   // intermediate symbols [batch][k][lanes]
+  const size_t bytes = (size_t)batch * k * lanes * 4;
+  hipError_t e = hipMallocAsync((void**)&mid, bytes, s);
+  int rc = FNTRS_OK;
+  if (e != hipSuccess) {
+    rc = fail(c, FNTRS_E_NOMEM, "intermediate symbols of %zu bytes: %s", bytes, hipGetErrorString(e));
+  } else {
+    rc = decode_run(c, L, lanes, false, src, ld_src, stride_src, mid, lanes, (size_t)k * lanes, batch, s);
+    if (!rc) rc = encode_run(c, n, k, lanes, mid, lanes, (size_t)k * lanes, dst, ld_dst, stride_dst, batch, 0, s);
+    (void)hipFreeAsync(mid, s);
+  }
+  L->refs--;
+  return rc;
+}
+
+// Systematic code (Sec. II-C), decoder: the intermediate symbols from the k
+// received symbols, then their transform at the first k positions.
+static int systematic_decode_run(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, bool full,
+                                 const uint32_t* recv, size_t ld_recv, size_t stride_recv, uint32_t* dst,
+                                 size_t ld_dst, size_t stride_dst, uint32_t batch, hipStream_t s) {
+  const uint32_t n = L->n, k = L->k;
+  uint32_t* mid = nullptr;
+  const size_t bytes = (size_t)batch * k * lanes * 4;
+  hipError_t e = hipMallocAsync((void**)&mid, bytes, s);
+  if (e != hipSuccess)
+    return fail(c, FNTRS_E_NOMEM, "intermediate symbols of %zu bytes: %s", bytes, hipGetErrorString(e));
+  int rc = decode_run(c, L, lanes, full, recv, ld_recv, stride_recv, mid, lanes, (size_t)k * lanes, batch, s);
+  if (!rc) rc = encode_run(c, n, k, lanes, mid, lanes, (size_t)k * lanes, dst, ld_dst, stride_dst, batch, k, s);
+  (void)hipFreeAsync(mid, s);
+  return rc;
+}
+
 extern "C" {
 
 const char* fntrs_version(void) { return "fntrs 0.1 (gfx950)"; }
@@ -707,6 +850,8 @@ int fntrs_encode(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uin
   std::lock_guard<std::mutex> lk(c->mu);
   c->err.clear();
   if (int rc = check_encode(c, n, k, lanes, src, ld_src, stride_src, dst, ld_dst, stride_dst, batch, flags)) return rc;
+  if ((flags & FNTRS_SYSTEMATIC) && !is_pow2(k))
+    return fail(c, FNTRS_E_UNSUPPORTED, "the systematic code needs k a power of two, got %u", k);
   if (c->device == FNTRS_HOST_ONLY) return fail(c, FNTRS_E_DEVICE, "host-only context: arguments valid, no device");
   DeviceGuard g(c->device);
   hipStream_t s = (hipStream_t)stream;
@@ -714,45 +859,9 @@ int fntrs_encode(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uin
     int rc = validate_range(c, src, batch, stride_src, k, ld_src, lanes, s);
     if (rc) return rc;
   }
-  if (n == 1) {  // k = 1: e_0 = s_0
-    HIP_TRY(c, launch_copy(src, stride_src, dst, stride_dst, lanes, batch, s));
-    return FNTRS_OK;
-  }
-  EncodeArgs a;
-  a.src = src; a.ld_src = ld_src; a.stride_src = stride_src;
-  a.dst = dst; a.ld_dst = ld_dst; a.stride_dst = stride_dst;
-  a.tw = c->tw; a.twi = c->twi;
-  a.n = n; a.k = k; a.lanes = lanes;
-  a.logn = ilog2(n);
-  a.logK = std::max(1, ilog2(k));        // transform size K: smallest power of two >= k, at least 2
-  if (a.logK >= kFourStepMinLog) {
-    // K >= 2^14: one FNT_n of the zero-padded source as four-step passes over
-    // 32-lane tiles, through a scratch buffer
-    FourStepArgs f{};
-    f.in = src; f.ld_in = ld_src; f.stride_in = stride_src;
-    f.out = dst; f.ld_out = ld_dst; f.stride_out = stride_dst;
-    f.tw = c->tw; f.twi = c->twi;
-    f.n = n; f.k = k; f.M = n; f.lanes = lanes; f.logn = a.logn; f.logm = a.logn;
-    f.tiles = (lanes + kFourStepTile - 1) / kFourStepTile;
-    const uint64_t lds = (uint64_t)f.tiles * kFourStepTile;
-    f.vec = aligned16(src, ld_src, stride_src) && aligned16(dst, ld_dst, stride_dst);
-    uint32_t* sa = nullptr;
-    const size_t bytes = (size_t)batch * n * lds * 4;
-    hipError_t e = hipMallocAsync((void**)&sa, bytes, s);
-    if (e != hipSuccess) return fail(c, FNTRS_E_NOMEM, "scratch of %zu bytes: %s", bytes, hipGetErrorString(e));
-    e = fourstep_encode(f, batch, sa, lds, s);
-    (void)hipFreeAsync(sa, s);
-    HIP_TRY(c, e);
-    return FNTRS_OK;
-  }
-  a.cosets = n >> a.logK;
-  const CtCfg cfg = call_cfg(c, c->enc_cfg[a.logK], a.logK, lanes, (uint64_t)a.cosets * batch);
-  a.vec = aligned16(src, ld_src, stride_src) && aligned16(dst, ld_dst, stride_dst);
-  a.tiles = (lanes + cfg.T - 1) / cfg.T;
-  const uint64_t blocks = (uint64_t)a.tiles * a.cosets * batch;
-  if (blocks > 0x7fffffffull) return fail(c, FNTRS_E_INVAL, "grid too large");
-  HIP_TRY(c, launch_ct_encode(c, a.logK, cfg, a, blocks, s));
-  return FNTRS_OK;
+  if (flags & FNTRS_SYSTEMATIC)
+    return systematic_encode_run(c, n, k, lanes, src, ld_src, stride_src, dst, ld_dst, stride_dst, batch, s);
+  return encode_run(c, n, k, lanes, src, ld_src, stride_src, dst, ld_dst, stride_dst, batch, 0, s);
 }
 
 int fntrs_locator(fntrs_ctx* c, uint32_t n, uint32_t k, const uint32_t* positions, uint32_t npos, void* stream,
@@ -816,47 +925,9 @@ int fntrs_decode(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, uint32_
     int rc = validate_range(c, recv, batch, stride_recv, rrows, ld_recv, lanes, s);
     if (rc) return rc;
   }
-  HIP_TRY(c, hipStreamWaitEvent(s, L->ready, 0));
-  if (n == 1) {  // k = n = 1: s_0 = e_0
-    HIP_TRY(c, launch_copy(recv, stride_recv, dst, stride_dst, lanes, batch, s));
-    return FNTRS_OK;
-  }
-  if (L->logn >= kFourStepMinLog) {
-    FourStepArgs f{};
-    f.in = recv; f.ld_in = ld_recv; f.stride_in = stride_recv;
-    f.out = dst; f.ld_out = ld_dst; f.stride_out = stride_dst;
-    f.tw = c->tw; f.twi = c->twi; f.wfull = L->wfull; f.ridx = L->ridx; f.ahat = L->ahat_s;
-    f.n = n; f.k = k; f.lanes = lanes; f.logn = L->logn;
-    f.logm = (k == n) ? L->logn : L->logm;
-    f.M = 1u << f.logm;
-    f.full = full ? 1u : 0u;
-    f.tiles = (lanes + kFourStepTile - 1) / kFourStepTile;
-    const uint64_t lds = (uint64_t)f.tiles * kFourStepTile;
-    f.vec = aligned16(recv, ld_recv, stride_recv) && aligned16(dst, ld_dst, stride_dst);
-    uint32_t* sa = nullptr;
-    const size_t bytes = (size_t)batch * (n + f.M) * lds * 4;
-    hipError_t e = hipMallocAsync((void**)&sa, bytes, s);
-    if (e != hipSuccess) return fail(c, FNTRS_E_NOMEM, "scratch of %zu bytes: %s", bytes, hipGetErrorString(e));
-    e = fourstep_decode(f, batch, sa, sa + (size_t)batch * n * lds, lds, s);
-    (void)hipFreeAsync(sa, s);
-    HIP_TRY(c, e);
-    return FNTRS_OK;
-  }
-  DecodeArgs a{};
-  a.recv = recv; a.ld_recv = ld_recv; a.stride_recv = stride_recv;
-  a.dst = dst; a.ld_dst = ld_dst; a.stride_dst = stride_dst;
-  a.tw = c->tw; a.twi = c->twi; a.wfull = L->wfull; a.ridx = L->ridx; a.ahat_br = L->ahat_br;
-  a.n = n; a.k = k; a.lanes = lanes; a.logn = L->logn; a.logk = L->logk;
-  a.full = full ? 1u : 0u;
-  a.row0 = full ? L->positions[0] : 0u;
-  const int D = (k == n) ? -1 : L->logn - L->logm;
-  const CtCfg cfg = call_cfg(c, c->dec_cfg[L->logn], L->logn, lanes, batch);
-  a.vec = aligned16(recv, ld_recv, stride_recv) && aligned16(dst, ld_dst, stride_dst);
-  a.tiles = (lanes + cfg.T - 1) / cfg.T;
-  const uint64_t blocks = (uint64_t)a.tiles * batch;
-  if (blocks > 0x7fffffffull) return fail(c, FNTRS_E_INVAL, "grid too large");
-  HIP_TRY(c, launch_ct_decode(c, L->logn, cfg, D, a, blocks, s));
-  return FNTRS_OK;
+  if (flags & FNTRS_SYSTEMATIC)
+    return systematic_decode_run(c, L, lanes, full, recv, ld_recv, stride_recv, dst, ld_dst, stride_dst, batch, s);
+  return decode_run(c, L, lanes, full, recv, ld_recv, stride_recv, dst, ld_dst, stride_dst, batch, s);
 }
 
 }  // extern "C"

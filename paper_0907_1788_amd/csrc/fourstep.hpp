@@ -349,7 +349,8 @@ __global__ void __launch_bounds__(kNT) k4_enc2(FourStepArgs a) {
   };
   auto destf = [&](uint32_t m1, uint32_t& w) -> uint64_t {
     w = 0;
-    return (uint64_t)m2 + 256u * m1;
+    const uint32_t r = m2 + 256u * m1;
+    return (a.rows_out && r >= a.rows_out) ? ~0ull : (uint64_t)r;
   };
   GLoad<LB, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.lane0, a.ld_in, wk.lane0, a.lanes, a.vec != 0, rowf};
   ct::LdsLoad<kV, Gm::G> lm{lds};

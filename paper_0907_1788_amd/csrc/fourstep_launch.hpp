@@ -19,6 +19,7 @@ struct FourStepArgs {
   uint32_t n, k, M, lanes;
   int logn, logm;
   uint32_t full, tiles, subs, vec;   // subs: sub-transforms per block
+  uint32_t rows_out;                 // encoder: only rows < rows_out of out are written (0: all n)
 };
 
 // Lanes per tile of the four-step kernels.

@@ -80,6 +80,19 @@ def test_encode_validation(hctx):
     assert "flags" in fntrs.fntrs_last_error(hctx)
 
 
+def test_systematic_flag_validation(hctx):
+    """The systematic code (Sec. II-C) is a flag of the single calls: valid with
+    k a power of two, unsupported otherwise, rejected in batches."""
+    S = fntrs.FNTRS_SYSTEMATIC
+    assert enc(hctx, 512, 256, 64, flags=S) == fntrs.FNTRS_E_DEVICE
+    assert enc(hctx, 512, 256, 64, flags=S | fntrs.FNTRS_FLAG_VALIDATE) == fntrs.FNTRS_E_DEVICE
+    assert enc(hctx, 512, 200, 64, flags=S) == fntrs.FNTRS_E_UNSUPPORTED
+    assert "power of two" in fntrs.fntrs_last_error(hctx)
+    assert enc(hctx, 512, 200, 64) == fntrs.FNTRS_E_DEVICE              # fine without the flag
+    assert fntrs.fntrs_submit(hctx, [ejob(512, 256, 64, SRC, DST, flags=S)]) == fntrs.FNTRS_E_UNSUPPORTED
+    assert "systematic" in fntrs.fntrs_last_error(hctx)
+
+
 def test_locator_validation(hctx):
     rc, h = fntrs.fntrs_locator(hctx, 16, 4, [1, 2, 3, 9])
     assert rc == fntrs.FNTRS_E_DEVICE and h is None
