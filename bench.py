@@ -93,26 +93,29 @@ def stored_traffic(kernel, workload):
     return e["hbm_bytes_per_launch"]
 
 
-def cpu_baseline(k, n, seed, budget_s=10.0):
+def cpu_baseline(k, n, seed, budget_s=10.0, systematic=False):
     """The CPU oracle timed on a bounded sample of the workload.
 
     One codeword block; a probe of a few lanes sizes each leg so that encode
     (Horner evaluation) and decode (Lagrange interpolation) each take about
-    ``budget_s`` seconds, whatever the host's speed.
+    ``budget_s`` seconds, whatever the host's speed.  ``systematic`` times the
+    oracle's systematic code instead (Sec. II-C).
     """
     from oracle import codec
     from paper_0907_1788_amd import synth
     src_all = synth.source(seed, 1, k, 2048)[0].astype(np.int64)
     z = synth.received_positions(seed + 1, n, k)
+    encode = codec.systematic_encode if systematic else codec.encode
+    decode = codec.systematic_decode if systematic else codec.decode_lagrange
 
     def enc(lanes):
         t0 = time.perf_counter()
-        e = codec.encode(src_all[:, :lanes], n)
+        e = encode(src_all[:, :lanes], n)
         return time.perf_counter() - t0, e
 
     def dec(e, lanes):
         t0 = time.perf_counter()
-        d = codec.decode_lagrange(n, z, e[z][:, :lanes])
+        d = decode(n, z, e[z][:, :lanes])
         dt = time.perf_counter() - t0
         assert np.array_equal(d, src_all[:, :lanes])
         return dt
@@ -129,9 +132,10 @@ def cpu_baseline(k, n, seed, budget_s=10.0):
     dec_rate = 2 * k * lanes_dec / t_dec
     value = 2.0 / (1.0 / enc_rate + 1.0 / dec_rate) / 1e9
     return {"value": value, "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"one block, k={k} n={n}: encode of {lanes_enc} lanes by Horner ({t_enc:.1f} s) and "
-                      f"decode of {lanes_dec} lanes by Lagrange ({t_dec:.1f} s), single-threaded numpy "
-                      f"on a host with {os.cpu_count()} cores; rate scaled linearly to the full payload",
+            "sample": f"one block, k={k} n={n}: {'systematic ' if systematic else ''}encode of {lanes_enc} "
+                      f"lanes ({t_enc:.1f} s) and decode of {lanes_dec} lanes ({t_dec:.1f} s) by Horner and "
+                      f"Lagrange, single-threaded numpy on a host with {os.cpu_count()} cores; rate scaled "
+                      f"linearly to the full payload",
             "enc_GBps": enc_rate / 1e9, "dec_GBps": dec_rate / 1e9}
 
 
@@ -359,6 +363,8 @@ def main():
     ap.add_argument("--requests", type=int, default=2000, help="requests per load point (served workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--systematic", action="store_true",
+                    help="the systematic code (Sec. II-C): interpolation + transform on both sides")
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM byte counters) and exit")
@@ -408,14 +414,16 @@ def main():
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(nsteps)]
     step_ms = []
 
+    sysf = fntrs.FNTRS_SYSTEMATIC if args.systematic else 0
+
     def step(i):
         e = ev[i]
         e[0].record(stream)
-        ctx.encode(src, enc, n, stream=stream)
+        ctx.encode(src, enc, n, flags=sysf, stream=stream)
         e[1].record(stream)
         loc = ctx.locator(n, k, patterns[i], stream=stream)
         e[2].record(stream)
-        ctx.decode(loc, enc, out, fntrs.FNTRS_RECV_FULL, stream=stream)
+        ctx.decode(loc, enc, out, fntrs.FNTRS_RECV_FULL | sysf, stream=stream)
         e[3].record(stream)
         loc.release()
 
@@ -448,6 +456,9 @@ def main():
     enc_bytes = 4 * (k + n) * lanes * blocks
     dec_bfly = decode_butterflies(n, k, lanes, blocks)
     enc_bfly = encode_butterflies(n, k, lanes, blocks)
+    if args.systematic:
+        # each side runs the decoder's transforms and the encoder's
+        dec_bfly = enc_bfly = dec_bfly + enc_bfly
     res = {
         "metric": "encode/decode payload GB/s (bit-exact) + p50/p99 latency, batched vs plain",
         "value": round(value, 3),
@@ -462,24 +473,26 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": args.workload, "k": k, "n": n, "lanes": lanes, "blocks": blocks,
+                   "code": "systematic" if args.systematic else "non-systematic",
                    "pattern": "uniform random n-k erasures, fresh pattern (locator rebuilt) every step",
                    "parallelism": "single GPU"},
         "bit_exact": exact,
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
         "phases_ms": {"encode": enc_avg, "locator": float(np.mean(loc_ms)), "decode": dec_avg},
         # dominant kernel: the decoder, bound by the integer vector ALUs
-        "roofline": {"bound": "alu", "kernel": "k_dec",
+        "roofline": {"bound": "alu", "kernel": "k_dec + k_enc (systematic decode)" if args.systematic else "k_dec",
                      "achieved": round(dec_bfly / (dec_avg * 1e-3) / 1e12, 4),
                      "peak": round(ALU_PEAK_BFLY / 1e12, 4), "unit": "Tbutterfly/s",
                      "frac": round(dec_bfly / (dec_avg * 1e-3) / ALU_PEAK_BFLY, 4),
-                     "traffic": stored_traffic("k_dec", args.workload),
+                     "traffic": None if args.systematic else stored_traffic("k_dec", args.workload),
                      "algorithmic_hbm_bytes": dec_bytes,
                      "hbm_frac": round(dec_bytes / (dec_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
-        "encode_roofline": {"bound": "alu", "kernel": "k_enc",
+        "encode_roofline": {"bound": "alu", "kernel": "k_dec + k_enc (systematic encode)" if args.systematic
+                            else "k_enc",
                             "achieved": round(enc_bfly / (enc_avg * 1e-3) / 1e12, 4),
                             "peak": round(ALU_PEAK_BFLY / 1e12, 4), "unit": "Tbutterfly/s",
                             "frac": round(enc_bfly / (enc_avg * 1e-3) / ALU_PEAK_BFLY, 4),
-                            "traffic": stored_traffic("k_enc", args.workload),
+                            "traffic": None if args.systematic else stored_traffic("k_enc", args.workload),
                             "algorithmic_hbm_bytes": enc_bytes,
                             "hbm_frac": round(enc_bytes / (enc_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
     }
@@ -490,9 +503,9 @@ def main():
         t0 = time.perf_counter()
         for b in range(blocks):
             t1 = time.perf_counter()
-            ctx.encode(src[b], enc[b], n, stream=stream)
+            ctx.encode(src[b], enc[b], n, flags=sysf, stream=stream)
             loc = ctx.locator(n, k, patterns[0], stream=stream)
-            ctx.decode(loc, enc[b], out[b], fntrs.FNTRS_RECV_FULL, stream=stream)
+            ctx.decode(loc, enc[b], out[b], fntrs.FNTRS_RECV_FULL | sysf, stream=stream)
             loc.release()
             torch.cuda.synchronize()
             lat.append((time.perf_counter() - t1) * 1e3)
@@ -503,7 +516,7 @@ def main():
     ctx.close()
     if not args.no_cpu_baseline:
         log("cpu baseline")
-        res["cpu_baseline"] = cpu_baseline(k, n, args.seed)
+        res["cpu_baseline"] = cpu_baseline(k, n, args.seed, systematic=args.systematic)
     print(json.dumps(res), flush=True)
 
 
