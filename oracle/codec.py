@@ -252,3 +252,55 @@ def systematic_decode(n: int, positions, v) -> np.ndarray:
     k = v.shape[0]
     inter = decode_lagrange(n, positions, v)
     return encode(inter, n, rows=np.arange(k, dtype=np.int64))
+
+
+# ---------------------------------------------------------------------------
+# Code lengths that are not a power of two (Sec. II-B: puncturing), and the
+# 16-bit transport of symbols (Sec. II-B: every value but 65536 fits in 16
+# bits; the positions holding 65536 travel in the symbol's header).
+# ---------------------------------------------------------------------------
+
+def padded_length(n: int) -> int:
+    """N = the smallest power of two >= n: the transform length of a code of length n."""
+    if n < 1 or n > 65536:
+        raise ValueError(f"n must be in [1, 65536], got {n}")
+    N = 1
+    while N < n:
+        N *= 2
+    return N
+
+
+def encode_punctured(s, n: int, rows=None) -> np.ndarray:
+    """The code of length n: the first n symbols of the code of length N =
+    padded_length(n) (the others are never sent)."""
+    N = padded_length(n)
+    idx = np.arange(n, dtype=np.int64) if rows is None else np.asarray(rows, dtype=np.int64)
+    if idx.size and (idx.min() < 0 or idx.max() >= n):
+        raise ValueError("rows must lie in [0, n)")
+    return encode(s, N, rows=idx)
+
+
+def decode_punctured(n: int, positions, v) -> np.ndarray:
+    """Decoding from k received symbols of a code of length n: the received
+    points are r_N^z, z < n, with N = padded_length(n)."""
+    z = np.asarray(positions, dtype=np.int64)
+    if z.size and (z.min() < 0 or z.max() >= n):
+        raise ValueError("positions must lie in [0, n)")
+    return decode_lagrange(padded_length(n), z, v)
+
+
+def pack16(symbol) -> tuple:
+    """One encoding symbol (a vector of residues) as 16-bit words plus the
+    positions holding 65536, which are sent as 0."""
+    v = np.asarray(symbol, dtype=np.int64)
+    if np.any((v < 0) | (v > 65536)):
+        raise ValueError("residues must lie in [0, 65536]")
+    esc = np.nonzero(v == 65536)[0].astype(np.int64)
+    return (v % 65536).astype(np.uint16), esc
+
+
+def unpack16(words, escapes) -> np.ndarray:
+    """Inverse of pack16."""
+    v = np.asarray(words, dtype=np.int64).copy()
+    v[np.asarray(escapes, dtype=np.int64)] = 65536
+    return v

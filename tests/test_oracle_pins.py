@@ -25,6 +25,8 @@ P16 systematic code: the first k codeword symbols are the source (Sec. II-C)
 P17 systematic code, k = n is the identity and k = 1 a constant     -- closed forms
 P18 systematic codewords are codewords; every k-subset decodes      -- brute force
 P19 systematic n = 4, k = 2 worked by Cramer's rule                 -- by hand
+P20 punctured length n: a prefix of the length-N code, still MDS    -- brute force
+P21 16-bit transport: 65536 is the only escape, round trip          -- definition
 """
 import itertools
 import os
@@ -389,3 +391,34 @@ def test_p19_systematic_n4_worked_example():
     want = [1, 65535, 251 * inv257 % P, 1022 * inv257 % P]
     got = codec.systematic_encode(np.array([[1], [65535]]), 4)[:, 0]
     assert list(got) == want
+
+
+# --------------------------------------------------------------- P20, P21
+def test_p20_punctured_code_is_a_prefix_and_still_mds():
+    """Sec. II-B: a length n that is not a power of two is the code of length
+    N = 8 with its last N - n symbols dropped.  Dropping symbols keeps any k
+    of the remaining n decodable (brute force over every k-subset)."""
+    assert [codec.padded_length(n) for n in (1, 2, 3, 5, 8, 9, 100, 65536)] == [1, 2, 4, 8, 8, 16, 128, 65536]
+    n, k = 6, 3
+    s = synth.residues(830, (k, 2))
+    e = codec.encode_punctured(s, n)
+    assert np.array_equal(e, codec.encode(s, 8)[:n])
+    for z in itertools.combinations(range(n), k):
+        z = np.array(z)
+        assert np.array_equal(codec.decode_punctured(n, z, e[z]), s.astype(np.int64)), z
+    with pytest.raises(ValueError):
+        codec.encode_punctured(s, n, rows=[6])
+
+
+def test_p21_sixteen_bit_transport():
+    """Sec. II-B: every residue but 65536 is a 16-bit value; the positions of
+    65536 are sent apart and the value comes back exactly."""
+    v = np.array([0, 1, 65535, 65536, 7, 65536], dtype=np.int64)
+    w, esc = codec.pack16(v)
+    assert w.dtype == np.uint16 and list(w) == [0, 1, 65535, 0, 7, 0]
+    assert list(esc) == [3, 5]
+    assert np.array_equal(codec.unpack16(w, esc), v)
+    r = synth.residues(840, (4096,))
+    assert np.array_equal(codec.unpack16(*codec.pack16(r)), r.astype(np.int64))
+    with pytest.raises(ValueError):
+        codec.pack16([65537])
