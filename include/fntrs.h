@@ -88,8 +88,11 @@ const char* fntrs_last_error(const fntrs_ctx* ctx);
 /* Encoder (Sec. II-B): for every block b, row i < n and lane l < lanes,
  *     dst[b][i][l] = sum_{j<k} src[b][j][l] * r_n^(i*j)  (mod 65537),
  * the FNT of size n of the zero-padded source.  src holds k rows, dst n rows.
- * n: power of two in [1, 65536]; 1 <= k <= n (any k, zero padding covers a k
- * that is not a power of two, Sec. II-B); lanes >= 1; batch >= 1 blocks.
+ * n in [1, 65536]; a length that is not a power of two is read as puncturing
+ * (Sec. II-B): the code of length N, the next power of two, with rows
+ * n..N-1 neither computed into dst nor sent (r_N takes the place of r_n);
+ * 1 <= k <= n (any k, zero padding covers a k that is not a power of two,
+ * Sec. II-B); lanes >= 1; batch >= 1 blocks.
  * src and dst must not overlap.
  * flags: 0, FNTRS_FLAG_VALIDATE, and/or FNTRS_SYSTEMATIC.  With
  * FNTRS_SYSTEMATIC the systematic code of Sec. II-C: the source is
@@ -110,7 +113,9 @@ int fntrs_encode(fntrs_ctx* ctx, uint32_t n, uint32_t k, uint32_t lanes,
  * on the received positions and are reused for every lane and block).
  * positions: host array of npos received positions in [0, n), strictly
  * ascending; the first k are used (Sec. II-B: "the first k evaluation
- * points received").  Builds on the device, enqueued on `stream`:
+ * points received").  n in [1, 65536], as for fntrs_encode (a punctured
+ * length uses the points of the next power of two).  Builds on the device,
+ * enqueued on `stream`:
  *   A(x) = prod_{i<k} (x - r_n^(z_i)) by a product tree of FNT products,
  *   A'(x), its values at the received points by FNT_n, their inverses,
  *   and the FNT of size 2k of the low coefficients of A.
@@ -165,6 +170,30 @@ int fntrs_decode(fntrs_ctx* ctx, const fntrs_locator_t* loc, uint32_t lanes, uin
                  const uint32_t* recv, size_t ld_recv, size_t stride_recv,
                  uint32_t* dst, size_t ld_dst, size_t stride_dst,
                  uint32_t batch, void* stream);
+
+/* 16-bit transport of encoding symbols (Sec. II-B: every residue but 65536
+ * is a 16-bit value; the positions holding 65536 travel in the symbol's
+ * header).  A symbol is one row of `lanes` residues; in/out hold `rows` rows
+ * per block, `batch` blocks, row-major with the given row pitch (ld) and
+ * block pitch (stride), in elements.  All pointers are device memory; the
+ * calls are asynchronous on `stream`.
+ *
+ * fntrs_pack16: out[b][r][l] = in[b][r][l] mod 65536 (65536 is sent as 0);
+ * esc_count[b*rows + r] = the number of lanes of row r of block b holding
+ * 65536, and esc_pos[(b*rows + r)*esc_cap + i], i < min(count, esc_cap),
+ * those lanes in ascending order (esc_cap = lanes always suffices; a row
+ * with more than esc_cap of them still reports its full count, and only
+ * the first esc_cap positions are written).  Inputs must be residues in
+ * [0, 65536].
+ * fntrs_unpack16: the inverse: out = in widened, and the first
+ * min(esc_count, esc_cap) listed lanes of each row set to 65536.
+ * lanes <= 65536.  Errors: FNTRS_E_INVAL, FNTRS_E_DEVICE. */
+int fntrs_pack16(fntrs_ctx* ctx, const uint32_t* in, size_t ld_in, size_t stride_in, uint32_t rows,
+                 uint32_t lanes, uint32_t batch, uint16_t* out, size_t ld_out, size_t stride_out,
+                 uint32_t* esc_count, uint32_t* esc_pos, uint32_t esc_cap, void* stream);
+int fntrs_unpack16(fntrs_ctx* ctx, const uint16_t* in, size_t ld_in, size_t stride_in, uint32_t rows,
+                   uint32_t lanes, uint32_t batch, const uint32_t* esc_count, const uint32_t* esc_pos,
+                   uint32_t esc_cap, uint32_t* out, size_t ld_out, size_t stride_out, void* stream);
 
 /* ------------------------------------------------------------------------
  * Batched path: uneven batches of encode and decode jobs.

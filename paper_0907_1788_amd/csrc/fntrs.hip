@@ -182,7 +182,7 @@ hipError_t launch_ct_decode(fntrs_ctx* c, int L, CtCfg cfg, int D, const DecodeA
 int check_encode(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uint32_t* src, size_t ld_src,
                  size_t stride_src, const uint32_t* dst, size_t ld_dst, size_t stride_dst, uint32_t batch,
                  uint32_t flags) {
-  if (!is_pow2(n) || n > 65536) return fail(c, FNTRS_E_INVAL, "n=%u must be a power of two in [1, 65536]", n);
+  if (n < 1 || n > 65536) return fail(c, FNTRS_E_INVAL, "n=%u must lie in [1, 65536]", n);
   if (k < 1 || k > n) return fail(c, FNTRS_E_INVAL, "k=%u must satisfy 1 <= k <= n=%u", k, n);
   if (lanes < 1 || batch < 1) return fail(c, FNTRS_E_INVAL, "lanes=%u and batch=%u must be >= 1", lanes, batch);
   if (!src || !dst) return fail(c, FNTRS_E_INVAL, "null src or dst");
@@ -206,8 +206,8 @@ int check_decode(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, uint32_
   if (flags & ~(FNTRS_RECV_FULL | FNTRS_FLAG_VALIDATE | FNTRS_SYSTEMATIC))
     return fail(c, FNTRS_E_INVAL, "unknown flags 0x%x", flags);
   const bool full = flags & FNTRS_RECV_FULL;
-  const uint32_t n = L->n, k = L->k;
-  const uint32_t rrows = full ? n : k;
+  const uint32_t k = L->k;
+  const uint32_t rrows = full ? L->nrows : k;
   if (ld_recv < lanes || ld_dst < lanes) return fail(c, FNTRS_E_INVAL, "ld_recv/ld_dst smaller than lanes");
   if (batch > 1 && (stride_recv < (size_t)(rrows - 1) * ld_recv + lanes || stride_dst < (size_t)(k - 1) * ld_dst + lanes))
     return fail(c, FNTRS_E_INVAL, "block strides overlap consecutive blocks");
@@ -534,7 +534,7 @@ int locators_acquire(fntrs_ctx* c, uint32_t count, const uint32_t* n_, const uin
     const uint32_t n = n_[q], k = k_[q], npos = npos_[q];
     const uint32_t* positions = positions_[q];
     int rc = FNTRS_OK;
-    if (!is_pow2(n) || n > 65536) rc = fail(c, FNTRS_E_INVAL, "n=%u must be a power of two in [1, 65536]", n);
+    if (n < 1 || n > 65536) rc = fail(c, FNTRS_E_INVAL, "n=%u must lie in [1, 65536]", n);
     else if (k < 1 || k > n) rc = fail(c, FNTRS_E_INVAL, "k=%u must satisfy 1 <= k <= n=%u", k, n);
     else if (!positions) rc = fail(c, FNTRS_E_INVAL, "null positions");
     else if (npos < k) rc = fail(c, FNTRS_E_TOOFEW, "%u positions received, k=%u needed", npos, k);
@@ -552,7 +552,7 @@ int locators_acquire(fntrs_ctx* c, uint32_t count, const uint32_t* n_, const uin
     }
     const uint64_t key = hash_positions(n, k, positions);
     auto same = [&](const fntrs_locator_t* L) {
-      return L->n == n && L->k == k && std::equal(L->positions.begin(), L->positions.end(), positions);
+      return L->nrows == n && L->k == k && std::equal(L->positions.begin(), L->positions.end(), positions);
     };
     fntrs_locator_t* hit = nullptr;
     auto range = c->cache.equal_range(key);
@@ -562,7 +562,7 @@ int locators_acquire(fntrs_ctx* c, uint32_t count, const uint32_t* n_, const uin
       if (!hit && L->key == key && same(L)) hit = L;
     if (!hit) {
       hit = new fntrs_locator_t();
-      hit->n = n; hit->k = k; hit->logn = ilog2(n); hit->logk = ilog2(k);
+      hit->n = pad_pow2(n); hit->nrows = n; hit->k = k; hit->logn = ilog2(n); hit->logk = ilog2(k);
       hit->logm = std::max(hit->logk + 1, hit->logn - 1);   // low-product length M >= 2k, M >= n/2
       hit->positions.assign(positions, positions + k);
       hit->key = key;
@@ -740,7 +740,9 @@ static int systematic_encode_run(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t 
     rc = fail(c, FNTRS_E_NOMEM, "intermediate symbols of %zu bytes: %s", bytes, hipGetErrorString(e));
   } else {
     rc = decode_run(c, L, lanes, false, src, ld_src, stride_src, mid, lanes, (size_t)k * lanes, batch, s);
-    if (!rc) rc = encode_run(c, n, k, lanes, mid, lanes, (size_t)k * lanes, dst, ld_dst, stride_dst, batch, 0, s);
+    if (!rc)
+      rc = encode_run(c, L->n, k, lanes, mid, lanes, (size_t)k * lanes, dst, ld_dst, stride_dst, batch,
+                      n < L->n ? n : 0, s);
     (void)hipFreeAsync(mid, s);
   }
   L->refs--;
@@ -861,7 +863,8 @@ int fntrs_encode(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uin
   }
   if (flags & FNTRS_SYSTEMATIC)
     return systematic_encode_run(c, n, k, lanes, src, ld_src, stride_src, dst, ld_dst, stride_dst, batch, s);
-  return encode_run(c, n, k, lanes, src, ld_src, stride_src, dst, ld_dst, stride_dst, batch, 0, s);
+  const uint32_t N = pad_pow2(n);   // a shorter code: the rows n..N-1 are not written
+  return encode_run(c, N, k, lanes, src, ld_src, stride_src, dst, ld_dst, stride_dst, batch, n < N ? n : 0, s);
 }
 
 int fntrs_locator(fntrs_ctx* c, uint32_t n, uint32_t k, const uint32_t* positions, uint32_t npos, void* stream,
@@ -916,8 +919,7 @@ int fntrs_decode(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, uint32_
   c->err.clear();
   if (int rc = check_decode(c, L, lanes, flags, recv, ld_recv, stride_recv, dst, ld_dst, stride_dst, batch)) return rc;
   const bool full = flags & FNTRS_RECV_FULL;
-  const uint32_t n = L->n, k = L->k;
-  const uint32_t rrows = full ? n : k;
+  const uint32_t rrows = full ? L->nrows : L->k;
   if (c->device == FNTRS_HOST_ONLY) return fail(c, FNTRS_E_DEVICE, "host-only context: arguments valid, no device");
   DeviceGuard g(c->device);
   hipStream_t s = (hipStream_t)stream;

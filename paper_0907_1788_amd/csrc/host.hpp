@@ -25,6 +25,9 @@ constexpr size_t kDefaultCap = size_t(4) << 30;
 
 inline bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
 inline int ilog2(uint64_t x) { int r = 0; while ((1ull << r) < x) ++r; return r; }
+// Transform length of a code of length n: the smallest power of two >= n (a
+// shorter code is the longer one with its last symbols never sent).
+inline uint32_t pad_pow2(uint32_t n) { return n <= 1 ? 1u : 1u << ilog2(n); }
 
 }  // namespace fntrs
 
@@ -43,7 +46,8 @@ struct LocSlab {
 };
 
 struct fntrs_locator_s {
-  uint32_t n = 0, k = 0;
+  uint32_t n = 0, k = 0;             // n: transform length, the power of two >= the code length
+  uint32_t nrows = 0;                // the code length (rows of a full received buffer)
   int logn = 0, logk = 0;
   int logm = 0;                      // low-product length M = 2^logm >= 2k (k < n)
   std::vector<uint32_t> positions;   // the k positions used

@@ -99,13 +99,15 @@ int make_plan(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, Plan& P) {
         f.in = J.in; f.ld_in = J.ld_in; f.stride_in = J.stride_in;
         f.out = J.out; f.ld_out = J.ld_out; f.stride_out = J.stride_out;
         f.tw = c->tw; f.twi = c->twi;
-        f.n = J.n; f.k = J.k; f.M = J.n; f.lanes = J.lanes; f.logn = ilog2(J.n); f.logm = f.logn;
+        const uint32_t N = pad_pow2(J.n);   // a shorter code: rows J.n..N-1 are not written
+        f.n = N; f.k = J.k; f.M = N; f.lanes = J.lanes; f.logn = ilog2(N); f.logm = f.logn;
+        f.rows_out = J.n < N ? J.n : 0;
         f.tiles = (J.lanes + kFourStepTile - 1) / kFourStepTile;
         f.vec = aligned16(J.in, J.ld_in, J.stride_in) && aligned16(J.out, J.ld_out, J.stride_out);
         s.batch = J.batch;
         s.ld_scratch = (uint64_t)f.tiles * kFourStepTile;
-        s.scratch_need = (size_t)J.batch * J.n * s.ld_scratch;
-        s.work = (uint64_t)J.lanes * J.batch * (J.n / 2) * f.logn;
+        s.scratch_need = (size_t)J.batch * N * s.ld_scratch;
+        s.work = (uint64_t)J.lanes * J.batch * (N / 2) * f.logn;
         P.singles.push_back(s);
       } else {
         classes[std::make_tuple(0, logK, 0)].push_back(j);
@@ -113,8 +115,8 @@ int make_plan(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, Plan& P) {
     } else if (J.op == FNTRS_OP_DECODE) {
       const fntrs_locator_t* L = J.loc;
       if (!L) return fail(c, FNTRS_E_INVAL, "job %u: a decode job needs a locator", j);
-      if ((J.n && J.n != L->n) || (J.k && J.k != L->k))
-        return fail(c, FNTRS_E_INVAL, "job %u: n=%u k=%u differ from the locator's n=%u k=%u", j, J.n, J.k, L->n,
+      if ((J.n && J.n != L->nrows) || (J.k && J.k != L->k))
+        return fail(c, FNTRS_E_INVAL, "job %u: n=%u k=%u differ from the locator's n=%u k=%u", j, J.n, J.k, L->nrows,
                     L->k);
       if (int rc = check_decode(c, L, J.lanes, J.flags, J.in, J.ld_in, J.stride_in, J.out, J.ld_out, J.stride_out,
                                 J.batch)) {
@@ -122,7 +124,7 @@ int make_plan(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, Plan& P) {
         return rc;
       }
       const bool full = J.flags & FNTRS_RECV_FULL;
-      const uint32_t rrows = full ? L->n : L->k;
+      const uint32_t rrows = full ? L->nrows : L->k;
       spans.push_back({(uintptr_t)J.in,
                        (uintptr_t)J.in + span_elems(J.batch, J.stride_in, rrows, J.ld_in, J.lanes) * 4, j, false});
       spans.push_back({(uintptr_t)J.out,
@@ -195,13 +197,15 @@ int make_plan(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, Plan& P) {
         a.src = J.in; a.ld_src = J.ld_in; a.stride_src = J.stride_in;
         a.dst = J.out; a.ld_dst = J.ld_out; a.stride_dst = J.stride_out;
         a.tw = c->tw; a.twi = c->twi;
-        a.n = J.n; a.k = J.k; a.lanes = J.lanes;
-        a.logn = ilog2(J.n); a.logK = cl.L;
-        a.tiles = tiles; a.cosets = J.n >> cl.L;
+        const uint32_t N = pad_pow2(J.n);
+        a.n = N; a.k = J.k; a.lanes = J.lanes;
+        a.logn = ilog2(N); a.logK = cl.L;
+        a.tiles = tiles; a.cosets = N >> cl.L;
+        a.rows_out = J.n < N ? J.n : 0;
         a.vec = aligned16(J.in, J.ld_in, J.stride_in) && aligned16(J.out, J.ld_out, J.stride_out);
         std::memcpy(P.blob.data() + cl.jobs_off + i * sizeof(EncodeArgs), &a, sizeof a);
         total += (uint64_t)tiles * a.cosets * J.batch;
-        cl.work += (uint64_t)J.lanes * J.batch * (J.n / 2) * cl.L;
+        cl.work += (uint64_t)J.lanes * J.batch * (N / 2) * cl.L;
       } else {
         const fntrs_locator_t* L = J.loc;
         DecodeArgs a{};

@@ -78,6 +78,8 @@ SIGNATURES = {
     "fntrs_locator_export": (_int, [_vp, _vp, _pu32, _pu32, _pu32]),
     "fntrs_decode": (_int, [_vp, _vp, _u32, _u32, _vp, _sz, _sz, _vp, _sz, _sz, _u32, _vp]),
     "fntrs_submit": (_int, [_vp, _pjob, _u32, _vp]),
+    "fntrs_pack16": (_int, [_vp, _vp, _sz, _sz, _u32, _u32, _u32, _vp, _sz, _sz, _vp, _vp, _u32, _vp]),
+    "fntrs_unpack16": (_int, [_vp, _vp, _sz, _sz, _u32, _u32, _u32, _vp, _vp, _u32, _vp, _sz, _sz, _vp]),
     "fntrs_graph_create": (_int, [_vp, _pjob, _u32, ctypes.POINTER(_vp)]),
     "fntrs_graph_launch": (_int, [_vp, _vp, _vp]),
     "fntrs_graph_destroy": (_int, [_vp, _vp]),
@@ -352,6 +354,36 @@ class Context:
     def submit(self, jobs, stream=None) -> None:
         """Enqueues a batch of jobs (encode_job / decode_job) in one call."""
         _check(self.handle, fntrs_submit(self.handle, jobs, _stream_handle(stream)))
+
+    # ------------------------------------------------------- 16-bit transport
+    def pack16(self, src, out16, esc_count, esc_pos, stream=None) -> None:
+        """out16 (int16 tensor, the same shape as src) <- src mod 65536; the
+        lanes holding 65536 of row r of block b go to esc_count[b*rows + r]
+        and esc_pos[b*rows + r, :] (int32 tensors; esc_pos has one row of
+        capacity per symbol)."""
+        b, rows, lanes, ld_s, st_s = _geom(src)
+        b2, rows2, lanes2, ld_o, st_o = _geom(out16, rows)
+        if (b2, lanes2) != (b, lanes):
+            raise ValueError("src and out16 disagree")
+        cap = esc_pos.shape[-1] if esc_pos.numel() else 0
+        if esc_count.numel() < b * rows or (cap and esc_pos.numel() < b * rows * cap):
+            raise ValueError("escape buffers too small")
+        _check(self.handle, lib().fntrs_pack16(self.handle, src.data_ptr(), ld_s, st_s, rows, lanes, b,
+                                               out16.data_ptr(), ld_o, st_o, esc_count.data_ptr(),
+                                               esc_pos.data_ptr() if cap else None, cap, _stream_handle(stream)))
+
+    def unpack16(self, in16, esc_count, esc_pos, dst, stream=None) -> None:
+        """Inverse of pack16: dst (int32) <- in16 widened, listed lanes 65536."""
+        b, rows, lanes, ld_i, st_i = _geom(in16)
+        b2, rows2, lanes2, ld_d, st_d = _geom(dst, rows)
+        if (b2, lanes2) != (b, lanes):
+            raise ValueError("in16 and dst disagree")
+        cap = esc_pos.shape[-1] if esc_pos.numel() else 0
+        if esc_count.numel() < b * rows or (cap and esc_pos.numel() < b * rows * cap):
+            raise ValueError("escape buffers too small")
+        _check(self.handle, lib().fntrs_unpack16(self.handle, in16.data_ptr(), ld_i, st_i, rows, lanes, b,
+                                                 esc_count.data_ptr(), esc_pos.data_ptr() if cap else None, cap,
+                                                 dst.data_ptr(), ld_d, st_d, _stream_handle(stream)))
 
     def graph(self, jobs) -> "Graph":
         """Captures a batch into a replayable HIP graph."""

@@ -67,7 +67,10 @@ def test_encode_validation(hctx):
     assert "host-only" in fntrs.fntrs_last_error(hctx)
     assert enc(hctx, 1, 1, 1) == fntrs.FNTRS_E_DEVICE
     assert enc(hctx, 65536, 3, 1) == fntrs.FNTRS_E_DEVICE           # any k <= n
-    for n, k in [(0, 1), (3, 1), (131072, 1), (96, 4), (8, 0), (8, 9)]:
+    assert enc(hctx, 3, 1, 4) == fntrs.FNTRS_E_DEVICE               # punctured lengths (Sec. II-B)
+    assert enc(hctx, 96, 4, 4) == fntrs.FNTRS_E_DEVICE
+    assert enc(hctx, 40000, 16384, 4) == fntrs.FNTRS_E_DEVICE
+    for n, k in [(0, 1), (65537, 1), (131072, 1), (8, 0), (8, 9), (96, 97)]:
         assert enc(hctx, n, k, 4) == fntrs.FNTRS_E_INVAL, (n, k)
     assert enc(hctx, 8, 4, 0) == fntrs.FNTRS_E_INVAL                # no lanes
     assert enc(hctx, 8, 4, 4, batch=0) == fntrs.FNTRS_E_INVAL
@@ -101,7 +104,9 @@ def test_locator_validation(hctx):
     assert fntrs.fntrs_locator(hctx, 16, 4, [3, 2, 5, 9])[0] == fntrs.FNTRS_E_POSITIONS
     assert fntrs.fntrs_locator(hctx, 16, 4, [1, 2, 3, 16])[0] == fntrs.FNTRS_E_POSITIONS
     assert fntrs.fntrs_locator(hctx, 16, 3, [1, 2, 3])[0] == fntrs.FNTRS_E_UNSUPPORTED
-    assert fntrs.fntrs_locator(hctx, 12, 4, [1, 2, 3, 4])[0] == fntrs.FNTRS_E_INVAL
+    assert fntrs.fntrs_locator(hctx, 12, 4, [1, 2, 3, 4])[0] == fntrs.FNTRS_E_DEVICE   # punctured length
+    assert fntrs.fntrs_locator(hctx, 12, 4, [1, 2, 3, 12])[0] == fntrs.FNTRS_E_POSITIONS
+    assert fntrs.fntrs_locator(hctx, 65537, 4, [1, 2, 3, 4])[0] == fntrs.FNTRS_E_INVAL
     assert fntrs.fntrs_locator(hctx, 16, 0, [1])[0] == fntrs.FNTRS_E_INVAL
     # more than k received: the first k are used, the rest are not checked for order
     assert fntrs.fntrs_locator(hctx, 16, 2, [1, 5, 3])[0] == fntrs.FNTRS_E_DEVICE
@@ -158,7 +163,7 @@ def test_submit_validation(hctx):
     assert fntrs.fntrs_submit(hctx, ok) == fntrs.FNTRS_E_DEVICE      # valid batch, no device
     assert fntrs.fntrs_submit(hctx, []) == fntrs.FNTRS_E_DEVICE
     # one bad job names its index
-    bad = ok + [ejob(96, 4, 4, SRC + 3 * MB, DST + 3 * MB)]
+    bad = ok + [ejob(96, 97, 4, SRC + 3 * MB, DST + 3 * MB)]
     assert fntrs.fntrs_submit(hctx, bad) == fntrs.FNTRS_E_INVAL
     assert "job 3" in fntrs.fntrs_last_error(hctx)
     # an output overlapping another job's input
@@ -213,3 +218,27 @@ def test_locator_batch_validation(hctx):
     assert fntrs.fntrs_locator_batch(hctx, [], [], [])[0] == fntrs.FNTRS_OK
     L = fntrs.lib()
     assert L.fntrs_locator_batch(hctx, 1, None, None, None, None, None, None) == fntrs.FNTRS_E_INVAL
+
+
+def test_wire_validation(hctx):
+    """fntrs_pack16 / fntrs_unpack16 argument checks (16-bit transport, Sec. II-B)."""
+    L = fntrs.lib()
+    CNT, POS = SRC + (1 << 22), SRC + (1 << 23)
+    ok = (hctx, SRC, 64, 64 * 8, 8, 64, 2, DST, 64, 64 * 8, CNT, POS, 64, None)
+    assert L.fntrs_pack16(*ok) == fntrs.FNTRS_E_DEVICE
+    assert L.fntrs_unpack16(hctx, SRC, 64, 64 * 8, 8, 64, 2, CNT, POS, 64, DST, 64, 64 * 8, None) \
+        == fntrs.FNTRS_E_DEVICE
+    assert L.fntrs_pack16(hctx, SRC, 64, 512, 8, 64, 2, DST, 64, 512, CNT, None, 0, None) == fntrs.FNTRS_E_DEVICE
+    bad = [
+        (hctx, SRC, 64, 512, 0, 64, 2, DST, 64, 512, CNT, POS, 64, None),       # no rows
+        (hctx, SRC, 64, 512, 8, 0, 2, DST, 64, 512, CNT, POS, 64, None),        # no lanes
+        (hctx, SRC, 32, 512, 8, 64, 2, DST, 64, 512, CNT, POS, 64, None),       # ld < lanes
+        (hctx, SRC, 64, 100, 8, 64, 2, DST, 64, 512, CNT, POS, 64, None),       # blocks overlap
+        (hctx, None, 64, 512, 8, 64, 2, DST, 64, 512, CNT, POS, 64, None),
+        (hctx, SRC, 64, 512, 8, 64, 2, DST, 64, 512, None, POS, 64, None),
+        (hctx, SRC, 64, 512, 8, 64, 2, DST, 64, 512, CNT, None, 64, None),      # cap without a list
+        (hctx, SRC, 70000, 70000, 1, 70000, 1, DST, 70000, 70000, CNT, POS, 0, None),   # lanes > 65536
+    ]
+    for args in bad:
+        assert L.fntrs_pack16(*args) == fntrs.FNTRS_E_INVAL, args
+    assert L.fntrs_pack16(None, *ok[1:]) == fntrs.FNTRS_E_INVAL

@@ -1,0 +1,167 @@
+"""Punctured code lengths and the 16-bit transport (Sec. II-B) on the GPU.
+
+A length n that is not a power of two is the code of length N = the next
+power of two with its last N - n symbols never sent; every value but 65536 is
+sent as 16 bits and the positions of 65536 travel apart.  Results are exact:
+compared with the oracle element by element.
+"""
+import numpy as np
+import pytest
+
+from oracle import codec
+from paper_0907_1788_amd import fntrs, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = fntrs.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a).astype(np.int32)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy().astype(np.int64)
+
+
+def punctured_positions(seed, n, k):
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n, k, replace=False)).astype(np.uint32)
+
+
+# n (not a power of two), k, lanes: lane tiles, four-step sizes, k = n
+PUNCT = [(3, 2, 5), (6, 4, 7), (100, 64, 33), (1000, 512, 9), (3000, 1024, 6), (6000, 4096, 5), (20000, 8192, 3),
+         (40000, 16384, 2), (65535, 32768, 2), (100, 100, 4)]
+
+
+@pytest.mark.parametrize("n,k,lanes", PUNCT)
+def test_punctured_encode_and_decode(ctx, n, k, lanes):
+    say("punctured", n, k, lanes)
+    src = synth.residues(6000 + n, (2, k, lanes))
+    e = torch.full((2, n + 1, lanes), -7, dtype=torch.int32, device="cuda")
+    ctx.encode(dev(src), e[:, :n, :], n)
+    torch.cuda.synchronize()
+    out = host(e)
+    assert np.all(out[:, n, :] == -7), "wrote past row n"
+    out = out[:, :n, :]
+    rows = np.arange(n) if n * k <= 2 ** 22 else np.unique(
+        np.concatenate([[0, n - 1, n // 2], synth.stream(n, 10) % np.uint64(n)]).astype(np.int64))
+    for b in range(2):
+        assert np.array_equal(out[b][rows][:, :2], codec.encode_punctured(src[b][:, :2], n, rows=rows)), b
+    if k & (k - 1) == 0:                       # the decoder takes k a power of two
+        z = punctured_positions(6100 + n, n, k)
+        loc = ctx.locator(n, k, z)
+        d = torch.empty((2, k, lanes), dtype=torch.int32, device="cuda")
+        ctx.decode(loc, dev(out[:, z, :]), d, fntrs.FNTRS_RECV_COMPACT)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(d), src.astype(np.int64))
+        ctx.decode(loc, dev(out), d, fntrs.FNTRS_RECV_FULL)     # a full buffer has n rows
+        torch.cuda.synchronize()
+        assert np.array_equal(host(d), src.astype(np.int64))
+        loc.release()
+
+
+def test_punctured_systematic_and_batched(ctx):
+    """The systematic flag and the batched path with punctured lengths."""
+    say("punctured systematic + batch")
+    n, k, lanes = 600, 256, 17
+    src = synth.residues(6200, (1, k, lanes))
+    e = torch.empty((1, n, lanes), dtype=torch.int32, device="cuda")
+    ctx.encode(dev(src), e, n, flags=fntrs.FNTRS_SYSTEMATIC)
+    torch.cuda.synchronize()
+    got = host(e)[0]
+    assert np.array_equal(got[:k], src[0].astype(np.int64))
+    rows = np.arange(k, n, 7)
+    ref = codec.encode(codec.systematic_intermediate(src[0][:, :2], 1024), 1024, rows=rows)
+    assert np.array_equal(got[rows][:, :2], ref)
+    # batched encode jobs of punctured lengths equal the single calls
+    specs = [(600, 256, 17), (3000, 1024, 40), (40000, 16384, 3)]
+    srcs = [dev(synth.residues(6300 + i, (1, kk, ll))) for i, (nn, kk, ll) in enumerate(specs)]
+    outs = [torch.full((1, nn, ll), -7, dtype=torch.int32, device="cuda") for nn, kk, ll in specs]
+    ctx.submit([ctx.encode_job(s_, o_, nn) for s_, o_, (nn, kk, ll) in zip(srcs, outs, specs)])
+    for s_, o_, (nn, kk, ll) in zip(srcs, outs, specs):
+        one = torch.empty_like(o_)
+        ctx.encode(s_, one, nn)
+        torch.cuda.synchronize()
+        assert torch.equal(one, o_), nn
+
+
+def oracle_pack(v):
+    """Per row: 16-bit words and the ascending lanes holding 65536."""
+    words = np.empty(v.shape, dtype=np.int64)
+    esc = []
+    for idx in np.ndindex(v.shape[:-1]):
+        w, e = codec.pack16(v[idx])
+        words[idx] = w.astype(np.int64)
+        esc.append(e)
+    return words, esc
+
+
+@pytest.mark.parametrize("batch,rows,lanes", [(1, 1, 1), (2, 5, 3), (3, 17, 300), (1, 64, 2048), (2, 9, 257)])
+def test_pack16_unpack16(ctx, batch, rows, lanes):
+    say("pack16", batch, rows, lanes)
+    v = synth.residues(6400 + rows + lanes, (batch, rows, lanes))
+    v[0, 0, ::max(1, lanes // 3)] = 65536          # several escapes in one row
+    src = dev(v)
+    out16 = torch.zeros((batch, rows, lanes), dtype=torch.int16, device="cuda")
+    cnt = torch.full((batch * rows,), -1, dtype=torch.int32, device="cuda")
+    pos = torch.full((batch * rows, lanes), -1, dtype=torch.int32, device="cuda")
+    ctx.pack16(src, out16, cnt, pos)
+    torch.cuda.synchronize()
+    words, esc = oracle_pack(v.astype(np.int64))
+    assert np.array_equal(out16.cpu().numpy().astype(np.int64) & 0xFFFF, words)
+    c = cnt.cpu().numpy()
+    p = pos.cpu().numpy()
+    for i, e in enumerate(esc):
+        assert c[i] == e.size
+        assert np.array_equal(p[i, :e.size], e), i
+    back = torch.full((batch, rows, lanes), -7, dtype=torch.int32, device="cuda")
+    ctx.unpack16(out16, cnt, pos, back)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(back), v.astype(np.int64))
+
+
+def test_pack16_capacity_and_wire_roundtrip(ctx):
+    """A row with more escapes than the capacity reports its full count; a
+    codeword sent as 16-bit words plus escapes decodes to the source."""
+    say("pack16 capacity, wire roundtrip")
+    v = np.full((1, 2, 40), 65536, dtype=np.uint32)
+    v[0, 1, :] = 5
+    out16 = torch.zeros((1, 2, 40), dtype=torch.int16, device="cuda")
+    cnt = torch.zeros(2, dtype=torch.int32, device="cuda")
+    pos = torch.full((2, 4), -1, dtype=torch.int32, device="cuda")
+    ctx.pack16(dev(v), out16, cnt, pos)
+    torch.cuda.synchronize()
+    assert list(cnt.cpu().numpy()) == [40, 0]
+    assert list(pos.cpu().numpy()[0]) == [0, 1, 2, 3] and list(pos.cpu().numpy()[1]) == [-1] * 4
+    # encode, pack every symbol, keep k of them, unpack, decode
+    n, k, lanes = 512, 256, 64
+    src = synth.residues(6500, (1, k, lanes))
+    e = torch.empty((1, n, lanes), dtype=torch.int32, device="cuda")
+    ctx.encode(dev(src), e, n)
+    w16 = torch.empty((1, n, lanes), dtype=torch.int16, device="cuda")
+    cnt = torch.empty(n, dtype=torch.int32, device="cuda")
+    pos = torch.empty((n, lanes), dtype=torch.int32, device="cuda")
+    ctx.pack16(e, w16, cnt, pos)
+    z = synth.received_positions(6501, n, k)
+    zi = torch.from_numpy(z.astype(np.int64)).cuda()
+    recv = torch.empty((1, k, lanes), dtype=torch.int32, device="cuda")
+    ctx.unpack16(w16.index_select(1, zi).contiguous(), cnt.index_select(0, zi).contiguous(),
+                 pos.index_select(0, zi).contiguous(), recv)
+    loc = ctx.locator(n, k, z)
+    d = torch.empty((1, k, lanes), dtype=torch.int32, device="cuda")
+    ctx.decode(loc, recv, d, fntrs.FNTRS_RECV_COMPACT)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(d), src.astype(np.int64))
+    loc.release()
