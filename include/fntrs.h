@@ -99,8 +99,7 @@ const char* fntrs_last_error(const fntrs_ctx* ctx);
  * interpolated on positions 0..k-1 into k intermediate symbols (the decoder,
  * with the locator of that pattern, which the context builds once and
  * caches), and dst is the transform above of the intermediate symbols, so
- * that dst rows 0..k-1 equal src; k must then be a power of two
- * (FNTRS_E_UNSUPPORTED otherwise), and the call holds a scratch of
+ * that dst rows 0..k-1 equal src; the call holds a scratch of
  * batch*k*lanes words of device memory, allocated and freed on `stream`.
  * Errors: FNTRS_E_INVAL, FNTRS_E_DEVICE, FNTRS_E_RANGE (validate flag),
  * FNTRS_E_NOMEM, FNTRS_E_UNSUPPORTED. */
@@ -121,10 +120,13 @@ int fntrs_encode(fntrs_ctx* ctx, uint32_t n, uint32_t k, uint32_t lanes,
  *   and the FNT of size 2k of the low coefficients of A.
  * A pattern already in the context's cache is returned without rebuilding.
  * *out receives a reference that must be given back with
- * fntrs_locator_release.  k must be a power of two (k = n is allowed: no
- * erasure).  Errors: FNTRS_E_INVAL, FNTRS_E_TOOFEW (npos < k),
- * FNTRS_E_POSITIONS, FNTRS_E_UNSUPPORTED (k not a power of two),
- * FNTRS_E_NOMEM, FNTRS_E_DEVICE. */
+ * fntrs_locator_release.  Any 1 <= k <= n (k = n is allowed: no erasure); a
+ * k that is not a power of two runs the product tree on the next power of
+ * two with the extra roots at 0 and divides their factor out.  Errors:
+ * FNTRS_E_INVAL, FNTRS_E_TOOFEW (npos < k), FNTRS_E_POSITIONS,
+ * FNTRS_E_UNSUPPORTED (k < N with 2K > N, N and K the powers of two at or
+ * above n and k: the low product would be longer than the transform; this
+ * includes 32768 < k < n), FNTRS_E_NOMEM, FNTRS_E_DEVICE. */
 int fntrs_locator(fntrs_ctx* ctx, uint32_t n, uint32_t k,
                   const uint32_t* positions, uint32_t npos,
                   void* stream, fntrs_locator_t** out);
@@ -150,7 +152,8 @@ int fntrs_locator_release(fntrs_ctx* ctx, fntrs_locator_t* loc);
 /* Copy a locator's state to host memory (synchronous; for inspection and
  * tests).  Any pointer may be NULL.  A: k+1 coefficients of A(x), lowest
  * first; w: k values 1/A'(x_i); ahat: 2k values FNT_2k(a_0..a_(k-1),0..0) in
- * natural order.  For k = n only A is meaningful (x^n - 1).  Returns
+ * natural order, written only when k is a power of two (the transform of
+ * length 2k exists only then).  For k = n only A is meaningful (x^n - 1).  Returns
  * FNTRS_OK, FNTRS_E_INVAL or FNTRS_E_DEVICE. */
 int fntrs_locator_export(fntrs_ctx* ctx, const fntrs_locator_t* loc,
                          uint32_t* A, uint32_t* w, uint32_t* ahat);

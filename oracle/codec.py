@@ -164,7 +164,8 @@ def locator(n: int, positions, with_w: bool = True) -> dict:
     w     -- w_i = 1 / A'(x_i) = 1 / prod_{j != i}(x_i - x_j) (step 3 and
              the identity A_i(x_i) = A'(x_i))
     Ahat  -- FNT_(2k) of (a_0 .. a_(k-1), 0 .. 0), used for the low product
-             of step 6 (requires 2k <= 65536)
+             of step 6 (requires 2k a power of two <= 65536: the transform
+             has power-of-two lengths, Sec. II-A)
     """
     z = np.asarray(positions, dtype=np.int64)
     k = z.size
@@ -174,7 +175,7 @@ def locator(n: int, positions, with_w: bool = True) -> dict:
     out = {"x": x, "A": A, "dA": dA}
     if with_w:
         out["w"] = inverse_array(lagrange_denominators(x))
-    if 2 * k <= 65536:
+    if 2 * k <= 65536 and k & (k - 1) == 0:
         pad = np.zeros(2 * k, dtype=np.int64)
         pad[:k] = A[:k]
         out["Ahat"] = fnt(pad)

@@ -377,12 +377,13 @@ static int build_locators(fntrs_ctx* c, std::vector<fntrs_locator_t*>& Ls, hipSt
     zoff[i] = zall.size();
     zall.insert(zall.end(), L->positions.begin(), L->positions.end());
     soff[i] = scratch;
-    if (k < n) scratch += 3 * round_words(k) + round_words(n);
+    const size_t kt = pad_pow2(L->k);    // points of the product tree
+    if (k < n) scratch += 3 * round_words(kt) + round_words(n);
     LocDesc& d = desc[i];
     d = LocDesc{};
     d.pos = L->pos; d.wfull = L->wfull; d.ridx = L->ridx; d.ahat_br = L->ahat_br; d.ahat_s = L->ahat_s;
     d.A = L->A; d.w = L->w; d.ahat = L->ahat;
-    d.n = L->n; d.k = L->k; d.G = std::min<uint32_t>(L->k, 64);
+    d.n = L->n; d.k = (uint32_t)kt; d.kr = L->k; d.G = std::min<uint32_t>((uint32_t)kt, 64);
     d.logn = L->logn; d.logk = L->logk; d.logm = L->logm;
   }
   // stage tables: (range of descriptors, start offsets relative to the range)
@@ -404,22 +405,23 @@ static int build_locators(fntrs_ctx* c, std::vector<fntrs_locator_t*>& Ls, hipSt
     return st;
   };
   const Stage prep = add_stage({0, P}, [](const fntrs_locator_t* L) { return (uint64_t)L->k + L->n; });
-  const Stage leaves =
-      add_stage({0, Pn}, [](const fntrs_locator_t* L) { return (uint64_t)L->k / std::min<uint32_t>(L->k, 64); });
+  const Stage leaves = add_stage({0, Pn}, [](const fntrs_locator_t* L) {
+    return (uint64_t)pad_pow2(L->k) / std::min<uint32_t>(pad_pow2(L->k), 64);
+  });
   std::vector<std::pair<int, Stage>> levels;   // (log2 d, stage)
   for (int logd = 6; logd <= 15; ++logd) {
     uint32_t first = 0;
-    while (first < Pn && Ls[first]->k <= (1u << logd)) ++first;
+    while (first < Pn && pad_pow2(Ls[first]->k) <= (1u << logd)) ++first;
     if (first == Pn) break;
     levels.emplace_back(logd, add_stage({first, Pn - first}, [logd](const fntrs_locator_t* L) {
-                          return (uint64_t)L->k >> (logd + 1);
+                          return (uint64_t)pad_pow2(L->k) >> (logd + 1);
                         }));
   }
-  const Stage deriv = add_stage({0, Pn}, [](const fntrs_locator_t* L) { return (uint64_t)L->k; });
-  std::vector<std::pair<int, Stage>> evals;   // (log2 k, stage)
+  const Stage deriv = add_stage({0, Pn}, [](const fntrs_locator_t* L) { return (uint64_t)pad_pow2(L->k); });
+  std::vector<std::pair<int, Stage>> evals;   // (log2 of the tree size, stage)
   for (uint32_t first = 0; first < Pn;) {
     uint32_t last = first;
-    while (last < Pn && Ls[last]->k == Ls[first]->k) ++last;
+    while (last < Pn && Ls[last]->logk == Ls[first]->logk) ++last;
     evals.emplace_back(Ls[first]->logk, add_stage({first, last - first}, [](const fntrs_locator_t* L) {
                          return (uint64_t)(L->n >> L->logk) + ((1ull << L->logm) >> L->logk);
                        }));
@@ -447,7 +449,7 @@ static int build_locators(fntrs_ctx* c, std::vector<fntrs_locator_t*>& Ls, hipSt
   for (uint32_t i = 0; i < P; ++i) {
     LocDesc& d = desc[i];
     d.zin = dz + zoff[i];
-    if (d.k < d.n) {
+    if (d.kr < d.n) {   // an erasure pattern: the scratch reserved under L->k < L->n
       uint32_t* q = dscr + soff[i];
       const size_t kw = round_words(d.k);
       d.t0 = q; d.t1 = q + kw; d.spec = q + 2 * kw; d.vals = q + 3 * kw;
@@ -538,12 +540,15 @@ int locators_acquire(fntrs_ctx* c, uint32_t count, const uint32_t* n_, const uin
     else if (k < 1 || k > n) rc = fail(c, FNTRS_E_INVAL, "k=%u must satisfy 1 <= k <= n=%u", k, n);
     else if (!positions) rc = fail(c, FNTRS_E_INVAL, "null positions");
     else if (npos < k) rc = fail(c, FNTRS_E_TOOFEW, "%u positions received, k=%u needed", npos, k);
+    else if (k < pad_pow2(n) && 2 * pad_pow2(k) > pad_pow2(n))
+      rc = fail(c, FNTRS_E_UNSUPPORTED,
+                "k=%u above half the transform length %u (k not a power of two, or 32768 < k < n): "
+                "the low product would be longer than the transform", k, pad_pow2(n));
     for (uint32_t i = 0; !rc && i < k; ++i) {
       if (positions[i] >= n) rc = fail(c, FNTRS_E_POSITIONS, "position %u at index %u is >= n=%u", positions[i], i, n);
       else if (i && positions[i] <= positions[i - 1])
         rc = fail(c, FNTRS_E_POSITIONS, "positions must be strictly ascending (index %u)", i);
     }
-    if (!rc && !is_pow2(k)) rc = fail(c, FNTRS_E_UNSUPPORTED, "decoding needs k a power of two, got %u", k);
     if (rc) {
       if (count > 1) c->err = "pattern " + std::to_string(q) + ": " + c->err;
       give_back(q);
@@ -852,8 +857,6 @@ int fntrs_encode(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uin
   std::lock_guard<std::mutex> lk(c->mu);
   c->err.clear();
   if (int rc = check_encode(c, n, k, lanes, src, ld_src, stride_src, dst, ld_dst, stride_dst, batch, flags)) return rc;
-  if ((flags & FNTRS_SYSTEMATIC) && !is_pow2(k))
-    return fail(c, FNTRS_E_UNSUPPORTED, "the systematic code needs k a power of two, got %u", k);
   if (c->device == FNTRS_HOST_ONLY) return fail(c, FNTRS_E_DEVICE, "host-only context: arguments valid, no device");
   DeviceGuard g(c->device);
   hipStream_t s = (hipStream_t)stream;
@@ -901,7 +904,7 @@ int fntrs_locator_export(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t* A, ui
   HIP_TRY(c, hipEventSynchronize(L->ready));
   if (A) HIP_TRY(c, hipMemcpy(A, L->A, (L->k + 1) * 4ull, hipMemcpyDeviceToHost));
   if (w) HIP_TRY(c, hipMemcpy(w, L->w, L->k * 4ull, hipMemcpyDeviceToHost));
-  if (ahat && L->k != L->n) {
+  if (ahat && L->k != L->n && is_pow2(L->k)) {
     // FNT_2k values are the FNT_M values at multiples of M/2k
     const size_t M = (size_t)1 << L->logm, step = M / (2ull * L->k);
     std::vector<uint32_t> h(M);

@@ -31,7 +31,8 @@ struct LocDesc {
   uint32_t* spec;           // scratch: parked transforms, then A', k words
   uint32_t* vals;           // scratch: A' at every n-th root, n words
   uint32_t* poly;           // t0 or t1: where the tree leaves A mod x^k
-  uint32_t n, k, G;         // G points per leaf
+  uint32_t n, k, G;         // k: points of the product tree (a power of two); G points per leaf
+  uint32_t kr;              // received positions (k rounded up to the tree is padded with roots at 0)
   int logn, logk, logm;
 };
 
@@ -55,16 +56,16 @@ __global__ void k_locb_prep(const LocDesc* __restrict__ D, const uint32_t* __res
   if (x >= start[count]) return;
   const uint32_t i = loc_find(start, count, x);
   const LocDesc& d = D[i];
-  const uint32_t j = x - start[i];   // j < k + n
-  if (j < d.k) {
+  const uint32_t j = x - start[i];   // j < kr + n
+  if (j < d.kr) {
     d.pos[j] = d.zin[j];
-    if (d.k == d.n) {
+    if (d.kr == d.n) {
       d.A[j] = j == 0 ? 65536u : 0u;
-      if (j == 0) d.A[d.k] = 1u;
+      if (j == 0) d.A[d.kr] = 1u;
     }
   } else {
-    const uint32_t z = j - d.k;
-    if (d.k == d.n) {
+    const uint32_t z = j - d.kr;
+    if (d.kr == d.n) {
       d.wfull[z] = 65537u - (65536u >> d.logn);
       d.ridx[z] = z;
     } else {
@@ -88,8 +89,9 @@ __global__ void __launch_bounds__(64) k_locb_leaves(const LocDesc* __restrict__ 
   const uint32_t g = blockIdx.x - start[i];
   const int G = (int)d.G;
   const int t = (int)threadIdx.x;
-  // the leaves: monic degree 1, low coefficient -x_i
-  if (t < G) c[0][t] = fsub(0u, point_of(tw, d.zin[g * G + t], d.logn));
+  // the leaves: monic degree 1, low coefficient -x_i; the points past the
+  // received ones are roots at 0 (the tree then yields A(x) x^(k - kr))
+  if (t < G) c[0][t] = g * G + t < d.kr ? fsub(0u, point_of(tw, d.zin[g * G + t], d.logn)) : 0u;
   __syncthreads();
   int cur = 0;
   for (int h = 1; h < G; h <<= 1) {
@@ -200,27 +202,34 @@ __global__ void __launch_bounds__(1024) k_locb_level(const LocDesc* __restrict__
   }
 }
 
-// Step 2, one thread per coefficient: A (monic, degree k) into the state and
-// A'(x): coefficient j of A' is (j+1) a_(j+1), with a_k = 1.
+// Step 2, one thread per coefficient of the tree (k of them): A (monic,
+// degree kr) into the state -- the tree holds A(x) x^(k - kr), so a_j is its
+// coefficient j + k - kr -- and A'(x): coefficient j of A' is (j+1) a_(j+1),
+// with a_kr = 1, and zero from kr on (the evaluation reads k coefficients).
 __global__ void k_locb_derivative(const LocDesc* __restrict__ D, const uint32_t* __restrict__ start, uint32_t count) {
   const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= start[count]) return;
   const uint32_t i = loc_find(start, count, x);
   const LocDesc& d = D[i];
   const uint32_t j = x - start[i];
-  const uint32_t next = (j + 1 < d.k) ? d.poly[j + 1] : 1u;
-  d.A[j] = d.poly[j];
-  if (j == 0) d.A[d.k] = 1u;
-  d.spec[j] = fmul(next, (j + 1) % 65537u);
+  const uint32_t shift = d.k - d.kr;
+  if (j < d.kr) {
+    const uint32_t next = (j + 1 < d.kr) ? d.poly[j + 1 + shift] : 1u;
+    d.A[j] = d.poly[j + shift];
+    d.spec[j] = fmul(next, (j + 1) % 65537u);
+  } else {
+    d.spec[j] = 0u;
+  }
+  if (j == 0) d.A[d.kr] = 1u;
 }
 
 // Evaluate a polynomial with K = 2^logK coefficients at every N-th root of
 // unity, N = K * cosets: the value at r_N^(t + cosets m) is FNT_K of
 // (c_j r_N^(t j))_j at m (Sec. II-A, polynomial view of the FNT).  One
-// workgroup per coset t.  Every pattern of the launch has k = K.  A
-// pattern's first n/k workgroups evaluate A' at the n-th roots (step 3);
-// the next M/k evaluate A mod x^k at the M-th roots (the transform of A used
-// by the low product of step 6).
+// workgroup per coset t.  Every pattern of the launch has a tree of K
+// points.  A pattern's first n/K workgroups evaluate A' at the n-th roots
+// (step 3); the next M/K evaluate A mod x^kr at the M-th roots (the
+// transform of A used by the low product of step 6).
 __global__ void __launch_bounds__(1024) k_locb_eval(const LocDesc* __restrict__ D, const uint32_t* __restrict__ start,
                                                     uint32_t count, int logK, const uint32_t* __restrict__ tw) {
   extern __shared__ uint32_t lds[];
@@ -234,7 +243,8 @@ __global__ void __launch_bounds__(1024) k_locb_eval(const LocDesc* __restrict__ 
   const int logN = deriv ? d.logn : d.logm;
   const uint32_t N = 1u << logN;
   const uint32_t cosets = N >> logK;
-  const uint32_t* c = deriv ? d.spec : d.poly;
+  const uint32_t* c = deriv ? d.spec : d.A;       // A' (zero from kr on) or A mod x^kr
+  const uint32_t lim = deriv ? K : d.kr;
   uint32_t* vals = deriv ? d.vals : d.ahat;
   const uint32_t nt = blockDim.x;
   for (uint32_t j0 = threadIdx.x; j0 < K; j0 += kU * nt) {   // global reads of kU words first
@@ -242,7 +252,7 @@ __global__ void __launch_bounds__(1024) k_locb_eval(const LocDesc* __restrict__ 
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const uint32_t j = j0 + u * nt < K ? j0 + u * nt : j0;
-      v[u] = gptr(c)[j];
+      v[u] = j < lim ? gptr(c)[j] : 0u;
       w[u] = gptr(tw)[((t * j) & (N - 1)) << (16 - logN)];
     }
 #pragma unroll
@@ -401,14 +411,14 @@ __global__ void __launch_bounds__(loc_nt<LK>()) k_locb_eval_ct(const LocDesc* __
   if (!deriv) t -= ncos;
   const int logN = deriv ? d.logn : d.logm;
   EncodeArgs e{};
-  e.src = deriv ? d.spec : d.poly;
+  e.src = deriv ? d.spec : d.A;    // A' or A mod x^kr (rows from e.k on read as zero)
   e.ld_src = 1;
   e.dst = deriv ? d.vals : d.ahat;
   e.ld_dst = 1;
   e.tw = tw;
   e.twi = twi;
   e.n = 1u << logN;
-  e.k = 1u << LK;
+  e.k = deriv ? 1u << LK : d.kr;
   e.lanes = 1;
   e.logn = logN;
   e.logK = LK;

@@ -84,14 +84,12 @@ def test_encode_validation(hctx):
 
 
 def test_systematic_flag_validation(hctx):
-    """The systematic code (Sec. II-C) is a flag of the single calls: valid with
-    k a power of two, unsupported otherwise, rejected in batches."""
+    """The systematic code (Sec. II-C) is a flag of the single calls, rejected
+    in batches."""
     S = fntrs.FNTRS_SYSTEMATIC
     assert enc(hctx, 512, 256, 64, flags=S) == fntrs.FNTRS_E_DEVICE
     assert enc(hctx, 512, 256, 64, flags=S | fntrs.FNTRS_FLAG_VALIDATE) == fntrs.FNTRS_E_DEVICE
-    assert enc(hctx, 512, 200, 64, flags=S) == fntrs.FNTRS_E_UNSUPPORTED
-    assert "power of two" in fntrs.fntrs_last_error(hctx)
-    assert enc(hctx, 512, 200, 64) == fntrs.FNTRS_E_DEVICE              # fine without the flag
+    assert enc(hctx, 512, 200, 64, flags=S) == fntrs.FNTRS_E_DEVICE    # any k
     assert fntrs.fntrs_submit(hctx, [ejob(512, 256, 64, SRC, DST, flags=S)]) == fntrs.FNTRS_E_UNSUPPORTED
     assert "systematic" in fntrs.fntrs_last_error(hctx)
 
@@ -103,7 +101,11 @@ def test_locator_validation(hctx):
     assert fntrs.fntrs_locator(hctx, 16, 4, [1, 2, 2, 9])[0] == fntrs.FNTRS_E_POSITIONS
     assert fntrs.fntrs_locator(hctx, 16, 4, [3, 2, 5, 9])[0] == fntrs.FNTRS_E_POSITIONS
     assert fntrs.fntrs_locator(hctx, 16, 4, [1, 2, 3, 16])[0] == fntrs.FNTRS_E_POSITIONS
-    assert fntrs.fntrs_locator(hctx, 16, 3, [1, 2, 3])[0] == fntrs.FNTRS_E_UNSUPPORTED
+    assert fntrs.fntrs_locator(hctx, 16, 3, [1, 2, 3])[0] == fntrs.FNTRS_E_DEVICE      # any k <= N/2
+    assert fntrs.fntrs_locator(hctx, 16, 9, list(range(9)))[0] == fntrs.FNTRS_E_UNSUPPORTED   # 2K > N
+    assert fntrs.fntrs_locator(hctx, 100, 100, list(range(100)))[0] == fntrs.FNTRS_E_UNSUPPORTED
+    assert fntrs.fntrs_locator(hctx, 16, 16, list(range(16)))[0] == fntrs.FNTRS_E_DEVICE     # k = n
+    assert fntrs.fntrs_locator(hctx, 65536, 40000, list(range(40000)))[0] == fntrs.FNTRS_E_UNSUPPORTED
     assert fntrs.fntrs_locator(hctx, 12, 4, [1, 2, 3, 4])[0] == fntrs.FNTRS_E_DEVICE   # punctured length
     assert fntrs.fntrs_locator(hctx, 12, 4, [1, 2, 3, 12])[0] == fntrs.FNTRS_E_POSITIONS
     assert fntrs.fntrs_locator(hctx, 65537, 4, [1, 2, 3, 4])[0] == fntrs.FNTRS_E_INVAL
@@ -214,7 +216,8 @@ def test_locator_batch_validation(hctx):
     rc, hs = fntrs.fntrs_locator_batch(hctx, [16, 8], [4, 2], [[1, 2, 3, 9], [5, 0]])
     assert rc == fntrs.FNTRS_E_POSITIONS and "pattern 1" in fntrs.fntrs_last_error(hctx)
     assert fntrs.fntrs_locator_batch(hctx, [16], [4], [[1, 2]])[0] == fntrs.FNTRS_E_TOOFEW
-    assert fntrs.fntrs_locator_batch(hctx, [16], [3], [[1, 2, 4]])[0] == fntrs.FNTRS_E_UNSUPPORTED
+    assert fntrs.fntrs_locator_batch(hctx, [16], [3], [[1, 2, 4]])[0] == fntrs.FNTRS_E_DEVICE   # any k
+    assert fntrs.fntrs_locator_batch(hctx, [65536], [40000], [list(range(40000))])[0] == fntrs.FNTRS_E_UNSUPPORTED
     assert fntrs.fntrs_locator_batch(hctx, [], [], [])[0] == fntrs.FNTRS_OK
     L = fntrs.lib()
     assert L.fntrs_locator_batch(hctx, 1, None, None, None, None, None, None) == fntrs.FNTRS_E_INVAL

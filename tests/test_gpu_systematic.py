@@ -62,6 +62,7 @@ def sys_decode(ctx, loc, recv, flags):
 # n, k, lanes, batch; the oracle checks every row up to the first bound,
 # sampled rows beyond
 CASES = [(2, 1, 3, 1), (4, 2, 5, 2), (8, 4, 9, 1), (64, 32, 33, 1), (64, 64, 4, 1), (512, 256, 65, 2),
+         (8, 3, 4, 1), (512, 200, 9, 1), (8192, 3000, 3, 1),
          (1024, 128, 7, 1), (2048, 1024, 6, 1), (8192, 4096, 5, 1), (16384, 8192, 3, 1), (65536, 16384, 2, 1)]
 
 
