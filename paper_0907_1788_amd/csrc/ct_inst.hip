@@ -78,6 +78,52 @@ constexpr bool pipe_ok() {
   return ct::pass0_per_thread<L, Gm::BM, Gm::G, NT>() >= 1 && ct::plan_np(L, Gm::BM) >= 2;
 }
 
+// The all-cosets encoder needs a first and a last pass.  It holds a tile's
+// source rows in registers across the cosets, so it is used only where that
+// costs neither a spill nor resident workgroups against k_enc (checked once
+// per configuration).
+template <int L, int T, int NT, int V>
+constexpr bool cos_ok() {
+  using Gm = ct::Geo<L, T, NT, V>;
+  return L >= 2 && ct::plan_np(L, Gm::BM) >= 2;
+}
+
+template <class K>
+bool kernel_spills(K kernel) {
+  hipFuncAttributes at{};
+  return hipFuncGetAttributes(&at, (const void*)kernel) != hipSuccess || at.localSizeBytes > 0;
+}
+
+template <int L, int T, int NT, int V>
+bool enc_cos_pays() {
+  constexpr size_t lds = ct::Geo<L, T, NT, V>::LDS_BYTES;
+  if (kernel_spills(ct::k_enc_cos<L, T, NT, V>)) return false;
+  int oc = 0, op = 0;
+  (void)hipFuncSetAttribute((const void*)ct::k_enc_cos<L, T, NT, V>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+  (void)hipFuncSetAttribute((const void*)ct::k_enc<L, T, NT, V>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&oc, ct::k_enc_cos<L, T, NT, V>, NT, lds) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&op, ct::k_enc<L, T, NT, V>, NT, lds) != hipSuccess)
+    return false;
+  return oc >= 1 && oc >= op;
+}
+
+template <int L, int T, int NT, int V>
+hipError_t enc_cos_one(const EncodeArgs& a, uint32_t blocks, hipStream_t s) {
+  if constexpr (cos_ok<L, T, NT, V>()) {
+    static const bool pays = enc_cos_pays<L, T, NT, V>();
+    if (!pays) return hipErrorNotSupported;
+    constexpr size_t lds = ct::Geo<L, T, NT, V>::LDS_BYTES;
+    (void)hipFuncSetAttribute((const void*)ct::k_enc_cos<L, T, NT, V>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    hipLaunchKernelGGL((ct::k_enc_cos<L, T, NT, V>), dim3(blocks), dim3(NT), lds, s, a);
+    return hipGetLastError();
+  } else {
+    return hipErrorNotSupported;
+  }
+}
+
 template <int L, int D, int T, int NT, int V>
 hipError_t dec_pipe_one(const JobTable<DecodeArgs>& t, const DecodeArgs& one, const uint32_t* tw, const uint32_t* twi,
                         uint32_t grid, hipStream_t s) {
@@ -194,6 +240,17 @@ hipError_t dec_tab_pick(CtCfg c, int D, const JobTable<DecodeArgs>& t, const uin
 }
 
 template <int I>
+hipError_t enc_cos_pick(CtCfg c, const EncodeArgs& a, uint32_t blocks, hipStream_t s) {
+  if constexpr (I < 4 && kVar.enc[I < 4 ? I : 0].T != 0) {
+    if (c.T == kVar.enc[I].T && c.NT == kVar.enc[I].NT && c.V == kVar.enc[I].V)
+      return enc_cos_one<FNTRS_L, kVar.enc[I].T, kVar.enc[I].NT, kVar.enc[I].V>(a, blocks, s);
+    return enc_cos_pick<I + 1>(c, a, blocks, s);
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int I>
 hipError_t dec_pipe_pick(CtCfg c, int D, const JobTable<DecodeArgs>& t, const DecodeArgs& one, const uint32_t* tw,
                          const uint32_t* twi, uint32_t grid, hipStream_t s) {
   if constexpr (I < 4 && kVar.dec[I < 4 ? I : 0].T != 0) {
@@ -242,6 +299,10 @@ hipError_t FNTRS_CAT(ct_enc_tab_launch_, FNTRS_L)(CtCfg c, const JobTable<Encode
 hipError_t FNTRS_CAT(ct_dec_tab_launch_, FNTRS_L)(CtCfg c, int D, const JobTable<DecodeArgs>& t, const uint32_t* tw,
                                                   const uint32_t* twi, uint32_t grid, hipStream_t s) {
   return dec_tab_pick<0>(c, D, t, tw, twi, grid, s);
+}
+
+hipError_t FNTRS_CAT(ct_enc_cos_launch_, FNTRS_L)(CtCfg c, const EncodeArgs& a, uint32_t blocks, hipStream_t s) {
+  return enc_cos_pick<0>(c, a, blocks, s);
 }
 
 hipError_t FNTRS_CAT(ct_dec_pipe_launch_, FNTRS_L)(CtCfg c, int D, const JobTable<DecodeArgs>& t,

@@ -183,6 +183,16 @@ struct EncLoad {
     raw<B>(base, g, x, aux, aux2);
     finish<B>(base, g, x, aux, aux2);
   }
+  // the twist factors of coset t for the positions of the item at base
+  template <int B>
+  __device__ __forceinline__ void twists(uint32_t base, uint32_t (&wt)[1 << B]) const {
+    const uint32_t jb = bitrev(base, L);
+#pragma unroll
+    for (int c = 0; c < (1 << B); ++c) {
+      const uint32_t j = jb | (bitrev((uint32_t)c, B) << (L - B));
+      wt[c] = gptr(tw)[((t * j) & (n - 1)) << sh];
+    }
+  }
 };
 
 // Last DIT pass of the encoder: output m of coset t is row t + cosets*m.
@@ -227,6 +237,49 @@ __device__ __forceinline__ void enc_item(const EncodeArgs& a, uint32_t item, uin
   LdsStore<V, G, false> sm{lds};
   EncStore<V> sl{a.dst + blk * a.stride_dst + lane0, a.ld_dst, t, a.cosets, lane0, a.lanes, a.vec != 0, a.rows_out};
   dit<LK, Gm::BM, V, G, false>(tws, l0, lm, sm, sl);
+}
+
+// Encoder with every coset of a lane tile in one workgroup: the tile's
+// source rows are read once into registers (pass-0 items, C0 slots per
+// thread),
+// and each coset's first pass twists them there; the stores of one coset
+// drain while the next computes.  Work item = (lane tile, block).
+template <int LK, int TT, int NT, int VV>
+__global__ void __launch_bounds__(NT) k_enc_cos(EncodeArgs a) {
+  using Gm = Geo<LK, TT, NT, VV>;
+  constexpr int V = Gm::V, G = Gm::G, T = Gm::T, BM = Gm::BM;
+  constexpr int B0 = plan_b(LK, BM, 0);
+  constexpr int C0 = pass0_slots<LK, BM, G, NT>();
+  static_assert(plan_np(LK, BM) >= 2, "needs a first and a last pass");
+  using TW = typename Gm::TwType;
+  extern __shared__ uint32_t lds[];
+  const TW tws = make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
+  const uint32_t item = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t lane0 = (item % a.tiles) * T;
+  const uint64_t blk = item / a.tiles;
+  EncLoad<LK, V> ld{a.src + blk * a.stride_src + lane0, a.tw, a.ld_src, a.k, a.n, 0u, lane0, a.lanes,
+                    16 - a.logn, a.vec != 0};
+  int32_t src[C0][1 << B0][V];
+  uint32_t wt[C0][1 << B0], unused[C0][1 << B0];
+  prefetch0<LK, BM, V, G, NT, C0>(ld, src, wt, unused);   // rows once (coset 0: no twist)
+  LdsLoad<V, G> lm{lds};
+  LdsStore<V, G, false> sm{lds};
+  NoHook none;
+  for (uint32_t t = 0; t < a.cosets; ++t) {
+    ld.t = t;
+    if (t) {
+#pragma unroll
+      for (int c = 0; c < C0; ++c)
+        if (threadIdx.x + (uint32_t)c * NT < pass0_items<LK, BM, G>())
+          ld.template twists<B0>(((threadIdx.x + (uint32_t)c * NT) / G) << B0, wt[c]);
+    }
+    dit_pass0_regs<LK, BM, V, G, NT, C0, false>(tws, ld, src, wt, unused, sm);
+    __syncthreads();
+    EncStore<V> sl{a.dst + blk * a.stride_dst + lane0, a.ld_dst, t, a.cosets, lane0, a.lanes, a.vec != 0,
+                   a.rows_out};
+    dit_from<LK, BM, V, G, false, 1>(tws, lm, sm, sl, none);
+    __syncthreads();   // the next coset's first pass overwrites the LDS tile
+  }
 }
 
 template <int LK, int TT, int NT, int VV>

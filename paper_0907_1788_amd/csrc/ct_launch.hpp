@@ -52,6 +52,9 @@ using CtEncTabLaunch = hipError_t (*)(CtCfg cfg, const JobTable<EncodeArgs>& t, 
                                       const uint32_t* twi, uint32_t grid, hipStream_t s);
 using CtDecTabLaunch = hipError_t (*)(CtCfg cfg, int D, const JobTable<DecodeArgs>& t, const uint32_t* tw,
                                       const uint32_t* twi, uint32_t grid, hipStream_t s);
+// Encoder with all cosets of a lane tile in one workgroup (k_enc_cos); blocks
+// = lane tiles x batch.  hipErrorNotSupported when the configuration has none.
+using CtEncCosLaunch = hipError_t (*)(CtCfg cfg, const EncodeArgs& a, uint32_t blocks, hipStream_t s);
 // Pipelined persistent decoder launch (k_dec_pipe): a table of jobs, or
 // (t.jobs == nullptr) the single job `one` with t.total work items.
 // hipErrorNotSupported when the configuration has no pipelined kernel.
@@ -69,6 +72,7 @@ using CtTabOccupancy = int (*)(CtCfg cfg, int op, int D);
                                    const uint32_t* twi, uint32_t grid, hipStream_t s);                    \
   hipError_t ct_dec_tab_launch_##L(CtCfg cfg, int D, const JobTable<DecodeArgs>& t, const uint32_t* tw,   \
                                    const uint32_t* twi, uint32_t grid, hipStream_t s);                    \
+  hipError_t ct_enc_cos_launch_##L(CtCfg cfg, const EncodeArgs& a, uint32_t blocks, hipStream_t s);         \
   hipError_t ct_dec_pipe_launch_##L(CtCfg cfg, int D, const JobTable<DecodeArgs>& t, const DecodeArgs& one,\
                                     const uint32_t* tw, const uint32_t* twi, uint32_t grid, hipStream_t s); \
   int ct_tab_occupancy_##L(CtCfg cfg, int op, int D);

@@ -372,6 +372,16 @@ template <int L, int BM, int G, int NT>
 __host__ __device__ constexpr int pass0_per_thread() {
   return (((1u << (L - plan_b(L, BM, 0))) * G) % NT == 0) ? (int)(((1u << (L - plan_b(L, BM, 0))) * G) / NT) : 0;
 }
+// Pass-0 items of a thread when the threads outnumber them or do not split
+// them evenly: ceil(items / NT) slots, of which the last may be empty.
+template <int L, int BM, int G, int NT>
+__host__ __device__ constexpr int pass0_slots() {
+  return (int)(((1u << (L - plan_b(L, BM, 0))) * G + NT - 1) / NT);
+}
+template <int L, int BM, int G>
+__host__ __device__ constexpr uint32_t pass0_items() {
+  return (1u << (L - plan_b(L, BM, 0))) * G;
+}
 
 // Reads the per-position values of this thread's pass-0 items that every
 // tile of a job shares (loader member consts<B>).
@@ -382,6 +392,7 @@ __device__ __forceinline__ void consts0(Ld& ld, uint32_t (&aux)[C0][1 << plan_b(
 #pragma unroll
   for (int c = 0; c < C0; ++c) {
     const uint32_t q = threadIdx.x + (uint32_t)c * NT;
+    if (q >= pass0_items<L, BM, G>()) continue;
     ld.template consts<B>((q / G) << B, aux[c], aux2[c]);
   }
 }
@@ -397,6 +408,7 @@ __device__ __forceinline__ void prefetch0(Ld& ld, int32_t (&x)[C0][1 << plan_b(L
 #pragma unroll
   for (int c = 0; c < C0; ++c) {
     const uint32_t q = threadIdx.x + (uint32_t)c * NT;
+    if (q >= pass0_items<L, BM, G>()) continue;
     const uint32_t g = q % G, it = q / G;
     ld.template raw<B>(it << B, g, x[c], aux[c], aux2[c]);
   }
@@ -411,6 +423,7 @@ __device__ __forceinline__ void dit_pass0_regs(const TW& tw, Ld& ld, int32_t (&p
 #pragma unroll
   for (int c = 0; c < C0; ++c) {
     const uint32_t q = threadIdx.x + (uint32_t)c * NT;
+    if (q >= pass0_items<L, BM, G>()) continue;
     const uint32_t g = q % G, it = q / G;
     const uint32_t base = it << B;
     int32_t x[1 << B][V];

@@ -45,12 +45,17 @@ const CtTables& ct_tables() {
     ct_tab_occupancy_4,  ct_tab_occupancy_5,  ct_tab_occupancy_6,  ct_tab_occupancy_7,
     ct_tab_occupancy_8,  ct_tab_occupancy_9,  ct_tab_occupancy_10, ct_tab_occupancy_11,
     ct_tab_occupancy_12, ct_tab_occupancy_13, ct_tab_occupancy_14, ct_tab_occupancy_15};
+  static const CtEncCosLaunch enc_cos[16] = {
+      nullptr,              ct_enc_cos_launch_1,  ct_enc_cos_launch_2,  ct_enc_cos_launch_3,
+      ct_enc_cos_launch_4,  ct_enc_cos_launch_5,  ct_enc_cos_launch_6,  ct_enc_cos_launch_7,
+      ct_enc_cos_launch_8,  ct_enc_cos_launch_9,  ct_enc_cos_launch_10, ct_enc_cos_launch_11,
+      ct_enc_cos_launch_12, ct_enc_cos_launch_13, ct_enc_cos_launch_14, ct_enc_cos_launch_15};
   static const CtDecPipeLaunch dec_pipe[16] = {
       nullptr,               ct_dec_pipe_launch_1,  ct_dec_pipe_launch_2,  ct_dec_pipe_launch_3,
       ct_dec_pipe_launch_4,  ct_dec_pipe_launch_5,  ct_dec_pipe_launch_6,  ct_dec_pipe_launch_7,
       ct_dec_pipe_launch_8,  ct_dec_pipe_launch_9,  ct_dec_pipe_launch_10, ct_dec_pipe_launch_11,
       ct_dec_pipe_launch_12, ct_dec_pipe_launch_13, ct_dec_pipe_launch_14, ct_dec_pipe_launch_15};
-  static const CtTables t{enc, dec, enc_tab, dec_tab, dec_pipe, occ};
+  static const CtTables t{enc, dec, enc_tab, dec_tab, enc_cos, dec_pipe, occ};
   return t;
 }
 
@@ -164,6 +169,10 @@ int kernel_occupancy(fntrs_ctx* c, int op, int L, int D, CtCfg cfg) {
 hipError_t launch_ct_encode(fntrs_ctx* c, int L, CtCfg cfg, const EncodeArgs& a, uint64_t items, hipStream_t s) {
   (void)c;
   if (items > 0x7fffffffull) return hipErrorInvalidValue;
+  if (a.cosets >= 2) {   // every coset of a lane tile in one workgroup, when the shape allows
+    const hipError_t e = ct_tables().enc_cos[L](cfg, a, (uint32_t)(items / a.cosets), s);
+    if (e != hipErrorNotSupported) return e;
+  }
   return ct_tables().enc[L](cfg, a, (uint32_t)items, s);
 }
 

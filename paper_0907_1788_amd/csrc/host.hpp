@@ -149,6 +149,7 @@ struct CtTables {
   const CtDecLaunch* dec;
   const CtEncTabLaunch* enc_tab;
   const CtDecTabLaunch* dec_tab;
+  const CtEncCosLaunch* enc_cos;
   const CtDecPipeLaunch* dec_pipe;
   const CtTabOccupancy* occ;
 };
