@@ -14,7 +14,9 @@ namespace ct {
 // Radix bound of the pass plan for a size-2^L transform on G lane groups of V
 // lanes: aim for kThreads items per pass (items = G 2^(L-B)), radix 8 at
 // least, the register budget of V lanes at most, and no more passes than
-// needed while a pass keeps at least half the threads busy.
+// needed while a pass keeps at least half the threads busy -- all of them in
+// a 1024-thread workgroup, which has its CU to itself: a half-idle pass would
+// leave the CU 8 waves for a third of the butterflies.
 __host__ __device__ constexpr int geo_bm(int L, int G, int V, int NT) {
   int lg = 0, lt = 0;
   while ((1 << lg) < G) ++lg;
@@ -27,9 +29,11 @@ __host__ __device__ constexpr int geo_bm(int L, int G, int V, int NT) {
   if (b > bmax) b = bmax;
   if (b > L) b = L;
   if (b < 1) b = 1;
-  // a larger radix that saves a pass while items >= kThreads/2
+  // a larger radix that saves a pass while items >= kThreads/2 (kThreads
+  // with 1024 threads)
+  const int busy = NT >= 1024 ? NT : NT / 2;
   for (int c = b + 1; c <= bmax && c <= L; ++c)
-    if ((L + c - 1) / c < (L + b - 1) / b && (G << (L - c)) >= NT / 2) return c;
+    if ((L + c - 1) / c < (L + b - 1) / b && (G << (L - c)) >= busy) return c;
   return b;
 }
 
