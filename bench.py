@@ -366,6 +366,9 @@ def main():
     ap.add_argument("--systematic", action="store_true",
                     help="the systematic code (Sec. II-C): interpolation + transform on both sides")
     ap.add_argument("--seed", type=int, default=2024)
+    ap.add_argument("--flush-mib", type=int, default=512,
+                    help="MiB written between steps when the workload's buffers total under 1 GiB, so that "
+                         "no step starts from data the previous one left in the caches (0: never)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
@@ -410,6 +413,12 @@ def main():
     patterns = [synth.received_positions(args.seed + 17 * i, n, k) for i in range(nsteps)]
     ctx = fntrs.Context(0)
     stream = torch.cuda.current_stream()
+    # a workload that fits in the caches (L2 4 MiB per XCD, 256 MiB Infinity
+    # Cache) would otherwise start every step from the previous step's data
+    footprint = 4 * lanes * blocks * (2 * k + n)
+    flush = None
+    if args.flush_mib > 0 and footprint < (1 << 30):
+        flush = torch.empty(args.flush_mib << 18, dtype=torch.int32, device=dev)
 
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(nsteps)]
     step_ms = []
@@ -418,6 +427,8 @@ def main():
 
     def step(i):
         e = ev[i]
+        if flush is not None:
+            flush.fill_(i)   # outside the step's events
         e[0].record(stream)
         ctx.encode(src, enc, n, flags=sysf, stream=stream)
         e[1].record(stream)
@@ -447,7 +458,9 @@ def main():
     exact = bool(torch.equal(out, src))
     log("exact", exact)
 
-    ms = wall * 1e3 / args.steps
+    # with flushes between steps the step time comes from its events, which
+    # exclude the flush; otherwise from the wall clock over all steps
+    ms = float(np.mean(step_ms)) if flush is not None else wall * 1e3 / args.steps
     payload = 2 * k * lanes * blocks              # bytes of 16-bit source per direction
     value = 2 * payload / (ms * 1e-3) / 1e9
     dec_avg = float(np.mean(dec_ms))
@@ -475,6 +488,9 @@ def main():
         "config": {"workload": args.workload, "k": k, "n": n, "lanes": lanes, "blocks": blocks,
                    "code": "systematic" if args.systematic else "non-systematic",
                    "pattern": "uniform random n-k erasures, fresh pattern (locator rebuilt) every step",
+                   "caches": (f"{args.flush_mib} MiB written between steps, outside the timed events"
+                              if flush is not None else "buffers larger than the caches" if footprint >= (1 << 30)
+                              else "no flush between steps: buffers may be cache-resident"),
                    "parallelism": "single GPU"},
         "bit_exact": exact,
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
@@ -500,6 +516,9 @@ def main():
     if not args.no_plain:
         # plain path: one synchronous request per block, no batching
         lat = []
+        if flush is not None:
+            flush.fill_(-1)
+            torch.cuda.synchronize()
         t0 = time.perf_counter()
         for b in range(blocks):
             t1 = time.perf_counter()
