@@ -483,36 +483,45 @@ static int build_locators(fntrs_ctx* c, std::vector<fntrs_locator_t*>& Ls, hipSt
   auto launch_err = [&]() { return hipGetLastError(); };
   auto st_ptr = [&](const Stage& st) { return dtab + st.start_off; };
   const uint32_t* tw = c->tw;
-  hipLaunchKernelGGL(k_locb_prep, dim3((prep.total + 255) / 256), dim3(256), 0, s, D, st_ptr(prep), P);
-  if (Pn) {
-    hipLaunchKernelGGL(k_locb_leaves, dim3(leaves.total), dim3(64), 0, s, D, st_ptr(leaves), Pn, tw);
-    for (size_t j = 0; j < levels.size(); ++j) {
-      const int logd = levels[j].first;
-      const Stage& st = levels[j].second;
-      const uint32_t d = 1u << logd;
-      if (!level_ct(logd + 1, st.total, D + st.r.first, st_ptr(st), st.r.count, (int)j, tw, c->twi, s)) {
-        const size_t lds = 2ull * d * 4;
-        (void)set_lds_attr((const void*)k_locb_level, lds);
-        const int nt = (int)std::min<uint32_t>(1024, std::max<uint32_t>(64, d / 2));
-        hipLaunchKernelGGL(k_locb_level, dim3(st.total), dim3(nt), lds, s, D + st.r.first, st_ptr(st), st.r.count,
-                           logd, (int)j, tw);
+  // short codes: one workgroup per pattern runs every step (its LDS holds a
+  // tree of n/2 points and an M-point transform, M <= n)
+  const bool small = P > 0 && Pn == P && std::all_of(Ls.begin(), Ls.end(), [](const fntrs_locator_t* L) {
+    return L->k < L->n && L->n <= kLocSmallN && 2 * pad_pow2(L->k) <= L->n && (1u << L->logm) <= L->n;
+  });
+  if (small) {
+    hipLaunchKernelGGL(k_locb_small, dim3(P), dim3(kLocSmallNT), 0, s, D, tw);
+  } else {
+    hipLaunchKernelGGL(k_locb_prep, dim3((prep.total + 255) / 256), dim3(256), 0, s, D, st_ptr(prep), P);
+    if (Pn) {
+      hipLaunchKernelGGL(k_locb_leaves, dim3(leaves.total), dim3(64), 0, s, D, st_ptr(leaves), Pn, tw);
+      for (size_t j = 0; j < levels.size(); ++j) {
+        const int logd = levels[j].first;
+        const Stage& st = levels[j].second;
+        const uint32_t d = 1u << logd;
+        if (!level_ct(logd + 1, st.total, D + st.r.first, st_ptr(st), st.r.count, (int)j, tw, c->twi, s)) {
+          const size_t lds = 2ull * d * 4;
+          (void)set_lds_attr((const void*)k_locb_level, lds);
+          const int nt = (int)std::min<uint32_t>(1024, std::max<uint32_t>(64, d / 2));
+          hipLaunchKernelGGL(k_locb_level, dim3(st.total), dim3(nt), lds, s, D + st.r.first, st_ptr(st), st.r.count,
+                             logd, (int)j, tw);
+        }
       }
+      hipLaunchKernelGGL(k_locb_derivative, dim3((deriv.total + 255) / 256), dim3(256), 0, s, D, st_ptr(deriv), Pn);
+      for (auto& ev : evals) {
+        if (eval_ct(ev.first, ev.second.total, D + ev.second.r.first, st_ptr(ev.second), ev.second.r.count, tw, c->twi,
+                    s))
+          continue;
+        const uint32_t K = 1u << ev.first;
+        const size_t lds = (size_t)K * 4;
+        (void)set_lds_attr((const void*)k_locb_eval, lds);
+        const int nt = (int)std::min<uint32_t>(1024, std::max<uint32_t>(64, K / 4));
+        hipLaunchKernelGGL(k_locb_eval, dim3(ev.second.total), dim3(nt), lds, s, D + ev.second.r.first,
+                           st_ptr(ev.second), ev.second.r.count, ev.first, tw);
+      }
+      hipLaunchKernelGGL(k_locb_weights, dim3((weights.total + 255) / 256), dim3(256), 0, s, D, st_ptr(weights), Pn,
+                         tw);
+      hipLaunchKernelGGL(k_locb_ahat, dim3((ahat.total + 255) / 256), dim3(256), 0, s, D, st_ptr(ahat), Pn);
     }
-    hipLaunchKernelGGL(k_locb_derivative, dim3((deriv.total + 255) / 256), dim3(256), 0, s, D, st_ptr(deriv), Pn);
-    for (auto& ev : evals) {
-      if (eval_ct(ev.first, ev.second.total, D + ev.second.r.first, st_ptr(ev.second), ev.second.r.count, tw, c->twi,
-                  s))
-        continue;
-      const uint32_t K = 1u << ev.first;
-      const size_t lds = (size_t)K * 4;
-      (void)set_lds_attr((const void*)k_locb_eval, lds);
-      const int nt = (int)std::min<uint32_t>(1024, std::max<uint32_t>(64, K / 4));
-      hipLaunchKernelGGL(k_locb_eval, dim3(ev.second.total), dim3(nt), lds, s, D + ev.second.r.first,
-                         st_ptr(ev.second), ev.second.r.count, ev.first, tw);
-    }
-    hipLaunchKernelGGL(k_locb_weights, dim3((weights.total + 255) / 256), dim3(256), 0, s, D, st_ptr(weights), Pn,
-                       tw);
-    hipLaunchKernelGGL(k_locb_ahat, dim3((ahat.total + 255) / 256), dim3(256), 0, s, D, st_ptr(ahat), Pn);
   }
   if (hipError_t le = launch_err(); le != hipSuccess)
     return fail_free(fail(c, FNTRS_E_DEVICE, "locator kernels: %s", hipGetErrorString(le)));

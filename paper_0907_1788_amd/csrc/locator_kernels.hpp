@@ -300,6 +300,111 @@ __global__ void k_locb_ahat(const LocDesc* __restrict__ D, const uint32_t* __res
   d.ahat_s[q] = v;
 }
 
+// ---------------------------------------------------------------- short codes
+// Every step of the locator for one pattern of a short code in one workgroup
+// (codes of at most kLocSmallN positions, so trees of at most kLocSmallN/2
+// points): the product tree in LDS with schoolbook products (level h of a
+// K-point tree costs K h products, h < K), A' at the n-th roots by K-point
+// transforms, one coset at a time, and the transform of A for step 6 -- steps 1-3 and
+// the tables of steps 4 and 6 of Sec. II-B without the launches and global
+// round trips of the staged kernels above.  The state written is the same.
+// Patterns with nothing erased take the staged path.
+constexpr uint32_t kLocSmallN = 1024;
+constexpr int kLocSmallNT = 512;
+
+__global__ void __launch_bounds__(kLocSmallNT) k_locb_small(const LocDesc* __restrict__ D,
+                                                            const uint32_t* __restrict__ tw) {
+  __shared__ uint32_t tree[2][kLocSmallN / 2];
+  __shared__ uint32_t spec[kLocSmallN];   // A', then the transform of A
+  __shared__ uint32_t vals[kLocSmallN];   // A' at the n-th roots
+  __shared__ uint32_t buf[kLocSmallN / 2];
+  const LocDesc& d = D[blockIdx.x];
+  const uint32_t n = d.n, K = d.k, kr = d.kr;
+  const uint32_t t = threadIdx.x, nt = blockDim.x;
+  // positions into the state; an erased position must read weight 0
+  for (uint32_t j = t; j < n; j += nt) d.wfull[j] = 0u;
+  for (uint32_t j = t; j < kr; j += nt) d.pos[j] = d.zin[j];
+  // step 1: the tree of the K linear factors (x - x_i); the points past the
+  // received ones are roots at 0, so the root holds A(x) x^(K - kr).  Round
+  // h pairs monic degree-h polynomials a = x^h + a_lo, b = x^h + b_lo into
+  // a b = x^(2h) + x^h (a_lo + b_lo) + a_lo b_lo, one coefficient a thread.
+  for (uint32_t j = t; j < K; j += nt) tree[0][j] = j < kr ? fsub(0u, point_of(tw, d.zin[j], d.logn)) : 0u;
+  __syncthreads();
+  int cur = 0;
+  for (uint32_t h = 1; h < K; h <<= 1) {
+    for (uint32_t j = t; j < K; j += nt) {
+      const uint32_t* a = &tree[cur][(j / (2 * h)) * 2 * h];
+      const uint32_t* b = a + h;
+      const uint32_t jj = j % (2 * h);
+      uint32_t acc = jj >= h ? fadd(a[jj - h], b[jj - h]) : 0u;
+      const uint32_t lo = jj >= h ? jj - h + 1 : 0u, hi = jj < h ? jj : h - 1;
+      // four independent sums, so that their LDS reads issue together
+      uint32_t acc1 = 0u, acc2 = 0u, acc3 = 0u, s2 = lo;
+      for (; s2 + 3 <= hi; s2 += 4) {
+        acc = fadd(acc, fmul(a[s2], b[jj - s2]));
+        acc1 = fadd(acc1, fmul(a[s2 + 1], b[jj - s2 - 1]));
+        acc2 = fadd(acc2, fmul(a[s2 + 2], b[jj - s2 - 2]));
+        acc3 = fadd(acc3, fmul(a[s2 + 3], b[jj - s2 - 3]));
+      }
+      for (; s2 <= hi; ++s2) acc = fadd(acc, fmul(a[s2], b[jj - s2]));
+      tree[cur ^ 1][j] = fadd(fadd(acc, acc1), fadd(acc2, acc3));
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  // step 2: A (monic, degree kr) into the state, and A' = sum (j+1) a_(j+1) x^j
+  const uint32_t* poly = tree[cur];
+  const uint32_t shift = K - kr;
+  for (uint32_t j = t; j < K; j += nt) {
+    if (j < kr) {
+      const uint32_t next = j + 1 < kr ? poly[j + 1 + shift] : 1u;
+      d.A[j] = poly[j + shift];
+      spec[j] = fmul(next, j + 1);
+    } else {
+      spec[j] = 0u;
+    }
+  }
+  if (t == 0) d.A[kr] = 1u;
+  __syncthreads();
+  // step 3: A' at every n-th root: the value at r_n^(c + cosets m) is FNT_K
+  // of (a'_j r_n^(c j))_j at m (Sec. II-A, polynomial view of the FNT)
+  const int logK = 31 - __clz(K);
+  const uint32_t cosets = n >> logK;
+  for (uint32_t c = 0; c < cosets; ++c) {
+    for (uint32_t j = t; j < K; j += nt)
+      buf[bitrev(j, logK)] = c ? fmul(spec[j], tw[((c * j) & (n - 1)) << (16 - d.logn)]) : spec[j];
+    __syncthreads();
+    lds_dit<1>(buf, 1, logK, false, tw);
+    for (uint32_t m = t; m < K; m += nt) vals[c + cosets * m] = buf[m];
+    __syncthreads();
+  }
+  // step 4: w_i = 1/A'(x_i), and the decoder weight -w_i x_i^(-1) (sign and
+  // index shift of step 5) and row i at position z_i
+  for (uint32_t q = t; q < kr; q += nt) {
+    const uint32_t z = d.zin[q];
+    const uint32_t wi = finv(vals[z]);
+    const uint32_t xinv = tw[(65536u - ((z << (16 - d.logn)) & 0xFFFFu)) & 0xFFFFu];
+    d.w[q] = wi;
+    d.wfull[z] = fsub(0u, fmul(wi, xinv));
+    d.ridx[z] = q;
+  }
+  // step 6 table: A mod x^kr at the M-th roots; unscaled in ahat, times M^-1
+  // in natural and bit-reversed order
+  const int logm = d.logm;
+  const uint32_t M = 1u << logm;
+  for (uint32_t j = t; j < M; j += nt) spec[bitrev(j, logm)] = j < kr ? poly[j + shift] : 0u;
+  __syncthreads();
+  lds_dit<1>(spec, 1, logm, false, tw);
+  const uint32_t inv = 65537u - (65536u >> logm);   // (2^logm)^-1 = -2^(16-logm)
+  for (uint32_t q = t; q < M; q += nt) {
+    const uint32_t u = spec[q];
+    const uint32_t v = fmul(u, inv);
+    d.ahat[q] = u;
+    d.ahat_br[bitrev(q, logm)] = v;
+    d.ahat_s[q] = v;
+  }
+}
+
 // ---------------------------------------------------------------- large
 // transforms of the locator on the lane-tile engine (ctfnt.hpp) with one
 // lane: radix-32 passes, one item per thread per pass (2^L / 32 threads,

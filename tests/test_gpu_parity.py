@@ -117,6 +117,39 @@ def test_locator_state_matches_oracle(ctx, n, k, seed):
     loc.release()
 
 
+@pytest.mark.parametrize("n,k,seed", [(512, 256, 21), (1024, 300, 22), (64, 5, 23), (2, 1, 24)])
+def test_short_code_locator_matches_staged(n, k, seed):
+    """A short-code pattern built alone runs the one-workgroup locator; in a
+    batch with a longer code it runs the staged kernels.  Both give the
+    oracle's state and decode the same."""
+    say("short-code locator", n, k, seed)
+    z = synth.received_positions(seed, n, k)
+    zl = synth.received_positions(seed + 1, 4096, 2048)
+    ca, cb = fntrs.Context(0), fntrs.Context(0)   # separate caches
+    try:
+        a = ca.locator(n, k, z)
+        b, big = cb.locators([(n, k, z), (4096, 2048, zl)])
+        ea, eb = a.export(), b.export()
+        for x, y in zip(ea, eb):
+            assert np.array_equal(x, y)
+        ref = codec.locator(n, z)
+        assert np.array_equal(ea[0].astype(np.int64), ref["A"])
+        assert np.array_equal(ea[1].astype(np.int64), ref["w"])
+        if "Ahat" in ref:
+            assert np.array_equal(ea[2].astype(np.int64), ref["Ahat"])
+        src = synth.source(seed, 1, k, 9)
+        e = codec.encode(src[0], n)[None]
+        for c, loc in ((ca, a), (cb, b)):
+            assert np.array_equal(gpu_decode(c, loc, e[:, z, :]), src.astype(np.int64))
+            assert np.array_equal(gpu_decode(c, loc, e, fntrs.FNTRS_RECV_FULL), src.astype(np.int64))
+        for x in (a, b, big):
+            x.release()
+    finally:
+        torch.cuda.synchronize()
+        ca.close()
+        cb.close()
+
+
 def test_locator_cache_returns_same_state(ctx):
     say("locator cache")
     z = synth.received_positions(77, 256, 64)
