@@ -277,7 +277,9 @@ __device__ __forceinline__ void dif_stages(int32_t (&x)[1 << B][V], uint32_t jp,
 // radices as equal as possible.  DIT passes run bottom-up (pass 0 has stride
 // 1) and put the larger radices first; DIF passes run top-down and put them
 // last.  Either way the stride-1 pass gets the largest radix, which keeps the
-// padded layout conflict-free when H*G < 16.
+// padded layout conflict-free there when that radix is 16 or more (or
+// H*G >= 16); a radix-8 stride-1 pass over one lane group shares banks
+// two-way.
 __host__ __device__ constexpr int plan_np(int L, int BM) { return L == 0 ? 0 : (L + BM - 1) / BM; }
 __host__ __device__ constexpr int plan_b(int L, int BM, int p) {
   return L / plan_np(L, BM) + (p < L % plan_np(L, BM) ? 1 : 0);
