@@ -434,6 +434,36 @@ struct ProductStore {
   }
 };
 
+// The same two operations at the seams of the decoder's transforms, where
+// the data stays in registers (seam_pass): the series mask of step 5, and the
+// product with FNT_M(A mod x^k)/M in bit-reversed order.
+template <int V>
+struct SeriesMask {
+  uint32_t k;
+  template <int B, uint32_t H>
+  __device__ __forceinline__ void item(uint32_t base, uint32_t, int32_t (&x)[1 << B][V]) const {
+#pragma unroll
+    for (int c = 0; c < (1 << B); ++c) {
+      const uint32_t m = base + c * H;
+#pragma unroll
+      for (int v = 0; v < V; ++v) x[c][v] = m < k ? fold1(x[c][v]) : 0;
+    }
+  }
+};
+template <int V>
+struct AhatProduct {
+  const uint32_t* ahat_br;
+  template <int B, uint32_t H>
+  __device__ __forceinline__ void item(uint32_t base, uint32_t, int32_t (&x)[1 << B][V]) const {
+#pragma unroll
+    for (int c = 0; c < (1 << B); ++c) {
+      const uint32_t h = gptr(ahat_br)[base + c * H];
+#pragma unroll
+      for (int v = 0; v < V; ++v) x[c][v] = mulc(canon(x[c][v]), h);
+    }
+  }
+};
+
 // Last DIT pass of step 6: coefficients m < k are the recovered source rows.
 template <int V>
 struct SourceStore {
@@ -484,12 +514,36 @@ __device__ __forceinline__ void dec_item(const DecodeArgs& a, uint32_t item, uin
     dit<LN, Gm::BM, V, G, true>(tws, lg, ll, sl, sg);
   } else {
     constexpr int L2 = LN - D;
+    constexpr int BM = Gm::BM;
+    constexpr int NP1 = plan_np(LN, BM), NP2 = plan_np(L2, BM);
     LdsStore<V, G, true> slf{lds};
-    SeriesStore<V, G> ss{lds, a.k};
-    ProductStore<V, G> sp{lds, a.ahat_br};
-    dit<LN, Gm::BM, V, G, true>(tws, lg, ll, sl, ss);
-    dif<L2, Gm::BM, V, G, false>(tws, ll, ll, slf, sp);
-    dit<L2, Gm::BM, V, G, true>(tws, ll, ll, sl, sg);
+    if constexpr (NP1 >= 2 && NP2 >= 2) {
+      // the transforms meet at seams (seam_pass): with M = n, the inverse
+      // FNT_n's last pass, the series mask and the DIF's first pass; for any
+      // M, the DIF's last pass, the product and the inverse DIT's first pass
+      AhatProduct<V> ap{a.ahat_br};
+      if constexpr (D == 0) {
+        SeriesMask<V> sk{a.k};
+        dit_passes<LN, BM, V, G, true, 0, NP1 - 1>(tws, lg, ll, sl);
+        seam_pass<LN, BM, V, G, true, true, false>(tws, ll, sk, slf);
+        __syncthreads();
+        dif_passes<L2, BM, V, G, false, 1, NP2 - 1>(tws, ll, slf);
+      } else {
+        SeriesStore<V, G> ss{lds, a.k};
+        dit<LN, BM, V, G, true>(tws, lg, ll, sl, ss);
+        dif_passes<L2, BM, V, G, false, 0, NP2 - 1>(tws, ll, slf);
+      }
+      seam_pass<L2, BM, V, G, false, false, true>(tws, ll, ap, sl);
+      __syncthreads();
+      NoHook none;
+      dit_from<L2, BM, V, G, true, 1>(tws, ll, sl, sg, none);
+    } else {
+      SeriesStore<V, G> ss{lds, a.k};
+      ProductStore<V, G> sp{lds, a.ahat_br};
+      dit<LN, BM, V, G, true>(tws, lg, ll, sl, ss);
+      dif<L2, BM, V, G, false>(tws, ll, ll, slf, sp);
+      dit<L2, BM, V, G, true>(tws, ll, ll, sl, sg);
+    }
   }
 }
 

@@ -364,6 +364,58 @@ __device__ __forceinline__ void dif(const TW& tw, L0& l0, LM& lm, SM& sm, SL& sl
   }
 }
 
+// Passes [P, Q) of a DIT transform (pass 0 reads through l0, the others
+// through lm; all store through sm), a barrier after each.
+template <int L, int BM, int V, int G, bool INV, int P, int Q, class TW, class L0, class LM, class SM>
+__device__ __forceinline__ void dit_passes(const TW& tw, L0& l0, LM& lm, SM& sm) {
+  if constexpr (P < Q) {
+    if constexpr (P == 0) dit_pass<L, BM, 0, V, G, INV>(tw, l0, sm);
+    else dit_pass<L, BM, P, V, G, INV>(tw, lm, sm);
+    __syncthreads();
+    dit_passes<L, BM, V, G, INV, P + 1, Q>(tw, l0, lm, sm);
+  }
+}
+
+// Passes [P, Q) of a DIF transform through lm and sm, a barrier after each.
+template <int L, int BM, int V, int G, bool INV, int P, int Q, class TW, class LM, class SM>
+__device__ __forceinline__ void dif_passes(const TW& tw, LM& lm, SM& sm) {
+  if constexpr (P < Q) {
+    dif_pass<L, BM, P, V, G, INV>(tw, lm, sm);
+    __syncthreads();
+    dif_passes<L, BM, V, G, INV, P + 1, Q>(tw, lm, sm);
+  }
+}
+
+// The last pass of one transform and the first pass of the next, over the
+// same 2^L points, in one pass: a DIT transform ends with its top stages and
+// a DIF transform starts with them (A_DIT), a DIF transform ends with its
+// bottom stages and a DIT transform starts with them (!A_DIT); either way the
+// two passes group the same positions, so a thread goes on with its item in
+// registers, mid(base, g, x) in between, and the data crosses LDS once.
+template <int L, int BM, int V, int G, bool A_DIT, bool A_INV, bool B_INV, class TW, class LM, class Mid, class SM>
+__device__ __forceinline__ void seam_pass(const TW& tw, LM& lm, Mid& mid, SM& sm) {
+  constexpr int NP = plan_np(L, BM);
+  constexpr int B = A_DIT ? plan_b(L, BM, NP - 1) : plan_b(L, BM, 0);
+  constexpr int S0 = A_DIT ? L - B : 0;
+  static_assert(!A_DIT || dit_s0(L, BM, NP - 1) == S0, "a DIT transform ends with its top stages");
+  static_assert(A_DIT || dif_top(L, BM, NP - 1) == B, "a DIF transform ends with its bottom stages");
+  constexpr uint32_t H = 1u << S0;
+  constexpr uint32_t ITEMS = (1u << (L - B)) * G;
+  for (uint32_t q = threadIdx.x; q < ITEMS; q += blockDim.x) {
+    const uint32_t g = q % G, it = q / G;
+    const uint32_t jp = it % H, blk = it / H;
+    const uint32_t base = blk * (H << B) + jp;
+    int32_t x[1 << B][V];
+    lm.template item<B, H>(base, g, x);
+    if constexpr (A_DIT) dit_stages<B, V, S0, A_INV>(x, jp, tw);
+    else dif_stages<B, V, S0 + B, A_INV>(x, jp, tw);
+    mid.template item<B, H>(base, g, x);
+    if constexpr (A_DIT) dif_stages<B, V, S0 + B, B_INV>(x, jp, tw);
+    else dit_stages<B, V, S0, B_INV>(x, jp, tw);
+    sm.template item<B, H>(base, g, x);
+  }
+}
+
 // ---------------------------------------------------------------- pipeline
 // Persistent kernels overlap the global reads of the next tile with the last
 // pass of the current one: pass 0's inputs are read into registers ahead of
