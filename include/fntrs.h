@@ -135,7 +135,8 @@ int fntrs_locator(fntrs_ctx* ctx, uint32_t n, uint32_t k,
  * n[q], k[q] source symbols and npos[q] received positions at positions[q]
  * (host memory, the rules of fntrs_locator).  Patterns not in the cache are
  * built together, one launch per stage for all of them (O(log k) launches
- * in total instead of per pattern), and share one device allocation that is
+ * in total instead of per pattern; a single launch when every pattern has
+ * erasures and n <= 1024), and share one device allocation that is
  * returned when the last of them leaves the cache.  out[q] receives a
  * reference as from fntrs_locator (release each).  All or nothing: on error
  * no reference is returned and fntrs_last_error names the pattern.  Errors:
