@@ -187,6 +187,20 @@ struct EncLoad {
     raw<B>(base, g, x, aux, aux2);
     finish<B>(base, g, x, aux, aux2);
   }
+  // the twist factors of coset 1 of two (n = 2K) for the positions of the
+  // item at base, from the transform's own twiddle source: r_n^j =
+  // omega_K^(j/2), times r_n for odd j (the item's positions share j's parity)
+  template <int B, class TW>
+  __device__ __forceinline__ void twists_half(uint32_t base, uint32_t (&wt)[1 << B], const TW& tws,
+                                              uint32_t rn) const {
+    const uint32_t jb = bitrev(base, L);
+#pragma unroll
+    for (int c = 0; c < (1 << B); ++c) {
+      const uint32_t j = jb | (bitrev((uint32_t)c, B) << (L - B));
+      const uint32_t w = tws.get(false, j >> 1, L);
+      wt[c] = (jb & 1u) ? canon(mulw((int32_t)w, rn)) : w;
+    }
+  }
   // the twist factors of coset t for the positions of the item at base
   template <int B>
   __device__ __forceinline__ void twists(uint32_t base, uint32_t (&wt)[1 << B]) const {
@@ -266,6 +280,7 @@ __global__ void __launch_bounds__(NT) k_enc_cos(EncodeArgs a) {
   int32_t src[C0][1 << B0][V];
   uint32_t wt[C0][1 << B0], unused[C0][1 << B0];
   prefetch0<LK, BM, V, G, NT, C0>(ld, src, wt, unused);   // rows once (coset 0: no twist)
+  const uint32_t rn = gptr(a.tw)[1u << (16 - a.logn)];     // r_n
   LdsLoad<V, G> lm{lds};
   LdsStore<V, G, false> sm{lds};
   NoHook none;
@@ -273,9 +288,14 @@ __global__ void __launch_bounds__(NT) k_enc_cos(EncodeArgs a) {
     ld.t = t;
     if (t) {
 #pragma unroll
-      for (int c = 0; c < C0; ++c)
-        if (threadIdx.x + (uint32_t)c * NT < pass0_items<LK, BM, G>())
-          ld.template twists<B0>(((threadIdx.x + (uint32_t)c * NT) / G) << B0, wt[c]);
+      for (int c = 0; c < C0; ++c) {
+        if (threadIdx.x + (uint32_t)c * NT >= pass0_items<LK, BM, G>()) continue;
+        const uint32_t base = ((threadIdx.x + (uint32_t)c * NT) / G) << B0;
+        // two cosets: the factors come from the twiddle table (LDS), so they
+        // do not wait behind the previous coset's stores
+        if (a.cosets == 2) ld.template twists_half<B0>(base, wt[c], tws, rn);
+        else ld.template twists<B0>(base, wt[c]);
+      }
     }
     dit_pass0_regs<LK, BM, V, G, NT, C0, false>(tws, ld, src, wt, unused, sm);
     __syncthreads();
