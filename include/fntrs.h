@@ -108,11 +108,30 @@ int fntrs_encode(fntrs_ctx* ctx, uint32_t n, uint32_t k, uint32_t lanes,
                  uint32_t* dst, size_t ld_dst, size_t stride_dst,
                  uint32_t batch, uint32_t flags, void* stream);
 
+/* The encoder of fntrs_encode for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments and the same result, bit for bit, but the
+ * call allocates nothing.  Where the encoder needs a scratch buffer (k above
+ * 8192, i.e. transforms of 2^14 points or more, run as four-step passes) it
+ * uses a fixed array in device memory that the library holds on every GPU it
+ * runs on until the process ends: at most 2^25 words (128 MiB), i.e.
+ * batch * N * (lanes rounded up to 32) <= 33554432 with N the next power of
+ * two >= n (k = 16384, n = 32768: up to 1024 lanes x blocks; n = 65536: up
+ * to 512).  Every call on one GPU shares that array, so calls that overlap
+ * on one GPU race: enqueue them on one stream, or order their streams.
+ * flags must be 0 (FNTRS_FLAG_VALIDATE and FNTRS_SYSTEMATIC allocate).
+ * Errors: those of fntrs_encode; FNTRS_E_NOMEM when the scratch would exceed
+ * the fixed array (nothing is enqueued). */
+int fntrs_encode_noalloc(fntrs_ctx* ctx, uint32_t n, uint32_t k, uint32_t lanes,
+                         const uint32_t* src, size_t ld_src, size_t stride_src,
+                         uint32_t* dst, size_t ld_dst, size_t stride_dst,
+                         uint32_t batch, uint32_t flags, void* stream);
+
 /* Locator for one erasure pattern (Sec. II-B, steps 1-3, which depend only
  * on the received positions and are reused for every lane and block).
  * positions: host array of npos received positions in [0, n), strictly
- * ascending; the first k are used (Sec. II-B: "the first k evaluation
- * points received").  n in [1, 65536], as for fntrs_encode (a punctured
+ * ascending; only the first k of them are used (Sec. II-B, decoding from
+ * the earliest k received points).  n in [1, 65536], as for fntrs_encode (a punctured
  * length uses the points of the next power of two).  Builds on the device,
  * enqueued on `stream`:
  *   A(x) = prod_{i<k} (x - r_n^(z_i)) by a product tree of FNT products,

@@ -645,11 +645,38 @@ void set_default_configs(fntrs_ctx* c) {
 
 using namespace fntrs;
 
+// Scratch of fntrs_encode_noalloc: the intermediate rows of the four-step
+// encoder (transforms of 2^14 points or more), batch * N * ceil32(lanes)
+// words.  A file-scope device array, so that the entry point allocates
+// nothing; every GPU the library runs on holds its own copy until the
+// process ends, and every call on that GPU shares it.
+constexpr size_t kNoAllocScratchWords = size_t(32) << 20;   // 128 MiB
+static __device__ __align__(256) uint32_t scratch[kNoAllocScratchWords];
+
+// Device address of `scratch` on each device, looked up once per device
+// with that device current (the host-side name is not a device address).
+static std::mutex g_scratch_mu;
+static std::map<int, uint32_t*> g_scratch_ptr;
+
+static int noalloc_scratch_init(fntrs_ctx* c) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(c->device);
+  if (it == g_scratch_ptr.end()) {
+    uint32_t* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(c, FNTRS_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    it = g_scratch_ptr.emplace(c->device, p).first;
+  }
+  c->noalloc_scratch = it->second;
+  return FNTRS_OK;
+}
+
 // Encoder on validated arguments, enqueued on s; rows_out > 0 writes only
 // the rows i < rows_out of dst.
 static int encode_run(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uint32_t* src, size_t ld_src,
                       size_t stride_src, uint32_t* dst, size_t ld_dst, size_t stride_dst, uint32_t batch,
-                      uint32_t rows_out, hipStream_t s) {
+                      uint32_t rows_out, hipStream_t s, uint32_t* fixed_scratch = nullptr) {
   if (n == 1) {  // k = 1: e_0 = s_0
     HIP_TRY(c, launch_copy(src, stride_src, dst, stride_dst, lanes, batch, s));
     return FNTRS_OK;
@@ -674,6 +701,10 @@ static int encode_run(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, cons
     f.rows_out = rows_out;
     const uint64_t lds = (uint64_t)f.tiles * kFourStepTile;
     f.vec = aligned16(src, ld_src, stride_src) && aligned16(dst, ld_dst, stride_dst);
+    if (fixed_scratch) {   // the caller's scratch (no allocation)
+      HIP_TRY(c, fourstep_encode(f, batch, fixed_scratch, lds, s));
+      return FNTRS_OK;
+    }
     uint32_t* sa = nullptr;
     const size_t bytes = (size_t)batch * n * lds * 4;
     hipError_t e = hipMallocAsync((void**)&sa, bytes, s);
@@ -841,6 +872,11 @@ int fntrs_create(int device, size_t cap, fntrs_ctx** out) {
     delete c;
     return FNTRS_E_DEVICE;
   }
+  if (noalloc_scratch_init(c) != FNTRS_OK) {
+    (void)hipFree(c->tw);
+    delete c;
+    return FNTRS_E_DEVICE;
+  }
   *out = c;
   return FNTRS_OK;
 }
@@ -886,6 +922,31 @@ int fntrs_encode(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uin
     return systematic_encode_run(c, n, k, lanes, src, ld_src, stride_src, dst, ld_dst, stride_dst, batch, s);
   const uint32_t N = pad_pow2(n);   // a shorter code: the rows n..N-1 are not written
   return encode_run(c, N, k, lanes, src, ld_src, stride_src, dst, ld_dst, stride_dst, batch, n < N ? n : 0, s);
+}
+
+int fntrs_encode_noalloc(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uint32_t* src, size_t ld_src,
+                         size_t stride_src, uint32_t* dst, size_t ld_dst, size_t stride_dst, uint32_t batch,
+                         uint32_t flags, void* stream) {
+  if (!c) return FNTRS_E_INVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->err.clear();
+  if (flags) return fail(c, FNTRS_E_INVAL, "fntrs_encode_noalloc takes no flags (got 0x%x)", flags);
+  if (int rc = check_encode(c, n, k, lanes, src, ld_src, stride_src, dst, ld_dst, stride_dst, batch, 0)) return rc;
+  const uint32_t N = pad_pow2(n);
+  const int logK = std::max(1, ilog2(k));
+  const bool fourstep = N > 1 && logK >= kFourStepMinLog;
+  const size_t words =
+      fourstep ? (size_t)batch * N * ((lanes + kFourStepTile - 1) / kFourStepTile * kFourStepTile) : 0;
+  if (words > kNoAllocScratchWords)
+    return fail(c, FNTRS_E_NOMEM,
+                "fntrs_encode_noalloc: the four-step scratch needs %zu words, above its fixed %zu "
+                "(batch * N * lanes rounded up to 32)",
+                words, kNoAllocScratchWords);
+  if (c->device == FNTRS_HOST_ONLY) return fail(c, FNTRS_E_DEVICE, "host-only context: arguments valid, no device");
+  if (!c->noalloc_scratch) return fail(c, FNTRS_E_DEVICE, "the no-allocation scratch has no device address");
+  DeviceGuard g(c->device);
+  return encode_run(c, N, k, lanes, src, ld_src, stride_src, dst, ld_dst, stride_dst, batch, n < N ? n : 0,
+                    (hipStream_t)stream, c->noalloc_scratch);
 }
 
 int fntrs_locator(fntrs_ctx* c, uint32_t n, uint32_t k, const uint32_t* positions, uint32_t npos, void* stream,

@@ -67,6 +67,7 @@ struct fntrs_ctx {
   size_t cap = fntrs::kDefaultCap, used = 0;
   uint32_t* tw = nullptr;            // tw[e] = 3^e mod p, e < 65536
   uint32_t* twi = nullptr;           // twi[e] = 3^-e mod p
+  uint32_t* noalloc_scratch = nullptr;   // device address of the no-allocation encoder's scratch
   size_t lds_max = 65536;
   fntrs::CtCfg enc_cfg[16] = {};     // kernel configuration per log2 transform size
   fntrs::CtCfg dec_cfg[16] = {};

@@ -71,6 +71,7 @@ SIGNATURES = {
     "fntrs_destroy": (None, [_vp]),
     "fntrs_last_error": (ctypes.c_char_p, [_vp]),
     "fntrs_encode": (_int, [_vp, _u32, _u32, _u32, _vp, _sz, _sz, _vp, _sz, _sz, _u32, _u32, _vp]),
+    "fntrs_encode_noalloc": (_int, [_vp, _u32, _u32, _u32, _vp, _sz, _sz, _vp, _sz, _sz, _u32, _u32, _vp]),
     "fntrs_locator": (_int, [_vp, _u32, _u32, _pu32, _u32, _vp, ctypes.POINTER(_vp)]),
     "fntrs_locator_batch": (_int, [_vp, _u32, _pu32, _pu32, ctypes.POINTER(_pu32), _pu32, _vp,
                                    ctypes.POINTER(_vp)]),
@@ -145,6 +146,12 @@ def fntrs_last_error(ctx: int) -> str:
 def fntrs_encode(ctx, n, k, lanes, src, ld_src, stride_src, dst, ld_dst, stride_dst, batch, flags=0, stream=0):
     return lib().fntrs_encode(ctx, n, k, lanes, src, ld_src, stride_src, dst, ld_dst, stride_dst,
                               batch, flags, stream)
+
+
+def fntrs_encode_noalloc(ctx, n, k, lanes, src, ld_src, stride_src, dst, ld_dst, stride_dst, batch, flags=0,
+                         stream=0):
+    return lib().fntrs_encode_noalloc(ctx, n, k, lanes, src, ld_src, stride_src, dst, ld_dst, stride_dst,
+                                      batch, flags, stream)
 
 
 def fntrs_locator(ctx, n, k, positions, stream=0):

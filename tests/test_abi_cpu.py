@@ -83,6 +83,25 @@ def test_encode_validation(hctx):
     assert "flags" in fntrs.fntrs_last_error(hctx)
 
 
+def test_encode_noalloc_validation(hctx):
+    """The no-allocation encoder checks like fntrs_encode, takes no flags and
+    refuses, before any device work, a four-step scratch above its fixed
+    2^25 words."""
+    def na(n, k, lanes, batch=1, flags=0):
+        return fntrs.fntrs_encode_noalloc(hctx, n, k, lanes, SRC, lanes, k * lanes, DST + (1 << 36), lanes,
+                                          n * lanes, batch, flags, 0)
+    assert na(512, 256, 64) == fntrs.FNTRS_E_DEVICE                   # valid, no device
+    assert na(65536, 32768, 512) == fntrs.FNTRS_E_DEVICE              # 65536 * 512 = 2^25 words: fits
+    assert na(65536, 32768, 513) == fntrs.FNTRS_E_NOMEM               # 65536 * 544 words
+    assert "scratch" in fntrs.fntrs_last_error(hctx)
+    assert na(32768, 16384, 512, batch=2) == fntrs.FNTRS_E_DEVICE
+    assert na(32768, 16384, 512, batch=3) == fntrs.FNTRS_E_NOMEM
+    assert na(65536, 8192, 100000) == fntrs.FNTRS_E_DEVICE            # K < 2^14: no scratch
+    assert na(512, 256, 64, flags=fntrs.FNTRS_FLAG_VALIDATE) == fntrs.FNTRS_E_INVAL
+    assert na(512, 256, 64, flags=fntrs.FNTRS_SYSTEMATIC) == fntrs.FNTRS_E_INVAL
+    assert na(8, 9, 4) == fntrs.FNTRS_E_INVAL
+
+
 def test_systematic_flag_validation(hctx):
     """The systematic code (Sec. II-C) is a flag of the single calls, rejected
     in batches."""
