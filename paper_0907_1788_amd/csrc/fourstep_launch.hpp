@@ -3,24 +3,10 @@
 #include <hip/hip_runtime.h>
 
 #include "codec_args.hpp"
+#include "kernel_args.hpp"
 
 namespace fntrs {
 
-struct FourStepArgs {
-  const uint32_t* in;       // first-pass input (recv / src) or scratch
-  uint64_t ld_in, stride_in;
-  uint32_t* out;            // scratch or final output
-  uint64_t ld_out, stride_out;
-  const uint32_t* tw;       // 3^e
-  const uint32_t* twi;      // 3^-e
-  const uint32_t* wfull;    // decoder weights per position
-  const uint32_t* ridx;     // compact recv row per position
-  const uint32_t* ahat;     // FNT_M(A mod x^k) / M, natural order
-  uint32_t n, k, M, lanes;
-  int logn, logm;
-  uint32_t full, tiles, subs, vec;   // subs: sub-transforms per block
-  uint32_t rows_out;                 // encoder: only rows < rows_out of out are written (0: all n)
-};
 
 // Lanes per tile of the four-step kernels.
 constexpr int kFourStepTile = 32;

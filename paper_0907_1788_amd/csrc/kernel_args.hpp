@@ -1,0 +1,90 @@
+// Kernel argument structs of the coding and locator kernels: plain data
+// (pointers and sizes) that the host fills in and passes by value or through
+// device-side tables.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+
+namespace fntrs {
+
+struct EncodeArgs {
+  const uint32_t* src;
+  uint64_t ld_src, stride_src;
+  uint32_t* dst;
+  uint64_t ld_dst, stride_dst;
+  const uint32_t* tw;        // tw[e] = 3^e
+  const uint32_t* twi;       // twi[e] = 3^-e
+  uint32_t n, k, lanes;
+  int logn, logK;            // transform size K = 2^logK >= k, K <= n
+  uint32_t tiles, cosets;    // lane tiles per block, n / K
+  uint32_t vec;              // src/dst rows are 16-byte aligned (vector access allowed)
+  uint32_t rows_out;         // only rows i < rows_out of dst are written (0: all n)
+};
+
+struct DecodeArgs {
+  const uint32_t* recv;
+  uint64_t ld_recv, stride_recv;
+  uint32_t* dst;
+  uint64_t ld_dst, stride_dst;
+  const uint32_t* tw;
+  const uint32_t* twi;
+  const uint32_t* wfull;    // per position z < n: decoder weight (0 if z is erased)
+  const uint32_t* ridx;     // per position z < n: row of z in a compact recv
+  const uint32_t* ahat_br;  // FNT_M of A's low part, bit-reversed order, times M^-1
+  uint32_t n, k, lanes;
+  int logn, logk;
+  uint32_t full;            // recv holds n rows indexed by position
+  uint32_t tiles, vec;
+  uint32_t row0;            // a received row of recv: erased positions read it and discard the value
+};
+
+// Work table of the batched path: the jobs of one class (one transform size,
+// one kernel configuration) share a persistent launch; job j owns the work
+// items [start[j], start[j+1]), numbered as the single-job grid numbers its
+// workgroups.
+template <class Args>
+struct JobTable {
+  const Args* jobs;
+  const uint32_t* start;    // njobs + 1 ascending entries, start[0] = 0
+  uint32_t njobs, total;    // total = start[njobs]
+};
+
+struct FourStepArgs {
+  const uint32_t* in;       // first-pass input (recv / src) or scratch
+  uint64_t ld_in, stride_in;
+  uint32_t* out;            // scratch or final output
+  uint64_t ld_out, stride_out;
+  const uint32_t* tw;       // 3^e
+  const uint32_t* twi;      // 3^-e
+  const uint32_t* wfull;    // decoder weights per position
+  const uint32_t* ridx;     // compact recv row per position
+  const uint32_t* ahat;     // FNT_M(A mod x^k) / M, natural order
+  uint32_t n, k, M, lanes;
+  int logn, logm;
+  uint32_t full, tiles, subs, vec;   // subs: sub-transforms per block
+  uint32_t rows_out;                 // encoder: only rows < rows_out of out are written (0: all n)
+};
+
+// One erasure pattern of a locator batch: where its positions come from,
+// where its state goes, its scratch, its sizes.
+struct LocDesc {
+  const uint32_t* zin;      // the k received positions (batch upload)
+  uint32_t* pos;            // state: positions, k words
+  uint32_t* wfull;          // state: decoder weight per position, n words
+  uint32_t* ridx;           // state: compact row per position, n words
+  uint32_t* ahat_br;        // state: FNT_M(A mod x^k) / M, bit-reversed, M words
+  uint32_t* ahat_s;         // state: the same in natural order, M words
+  uint32_t* A;              // state: A(x), k+1 coefficients
+  uint32_t* w;              // state: 1/A'(x_i), k words
+  uint32_t* ahat;           // state: FNT_M(A mod x^k), M words
+  uint32_t* t0;             // scratch: product-tree levels, k words each
+  uint32_t* t1;
+  uint32_t* spec;           // scratch: parked transforms, then A', k words
+  uint32_t* vals;           // scratch: A' at every n-th root, n words
+  uint32_t* poly;           // t0 or t1: where the tree leaves A mod x^k
+  uint32_t n, k, G;         // k: points of the product tree (a power of two); G points per leaf
+  uint32_t kr;              // received positions (k rounded up to the tree is padded with roots at 0)
+  int logn, logk, logm;
+};
+
+}  // namespace fntrs

@@ -6,6 +6,7 @@
 #pragma once
 #include "ct_kernels.hpp"
 #include "lds_fnt.hpp"
+#include "kernel_args.hpp"
 
 namespace fntrs {
 
@@ -14,27 +15,6 @@ __device__ __forceinline__ uint32_t point_of(const uint32_t* tw, uint32_t z, int
   return tw[(z << (16 - logn)) & 0xFFFFu];
 }
 
-// One erasure pattern of a locator batch: where its positions come from,
-// where its state goes, its scratch, its sizes.
-struct LocDesc {
-  const uint32_t* zin;      // the k received positions (batch upload)
-  uint32_t* pos;            // state: positions, k words
-  uint32_t* wfull;          // state: decoder weight per position, n words
-  uint32_t* ridx;           // state: compact row per position, n words
-  uint32_t* ahat_br;        // state: FNT_M(A mod x^k) / M, bit-reversed, M words
-  uint32_t* ahat_s;         // state: the same in natural order, M words
-  uint32_t* A;              // state: A(x), k+1 coefficients
-  uint32_t* w;              // state: 1/A'(x_i), k words
-  uint32_t* ahat;           // state: FNT_M(A mod x^k), M words
-  uint32_t* t0;             // scratch: product-tree levels, k words each
-  uint32_t* t1;
-  uint32_t* spec;           // scratch: parked transforms, then A', k words
-  uint32_t* vals;           // scratch: A' at every n-th root, n words
-  uint32_t* poly;           // t0 or t1: where the tree leaves A mod x^k
-  uint32_t n, k, G;         // k: points of the product tree (a power of two); G points per leaf
-  uint32_t kr;              // received positions (k rounded up to the tree is padded with roots at 0)
-  int logn, logk, logm;
-};
 
 // Pattern owning index x of a batch stage: the last i with start[i] <= x.
 __device__ __forceinline__ uint32_t loc_find(const uint32_t* start, uint32_t count, uint32_t x) {

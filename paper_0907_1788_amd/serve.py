@@ -58,19 +58,28 @@ class Request:
         return 2 * self.k * self.lanes
 
     def device_bytes(self) -> int:
-        """Working-set charge: input, output, locator state, four-step scratch."""
+        """Working-set charge: input, output, locator state, four-step scratch.
+
+        Transforms of 2^14 points or more (encode: K = 2^ceil(log2 k);
+        decode: N = 2^ceil(log2 n)) run as four-step passes through a
+        scratch of N rows (decode: N + M rows, M the low-product length) of
+        `lanes` rounded up to 32, which the batch holds while it runs."""
         L = self.lanes
+        L32 = (L + 31) // 32 * 32
+        logn = (self.n - 1).bit_length()
+        logk = (self.k - 1).bit_length()
+        N = 1 << logn
         if self.op == ENCODE:
             b = 4 * L * (self.k + self.n)
-            if self.k > 32768:
-                b += 4 * self.n * ((L + 31) // 32 * 32)
+            if max(1, logk) >= 14:
+                b += 4 * N * L32
             return b
         rows_in = self.k if self.compact else self.n
         b = 4 * L * (rows_in + self.k)
-        m = max(2 * self.k, self.n // 2)
-        b += 4 * (2 * self.k + 2 * self.n + 3 * m + 64 * 8)          # locator state
-        if self.n == 65536:
-            b += 4 * (self.n + m) * ((L + 31) // 32 * 32)
+        m = 1 << max(logk + 1, logn - 1) if self.k < N else N   # M = max(2K, N/2)
+        b += 4 * (2 * self.k + 2 * N + 3 * m + 64 * 8)               # locator state
+        if N >= 1 << 14:
+            b += 4 * (N + m) * L32
         return b
 
 
