@@ -1,15 +1,17 @@
 """Benchmark of the FNT Reed-Solomon hot path on one MI355X.
 
-One step = encode a batch of codeword blocks, build the locator of a fresh
-erasure pattern, and decode the batch from the received rows (every row of
-the method: encoder FNT, locator steps 1-3, decoder steps 4-6).
+Default workload (the headline): an uneven batch of 512 codewords, k = 2^6 ..
+2^14, rate 1/2 or 1/4 (n = 128 .. 65536), 128 .. 8192 16-bit lanes per symbol,
+each codeword with its own uniformly random erasure pattern.  One step =
+batched encode of every codeword, the locators of a fresh pattern per
+codeword built together, batched decode (every row of the method: encoder
+FNT, locator steps 1-3, decoder steps 4-6).  The same batch is also run as
+replayed HIP graphs and through the plain per-codeword calls.  The
+single-size workloads (k=4096 n=8192 2048 lanes x 64 blocks; k=256 n=512 512
+lanes; k=32768 n=65536 512 lanes) follow as secondary figures.
 
-Workload (default): k = 4096 source symbols, n = 8192, 2048 16-bit lanes per
-symbol (4 KiB), 64 codeword blocks sharing one uniformly random erasure
-pattern of n - k positions; inputs are uniform 16-bit source symbols stored as
-uint32 residues, resident in device memory before timing starts.
-
-Prints one JSON line (see the fields below).
+Inputs are uniform 16-bit source symbols stored as uint32 residues, resident
+in device memory before timing starts.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -28,10 +30,13 @@ import numpy as np  # noqa: E402
 # 39.3 T lane-ops/s; a modular radix-2 butterfly over GF(65537) costs at
 # least 6 int32 operations in the kernels' representation (two 24-bit
 # multiplies, two folding adds, one add, one subtract), so the chip tops out
-# at 39.3e12 / 6 butterflies per second.
+# at 39.3e12 / 6 butterflies per second.  The 6 is the instruction floor of
+# the representation, an assumption of the peak, not a measured count.
 VALU_LANE_OPS = 256 * 64 * 2.4e9
 OPS_PER_BUTTERFLY = 6
 ALU_PEAK_BFLY = VALU_LANE_OPS / OPS_PER_BUTTERFLY
+PEAK_BASIS = ("256 CUs x 64 int32 lanes x 2.4 GHz / 6 VALU ops per radix-2 butterfly "
+              "(2 mul24 + 2 fold + add + sub: the floor of the representation, assumed)")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 WORKLOADS = {
@@ -47,7 +52,7 @@ UNEVEN = "uneven512_seed4"
 # sizes from the uneven-batch distribution, offered load swept around the
 # measured batched peak, 32 GB device working-set cap
 SERVED = "served_poisson"
-DEFAULT = "k4096_n8192_l2048_b64"
+DEFAULT = UNEVEN
 HBM_PEAK_GBS = 8000.0
 
 
@@ -102,55 +107,91 @@ def stored_traffic(kernel, workload):
     return e["hbm_bytes_per_launch"]
 
 
-def cpu_baseline(k, n, seed, budget_s=10.0, systematic=False):
-    """The CPU oracle timed on a bounded sample of the workload.
+def oracle_workers():
+    """Worker processes for the CPU oracle: the host's cores, at most 16 (the
+    CPU share of one GPU on the benchmark machines)."""
+    return max(1, min(16, os.cpu_count() or 1))
 
-    One codeword block; a probe of a few lanes sizes each leg so that encode
-    (Horner evaluation) and decode (Lagrange interpolation) each take about
-    ``budget_s`` seconds, whatever the host's speed.  ``systematic`` times the
-    oracle's systematic code instead (Sec. II-C).
-    """
+
+def _oracle_leg(job):
+    """One timed leg of the CPU oracle, run in a worker process: Horner
+    encode and Lagrange decode (or the systematic code) of `lanes` lanes of one
+    codeword; returns (k, n, lanes, encode s, decode s)."""
+    k, n, lanes, seed, systematic = job
     from oracle import codec
     from paper_0907_1788_amd import synth
-    src_all = synth.source(seed, 1, k, 2048)[0].astype(np.int64)
+    src = synth.source(seed, 1, k, lanes)[0].astype(np.int64)
     z = synth.received_positions(seed + 1, n, k)
     encode = codec.systematic_encode if systematic else codec.encode
     decode = codec.systematic_decode if systematic else codec.decode_lagrange
+    t0 = time.perf_counter()
+    e = encode(src, n)
+    te = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    d = decode(n, z, e[z])
+    td = time.perf_counter() - t0
+    if not np.array_equal(d, src):
+        raise AssertionError(f"oracle round trip failed at k={k} n={n}")
+    return k, n, lanes, te, td
 
-    def enc(lanes):
-        t0 = time.perf_counter()
-        e = encode(src_all[:, :lanes], n)
-        return time.perf_counter() - t0, e
 
-    def dec(e, lanes):
-        t0 = time.perf_counter()
-        d = decode(n, z, e[z][:, :lanes])
-        dt = time.perf_counter() - t0
-        assert np.array_equal(d, src_all[:, :lanes])
-        return dt
+def _oracle_lanes(k, n, budget_s):
+    """Lanes of one leg that take about budget_s seconds (the oracle's cost
+    is about n*k multiply-adds per lane to encode and a few k^2 to decode)."""
+    per_lane = 8e-9 * n * k + 3e-8 * k * k
+    return int(max(1, min(4096, budget_s / per_lane)))
 
-    probe = 4
-    t_probe, _ = enc(probe)
-    lanes_enc = int(min(2048, max(probe, probe * budget_s / max(t_probe, 1e-6))))
-    t_enc, e = enc(lanes_enc)
-    t_probe = dec(e, min(probe, lanes_enc))
-    lanes_dec = int(min(lanes_enc, max(probe, probe * budget_s / max(t_probe, 1e-6))))
-    t_dec = dec(e, lanes_dec)
-    # payload: 2 bytes per source symbol lane, for encode and for decode
-    enc_rate = 2 * k * lanes_enc / t_enc
-    dec_rate = 2 * k * lanes_dec / t_dec
+
+def _run_legs(jobs, workers):
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(workers) as pool:
+        return pool.map(_oracle_leg, jobs, chunksize=1)
+
+
+def cpu_baseline(k, n, seed, budget_s=8.0, systematic=False):
+    """The CPU oracle on a bounded sample of a single-size workload: every
+    worker process times encode + decode of its own share of one block's
+    lanes; the aggregate rate over the workers is the oracle's throughput."""
+    workers = oracle_workers()
+    lanes = _oracle_lanes(k, n, budget_s)
+    legs = _run_legs([(k, n, lanes, seed + 101 * w, systematic) for w in range(workers)], workers)
+    enc_rate = sum(2 * k * l / te for _, _, l, te, _ in legs)
+    dec_rate = sum(2 * k * l / td for _, _, l, _, td in legs)
     value = 2.0 / (1.0 / enc_rate + 1.0 / dec_rate) / 1e9
-    return {"value": value, "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"one block, k={k} n={n}: {'systematic ' if systematic else ''}encode of {lanes_enc} "
-                      f"lanes ({t_enc:.1f} s) and decode of {lanes_dec} lanes ({t_dec:.1f} s) by Horner and "
-                      f"Lagrange, single-threaded numpy on a host with {os.cpu_count()} cores; rate scaled "
-                      f"linearly to the full payload",
+    wall = max(te + td for *_, te, td in legs)
+    return {"value": value, "unit": "GB/s", "cores": workers, "kind": "oracle",
+            "sample": f"k={k} n={n}: {workers} processes, each the {'systematic ' if systematic else ''}encode "
+                      f"(Horner) and decode (Lagrange) of {lanes} lanes of one block, {wall:.1f} s wall; "
+                      f"rate = sum over the processes, extrapolated linearly in lanes to the full payload "
+                      f"(host reports {os.cpu_count()} cores)",
             "enc_GBps": enc_rate / 1e9, "dec_GBps": dec_rate / 1e9}
+
+
+def cpu_baseline_uneven(sizes, seed, budget_s=6.0):
+    """The CPU oracle on a bounded sample of the uneven batch: one leg per
+    distinct (k, n) of the batch, a few lanes each, in parallel worker
+    processes; every codeword's time is its class's time per lane times its
+    lanes, and the batch's time is their sum divided over the workers."""
+    workers = oracle_workers()
+    classes = sorted({(k, n) for k, n, _ in sizes}, key=lambda c: -c[0] * c[1])
+    jobs = [(k, n, _oracle_lanes(k, n, budget_s), seed + 7 * i, False) for i, (k, n) in enumerate(classes)]
+    legs = _run_legs(jobs, workers)
+    per_lane = {(k, n): ((te + td) / l, te / l, td / l) for k, n, l, te, td in legs}
+    t1 = sum(per_lane[(k, n)][0] * l for k, n, l in sizes)
+    payload = sum(2 * k * l for k, n, l in sizes)
+    wall = max(te + td for *_, te, td in legs)
+    return {"value": 2 * payload / (t1 / workers) / 1e9, "unit": "GB/s", "cores": workers, "kind": "oracle",
+            "sample": f"one leg per (k, n) class of the batch ({len(classes)} classes, "
+                      f"{sum(j[2] for j in jobs)} lanes in all) timed in {workers} worker processes "
+                      f"({wall:.1f} s wall for the longest): Horner encode + Lagrange decode; extrapolated "
+                      f"linearly in lanes to every codeword of the batch and divided over {workers} cores "
+                      f"(host reports {os.cpu_count()} cores)"}
 
 
 def run_uneven(args, torch, fntrs, synth):
     """Uneven batch: one step = batched encode of all codewords, the locators
-    of a fresh erasure pattern per codeword built together, batched decode."""
+    of a fresh erasure pattern per codeword built together, batched decode.
+    Returns the result dict (printed by main)."""
     sizes = synth.uneven_batch(4, 512)
     dev = torch.device("cuda:0")
     gen = torch.Generator(device=dev)
@@ -186,6 +227,7 @@ def run_uneven(args, torch, fntrs, synth):
         e[3].record(stream)
         held.append(locs)
 
+    log("warmup", args.warmup)
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
@@ -196,6 +238,7 @@ def run_uneven(args, torch, fntrs, synth):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     exact = all(torch.equal(dec, src) for k, n, lanes, src, enc, dec in cws)
+    log("exact", exact)
     ph = {name: float(np.mean([ev[i][a].elapsed_time(ev[i][b]) for i in range(args.warmup, nsteps)]))
           for name, a, b in (("encode", 0, 1), ("locator", 1, 2), ("decode", 2, 3))}
     step_ms = [ev[i][0].elapsed_time(ev[i][3]) for i in range(args.warmup, nsteps)]
@@ -211,23 +254,21 @@ def run_uneven(args, torch, fntrs, synth):
     bfly = float(sum(encode_butterflies(int(n), int(k), int(l), 1) + decode_butterflies(int(n), int(k), int(l), 1)
                      for k, n, l in zip(ks, ns, ls)))
     alg = float((4 * (ks + ns) * ls + 8 * ks * ls).sum())
-    coding_ms = ph["encode"] + ph["decode"]
     res = {
         "metric": "encode/decode payload GB/s (bit-exact) + p50/p99 latency, batched vs plain",
         "value": round(2 * payload / (ms * 1e-3) / 1e9, 3), "unit": "GB/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "paper_context": PAPER_CONTEXT, "dtype": "u32", "data": "synthetic",
         "config": {"workload": UNEVEN, "codewords": len(cws), "payload_bytes": int(payload),
+                   "k": "2^6..2^14", "rate": "1/2 or 1/4", "lanes": "128..8192",
                    "pattern": "fresh uniform random n-k erasures per codeword every step (locators rebuilt)",
                    "parallelism": "single GPU"},
         "bit_exact": bool(exact),
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
         "phases_ms": ph,
-        "roofline": {"bound": "alu", "kernel": "k_enc_tab + k_dec_tab (all size classes)",
-                     "achieved": round(bfly / (coding_ms * 1e-3) / 1e12, 4), "peak": round(ALU_PEAK_BFLY / 1e12, 4),
-                     "unit": "Tbutterfly/s", "frac": round(bfly / (coding_ms * 1e-3) / ALU_PEAK_BFLY, 4),
-                     "traffic": None, "algorithmic_hbm_bytes": alg,
-                     "hbm_frac": round(alg / (coding_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "step": {"butterflies": bfly, "algorithmic_hbm_bytes": alg,
+                 "alu_frac": round(bfly / (ms * 1e-3) / ALU_PEAK_BFLY, 4),
+                 "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
     }
     # the same batch captured in graphs (fixed patterns), replayed
     locs = ctx.locators(patterns[-1], stream=stream)
@@ -248,6 +289,30 @@ def run_uneven(args, torch, fntrs, synth):
                     "exact": bool(all(torch.equal(dec, src) for k, n, lanes, src, enc, dec in cws))}
     g_enc.destroy()
     g_dec.destroy()
+    # The dominant kernel class of this workload: the four-step decoder
+    # (k4_dec1..4, transforms of 2^14 points or more), about half of the
+    # summed kernel time.  One call on the largest such code of the batch,
+    # timed with events on the stream it runs on.
+    j4 = max((i for i, c in enumerate(cws) if c[1] >= 16384), key=lambda i: (cws[i][1], cws[i][2]))
+    k4, n4, l4, src4, enc4, dec4 = cws[j4]
+    ctx.decode(locs[j4], enc4, dec4, fntrs.FNTRS_RECV_FULL, stream=stream)
+    e4 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    reps = 10
+    e4[0].record(stream)
+    for _ in range(reps):
+        ctx.decode(locs[j4], enc4, dec4, fntrs.FNTRS_RECV_FULL, stream=stream)
+    e4[1].record(stream)
+    torch.cuda.synchronize()
+    ms4 = e4[0].elapsed_time(e4[1]) / reps
+    b4 = decode_butterflies(n4, k4, l4, 1)
+    a4 = 8 * k4 * l4
+    res["roofline"] = {"bound": "alu", "kernel": f"four-step decoder k4_dec1..4 (one call: n={n4} k={k4} "
+                                                 f"lanes={l4}, four launches back to back)",
+                       "achieved": round(b4 / (ms4 * 1e-3) / 1e12, 4), "peak": round(ALU_PEAK_BFLY / 1e12, 4),
+                       "unit": "Tbutterfly/s", "frac": round(b4 / (ms4 * 1e-3) / ALU_PEAK_BFLY, 4),
+                       "traffic": stored_traffic("k4_dec", UNEVEN), "ms_per_call": round(ms4, 4),
+                       "butterflies_per_call": b4, "algorithmic_hbm_bytes": a4,
+                       "hbm_frac": round(a4 / (ms4 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "peak_basis": PEAK_BASIS}
     if not args.no_plain:
         # plain path: one synchronous request per codeword, no batching
         lat = []
@@ -266,12 +331,12 @@ def run_uneven(args, torch, fntrs, synth):
     for loc in locs:
         loc.release()
     ctx.close()
+    del cws, enc_jobs
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline")
-        k, n, lanes = 4096, 8192, 64
-        res["cpu_baseline"] = cpu_baseline(k, n, args.seed)
-        res["cpu_baseline"]["sample"] += " (one mid-size codeword of the batch's distribution)"
-    print(json.dumps(res), flush=True)
+        res["cpu_baseline"] = cpu_baseline_uneven(sizes, args.seed)
+    return res
 
 
 def served_pool(torch, ctx, synth, seed, count=64):
@@ -374,53 +439,13 @@ def run_served(args, torch, fntrs, synth):
     print(json.dumps(res), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + [UNEVEN, SERVED])
-    ap.add_argument("--requests", type=int, default=2000, help="requests per load point (served workload)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--systematic", action="store_true",
-                    help="the systematic code (Sec. II-C): interpolation + transform on both sides")
-    ap.add_argument("--seed", type=int, default=2024)
-    ap.add_argument("--flush-mib", type=int, default=512,
-                    help="MiB written between steps when the workload's buffers total under 1 GiB, so that "
-                         "no step starts from data the previous one left in the caches (0: never)")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="only run a plain device copy of MIB MiB (calibrates HBM byte counters) and exit")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only: lanes, codewords and "
-                                   "requests shard over GPUs with no exchange, so one GPU's "
-                                   "throughput is the figure"}))
-        sys.exit(2)
-
-    import torch
-    from paper_0907_1788_amd import fntrs, synth
-
-    if args.copy_calibration:
-        nbytes = args.copy_calibration << 20
-        a = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(args.steps):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": args.steps}), flush=True)
-        return
-
-    if args.workload == UNEVEN:
-        run_uneven(args, torch, fntrs, synth)
-        return
-    if args.workload == SERVED:
-        run_served(args, torch, fntrs, synth)
-        return
-
-    k, n, lanes, blocks = WORKLOADS[args.workload]
+def run_single(args, torch, fntrs, synth, workload, cpu=True):
+    """A single-size workload: one step = encode every block, build the locator
+    of a fresh pattern shared by the blocks, decode every block.  Returns the
+    result dict."""
+    k, n, lanes, blocks = WORKLOADS[workload]
     dev = torch.device("cuda:0")
-    log("workload", args.workload, "generating inputs")
+    log("workload", workload, "generating inputs")
     src = torch.empty((blocks, k, lanes), dtype=torch.int32, device=dev)
     for b in range(blocks):
         src[b] = torch.from_numpy(synth.source(args.seed * 1000 + b, 1, k, lanes)[0].astype(np.int32)).to(dev)
@@ -503,7 +528,7 @@ def main():
         "paper_context": PAPER_CONTEXT,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "k": k, "n": n, "lanes": lanes, "blocks": blocks,
+        "config": {"workload": workload, "k": k, "n": n, "lanes": lanes, "blocks": blocks,
                    "code": "systematic" if args.systematic else "non-systematic",
                    "pattern": "uniform random n-k erasures, fresh pattern (locator rebuilt) every step",
                    "caches": (f"{args.flush_mib} MiB written between steps, outside the timed events"
@@ -516,9 +541,9 @@ def main():
         # dominant kernel: the decoder, bound by the integer vector ALUs
         "roofline": {"bound": "alu", "kernel": "k_dec + k_enc_cos (systematic decode)" if args.systematic else "k_dec",
                      "achieved": round(dec_bfly / (dec_avg * 1e-3) / 1e12, 4),
-                     "peak": round(ALU_PEAK_BFLY / 1e12, 4), "unit": "Tbutterfly/s",
+                     "peak": round(ALU_PEAK_BFLY / 1e12, 4), "unit": "Tbutterfly/s", "peak_basis": PEAK_BASIS,
                      "frac": round(dec_bfly / (dec_avg * 1e-3) / ALU_PEAK_BFLY, 4),
-                     "traffic": None if args.systematic else stored_traffic("k_dec", args.workload),
+                     "traffic": None if args.systematic else stored_traffic("k_dec", workload),
                      "algorithmic_hbm_bytes": dec_bytes,
                      "hbm_frac": round(dec_bytes / (dec_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "encode_roofline": {"bound": "alu", "kernel": "k_dec + k_enc_cos (systematic encode)"
@@ -526,7 +551,7 @@ def main():
                             "achieved": round(enc_bfly / (enc_avg * 1e-3) / 1e12, 4),
                             "peak": round(ALU_PEAK_BFLY / 1e12, 4), "unit": "Tbutterfly/s",
                             "frac": round(enc_bfly / (enc_avg * 1e-3) / ALU_PEAK_BFLY, 4),
-                            "traffic": None if args.systematic else stored_traffic("k_enc_cos", args.workload),
+                            "traffic": None if args.systematic else stored_traffic("k_enc_cos", workload),
                             "algorithmic_hbm_bytes": enc_bytes,
                             "hbm_frac": round(enc_bytes / (enc_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
     }
@@ -551,9 +576,76 @@ def main():
                         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
                         "exact": bool(torch.equal(out, src))}
     ctx.close()
-    if not args.no_cpu_baseline:
+    del src, enc, out, flush
+    torch.cuda.empty_cache()
+    if cpu:
         log("cpu baseline")
         res["cpu_baseline"] = cpu_baseline(k, n, args.seed, systematic=args.systematic)
+    return res
+
+
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + [UNEVEN, SERVED])
+    ap.add_argument("--requests", type=int, default=2000, help="requests per load point (served workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true", help="uneven batch only, without the single-size workloads")
+    ap.add_argument("--systematic", action="store_true",
+                    help="the systematic code (Sec. II-C): interpolation + transform on both sides")
+    ap.add_argument("--seed", type=int, default=2024)
+    ap.add_argument("--flush-mib", type=int, default=512,
+                    help="MiB written between steps when the workload's buffers total under 1 GiB, so that "
+                         "no step starts from data the previous one left in the caches (0: never)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (calibrates HBM byte counters) and exit")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only: lanes, codewords and "
+                                   "requests shard over GPUs with no exchange, so one GPU's "
+                                   "throughput is the figure"}))
+        sys.exit(2)
+
+    import torch
+    from paper_0907_1788_amd import fntrs, synth
+
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        a = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": args.steps}), flush=True)
+        return
+
+    if args.workload == SERVED:
+        run_served(args, torch, fntrs, synth)
+        return
+    if args.workload != UNEVEN:
+        print(json.dumps(run_single(args, torch, fntrs, synth, args.workload, cpu=not args.no_cpu_baseline)),
+              flush=True)
+        return
+    res = run_uneven(args, torch, fntrs, synth)
+    if not args.no_secondary:
+        # the single-size workloads, briefly, as secondary figures
+        sec = argparse.Namespace(**vars(args))
+        sec.steps, sec.warmup, sec.systematic = max(3, min(args.steps, 10)), 2, False
+        other = {}
+        for w in ("k4096_n8192_l2048_b64", "k256_n512_l512_b1", "k32768_n65536_l512_b1"):
+            r = run_single(sec, torch, fntrs, synth, w, cpu=False)
+            other[w] = {key: r[key] for key in ("value", "ms_per_step", "bit_exact", "latency_ms", "phases_ms")}
+            other[w]["steps"] = sec.steps
+            other[w]["plain_GBps"] = r.get("plain", {}).get("value")
+            other[w]["decoder_alu_frac"] = r["roofline"]["frac"]
+            other[w]["encoder_alu_frac"] = r["encode_roofline"]["frac"]
+            log(w, other[w]["value"], "GB/s")
+        res["other_workloads"] = other
     print(json.dumps(res), flush=True)
 
 

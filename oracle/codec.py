@@ -9,7 +9,7 @@ points):
 * the root has order n (not n-1): r_n = 3^(65536/n) (Sec. II-B root choice);
 * encoding is e_i = s(r^i) in natural order i = 0..n-1 (Sec. II-B);
 * the decoder uses the first k received positions in ascending order
-  (Sec. II-B, "the first k evaluation points received");
+  (Sec. II-B: decoding uses the earliest k points received);
 * step 5 forms the power series S_j = -N'(r^(-j-1)), j = 0..k-1, which is the
   unscaled evaluation of N'(y) = sum_i n_i y^(z_i) at the inverse roots, and
   step 6 keeps P(x) = (A(x) S(x)) mod x^k.  P has degree < k and equals

@@ -1,4 +1,4 @@
-"""The prime field GF(65537) (Sec. II-A "The Fourier Transform over GF(q)").
+"""The prime field GF(65537) (Sec. II-A, the transform over a finite field).
 
 Residues are the integers 0 .. p-1; addition and product are taken modulo p.
 The paper fixes q = 65537, the Fermat prime 2^16 + 1 (Sec. II-B), and uses the
