@@ -16,4 +16,6 @@ Modules:
   codec     -- encoder (Sec. II-B), decoders by Gaussian elimination and by
                Lagrange interpolation (Sec. II-B), locator quantities used by
                the six-step interpolation (Sec. II-B, steps 1-6)
+  direct    -- the quadratic encoders and decoders of Sec. III (Tables I and II,
+               and the classic quadratic schemes of its footnote)
 """

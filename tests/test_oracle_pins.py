@@ -27,6 +27,13 @@ P18 systematic codewords are codewords; every k-subset decodes      -- brute for
 P19 systematic n = 4, k = 2 worked by Cramer's rule                 -- by hand
 P20 punctured length n: a prefix of the length-N code, still MDS    -- brute force
 P21 16-bit transport: 65536 is the only escape, round trip          -- definition
+P22 W V_R = I for the quadratic decoder's matrix (Sec. III)         -- identity
+P23 quadratic (Vandermonde) encoder = transform encoder; n=4 example -- two algorithms, by hand
+P24 quadratic decoder decodes from every k-subset                    -- brute force
+P25 Lagrange basis: L_i(x_j) = [i = j], sum_i L_i = 1                -- closed forms
+P26 systematic direct encoding (Table I) = systematic code; k=1, k=n -- P16..P19, closed forms
+P27 direct intermediate & FNT (Table I) = direct encoding            -- two algorithms
+P28 systematic direct decoding (Table II) from every k-subset        -- brute force
 """
 import itertools
 import os
@@ -34,7 +41,7 @@ import os
 import numpy as np
 import pytest
 
-from oracle import codec, field, poly, transform
+from oracle import codec, direct, field, poly, transform
 from paper_0907_1788_amd import synth
 
 P = 65537
@@ -422,3 +429,84 @@ def test_p21_sixteen_bit_transport():
     assert np.array_equal(codec.unpack16(*codec.pack16(r)), r.astype(np.int64))
     with pytest.raises(ValueError):
         codec.pack16([65537])
+
+
+# --------------------------------------------------------------- P22 .. P28
+@pytest.mark.parametrize("n,k,seed", [(8, 3, 1), (16, 5, 2), (64, 20, 3), (512, 64, 4), (1024, 1000, 5)])
+def test_p22_inverse_vandermonde_is_an_inverse(n, k, seed):
+    """Sec. III: the classic quadratic decoder multiplies the k received
+    symbols by the inverse of the generator's received rows.  W V_R = I,
+    with V_R[i][j] = x_i^j built here by repeated products."""
+    z = synth.received_positions(900 + seed, n, k).astype(np.int64)
+    W = direct.inverse_vandermonde(n, z)
+    x = codec.eval_points(n, z)
+    V = np.ones((k, k), dtype=np.int64)
+    for j in range(1, k):
+        V[:, j] = V[:, j - 1] * x % P
+    assert np.array_equal(W @ V % P if k <= 64 else direct._matmul(W, V), np.eye(k, dtype=np.int64))
+
+
+@pytest.mark.parametrize("n,k", [(4, 2), (16, 16), (64, 7), (256, 256), (512, 100)])
+def test_p23_quadratic_encoder_equals_transform_encoder(n, k):
+    """The generator-matrix product e = G s (G[i][j] = r^(ij), the Vandermonde
+    view of Sec. II-A) gives the transform of the zero-padded source."""
+    s = synth.residues(910 + n + k, (k, 3))
+    padded = np.pad(s.astype(np.int64), ((0, n - k), (0, 0)))
+    assert np.array_equal(direct.encode_direct(s, n), transform.dft(padded) if n <= 64 else transform.fnt(padded))
+    assert list(direct.encode_direct(np.array([[1], [65535]]), 4)[:, 0]) == [65536, 513, 3, 65026]
+
+
+@pytest.mark.parametrize("n,k", [(8, 3), (16, 4)])
+def test_p24_quadratic_decoder_every_subset(n, k):
+    s = synth.residues(920 + n, (k, 2))
+    e = codec.encode(s, n)
+    for z in itertools.combinations(range(n), k):
+        z = np.array(z)
+        assert np.array_equal(direct.decode_direct(n, z, e[z]), s.astype(np.int64)), z
+
+
+def test_p25_lagrange_basis_closed_forms():
+    """L_i(x_j) = 1 if i = j else 0, and sum_i L_i(y) = 1 (the interpolant of
+    the constant 1) at any point y."""
+    xs = codec.eval_points(64, np.array([0, 3, 9, 10, 33, 63]))
+    assert np.array_equal(direct.lagrange_values(xs, xs), np.eye(6, dtype=np.int64))
+    ys = np.array([0, 1, 2, 12345, 65536])
+    assert np.array_equal(direct.lagrange_values(xs, ys).sum(axis=1) % P, np.ones(5, dtype=np.int64))
+
+
+@pytest.mark.parametrize("n,k", [(4, 2), (8, 3), (16, 8), (64, 13), (512, 256)])
+def test_p26_systematic_direct_encoding(n, k):
+    """Table I, direct encoding: the parity rows C s give the systematic
+    codeword of Sec. II-C (pinned by P16..P19).  k = 1: every L_0 = 1, so
+    every parity symbol equals s_0.  n = 4: the Cramer example of P19."""
+    s = synth.residues(930 + n + k, (k, 2))
+    assert np.array_equal(direct.systematic_encode_direct(s, n), codec.systematic_encode(s, n))
+    assert np.array_equal(direct.parity_matrix(32, 1), np.ones((31, 1), dtype=np.int64))
+    assert direct.parity_matrix(16, 16).shape == (0, 16)
+    inv257 = pow(257, P - 2, P)
+    got = direct.systematic_encode_direct(np.array([[1], [65535]]), 4)[:, 0]
+    assert list(got) == [1, 65535, 251 * inv257 % P, 1022 * inv257 % P]
+
+
+@pytest.mark.parametrize("n,k", [(8, 3), (64, 32), (512, 200)])
+def test_p27_intermediate_then_transform_equals_direct_encoding(n, k):
+    """Table I, direct intermediate & FNT: W_0 s, then one transform, gives the
+    same systematic codeword, whose first k rows are the source."""
+    s = synth.residues(940 + n, (k, 2))
+    e = direct.systematic_encode_intermediate(s, n)
+    assert np.array_equal(e[:k], s.astype(np.int64))
+    assert np.array_equal(e, direct.systematic_encode_direct(s, n))
+
+
+@pytest.mark.parametrize("n,k", [(8, 3), (16, 4)])
+def test_p28_systematic_direct_decoding_every_subset(n, k):
+    """Table II, direct decoding: from every k-subset, the received source
+    symbols are kept and the missing ones recomputed; the result is the
+    source.  Its cost is k products per missing source symbol."""
+    s = synth.residues(950 + n, (k, 2))
+    e = codec.systematic_encode(s, n)
+    for z in itertools.combinations(range(n), k):
+        z = np.array(z)
+        assert np.array_equal(direct.systematic_decode_direct(n, z, e[z]), s.astype(np.int64)), z
+    assert direct.direct_decode_cost(16, np.arange(4, 8), 4) == 16
+    assert direct.direct_decode_cost(16, np.arange(0, 4), 4) == 0
