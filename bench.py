@@ -466,6 +466,8 @@ def run_single(args, torch, fntrs, synth, workload, cpu=True):
     step_ms = []
 
     sysf = fntrs.FNTRS_SYSTEMATIC if args.systematic else 0
+    if getattr(args, "direct", False):
+        sysf |= fntrs.FNTRS_DIRECT   # the quadratic methods of Sec. III (small codes)
 
     def step(i):
         e = ev[i]
@@ -530,6 +532,7 @@ def run_single(args, torch, fntrs, synth, workload, cpu=True):
         "data": "synthetic",
         "config": {"workload": workload, "k": k, "n": n, "lanes": lanes, "blocks": blocks,
                    "code": "systematic" if args.systematic else "non-systematic",
+                   "method": "direct (quadratic)" if getattr(args, "direct", False) else "FNT",
                    "pattern": "uniform random n-k erasures, fresh pattern (locator rebuilt) every step",
                    "caches": (f"{args.flush_mib} MiB written between steps, outside the timed events"
                               if flush is not None else "buffers larger than the caches" if footprint >= (1 << 30)
@@ -598,6 +601,8 @@ def main():
     ap.add_argument("--no-secondary", action="store_true", help="uneven batch only, without the single-size workloads")
     ap.add_argument("--systematic", action="store_true",
                     help="the systematic code (Sec. II-C): interpolation + transform on both sides")
+    ap.add_argument("--direct", action="store_true",
+                    help="the direct (quadratic) encoder and decoder of Sec. III instead of the transforms")
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--flush-mib", type=int, default=512,
                     help="MiB written between steps when the workload's buffers total under 1 GiB, so that "
@@ -635,7 +640,7 @@ def main():
     if not args.no_secondary:
         # the single-size workloads, briefly, as secondary figures
         sec = argparse.Namespace(**vars(args))
-        sec.steps, sec.warmup, sec.systematic = max(3, min(args.steps, 10)), 2, False
+        sec.steps, sec.warmup, sec.systematic, sec.direct = max(3, min(args.steps, 10)), 2, False, False
         other = {}
         for w in ("k4096_n8192_l2048_b64", "k256_n512_l512_b1", "k32768_n65536_l512_b1"):
             r = run_single(sec, torch, fntrs, synth, w, cpu=False)

@@ -64,6 +64,25 @@ enum {
 /* encode and decode flag: the systematic code of Sec. II-C (single calls
  * only; a batched job with this flag is rejected with FNTRS_E_UNSUPPORTED) */
 #define FNTRS_SYSTEMATIC 4u
+/* encode and decode flag: the direct (quadratic) methods of Sec. III instead
+ * of the transforms, for k <= 1024 and n <= 16384 (else FNTRS_E_UNSUPPORTED;
+ * decoding also needs k < n).  The result is the same, bit for bit; only the
+ * cost differs: a product with a fixed matrix, O(n k) per lane to encode and
+ * O(k^2) to decode, which on small codes does in one kernel what the
+ * transforms do in several passes.
+ *   encode:                 dst = G src, G[i][j] = r_N^(i j)
+ *   encode | SYSTEMATIC:    dst rows 0..k-1 = src, rows k..n-1 = C src, C the
+ *                           Lagrange basis of positions 0..k-1 evaluated at
+ *                           the other positions (Table I, direct encoding;
+ *                           C is built once per (n, k) and kept)
+ *   decode:                 dst = W v, W the inverse of the generator's rows
+ *                           at the received positions (built once per
+ *                           locator and kept with it)
+ *   decode | SYSTEMATIC:    the received source positions are copied and only
+ *                           the missing ones computed (Table II, direct
+ *                           decoding)
+ * Single calls only: a batched job with this flag is rejected. */
+#define FNTRS_DIRECT 8u
 
 /* Pseudo-device for fntrs_create: a context that touches no GPU.  Every call
  * on it runs the full host-side argument validation and, if the arguments
@@ -94,7 +113,7 @@ const char* fntrs_last_error(const fntrs_ctx* ctx);
  * 1 <= k <= n (any k, zero padding covers a k that is not a power of two,
  * Sec. II-B); lanes >= 1; batch >= 1 blocks.
  * src and dst must not overlap.
- * flags: 0, FNTRS_FLAG_VALIDATE, and/or FNTRS_SYSTEMATIC.  With
+ * flags: 0, FNTRS_FLAG_VALIDATE, FNTRS_SYSTEMATIC and/or FNTRS_DIRECT.  With
  * FNTRS_SYSTEMATIC the systematic code of Sec. II-C: the source is
  * interpolated on positions 0..k-1 into k intermediate symbols (the decoder,
  * with the locator of that pattern, which the context builds once and

@@ -198,7 +198,8 @@ int check_encode(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uin
   if (ld_src < lanes || ld_dst < lanes) return fail(c, FNTRS_E_INVAL, "ld_src/ld_dst smaller than lanes");
   if (batch > 1 && (stride_src < (size_t)(k - 1) * ld_src + lanes || stride_dst < (size_t)(n - 1) * ld_dst + lanes))
     return fail(c, FNTRS_E_INVAL, "block strides overlap consecutive blocks");
-  if (flags & ~(FNTRS_FLAG_VALIDATE | FNTRS_SYSTEMATIC)) return fail(c, FNTRS_E_INVAL, "unknown flags 0x%x", flags);
+  if (flags & ~(FNTRS_FLAG_VALIDATE | FNTRS_SYSTEMATIC | FNTRS_DIRECT))
+    return fail(c, FNTRS_E_INVAL, "unknown flags 0x%x", flags);
   const size_t sb = span_elems(batch, stride_src, k, ld_src, lanes) * 4;
   const size_t db = span_elems(batch, stride_dst, n, ld_dst, lanes) * 4;
   if (ranges_overlap(src, sb, dst, db)) return fail(c, FNTRS_E_INVAL, "src and dst overlap");
@@ -212,7 +213,7 @@ int check_decode(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, uint32_
   if (L->refs <= 0) return fail(c, FNTRS_E_INVAL, "locator was released");
   if (lanes < 1 || batch < 1) return fail(c, FNTRS_E_INVAL, "lanes=%u and batch=%u must be >= 1", lanes, batch);
   if (!recv || !dst) return fail(c, FNTRS_E_INVAL, "null recv or dst");
-  if (flags & ~(FNTRS_RECV_FULL | FNTRS_FLAG_VALIDATE | FNTRS_SYSTEMATIC))
+  if (flags & ~(FNTRS_RECV_FULL | FNTRS_FLAG_VALIDATE | FNTRS_SYSTEMATIC | FNTRS_DIRECT))
     return fail(c, FNTRS_E_INVAL, "unknown flags 0x%x", flags);
   const bool full = flags & FNTRS_RECV_FULL;
   const uint32_t k = L->k;
@@ -302,6 +303,11 @@ int validate_range(fntrs_ctx* c, const uint32_t* p, uint32_t batch, size_t strid
 
 static void free_locator(fntrs_ctx* c, fntrs_locator_t* L) {
   if (L->slab) c->used -= L->bytes;
+  for (DirectMat** m : {&L->direct_w, &L->direct_sys}) {
+    if (*m) c->used -= direct_mat_bytes(*m);
+    direct_mat_free(*m);
+    *m = nullptr;
+  }
   delete L;   // the slab goes with its last locator
 }
 
@@ -888,6 +894,8 @@ void fntrs_destroy(fntrs_ctx* c) {
   (void)hipDeviceSynchronize();
   for (auto& kv : c->cache) free_locator(c, kv.second);
   c->cache.clear();
+  for (auto& kv : c->parity) direct_mat_free(kv.second);
+  c->parity.clear();
   auto drop = [](fntrs_ctx::SideSet& ss) {
     for (int b = 0; b < fntrs_ctx::kSide; ++b) {
       if (ss.st[b]) (void)hipStreamDestroy(ss.st[b]);
@@ -917,6 +925,15 @@ int fntrs_encode(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uin
   if (flags & FNTRS_FLAG_VALIDATE) {
     int rc = validate_range(c, src, batch, stride_src, k, ld_src, lanes, s);
     if (rc) return rc;
+  }
+  if (flags & FNTRS_DIRECT) {   // the quadratic methods of Sec. III
+    const uint32_t N = pad_pow2(n);
+    if (!direct_fits(N, k))
+      return fail(c, FNTRS_E_UNSUPPORTED, "direct encoding covers k <= %u and n <= %u (k=%u n=%u)", kDirectMaxK,
+                  kDirectMaxN, k, n);
+    if (flags & FNTRS_SYSTEMATIC)
+      return direct_systematic_encode(c, N, n, k, lanes, src, ld_src, stride_src, dst, ld_dst, stride_dst, batch, s);
+    return direct_encode(c, N, n, k, lanes, src, ld_src, stride_src, dst, ld_dst, stride_dst, batch, s);
   }
   if (flags & FNTRS_SYSTEMATIC)
     return systematic_encode_run(c, n, k, lanes, src, ld_src, stride_src, dst, ld_dst, stride_dst, batch, s);
@@ -1008,6 +1025,16 @@ int fntrs_decode(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, uint32_
   if (flags & FNTRS_FLAG_VALIDATE) {
     int rc = validate_range(c, recv, batch, stride_recv, rrows, ld_recv, lanes, s);
     if (rc) return rc;
+  }
+  if (flags & FNTRS_DIRECT) {   // the quadratic methods of Sec. III
+    if (L->k == L->n || !direct_fits(L->n, L->k))
+      return fail(c, FNTRS_E_UNSUPPORTED, "direct decoding covers 1 <= k < n, k <= %u, n <= %u (k=%u n=%u)",
+                  kDirectMaxK, kDirectMaxN, L->k, L->nrows);
+    auto* Lm = const_cast<fntrs_locator_t*>(L);
+    if (flags & FNTRS_SYSTEMATIC)
+      return direct_systematic_decode(c, Lm, lanes, full, recv, ld_recv, stride_recv, dst, ld_dst, stride_dst, batch,
+                                      s);
+    return direct_decode(c, Lm, lanes, full, recv, ld_recv, stride_recv, dst, ld_dst, stride_dst, batch, s);
   }
   if (flags & FNTRS_SYSTEMATIC)
     return systematic_decode_run(c, L, lanes, full, recv, ld_recv, stride_recv, dst, ld_dst, stride_dst, batch, s);

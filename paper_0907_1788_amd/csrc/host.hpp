@@ -45,6 +45,12 @@ struct LocSlab {
   }
 };
 
+namespace fntrs {
+struct DirectMat;
+void direct_mat_free(DirectMat* m);
+size_t direct_mat_bytes(const DirectMat* m);
+}  // namespace fntrs
+
 struct fntrs_locator_s {
   uint32_t n = 0, k = 0;             // n: transform length, the power of two >= the code length
   uint32_t nrows = 0;                // the code length (rows of a full received buffer)
@@ -57,6 +63,11 @@ struct fntrs_locator_s {
   uint32_t *pos = nullptr, *wfull = nullptr, *ridx = nullptr, *ahat_br = nullptr, *ahat_s = nullptr;
   uint32_t *A = nullptr, *w = nullptr, *ahat = nullptr;
   hipEvent_t ready = nullptr;        // the slab's event
+  // direct (quadratic) decoders: the inverse of the received rows of the
+  // generator, and the systematic decoder's matrix and row tables
+  fntrs::DirectMat* direct_w = nullptr;
+  fntrs::DirectMat* direct_sys = nullptr;
+  uint32_t direct_e = 0, direct_g = 0;   // missing / received source positions
   int refs = 0;
   uint64_t last_use = 0;
 };
@@ -107,6 +118,8 @@ struct fntrs_ctx {
     bool pending = false;
   };
   std::vector<DevSlot> dev_slots;
+  // direct systematic encoder: parity matrix per (N, k)
+  std::map<std::pair<uint32_t, uint32_t>, fntrs::DirectMat*> parity;
 };
 
 namespace fntrs {
@@ -197,6 +210,21 @@ int check_decode(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, uint32_
 // Reads a strided device region back and checks every residue <= 65536.
 int validate_range(fntrs_ctx* c, const uint32_t* p, uint32_t batch, size_t stride, uint32_t rows, size_t ld,
                    uint32_t lanes, hipStream_t s);
+// Direct (quadratic) methods of Sec. III (direct.hip), for codes with
+// k <= kDirectMaxK and transform length N <= kDirectMaxN.
+constexpr uint32_t kDirectMaxK = 1024, kDirectMaxN = 16384;
+bool direct_fits(uint32_t N, uint32_t k);
+int direct_encode(fntrs_ctx* c, uint32_t N, uint32_t rows, uint32_t k, uint32_t lanes, const uint32_t* src,
+                  size_t ld_src, size_t stride_src, uint32_t* dst, size_t ld_dst, size_t stride_dst, uint32_t batch,
+                  hipStream_t s);
+int direct_decode(fntrs_ctx* c, fntrs_locator_t* L, uint32_t lanes, bool full, const uint32_t* recv, size_t ld_recv,
+                  size_t stride_recv, uint32_t* dst, size_t ld_dst, size_t stride_dst, uint32_t batch, hipStream_t s);
+int direct_systematic_encode(fntrs_ctx* c, uint32_t N, uint32_t rows, uint32_t k, uint32_t lanes,
+                             const uint32_t* src, size_t ld_src, size_t stride_src, uint32_t* dst, size_t ld_dst,
+                             size_t stride_dst, uint32_t batch, hipStream_t s);
+int direct_systematic_decode(fntrs_ctx* c, fntrs_locator_t* L, uint32_t lanes, bool full, const uint32_t* recv,
+                             size_t ld_recv, size_t stride_recv, uint32_t* dst, size_t ld_dst, size_t stride_dst,
+                             uint32_t batch, hipStream_t s);
 // Evicts unreferenced cached locators until `need` more bytes fit the cap.
 bool make_room(fntrs_ctx* c, size_t need);
 // Finds the cached locators of `count` patterns or builds the missing ones

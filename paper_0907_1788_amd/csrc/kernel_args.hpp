@@ -87,4 +87,23 @@ struct LocDesc {
   int logn, logk, logm;
 };
 
+// Direct (quadratic) methods: Y[b][yrow(r)][l] = sum_j M(r, j) X[b][xrow(j)][l]
+// mod p, r < R, j < K, l < lanes.  M(r, j) is M[r*ldm + j], or (M null)
+// r_N^(pw(r) j) from the table 3^e, with pw(r) = pw[r] (or r when pw is
+// null); null row maps are the identity.
+struct GemmArgs {
+  const uint32_t* M;
+  uint64_t ldm;
+  const uint32_t* pw;
+  const uint32_t* tw;
+  int logN;
+  const uint32_t* X;
+  uint64_t ld_x, stride_x;
+  const uint32_t* xrow;
+  uint32_t* Y;
+  uint64_t ld_y, stride_y;
+  const uint32_t* yrow;
+  uint32_t R, K, lanes;
+};
+
 }  // namespace fntrs

@@ -75,6 +75,8 @@ int make_plan(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, Plan& P) {
       return fail(c, FNTRS_E_INVAL, "job %u: FNTRS_FLAG_VALIDATE is not available in a batch", j);
     if (J.flags & FNTRS_SYSTEMATIC)
       return fail(c, FNTRS_E_UNSUPPORTED, "job %u: the systematic code is not available in a batch", j);
+    if (J.flags & FNTRS_DIRECT)
+      return fail(c, FNTRS_E_UNSUPPORTED, "job %u: the direct methods are not available in a batch", j);
     if (J.op == FNTRS_OP_ENCODE) {
       if (J.loc) return fail(c, FNTRS_E_INVAL, "job %u: an encode job takes no locator", j);
       if (int rc = check_encode(c, J.n, J.k, J.lanes, J.in, J.ld_in, J.stride_in, J.out, J.ld_out, J.stride_out,

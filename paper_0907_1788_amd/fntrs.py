@@ -42,6 +42,7 @@ FNTRS_RECV_COMPACT = 0
 FNTRS_RECV_FULL = 1
 FNTRS_FLAG_VALIDATE = 2
 FNTRS_SYSTEMATIC = 4
+FNTRS_DIRECT = 8
 
 FNTRS_OP_ENCODE = 0
 FNTRS_OP_DECODE = 1

@@ -55,6 +55,7 @@ namespace {
 using fntrs::DecodeArgs;
 using fntrs::EncodeArgs;
 using fntrs::FourStepArgs;
+using fntrs::GemmArgs;
 using fntrs::JobTable;
 using fntrs::LocDesc;
 
@@ -360,6 +361,8 @@ void model_loc_range(Op& x, const LocDesc* D, const uint32_t* start, uint32_t co
 // as the launch does).
 std::function<void(Op&)> kernel_model(const std::string& name, dim3 grid, void** args) {
   std::string base = name;
+  for (size_t an; (an = base.find("(anonymous namespace)::")) != std::string::npos;)
+    base.erase(an, std::strlen("(anonymous namespace)::"));
   const size_t par = base.find('(');
   if (par != std::string::npos) base = base.substr(0, par);
   const size_t lt = base.find('<');
@@ -422,6 +425,64 @@ std::function<void(Op&)> kernel_model(const std::string& name, dim3 grid, void**
     return [=](Op& x) {
       touch(x, (uintptr_t)src, span_words(batch, ss, 1, 0, lanes) * 4, false, "src");
       touch(x, (uintptr_t)dst, span_words(batch, sd, 1, 0, lanes) * 4, true, "dst");
+    };
+  }
+  if (fn == "k_gemm_modp") {
+    const GemmArgs a = *(const GemmArgs*)args[0];
+    const uint64_t batch = grid.z;
+    return [a, batch](Op& x) {
+      // row maps are read from the simulated memory; rows they name are touched one by one
+      auto rows_of = [&](const uint32_t* map, uint32_t count, const char* what) {
+        std::vector<uint32_t> r(count);
+        if (map) touch(x, (uintptr_t)map, (size_t)count * 4, false, what);
+        for (uint32_t i = 0; i < count; ++i) r[i] = map ? load_dev(x, map + i, what) : i;
+        return r;
+      };
+      if (a.M) touch(x, (uintptr_t)a.M, ((size_t)(a.R - 1) * a.ldm + a.K) * 4, false, "M");
+      else {
+        if (a.pw) touch(x, (uintptr_t)a.pw, (size_t)a.R * 4, false, "pw");
+        touch(x, (uintptr_t)a.tw, 65536 * 4, false, "tw");
+      }
+      for (uint32_t r : rows_of(a.xrow, a.K, "xrow"))
+        for (uint64_t b = 0; b < batch; ++b)
+          touch(x, (uintptr_t)(a.X + b * a.stride_x + (uint64_t)r * a.ld_x), (size_t)a.lanes * 4, false, "X row");
+      for (uint32_t r : rows_of(a.yrow, a.R, "yrow"))
+        for (uint64_t b = 0; b < batch; ++b)
+          touch(x, (uintptr_t)(a.Y + b * a.stride_y + (uint64_t)r * a.ld_y), (size_t)a.lanes * 4, true, "Y row");
+    };
+  }
+  if (fn == "k_inv_vandermonde") {
+    const uint32_t* A = *(const uint32_t* const*)args[0];
+    const uint32_t* w = *(const uint32_t* const*)args[1];
+    const uint32_t* pos = *(const uint32_t* const*)args[2];
+    const uint32_t* tw = *(const uint32_t* const*)args[3];
+    const uint32_t k = *(const uint32_t*)args[5];
+    uint32_t* W = *(uint32_t* const*)args[6];
+    return [=](Op& x) {
+      touch(x, (uintptr_t)A, (size_t)(k + 1) * 4, false, "A");
+      touch(x, (uintptr_t)w, (size_t)k * 4, false, "w");
+      touch(x, (uintptr_t)pos, (size_t)k * 4, false, "pos");
+      touch(x, (uintptr_t)tw, 65536 * 4, false, "tw");
+      touch(x, (uintptr_t)W, (size_t)k * k * 4, true, "W");
+    };
+  }
+  if (fn == "k_copy_rowmap") {
+    const uint32_t* src = *(const uint32_t* const*)args[0];
+    const uint64_t ld_s = *(const uint64_t*)args[1], st_s = *(const uint64_t*)args[2];
+    const uint32_t* srow = *(const uint32_t* const*)args[3];
+    uint32_t* dst = *(uint32_t* const*)args[4];
+    const uint64_t ld_d = *(const uint64_t*)args[5], st_d = *(const uint64_t*)args[6];
+    const uint32_t* drow = *(const uint32_t* const*)args[7];
+    const uint32_t rows = *(const uint32_t*)args[8], lanes = *(const uint32_t*)args[9];
+    const uint64_t batch = grid.z;
+    return [=](Op& x) {
+      for (uint32_t r = 0; r < rows; ++r) {
+        const uint32_t rs = srow ? load_dev(x, srow + r, "srow") : r, rd = drow ? load_dev(x, drow + r, "drow") : r;
+        for (uint64_t b = 0; b < batch; ++b) {
+          touch(x, (uintptr_t)(src + b * st_s + (uint64_t)rs * ld_s), (size_t)lanes * 4, false, "src row");
+          touch(x, (uintptr_t)(dst + b * st_d + (uint64_t)rd * ld_d), (size_t)lanes * 4, true, "dst row");
+        }
+      }
     };
   }
   return [name](Op&) { error("no model of kernel " + name); };

@@ -162,6 +162,21 @@ def scenario(name, fake, torch, fntrs):
         ctx.decode(loc, b, out, fntrs.FNTRS_RECV_FULL, stream=s2)
         fake.fakehip_drain()
         loc.release()
+    elif name == "direct_ok":
+        # the direct methods' matrices are built on one stream and used on another
+        z = np.arange(1, n, 2, dtype=np.uint32)[:k]
+        loc = ctx.locator(n, k, z, stream=s1)
+        outs = [torch.empty((1, k, lanes)) for _ in range(4)]
+        ctx.decode(loc, b, outs[0], fntrs.FNTRS_RECV_FULL | fntrs.FNTRS_DIRECT, stream=s1)
+        ctx.decode(loc, b, outs[1], fntrs.FNTRS_RECV_FULL | fntrs.FNTRS_DIRECT, stream=s2)
+        ctx.decode(loc, b, outs[2], fntrs.FNTRS_RECV_FULL | fntrs.FNTRS_DIRECT | fntrs.FNTRS_SYSTEMATIC, stream=s1)
+        ctx.decode(loc, b, outs[3], fntrs.FNTRS_RECV_FULL | fntrs.FNTRS_DIRECT | fntrs.FNTRS_SYSTEMATIC, stream=s2)
+        encs = [torch.empty((1, n, lanes)) for _ in range(3)]
+        ctx.encode(a, encs[0], n, flags=fntrs.FNTRS_DIRECT, stream=s1)
+        ctx.encode(a, encs[1], n, flags=fntrs.FNTRS_DIRECT | fntrs.FNTRS_SYSTEMATIC, stream=s2)
+        ctx.encode(a, encs[2], n, flags=fntrs.FNTRS_DIRECT | fntrs.FNTRS_SYSTEMATIC, stream=s1)
+        fake.fakehip_drain()
+        loc.release()
     elif name == "out_of_bounds":
         fake.hipMemsetAsync.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_void_p]
         fake.hipMemsetAsync(a.ptr, 0, 4 * k * lanes + 4, s1.cuda_stream)

@@ -404,3 +404,30 @@ def test_max_length_decode_matches_oracle(ctx):
     got = gpu_decode(ctx, loc, v)[0]
     loc.release()
     assert np.array_equal(got, codec.decode_lagrange(n, z, v[0]))
+
+
+@pytest.mark.parametrize("n,k,extra,lanes", [(512, 256, 100, 40), (8192, 4096, 3000, 12), (1000, 300, 700, 9),
+                                             (65536, 16384, 20000, 5), (64, 5, 59, 33)])
+def test_decode_from_more_than_k_received(ctx, n, k, extra, lanes):
+    """More than k symbols received (Sec. II-B): the decoder interpolates
+    through the earliest k of them in position order.  The received buffer
+    holds arbitrary residues, so a decoder that read any later position would
+    give another result; the expected one is the oracle's interpolant through
+    the first k positions."""
+    say("decode from", k + extra, "received", n, k, lanes)
+    z = synth.received_positions(5000 + n + k, n, k + extra)
+    assert z.size == k + extra
+    buf = synth.residues(5100 + n, (1, n, lanes))
+    loc = ctx.locator(n, k, z)
+    assert loc.positions.size == k and np.array_equal(loc.positions, z[:k])
+    got_full = gpu_decode(ctx, loc, buf, fntrs.FNTRS_RECV_FULL)[0]
+    got_compact = gpu_decode(ctx, loc, buf[:, z[:k], :])[0]
+    assert np.array_equal(got_full, got_compact)
+    cols = 1 if k > 4096 else lanes
+    ref = codec.decode_lagrange(n if n & (n - 1) == 0 else 1 << (n - 1).bit_length(), z[:k], buf[0][z[:k]][:, :cols])
+    assert np.array_equal(got_full[:, :cols], ref)
+    # a codeword: every lane returns its source
+    src = synth.source(5200 + n, 1, k, lanes)
+    e = gpu_encode(ctx, src, n)
+    assert np.array_equal(gpu_decode(ctx, loc, e, fntrs.FNTRS_RECV_FULL), src.astype(np.int64))
+    loc.release()
