@@ -204,7 +204,8 @@ def run_uneven(args, torch, fntrs, synth):
         dec = torch.empty((1, k, lanes), dtype=torch.int32, device=dev)
         cws.append((k, n, lanes, src, enc, dec))
     torch.cuda.synchronize()
-    nsteps = args.steps + args.warmup
+    ndef = 0 if args.no_tune else min(3, args.steps)   # steps timed with the default configurations
+    nsteps = args.steps + args.warmup + ndef + (0 if args.no_tune else 1)
     rng = np.random.default_rng(args.seed)
     log("drawing", nsteps, "x", len(sizes), "erasure patterns")
     patterns = [[(n, k, np.sort(rng.choice(n, k, replace=False)).astype(np.uint32)) for k, n, _ in sizes]
@@ -231,17 +232,37 @@ def run_uneven(args, torch, fntrs, synth):
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
+    tuning = None
+    default_ms = None
+    first = args.warmup
+    if not args.no_tune:
+        # the default configurations, then the autotuner on this batch's own jobs
+        t0 = time.perf_counter()
+        for i in range(first, first + ndef):
+            step(i)
+        torch.cuda.synchronize()
+        default_ms = (time.perf_counter() - t0) * 1e3 / ndef
+        log("default configurations", round(default_ms, 3), "ms/step; tuning")
+        tl = ctx.locators(patterns[0], stream=stream)
+        tuning = ctx.autotune_batch(enc_jobs, reps=3, stream=stream)
+        tuning += ctx.autotune_batch([ctx.decode_job(loc, enc, dec, fntrs.FNTRS_RECV_FULL)
+                                      for loc, (k, n, lanes, src, enc, dec) in zip(tl, cws)], reps=3, stream=stream)
+        for loc in tl:
+            loc.release()
+        step(first + ndef)   # warm-up with the tuned configurations
+        torch.cuda.synchronize()
+        first += ndef + 1
     log("timed", args.steps)
     t0 = time.perf_counter()
-    for i in range(args.warmup, nsteps):
+    for i in range(first, nsteps):
         step(i)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     exact = all(torch.equal(dec, src) for k, n, lanes, src, enc, dec in cws)
     log("exact", exact)
-    ph = {name: float(np.mean([ev[i][a].elapsed_time(ev[i][b]) for i in range(args.warmup, nsteps)]))
+    ph = {name: float(np.mean([ev[i][a].elapsed_time(ev[i][b]) for i in range(first, nsteps)]))
           for name, a, b in (("encode", 0, 1), ("locator", 1, 2), ("decode", 2, 3))}
-    step_ms = [ev[i][0].elapsed_time(ev[i][3]) for i in range(args.warmup, nsteps)]
+    step_ms = [ev[i][0].elapsed_time(ev[i][3]) for i in range(first, nsteps)]
     for locs in held:
         for loc in locs:
             loc.release()
@@ -266,6 +287,11 @@ def run_uneven(args, torch, fntrs, synth):
         "bit_exact": bool(exact),
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
         "phases_ms": ph,
+        "tuning": None if tuning is None else {
+            "default_ms_per_step": round(default_ms, 4),
+            "classes": [{key: t[key] for key in ("op", "log2_size", "method", "tile_lanes", "threads",
+                                                 "lanes_per_thread", "radix_log2", "ms", "default_ms")}
+                        for t in tuning]},
         "step": {"butterflies": bfly, "algorithmic_hbm_bytes": alg,
                  "alu_frac": round(bfly / (ms * 1e-3) / ALU_PEAK_BFLY, 4),
                  "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
@@ -599,6 +625,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="uneven batch only, without the single-size workloads")
+    ap.add_argument("--no-tune", action="store_true", help="uneven batch: keep the default kernel configurations")
     ap.add_argument("--systematic", action="store_true",
                     help="the systematic code (Sec. II-C): interpolation + transform on both sides")
     ap.add_argument("--direct", action="store_true",

@@ -83,6 +83,9 @@ enum {
  *                           decoding)
  * Single calls only: a batched job with this flag is rejected. */
 #define FNTRS_DIRECT 8u
+/* encode and decode flag: always the transforms, even for a class the
+ * autotuner gave to the direct methods. */
+#define FNTRS_TRANSFORM 16u
 
 /* Pseudo-device for fntrs_create: a context that touches no GPU.  Every call
  * on it runs the full host-side argument validation and, if the arguments
@@ -306,17 +309,39 @@ typedef struct fntrs_tuning {
   uint32_t threads;           /* threads per workgroup */
   uint32_t lanes_per_thread;  /* lanes one thread carries through a pass */
   uint32_t radix_log2;        /* largest radix of the LDS passes, as log2 */
-  float ms;                   /* autotune: mean time of the chosen kernel per launch */
+  float ms;                   /* autotune: mean time of the chosen configuration per launch */
+  uint32_t op;                /* FNTRS_OP_ENCODE or FNTRS_OP_DECODE */
+  uint32_t log2_size;         /* transform size class: encode log2 K, decode log2 N */
+  uint32_t method;            /* FNTRS_METHOD_TRANSFORM, _DIRECT or _FOURSTEP */
+  float default_ms;           /* autotune: the default configuration's time */
 } fntrs_tuning;
 
-/* Autotuner: times every compiled configuration of the size class of
- * (op, n, k) on `lanes` x `batch` scratch codewords, `reps` launches each
- * (synchronous), and makes the fastest the context's configuration for that
- * class, used by later single calls, batches and graphs.  n <= 32768.
- * Errors: FNTRS_E_INVAL, FNTRS_E_UNSUPPORTED (decode with k not a power of
- * two), FNTRS_E_NOMEM, FNTRS_E_DEVICE. */
+#define FNTRS_METHOD_TRANSFORM 0u   /* one-pass-per-tile transform kernels */
+#define FNTRS_METHOD_DIRECT 1u      /* the quadratic methods of Sec. III (FNTRS_DIRECT) */
+#define FNTRS_METHOD_FOURSTEP 2u    /* four-step transforms (2^14 points or more) */
+
+/* Autotuner for single calls: times every compiled configuration of the size
+ * class of (op, n, k) on `lanes` x `batch` scratch codewords, `reps` calls
+ * each (synchronous), and makes the fastest the context's configuration for
+ * that class, used by later single calls, batches and graphs.  For codes the
+ * direct methods cover (k <= 1024, n <= 16384, and k < n to decode) it also
+ * times FNTRS_DIRECT and, if that is faster, makes later non-systematic
+ * single calls of the class without FNTRS_DIRECT or FNTRS_TRANSFORM use it.
+ * Any 1 <= k <= n <= 65536; four-step classes (2^14 points or more) have one
+ * configuration, which is timed and reported.  Errors: FNTRS_E_INVAL,
+ * FNTRS_E_UNSUPPORTED, FNTRS_E_NOMEM, FNTRS_E_DEVICE. */
 int fntrs_autotune(fntrs_ctx* ctx, uint32_t op, uint32_t n, uint32_t k, uint32_t lanes, uint32_t batch,
                    uint32_t reps, void* stream, fntrs_tuning* chosen);
+
+/* Autotuner for a batch: for every size class of the table kernels in the
+ * batch (encode by K, decode by N), runs the class's own jobs, `reps` times
+ * per compiled configuration, and keeps the fastest as the context's
+ * configuration; four-step classes are timed with their one configuration.
+ * The batch's buffers are written (outputs) but inputs are only read.
+ * Synchronous.  out[0 .. *nout) receives one entry per class (at most cap).
+ * Errors: those of fntrs_submit. */
+int fntrs_autotune_batch(fntrs_ctx* ctx, const fntrs_job* jobs, uint32_t njobs, uint32_t reps, void* stream,
+                         fntrs_tuning* out, uint32_t cap, uint32_t* nout);
 
 /* Current configuration of transform size 2^log2_size (1..15) for op. */
 int fntrs_get_config(fntrs_ctx* ctx, uint32_t op, uint32_t log2_size, fntrs_tuning* cfg);

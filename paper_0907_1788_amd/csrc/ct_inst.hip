@@ -124,6 +124,37 @@ hipError_t enc_cos_one(const EncodeArgs& a, uint32_t blocks, hipStream_t s) {
   }
 }
 
+template <int L, int T, int NT, int V>
+bool enc_cos_tab_pays() {
+  constexpr size_t lds = ct::Geo<L, T, NT, V>::LDS_BYTES;
+  if (kernel_spills(ct::k_enc_cos_tab<L, T, NT, V>)) return false;
+  int oc = 0, op = 0;
+  (void)hipFuncSetAttribute((const void*)ct::k_enc_cos_tab<L, T, NT, V>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipFuncSetAttribute((const void*)ct::k_enc_tab<L, T, NT, V>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&oc, ct::k_enc_cos_tab<L, T, NT, V>, NT, lds) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&op, ct::k_enc_tab<L, T, NT, V>, NT, lds) != hipSuccess)
+    return false;
+  return oc >= 1 && oc >= op;
+}
+
+template <int L, int T, int NT, int V>
+hipError_t enc_cos_tab_one(const JobTable<EncodeArgs>& t, const uint32_t* tw, const uint32_t* twi, uint32_t grid,
+                           hipStream_t s) {
+  if constexpr (cos_ok<L, T, NT, V>()) {
+    static const bool pays = enc_cos_tab_pays<L, T, NT, V>();
+    if (!pays) return hipErrorNotSupported;
+    constexpr size_t lds = ct::Geo<L, T, NT, V>::LDS_BYTES;
+    (void)hipFuncSetAttribute((const void*)ct::k_enc_cos_tab<L, T, NT, V>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((ct::k_enc_cos_tab<L, T, NT, V>), dim3(grid), dim3(NT), lds, s, t, tw, twi);
+    return hipGetLastError();
+  } else {
+    return hipErrorNotSupported;
+  }
+}
+
 template <int L, int D, int T, int NT, int V>
 hipError_t dec_pipe_one(const JobTable<DecodeArgs>& t, const DecodeArgs& one, const uint32_t* tw, const uint32_t* twi,
                         uint32_t grid, hipStream_t s) {
@@ -172,7 +203,14 @@ int occupancy(K kernel, int NT, size_t lds) {
 template <int L, int T, int NT, int V>
 int occ_t(int op, int D) {
   constexpr size_t lds = ct::Geo<L, T, NT, V>::LDS_BYTES;
-  if (op >= 2) {
+  if (op == 3) {   // the all-cosets table encoder, where it exists and pays
+    if constexpr (cos_ok<L, T, NT, V>()) {
+      static const bool pays = enc_cos_tab_pays<L, T, NT, V>();
+      if (pays) return occupancy(ct::k_enc_cos_tab<L, T, NT, V>, NT, lds);
+    }
+    return 0;
+  }
+  if (op == 2) {
     if constexpr (pipe_ok<L, T, NT, V>()) {
       if (D == -1) return occupancy_no_spill(ct::k_dec_pipe<L, -1, T, NT, V>, NT, lds);
       if (D == 0) return occupancy_no_spill(ct::k_dec_pipe<L, 0, T, NT, V>, NT, lds);
@@ -251,6 +289,18 @@ hipError_t enc_cos_pick(CtCfg c, const EncodeArgs& a, uint32_t blocks, hipStream
 }
 
 template <int I>
+hipError_t enc_cos_tab_pick(CtCfg c, const JobTable<EncodeArgs>& t, const uint32_t* tw, const uint32_t* twi,
+                            uint32_t grid, hipStream_t s) {
+  if constexpr (I < 4 && kVar.enc[I < 4 ? I : 0].T != 0) {
+    if (c.T == kVar.enc[I].T && c.NT == kVar.enc[I].NT && c.V == kVar.enc[I].V)
+      return enc_cos_tab_one<FNTRS_L, kVar.enc[I].T, kVar.enc[I].NT, kVar.enc[I].V>(t, tw, twi, grid, s);
+    return enc_cos_tab_pick<I + 1>(c, t, tw, twi, grid, s);
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int I>
 hipError_t dec_pipe_pick(CtCfg c, int D, const JobTable<DecodeArgs>& t, const DecodeArgs& one, const uint32_t* tw,
                          const uint32_t* twi, uint32_t grid, hipStream_t s) {
   if constexpr (I < 4 && kVar.dec[I < 4 ? I : 0].T != 0) {
@@ -267,7 +317,7 @@ int occ_pick(CtCfg c, int op, int D) {
   if constexpr (I < 4) {
     constexpr CtCfg e = kVar.enc[I], d = kVar.dec[I];
     if constexpr (e.T != 0) {
-      if (op == 0 && c.T == e.T && c.NT == e.NT && c.V == e.V) return occ_t<FNTRS_L, e.T, e.NT, e.V>(op, D);
+      if ((op == 0 || op == 3) && c.T == e.T && c.NT == e.NT && c.V == e.V) return occ_t<FNTRS_L, e.T, e.NT, e.V>(op, D);
     }
     if constexpr (d.T != 0) {
       if ((op == 1 || op == 2) && c.T == d.T && c.NT == d.NT && c.V == d.V) return occ_t<FNTRS_L, d.T, d.NT, d.V>(op, D);
@@ -299,6 +349,11 @@ hipError_t FNTRS_CAT(ct_enc_tab_launch_, FNTRS_L)(CtCfg c, const JobTable<Encode
 hipError_t FNTRS_CAT(ct_dec_tab_launch_, FNTRS_L)(CtCfg c, int D, const JobTable<DecodeArgs>& t, const uint32_t* tw,
                                                   const uint32_t* twi, uint32_t grid, hipStream_t s) {
   return dec_tab_pick<0>(c, D, t, tw, twi, grid, s);
+}
+
+hipError_t FNTRS_CAT(ct_enc_cos_tab_launch_, FNTRS_L)(CtCfg c, const JobTable<EncodeArgs>& t, const uint32_t* tw,
+                                                      const uint32_t* twi, uint32_t grid, hipStream_t s) {
+  return enc_cos_tab_pick<0>(c, t, tw, twi, grid, s);
 }
 
 hipError_t FNTRS_CAT(ct_enc_cos_launch_, FNTRS_L)(CtCfg c, const EncodeArgs& a, uint32_t blocks, hipStream_t s) {

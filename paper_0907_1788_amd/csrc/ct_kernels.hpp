@@ -262,17 +262,13 @@ __device__ __forceinline__ void enc_item(const EncodeArgs& a, uint32_t item, uin
 // thread),
 // and each coset's first pass twists them there; the stores of one coset
 // drain while the next computes.  Work item = (lane tile, block).
-template <int LK, int TT, int NT, int VV>
-__global__ void __launch_bounds__(NT) k_enc_cos(EncodeArgs a) {
+template <int LK, int TT, int NT, int VV, class TW>
+__device__ __forceinline__ void enc_cos_item(const EncodeArgs& a, uint32_t item, uint32_t* lds, const TW& tws) {
   using Gm = Geo<LK, TT, NT, VV>;
   constexpr int V = Gm::V, G = Gm::G, T = Gm::T, BM = Gm::BM;
   constexpr int B0 = plan_b(LK, BM, 0);
   constexpr int C0 = pass0_slots<LK, BM, G, NT>();
   static_assert(plan_np(LK, BM) >= 2, "needs a first and a last pass");
-  using TW = typename Gm::TwType;
-  extern __shared__ uint32_t lds[];
-  const TW tws = make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
-  const uint32_t item = xcd_remap(blockIdx.x, gridDim.x);
   const uint32_t lane0 = (item % a.tiles) * T;
   const uint64_t blk = item / a.tiles;
   EncLoad<LK, V> ld{a.src + blk * a.stride_src + lane0, a.tw, a.ld_src, a.k, a.n, 0u, lane0, a.lanes,
@@ -307,6 +303,15 @@ __global__ void __launch_bounds__(NT) k_enc_cos(EncodeArgs a) {
 }
 
 template <int LK, int TT, int NT, int VV>
+__global__ void __launch_bounds__(NT) k_enc_cos(EncodeArgs a) {
+  using Gm = Geo<LK, TT, NT, VV>;
+  using TW = typename Gm::TwType;
+  extern __shared__ uint32_t lds[];
+  const TW tws = make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
+  enc_cos_item<LK, TT, NT, VV>(a, xcd_remap(blockIdx.x, gridDim.x), lds, tws);
+}
+
+template <int LK, int TT, int NT, int VV>
 __global__ void __launch_bounds__(NT) k_enc(EncodeArgs a) {
   using Gm = Geo<LK, TT, NT, VV>;
   using TW = typename Gm::TwType;
@@ -338,6 +343,23 @@ __global__ void __launch_bounds__(NT) k_enc_tab(JobTable<EncodeArgs> t, const ui
     const uint32_t j = find_job(t.start, t.njobs, w);
     const EncodeArgs a = load_global(t.jobs + j);
     enc_item<LK, TT, NT, VV>(a, w - gptr(t.start)[j], lds, tws);
+    __syncthreads();   // the next item overwrites the LDS tile
+  }
+}
+
+// Batched all-cosets encoder: as k_enc_tab, but a work item is a (lane tile,
+// block) whose every coset the workgroup computes from one load of the
+// source rows (k_enc_cos).
+template <int LK, int TT, int NT, int VV>
+__global__ void __launch_bounds__(NT) k_enc_cos_tab(JobTable<EncodeArgs> t, const uint32_t* tw, const uint32_t* twi) {
+  using Gm = Geo<LK, TT, NT, VV>;
+  using TW = typename Gm::TwType;
+  extern __shared__ uint32_t lds[];
+  const TW tws = make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, tw, twi);
+  for (uint32_t w = xcd_remap(blockIdx.x, gridDim.x); w < t.total; w += gridDim.x) {
+    const uint32_t j = find_job(t.start, t.njobs, w);
+    const EncodeArgs a = load_global(t.jobs + j);
+    enc_cos_item<LK, TT, NT, VV>(a, w - gptr(t.start)[j], lds, tws);
     __syncthreads();   // the next item overwrites the LDS tile
   }
 }

@@ -55,6 +55,10 @@ using CtDecTabLaunch = hipError_t (*)(CtCfg cfg, int D, const JobTable<DecodeArg
 // Encoder with all cosets of a lane tile in one workgroup (k_enc_cos); blocks
 // = lane tiles x batch.  hipErrorNotSupported when the configuration has none.
 using CtEncCosLaunch = hipError_t (*)(CtCfg cfg, const EncodeArgs& a, uint32_t blocks, hipStream_t s);
+// Batched all-cosets encoder (k_enc_cos_tab): work items are (lane tile,
+// block); hipErrorNotSupported when the configuration has none or it does
+// not pay (occupancy op 3 is then 0).
+using CtEncCosTabLaunch = CtEncTabLaunch;
 // Pipelined persistent decoder launch (k_dec_pipe): a table of jobs, or
 // (t.jobs == nullptr) the single job `one` with t.total work items.
 // hipErrorNotSupported when the configuration has no pipelined kernel.
@@ -62,7 +66,7 @@ using CtDecPipeLaunch = hipError_t (*)(CtCfg cfg, int D, const JobTable<DecodeAr
                                        const uint32_t* tw, const uint32_t* twi, uint32_t grid, hipStream_t s);
 // Workgroups of a persistent kernel that fit on one CU at once (0 when the
 // configuration is not instantiated or has no such kernel); op 0 = encode
-// table, 1 = decode table, 2 = decode pipelined.
+// table, 1 = decode table, 2 = decode pipelined, 3 = all-cosets encode table.
 using CtTabOccupancy = int (*)(CtCfg cfg, int op, int D);
 
 #define FNTRS_CT_DECL(L)                                                                              \
@@ -73,6 +77,8 @@ using CtTabOccupancy = int (*)(CtCfg cfg, int op, int D);
   hipError_t ct_dec_tab_launch_##L(CtCfg cfg, int D, const JobTable<DecodeArgs>& t, const uint32_t* tw,   \
                                    const uint32_t* twi, uint32_t grid, hipStream_t s);                    \
   hipError_t ct_enc_cos_launch_##L(CtCfg cfg, const EncodeArgs& a, uint32_t blocks, hipStream_t s);         \
+  hipError_t ct_enc_cos_tab_launch_##L(CtCfg cfg, const JobTable<EncodeArgs>& t, const uint32_t* tw,      \
+                                       const uint32_t* twi, uint32_t grid, hipStream_t s);                \
   hipError_t ct_dec_pipe_launch_##L(CtCfg cfg, int D, const JobTable<DecodeArgs>& t, const DecodeArgs& one,\
                                     const uint32_t* tw, const uint32_t* twi, uint32_t grid, hipStream_t s); \
   int ct_tab_occupancy_##L(CtCfg cfg, int op, int D);

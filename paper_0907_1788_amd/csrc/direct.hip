@@ -13,12 +13,10 @@
 // division; A and w are the locator's (steps 1-3 of Sec. II-B).  W_0 is the
 // same for the positions 0..k-1.
 //
-// The product runs on the vector ALUs in double precision: residues are at
-// most 2^16, so every product is an integer below 2^32 and a sum of up to
-// 2^20 of them is exact in a double's 53-bit mantissa.  One fused
-// multiply-add per term, one reduction mod p per output.  (On this chip the
-// double-precision matrix cores have the same peak as the vector FMA, and
-// these products are small: k <= 1024.)
+// These are dense contractions, so they run on the matrix cores, in double
+// precision: residues are at most 2^16, so every product is an integer below
+// 2^32 and a sum of up to 2^20 of them is exact in a double's 53-bit
+// mantissa.  One reduction mod p per output.
 #include "field.hpp"
 #include "host.hpp"
 
@@ -26,90 +24,119 @@ namespace fntrs {
 
 namespace {
 
-constexpr int kGR = 64, kGL = 64, kGJ = 16;   // output rows x lanes per workgroup, K chunk
-constexpr int kGNT = 256;                      // threads: each a 4 x 4 block of outputs
+// One wave computes a 16 x 16 tile of Y (16 rows r, 16 lanes l) with the
+// double-precision matrix instruction D += A B, A 16 x 4 (M), B 4 x 16 (X):
+// lane t supplies A[t % 16][t / 16] and B[t / 16][t % 16] and holds
+// D[4 i + t / 16][t % 16], i < 4 (the lane layout measured on gfx950).  K advances 4 per instruction; the
+// operands of kKU instructions are loaded before they run.
+constexpr int kKU = 8;
+static_assert(kDirectMaxK <= 4 * 256, "the inverse-Vandermonde builder holds 4 terms per thread");
+
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint32_t mod_p(double acc) {
   const uint64_t v = (uint64_t)acc;   // exact: acc is a non-negative integer below 2^53
   return (uint32_t)(v % 65537ull);
 }
 
-__global__ void __launch_bounds__(kGNT) k_gemm_modp(GemmArgs a) {
-  __shared__ double ms[kGR][kGJ + 1];
-  __shared__ double xs[kGJ][kGL + 1];
-  const uint32_t l0 = blockIdx.x * kGL, r0 = blockIdx.y * kGR;
-  const uint64_t b = blockIdx.z;
-  const int t = threadIdx.x;
-  const int tr = (t / (kGL / 4)) * 4, tl = (t % (kGL / 4)) * 4;
-  double acc[4][4] = {};
-  const uint32_t* X = a.X + b * a.stride_x;
-  const uint32_t Nmask = (1u << a.logN) - 1u;
-  for (uint32_t j0 = 0; j0 < a.K; j0 += kGJ) {
-    // stage M[r0 .. r0+64)[j0 .. j0+16) and X[j0 .. j0+16)[l0 .. l0+64)
-    for (int e = t; e < kGR * kGJ; e += kGNT) {
-      const int rr = e / kGJ, jj = e % kGJ;
-      const uint32_t r = r0 + rr, j = j0 + jj;
-      uint32_t v = 0;
-      if (r < a.R && j < a.K) {
-        if (a.M) {
-          v = a.M[(uint64_t)r * a.ldm + j];
-        } else {
-          const uint32_t p = a.pw ? a.pw[r] : r;
-          v = a.tw[((p * j) & Nmask) << (16 - a.logN)];
-        }
+// Operand values of K-step u for this lane (0 past the edges).
+struct GemmLane {
+  const GemmArgs& a;
+  const uint32_t* X;
+  const uint32_t* mrow;
+  uint32_t p, Nmask, l, tk;
+  bool rok, lok;
+  __device__ __forceinline__ void load(uint32_t k0, uint32_t (&m)[kKU], uint32_t (&x)[kKU]) const {
+#pragma unroll
+    for (int u = 0; u < kKU; ++u) {
+      const uint32_t k = k0 + 4 * u + tk;
+      m[u] = 0;
+      x[u] = 0;
+      if (k < a.K) {
+        if (rok) m[u] = mrow ? mrow[k] : a.tw[((p * k) & Nmask) << (16 - a.logN)];
+        if (lok) x[u] = X[(uint64_t)(a.xrow ? a.xrow[k] : k) * a.ld_x + l];
       }
-      ms[rr][jj] = (double)v;
     }
-    for (int e = t; e < kGJ * kGL; e += kGNT) {
-      const int jj = e / kGL, ll = e % kGL;
-      const uint32_t j = j0 + jj, l = l0 + ll;
-      uint32_t v = 0;
-      if (j < a.K && l < a.lanes) v = X[(uint64_t)(a.xrow ? a.xrow[j] : j) * a.ld_x + l];
-      xs[jj][ll] = (double)v;
+  }
+};
+
+__global__ void __launch_bounds__(64) k_gemm_modp(GemmArgs a) {
+  const uint32_t t = threadIdx.x, tc = t % 16, tk = t / 16;
+  const uint32_t l0 = blockIdx.x * 16, r0 = blockIdx.y * 16;
+  const uint64_t b = blockIdx.z;
+  const uint32_t r = r0 + tc, l = l0 + tc;   // the A row and the B column this lane supplies
+  const bool rok = r < a.R, lok = l < a.lanes;
+  const GemmLane g{a, a.X + b * a.stride_x, (rok && a.M) ? a.M + (uint64_t)r * a.ldm : nullptr,
+                   (rok && !a.M) ? (a.pw ? a.pw[r] : r) : 0u, (1u << a.logN) - 1u, l, tk, rok, lok};
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  // the loads of the next kKU steps are in flight while this group's products run
+  uint32_t m[kKU], x[kKU], mn[kKU], xn[kKU];
+  g.load(0, m, x);
+  for (uint32_t k0 = 0; k0 < a.K; k0 += 4 * kKU) {
+    if (k0 + 4 * kKU < a.K) g.load(k0 + 4 * kKU, mn, xn);
+#pragma unroll
+    for (int u = 0; u < kKU; ++u)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)m[u], (double)x[u], acc, 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < kKU; ++u) {
+      m[u] = mn[u];
+      x[u] = xn[u];
     }
-    __syncthreads();
-#pragma unroll
-    for (int jj = 0; jj < kGJ; ++jj) {
-      double mv[4], xv[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) mv[i] = ms[tr + i][jj];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) xv[i] = xs[jj][tl + i];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[i][q] = fma(mv[i], xv[q], acc[i][q]);
-    }
-    __syncthreads();
   }
   uint32_t* Y = a.Y + b * a.stride_y;
+  const uint32_t lo = l0 + tc;
+  if (lo >= a.lanes) return;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const uint32_t r = r0 + tr + i;
-    if (r >= a.R) continue;
-    uint32_t* row = Y + (uint64_t)(a.yrow ? a.yrow[r] : r) * a.ld_y;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint32_t l = l0 + tl + q;
-      if (l < a.lanes) row[l] = mod_p(acc[i][q]);
-    }
+    const uint32_t ro = r0 + 4 * i + tk;
+    if (ro < a.R) Y[(uint64_t)(a.yrow ? a.yrow[ro] : ro) * a.ld_y + lo] = mod_p(acc[i]);
   }
 }
 
-// W[j][i] = w_i * (coefficient j of A(x)/(x - x_i)), one thread per column i:
-// synthetic division from the top, q_(k-1) = 1, q_(j-1) = a_j + x_i q_j.
-__global__ void k_inv_vandermonde(const uint32_t* __restrict__ A, const uint32_t* __restrict__ w,
-                                  const uint32_t* __restrict__ pos, const uint32_t* __restrict__ tw, int logN,
-                                  uint32_t k, uint32_t* __restrict__ W) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= k) return;
-  const uint32_t x = tw[(pos[i] << (16 - logN)) & 0xFFFFu];
+// W[j][i] = w_i * (coefficient j of A(x)/(x - x_i)), one workgroup per
+// column i.  Synthetic division gives coefficient j of A(x)/(x - x_i) as
+// q_j = sum_{m > j} a_m x_i^(m-j-1) = x_i^(-j-1) S_j with the suffix sums
+// S_j = sum_{m > j} a_m x_i^m (a_k = 1): every term is independent (x_i^m is
+// one table lookup, x_i being a power of the root), and S is a suffix scan.
+constexpr int kIVT = 256;
+__global__ void __launch_bounds__(kIVT) k_inv_vandermonde(const uint32_t* __restrict__ A,
+                                                         const uint32_t* __restrict__ w,
+                                                         const uint32_t* __restrict__ pos,
+                                                         const uint32_t* __restrict__ tw,
+                                                         const uint32_t* __restrict__ twi, int logN, uint32_t k,
+                                                         uint32_t* __restrict__ W) {
+  __shared__ uint32_t part[kIVT];
+  const uint32_t i = blockIdx.x, t = threadIdx.x;
+  const uint32_t sh = 16 - logN, Nmask = (1u << logN) - 1u;
+  const uint32_t z = pos[i];
+  // thread t owns terms m = 1 + t*c .. t*c + c (c per thread), suffix-summed locally
+  const uint32_t c = (k + kIVT - 1) / kIVT;
+  uint32_t loc[4];   // c <= 4 (k <= 1024)
+  uint32_t run = 0;
+  for (int u = (int)c - 1; u >= 0; --u) {
+    const uint32_t m = 1 + t * c + (uint32_t)u;
+    const uint32_t term = m <= k ? fmul(A[m], tw[((z * m) & Nmask) << sh]) : 0u;
+    run = fadd(run, term);
+    loc[u] = run;
+  }
+  part[t] = run;
+  __syncthreads();
+  // suffix scan of the thread totals: part[t] = sum over threads >= t
+  for (uint32_t d = 1; d < kIVT; d <<= 1) {
+    const uint32_t v = t + d < kIVT ? part[t + d] : 0u;
+    __syncthreads();
+    part[t] = fadd(part[t], v);
+    __syncthreads();
+  }
+  const uint32_t after = t + 1 < kIVT ? part[t + 1] : 0u;
   const uint32_t wi = w[i];
-  uint32_t q = 1u;
-  W[(uint64_t)(k - 1) * k + i] = wi;
-  for (uint32_t j = k - 1; j >= 1; --j) {
-    q = fadd(A[j], fmul(x, q));
-    W[(uint64_t)(j - 1) * k + i] = fmul(wi, q);
+  for (uint32_t u = 0; u < c; ++u) {
+    const uint32_t m = 1 + t * c + u;   // S_(m-1) = sum of terms >= m
+    if (m > k) break;
+    const uint32_t j = m - 1;
+    const uint32_t S = fadd(loc[u], after);
+    const uint32_t xinv = twi[((z * (j + 1)) & Nmask) << sh];   // x_i^(-j-1)
+    W[(uint64_t)j * k + i] = fmul(wi, fmul(S, xinv));
   }
 }
 
@@ -127,8 +154,9 @@ __global__ void k_copy_rowmap(const uint32_t* __restrict__ src, uint64_t ld_s, u
 
 hipError_t gemm(const GemmArgs& a, uint32_t batch, hipStream_t s) {
   if (!a.R || !a.lanes || !batch) return hipSuccess;
-  const dim3 grid((a.lanes + kGL - 1) / kGL, (a.R + kGR - 1) / kGR, batch);
-  hipLaunchKernelGGL(k_gemm_modp, grid, dim3(kGNT), 0, s, a);
+  if (a.R > 16u * 65535u) return hipErrorInvalidValue;
+  const dim3 grid((a.lanes + 15) / 16, (a.R + 15) / 16, batch);
+  hipLaunchKernelGGL(k_gemm_modp, grid, dim3(64), 0, s, a);
   return hipGetLastError();
 }
 
@@ -179,8 +207,8 @@ int locator_inverse(fntrs_ctx* c, fntrs_locator_t* L, hipStream_t s, const Direc
     DirectMat* m = nullptr;
     if (int rc = direct_mat_alloc(c, (size_t)L->k * L->k, m)) return rc;
     HIP_TRY(c, hipStreamWaitEvent(s, L->ready, 0));
-    hipLaunchKernelGGL(k_inv_vandermonde, dim3((L->k + 255) / 256), dim3(256), 0, s, L->A, L->w, L->pos, c->tw,
-                       L->logn, L->k, m->p);
+    hipLaunchKernelGGL(k_inv_vandermonde, dim3(L->k), dim3(kIVT), 0, s, L->A, L->w, L->pos, c->tw, c->twi, L->logn,
+                       L->k, m->p);
     if (hipError_t e = hipGetLastError(); e != hipSuccess) {
       direct_mat_free(m);
       c->used -= (size_t)L->k * L->k * 4;

@@ -55,7 +55,12 @@ const CtTables& ct_tables() {
       ct_dec_pipe_launch_4,  ct_dec_pipe_launch_5,  ct_dec_pipe_launch_6,  ct_dec_pipe_launch_7,
       ct_dec_pipe_launch_8,  ct_dec_pipe_launch_9,  ct_dec_pipe_launch_10, ct_dec_pipe_launch_11,
       ct_dec_pipe_launch_12, ct_dec_pipe_launch_13, ct_dec_pipe_launch_14, ct_dec_pipe_launch_15};
-  static const CtTables t{enc, dec, enc_tab, dec_tab, enc_cos, dec_pipe, occ};
+  static const CtEncCosTabLaunch enc_cos_tab[16] = {
+      nullptr,                  ct_enc_cos_tab_launch_1,  ct_enc_cos_tab_launch_2,  ct_enc_cos_tab_launch_3,
+      ct_enc_cos_tab_launch_4,  ct_enc_cos_tab_launch_5,  ct_enc_cos_tab_launch_6,  ct_enc_cos_tab_launch_7,
+      ct_enc_cos_tab_launch_8,  ct_enc_cos_tab_launch_9,  ct_enc_cos_tab_launch_10, ct_enc_cos_tab_launch_11,
+      ct_enc_cos_tab_launch_12, ct_enc_cos_tab_launch_13, ct_enc_cos_tab_launch_14, ct_enc_cos_tab_launch_15};
+  static const CtTables t{enc, dec, enc_tab, dec_tab, enc_cos, dec_pipe, occ, enc_cos_tab};
   return t;
 }
 
@@ -198,8 +203,10 @@ int check_encode(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uin
   if (ld_src < lanes || ld_dst < lanes) return fail(c, FNTRS_E_INVAL, "ld_src/ld_dst smaller than lanes");
   if (batch > 1 && (stride_src < (size_t)(k - 1) * ld_src + lanes || stride_dst < (size_t)(n - 1) * ld_dst + lanes))
     return fail(c, FNTRS_E_INVAL, "block strides overlap consecutive blocks");
-  if (flags & ~(FNTRS_FLAG_VALIDATE | FNTRS_SYSTEMATIC | FNTRS_DIRECT))
+  if (flags & ~(FNTRS_FLAG_VALIDATE | FNTRS_SYSTEMATIC | FNTRS_DIRECT | FNTRS_TRANSFORM))
     return fail(c, FNTRS_E_INVAL, "unknown flags 0x%x", flags);
+  if ((flags & FNTRS_DIRECT) && (flags & FNTRS_TRANSFORM))
+    return fail(c, FNTRS_E_INVAL, "FNTRS_DIRECT and FNTRS_TRANSFORM exclude each other");
   const size_t sb = span_elems(batch, stride_src, k, ld_src, lanes) * 4;
   const size_t db = span_elems(batch, stride_dst, n, ld_dst, lanes) * 4;
   if (ranges_overlap(src, sb, dst, db)) return fail(c, FNTRS_E_INVAL, "src and dst overlap");
@@ -213,8 +220,10 @@ int check_decode(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, uint32_
   if (L->refs <= 0) return fail(c, FNTRS_E_INVAL, "locator was released");
   if (lanes < 1 || batch < 1) return fail(c, FNTRS_E_INVAL, "lanes=%u and batch=%u must be >= 1", lanes, batch);
   if (!recv || !dst) return fail(c, FNTRS_E_INVAL, "null recv or dst");
-  if (flags & ~(FNTRS_RECV_FULL | FNTRS_FLAG_VALIDATE | FNTRS_SYSTEMATIC | FNTRS_DIRECT))
+  if (flags & ~(FNTRS_RECV_FULL | FNTRS_FLAG_VALIDATE | FNTRS_SYSTEMATIC | FNTRS_DIRECT | FNTRS_TRANSFORM))
     return fail(c, FNTRS_E_INVAL, "unknown flags 0x%x", flags);
+  if ((flags & FNTRS_DIRECT) && (flags & FNTRS_TRANSFORM))
+    return fail(c, FNTRS_E_INVAL, "FNTRS_DIRECT and FNTRS_TRANSFORM exclude each other");
   const bool full = flags & FNTRS_RECV_FULL;
   const uint32_t k = L->k;
   const uint32_t rrows = full ? L->nrows : k;
@@ -680,9 +689,9 @@ static int noalloc_scratch_init(fntrs_ctx* c) {
 
 // Encoder on validated arguments, enqueued on s; rows_out > 0 writes only
 // the rows i < rows_out of dst.
-static int encode_run(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uint32_t* src, size_t ld_src,
-                      size_t stride_src, uint32_t* dst, size_t ld_dst, size_t stride_dst, uint32_t batch,
-                      uint32_t rows_out, hipStream_t s, uint32_t* fixed_scratch = nullptr) {
+int fntrs::encode_run(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uint32_t* src, size_t ld_src,
+               size_t stride_src, uint32_t* dst, size_t ld_dst, size_t stride_dst, uint32_t batch, uint32_t rows_out,
+               hipStream_t s, uint32_t* fixed_scratch) {
   if (n == 1) {  // k = 1: e_0 = s_0
     HIP_TRY(c, launch_copy(src, stride_src, dst, stride_dst, lanes, batch, s));
     return FNTRS_OK;
@@ -695,7 +704,7 @@ static int encode_run(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, cons
   a.n = n; a.k = k; a.lanes = lanes;
   a.logn = ilog2(n);
   a.logK = std::max(1, ilog2(k));        // transform size K: smallest power of two >= k, at least 2
-  if (a.logK >= kFourStepMinLog) {
+  if (encode_fourstep(c, a.logK, a.logn)) {
     // K >= 2^14: one FNT_n of the zero-padded source as four-step passes over
     // 32-lane tiles, through a scratch buffer
     FourStepArgs f{};
@@ -732,9 +741,9 @@ static int encode_run(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, cons
 
 
 // Decoder on validated arguments, enqueued on s.
-static int decode_run(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, bool full, const uint32_t* recv,
-                      size_t ld_recv, size_t stride_recv, uint32_t* dst, size_t ld_dst, size_t stride_dst,
-                      uint32_t batch, hipStream_t s) {
+int fntrs::decode_run(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, bool full, const uint32_t* recv,
+               size_t ld_recv, size_t stride_recv, uint32_t* dst, size_t ld_dst, size_t stride_dst, uint32_t batch,
+               hipStream_t s) {
   const uint32_t n = L->n, k = L->k;
   HIP_TRY(c, hipStreamWaitEvent(s, L->ready, 0));
   if (n == 1) {  // k = n = 1: s_0 = e_0
@@ -926,6 +935,9 @@ int fntrs_encode(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uin
     int rc = validate_range(c, src, batch, stride_src, k, ld_src, lanes, s);
     if (rc) return rc;
   }
+  if (!(flags & (FNTRS_DIRECT | FNTRS_TRANSFORM | FNTRS_SYSTEMATIC)) && direct_fits(pad_pow2(n), k) &&
+      c->use_direct[FNTRS_OP_ENCODE][std::max(1, ilog2(k))])
+    flags |= FNTRS_DIRECT;   // the autotuner found the direct method faster for this class
   if (flags & FNTRS_DIRECT) {   // the quadratic methods of Sec. III
     const uint32_t N = pad_pow2(n);
     if (!direct_fits(N, k))
@@ -951,7 +963,7 @@ int fntrs_encode_noalloc(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, c
   if (int rc = check_encode(c, n, k, lanes, src, ld_src, stride_src, dst, ld_dst, stride_dst, batch, 0)) return rc;
   const uint32_t N = pad_pow2(n);
   const int logK = std::max(1, ilog2(k));
-  const bool fourstep = N > 1 && logK >= kFourStepMinLog;
+  const bool fourstep = N > 1 && encode_fourstep(c, logK, ilog2(N));
   const size_t words =
       fourstep ? (size_t)batch * N * ((lanes + kFourStepTile - 1) / kFourStepTile * kFourStepTile) : 0;
   if (words > kNoAllocScratchWords)
@@ -1026,6 +1038,9 @@ int fntrs_decode(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, uint32_
     int rc = validate_range(c, recv, batch, stride_recv, rrows, ld_recv, lanes, s);
     if (rc) return rc;
   }
+  if (!(flags & (FNTRS_DIRECT | FNTRS_TRANSFORM | FNTRS_SYSTEMATIC)) && L->k < L->n && direct_fits(L->n, L->k) &&
+      c->use_direct[FNTRS_OP_DECODE][L->logn])
+    flags |= FNTRS_DIRECT;   // the autotuner found the direct method faster for this class
   if (flags & FNTRS_DIRECT) {   // the quadratic methods of Sec. III
     if (L->k == L->n || !direct_fits(L->n, L->k))
       return fail(c, FNTRS_E_UNSUPPORTED, "direct decoding covers 1 <= k < n, k <= %u, n <= %u (k=%u n=%u)",

@@ -82,6 +82,8 @@ struct fntrs_ctx {
   size_t lds_max = 65536;
   fntrs::CtCfg enc_cfg[16] = {};     // kernel configuration per log2 transform size
   fntrs::CtCfg dec_cfg[16] = {};
+  bool use_direct[2][17] = {};       // autotuner: the class's single calls use the direct methods
+  bool enc_fourstep13 = false;       // autotuner: encode K = 2^13 into n >= 2^14 as one four-step FNT_n
   std::mutex mu;
   std::string err;
   std::unordered_multimap<uint64_t, fntrs_locator_t*> cache;
@@ -166,6 +168,7 @@ struct CtTables {
   const CtEncCosLaunch* enc_cos;
   const CtDecPipeLaunch* dec_pipe;
   const CtTabOccupancy* occ;
+  const CtEncCosTabLaunch* enc_cos_tab;
 };
 const CtTables& ct_tables();
 
@@ -210,6 +213,21 @@ int check_decode(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, uint32_
 // Reads a strided device region back and checks every residue <= 65536.
 int validate_range(fntrs_ctx* c, const uint32_t* p, uint32_t batch, size_t stride, uint32_t rows, size_t ld,
                    uint32_t lanes, hipStream_t s);
+// The transform encoder / decoder of one call on validated arguments (N a
+// power of two; rows_out > 0 writes only rows < rows_out), enqueued on s.
+// fixed_scratch: the four-step scratch to use instead of allocating one.
+int encode_run(fntrs_ctx* c, uint32_t N, uint32_t k, uint32_t lanes, const uint32_t* src, size_t ld_src,
+               size_t stride_src, uint32_t* dst, size_t ld_dst, size_t stride_dst, uint32_t batch, uint32_t rows_out,
+               hipStream_t s, uint32_t* fixed_scratch = nullptr);
+int decode_run(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, bool full, const uint32_t* recv,
+               size_t ld_recv, size_t stride_recv, uint32_t* dst, size_t ld_dst, size_t stride_dst, uint32_t batch,
+               hipStream_t s);
+// Whether an encode of transform size 2^logK into a code of transform length
+// 2^logN runs as one four-step FNT_n: always from 2^14 points, and at 2^13
+// when the autotuner found that faster (the four-step kernels need N >= 2^14).
+inline bool encode_fourstep(const fntrs_ctx* c, int logK, int logN) {
+  return logK >= kFourStepMinLog || (logK == kFourStepMinLog - 1 && logN >= kFourStepMinLog && c->enc_fourstep13);
+}
 // Direct (quadratic) methods of Sec. III (direct.hip), for codes with
 // k <= kDirectMaxK and transform length N <= kDirectMaxN.
 constexpr uint32_t kDirectMaxK = 1024, kDirectMaxN = 16384;

@@ -31,6 +31,7 @@ struct ClassLaunch {
   uint64_t work = 0;   // butterflies, to balance the streams
   int stream = 0;      // 0 = the caller's stream, b > 0 = side stream b-1
   bool pipe = false;   // pipelined persistent kernel (else the table kernel)
+  bool cos = false;    // encode: all cosets of a lane tile per work item (k_enc_cos_tab)
 };
 
 struct SingleJob {
@@ -94,7 +95,7 @@ int make_plan(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, Plan& P) {
         s.kind = 0; s.src = J.in; s.dst = J.out; s.stride_src = J.stride_in; s.stride_dst = J.stride_out;
         s.lanes = J.lanes; s.batch = J.batch;
         P.singles.push_back(s);
-      } else if (logK >= kFourStepMinLog) {
+      } else if (encode_fourstep(c, logK, ilog2(pad_pow2(J.n)))) {
         SingleJob s;
         s.kind = 1;
         FourStepArgs& f = s.f;
@@ -180,6 +181,11 @@ int make_plan(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, Plan& P) {
     cl.L = std::get<1>(kv.first);
     cl.D = std::get<2>(kv.first);
     cl.cfg = cl.op == 0 ? c->enc_cfg[cl.L] : c->dec_cfg[cl.L];
+    int occ_cos = 0;
+    if (cl.op == 0 && c->device != FNTRS_HOST_ONLY) {
+      occ_cos = kernel_occupancy(c, 3, cl.L, 0, cl.cfg);
+      cl.cos = occ_cos > 0;
+    }
     const auto& js = kv.second;
     cl.njobs = (uint32_t)js.size();
     const size_t args_bytes = cl.op == 0 ? sizeof(EncodeArgs) : sizeof(DecodeArgs);
@@ -206,7 +212,7 @@ int make_plan(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, Plan& P) {
         a.rows_out = J.n < N ? J.n : 0;
         a.vec = aligned16(J.in, J.ld_in, J.stride_in) && aligned16(J.out, J.ld_out, J.stride_out);
         std::memcpy(P.blob.data() + cl.jobs_off + i * sizeof(EncodeArgs), &a, sizeof a);
-        total += (uint64_t)tiles * a.cosets * J.batch;
+        total += (uint64_t)tiles * (cl.cos ? 1u : a.cosets) * J.batch;
         cl.work += (uint64_t)J.lanes * J.batch * (N / 2) * cl.L;
       } else {
         const fntrs_locator_t* L = J.loc;
@@ -229,9 +235,9 @@ int make_plan(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, Plan& P) {
     cl.total = (uint32_t)total;
     int occ = 1;
     if (c->device != FNTRS_HOST_ONLY) {
-      occ = cl.op == 1 ? kernel_occupancy(c, 2, cl.L, cl.D, cl.cfg) : 0;   // pipelined decoder first
-      cl.pipe = occ > 0;
-      if (!cl.pipe) occ = kernel_occupancy(c, cl.op, cl.L, cl.D, cl.cfg);
+      occ = cl.op == 1 ? kernel_occupancy(c, 2, cl.L, cl.D, cl.cfg) : occ_cos;   // pipelined / all-cosets first
+      cl.pipe = cl.op == 1 && occ > 0;
+      if (occ <= 0) occ = kernel_occupancy(c, cl.op, cl.L, cl.D, cl.cfg);
     }
     if (occ <= 0)
       return fail(c, FNTRS_E_DEVICE, "no occupancy for the %s kernel of size 2^%d (T=%d, NT=%d)",
@@ -308,7 +314,8 @@ int run_plan(fntrs_ctx* c, const Plan& P, const uint8_t* dblob, uint32_t* scratc
     if (cl.op == 0) {
       JobTable<EncodeArgs> t{reinterpret_cast<const EncodeArgs*>(dblob + cl.jobs_off),
                              reinterpret_cast<const uint32_t*>(dblob + cl.start_off), cl.njobs, cl.total};
-      HIP_TRY(c, ct_tables().enc_tab[cl.L](cl.cfg, t, c->tw, c->twi, cl.grid, st));
+      if (cl.cos) HIP_TRY(c, ct_tables().enc_cos_tab[cl.L](cl.cfg, t, c->tw, c->twi, cl.grid, st));
+      else HIP_TRY(c, ct_tables().enc_tab[cl.L](cl.cfg, t, c->tw, c->twi, cl.grid, st));
     } else {
       JobTable<DecodeArgs> t{reinterpret_cast<const DecodeArgs*>(dblob + cl.jobs_off),
                              reinterpret_cast<const uint32_t*>(dblob + cl.start_off), cl.njobs, cl.total};
@@ -488,19 +495,19 @@ int fntrs_autotune(fntrs_ctx* c, uint32_t op, uint32_t n, uint32_t k, uint32_t l
   std::lock_guard<std::mutex> lk(c->mu);
   c->err.clear();
   if (op != FNTRS_OP_ENCODE && op != FNTRS_OP_DECODE) return fail(c, FNTRS_E_INVAL, "unknown op %u", op);
-  if (!is_pow2(n) || n < 2 || n > 32768)
-    return fail(c, FNTRS_E_INVAL, "n=%u: the tuner covers powers of two in [2, 32768]", n);
+  if (n < 2 || n > 65536) return fail(c, FNTRS_E_INVAL, "n=%u must lie in [2, 65536]", n);
   if (k < 1 || k > n) return fail(c, FNTRS_E_INVAL, "k=%u must satisfy 1 <= k <= n=%u", k, n);
-  if (op == FNTRS_OP_DECODE && !is_pow2(k)) return fail(c, FNTRS_E_UNSUPPORTED, "decoding needs k a power of two");
   if (lanes < 1 || batch < 1) return fail(c, FNTRS_E_INVAL, "lanes and batch must be >= 1");
+  const uint32_t N = pad_pow2(n);
+  if (op == FNTRS_OP_DECODE && k < N && 2 * pad_pow2(k) > N)
+    return fail(c, FNTRS_E_UNSUPPORTED, "k=%u above half the transform length %u", k, N);
   if (c->device == FNTRS_HOST_ONLY) return fail(c, FNTRS_E_DEVICE, "host-only context: arguments valid, no device");
   DeviceGuard g(c->device);
   hipStream_t s = (hipStream_t)stream;
   reps = std::max(1u, std::min(reps, 100u));
-  const int L = op == FNTRS_OP_ENCODE ? std::max(1, ilog2(k)) : ilog2(n);
-  if (op == FNTRS_OP_ENCODE && L == 16) return fail(c, FNTRS_E_INVAL, "K = 65536 has one configuration");
+  const int L = op == FNTRS_OP_ENCODE ? std::max(1, ilog2(k)) : ilog2(N);
   // scratch input (zero residues: timing does not depend on the values) and output
-  const uint32_t in_rows = k, out_rows = op == FNTRS_OP_ENCODE ? n : k;
+  const uint32_t in_rows = op == FNTRS_OP_ENCODE ? k : N, out_rows = op == FNTRS_OP_ENCODE ? N : k;
   const size_t in_elems = (size_t)batch * in_rows * lanes, out_elems = (size_t)batch * out_rows * lanes;
   const size_t bytes = (in_elems + out_elems) * 4;
   if (!make_room(c, bytes)) return fail(c, FNTRS_E_NOMEM, "tuning buffers of %zu bytes exceed the context cap", bytes);
@@ -515,9 +522,9 @@ int fntrs_autotune(fntrs_ctx* c, uint32_t op, uint32_t n, uint32_t k, uint32_t l
   uint32_t* out = buf + in_elems;
   fntrs_locator_t* loc = nullptr;
   if (op == FNTRS_OP_DECODE) {
-    // a coset pattern: every (n/k)-th position
+    // an evenly spread pattern: positions floor(i n / k)
     std::vector<uint32_t> z(k);
-    for (uint32_t i = 0; i < k; ++i) z[i] = i * (n / k);
+    for (uint32_t i = 0; i < k; ++i) z[i] = (uint32_t)((uint64_t)i * n / k);
     const uint32_t* zp = z.data();
     if (int rc = locators_acquire(c, 1, &n, &k, &zp, &k, s, &loc)) return rc;
     HIP_TRY(c, hipStreamWaitEvent(s, loc->ready, 0));
@@ -535,52 +542,210 @@ int fntrs_autotune(fntrs_ctx* c, uint32_t op, uint32_t n, uint32_t k, uint32_t l
     hipEvent_t a, b;
     ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
   } ev{e0, e1};
-  const CtVariants var = ct_variants(L);
-  const CtCfg* cands = op == FNTRS_OP_ENCODE ? var.enc : var.dec;
-  float best = -1.f;
-  CtCfg best_cfg{};
-  for (int i = 0; i < 4 && cands[i].T; ++i) {
-    const CtCfg cfg = cands[i];
-    auto launch = [&]() -> hipError_t {
-      if (op == FNTRS_OP_ENCODE) {
-        EncodeArgs a{};
-        a.src = in; a.ld_src = lanes; a.stride_src = (size_t)k * lanes;
-        a.dst = out; a.ld_dst = lanes; a.stride_dst = (size_t)n * lanes;
-        a.tw = c->tw; a.twi = c->twi; a.n = n; a.k = k; a.lanes = lanes;
-        a.logn = ilog2(n); a.logK = L;
-        a.tiles = (lanes + cfg.T - 1) / cfg.T; a.cosets = n >> L;
-        a.vec = aligned16(in, lanes, a.stride_src) && aligned16(out, lanes, a.stride_dst);
-        return launch_ct_encode(c, L, cfg, a, (uint64_t)a.tiles * a.cosets * batch, s);
-      }
-      DecodeArgs a{};
-      a.recv = in; a.ld_recv = lanes; a.stride_recv = (size_t)k * lanes;
-      a.dst = out; a.ld_dst = lanes; a.stride_dst = (size_t)k * lanes;
-      a.tw = c->tw; a.twi = c->twi; a.wfull = loc->wfull; a.ridx = loc->ridx; a.ahat_br = loc->ahat_br;
-      a.n = n; a.k = k; a.lanes = lanes; a.logn = loc->logn; a.logk = loc->logk; a.full = 0;
-      a.tiles = (lanes + cfg.T - 1) / cfg.T;
-      a.vec = aligned16(in, lanes, a.stride_recv) && aligned16(out, lanes, a.stride_dst);
-      const int D = (k == n) ? -1 : loc->logn - loc->logm;
-      return launch_ct_decode(c, L, cfg, D, a, (uint64_t)a.tiles * batch, s);
-    };
-    HIP_TRY(c, launch());   // warm-up (first launch loads the code object)
+  auto timed = [&](auto&& launch, float& ms) -> int {
+    if (int rc = launch()) return rc;   // warm-up (first launch loads the code object)
     HIP_TRY(c, hipEventRecord(e0, s));
-    for (uint32_t r = 0; r < reps; ++r) HIP_TRY(c, launch());
+    for (uint32_t r = 0; r < reps; ++r)
+      if (int rc = launch()) return rc;
     HIP_TRY(c, hipEventRecord(e1, s));
     HIP_TRY(c, hipEventSynchronize(e1));
-    float ms = 0.f;
     HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
     ms /= (float)reps;
-    if (best < 0.f || ms < best) {
-      best = ms;
-      best_cfg = cfg;
+    return FNTRS_OK;
+  };
+  const bool fourstep = L >= kFourStepMinLog;
+  auto call_fnt = [&]() -> int {
+    if (op == FNTRS_OP_ENCODE)
+      return encode_run(c, N, k, lanes, in, lanes, (size_t)k * lanes, out, lanes, (size_t)N * lanes, batch,
+                        n < N ? n : 0, s);
+    return decode_run(c, loc, lanes, true, in, lanes, (size_t)N * lanes, out, lanes, (size_t)k * lanes, batch, s);
+  };
+  fntrs_tuning best{};
+  best.op = op;
+  best.log2_size = (uint32_t)L;
+  float best_ms = -1.f, default_ms = -1.f;
+  if (fourstep) {
+    if (int rc = timed(call_fnt, best_ms)) return rc;
+    default_ms = best_ms;
+    best.tile_lanes = kFourStepTile;
+    best.threads = 256;
+    best.lanes_per_thread = 2;
+    best.radix_log2 = 4;
+    best.method = FNTRS_METHOD_FOURSTEP;
+  } else {
+    const CtVariants var = ct_variants(L);
+    const CtCfg* cands = op == FNTRS_OP_ENCODE ? var.enc : var.dec;
+    CtCfg& slot = op == FNTRS_OP_ENCODE ? c->enc_cfg[L] : c->dec_cfg[L];
+    const CtCfg keep = slot;
+    CtCfg best_cfg = keep;
+    for (int i = 0; i < 4 && cands[i].T; ++i) {
+      slot = cands[i];
+      float ms = 0.f;
+      if (int rc = timed(call_fnt, ms)) {
+        slot = keep;
+        return rc;
+      }
+      if (i == 0) default_ms = ms;
+      if (best_ms < 0.f || ms < best_ms) {
+        best_ms = ms;
+        best_cfg = cands[i];
+      }
+    }
+    slot = best_cfg;
+    fill_tuning(L, best_cfg, &best);
+    best.method = FNTRS_METHOD_TRANSFORM;
+  }
+  // the quadratic methods of Sec. III, where they apply
+  bool& use_direct = c->use_direct[op][L];
+  use_direct = false;
+  if (direct_fits(N, k) && (op == FNTRS_OP_ENCODE || k < N)) {
+    auto call_direct = [&]() -> int {
+      if (op == FNTRS_OP_ENCODE)
+        return direct_encode(c, N, n, k, lanes, in, lanes, (size_t)k * lanes, out, lanes, (size_t)N * lanes, batch, s);
+      return direct_decode(c, loc, lanes, true, in, lanes, (size_t)N * lanes, out, lanes, (size_t)k * lanes, batch,
+                           s);
+    };
+    float ms = 0.f;
+    if (int rc = timed(call_direct, ms)) return rc;
+    if (ms < best_ms) {
+      best_ms = ms;
+      use_direct = true;
+      best.method = FNTRS_METHOD_DIRECT;
+      best.tile_lanes = 16;
+      best.threads = 64;
+      best.lanes_per_thread = 1;
+      best.radix_log2 = 0;
     }
   }
-  if (op == FNTRS_OP_ENCODE) c->enc_cfg[L] = best_cfg;
-  else c->dec_cfg[L] = best_cfg;
-  if (chosen) {
-    fill_tuning(L, best_cfg, chosen);
-    chosen->ms = best;
+  best.ms = best_ms;
+  best.default_ms = default_ms;
+  if (chosen) *chosen = best;
+  return FNTRS_OK;
+}
+
+int fntrs_autotune_batch(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, uint32_t reps, void* stream,
+                         fntrs_tuning* out, uint32_t cap, uint32_t* nout) {
+  if (!c) return FNTRS_E_INVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->err.clear();
+  if (nout) *nout = 0;
+  Plan all;
+  if (int rc = make_plan(c, jobs, njobs, all)) return rc;
+  if (c->device == FNTRS_HOST_ONLY) return fail(c, FNTRS_E_DEVICE, "host-only context: arguments valid, no device");
+  if (njobs == 0) return FNTRS_OK;
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  for (fntrs_locator_t* L : all.locs) HIP_TRY(c, hipStreamWaitEvent(s, L->ready, 0));
+  reps = std::max(1u, std::min(reps, 50u));
+  // the jobs of each class: (op, log2 size) -> job indices; four-step classes by size too
+  std::map<std::pair<int, int>, std::vector<fntrs_job>> classes;
+  for (uint32_t j = 0; j < njobs; ++j) {
+    const fntrs_job& J = jobs[j];
+    int L;
+    if (J.op == FNTRS_OP_ENCODE) L = std::max(1, ilog2(J.k));
+    else L = J.loc->logn;
+    classes[{(int)J.op, L}].push_back(J);
   }
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+  } ev{e0, e1};
+  // one class's batch, planned with the context's current configuration
+  auto run_class = [&](const std::vector<fntrs_job>& js, float& ms) -> int {
+    Plan P;
+    if (int rc = make_plan(c, js.data(), (uint32_t)js.size(), P)) return rc;
+    const size_t blob = align_up(P.blob.size());
+    const size_t bytes = blob + P.scratch_elems * 4;
+    uint8_t* mem = nullptr;
+    if (bytes) {
+      hipError_t e = hipMallocAsync((void**)&mem, bytes, s);
+      if (e != hipSuccess) return fail(c, FNTRS_E_NOMEM, "tuning workspace of %zu bytes", bytes);
+      if (int rc = upload_async(c, mem, P.blob.data(), P.blob.size(), s)) {
+        (void)hipFreeAsync(mem, s);
+        return rc;
+      }
+    }
+    int rc = run_plan(c, P, mem, reinterpret_cast<uint32_t*>(mem + blob), s, c->sides[s]);   // warm-up
+    if (!rc && hipEventRecord(e0, s) != hipSuccess) rc = fail(c, FNTRS_E_DEVICE, "event record");
+    for (uint32_t r = 0; !rc && r < reps; ++r)
+      rc = run_plan(c, P, mem, reinterpret_cast<uint32_t*>(mem + blob), s, c->sides[s]);
+    if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = fail(c, FNTRS_E_DEVICE, "event record");
+    if (mem) (void)hipFreeAsync(mem, s);
+    if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = fail(c, FNTRS_E_DEVICE, "event synchronize");
+    if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(c, FNTRS_E_DEVICE, "elapsed time");
+    ms /= (float)reps;
+    return rc;
+  };
+  uint32_t count = 0;
+  for (auto& kv : classes) {
+    const int op = kv.first.first, L = kv.first.second;
+    fntrs_tuning best{};
+    best.op = (uint32_t)op;
+    best.log2_size = (uint32_t)L;
+    float best_ms = -1.f, default_ms = -1.f;
+    const bool fourstep = L >= kFourStepMinLog;
+    if (fourstep) {
+      if (int rc = run_class(kv.second, best_ms)) return rc;
+      default_ms = best_ms;
+      best.tile_lanes = kFourStepTile;
+      best.threads = 256;
+      best.lanes_per_thread = 2;
+      best.radix_log2 = 4;
+      best.method = FNTRS_METHOD_FOURSTEP;
+    } else {
+      const CtVariants var = ct_variants(L);
+      const CtCfg* cands = op == FNTRS_OP_ENCODE ? var.enc : var.dec;
+      CtCfg& slot = op == FNTRS_OP_ENCODE ? c->enc_cfg[L] : c->dec_cfg[L];
+      const CtCfg keep = slot;
+      CtCfg best_cfg = keep;
+      for (int i = 0; i < 4 && cands[i].T; ++i) {
+        slot = cands[i];
+        float ms = 0.f;
+        if (int rc = run_class(kv.second, ms)) {
+          slot = keep;
+          return rc;
+        }
+        if (i == 0) default_ms = ms;
+        if (best_ms < 0.f || ms < best_ms) {
+          best_ms = ms;
+          best_cfg = cands[i];
+        }
+      }
+      slot = best_cfg;
+      fill_tuning(L, best_cfg, &best);
+      best.method = FNTRS_METHOD_TRANSFORM;
+      // K = 2^13 into n >= 2^14: the four-step FNT_n of the zero-padded source competes
+      const bool all_long = std::all_of(kv.second.begin(), kv.second.end(),
+                                        [](const fntrs_job& J) { return pad_pow2(J.n) >= (1u << kFourStepMinLog); });
+      if (op == FNTRS_OP_ENCODE && L == kFourStepMinLog - 1 && all_long) {
+        const bool keep4 = c->enc_fourstep13;
+        c->enc_fourstep13 = true;
+        float ms = 0.f;
+        if (int rc = run_class(kv.second, ms)) {
+          c->enc_fourstep13 = keep4;
+          return rc;
+        }
+        if (ms < best_ms) {
+          best_ms = ms;
+          best.tile_lanes = kFourStepTile;
+          best.threads = 256;
+          best.lanes_per_thread = 2;
+          best.radix_log2 = 4;
+          best.method = FNTRS_METHOD_FOURSTEP;
+        } else {
+          c->enc_fourstep13 = false;
+        }
+      }
+    }
+    best.ms = best_ms;
+    best.default_ms = default_ms;
+    if (out && count < cap) out[count] = best;
+    ++count;
+  }
+  if (nout) *nout = std::min(count, cap);
   return FNTRS_OK;
 }
 
@@ -591,6 +756,10 @@ int fntrs_get_config(fntrs_ctx* c, uint32_t op, uint32_t log2_size, fntrs_tuning
     return fail(c, FNTRS_E_INVAL, "op %u / size 2^%u has no table configuration", op, log2_size);
   fill_tuning((int)log2_size, op == FNTRS_OP_ENCODE ? c->enc_cfg[log2_size] : c->dec_cfg[log2_size], cfg);
   cfg->ms = 0.f;
+  cfg->default_ms = 0.f;
+  cfg->op = op;
+  cfg->log2_size = log2_size;
+  cfg->method = c->use_direct[op][log2_size] ? FNTRS_METHOD_DIRECT : FNTRS_METHOD_TRANSFORM;
   return FNTRS_OK;
 }
 

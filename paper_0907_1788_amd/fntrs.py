@@ -43,6 +43,10 @@ FNTRS_RECV_FULL = 1
 FNTRS_FLAG_VALIDATE = 2
 FNTRS_SYSTEMATIC = 4
 FNTRS_DIRECT = 8
+FNTRS_TRANSFORM = 16
+FNTRS_METHOD_TRANSFORM = 0
+FNTRS_METHOD_DIRECT = 1
+FNTRS_METHOD_FOURSTEP = 2
 
 FNTRS_OP_ENCODE = 0
 FNTRS_OP_DECODE = 1
@@ -62,7 +66,8 @@ class fntrs_job(ctypes.Structure):
 class fntrs_tuning(ctypes.Structure):
     """struct fntrs_tuning of include/fntrs.h."""
     _fields_ = [("tile_lanes", _u32), ("threads", _u32), ("lanes_per_thread", _u32), ("radix_log2", _u32),
-                ("ms", ctypes.c_float)]
+                ("ms", ctypes.c_float), ("op", _u32), ("log2_size", _u32), ("method", _u32),
+                ("default_ms", ctypes.c_float)]
 
 
 _pjob = ctypes.POINTER(fntrs_job)
@@ -87,6 +92,7 @@ SIGNATURES = {
     "fntrs_graph_destroy": (_int, [_vp, _vp]),
     "fntrs_autotune": (_int, [_vp, _u32, _u32, _u32, _u32, _u32, _u32, _vp, _ptun]),
     "fntrs_get_config": (_int, [_vp, _u32, _u32, _ptun]),
+    "fntrs_autotune_batch": (_int, [_vp, _pjob, _u32, _u32, _vp, _ptun, _u32, ctypes.POINTER(_u32)]),
     "fntrs_version": (ctypes.c_char_p, []),
 }
 
@@ -224,6 +230,16 @@ def fntrs_autotune(ctx, op, n, k, lanes, batch, reps=5, stream=0):
     return rc, t
 
 
+def fntrs_autotune_batch(ctx, jobs, reps=3, stream=0):
+    """Returns (rc, [fntrs_tuning per class])."""
+    arr = _job_array(jobs)
+    cap = 64
+    out = (fntrs_tuning * cap)()
+    nout = _u32(0)
+    rc = lib().fntrs_autotune_batch(ctx, arr, len(arr), reps, stream, out, cap, ctypes.byref(nout))
+    return rc, [out[i] for i in range(nout.value)]
+
+
 def fntrs_get_config(ctx, op, log2_size):
     t = fntrs_tuning()
     rc = lib().fntrs_get_config(ctx, op, log2_size, ctypes.byref(t))
@@ -268,6 +284,14 @@ def _stream_handle(stream) -> int:
     if isinstance(stream, int):
         return stream
     return stream.cuda_stream
+
+
+def _tuning_dict(t):
+    method = {FNTRS_METHOD_TRANSFORM: "transform", FNTRS_METHOD_DIRECT: "direct",
+              FNTRS_METHOD_FOURSTEP: "four-step"}.get(t.method, str(t.method))
+    return {"op": "encode" if t.op == FNTRS_OP_ENCODE else "decode", "log2_size": t.log2_size, "method": method,
+            "tile_lanes": t.tile_lanes, "threads": t.threads, "lanes_per_thread": t.lanes_per_thread,
+            "radix_log2": t.radix_log2, "ms": round(t.ms, 4), "default_ms": round(t.default_ms, 4)}
 
 
 class Locator:
@@ -403,8 +427,13 @@ class Context:
         """Times every configuration of the size class and keeps the fastest; returns it as a dict."""
         rc, t = fntrs_autotune(self.handle, op, n, k, lanes, batch, reps, _stream_handle(stream))
         _check(self.handle, rc)
-        return {"tile_lanes": t.tile_lanes, "threads": t.threads, "lanes_per_thread": t.lanes_per_thread,
-                "radix_log2": t.radix_log2, "ms": t.ms}
+        return _tuning_dict(t)
+
+    def autotune_batch(self, jobs, reps: int = 3, stream=None):
+        """Tunes every size class of a batch on its own jobs; returns one dict per class."""
+        rc, ts = fntrs_autotune_batch(self.handle, jobs, reps, _stream_handle(stream))
+        _check(self.handle, rc)
+        return [_tuning_dict(t) for t in ts]
 
     def config(self, op: int, log2_size: int):
         rc, t = fntrs_get_config(self.handle, op, log2_size)

@@ -375,11 +375,12 @@ std::function<void(Op&)> kernel_model(const std::string& name, dim3 grid, void**
     const bool cos = fn == "k_enc_cos";
     return [a, g, cos](Op& x) { model_encode(x, a, cos ? g * a.cosets : g, (uint64_t)a.tiles * a.cosets); };
   }
-  if (fn == "k_enc_tab") {
+  if (fn == "k_enc_tab" || fn == "k_enc_cos_tab") {
     const JobTable<EncodeArgs> t = *(const JobTable<EncodeArgs>*)args[0];
-    return [t](Op& x) {
+    const bool cos = fn == "k_enc_cos_tab";   // a work item covers every coset of its tile
+    return [t, cos](Op& x) {
       model_table(x, t, [&](const EncodeArgs& a, uint64_t items) {
-        model_encode(x, a, items, (uint64_t)a.tiles * a.cosets);
+        model_encode(x, a, cos ? items * a.cosets : items, (uint64_t)a.tiles * a.cosets);
       });
     };
   }
@@ -456,13 +457,14 @@ std::function<void(Op&)> kernel_model(const std::string& name, dim3 grid, void**
     const uint32_t* w = *(const uint32_t* const*)args[1];
     const uint32_t* pos = *(const uint32_t* const*)args[2];
     const uint32_t* tw = *(const uint32_t* const*)args[3];
-    const uint32_t k = *(const uint32_t*)args[5];
-    uint32_t* W = *(uint32_t* const*)args[6];
+    const uint32_t* twi = *(const uint32_t* const*)args[4];
+    const uint32_t k = *(const uint32_t*)args[6];
+    uint32_t* W = *(uint32_t* const*)args[7];
     return [=](Op& x) {
       touch(x, (uintptr_t)A, (size_t)(k + 1) * 4, false, "A");
       touch(x, (uintptr_t)w, (size_t)k * 4, false, "w");
       touch(x, (uintptr_t)pos, (size_t)k * 4, false, "pos");
-      touch(x, (uintptr_t)tw, 65536 * 4, false, "tw");
+      model_tw(x, tw, twi);
       touch(x, (uintptr_t)W, (size_t)k * k * 4, true, "W");
     };
   }

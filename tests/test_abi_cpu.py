@@ -221,9 +221,14 @@ def test_graph_and_tuner_validation(hctx):
     assert L.fntrs_graph_destroy(hctx, None) == fntrs.FNTRS_E_INVAL
     assert fntrs.fntrs_autotune(hctx, 0, 8192, 4096, 64, 1)[0] == fntrs.FNTRS_E_DEVICE
     assert fntrs.fntrs_autotune(hctx, 2, 8192, 4096, 64, 1)[0] == fntrs.FNTRS_E_INVAL
-    assert fntrs.fntrs_autotune(hctx, 0, 65536, 4096, 64, 1)[0] == fntrs.FNTRS_E_INVAL
-    assert fntrs.fntrs_autotune(hctx, 1, 8192, 3000, 64, 1)[0] == fntrs.FNTRS_E_UNSUPPORTED
+    assert fntrs.fntrs_autotune(hctx, 0, 65536, 16384, 64, 1)[0] == fntrs.FNTRS_E_DEVICE   # four-step sizes
+    assert fntrs.fntrs_autotune(hctx, 1, 65536, 16384, 64, 1)[0] == fntrs.FNTRS_E_DEVICE
+    assert fntrs.fntrs_autotune(hctx, 1, 8192, 3000, 64, 1)[0] == fntrs.FNTRS_E_DEVICE    # any k
+    assert fntrs.fntrs_autotune(hctx, 1, 8192, 5000, 64, 1)[0] == fntrs.FNTRS_E_UNSUPPORTED
+    assert fntrs.fntrs_autotune(hctx, 0, 131072, 4096, 64, 1)[0] == fntrs.FNTRS_E_INVAL
     assert fntrs.fntrs_autotune(hctx, 0, 8192, 4096, 0, 1)[0] == fntrs.FNTRS_E_INVAL
+    rc, ts = fntrs.fntrs_autotune_batch(hctx, [ejob(512, 256, 64, SRC, DST)])
+    assert rc == fntrs.FNTRS_E_DEVICE and ts == []
     rc, t = fntrs.fntrs_get_config(hctx, 1, 13)
     assert rc == fntrs.FNTRS_OK and t.tile_lanes >= 1 and t.threads >= 64 and 1 <= t.radix_log2 <= 5
     assert fntrs.fntrs_get_config(hctx, 0, 16)[0] == fntrs.FNTRS_E_INVAL

@@ -221,6 +221,63 @@ def test_autotune_keeps_results_exact(ctx):
         cw.loc.release()
 
 
+def test_autotune_covers_every_size_and_the_direct_methods():
+    """Four-step classes (2^14 points and more) are timed, any k decodes, and
+    for small codes the direct methods compete; whichever wins, single calls
+    stay bit-exact (their outputs are unique)."""
+    from paper_0907_1788_amd.fntrs import FNTRS_OP_DECODE, FNTRS_OP_ENCODE
+    with fntrs.Context(0) as c:
+        for op, n, k, lanes in [(FNTRS_OP_ENCODE, 65536, 16384, 64), (FNTRS_OP_DECODE, 65536, 16384, 64),
+                                (FNTRS_OP_DECODE, 32768, 9000, 32), (FNTRS_OP_DECODE, 8192, 3000, 64),
+                                (FNTRS_OP_ENCODE, 128, 64, 256), (FNTRS_OP_DECODE, 128, 64, 256),
+                                (FNTRS_OP_ENCODE, 512, 200, 512), (FNTRS_OP_DECODE, 512, 256, 512)]:
+            say("autotune", op, n, k, lanes)
+            t = c.autotune(op, n, k, lanes=lanes, batch=1, reps=3)
+            assert t["ms"] > 0 and t["default_ms"] > 0
+            if n >= 16384 and (op == FNTRS_OP_DECODE or k > 8192):
+                assert t["method"] == "four-step"
+            else:
+                assert t["method"] in ("transform", "direct")
+        # single calls after tuning, whatever method the tuner chose
+        for n, k, lanes in [(128, 64, 256), (512, 200, 512), (512, 256, 512)]:
+            src = synth.source(1300 + n, 1, k, lanes)
+            e = torch.empty((1, n, lanes), dtype=torch.int32, device="cuda")
+            c.encode(dev(src), e, n)
+            torch.cuda.synchronize()
+            rows = np.array([0, 1, n // 2, n - 1])
+            assert np.array_equal(host(e)[0][rows][:, :2], codec.encode(src[0][:, :2].astype(np.int64), n, rows=rows))
+            z = synth.received_positions(1400 + n, n, k)
+            loc = c.locator(n, k, z)
+            d = torch.empty((1, k, lanes), dtype=torch.int32, device="cuda")
+            c.decode(loc, e, d, fntrs.FNTRS_RECV_FULL)
+            torch.cuda.synchronize()
+            assert np.array_equal(host(d), src.astype(np.int64))
+            loc.release()
+
+
+def test_autotune_batch_tunes_each_class_and_keeps_results_exact():
+    with fntrs.Context(0) as c:
+        cws = build_batch(c, [(4096, 8192, 70), (2048, 4096, 9), (256, 512, 300), (16384, 65536, 40),
+                              (1000, 4096, 33)], seed=6)
+        enc_jobs = [c.encode_job(cw.src, cw.enc, cw.n) for cw in cws]
+        ts = c.autotune_batch(enc_jobs, reps=2)
+        assert {(t["op"], t["log2_size"]) for t in ts} == {("encode", 12), ("encode", 11), ("encode", 8),
+                                                           ("encode", 14), ("encode", 10)}
+        assert all(t["ms"] > 0 for t in ts)
+        for t in ts:
+            if t["method"] == "transform":
+                assert c.config(fntrs.FNTRS_OP_ENCODE, t["log2_size"])["tile_lanes"] == t["tile_lanes"]
+        run_submit(c, cws)
+        dec_jobs = [c.decode_job(cw.loc, cw.recv, cw.dec, cw.dec_flags()) for cw in cws]
+        ts = c.autotune_batch(dec_jobs, reps=2)
+        assert {t["log2_size"] for t in ts} == {13, 12, 9, 16}
+        run_submit(c, cws)
+        check_against_oracle(cws, lanes_checked=1)
+        check_against_singles(c, cws)
+        for cw in cws:
+            cw.loc.release()
+
+
 def test_locator_batch_state_matches_oracle(ctx):
     """Patterns built together (mixed n and k, nothing erased, k = 1, repeats) equal the oracle's locators."""
     specs = [(16, 4, 1), (64, 64, 0), (128, 1, 2), (256, 64, 3), (512, 256, 4), (1024, 128, 5), (2048, 1024, 6),
