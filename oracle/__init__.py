@@ -18,4 +18,6 @@ Modules:
                the six-step interpolation (Sec. II-B, steps 1-6)
   direct    -- the quadratic encoders and decoders of Sec. III (Tables I and II,
                and the classic quadratic schemes of its footnote)
+  chirp     -- evaluation on a geometric sequence by one middle product
+               (Sec. II-B, steps 3 and 5; Sec. III)
 """

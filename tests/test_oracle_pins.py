@@ -34,6 +34,9 @@ P25 Lagrange basis: L_i(x_j) = [i = j], sum_i L_i = 1                -- closed f
 P26 systematic direct encoding (Table I) = systematic code; k=1, k=n -- P16..P19, closed forms
 P27 direct intermediate & FNT (Table I) = direct encoding            -- two algorithms
 P28 systematic direct decoding (Table II) from every k-subset        -- brute force
+P29 chirp evaluation on a geometric sequence = Horner at each point   -- two algorithms, closed forms
+P30 step 3 by the chirp: A' on an arithmetic run of positions          -- product of differences (P7)
+P31 step 5 by the chirp: S_j = -N'(r^(-j-1))                            -- Taylor series (step 5 pin)
 """
 import itertools
 import os
@@ -41,7 +44,7 @@ import os
 import numpy as np
 import pytest
 
-from oracle import codec, direct, field, poly, transform
+from oracle import chirp, codec, direct, field, poly, transform
 from paper_0907_1788_amd import synth
 
 P = 65537
@@ -510,3 +513,45 @@ def test_p28_systematic_direct_decoding_every_subset(n, k):
         assert np.array_equal(direct.systematic_decode_direct(n, z, e[z]), s.astype(np.int64)), z
     assert direct.direct_decode_cost(16, np.arange(4, 8), 4) == 16
     assert direct.direct_decode_cost(16, np.arange(0, 4), 4) == 0
+
+
+# --------------------------------------------------------------- P29 .. P31
+@pytest.mark.parametrize("L,M,q,a", [(5, 7, 3, 1), (16, 16, 4096, 1), (9, 4, 5, 7), (1, 3, 2, 9), (12, 20, 1, 3),
+                                     (8, 8, 65536, 65536), (33, 10, 12345, 54321)])
+def test_p29_chirp_equals_horner(L, M, q, a):
+    """Sec. II-B: with t_i = i(i-1)/2, c(a q^i) = q^(-t_i) sum_j c_j a^j
+    q^(-t_j) q^(t_(i+j)), the middle coefficients of one product.  Against
+    Horner's rule at every point, for roots of unity, other elements, q = 1
+    (every point equal) and q = -1; and a unit vector gives (a q^i)^j."""
+    c = synth.residues(960 + L + M, (L, 3))
+    assert np.array_equal(chirp.chirp_eval(c, q, M, a), chirp.horner_points(c, q, M, a))
+    e = np.zeros(L, dtype=np.int64)
+    e[L - 1] = 1
+    want = [pow(a * pow(q, i, P) % P, L - 1, P) for i in range(M)]
+    assert list(chirp.chirp_eval(e, q, M, a)) == want
+
+
+@pytest.mark.parametrize("n,k,s,d", [(64, 8, 3, 5), (512, 64, 0, 2), (256, 100, 17, 1)])
+def test_p30_step3_by_chirp_on_an_arithmetic_run(n, k, s, d):
+    """Received positions z_i = s + d i are the points r^s (r^d)^i: the chirp
+    evaluates A' there (step 3) and gives the products of differences A'(x_i)
+    = prod_{j != i} (x_i - x_j) (pin P7)."""
+    z = np.array([(s + d * i) % n for i in range(k)])
+    assert len(set(z)) == k
+    loc = codec.locator(n, np.sort(z), with_w=False)
+    r = field.root(n)
+    got = chirp.chirp_eval(loc["dA"], pow(r, d, P), k, pow(r, s, P))
+    assert np.array_equal(got, codec.lagrange_denominators(codec.eval_points(n, z)))
+
+
+@pytest.mark.parametrize("n,k,seed", [(64, 16, 1), (512, 100, 2)])
+def test_p31_step5_by_chirp(n, k, seed):
+    """Step 5: S_j = -N'(r^(-j-1)), j < k, with N'(y) = sum_i n_i y^(z_i): the
+    chirp on q = a = r^(-1) gives the series of the step-5 pin."""
+    z = synth.received_positions(970 + seed, n, k).astype(np.int64)
+    nv = synth.residues(971 + seed, (k, 2))
+    Np = np.zeros((n, 2), dtype=np.int64)
+    Np[z] = nv
+    rinv = field.inverse(field.root(n))
+    got = (P - chirp.chirp_eval(Np, rinv, k, rinv)) % P
+    assert np.array_equal(got, codec.step5_series(n, z, nv, k))
