@@ -52,6 +52,10 @@ UNEVEN = "uneven512_seed4"
 # sizes from the uneven-batch distribution, offered load swept around the
 # measured batched peak, 32 GB device working-set cap
 SERVED = "served_poisson"
+# evaluation of 4 x 2048 polynomials of degree < 4096 at 4096 points of a
+# geometric sequence (the chirp of Sec. II-B): one product of length 8192
+CHIRP = "chirp_L4096_M4096_l2048_b4"
+CHIRP_SHAPE = (4096, 4096, 2048, 4)   # L, M, lanes, blocks
 DEFAULT = UNEVEN
 HBM_PEAK_GBS = 8000.0
 
@@ -465,6 +469,75 @@ def run_served(args, torch, fntrs, synth):
     print(json.dumps(res), flush=True)
 
 
+def cpu_baseline_chirp(synth, L, M, seed, budget_s=10.0):
+    """The oracle's chirp evaluation (one schoolbook product per lane) on
+    whole lanes of the workload, one process, until the budget is spent."""
+    from oracle import chirp
+    c = synth.residues(seed, (L, 64))
+    t0 = time.perf_counter()
+    done = 0
+    while done < 64 and time.perf_counter() - t0 < budget_s:
+        chirp.chirp_eval(c[:, done], 3, M, 5)
+        done += 1
+    dt = time.perf_counter() - t0
+    return {"value": round(4 * (L + M) * done / dt / 1e9, 6), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} lanes of L = {L}, M = {M} (oracle/chirp.py, schoolbook middle product), {dt:.1f} s"}
+
+
+def run_chirp(args, torch, fntrs, synth, cpu=True):
+    """Evaluation on a geometric sequence by one middle product (fntrs_chirp_eval):
+    one step = one call over every block.  Exactness: Horner's rule at sampled
+    points on the host, every lane of the first and last block."""
+    L, M, lanes, blocks = CHIRP_SHAPE
+    dev = torch.device("cuda:0")
+    a, q = 5, 3
+    coef = torch.from_numpy(synth.residues(args.seed, (blocks, L, lanes)).astype(np.int32)).to(dev)
+    out = torch.empty((blocks, M, lanes), dtype=torch.int32, device=dev)
+    ctx = fntrs.Context(0)
+    stream = torch.cuda.current_stream()
+    nsteps = args.steps + args.warmup
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(nsteps)]
+    for i in range(nsteps):
+        ev[i][0].record(stream)
+        ctx.chirp_eval(coef, out, a, q, stream=stream)
+        ev[i][1].record(stream)
+        if i == args.warmup - 1:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    ms_list = [ev[i][0].elapsed_time(ev[i][1]) for i in range(args.warmup, nsteps)]
+    ms = float(np.mean(ms_list))
+    pick = np.array([0, 1, 2, 977, 2048, M - 1])
+    x = np.array([a * pow(q, int(i), 65537) % 65537 for i in pick], dtype=np.int64)[:, None]
+    exact = True
+    for b in (0, blocks - 1):
+        cb = coef[b].cpu().numpy().astype(np.int64)
+        ref = np.zeros((pick.size, lanes), dtype=np.int64)
+        for j in range(L - 1, -1, -1):
+            ref = (ref * x + cb[j][None, :]) % 65537
+        exact &= bool(np.array_equal(out[b].cpu().numpy().astype(np.int64)[pick], ref))
+    log("chirp exact", exact, "ms", ms)
+    nbytes = 4 * (L + M) * lanes * blocks
+    res = {
+        "metric": "chirp evaluation GB/s (coefficients in + values out, bit-exact)",
+        "value": round(nbytes / (ms * 1e-3) / 1e9, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": CHIRP, "L": L, "M": M, "lanes": lanes, "blocks": blocks, "a": a, "q": q,
+                   "product_length": 8192, "parallelism": "single GPU"},
+        "bit_exact": exact,
+        "latency_ms": {"p50": float(np.percentile(ms_list, 50)), "p99": float(np.percentile(ms_list, 99))},
+        "roofline": {"bound": "hbm", "kernel": "fntrs_chirp_eval (the whole call: 3 transforms, 4 pointwise kernels)",
+                     "achieved": round(nbytes / (ms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_hbm_bytes": nbytes},
+    }
+    ctx.close()
+    if cpu:
+        log("cpu baseline")
+        res["cpu_baseline"] = cpu_baseline_chirp(synth, L, M, args.seed)
+    return res
+
+
 def run_single(args, torch, fntrs, synth, workload, cpu=True):
     """A single-size workload: one step = encode every block, build the locator
     of a fresh pattern shared by the blocks, decode every block.  Returns the
@@ -620,7 +693,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + [UNEVEN, SERVED])
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + [UNEVEN, SERVED, CHIRP])
     ap.add_argument("--requests", type=int, default=2000, help="requests per load point (served workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -658,6 +731,9 @@ def main():
 
     if args.workload == SERVED:
         run_served(args, torch, fntrs, synth)
+        return
+    if args.workload == CHIRP:
+        print(json.dumps(run_chirp(args, torch, fntrs, synth, cpu=not args.no_cpu_baseline)), flush=True)
         return
     if args.workload != UNEVEN:
         print(json.dumps(run_single(args, torch, fntrs, synth, args.workload, cpu=not args.no_cpu_baseline)),

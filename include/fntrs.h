@@ -216,6 +216,25 @@ int fntrs_decode(fntrs_ctx* ctx, const fntrs_locator_t* loc, uint32_t lanes, uin
                  uint32_t* dst, size_t ld_dst, size_t stride_dst,
                  uint32_t batch, void* stream);
 
+/* Evaluation of polynomials on a geometric sequence by one middle product
+ * (the chirp of Sec. II-B, step 3, which also serves step 5; the middle
+ * product of Sec. III): for every block b, point i < M and lane l,
+ *     out[b][i][l] = sum_{j<L} coeffs[b][j][l] * (a q^i)^j   (mod 65537),
+ * i.e. each lane holds the L coefficients of one polynomial, lowest degree
+ * first.  With t_i = i(i-1)/2 the values are q^(-t_i) times the middle
+ * coefficients L-1 .. L+M-2 of the product of (c_j a^j q^(-t_j)) reversed by
+ * (q^(t_m)), computed as a cyclic product of length P = 2^ceil(log2(L+M-1)):
+ * three transforms of the encoder and three pointwise kernels.  Step 3
+ * evaluates A' on positions in arithmetic progression (q = r_n^d,
+ * a = r_n^s); step 5's S_j = -N'(r_n^(-j-1)) is q = a = r_n^-1.  a and q:
+ * nonzero residues; L + M - 1 <= 65536.  Device pointers; asynchronous on
+ * `stream`; holds 2(P + batch P lanes) words of stream-ordered scratch.
+ * Errors: FNTRS_E_INVAL, FNTRS_E_UNSUPPORTED (L + M - 1 > 65536),
+ * FNTRS_E_NOMEM, FNTRS_E_DEVICE. */
+int fntrs_chirp_eval(fntrs_ctx* ctx, uint32_t L, uint32_t M, uint32_t a, uint32_t q, const uint32_t* coeffs,
+                     size_t ld_in, size_t stride_in, uint32_t* out, size_t ld_out, size_t stride_out,
+                     uint32_t lanes, uint32_t batch, void* stream);
+
 /* 16-bit transport of encoding symbols (Sec. II-B: every residue but 65536
  * is a 16-bit value; the positions holding 65536 travel in the symbol's
  * header).  A symbol is one row of `lanes` residues; in/out hold `rows` rows

@@ -5,7 +5,8 @@ kernels; submit.hip: batches, graphs, autotuner) plus one translation unit
 per transform size for the
 compile-time kernels (ct_inst.hip with -DFNTRS_L=1..15), plus the
 four-step kernels for n = 2^14 .. 2^16 (fourstep.hip), the 16-bit
-transport kernels (wire.hip) and the direct quadratic methods (direct.hip).  They compile in
+transport kernels (wire.hip) and the direct quadratic methods (direct.hip) and the chirp evaluation
+(chirp.hip).  They compile in
 parallel into paper_0907_1788_amd/_build/ and link into libfntrs.so.
 
 Usage: python -m paper_0907_1788_amd.build   (or call build()).
@@ -48,7 +49,8 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
              (os.path.join(CSRC, "submit.hip"), os.path.join(BUILD, "submit.o"), []),
              (os.path.join(CSRC, "fourstep.hip"), os.path.join(BUILD, "fourstep.o"), []),
              (os.path.join(CSRC, "wire.hip"), os.path.join(BUILD, "wire.o"), []),
-             (os.path.join(CSRC, "direct.hip"), os.path.join(BUILD, "direct.o"), [])]
+             (os.path.join(CSRC, "direct.hip"), os.path.join(BUILD, "direct.o"), []),
+             (os.path.join(CSRC, "chirp.hip"), os.path.join(BUILD, "chirp.o"), [])]
     for L in SIZES:
         units.append((os.path.join(CSRC, "ct_inst.hip"), os.path.join(BUILD, f"ct_{L}.o"), [f"-DFNTRS_L={L}"]))
     jobs = jobs or min(16, os.cpu_count() or 4)

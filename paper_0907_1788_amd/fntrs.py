@@ -92,6 +92,7 @@ SIGNATURES = {
     "fntrs_graph_destroy": (_int, [_vp, _vp]),
     "fntrs_autotune": (_int, [_vp, _u32, _u32, _u32, _u32, _u32, _u32, _vp, _ptun]),
     "fntrs_get_config": (_int, [_vp, _u32, _u32, _ptun]),
+    "fntrs_chirp_eval": (_int, [_vp, _u32, _u32, _u32, _u32, _vp, _sz, _sz, _vp, _sz, _sz, _u32, _u32, _vp]),
     "fntrs_autotune_batch": (_int, [_vp, _pjob, _u32, _u32, _vp, _ptun, _u32, ctypes.POINTER(_u32)]),
     "fntrs_version": (ctypes.c_char_p, []),
 }
@@ -386,6 +387,15 @@ class Context:
     def submit(self, jobs, stream=None) -> None:
         """Enqueues a batch of jobs (encode_job / decode_job) in one call."""
         _check(self.handle, fntrs_submit(self.handle, jobs, _stream_handle(stream)))
+
+    def chirp_eval(self, coeffs, out, a: int, q: int, stream=None) -> None:
+        """out[b, i, l] = sum_j coeffs[b, j, l] (a q^i)^j for i < out rows (Sec. II-B, the chirp)."""
+        b, L, lanes, ld_c, st_c = _geom(coeffs)
+        b2, M, lanes2, ld_o, st_o = _geom(out)
+        if (b2, lanes2) != (b, lanes):
+            raise ValueError("coeffs and out disagree on batch or lanes")
+        _check(self.handle, lib().fntrs_chirp_eval(self.handle, L, M, a, q, coeffs.data_ptr(), ld_c, st_c,
+                                                   out.data_ptr(), ld_o, st_o, lanes, b, _stream_handle(stream)))
 
     # ------------------------------------------------------- 16-bit transport
     def pack16(self, src, out16, esc_count, esc_pos, stream=None) -> None:

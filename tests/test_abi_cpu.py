@@ -269,3 +269,25 @@ def test_wire_validation(hctx):
     for args in bad:
         assert L.fntrs_pack16(*args) == fntrs.FNTRS_E_INVAL, args
     assert L.fntrs_pack16(None, *ok[1:]) == fntrs.FNTRS_E_INVAL
+
+
+def test_chirp_validation(hctx):
+    """fntrs_chirp_eval argument checks (the chirp of Sec. II-B)."""
+    L = fntrs.lib()
+    OUT = SRC + (1 << 24)
+
+    def call(L_, M, a, q, src=SRC, ld_i=4, st_i=None, out=OUT, ld_o=4, st_o=None, lanes=4, batch=2):
+        st_i = L_ * ld_i if st_i is None else st_i
+        st_o = M * ld_o if st_o is None else st_o
+        return L.fntrs_chirp_eval(hctx, L_, M, a, q, src, ld_i, st_i, out, ld_o, st_o, lanes, batch, None)
+
+    assert call(10, 20, 1, 3) == fntrs.FNTRS_E_DEVICE             # valid: no device behind the context
+    assert call(65536, 1, 65536, 65536) == fntrs.FNTRS_E_DEVICE    # the longest product
+    assert call(40000, 30000, 1, 3) == fntrs.FNTRS_E_UNSUPPORTED   # L + M - 1 > 65536
+    for args, kw in [((0, 5, 1, 3), {}), ((5, 0, 1, 3), {}), ((5, 5, 0, 3), {}), ((5, 5, 1, 0), {}),
+                     ((5, 5, 65537, 3), {}), ((5, 5, 1, 3), {"lanes": 0}), ((5, 5, 1, 3), {"batch": 0}),
+                     ((5, 5, 1, 3), {"src": None}), ((5, 5, 1, 3), {"out": None}), ((5, 5, 1, 3), {"ld_i": 3}),
+                     ((5, 5, 1, 3), {"ld_o": 2}), ((5, 5, 1, 3), {"st_i": 10}), ((5, 5, 1, 3), {"st_o": 19}),
+                     ((5, 5, 1, 3), {"out": SRC + 16})]:
+        assert call(*args, **kw) == fntrs.FNTRS_E_INVAL, (args, kw)
+    assert L.fntrs_chirp_eval(None, 5, 5, 1, 3, SRC, 4, 20, OUT, 4, 20, 4, 1, None) == fntrs.FNTRS_E_INVAL
