@@ -94,9 +94,14 @@ enum {
 
 /* Create a context on HIP device `device` (or FNTRS_HOST_ONLY).  It owns the
  * twiddle table (powers of the primitive root 3, Sec. II-A), the locator
- * cache and scratch memory; `workspace_cap_bytes` caps that memory
- * (0 = 4 GiB).  On success *out receives the context.  Errors: FNTRS_E_INVAL
- * (null out, bad device), FNTRS_E_DEVICE, FNTRS_E_NOMEM. */
+ * cache and scratch memory; `workspace_cap_bytes` (0 = 4 GiB) caps the
+ * locator cache, and separately the device blocks the context keeps for
+ * reuse as scratch (four-step passes, batch tables, locator builds).  A call
+ * whose scratch fits in no kept block under the cap allocates it
+ * stream-ordered instead.  Kept blocks are reused in stream order: a call on
+ * another stream first waits (on the device) for the block's last use.  On
+ * success *out receives the context.  Errors: FNTRS_E_INVAL (null out, bad
+ * device), FNTRS_E_DEVICE, FNTRS_E_NOMEM. */
 int fntrs_create(int device, size_t workspace_cap_bytes, fntrs_ctx** out);
 
 /* Destroy a context: waits for the device, frees everything it owns,
@@ -121,8 +126,8 @@ const char* fntrs_last_error(const fntrs_ctx* ctx);
  * interpolated on positions 0..k-1 into k intermediate symbols (the decoder,
  * with the locator of that pattern, which the context builds once and
  * caches), and dst is the transform above of the intermediate symbols, so
- * that dst rows 0..k-1 equal src; the call holds a scratch of
- * batch*k*lanes words of device memory, allocated and freed on `stream`.
+ * that dst rows 0..k-1 equal src; the call holds batch*k*lanes words of
+ * the context's scratch, ordered on `stream`.
  * Errors: FNTRS_E_INVAL, FNTRS_E_DEVICE, FNTRS_E_RANGE (validate flag),
  * FNTRS_E_NOMEM, FNTRS_E_UNSUPPORTED. */
 int fntrs_encode(fntrs_ctx* ctx, uint32_t n, uint32_t k, uint32_t lanes,
@@ -208,8 +213,8 @@ int fntrs_locator_export(fntrs_ctx* ctx, const fntrs_locator_t* loc,
  * overlap.  With FNTRS_SYSTEMATIC (Sec. II-C) the received symbols are those
  * of a systematic codeword (fntrs_encode with FNTRS_SYSTEMATIC): the decoder
  * recovers the k intermediate symbols and transforms them at positions
- * 0..k-1, so dst receives the source; the call holds a scratch of
- * batch*k*lanes words of device memory, allocated and freed on `stream`.
+ * 0..k-1, so dst receives the source; the call holds batch*k*lanes words
+ * of the context's scratch, ordered on `stream`.
  * Errors: FNTRS_E_INVAL, FNTRS_E_DEVICE, FNTRS_E_RANGE, FNTRS_E_NOMEM. */
 int fntrs_decode(fntrs_ctx* ctx, const fntrs_locator_t* loc, uint32_t lanes, uint32_t flags,
                  const uint32_t* recv, size_t ld_recv, size_t stride_recv,
@@ -228,7 +233,7 @@ int fntrs_decode(fntrs_ctx* ctx, const fntrs_locator_t* loc, uint32_t lanes, uin
  * evaluates A' on positions in arithmetic progression (q = r_n^d,
  * a = r_n^s); step 5's S_j = -N'(r_n^(-j-1)) is q = a = r_n^-1.  a and q:
  * nonzero residues; L + M - 1 <= 65536.  Device pointers; asynchronous on
- * `stream`; holds 2(P + batch P lanes) words of stream-ordered scratch.
+ * `stream`; uses 4 P + 2 batch P lanes words of context scratch.
  * Errors: FNTRS_E_INVAL, FNTRS_E_UNSUPPORTED (L + M - 1 > 65536),
  * FNTRS_E_NOMEM, FNTRS_E_DEVICE. */
 int fntrs_chirp_eval(fntrs_ctx* ctx, uint32_t L, uint32_t M, uint32_t a, uint32_t q, const uint32_t* coeffs,

@@ -122,11 +122,9 @@ extern "C" int fntrs_chirp_eval(fntrs_ctx* c, uint32_t L, uint32_t M, uint32_t a
   // scratch: v and its transform (P words each), the two scale tables, u and
   // its transform (batch x P x lanes each)
   const size_t vw = (P + 63) / 64 * 64, uw = (size_t)batch * P * lanes;
-  uint32_t* mem = nullptr;
-  const size_t bytes = (4 * vw + 2 * uw) * 4;
-  if (hipMallocAsync((void**)&mem, bytes, s) != hipSuccess)
-    return fail(c, FNTRS_E_NOMEM, "chirp scratch of %zu bytes", bytes);
-  uint32_t* v = mem;
+  Scratch sc;
+  if (int rc = scratch_acquire(c, (4 * vw + 2 * uw) * 4, s, sc)) return rc;
+  uint32_t* v = reinterpret_cast<uint32_t*>(sc.p);
   uint32_t* vhat = v + vw;
   uint32_t* su = vhat + vw;
   uint32_t* so = su + vw;
@@ -153,6 +151,6 @@ extern "C" int fntrs_chirp_eval(fntrs_ctx* c, uint32_t L, uint32_t M, uint32_t a
   // the inverse transform: the forward one (into u) read at negated indices
   if (!rc) rc = encode_run(c, P, P, lanes, uhat, ld_u, st_u, u, ld_u, st_u, batch, 0, s);
   if (!rc) rc = rows(kGather, u, ld_u, st_u, out, ld_out, stride_out, so, M, "output");
-  (void)hipFreeAsync(mem, s);
+  scratch_release(c, sc, s);
   return rc;
 }

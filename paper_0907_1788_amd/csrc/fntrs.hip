@@ -116,19 +116,24 @@ void stage_release(fntrs_ctx* c) {
 int dev_slot_acquire(fntrs_ctx* c, size_t bytes, fntrs_ctx::DevSlot*& out) {
   constexpr size_t kMaxSlots = 8;
   out = nullptr;
-  auto idle = [](fntrs_ctx::DevSlot& q) { return !q.pending || hipEventQuery(q.ev) == hipSuccess; };
+  auto idle = [](fntrs_ctx::DevSlot& q) {
+    return !q.busy && (!q.pending || hipEventQuery(q.ev) == hipSuccess);
+  };
   for (auto& q : c->dev_slots)   // the smallest idle slot that fits
     if (q.bytes >= bytes && idle(q) && (!out || q.bytes < out->bytes)) out = &q;
-  if (out) return FNTRS_OK;
+  if (out) {
+    out->busy = true;
+    return FNTRS_OK;
+  }
   fntrs_ctx::DevSlot* slot = nullptr;
   if (c->dev_slots.size() < kMaxSlots) {
     c->dev_slots.emplace_back();
     slot = &c->dev_slots.back();
     HIP_TRY(c, hipEventCreateWithFlags(&slot->ev, hipEventDisableTiming));
-  } else {                       // replace the smallest slot once it is idle
-    slot = &c->dev_slots.front();
+  } else {                       // replace the smallest slot no call holds, once it is idle
     for (auto& q : c->dev_slots)
-      if (q.bytes < slot->bytes) slot = &q;
+      if (!q.busy && (!slot || q.bytes < slot->bytes)) slot = &q;
+    if (!slot) return fail(c, FNTRS_E_DEVICE, "every device table slot is held");
     if (slot->pending) HIP_TRY(c, hipEventSynchronize(slot->ev));
     HIP_TRY(c, hipFree(slot->p));
     slot->p = nullptr;
@@ -142,14 +147,92 @@ int dev_slot_acquire(fntrs_ctx* c, size_t bytes, fntrs_ctx::DevSlot*& out) {
   }
   slot->bytes = sz;
   slot->pending = false;
+  slot->busy = true;
   out = slot;
   return FNTRS_OK;
 }
 
 int dev_slot_done(fntrs_ctx* c, fntrs_ctx::DevSlot* slot, hipStream_t s) {
-  HIP_TRY(c, hipEventRecord(slot->ev, s));
+  slot->busy = false;
+  if (hipEventRecord(slot->ev, s) != hipSuccess) {
+    (void)hipStreamSynchronize(s);   // no event: wait here rather than reuse early
+    slot->pending = false;
+    return fail(c, FNTRS_E_DEVICE, "event record after a device table slot");
+  }
   slot->pending = true;
   return FNTRS_OK;
+}
+
+int scratch_acquire(fntrs_ctx* c, size_t bytes, hipStream_t s, Scratch& out) {
+  out = Scratch{};
+  if (bytes == 0) return FNTRS_OK;
+  if (bytes <= kDevSlotMax) {
+    fntrs_ctx::DevSlot* d = nullptr;
+    if (int rc = dev_slot_acquire(c, bytes, d)) return rc;
+    out = Scratch{d->p, 1, d};
+    return FNTRS_OK;
+  }
+  using Blk = fntrs_ctx::WsBlock;
+  auto idle = [](Blk& b) { return !b.busy && (!b.pending || hipEventQuery(b.ev) == hipSuccess); };
+  Blk* best = nullptr;
+  for (auto& b : c->ws)   // the smallest idle block that fits
+    if (b.bytes >= bytes && idle(b) && (!best || b.bytes < best->bytes)) best = &b;
+  if (!best) {            // a new block, if the cap allows
+    constexpr size_t kGrain = size_t(256) << 20;
+    const size_t want = (bytes + kGrain - 1) / kGrain * kGrain;
+    uint8_t* p = nullptr;
+    if (c->ws_held + want <= c->cap && hipMalloc((void**)&p, want) == hipSuccess) {
+      hipEvent_t ev = nullptr;
+      if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipFree(p);
+        return fail(c, FNTRS_E_DEVICE, "event for a workspace block");
+      }
+      c->ws.emplace_back();
+      best = &c->ws.back();
+      best->p = p;
+      best->bytes = want;
+      best->ev = ev;
+      c->ws_held += want;
+    }
+  }
+  if (!best) {            // a block still in use on some stream, after that use
+    for (auto& b : c->ws)
+      if (!b.busy && b.bytes >= bytes && (!best || b.bytes < best->bytes)) best = &b;
+    if (best && best->pending) HIP_TRY(c, hipStreamWaitEvent(s, best->ev, 0));
+  }
+  if (best) {
+    best->busy = true;
+    out = Scratch{best->p, 2, best};
+    return FNTRS_OK;
+  }
+  uint8_t* p = nullptr;   // nothing fits under the cap: stream-ordered memory
+  const hipError_t e = hipMallocAsync((void**)&p, bytes, s);
+  if (e != hipSuccess) return fail(c, FNTRS_E_NOMEM, "scratch of %zu bytes: %s", bytes, hipGetErrorString(e));
+  out = Scratch{p, 3, nullptr};
+  return FNTRS_OK;
+}
+
+void scratch_release(fntrs_ctx* c, Scratch& sc, hipStream_t s) {
+  if (sc.kind == 1) {
+    (void)dev_slot_done(c, static_cast<fntrs_ctx::DevSlot*>(sc.ref), s);
+  } else if (sc.kind == 2) {
+    auto* b = static_cast<fntrs_ctx::WsBlock*>(sc.ref);
+    b->pending = hipEventRecord(b->ev, s) == hipSuccess;
+    if (!b->pending) (void)hipStreamSynchronize(s);   // no event: wait here rather than reuse early
+    b->busy = false;
+  } else if (sc.kind == 3) {
+    (void)hipFreeAsync(sc.p, s);
+  }
+  sc = Scratch{};
+}
+
+void workspace_release(fntrs_ctx* c) {
+  for (auto& b : c->ws) {
+    if (b.p) (void)hipFree(b.p);
+    if (b.ev) (void)hipEventDestroy(b.ev);
+  }
+  c->ws.clear();
+  c->ws_held = 0;
 }
 
 // The configuration of one single call: the size's configuration, or its
@@ -457,16 +540,9 @@ static int build_locators(fntrs_ctx* c, std::vector<fntrs_locator_t*>& Ls, hipSt
   const size_t desc_bytes = (P * sizeof(LocDesc) + 255) / 256 * 256;
   const size_t z_words = round_words(zall.size()), tab_words = round_words(tab.size());
   const size_t tmp_bytes = desc_bytes + (z_words + tab_words + scratch) * 4;
-  uint8_t* tmp = nullptr;
-  fntrs_ctx::DevSlot* slot = nullptr;
-  if (tmp_bytes <= kDevSlotMax) {
-    if (int rc = dev_slot_acquire(c, tmp_bytes, slot)) return rc;
-    tmp = slot->p;
-  } else {
-    hipError_t e = hipMallocAsync((void**)&tmp, tmp_bytes, s);
-    if (e != hipSuccess) return fail(c, FNTRS_E_NOMEM, "locator build buffer of %zu bytes: %s", tmp_bytes,
-                                     hipGetErrorString(e));
-  }
+  Scratch tsc;
+  if (int rc = scratch_acquire(c, tmp_bytes, s, tsc)) return rc;
+  uint8_t* tmp = tsc.p;
   uint32_t* dz = reinterpret_cast<uint32_t*>(tmp + desc_bytes);
   uint32_t* dtab = dz + z_words;
   uint32_t* dscr = dtab + tab_words;
@@ -485,10 +561,7 @@ static int build_locators(fntrs_ctx* c, std::vector<fntrs_locator_t*>& Ls, hipSt
   std::memcpy(img.data(), desc.data(), P * sizeof(LocDesc));
   std::memcpy(img.data() + desc_bytes, zall.data(), zall.size() * 4);
   std::memcpy(img.data() + desc_bytes + z_words * 4, tab.data(), tab.size() * 4);
-  auto release_tmp = [&]() {
-    if (slot) (void)dev_slot_done(c, slot, s);
-    else (void)hipFreeAsync(tmp, s);
-  };
+  auto release_tmp = [&]() { scratch_release(c, tsc, s); };
   auto fail_free = [&](int rc) {
     release_tmp();
     return rc;
@@ -720,12 +793,10 @@ int fntrs::encode_run(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, cons
       HIP_TRY(c, fourstep_encode(f, batch, fixed_scratch, lds, s));
       return FNTRS_OK;
     }
-    uint32_t* sa = nullptr;
-    const size_t bytes = (size_t)batch * n * lds * 4;
-    hipError_t e = hipMallocAsync((void**)&sa, bytes, s);
-    if (e != hipSuccess) return fail(c, FNTRS_E_NOMEM, "scratch of %zu bytes: %s", bytes, hipGetErrorString(e));
-    e = fourstep_encode(f, batch, sa, lds, s);
-    (void)hipFreeAsync(sa, s);
+    Scratch sc;
+    if (int rc = scratch_acquire(c, (size_t)batch * n * lds * 4, s, sc)) return rc;
+    const hipError_t e = fourstep_encode(f, batch, reinterpret_cast<uint32_t*>(sc.p), lds, s);
+    scratch_release(c, sc, s);
     HIP_TRY(c, e);
     return FNTRS_OK;
   }
@@ -762,12 +833,11 @@ int fntrs::decode_run(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, bo
     f.tiles = (lanes + kFourStepTile - 1) / kFourStepTile;
     const uint64_t lds = (uint64_t)f.tiles * kFourStepTile;
     f.vec = aligned16(recv, ld_recv, stride_recv) && aligned16(dst, ld_dst, stride_dst);
-    uint32_t* sa = nullptr;
-    const size_t bytes = (size_t)batch * (n + f.M) * lds * 4;
-    hipError_t e = hipMallocAsync((void**)&sa, bytes, s);
-    if (e != hipSuccess) return fail(c, FNTRS_E_NOMEM, "scratch of %zu bytes: %s", bytes, hipGetErrorString(e));
-    e = fourstep_decode(f, batch, sa, sa + (size_t)batch * n * lds, lds, s);
-    (void)hipFreeAsync(sa, s);
+    Scratch sc;
+    if (int rc = scratch_acquire(c, (size_t)batch * (n + f.M) * lds * 4, s, sc)) return rc;
+    uint32_t* sa = reinterpret_cast<uint32_t*>(sc.p);
+    const hipError_t e = fourstep_decode(f, batch, sa, sa + (size_t)batch * n * lds, lds, s);
+    scratch_release(c, sc, s);
     HIP_TRY(c, e);
     return FNTRS_OK;
   }
@@ -801,18 +871,15 @@ static int systematic_encode_run(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t 
   const uint32_t* fp = first.data();
   fntrs_locator_t* L = nullptr;
   if (int rc = locators_acquire(c, 1, &n, &k, &fp, &k, s, &L)) return rc;
-  uint32_t* mid = nullptr;   // intermediate symbols [batch][k][lanes]
-  const size_t bytes = (size_t)batch * k * lanes * 4;
-  hipError_t e = hipMallocAsync((void**)&mid, bytes, s);
-  int rc = FNTRS_OK;
-  if (e != hipSuccess) {
-    rc = fail(c, FNTRS_E_NOMEM, "intermediate symbols of %zu bytes: %s", bytes, hipGetErrorString(e));
-  } else {
+  Scratch sc;   // intermediate symbols [batch][k][lanes]
+  int rc = scratch_acquire(c, (size_t)batch * k * lanes * 4, s, sc);
+  if (!rc) {
+    uint32_t* mid = reinterpret_cast<uint32_t*>(sc.p);
     rc = decode_run(c, L, lanes, false, src, ld_src, stride_src, mid, lanes, (size_t)k * lanes, batch, s);
     if (!rc)
       rc = encode_run(c, L->n, k, lanes, mid, lanes, (size_t)k * lanes, dst, ld_dst, stride_dst, batch,
                       n < L->n ? n : 0, s);
-    (void)hipFreeAsync(mid, s);
+    scratch_release(c, sc, s);
   }
   L->refs--;
   return rc;
@@ -824,14 +891,12 @@ static int systematic_decode_run(fntrs_ctx* c, const fntrs_locator_t* L, uint32_
                                  const uint32_t* recv, size_t ld_recv, size_t stride_recv, uint32_t* dst,
                                  size_t ld_dst, size_t stride_dst, uint32_t batch, hipStream_t s) {
   const uint32_t n = L->n, k = L->k;
-  uint32_t* mid = nullptr;
-  const size_t bytes = (size_t)batch * k * lanes * 4;
-  hipError_t e = hipMallocAsync((void**)&mid, bytes, s);
-  if (e != hipSuccess)
-    return fail(c, FNTRS_E_NOMEM, "intermediate symbols of %zu bytes: %s", bytes, hipGetErrorString(e));
+  Scratch sc;   // intermediate symbols [batch][k][lanes]
+  if (int rc = scratch_acquire(c, (size_t)batch * k * lanes * 4, s, sc)) return rc;
+  uint32_t* mid = reinterpret_cast<uint32_t*>(sc.p);
   int rc = decode_run(c, L, lanes, full, recv, ld_recv, stride_recv, mid, lanes, (size_t)k * lanes, batch, s);
   if (!rc) rc = encode_run(c, n, k, lanes, mid, lanes, (size_t)k * lanes, dst, ld_dst, stride_dst, batch, k, s);
-  (void)hipFreeAsync(mid, s);
+  scratch_release(c, sc, s);
   return rc;
 }
 
@@ -915,6 +980,7 @@ void fntrs_destroy(fntrs_ctx* c) {
   for (auto& kv : c->sides) drop(kv.second);
   drop(c->capture_side);
   stage_release(c);
+  workspace_release(c);
   if (c->tw) (void)hipFree(c->tw);
   delete c;
 }

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -117,9 +118,23 @@ struct fntrs_ctx {
     uint8_t* p = nullptr;
     size_t bytes = 0;
     hipEvent_t ev = nullptr;
-    bool pending = false;
+    bool pending = false, busy = false;   // busy: held by a call (calls nest)
   };
-  std::vector<DevSlot> dev_slots;
+  std::deque<DevSlot> dev_slots;
+  // reusable device blocks for larger transient buffers (four-step scratch,
+  // big batch tables, locator builds), held up to the workspace cap: a
+  // serving loop then stops allocating once it has seen its largest batch
+  // (new device memory can make the allocating call wait for the GPU).  A
+  // block is busy while a call holds it and pending until the event recorded
+  // after its last use has fired; a pending block is reused in stream order.
+  struct WsBlock {
+    uint8_t* p = nullptr;
+    size_t bytes = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false, busy = false;
+  };
+  std::deque<WsBlock> ws;   // stable addresses: calls nest (systematic, chirp)
+  size_t ws_held = 0;
   // direct systematic encoder: parity matrix per (N, k)
   std::map<std::pair<uint32_t, uint32_t>, fntrs::DirectMat*> parity;
 };
@@ -186,6 +201,19 @@ constexpr size_t kDevSlotMax = size_t(64) << 20;
 // dev_slot_done must follow its last use on stream s.
 int dev_slot_acquire(fntrs_ctx* c, size_t bytes, fntrs_ctx::DevSlot*& out);
 int dev_slot_done(fntrs_ctx* c, fntrs_ctx::DevSlot* slot, hipStream_t s);
+
+// A transient device buffer of a call: a device slot (small tables), a
+// workspace block, or a stream-ordered allocation when no block fits under
+// the cap.  scratch_release must follow its last use on stream s.
+struct Scratch {
+  uint8_t* p = nullptr;
+  int kind = 0;            // 0 none, 1 device slot, 2 workspace block, 3 stream-ordered
+  void* ref = nullptr;
+};
+int scratch_acquire(fntrs_ctx* c, size_t bytes, hipStream_t s, Scratch& out);
+void scratch_release(fntrs_ctx* c, Scratch& sc, hipStream_t s);
+// Frees the workspace blocks (the device must be idle).
+void workspace_release(fntrs_ctx* c);
 
 // The configuration of one single call of size 2^L (see ct_small).
 CtCfg call_cfg(const fntrs_ctx* c, CtCfg cfg, int L, uint32_t lanes, uint64_t per);

@@ -378,19 +378,10 @@ int fntrs_submit(fntrs_ctx* c, const fntrs_job* jobs, uint32_t njobs, void* stre
   for (fntrs_locator_t* L : P.locs) HIP_TRY(c, hipStreamWaitEvent(s, L->ready, 0));
   const size_t blob = align_up(P.blob.size());
   const size_t bytes = blob + P.scratch_elems * 4;
-  uint8_t* mem = nullptr;
-  fntrs_ctx::DevSlot* slot = nullptr;
-  if (bytes && bytes <= kDevSlotMax) {
-    if (int rc = dev_slot_acquire(c, bytes, slot)) return rc;
-    mem = slot->p;
-  } else if (bytes) {
-    hipError_t e = hipMallocAsync((void**)&mem, bytes, s);
-    if (e != hipSuccess) return fail(c, FNTRS_E_NOMEM, "batch workspace of %zu bytes: %s", bytes, hipGetErrorString(e));
-  }
-  auto release = [&]() {
-    if (slot) (void)dev_slot_done(c, slot, s);
-    else if (mem) (void)hipFreeAsync(mem, s);
-  };
+  Scratch sc;
+  if (int rc = scratch_acquire(c, bytes, s, sc)) return rc;
+  uint8_t* mem = sc.p;
+  auto release = [&]() { scratch_release(c, sc, s); };
   if (bytes) {
     if (int rc = upload_async(c, mem, P.blob.data(), P.blob.size(), s)) {
       release();

@@ -7,8 +7,12 @@ k received rows of an erasure pattern -> k source rows) of a codeword of
 * admits waiting requests in arrival order while the device working set
   (input + output + locator state + four-step scratch of every admitted
   request) stays under a byte cap -- memory-based admission;
-* turns everything admitted since the last launch into one batch: the
-  locators of its decode requests are fetched or built together
+* turns what it admits at one time into one batch of at most
+  `max_batch_bytes` of working set (by default the cap over the number of
+  batches in flight): a backlog is served as several batches in flight, not
+  as one batch that takes the whole cap.  Batches of new, larger shapes make
+  the runtime's allocators block, and a blocked loop builds a larger backlog.
+  The locators of a batch's decode requests are fetched or built together
   (fntrs_locator_batch, cached per erasure pattern on the device) and the
   batch is enqueued with one fntrs_submit;
 * keeps up to `max_inflight` batches on the device at once, on rotating
@@ -93,6 +97,7 @@ class Stats:
     mean_batch: float
     peak_bytes: int
     peak_inflight: int
+    host_ms: dict = field(default_factory=dict)   # host time per phase of the loop
 
     @property
     def gbps(self) -> float:
@@ -103,24 +108,29 @@ class Server:
     """Continuous-batching request loop on one GPU (see the module docstring)."""
 
     def __init__(self, ctx: fntrs.Context, mem_cap_bytes: int = 32 << 30, max_inflight: int = 4,
-                 max_batch: int = 256):
+                 max_batch: int = 256, max_batch_bytes: int | None = None):
         import torch
         self.torch = torch
         self.ctx = ctx
         self.cap = mem_cap_bytes
         self.max_inflight = max_inflight
         self.max_batch = max_batch
+        self.max_batch_bytes = mem_cap_bytes // max_inflight if max_batch_bytes is None else max_batch_bytes
         self.streams = [torch.cuda.Stream() for _ in range(max_inflight)]
+        self.host = collections.Counter()
 
     def _launch(self, batch, stream):
         torch = self.torch
+        t0 = time.perf_counter()
         dec = [r for r in batch if r.op == DECODE]
         locs = self.ctx.locators([(r.n, r.k, r.positions) for r in dec], stream=stream) if dec else []
+        t1 = time.perf_counter()
         jobs = []
         with torch.cuda.stream(stream):
             for r in batch:
                 rows = r.n if r.op == ENCODE else r.k
                 r.out = torch.empty((1, rows, r.lanes), dtype=torch.int32, device="cuda")
+        t2 = time.perf_counter()
         li = iter(locs)
         for r in batch:
             if r.op == ENCODE:
@@ -131,6 +141,10 @@ class Server:
         self.ctx.submit(jobs, stream=stream)
         ev = torch.cuda.Event()
         ev.record(stream)
+        t3 = time.perf_counter()
+        self.host["locators"] += t1 - t0
+        self.host["outputs"] += t2 - t1
+        self.host["submit"] += t3 - t2
         return ev, locs
 
     def run(self, requests, keep=None, on_done=None) -> Stats:
@@ -152,12 +166,14 @@ class Server:
         peak_inflight = 0
         nb = 0
         slot = 0
+        self.host.clear()
         t0 = time.perf_counter()
         while pending or queue or inflight:
             now = time.perf_counter() - t0
             while pending and pending[0].arrival <= now:
                 queue.append(pending.popleft())
             # retire finished batches
+            tr = time.perf_counter()
             still = []
             for ev, batch, locs, nbytes in inflight:
                 if ev.query():
@@ -174,6 +190,7 @@ class Server:
                 else:
                     still.append((ev, batch, locs, nbytes))
             inflight = still
+            self.host["retire"] += time.perf_counter() - tr
             # admit and launch what has arrived, as memory and slots allow
             if queue and len(inflight) < self.max_inflight:
                 batch, nbytes = [], 0
@@ -182,6 +199,8 @@ class Server:
                     if need > self.cap:
                         raise ValueError(f"request {queue[0].rid} needs {need} bytes, above the cap {self.cap}")
                     if used + nbytes + need > self.cap:
+                        break
+                    if batch and nbytes + need > self.max_batch_bytes:
                         break
                     r = queue.popleft()
                     r.t_admit = now
@@ -207,7 +226,8 @@ class Server:
         return Stats(completed=len(reqs), payload_bytes=sum(r.payload_bytes for r in reqs), seconds=span,
                      latency_ms={"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                                  "mean": float(lat.mean())},
-                     batches=nb, mean_batch=len(reqs) / max(1, nb), peak_bytes=peak, peak_inflight=peak_inflight)
+                     batches=nb, mean_batch=len(reqs) / max(1, nb), peak_bytes=peak, peak_inflight=peak_inflight,
+                     host_ms={k: round(v * 1e3, 3) for k, v in self.host.items()})
 
 
 def poisson_arrivals(rate_per_s: float, count: int, seed: int) -> np.ndarray:

@@ -129,6 +129,7 @@ struct State {
   };
   std::vector<Cfg> cfg;
   uint64_t ops_run = 0, kernels_run = 0, checks = 0;
+  uint64_t n_malloc = 0, n_malloc_async = 0, n_wait_event = 0;   // call counts
   State() {
     streams.resize(1);   // the null stream
     const size_t span = size_t(1) << 42;   // 4 TiB of address space, touched pages only
@@ -611,6 +612,11 @@ void fakehip_stats(uint64_t* ops, uint64_t* kernels, uint64_t* checks) {
   *kernels = S().kernels_run;
   *checks = S().checks;
 }
+void fakehip_alloc_stats(uint64_t* malloc_calls, uint64_t* malloc_async_calls, uint64_t* wait_event_calls) {
+  *malloc_calls = S().n_malloc;
+  *malloc_async_calls = S().n_malloc_async;
+  *wait_event_calls = S().n_wait_event;
+}
 
 // ------------------------------------------------------------ registration
 void** __hipRegisterFatBinary(const void*) {
@@ -682,6 +688,7 @@ const char* hipGetErrorString(hipError_t e) { return e == hipSuccess ? "no error
 // ------------------------------------------------------------ memory
 hipError_t hipMalloc(void** p, size_t bytes) {
   std::lock_guard<std::mutex> lk(S().mu);
+  ++S().n_malloc;
   *p = (void*)dev_alloc(bytes, 0);
   return *p ? hipSuccess : hipErrorOutOfMemory;
 }
@@ -700,6 +707,7 @@ hipError_t hipFree(void* p) {
 }
 hipError_t hipMallocAsync(void** p, size_t bytes, hipStream_t s) {
   std::lock_guard<std::mutex> lk(S().mu);
+  ++S().n_malloc_async;
   const uintptr_t a = dev_alloc(bytes, 1);
   if (!a) return hipErrorOutOfMemory;
   Op& op = enqueue(sid(s), "hipMallocAsync", nullptr);
@@ -837,6 +845,7 @@ hipError_t hipDeviceSynchronize() {
 }
 hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned int) {
   std::lock_guard<std::mutex> lk(S().mu);
+  ++S().n_wait_event;
   if (!e) return hipErrorInvalidValue;
   const Event& ev = S().events[e->id];
   if (ev.recorded) join(S().streams[sid(s)].clk, ev.clk);

@@ -259,10 +259,13 @@ def main():
     ctx.close()
     ops, kernels, checks = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
     fake.fakehip_stats(ctypes.byref(ops), ctypes.byref(kernels), ctypes.byref(checks))
+    nm, nma, nw = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    fake.fakehip_alloc_stats(ctypes.byref(nm), ctypes.byref(nma), ctypes.byref(nw))
     errs = [fake.fakehip_error_text(i).decode() for i in range(fake.fakehip_errors())]
     print(json.dumps({"errors": errs, "requests": st.completed, "batches": st.batches,
                       "peak_inflight": st.peak_inflight, "ops": ops.value, "kernels": kernels.value,
-                      "checks": checks.value}), flush=True)
+                      "checks": checks.value, "hipMalloc": nm.value, "hipMallocAsync": nma.value,
+                      "hipStreamWaitEvent": nw.value}), flush=True)
 
 
 if __name__ == "__main__":

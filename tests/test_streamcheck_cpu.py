@@ -73,6 +73,8 @@ def test_checker_reports_planted_mistakes(fake, name, expect):
     (4, 0.99, 0.3, 12, 32, 16),      # a tiny cache cap: evictions under load
     (5, 0.50, 0.5, 4, 8192, 0),      # fresh patterns (the load sweep)
     (6, 0.99, 0.0, 8, 8192, 16),     # closed loop: large batches
+    (7, 0.99, 0.0, 8, 4096, 0),      # few scratch blocks: reused across streams while pending
+    (8, 0.995, 0.3, 12, 1024, 16),   # scratch larger than the blocks: stream-ordered fallback
 ])
 def test_served_replay_is_clean(fake, seed, lag, span, inflight, cap_mib, patterns):
     r = run(fake, "--seed", seed, "--lag", lag, "--span-s", span, "--max-inflight", inflight,
@@ -80,3 +82,15 @@ def test_served_replay_is_clean(fake, seed, lag, span, inflight, cap_mib, patter
     assert r["requests"] == 2000
     assert r["kernels"] > 1000
     assert r["errors"] == [], r["errors"][:5]
+
+
+def test_served_replay_keeps_scratch_blocks(fake):
+    """Under a cap that holds the batches' scratch, the context keeps and
+    reuses its scratch blocks: after the first batches no call allocates
+    stream-ordered memory (new device memory can make the allocating call wait
+    for the GPU, which stalls a serving loop)."""
+    r = run(fake, "--seed", 9, "--lag", 0.99, "--span-s", 0.0, "--max-inflight", 8, "--ctx-cap-mib", 8192,
+            "--pattern-pool", 0, "--requests", 2000)
+    assert r["errors"] == [], r["errors"][:5]
+    assert r["batches"] > 40
+    assert r["hipMallocAsync"] <= 8, r
