@@ -29,6 +29,7 @@ __device__ __forceinline__ FNTRS_GLOBAL T* gptr(T* p) {
 
 // 16-byte vector of the global accesses.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 // A trivially copyable struct read from global memory word by word.
 template <class T>

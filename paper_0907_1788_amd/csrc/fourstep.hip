@@ -36,7 +36,7 @@ hipError_t dec4_any(int LB, const FourStepArgs& a, uint32_t blocks, hipStream_t 
 
 template <int LB1, int LB2>
 hipError_t dec2(const FourStepArgs& a, uint32_t blocks, hipStream_t s) {
-  return launch(fs::k4_dec2<LB1, LB2>, fs::Geo<LB1>::LDS_BYTES, blocks, a, s);
+  return launch(fs::k4_dec2<LB1, LB2>, fs::lds_with_tables<LB1>(), blocks, a, s);
 }
 
 // K2 for pass-B size 2^LB1 (n / 256) and FNT_M pass-A size 2^LB2 (M / 256).
@@ -57,55 +57,72 @@ hipError_t dec2_any(int LB1, int LB2, const FourStepArgs& a, uint32_t blocks, hi
 // FNT_n, K2 its size-N1 passes B and the size-M/256 passes A of FNT_M, K3 the
 // size-256 passes B of FNT_M, the product with the locator's transform and
 // the size-256 passes A of the inverse FNT_M, K4 its size-M/256 passes B.
+// sa holds batch*n*lds_ words and sb batch*M*lds_ (lds_ = tiles * kT), both
+// used tile-major.
 hipError_t fourstep_decode(const FourStepArgs& base, uint32_t batch, uint32_t* sa, uint32_t* sb, uint64_t lds_,
                            hipStream_t s) {
   const uint32_t tiles = base.tiles;
-  const uint64_t ld = lds_;
   if (base.logn < 14 || base.logn > 16) return hipErrorInvalidValue;
+  if (lds_ != (uint64_t)tiles * fs::kT) return hipErrorInvalidValue;
   const int LB1 = base.logn - 8;
-  FourStepArgs a = base;
+  const uint64_t T = fs::kT;
+  // scratch of `rows` rows, tile-major
+  auto scr_in = [&](FourStepArgs& f, const uint32_t* p, uint64_t rows) {
+    f.in = p; f.ld_in = T; f.tstride_in = rows * T; f.stride_in = tiles * rows * T;
+  };
+  auto scr_out = [&](FourStepArgs& f, uint32_t* p, uint64_t rows) {
+    f.out = p; f.ld_out = T; f.tstride_out = rows * T; f.stride_out = tiles * rows * T;
+  };
+  FourStepArgs user = base;   // the caller's buffers are row-major
+  user.tstride_in = T;
+  user.tstride_out = T;
   // K1: recv -> sa (n rows)
-  a.out = sa; a.ld_out = ld; a.stride_out = ld * a.n;
+  FourStepArgs a = user;
+  scr_out(a, sa, a.n);
   a.subs = a.n >> 8;
-  FNTRS_TRY(launch(fs::k4_dec1<8>, fs::Geo<8>::LDS_BYTES, tiles * a.subs * batch, a, s));
+  FNTRS_TRY(launch(fs::k4_dec1<8>, fs::lds_with_tables<8>(), tiles * a.subs * batch, a, s));
   if (base.k == base.n) {
     // erasure-free: the inverse transform's pass B writes the source
-    FourStepArgs b = base;
-    b.in = sa; b.ld_in = ld; b.stride_in = ld * a.n;
+    FourStepArgs b = user;
+    scr_in(b, sa, base.n);
     b.subs = 256;
     b.M = base.n;
     return dec4_any(LB1, b, tiles * b.subs * batch, s);
   }
   const int LB2 = base.logm - 8;
   // K2: sa -> sb (M rows)
-  FourStepArgs b = base;
-  b.in = sa; b.ld_in = ld; b.stride_in = ld * a.n;
-  b.out = sb; b.ld_out = ld; b.stride_out = ld * base.M;
+  FourStepArgs b = user;
+  scr_in(b, sa, base.n);
+  scr_out(b, sb, base.M);
   b.subs = 256;
   FNTRS_TRY(dec2_any(LB1, LB2, b, tiles * b.subs * batch, s));
   // K3: sb -> sa (M rows)
-  FourStepArgs c = base;
-  c.in = sb; c.ld_in = ld; c.stride_in = ld * base.M;
-  c.out = sa; c.ld_out = ld; c.stride_out = ld * a.n;
+  FourStepArgs c = user;
+  scr_in(c, sb, base.M);
+  scr_out(c, sa, base.M);
   c.subs = base.M >> 8;
-  FNTRS_TRY(launch(fs::k4_dec3, fs::Geo<8>::LDS_BYTES, tiles * c.subs * batch, c, s));
+  FNTRS_TRY(launch(fs::k4_dec3, fs::lds_with_tables<8>(), tiles * c.subs * batch, c, s));
   // K4: sa -> dst
-  FourStepArgs d = base;
-  d.in = sa; d.ld_in = ld; d.stride_in = ld * a.n;
+  FourStepArgs d = user;
+  scr_in(d, sa, base.M);
   d.subs = 256;
   return dec4_any(LB2, d, tiles * d.subs * batch, s);
 }
 
 // Encoder as one FNT_n of the zero-padded source, n = 2^14 .. 2^16, through
-// one scratch buffer of n rows.
+// one scratch buffer of batch*n*lds_ words (lds_ = tiles * kT), tile-major.
 hipError_t fourstep_encode(const FourStepArgs& base, uint32_t batch, uint32_t* sa, uint64_t lds_, hipStream_t s) {
   if (base.logn < 14 || base.logn > 16) return hipErrorInvalidValue;
+  if (lds_ != (uint64_t)base.tiles * fs::kT) return hipErrorInvalidValue;
+  const uint64_t T = fs::kT, rows = base.n;
   FourStepArgs a = base;
-  a.out = sa; a.ld_out = lds_; a.stride_out = lds_ * a.n;
+  a.tstride_in = T;
+  a.out = sa; a.ld_out = T; a.tstride_out = rows * T; a.stride_out = base.tiles * rows * T;
   a.subs = a.n >> 8;
-  FNTRS_TRY(launch(fs::k4_enc1, fs::Geo<8>::LDS_BYTES, base.tiles * a.subs * batch, a, s));
+  FNTRS_TRY(launch(fs::k4_enc1, fs::lds_with_tables<8>(), base.tiles * a.subs * batch, a, s));
   FourStepArgs b = base;
-  b.in = sa; b.ld_in = lds_; b.stride_in = lds_ * a.n;
+  b.in = sa; b.ld_in = T; b.tstride_in = rows * T; b.stride_in = base.tiles * rows * T;
+  b.tstride_out = T;
   b.subs = 256;
   switch (base.logn) {
     case 14: return launch(fs::k4_enc2<6>, fs::Geo<6>::LDS_BYTES, base.tiles * b.subs * batch, b, s);

@@ -23,18 +23,28 @@ namespace fntrs {
 
 namespace fs {
 
-constexpr int kT = 32;       // lanes per tile
-constexpr int kNT = 256;     // threads per workgroup
+constexpr int kT = kFourStepTile;   // lanes per tile
+#ifndef FNTRS_FS_THREADS
+#define FNTRS_FS_THREADS 256
+#endif
+#ifndef FNTRS_FS_V
+#define FNTRS_FS_V 2
+#endif
+constexpr int kNT = FNTRS_FS_THREADS;   // threads per workgroup
 // Two lanes per thread: a 256-point pass then has an item for every thread
 // (with four, half the threads would idle), and a ragged lane tail wastes
 // less of a vector.
-constexpr int kV = 2;
+constexpr int kV = FNTRS_FS_V;
 
 template <int L>
 using Geo = ct::Geo<L, kT, kNT, kV>;
 
-// scratch row stride: every scratch buffer is [block][row][lane], ld = lanes
-// rounded up to the tile, rows = N.
+// Buffers are addressed per lane tile: element (block b, row r, lane
+// tile*kT + l) lies at b*stride + tile*tstride + r*ld + l.  Input and output
+// buffers are row-major (tstride = kT, ld = lanes); scratch is tile-major
+// ([block][tile][row][kT]: tstride = rows*kT, ld = kT), so a workgroup's
+// rows of one tile lie in one contiguous region of rows*128 bytes instead of
+// being spread over the whole buffer at a stride of ld*4 bytes.
 
 // Decodes blockIdx into (lane tile, sub-transform, block).
 struct Work {
@@ -64,16 +74,46 @@ __device__ __forceinline__ void zero_item(int32_t (&x)[V]) {
   for (int v = 0; v < V; ++v) x[v] = 0;
 }
 
-// Generic global loader for the first DIT pass: position p of the size-2^L
-// sub-transform holds input index i = bitrev(p); `row(i)` gives the row to
-// read (or ~0u for a zero), `scale(i)` a per-row multiplier (0 = none).
-// The reads of an item go out in three rounds -- the row descriptors (which
-// may themselves be reads), then every row with no branch (a zero position
-// reads row 0, which exists in every input, and is discarded), then the
-// scaling -- so each round waits once for the whole item.
-template <int L, class RowFn>
+// Scratch rows move as whole vectors of kV lanes: every lane tile of a
+// scratch buffer is complete (the first kernel writes its padding lanes,
+// which it reads as zero), vectors are kV-aligned, and scratch values stay
+// in the lazy range (|v| < 2^17) instead of being made canonical.
+__device__ __forceinline__ void scratch_get(const uint32_t* p, int32_t (&x)[kV]) {
+  if constexpr (kV == 2) {
+    const u32x2 t = *(const FNTRS_GLOBAL u32x2*)gptr(p);
+    x[0] = (int32_t)t.x; x[1] = (int32_t)t.y;
+  } else {
+#pragma unroll
+    for (int v = 0; v < kV; ++v) x[v] = (int32_t)gptr(p)[v];
+  }
+}
+__device__ __forceinline__ void scratch_put(uint32_t* p, const int32_t (&x)[kV]) {
+  if constexpr (kV == 2) {
+    const u32x2 t = {(uint32_t)x[0], (uint32_t)x[1]};
+    *(FNTRS_GLOBAL u32x2*)gptr(p) = t;
+  } else {
+#pragma unroll
+    for (int v = 0; v < kV; ++v) gptr(p)[v] = (uint32_t)x[v];
+  }
+}
+
+// Where a loader's rows come from and what it does to them:
+//   kScratch  - a tile-major scratch buffer (row stride kT), values as read;
+//   kZeros    - the caller's input; rows the row function maps to ~0 are zero;
+//   kWeighted - the caller's input times a per-row weight (0: the row is
+//               erased and reads as zero; the row function then names any
+//               existing row).
+enum LoadKind { kScratch = 0, kZeros = 1, kWeighted = 2 };
+
+// Global loader for the first DIT pass: position p of the size-2^L
+// sub-transform holds input index i = bitrev(p); `row(i, w)` gives the row to
+// read and (kWeighted) its weight.  The reads of an item go out in three
+// rounds -- the row descriptors (which may themselves be reads), then every
+// row with no branch, then the weights -- so each round waits once for the
+// whole item.
+template <int L, int KIND, class RowFn>
 struct GLoad {
-  const uint32_t* base;   // block base + lane0
+  const uint32_t* base;   // block base + lane tile
   uint64_t ld;
   uint32_t lane0, lanes;
   bool vec;
@@ -85,34 +125,44 @@ struct GLoad {
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c) {
       const uint32_t i = ib | (bitrev((uint32_t)c, B) << (L - B));
-      w[c] = 0;
+      w[c] = 1;
       r[c] = rowf(i, w[c]);
     }
 #pragma unroll
-    for (int c = 0; c < (1 << B); ++c)
-      ct::load_lanes<kV, WHOLE>(rowp(base, ld, r[c] == ~0ull ? 0 : r[c], g), lane0 + g * kV, lanes, x[c]);
+    for (int c = 0; c < (1 << B); ++c) {
+      if constexpr (KIND == kScratch) {
+        scratch_get(base + r[c] * kT + g * kV, x[c]);
+      } else {
+        const uint64_t rr = (KIND == kZeros && r[c] == ~0ull) ? 0 : r[c];
+        ct::load_lanes<kV, WHOLE>(rowp(base, ld, rr, g), lane0 + g * kV, lanes, x[c]);
+      }
+    }
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c) {
 #pragma unroll
-      for (int v = 0; v < kV; ++v)
-        x[c][v] = r[c] == ~0ull ? 0 : (w[c] ? (int32_t)ct::mulc((uint32_t)x[c][v], w[c]) : x[c][v]);
+      for (int v = 0; v < kV; ++v) {
+        if constexpr (KIND == kZeros) x[c][v] = r[c] == ~0ull ? 0 : x[c][v];
+        if constexpr (KIND == kWeighted) x[c][v] = ct::mulw(x[c][v], w[c]);
+      }
     }
   }
   template <int B, uint32_t H>
   __device__ __forceinline__ void item(uint32_t pb, uint32_t g, int32_t (&x)[1 << B][kV]) {
     static_assert(H == 1, "the first DIT pass has stride 1");
     const uint32_t ib = bitrev(pb, L);
-    if (whole_vector<kV>(lane0 + g * kV, lanes, vec)) rows<B, true>(ib, g, x);
+    if (KIND == kScratch || whole_vector<kV>(lane0 + g * kV, lanes, vec)) rows<B, true>(ib, g, x);
     else rows<B, false>(ib, g, x);
   }
 };
 
-// Generic global storer: position p holds output index m = p (natural, DIT)
-// or m = bitrev(p) (DIF, REV); `dest(m, w)` gives the row (or ~0 to drop) and
-// a multiplier w (0 = none) applied before the store.  The multipliers of an
-// item (table reads) are all read before its first store: a read placed after
-// a store could not be moved above it, and would wait on every row.
-template <int L, bool REV, class DestFn>
+// Global storer: position p holds output index m = p (natural, DIT) or
+// m = bitrev(p) (DIF, REV); `dest(m, w)` gives the row and, for a scratch
+// destination, the twiddle w it is multiplied by (lazy result) before the
+// store; for the caller's output it gives the row or ~0 (drop), and values
+// are stored canonical.  The twiddles of an item (table reads) are all read
+// before its first store: a read placed after a store could not be moved
+// above it, and would wait on every row.
+template <int L, bool REV, bool SCRATCH, class DestFn>
 struct GStore {
   uint32_t* base;
   uint64_t ld;
@@ -131,16 +181,20 @@ struct GStore {
     }
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c) {
-      if (r[c] == ~0ull) continue;
-      int32_t y[kV];
+      if constexpr (SCRATCH) {
+        int32_t y[kV];
 #pragma unroll
-      for (int v = 0; v < kV; ++v) y[v] = w[c] ? ct::mulc(ct::canon(x[c][v]), w[c]) : x[c][v];
-      ct::store_lanes<kV, WHOLE>(const_cast<uint32_t*>(rowp(base, ld, r[c], g)), lane0 + g * kV, lanes, y);
+        for (int v = 0; v < kV; ++v) y[v] = ct::mulw(x[c][v], w[c]);
+        scratch_put(base + r[c] * kT + g * kV, y);
+      } else {
+        if (r[c] == ~0ull) continue;
+        ct::store_lanes<kV, WHOLE>(const_cast<uint32_t*>(rowp(base, ld, r[c], g)), lane0 + g * kV, lanes, x[c]);
+      }
     }
   }
   template <int B, uint32_t H>
   __device__ __forceinline__ void item(uint32_t pb, uint32_t g, int32_t (&x)[1 << B][kV]) {
-    if (whole_vector<kV>(lane0 + g * kV, lanes, vec)) rows<B, H, true>(pb, g, x);
+    if (SCRATCH || whole_vector<kV>(lane0 + g * kV, lanes, vec)) rows<B, H, true>(pb, g, x);
     else rows<B, H, false>(pb, g, x);
   }
 };
@@ -152,6 +206,15 @@ __device__ __forceinline__ uint32_t tw4(const FourStepArgs& a, bool inv, uint32_
   return inv ? gptr(a.twi)[idx] : gptr(a.tw)[idx];
 }
 
+// Per-workgroup tables of the per-row factors of a tile (decoder weights and
+// rows, split twiddles, the locator's transform): each word is read from
+// global memory once per workgroup, one word per thread, into LDS behind the
+// tile, instead of by every lane group at every row of its items -- those
+// broadcast reads would otherwise keep the vector memory pipeline busy.
+constexpr uint32_t kTabWords = 3 * 256;
+template <int L>
+constexpr uint32_t lds_with_tables() { return Geo<L>::LDS_BYTES + kTabWords * 4; }
+
 // ------------------------------------------------------------------ kernels
 // Decoder K1: inverse FNT_n pass A (N1 = n/256, N2 = 256).  Input index
 // i2 -> position z = i1 + N1 i2 with weight wfull[z] (0 = erased).  Output
@@ -162,20 +225,26 @@ __global__ void __launch_bounds__(kNT) k4_dec1(FourStepArgs a) {
   extern __shared__ uint32_t lds[];
   const Work wk = work_of(a);
   const uint32_t i1 = wk.sub, N1 = a.n >> LA;
+  // the weights and rows are read where the first pass needs them (a table
+  // would put a barrier between two global reads); the twiddles of the
+  // last pass come from a table read after the first barrier
+  uint32_t* t_tw = lds + Gm::LDS_BYTES / 4;   // w_n^-(i1 m2)
+  for (uint32_t t = threadIdx.x; t < (1u << LA); t += kNT) t_tw[t] = tw4(a, true, i1 * t, a.logn);
   auto rowf = [&](uint32_t i2, uint32_t& w) -> uint64_t {
     const uint32_t z = i1 + N1 * i2;
-    w = gptr(a.wfull)[z];
+    w = gptr(a.wfull)[z];   // 0: erased (the row read is then discarded)
     const uint32_t r = a.full ? z : gptr(a.ridx)[z];
-    return w ? (uint64_t)r : ~0ull;
+    return w ? (uint64_t)r : 0;
   };
   auto destf = [&](uint32_t m2, uint32_t& w) -> uint64_t {
-    w = tw4(a, true, i1 * m2, a.logn);
+    w = t_tw[m2];
     return (uint64_t)i1 * (1u << LA) + m2;
   };
-  GLoad<LA, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.lane0, a.ld_in, wk.lane0, a.lanes, a.vec != 0, rowf};
+  GLoad<LA, kWeighted, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.tile * a.tstride_in, a.ld_in, wk.lane0,
+                                          a.lanes, a.vec != 0, rowf};
   ct::LdsLoad<kV, Gm::G> lm{lds};
   ct::LdsStore<kV, Gm::G, false> sm{lds};
-  GStore<LA, false, decltype(destf)> sl{a.out + wk.blk * a.stride_out + wk.lane0, a.ld_out, wk.lane0, a.lanes,
+  GStore<LA, false, true, decltype(destf)> sl{a.out + wk.blk * a.stride_out + wk.tile * a.tstride_out, a.ld_out, wk.lane0, a.lanes,
                                         a.vec != 0, destf};
   using TW = typename Gm::TwType;
   const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
@@ -210,21 +279,23 @@ __global__ void __launch_bounds__(kNT) k4_dec2(FourStepArgs a) {
   extern __shared__ uint32_t lds[];
   const Work wk = work_of(a);
   const uint32_t m2 = wk.sub;
+  uint32_t* t_tw = lds + Gm::LDS_BYTES / 4;   // w_M^(m2 mp), read after the first barrier
+  for (uint32_t t = threadIdx.x; t < (1u << LB2); t += kNT) t_tw[t] = tw4(a, false, m2 * t, a.logm);
   auto rowf = [&](uint32_t i1, uint32_t& w) -> uint64_t {
     w = 0;
     return (uint64_t)i1 * 256u + m2;
   };
   auto destf = [&](uint32_t mp, uint32_t& w) -> uint64_t {
-    w = tw4(a, false, m2 * mp, a.logm);
+    w = t_tw[mp];
     return (uint64_t)m2 * (1u << LB2) + mp;
   };
-  GLoad<LB1, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.lane0, a.ld_in, wk.lane0, a.lanes, a.vec != 0,
+  GLoad<LB1, kScratch, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.tile * a.tstride_in, a.ld_in, wk.lane0, a.lanes, a.vec != 0,
                                 rowf};
   ct::LdsLoad<kV, Gm::G> ll{lds};
   ct::LdsStore<kV, Gm::G, false> sl{lds};
   ct::LdsStore<kV, Gm::G, true> slf{lds};
   MaskStore<Gm::G> ms{lds, m2, a.k};
-  GStore<LB2, true, decltype(destf)> sg{a.out + wk.blk * a.stride_out + wk.lane0, a.ld_out, wk.lane0, a.lanes,
+  GStore<LB2, true, true, decltype(destf)> sg{a.out + wk.blk * a.stride_out + wk.tile * a.tstride_out, a.ld_out, wk.lane0, a.lanes,
                                         a.vec != 0, destf};
   using TW = typename Gm::TwType;
   const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
@@ -233,19 +304,19 @@ __global__ void __launch_bounds__(kNT) k4_dec2(FourStepArgs a) {
 }
 
 // LDS storer of the product: natural index m1' of FNT_M pass B with
-// sub = m2' -> times ahat[m2' + (M/256) m1'] (which carries M^-1), folded.
+// sub = m2' -> times ahat[m2' + (M/256) m1'] (which carries M^-1); the lazy
+// product is below 2^17 in magnitude.
 template <int G>
 struct AhatStore {
   uint32_t* lds;
-  const uint32_t* ahat;
-  uint32_t m2p, rows2;   // rows2 = M / 256
+  const uint32_t* t_ah;   // ahat[m2' + (M/256) m1'] by m1' (the workgroup's table)
   template <int B, uint32_t H>
   __device__ __forceinline__ void item(uint32_t pb, uint32_t g, int32_t (&x)[1 << B][kV]) {
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c) {
-      const uint32_t h = gptr(ahat)[m2p + rows2 * (pb + c * H)];
+      const uint32_t h = t_ah[pb + c * H];
 #pragma unroll
-      for (int v = 0; v < kV; ++v) x[c][v] = ct::mulc(ct::canon(x[c][v]), h);
+      for (int v = 0; v < kV; ++v) x[c][v] = ct::mulw(x[c][v], h);
     }
     ct::lds_item_put<B, kV, G, H>(lds, pb, g, x);
   }
@@ -259,20 +330,27 @@ __global__ void __launch_bounds__(kNT) k4_dec3(FourStepArgs a) {
   extern __shared__ uint32_t lds[];
   const Work wk = work_of(a);
   const uint32_t m2p = wk.sub, rows2 = a.M >> 8;
+  uint32_t* t_ah = lds + Gm::LDS_BYTES / 4;   // read after the first barrier
+  uint32_t* t_tw = t_ah + 256;                // w_M^-(m2' m2'')
+  for (uint32_t t = threadIdx.x; t < 256u; t += kNT) {
+    t_ah[t] = gptr(a.ahat)[m2p + rows2 * t];
+    t_tw[t] = tw4(a, true, m2p * t, a.logm);
+  }
   auto rowf = [&](uint32_t i1p, uint32_t& w) -> uint64_t {
     w = 0;
     return (uint64_t)i1p * rows2 + m2p;
   };
   auto destf = [&](uint32_t m2pp, uint32_t& w) -> uint64_t {
-    w = tw4(a, true, m2p * m2pp, a.logm);
+    w = t_tw[m2pp];
     return (uint64_t)m2p * 256u + m2pp;
   };
-  GLoad<8, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.lane0, a.ld_in, wk.lane0, a.lanes, a.vec != 0, rowf};
+  GLoad<8, kScratch, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.tile * a.tstride_in, a.ld_in, wk.lane0,
+                                        a.lanes, a.vec != 0, rowf};
   ct::LdsLoad<kV, Gm::G> ll{lds};
   ct::LdsStore<kV, Gm::G, false> sl{lds};
   ct::LdsStore<kV, Gm::G, true> slf{lds};
-  AhatStore<Gm::G> ah{lds, a.ahat, m2p, rows2};
-  GStore<8, true, decltype(destf)> sg{a.out + wk.blk * a.stride_out + wk.lane0, a.ld_out, wk.lane0, a.lanes,
+  AhatStore<Gm::G> ah{lds, t_ah};
+  GStore<8, true, true, decltype(destf)> sg{a.out + wk.blk * a.stride_out + wk.tile * a.tstride_out, a.ld_out, wk.lane0, a.lanes,
                                       a.vec != 0, destf};
   using TW = typename Gm::TwType;
   const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
@@ -297,11 +375,11 @@ __global__ void __launch_bounds__(kNT) k4_dec4(FourStepArgs a) {
     const uint32_t m = m2 + 256u * m1;
     return m < a.k ? (uint64_t)m : ~0ull;
   };
-  GLoad<LB, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.lane0, a.ld_in, wk.lane0, a.lanes, a.vec != 0,
-                               rowf};
+  GLoad<LB, kScratch, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.tile * a.tstride_in, a.ld_in, wk.lane0,
+                                         a.lanes, a.vec != 0, rowf};
   ct::LdsLoad<kV, Gm::G> ll{lds};
   ct::LdsStore<kV, Gm::G, false> sl{lds};
-  GStore<LB, false, decltype(destf)> sg{a.out + wk.blk * a.stride_out + wk.lane0, a.ld_out, wk.lane0, a.lanes,
+  GStore<LB, false, false, decltype(destf)> sg{a.out + wk.blk * a.stride_out + wk.tile * a.tstride_out, a.ld_out, wk.lane0, a.lanes,
                                         a.vec != 0, destf};
   using TW = typename Gm::TwType;
   const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
@@ -316,19 +394,22 @@ __global__ void __launch_bounds__(kNT) k4_enc1(FourStepArgs a) {
   extern __shared__ uint32_t lds[];
   const Work wk = work_of(a);
   const uint32_t i1 = wk.sub, N1 = a.n >> 8;
+  uint32_t* t_tw = lds + Gm::LDS_BYTES / 4;   // w_n^(i1 m2), read after the first barrier
+  for (uint32_t t = threadIdx.x; t < 256u; t += kNT) t_tw[t] = tw4(a, false, i1 * t, a.logn);
   auto rowf = [&](uint32_t i2, uint32_t& w) -> uint64_t {
     w = 0;
     const uint32_t j = i1 + N1 * i2;
     return j < a.k ? (uint64_t)j : ~0ull;
   };
   auto destf = [&](uint32_t m2, uint32_t& w) -> uint64_t {
-    w = tw4(a, false, i1 * m2, a.logn);
+    w = t_tw[m2];
     return (uint64_t)i1 * 256u + m2;
   };
-  GLoad<8, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.lane0, a.ld_in, wk.lane0, a.lanes, a.vec != 0, rowf};
+  GLoad<8, kZeros, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.tile * a.tstride_in, a.ld_in, wk.lane0,
+                                      a.lanes, a.vec != 0, rowf};
   ct::LdsLoad<kV, Gm::G> lm{lds};
   ct::LdsStore<kV, Gm::G, false> sm{lds};
-  GStore<8, false, decltype(destf)> sl{a.out + wk.blk * a.stride_out + wk.lane0, a.ld_out, wk.lane0, a.lanes,
+  GStore<8, false, true, decltype(destf)> sl{a.out + wk.blk * a.stride_out + wk.tile * a.tstride_out, a.ld_out, wk.lane0, a.lanes,
                                        a.vec != 0, destf};
   using TW = typename Gm::TwType;
   const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
@@ -352,10 +433,11 @@ __global__ void __launch_bounds__(kNT) k4_enc2(FourStepArgs a) {
     const uint32_t r = m2 + 256u * m1;
     return (a.rows_out && r >= a.rows_out) ? ~0ull : (uint64_t)r;
   };
-  GLoad<LB, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.lane0, a.ld_in, wk.lane0, a.lanes, a.vec != 0, rowf};
+  GLoad<LB, kScratch, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.tile * a.tstride_in, a.ld_in, wk.lane0,
+                                         a.lanes, a.vec != 0, rowf};
   ct::LdsLoad<kV, Gm::G> lm{lds};
   ct::LdsStore<kV, Gm::G, false> sm{lds};
-  GStore<LB, false, decltype(destf)> sl{a.out + wk.blk * a.stride_out + wk.lane0, a.ld_out, wk.lane0, a.lanes,
+  GStore<LB, false, false, decltype(destf)> sl{a.out + wk.blk * a.stride_out + wk.tile * a.tstride_out, a.ld_out, wk.lane0, a.lanes,
                                        a.vec != 0, destf};
   using TW = typename Gm::TwType;
   const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);

@@ -9,7 +9,10 @@ namespace fntrs {
 
 
 // Lanes per tile of the four-step kernels.
-constexpr int kFourStepTile = 32;
+#ifndef FNTRS_FS_TILE
+#define FNTRS_FS_TILE 32
+#endif
+constexpr int kFourStepTile = FNTRS_FS_TILE;
 // Transforms of 2^kFourStepMinLog points or more run as four-step passes:
 // a single-pass tile of one such lane-transform fills the LDS with 1 or 2
 // lanes, whose 4- or 8-byte row segments waste most of each HBM burst.

@@ -63,6 +63,7 @@ struct FourStepArgs {
   int logn, logm;
   uint32_t full, tiles, subs, vec;   // subs: sub-transforms per block
   uint32_t rows_out;                 // encoder: only rows < rows_out of out are written (0: all n)
+  uint64_t tstride_in, tstride_out;  // elements between lane tiles (set by the four-step launchers)
 };
 
 // One erasure pattern of a locator batch: where its positions come from,

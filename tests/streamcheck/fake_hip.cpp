@@ -332,8 +332,18 @@ void model_fourstep(Op& x, const std::string& base, const FourStepArgs& a, uint6
     error("no model of four-step kernel " + base);
     return;
   }
-  touch(x, (uintptr_t)a.in, span_words(batch, a.stride_in, rin, a.ld_in, a.lanes) * 4, false, "in");
-  touch(x, (uintptr_t)a.out, span_words(batch, a.stride_out, rout, a.ld_out, a.lanes) * 4, true, "out");
+  // element (b, row, tile*T + l) lies at b*stride + tile*tstride + row*ld + l:
+  // row-major buffers have tstride = T (the span of all lanes), tile-major
+  // scratch has tstride = rows*T and holds whole tiles of T lanes
+  constexpr uint64_t T = 32;
+  auto span = [&](uint64_t stride, uint64_t tstride, uint64_t rows, uint64_t ld) -> size_t {
+    if (tstride == T) return span_words(batch, stride, rows, ld, a.lanes);
+    if (!batch || !rows) return 0;
+    if (tstride < rows * ld) error(x.what + ": lane tiles of a tile-major buffer overlap");
+    return (batch - 1) * stride + (uint64_t)(a.tiles - 1) * tstride + (rows - 1) * ld + T;
+  };
+  touch(x, (uintptr_t)a.in, span(a.stride_in, a.tstride_in, rin, a.ld_in) * 4, false, "in");
+  touch(x, (uintptr_t)a.out, span(a.stride_out, a.tstride_out, rout, a.ld_out) * 4, true, "out");
   model_tw(x, a.tw, a.twi);
 }
 
