@@ -99,7 +99,8 @@ __device__ __forceinline__ void scratch_put(uint32_t* p, const int32_t (&x)[kV])
 
 // Where a loader's rows come from and what it does to them:
 //   kScratch  - a tile-major scratch buffer (row stride kT), values as read;
-//   kZeros    - the caller's input; rows the row function maps to ~0 are zero;
+//   kZeros    - the caller's input; rows the row function maps to ~0 are zero
+//               and not read;
 //   kWeighted - the caller's input times a per-row weight (0: the row is
 //               erased and reads as zero; the row function then names any
 //               existing row).
@@ -108,9 +109,9 @@ enum LoadKind { kScratch = 0, kZeros = 1, kWeighted = 2 };
 // Global loader for the first DIT pass: position p of the size-2^L
 // sub-transform holds input index i = bitrev(p); `row(i, w)` gives the row to
 // read and (kWeighted) its weight.  The reads of an item go out in three
-// rounds -- the row descriptors (which may themselves be reads), then every
-// row with no branch, then the weights -- so each round waits once for the
-// whole item.
+// rounds -- the row descriptors (which may themselves be reads), then the
+// rows, then the weights -- so each round waits once for the
+// whole item (zero rows of kZeros excepted).
 template <int L, int KIND, class RowFn>
 struct GLoad {
   const uint32_t* base;   // block base + lane tile
@@ -132,18 +133,22 @@ struct GLoad {
     for (int c = 0; c < (1 << B); ++c) {
       if constexpr (KIND == kScratch) {
         scratch_get(base + r[c] * kT + g * kV, x[c]);
+      } else if constexpr (KIND == kZeros) {
+        // zero rows (the encoder's padding: the top rows of every
+        // sub-transform, a whole wave at a time) issue no read
+        if (r[c] != ~0ull) ct::load_lanes<kV, WHOLE>(rowp(base, ld, r[c], g), lane0 + g * kV, lanes, x[c]);
+        else
+#pragma unroll
+          for (int v = 0; v < kV; ++v) x[c][v] = 0;
       } else {
-        const uint64_t rr = (KIND == kZeros && r[c] == ~0ull) ? 0 : r[c];
-        ct::load_lanes<kV, WHOLE>(rowp(base, ld, rr, g), lane0 + g * kV, lanes, x[c]);
+        ct::load_lanes<kV, WHOLE>(rowp(base, ld, r[c], g), lane0 + g * kV, lanes, x[c]);
       }
     }
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c) {
 #pragma unroll
-      for (int v = 0; v < kV; ++v) {
-        if constexpr (KIND == kZeros) x[c][v] = r[c] == ~0ull ? 0 : x[c][v];
+      for (int v = 0; v < kV; ++v)
         if constexpr (KIND == kWeighted) x[c][v] = ct::mulw(x[c][v], w[c]);
-      }
     }
   }
   template <int B, uint32_t H>
