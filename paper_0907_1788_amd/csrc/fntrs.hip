@@ -375,6 +375,44 @@ bool eval_ct(int L, uint32_t grid, const LocDesc* D, const uint32_t* start, uint
   }
 }
 
+// FNT_n (n = 2^14 .. 2^16) of one vector: k <= n values at src, zero-padded
+// to n, natural order in and out, on the four-step kernels -- hundreds of
+// workgroups where a one-lane transform of the lane-tile kernels runs in one
+// or two.
+// `scr` holds n * kFourStepTile words (kFnOneScratchWords covers any n).
+constexpr size_t kFnOneScratchWords = size_t(65536) * kFourStepTile;
+int fnt_one(fntrs_ctx* c, uint32_t n, uint32_t k, const uint32_t* src, uint32_t* dst, uint32_t* scr, hipStream_t s) {
+  FourStepArgs f{};
+  f.in = src; f.ld_in = 1; f.stride_in = k;
+  f.out = dst; f.ld_out = 1; f.stride_out = n;
+  f.tw = c->tw; f.twi = c->twi;
+  f.n = n; f.k = k; f.M = n; f.lanes = 1; f.logn = ilog2(n); f.logm = f.logn;
+  f.tiles = 1;
+  HIP_TRY(c, fourstep_encode(f, 1, scr, kFourStepTile, s));
+  return FNTRS_OK;
+}
+
+// Top product-tree level of one pattern (one pair, 2d = the tree's points,
+// 2^14 or 2^15) through fnt_one: spec and vals (>= 2d words each, unused
+// until the derivative and the evaluation) hold the transforms.
+int top_level_fourstep(fntrs_ctx* c, const LocDesc& d, int lev, uint32_t half, uint32_t* scr, hipStream_t s) {
+  const uint32_t* in = (lev & 1) ? d.t1 : d.t0;
+  uint32_t* out = (lev & 1) ? d.t0 : d.t1;
+  const uint32_t n2 = 2 * half;
+  if (int rc = fnt_one(c, n2, half, in, d.spec, scr, s)) return rc;          // a_lo
+  if (int rc = fnt_one(c, n2, half, in + half, d.vals, scr, s)) return rc;   // b_lo
+  hipLaunchKernelGGL(k_loc_mul, dim3((n2 + 255) / 256), dim3(256), 0, s, d.spec, (const uint32_t*)d.vals, n2);
+  HIP_TRY(c, hipGetLastError());
+  if (int rc = fnt_one(c, n2, n2, d.spec, d.vals, scr, s)) return rc;        // the product, at negated indices
+  uint64_t inv = 1, b = n2 % 65537u;                                    // (2d)^-1 = (2d)^65535
+  for (uint32_t e = 65535; e; e >>= 1, b = b * b % 65537u)
+    if (e & 1u) inv = inv * b % 65537u;
+  hipLaunchKernelGGL(k_loc_combine, dim3((n2 + 255) / 256), dim3(256), 0, s, (const uint32_t*)d.vals, in, in + half,
+                     out, half, (uint32_t)inv);
+  HIP_TRY(c, hipGetLastError());
+  return FNTRS_OK;
+}
+
 }  // namespace
 
 int validate_range(fntrs_ctx* c, const uint32_t* p, uint32_t batch, size_t stride, uint32_t rows,
@@ -582,10 +620,25 @@ static int build_locators(fntrs_ctx* c, std::vector<fntrs_locator_t*>& Ls, hipSt
     hipLaunchKernelGGL(k_locb_prep, dim3((prep.total + 255) / 256), dim3(256), 0, s, D, st_ptr(prep), P);
     if (Pn) {
       hipLaunchKernelGGL(k_locb_leaves, dim3(leaves.total), dim3(64), 0, s, D, st_ptr(leaves), Pn, tw);
+      // one pattern with a tree of 2^14 points or more: the top level and
+      // the evaluations on the four-step kernels
+      const bool one_big = Pn == 1 && desc[0].k >= (1u << 14);
+      Scratch fsc;   // the four-step passes' rows, reused by each transform in turn
+      if (one_big)
+        if (int rc = scratch_acquire(c, kFnOneScratchWords * 4, s, fsc)) return fail_free(rc);
+      uint32_t* fscr = reinterpret_cast<uint32_t*>(fsc.p);
+      auto fail_both = [&](int rc) {
+        scratch_release(c, fsc, s);
+        return fail_free(rc);
+      };
       for (size_t j = 0; j < levels.size(); ++j) {
         const int logd = levels[j].first;
         const Stage& st = levels[j].second;
         const uint32_t d = 1u << logd;
+        if (one_big && 2 * d == desc[0].k) {
+          if (int rc = top_level_fourstep(c, desc[0], (int)j, d, fscr, s)) return fail_both(rc);
+          continue;
+        }
         if (!level_ct(logd + 1, st.total, D + st.r.first, st_ptr(st), st.r.count, (int)j, tw, c->twi, s)) {
           const size_t lds = 2ull * d * 4;
           (void)set_lds_attr((const void*)k_locb_level, lds);
@@ -596,6 +649,12 @@ static int build_locators(fntrs_ctx* c, std::vector<fntrs_locator_t*>& Ls, hipSt
       }
       hipLaunchKernelGGL(k_locb_derivative, dim3((deriv.total + 255) / 256), dim3(256), 0, s, D, st_ptr(deriv), Pn);
       for (auto& ev : evals) {
+        if (one_big) {   // A' at the n-th roots, A mod x^kr at the M-th roots
+          const LocDesc& d0 = desc[0];
+          if (int rc = fnt_one(c, d0.n, d0.k, d0.spec, d0.vals, fscr, s)) return fail_both(rc);
+          if (int rc = fnt_one(c, 1u << d0.logm, d0.kr, d0.A, d0.ahat, fscr, s)) return fail_both(rc);
+          continue;
+        }
         if (eval_ct(ev.first, ev.second.total, D + ev.second.r.first, st_ptr(ev.second), ev.second.r.count, tw, c->twi,
                     s))
           continue;
@@ -609,6 +668,7 @@ static int build_locators(fntrs_ctx* c, std::vector<fntrs_locator_t*>& Ls, hipSt
       hipLaunchKernelGGL(k_locb_weights, dim3((weights.total + 255) / 256), dim3(256), 0, s, D, st_ptr(weights), Pn,
                          tw);
       hipLaunchKernelGGL(k_locb_ahat, dim3((ahat.total + 255) / 256), dim3(256), 0, s, D, st_ptr(ahat), Pn);
+      scratch_release(c, fsc, s);
     }
   }
   if (hipError_t le = launch_err(); le != hipSuccess)

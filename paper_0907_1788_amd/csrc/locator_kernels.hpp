@@ -512,6 +512,28 @@ __global__ void __launch_bounds__(loc_nt<LK>()) k_locb_eval_ct(const LocDesc* __
   ct::enc_item<LK, 1, loc_nt<LK>(), 1>(e, t, lds, tws);
 }
 
+// ---------------------------------------------------------------- one large
+// pattern: its top product-tree level and its evaluations as transforms
+// spread over the four-step kernels (one lane), with these two pointwise
+// kernels around them.
+// x[i] = x[i] * y[i], i < count.
+__global__ void k_loc_mul(uint32_t* __restrict__ x, const uint32_t* __restrict__ y, uint32_t count) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) x[i] = fmul(x[i], y[i]);
+}
+
+// The top level's product from the forward transform F of the product of
+// the two halves' transforms: a_lo b_lo = F at negated indices / 2d, plus
+// x^d (a_lo + b_lo) (monic factors: a b = x^(2d) + x^d (a_lo + b_lo) + a_lo b_lo).
+__global__ void k_loc_combine(const uint32_t* __restrict__ F, const uint32_t* __restrict__ a,
+                              const uint32_t* __restrict__ b, uint32_t* __restrict__ out, uint32_t d,
+                              uint32_t inv2d) {
+  const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= 2 * d) return;
+  const uint32_t v = fmul(F[(2 * d - m) & (2 * d - 1)], inv2d);
+  out[m] = m >= d ? fadd(v, fadd(a[m - d], b[m - d])) : v;
+}
+
 // n = 1 (and k = 1): encoding and decoding both copy the single symbol.
 __global__ void k_copy_rows(const uint32_t* __restrict__ src, uint64_t stride_src, uint32_t* __restrict__ dst,
                             uint64_t stride_dst, uint32_t lanes, uint32_t batch, const uint32_t* __restrict__ scale) {

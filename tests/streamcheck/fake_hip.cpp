@@ -428,6 +428,28 @@ std::function<void(Op&)> kernel_model(const std::string& name, dim3 grid, void**
     const uint32_t count = *(const uint32_t*)args[2];
     return [D, start, count](Op& x) { model_loc_range(x, D, start, count, nullptr); };
   }
+  if (fn == "k_loc_mul") {
+    uint32_t* xp = *(uint32_t* const*)args[0];
+    const uint32_t* yp = *(const uint32_t* const*)args[1];
+    const uint32_t count = *(const uint32_t*)args[2];
+    return [=](Op& x) {
+      touch(x, (uintptr_t)yp, (size_t)count * 4, false, "y");
+      touch(x, (uintptr_t)xp, (size_t)count * 4, true, "x");
+    };
+  }
+  if (fn == "k_loc_combine") {
+    const uint32_t* F = *(const uint32_t* const*)args[0];
+    const uint32_t* a = *(const uint32_t* const*)args[1];
+    const uint32_t* b = *(const uint32_t* const*)args[2];
+    uint32_t* out = *(uint32_t* const*)args[3];
+    const uint32_t d = *(const uint32_t*)args[4];
+    return [=](Op& x) {
+      touch(x, (uintptr_t)F, (size_t)2 * d * 4, false, "F");
+      touch(x, (uintptr_t)a, (size_t)d * 4, false, "a");
+      touch(x, (uintptr_t)b, (size_t)d * 4, false, "b");
+      touch(x, (uintptr_t)out, (size_t)2 * d * 4, true, "out");
+    };
+  }
   if (fn == "k_copy_rows") {
     const uint32_t* src = *(const uint32_t* const*)args[0];
     const uint64_t ss = *(const uint64_t*)args[1];

@@ -102,7 +102,11 @@ def test_encode_worked_example(ctx):
 # ------------------------------------------------------------------ locator
 @pytest.mark.parametrize("n,k,seed", [(2, 1, 1), (8, 4, 2), (64, 32, 3), (128, 64, 4), (512, 256, 5),
                                       (512, 128, 6), (1024, 64, 7), (4096, 1024, 8), (8192, 4096, 9),
-                                      (16, 3, 10), (512, 100, 11), (2048, 1000, 12), (8192, 2500, 13)])
+                                      (16, 3, 10), (512, 100, 11), (2048, 1000, 12), (8192, 2500, 13),
+                                      # one pattern with a tree of 2^14 / 2^15 points: the top level
+                                      # and the evaluations run on the four-step kernels
+                                      (32768, 16384, 14), (65536, 32768, 15), (65536, 20000, 16),
+                                      (65536, 9000, 17)])
 def test_locator_state_matches_oracle(ctx, n, k, seed):
     say("locator", n, k, seed)
     z = synth.received_positions(seed, n, k)
