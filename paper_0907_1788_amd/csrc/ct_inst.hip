@@ -14,8 +14,7 @@ template <int L, int T, int NT, int V>
 hipError_t enc_one(const EncodeArgs& a, uint32_t blocks, hipStream_t s) {
   constexpr size_t lds = ct::Geo<L, T, NT, V>::LDS_BYTES;
   static_assert(lds <= 163840, "tile exceeds LDS");
-  (void)hipFuncSetAttribute((const void*)ct::k_enc<L, T, NT, V>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds);
+  lds_attr_once((const void*)ct::k_enc<L, T, NT, V>, lds);
   hipLaunchKernelGGL((ct::k_enc<L, T, NT, V>), dim3(blocks), dim3(NT), lds, s, a);
   return hipGetLastError();
 }
@@ -24,8 +23,7 @@ template <int L, int D, int T, int NT, int V>
 hipError_t dec_one(const DecodeArgs& a, uint32_t blocks, hipStream_t s) {
   constexpr size_t lds = ct::Geo<L, T, NT, V>::LDS_BYTES;
   static_assert(lds <= 163840, "tile exceeds LDS");
-  (void)hipFuncSetAttribute((const void*)ct::k_dec<L, D, T, NT, V>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds);
+  lds_attr_once((const void*)ct::k_dec<L, D, T, NT, V>, lds);
   hipLaunchKernelGGL((ct::k_dec<L, D, T, NT, V>), dim3(blocks), dim3(NT), lds, s, a);
   return hipGetLastError();
 }
@@ -44,8 +42,7 @@ template <int L, int T, int NT, int V>
 hipError_t enc_tab_one(const JobTable<EncodeArgs>& t, const uint32_t* tw, const uint32_t* twi, uint32_t grid,
                        hipStream_t s) {
   constexpr size_t lds = ct::Geo<L, T, NT, V>::LDS_BYTES;
-  (void)hipFuncSetAttribute((const void*)ct::k_enc_tab<L, T, NT, V>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds);
+  lds_attr_once((const void*)ct::k_enc_tab<L, T, NT, V>, lds);
   hipLaunchKernelGGL((ct::k_enc_tab<L, T, NT, V>), dim3(grid), dim3(NT), lds, s, t, tw, twi);
   return hipGetLastError();
 }
@@ -54,8 +51,7 @@ template <int L, int D, int T, int NT, int V>
 hipError_t dec_tab_one(const JobTable<DecodeArgs>& t, const uint32_t* tw, const uint32_t* twi, uint32_t grid,
                        hipStream_t s) {
   constexpr size_t lds = ct::Geo<L, T, NT, V>::LDS_BYTES;
-  (void)hipFuncSetAttribute((const void*)ct::k_dec_tab<L, D, T, NT, V>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds);
+  lds_attr_once((const void*)ct::k_dec_tab<L, D, T, NT, V>, lds);
   hipLaunchKernelGGL((ct::k_dec_tab<L, D, T, NT, V>), dim3(grid), dim3(NT), lds, s, t, tw, twi);
   return hipGetLastError();
 }
@@ -99,10 +95,8 @@ bool enc_cos_pays() {
   constexpr size_t lds = ct::Geo<L, T, NT, V>::LDS_BYTES;
   if (kernel_spills(ct::k_enc_cos<L, T, NT, V>)) return false;
   int oc = 0, op = 0;
-  (void)hipFuncSetAttribute((const void*)ct::k_enc_cos<L, T, NT, V>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds);
-  (void)hipFuncSetAttribute((const void*)ct::k_enc<L, T, NT, V>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds);
+  lds_attr_once((const void*)ct::k_enc_cos<L, T, NT, V>, lds);
+  lds_attr_once((const void*)ct::k_enc<L, T, NT, V>, lds);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&oc, ct::k_enc_cos<L, T, NT, V>, NT, lds) != hipSuccess ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&op, ct::k_enc<L, T, NT, V>, NT, lds) != hipSuccess)
     return false;
@@ -115,8 +109,7 @@ hipError_t enc_cos_one(const EncodeArgs& a, uint32_t blocks, hipStream_t s) {
     static const bool pays = enc_cos_pays<L, T, NT, V>();
     if (!pays) return hipErrorNotSupported;
     constexpr size_t lds = ct::Geo<L, T, NT, V>::LDS_BYTES;
-    (void)hipFuncSetAttribute((const void*)ct::k_enc_cos<L, T, NT, V>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
+    lds_attr_once((const void*)ct::k_enc_cos<L, T, NT, V>, lds);
     hipLaunchKernelGGL((ct::k_enc_cos<L, T, NT, V>), dim3(blocks), dim3(NT), lds, s, a);
     return hipGetLastError();
   } else {
@@ -129,10 +122,8 @@ bool enc_cos_tab_pays() {
   constexpr size_t lds = ct::Geo<L, T, NT, V>::LDS_BYTES;
   if (kernel_spills(ct::k_enc_cos_tab<L, T, NT, V>)) return false;
   int oc = 0, op = 0;
-  (void)hipFuncSetAttribute((const void*)ct::k_enc_cos_tab<L, T, NT, V>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  (void)hipFuncSetAttribute((const void*)ct::k_enc_tab<L, T, NT, V>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds);
+  lds_attr_once((const void*)ct::k_enc_cos_tab<L, T, NT, V>, lds);
+  lds_attr_once((const void*)ct::k_enc_tab<L, T, NT, V>, lds);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&oc, ct::k_enc_cos_tab<L, T, NT, V>, NT, lds) != hipSuccess ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&op, ct::k_enc_tab<L, T, NT, V>, NT, lds) != hipSuccess)
     return false;
@@ -146,8 +137,7 @@ hipError_t enc_cos_tab_one(const JobTable<EncodeArgs>& t, const uint32_t* tw, co
     static const bool pays = enc_cos_tab_pays<L, T, NT, V>();
     if (!pays) return hipErrorNotSupported;
     constexpr size_t lds = ct::Geo<L, T, NT, V>::LDS_BYTES;
-    (void)hipFuncSetAttribute((const void*)ct::k_enc_cos_tab<L, T, NT, V>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    lds_attr_once((const void*)ct::k_enc_cos_tab<L, T, NT, V>, lds);
     hipLaunchKernelGGL((ct::k_enc_cos_tab<L, T, NT, V>), dim3(grid), dim3(NT), lds, s, t, tw, twi);
     return hipGetLastError();
   } else {
@@ -160,8 +150,7 @@ hipError_t dec_pipe_one(const JobTable<DecodeArgs>& t, const DecodeArgs& one, co
                         uint32_t grid, hipStream_t s) {
   if constexpr (pipe_ok<L, T, NT, V>()) {
     constexpr size_t lds = ct::Geo<L, T, NT, V>::LDS_BYTES;
-    (void)hipFuncSetAttribute((const void*)ct::k_dec_pipe<L, D, T, NT, V>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    lds_attr_once((const void*)ct::k_dec_pipe<L, D, T, NT, V>, lds);
     hipLaunchKernelGGL((ct::k_dec_pipe<L, D, T, NT, V>), dim3(grid), dim3(NT), lds, s, t, one, tw, twi);
     return hipGetLastError();
   } else {
@@ -187,7 +176,7 @@ int occupancy_no_spill(K kernel, int NT, size_t lds) {
   hipFuncAttributes at{};
   if (hipFuncGetAttributes(&at, (const void*)kernel) != hipSuccess || at.localSizeBytes > 0) return 0;
   int nb = 0;
-  (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  lds_attr_once((const void*)kernel, lds);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, NT, lds) != hipSuccess) return 0;
   return nb;
 }
@@ -195,7 +184,7 @@ int occupancy_no_spill(K kernel, int NT, size_t lds) {
 template <class K>
 int occupancy(K kernel, int NT, size_t lds) {
   int nb = 0;
-  (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  lds_attr_once((const void*)kernel, lds);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, NT, lds) != hipSuccess) return 0;
   return nb;
 }

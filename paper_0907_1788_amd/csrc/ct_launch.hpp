@@ -12,6 +12,10 @@ namespace fntrs {
 // tile width T, threads per workgroup NT and lanes per thread V (T = 0 ends
 // a list).  The first
 // entry is the default; the autotuner may pick another.
+// Sets a kernel's dynamic LDS limit on the current device once per (kernel,
+// device): the runtime call would otherwise cost host time at every launch.
+void lds_attr_once(const void* fn, size_t bytes);
+
 struct CtCfg {
   int T, NT;
   int V = 0;   // lanes per thread; 0 = 4 when the tile allows, else T

@@ -5,6 +5,8 @@
 // translation unit per transform size) and the locator kernels
 // (locator_kernels.hpp).  The batched path (jobs, graphs, autotuning) is in
 // submit.hip.
+#include <set>
+
 #include "host.hpp"
 #include "locator_kernels.hpp"
 
@@ -62,6 +64,16 @@ const CtTables& ct_tables() {
       ct_enc_cos_tab_launch_12, ct_enc_cos_tab_launch_13, ct_enc_cos_tab_launch_14, ct_enc_cos_tab_launch_15};
   static const CtTables t{enc, dec, enc_tab, dec_tab, enc_cos, dec_pipe, occ, enc_cos_tab};
   return t;
+}
+
+void lds_attr_once(const void* fn, size_t bytes) {
+  static std::mutex mu;
+  static std::set<std::tuple<const void*, int, size_t>> done;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(mu);
+  if (done.insert({fn, dev, bytes}).second)
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 int upload_async(fntrs_ctx* c, void* dst, const void* src, size_t bytes, hipStream_t s) {
@@ -331,7 +343,8 @@ uint64_t hash_positions(uint32_t n, uint32_t k, const uint32_t* z) {
 }
 
 hipError_t set_lds_attr(const void* fn, size_t bytes) {
-  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  lds_attr_once(fn, bytes);
+  return hipSuccess;
 }
 
 // One launch of a locator stage on the one-lane ct kernels (transform size

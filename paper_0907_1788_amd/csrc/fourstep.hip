@@ -1,6 +1,5 @@
 // Launches of the four-step kernels (fourstep.hpp) for n = 2^14 .. 2^16.
-#include <atomic>
-
+#include "ct_launch.hpp"
 #include "fourstep.hpp"
 #include "fourstep_launch.hpp"
 
@@ -8,18 +7,9 @@ namespace fntrs {
 
 namespace {
 
-// The LDS size of each kernel is a compile-time constant: its attribute is
-// set on the first launch on each device only.
 template <class K>
 hipError_t launch(K kernel, size_t lds, uint32_t blocks, const FourStepArgs& a, hipStream_t s) {
-  static std::atomic<uint64_t> done{0};   // bit d: set on device d (devices 0..63)
-  int dev = 0;
-  (void)hipGetDevice(&dev);
-  const uint64_t bit = dev >= 0 && dev < 64 ? (1ull << dev) : 0;
-  if (!bit || !(done.load(std::memory_order_relaxed) & bit)) {
-    (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    done.fetch_or(bit);
-  }
+  lds_attr_once((const void*)kernel, lds);
   hipLaunchKernelGGL(kernel, dim3(blocks), dim3(fs::kNT), lds, s, a);
   return hipGetLastError();
 }
