@@ -437,6 +437,18 @@ def run_served(args, torch, fntrs, synth):
         r.out = None
 
     cap = 32 << 30
+    # the kernel configurations of the served size classes, tuned once on one
+    # request of each pool entry and kind (kept in the context for every batch)
+    tuned = []
+    if not args.no_tune:
+        sample = []
+        for k, n, lanes, src, enc in pool:
+            sample.append(serve.Request(serve.ENCODE, n, k, lanes, src))
+            z = np.sort(rng.choice(n, k, replace=False)).astype(np.uint32)
+            sample.append(serve.Request(serve.DECODE, n, k, lanes, enc, positions=z))
+        tuned = serve.Server(ctx, mem_cap_bytes=cap).autotune(sample)
+        torch.cuda.synchronize()
+        log("tuned", len(tuned), "classes")
     # closed loop: every request present at t = 0
     reqs = requests(args.requests, np.zeros(args.requests))
     serve.Server(ctx, mem_cap_bytes=cap).run(reqs[: min(200, len(reqs))], on_done=check)   # warm-up
@@ -475,6 +487,7 @@ def run_served(args, torch, fntrs, synth):
         "latency_ms": {"p50": at100["p50_ms"], "p99": at100["p99_ms"], "at_offered_load": at100["offered_load"]},
         "sweep": sweep,
         "locator_cache_point": "not run: its only GPU run ended in a memory fault whose cause is not shown",
+        "tuning": tuned,
     }
     print(json.dumps(res), flush=True)
 

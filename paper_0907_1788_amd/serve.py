@@ -147,6 +147,32 @@ class Server:
         self.host["submit"] += t3 - t2
         return ev, locs
 
+    def autotune(self, requests, reps: int = 3) -> list:
+        """Tunes the kernel configuration of every size class of `requests`
+        (run as one encode batch and one decode batch on their own buffers,
+        with scratch outputs) and keeps the fastest in the context, where
+        every later batch of the server uses it.  Returns one dict per class."""
+        torch = self.torch
+        enc = [r for r in requests if r.op == ENCODE]
+        dec = [r for r in requests if r.op == DECODE]
+        out = []
+        stream = self.streams[0]
+        with torch.cuda.stream(stream):
+            if enc:
+                outs = [torch.empty((1, r.n, r.lanes), dtype=torch.int32, device="cuda") for r in enc]
+                out += self.ctx.autotune_batch([self.ctx.encode_job(r.inp, o, r.n) for r, o in zip(enc, outs)],
+                                               reps=reps, stream=stream)
+            if dec:
+                locs = self.ctx.locators([(r.n, r.k, r.positions) for r in dec], stream=stream)
+                outs = [torch.empty((1, r.k, r.lanes), dtype=torch.int32, device="cuda") for r in dec]
+                jobs = [self.ctx.decode_job(l, r.inp, o, fntrs.FNTRS_RECV_COMPACT if r.compact else fntrs.FNTRS_RECV_FULL)
+                        for r, l, o in zip(dec, locs, outs)]
+                out += self.ctx.autotune_batch(jobs, reps=reps, stream=stream)
+                for l in locs:
+                    l.release()
+        stream.synchronize()
+        return out
+
     def run(self, requests, keep=None, on_done=None) -> Stats:
         """Serves `requests` (arrival times in seconds from now) to completion.
 

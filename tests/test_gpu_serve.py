@@ -122,6 +122,26 @@ def test_served_results_equal_solo_results(ctx):
             checked += 1
 
 
+def test_tuned_server_results_equal_default_results(ctx):
+    """Server.autotune keeps the fastest configuration of each size class in
+    its context; the outputs stay those of the default configurations."""
+    tctx = fntrs.Context(0)
+    try:
+        pool = make_pool(tctx, 12, seed=31)
+        reqs = make_requests(pool, 60, seed=32, rate=5000.0)
+        say("tuned serve", len(reqs), "requests")
+        srv = serve.Server(tctx, mem_cap_bytes=max(r.device_bytes() for r in reqs) * 6, max_inflight=3)
+        classes = srv.autotune(reqs[:30])
+        assert classes and all(c["ms"] > 0 for c in classes)
+        st = srv.run(reqs)
+        assert st.completed == len(reqs)
+        for r in reqs:
+            assert torch.equal(r.out, solo(ctx, r)), ("tuned vs default", r.rid, r.op, r.n, r.k, r.lanes)
+    finally:
+        torch.cuda.synchronize()
+        tctx.close()
+
+
 def test_admission_rejects_oversized_request(ctx):
     s = torch.zeros((1, 64, 4), dtype=torch.int32, device="cuda")
     r = serve.Request(serve.ENCODE, 128, 64, 4, s)
