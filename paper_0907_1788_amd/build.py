@@ -6,7 +6,8 @@ per transform size for the
 compile-time kernels (ct_inst.hip with -DFNTRS_L=1..15), plus the
 four-step kernels for n = 2^14 .. 2^16 (fourstep.hip), the 16-bit
 transport kernels (wire.hip) and the direct quadratic methods (direct.hip) and the chirp evaluation
-(chirp.hip).  They compile in
+(chirp.hip, with one fused kernel per product length in chirp_inst.hip
+-DFNTRS_L=1..13).  They compile in
 parallel into paper_0907_1788_amd/_build/ and link into libfntrs.so.
 
 Usage: python -m paper_0907_1788_amd.build   (or call build()).
@@ -24,6 +25,7 @@ BUILD = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "libfntrs.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SIZES = range(1, 16)
+CHIRP_SIZES = range(1, 14)   # fused chirp products of 2^1 .. 2^13 points
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC",
@@ -53,6 +55,8 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
              (os.path.join(CSRC, "chirp.hip"), os.path.join(BUILD, "chirp.o"), [])]
     for L in SIZES:
         units.append((os.path.join(CSRC, "ct_inst.hip"), os.path.join(BUILD, f"ct_{L}.o"), [f"-DFNTRS_L={L}"]))
+    for L in CHIRP_SIZES:
+        units.append((os.path.join(CSRC, "chirp_inst.hip"), os.path.join(BUILD, f"chirp_{L}.o"), [f"-DFNTRS_L={L}"]))
     jobs = jobs or min(16, os.cpu_count() or 4)
     # the large sizes take longest: start them first
     order = sorted(units, key=lambda u: -int(u[2][0].split("=")[1]) if u[2] else 0)

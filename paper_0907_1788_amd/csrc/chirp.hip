@@ -9,10 +9,21 @@
 // coefficients L-1 .. L+M-2 exact.  Its three transforms are the encoder's
 // (the forward transform of a zero-padded vector); the inverse transform is
 // the forward one at negated indices, divided by P.
+#include "chirp_kernels.hpp"
 #include "field.hpp"
 #include "host.hpp"
 
 namespace fntrs {
+
+// the fused kernels, one translation unit per product length 2^L (chirp_inst.hip)
+#define FNTRS_CHIRP_DECL(L)                                                          \
+  hipError_t chirp_launch_##L(const ChirpArgs& a, uint32_t blocks, hipStream_t s); \
+  uint32_t chirp_tile_##L();
+FNTRS_CHIRP_DECL(1) FNTRS_CHIRP_DECL(2) FNTRS_CHIRP_DECL(3) FNTRS_CHIRP_DECL(4) FNTRS_CHIRP_DECL(5)
+FNTRS_CHIRP_DECL(6) FNTRS_CHIRP_DECL(7) FNTRS_CHIRP_DECL(8) FNTRS_CHIRP_DECL(9) FNTRS_CHIRP_DECL(10)
+FNTRS_CHIRP_DECL(11) FNTRS_CHIRP_DECL(12) FNTRS_CHIRP_DECL(13)
+#undef FNTRS_CHIRP_DECL
+constexpr int kChirpFusedMaxLog = 13;
 
 namespace {
 
@@ -76,6 +87,26 @@ __global__ void k_chirp_rows(RowScaleArgs a) {
   }
 }
 
+// vbr[p] = vhat[bitrev(p)], p < 2^logp.
+__global__ void k_chirp_perm(const uint32_t* __restrict__ vhat, uint32_t* __restrict__ vbr, int logp) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < (1u << logp)) vbr[p] = vhat[bitrev(p, logp)];
+}
+
+struct ChirpFused {
+  hipError_t (*launch)(const ChirpArgs&, uint32_t, hipStream_t);
+  uint32_t (*tile)();
+};
+const ChirpFused& chirp_fused(int logp) {
+  static const ChirpFused t[kChirpFusedMaxLog + 1] = {
+      {nullptr, nullptr},               {chirp_launch_1, chirp_tile_1},   {chirp_launch_2, chirp_tile_2},
+      {chirp_launch_3, chirp_tile_3},   {chirp_launch_4, chirp_tile_4},   {chirp_launch_5, chirp_tile_5},
+      {chirp_launch_6, chirp_tile_6},   {chirp_launch_7, chirp_tile_7},   {chirp_launch_8, chirp_tile_8},
+      {chirp_launch_9, chirp_tile_9},   {chirp_launch_10, chirp_tile_10}, {chirp_launch_11, chirp_tile_11},
+      {chirp_launch_12, chirp_tile_12}, {chirp_launch_13, chirp_tile_13}};
+  return t[logp];
+}
+
 uint32_t P_of(uint64_t len) { return std::max<uint32_t>(2, pad_pow2((uint32_t)len)); }
 
 uint32_t host_pow(uint32_t x, uint32_t e) {
@@ -119,8 +150,45 @@ extern "C" int fntrs_chirp_eval(fntrs_ctx* c, uint32_t L, uint32_t M, uint32_t a
   hipStream_t s = (hipStream_t)stream;
   const uint32_t P = P_of(len);
   const uint32_t qinv = host_pow(q, 65535), pinv = host_pow(P, 65535);
-  // scratch: v and its transform (P words each), the two scale tables, u and
-  // its transform (batch x P x lanes each)
+  if (ilog2(P) <= kChirpFusedMaxLog) {
+    // fused: tables v, v^, v^ bit-reversed, su, so (P words each), then one
+    // kernel over (lane tile, block)
+    const int logp = ilog2(P);
+    const size_t vw = (P + 63) / 64 * 64;
+    const uint32_t T = chirp_fused(logp).tile();
+    const uint64_t blocks = (uint64_t)((lanes + T - 1) / T) * batch;
+    if (blocks > 0x7fffffffull) return fail(c, FNTRS_E_INVAL, "grid too large");
+    Scratch sc;
+    if (int rc = scratch_acquire(c, 5 * vw * 4, s, sc)) return rc;
+    uint32_t* v = reinterpret_cast<uint32_t*>(sc.p);
+    uint32_t* vhat = v + vw;
+    uint32_t* vbr = vhat + vw;
+    uint32_t* su = vbr + vw;
+    uint32_t* so = su + vw;
+    int rc = FNTRS_OK;
+    hipLaunchKernelGGL(k_chirp_tables, dim3((uint32_t)((len + 255) / 256)), dim3(256), 0, s, a, q, qinv, pinv, L, M,
+                       v, su, so);
+    if (hipGetLastError() != hipSuccess) rc = fail(c, FNTRS_E_DEVICE, "chirp table kernel");
+    if (!rc) rc = encode_run(c, P, (uint32_t)len, 1, v, 1, P, vhat, 1, P, 1, 0, s);
+    if (!rc) {
+      hipLaunchKernelGGL(k_chirp_perm, dim3((P + 255) / 256), dim3(256), 0, s, (const uint32_t*)vhat, vbr, logp);
+      if (hipGetLastError() != hipSuccess) rc = fail(c, FNTRS_E_DEVICE, "chirp permutation kernel");
+    }
+    if (!rc) {
+      ChirpArgs ca{};
+      ca.c = coeffs; ca.ld_c = ld_in; ca.st_c = stride_in;
+      ca.out = out; ca.ld_o = ld_out; ca.st_o = stride_out;
+      ca.su = su; ca.so = so; ca.vhat_br = vbr; ca.tw = c->tw; ca.twi = c->twi;
+      ca.L = L; ca.M = M; ca.lanes = lanes; ca.tiles = (lanes + T - 1) / T;
+      ca.vec = aligned16(coeffs, ld_in, stride_in) && aligned16(out, ld_out, stride_out);
+      if (chirp_fused(logp).launch(ca, (uint32_t)blocks, s) != hipSuccess) rc = fail(c, FNTRS_E_DEVICE, "chirp kernel");
+    }
+    scratch_release(c, sc, s);
+    return rc;
+  }
+  // P > 2^13: three transforms through HBM.  Scratch: v and its transform
+  // (P words each), the two scale tables, u and its transform (batch x P x
+  // lanes each)
   const size_t vw = (P + 63) / 64 * 64, uw = (size_t)batch * P * lanes;
   Scratch sc;
   if (int rc = scratch_acquire(c, (4 * vw + 2 * uw) * 4, s, sc)) return rc;
