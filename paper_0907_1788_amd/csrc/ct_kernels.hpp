@@ -259,23 +259,46 @@ __device__ __forceinline__ void enc_item(const EncodeArgs& a, uint32_t item, uin
 
 // Encoder with every coset of a lane tile in one workgroup: the tile's
 // source rows are read once into registers (pass-0 items, C0 slots per
-// thread),
-// and each coset's first pass twists them there; the stores of one coset
-// drain while the next computes.  Work item = (lane tile, block).
-template <int LK, int TT, int NT, int VV, class TW>
-__device__ __forceinline__ void enc_cos_item(const EncodeArgs& a, uint32_t item, uint32_t* lds, const TW& tws) {
+// thread), and each coset's first pass twists them there; the stores of one
+// coset drain while the next computes.  Work item = (lane tile, block).
+template <int LK, int TT, int NT, int VV>
+struct EncCosRegs {
+  using Gm = Geo<LK, TT, NT, VV>;
+  static constexpr int V = Gm::V, B0 = plan_b(LK, Gm::BM, 0), C0 = pass0_slots<LK, Gm::BM, Gm::G, NT>();
+  int32_t src[C0][1 << B0][V];
+  uint32_t wt[C0][1 << B0], unused[C0][1 << B0];
+};
+
+// The loader of item `item` of job `a` (coset 0).
+template <int LK, int TT, int NT, int VV>
+__device__ __forceinline__ EncLoad<LK, Geo<LK, TT, NT, VV>::V> enc_cos_loader(const EncodeArgs& a, uint32_t item) {
+  using Gm = Geo<LK, TT, NT, VV>;
+  const uint32_t lane0 = (item % a.tiles) * Gm::T;
+  const uint64_t blk = item / a.tiles;
+  return {a.src + blk * a.stride_src + lane0, a.tw, a.ld_src, a.k, a.n, 0u, lane0, a.lanes, 16 - a.logn, a.vec != 0};
+}
+
+// Reads the source rows of item `item` into the registers (coset 0: no twist).
+template <int LK, int TT, int NT, int VV>
+__device__ __forceinline__ void enc_cos_prefetch(const EncodeArgs& a, uint32_t item, EncCosRegs<LK, TT, NT, VV>& r) {
+  using Gm = Geo<LK, TT, NT, VV>;
+  auto ld = enc_cos_loader<LK, TT, NT, VV>(a, item);
+  prefetch0<LK, Gm::BM, Gm::V, Gm::G, NT, EncCosRegs<LK, TT, NT, VV>::C0>(ld, r.src, r.wt, r.unused);
+}
+
+// Every coset of item `item` from the rows in `r`; `last` runs right before
+// the last coset's last pass, when the rows in `r` are no longer needed (a
+// persistent kernel reads the next item's rows there).
+template <int LK, int TT, int NT, int VV, class TW, class Hook>
+__device__ __forceinline__ void enc_cos_body(const EncodeArgs& a, uint32_t item, uint32_t* lds, const TW& tws,
+                                             EncCosRegs<LK, TT, NT, VV>& r, Hook& last) {
   using Gm = Geo<LK, TT, NT, VV>;
   constexpr int V = Gm::V, G = Gm::G, T = Gm::T, BM = Gm::BM;
-  constexpr int B0 = plan_b(LK, BM, 0);
-  constexpr int C0 = pass0_slots<LK, BM, G, NT>();
+  constexpr int B0 = EncCosRegs<LK, TT, NT, VV>::B0, C0 = EncCosRegs<LK, TT, NT, VV>::C0;
   static_assert(plan_np(LK, BM) >= 2, "needs a first and a last pass");
   const uint32_t lane0 = (item % a.tiles) * T;
   const uint64_t blk = item / a.tiles;
-  EncLoad<LK, V> ld{a.src + blk * a.stride_src + lane0, a.tw, a.ld_src, a.k, a.n, 0u, lane0, a.lanes,
-                    16 - a.logn, a.vec != 0};
-  int32_t src[C0][1 << B0][V];
-  uint32_t wt[C0][1 << B0], unused[C0][1 << B0];
-  prefetch0<LK, BM, V, G, NT, C0>(ld, src, wt, unused);   // rows once (coset 0: no twist)
+  auto ld = enc_cos_loader<LK, TT, NT, VV>(a, item);
   const uint32_t rn = gptr(a.tw)[1u << (16 - a.logn)];     // r_n
   LdsLoad<V, G> lm{lds};
   LdsStore<V, G, false> sm{lds};
@@ -289,17 +312,26 @@ __device__ __forceinline__ void enc_cos_item(const EncodeArgs& a, uint32_t item,
         const uint32_t base = ((threadIdx.x + (uint32_t)c * NT) / G) << B0;
         // two cosets: the factors come from the twiddle table (LDS), so they
         // do not wait behind the previous coset's stores
-        if (a.cosets == 2) ld.template twists_half<B0>(base, wt[c], tws, rn);
-        else ld.template twists<B0>(base, wt[c]);
+        if (a.cosets == 2) ld.template twists_half<B0>(base, r.wt[c], tws, rn);
+        else ld.template twists<B0>(base, r.wt[c]);
       }
     }
-    dit_pass0_regs<LK, BM, V, G, NT, C0, false>(tws, ld, src, wt, unused, sm);
+    dit_pass0_regs<LK, BM, V, G, NT, C0, false>(tws, ld, r.src, r.wt, r.unused, sm);
     __syncthreads();
     EncStore<V> sl{a.dst + blk * a.stride_dst + lane0, a.ld_dst, t, a.cosets, lane0, a.lanes, a.vec != 0,
                    a.rows_out};
-    dit_from<LK, BM, V, G, false, 1>(tws, lm, sm, sl, none);
-    __syncthreads();   // the next coset's first pass overwrites the LDS tile
+    if (t + 1 == a.cosets) dit_from<LK, BM, V, G, false, 1>(tws, lm, sm, sl, last);
+    else dit_from<LK, BM, V, G, false, 1>(tws, lm, sm, sl, none);
+    __syncthreads();   // the next coset's (or item's) first pass overwrites the LDS tile
   }
+}
+
+template <int LK, int TT, int NT, int VV, class TW>
+__device__ __forceinline__ void enc_cos_item(const EncodeArgs& a, uint32_t item, uint32_t* lds, const TW& tws) {
+  EncCosRegs<LK, TT, NT, VV> r;
+  enc_cos_prefetch<LK, TT, NT, VV>(a, item, r);
+  NoHook none;
+  enc_cos_body<LK, TT, NT, VV>(a, item, lds, tws, r, none);
 }
 
 template <int LK, int TT, int NT, int VV>
@@ -350,17 +382,33 @@ __global__ void __launch_bounds__(NT) k_enc_tab(JobTable<EncodeArgs> t, const ui
 // Batched all-cosets encoder: as k_enc_tab, but a work item is a (lane tile,
 // block) whose every coset the workgroup computes from one load of the
 // source rows (k_enc_cos).
+// The next item's source rows are read into the registers right before the
+// last coset's last pass of the current one, so their latency overlaps that
+// pass and its stores.
 template <int LK, int TT, int NT, int VV>
 __global__ void __launch_bounds__(NT) k_enc_cos_tab(JobTable<EncodeArgs> t, const uint32_t* tw, const uint32_t* twi) {
   using Gm = Geo<LK, TT, NT, VV>;
   using TW = typename Gm::TwType;
   extern __shared__ uint32_t lds[];
   const TW tws = make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, tw, twi);
-  for (uint32_t w = xcd_remap(blockIdx.x, gridDim.x); w < t.total; w += gridDim.x) {
+  uint32_t w = xcd_remap(blockIdx.x, gridDim.x);
+  if (w >= t.total) return;
+  EncCosRegs<LK, TT, NT, VV> r;
+  {
+    const uint32_t j = find_job(t.start, t.njobs, w);
+    enc_cos_prefetch<LK, TT, NT, VV>(load_global(t.jobs + j), w - gptr(t.start)[j], r);
+  }
+  for (; w < t.total; w += gridDim.x) {
     const uint32_t j = find_job(t.start, t.njobs, w);
     const EncodeArgs a = load_global(t.jobs + j);
-    enc_cos_item<LK, TT, NT, VV>(a, w - gptr(t.start)[j], lds, tws);
-    __syncthreads();   // the next item overwrites the LDS tile
+    const uint32_t wn = w + gridDim.x;
+    auto next = [&]() {
+      if (wn < t.total) {
+        const uint32_t jn = find_job(t.start, t.njobs, wn);
+        enc_cos_prefetch<LK, TT, NT, VV>(load_global(t.jobs + jn), wn - gptr(t.start)[jn], r);
+      }
+    };
+    enc_cos_body<LK, TT, NT, VV>(a, w - gptr(t.start)[j], lds, tws, r, next);
   }
 }
 
