@@ -286,9 +286,9 @@ __device__ __forceinline__ void enc_cos_prefetch(const EncodeArgs& a, uint32_t i
   prefetch0<LK, Gm::BM, Gm::V, Gm::G, NT, EncCosRegs<LK, TT, NT, VV>::C0>(ld, r.src, r.wt, r.unused);
 }
 
-// Every coset of item `item` from the rows in `r`; `last` runs right before
-// the last coset's last pass, when the rows in `r` are no longer needed (a
-// persistent kernel reads the next item's rows there).
+// Every coset of item `item` from the rows in `r`; `last` runs once the last
+// coset's first pass has consumed the rows in `r` (a persistent kernel reads
+// the next item's rows there, and that read overlaps every later pass).
 template <int LK, int TT, int NT, int VV, class TW, class Hook>
 __device__ __forceinline__ void enc_cos_body(const EncodeArgs& a, uint32_t item, uint32_t* lds, const TW& tws,
                                              EncCosRegs<LK, TT, NT, VV>& r, Hook& last) {
@@ -320,8 +320,8 @@ __device__ __forceinline__ void enc_cos_body(const EncodeArgs& a, uint32_t item,
     __syncthreads();
     EncStore<V> sl{a.dst + blk * a.stride_dst + lane0, a.ld_dst, t, a.cosets, lane0, a.lanes, a.vec != 0,
                    a.rows_out};
-    if (t + 1 == a.cosets) dit_from<LK, BM, V, G, false, 1>(tws, lm, sm, sl, last);
-    else dit_from<LK, BM, V, G, false, 1>(tws, lm, sm, sl, none);
+    if (t + 1 == a.cosets) last();
+    dit_from<LK, BM, V, G, false, 1>(tws, lm, sm, sl, none);
     __syncthreads();   // the next coset's (or item's) first pass overwrites the LDS tile
   }
 }
@@ -382,9 +382,9 @@ __global__ void __launch_bounds__(NT) k_enc_tab(JobTable<EncodeArgs> t, const ui
 // Batched all-cosets encoder: as k_enc_tab, but a work item is a (lane tile,
 // block) whose every coset the workgroup computes from one load of the
 // source rows (k_enc_cos).
-// The next item's source rows are read into the registers right before the
-// last coset's last pass of the current one, so their latency overlaps that
-// pass and its stores.
+// The next item's source rows are read into the registers as soon as the
+// current item's last coset has consumed them (after its first pass), so
+// their latency overlaps that coset's remaining passes and its stores.
 template <int LK, int TT, int NT, int VV>
 __global__ void __launch_bounds__(NT) k_enc_cos_tab(JobTable<EncodeArgs> t, const uint32_t* tw, const uint32_t* twi) {
   using Gm = Geo<LK, TT, NT, VV>;
