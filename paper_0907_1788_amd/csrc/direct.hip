@@ -204,6 +204,7 @@ int direct_mat_alloc(fntrs_ctx* c, size_t words, DirectMat*& out) {
 // W = V_R^-1 of a locator (k x k), built once on the first direct decode.
 int locator_inverse(fntrs_ctx* c, fntrs_locator_t* L, hipStream_t s, const DirectMat*& out) {
   if (!L->direct_w) {
+    if (int rc = locator_coeffs(c, L, s)) return rc;   // reads A
     DirectMat* m = nullptr;
     if (int rc = direct_mat_alloc(c, (size_t)L->k * L->k, m)) return rc;
     HIP_TRY(c, hipStreamWaitEvent(s, L->ready, 0));

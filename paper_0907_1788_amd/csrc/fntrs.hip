@@ -388,21 +388,25 @@ bool eval_ct(int L, uint32_t grid, const LocDesc* D, const uint32_t* start, uint
   }
 }
 
-// FNT_n (n = 2^14 .. 2^16) of one vector: k <= n values at src, zero-padded
-// to n, natural order in and out, on the four-step kernels -- hundreds of
-// workgroups where a one-lane transform of the lane-tile kernels runs in one
-// or two.
+// FNT_n (n = 2^14 .. 2^16) of `lanes` <= kFourStepTile vectors stored
+// [row][lanes]: k <= n rows at src, zero-padded to n, natural order in and
+// out, on the four-step kernels -- hundreds of workgroups where a one-lane
+// transform of the lane-tile kernels runs in one or two.
 // `scr` holds n * kFourStepTile words (kFnOneScratchWords covers any n).
 constexpr size_t kFnOneScratchWords = size_t(65536) * kFourStepTile;
-int fnt_one(fntrs_ctx* c, uint32_t n, uint32_t k, const uint32_t* src, uint32_t* dst, uint32_t* scr, hipStream_t s) {
+int fnt_lanes(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uint32_t* src, uint32_t* dst, uint32_t* scr,
+              hipStream_t s) {
   FourStepArgs f{};
-  f.in = src; f.ld_in = 1; f.stride_in = k;
-  f.out = dst; f.ld_out = 1; f.stride_out = n;
+  f.in = src; f.ld_in = lanes; f.stride_in = (size_t)k * lanes;
+  f.out = dst; f.ld_out = lanes; f.stride_out = (size_t)n * lanes;
   f.tw = c->tw; f.twi = c->twi;
-  f.n = n; f.k = k; f.M = n; f.lanes = 1; f.logn = ilog2(n); f.logm = f.logn;
+  f.n = n; f.k = k; f.M = n; f.lanes = lanes; f.logn = ilog2(n); f.logm = f.logn;
   f.tiles = 1;
   HIP_TRY(c, fourstep_encode(f, 1, scr, kFourStepTile, s));
   return FNTRS_OK;
+}
+int fnt_one(fntrs_ctx* c, uint32_t n, uint32_t k, const uint32_t* src, uint32_t* dst, uint32_t* scr, hipStream_t s) {
+  return fnt_lanes(c, n, k, 1, src, dst, scr, s);
 }
 
 // Top product-tree level of one pattern (one pair, 2d = the tree's points,
@@ -426,7 +430,117 @@ int top_level_fourstep(fntrs_ctx* c, const LocDesc& d, int lev, uint32_t half, u
   return FNTRS_OK;
 }
 
+// Logarithmic locator (k_conv_*) for one pattern of n >= 2^kConvMinLog
+// positions: a fixed number of launches whatever k, where the product tree
+// takes one dependent launch per level, each with few workgroups near the top.
+constexpr int kConvMinLog = 14;
+
+// dlog[x] = log_3 x for x in [1, 65536] (3 generates GF(65537)*).
+const std::vector<uint16_t>& dlog_table() {
+  static const std::vector<uint16_t> t = [] {
+    std::vector<uint16_t> v(65537, 0);
+    uint32_t x = 1;
+    for (uint32_t e = 0; e < 65536; ++e, x = x * 3u % 65537u) v[x] = (uint16_t)e;
+    return v;
+  }();
+  return t;
+}
+
+// The table FNT_n(plane_b(l)), [n][16], l(d) = log(r_n^d - 1), l(0) = 0: built
+// on first use for this n (host planes, one 16-lane transform, synchronised)
+// and kept with the context.  `scr`: four-step scratch of the caller.
+int conv_table(fntrs_ctx* c, int logn, uint32_t* scr, hipStream_t s) {
+  if (c->conv_tab[logn]) return FNTRS_OK;
+  const uint32_t n = 1u << logn;
+  const auto& lg = dlog_table();
+  uint64_t r = 1;
+  for (uint32_t e = 0; e < (65536u >> logn); ++e) r = r * 3u % 65537u;   // r_n
+  std::vector<uint32_t> planes((size_t)n * 16);
+  uint64_t x = 1;
+  for (uint32_t d = 0; d < n; ++d, x = x * r % 65537u) {
+    const uint32_t l = d ? lg[(x + 65536u) % 65537u] : 0u;   // log(r_n^d - 1)
+    for (int b = 0; b < 16; ++b) planes[(size_t)d * 16 + b] = (l >> b) & 1u;
+  }
+  const size_t bytes = planes.size() * 4;
+  uint32_t *T = nullptr, *tmp = nullptr;
+  if (hipMalloc((void**)&T, bytes) != hipSuccess) return fail(c, FNTRS_E_NOMEM, "hipMalloc(%zu) for the log table", bytes);
+  if (hipMalloc((void**)&tmp, bytes) != hipSuccess) {
+    (void)hipFree(T);
+    return fail(c, FNTRS_E_NOMEM, "hipMalloc(%zu) for the log planes", bytes);
+  }
+  int rc = FNTRS_OK;
+  if (hipMemcpyAsync(tmp, planes.data(), bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+    rc = fail(c, FNTRS_E_DEVICE, "log planes upload failed");
+  if (!rc) rc = fnt_lanes(c, n, n, 16, tmp, T, scr, s);
+  if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = fail(c, FNTRS_E_DEVICE, "log table transform failed");
+  (void)hipFree(tmp);
+  if (rc) {
+    (void)hipFree(T);
+    return rc;
+  }
+  c->conv_tab[logn] = T;
+  c->used += bytes;
+  return FNTRS_OK;
+}
+
+// Steps 1-3 of one pattern from logarithms (the identities at k_conv_mark);
+// d.zin holds its positions on the device and bstart the first rank of each
+// 256 positions (n/256 + 1 words), S = e sum z mod 65536.  A's values at the
+// n-th roots stay in L->Avals; its coefficients wait for locator_coeffs.
+int conv_locator(fntrs_ctx* c, fntrs_locator_t* L, const LocDesc& d, const uint32_t* bstart, uint32_t S,
+                 hipStream_t s) {
+  const uint32_t n = d.n;
+  const size_t wn = n;   // n >= 2^14: every part stays 256-byte aligned
+  Scratch sc;
+  if (int rc = scratch_acquire(c, (2 * wn + 32 * wn + kFnOneScratchWords) * 4, s, sc)) return rc;
+  uint32_t* ind = reinterpret_cast<uint32_t*>(sc.p);
+  uint32_t* F = ind + wn;
+  uint32_t* P = F + wn;
+  uint32_t* Q = P + 16 * wn;
+  uint32_t* fs = Q + 16 * wn;
+  int rc = conv_table(c, d.logn, fs, s);
+  const uint32_t blocks = n / 256;
+  if (!rc) {
+    hipLaunchKernelGGL(k_conv_mark, dim3(blocks), dim3(256), 0, s, d.zin, bstart, ind, d.pos, d.ridx);
+    rc = fnt_lanes(c, n, n, 1, ind, F, fs, s);
+  }
+  if (!rc) {
+    hipLaunchKernelGGL(k_conv_mul, dim3(4 * blocks), dim3(256), 0, s, (const uint32_t*)F,
+                       (const uint32_t*)c->conv_tab[d.logn], P, n);
+    rc = fnt_lanes(c, n, n, 16, P, Q, fs, s);
+  }
+  if (!rc) {
+    ConvFinishArgs a{Q, ind, d.ridx, c->tw, d.w, d.wfull, d.ahat, d.ahat_br, d.ahat_s, L->Avals, S, d.kr, d.logn,
+                     d.logm};
+    hipLaunchKernelGGL(k_conv_finish, dim3(blocks), dim3(256), 0, s, a);
+    if (hipGetLastError() != hipSuccess) rc = fail(c, FNTRS_E_DEVICE, "logarithmic locator kernels failed");
+  }
+  scratch_release(c, sc, s);
+  if (!rc) L->coeffs_pending = true;
+  return rc;
+}
+
 }  // namespace
+
+int locator_coeffs(fntrs_ctx* c, const fntrs_locator_t* L, hipStream_t s) {
+  if (!L->coeffs_pending) return FNTRS_OK;
+  const uint32_t n = L->n;
+  Scratch sc;
+  if (int rc = scratch_acquire(c, ((size_t)n + kFnOneScratchWords) * 4, s, sc)) return rc;
+  uint32_t* G = reinterpret_cast<uint32_t*>(sc.p);
+  int rc = FNTRS_OK;
+  if (hipStreamWaitEvent(s, L->ready, 0) != hipSuccess) rc = fail(c, FNTRS_E_DEVICE, "stream wait failed");
+  if (!rc) rc = fnt_lanes(c, n, n, 1, L->Avals, G, G + n, s);   // A = FNT_n of its values at negated indices / n
+  if (!rc) {
+    hipLaunchKernelGGL(k_conv_coef, dim3((L->k + 256) / 256), dim3(256), 0, s, (const uint32_t*)G, L->A, L->k, L->logn);
+    if (hipGetLastError() != hipSuccess) rc = fail(c, FNTRS_E_DEVICE, "locator coefficients kernel failed");
+  }
+  if (!rc && hipEventRecord(L->ready, s) != hipSuccess) rc = fail(c, FNTRS_E_DEVICE, "event record failed");
+  scratch_release(c, sc, s);
+  if (!rc) L->coeffs_pending = false;
+  return rc;
+}
+
 
 int validate_range(fntrs_ctx* c, const uint32_t* p, uint32_t batch, size_t stride, uint32_t rows,
                    size_t ld, uint32_t lanes, hipStream_t s) {
@@ -498,11 +612,15 @@ static int build_locators(fntrs_ctx* c, std::vector<fntrs_locator_t*>& Ls, hipSt
   const uint32_t P = (uint32_t)Ls.size();
   uint32_t Pn = 0;   // patterns with erasures
   while (Pn < P && Ls[Pn]->k < Ls[Pn]->n) ++Pn;
+  // one large pattern alone: logarithms instead of the product tree (its
+  // state keeps A at the n-th roots for the coefficients, taken on first use)
+  const bool conv = P == 1 && Pn == 1 && Ls[0]->n >= (1u << kConvMinLog);
   // persistent state: one slab for the batch
   size_t words = 0;
   for (auto* L : Ls) {
-    L->bytes = state_words(L) * 4;
-    words += state_words(L);
+    const size_t sw = state_words(L) + (conv ? round_words(L->n) : 0);
+    L->bytes = sw * 4;
+    words += sw;
   }
   if (!make_room(c, words * 4))
     return fail(c, FNTRS_E_NOMEM, "locator state of %zu bytes exceeds the context cap (%zu used of %zu)", words * 4,
@@ -530,6 +648,10 @@ static int build_locators(fntrs_ctx* c, std::vector<fntrs_locator_t*>& Ls, hipSt
     L->A = p; p += round_words(k + 1);
     L->w = p; p += round_words(k);
     L->ahat = p; p += round_words(M);
+    if (conv) {
+      L->Avals = p;
+      p += round_words(n);
+    }
     L->slab = slab;
     L->ready = slab->ready;
     zoff[i] = zall.size();
@@ -587,6 +709,19 @@ static int build_locators(fntrs_ctx* c, std::vector<fntrs_locator_t*>& Ls, hipSt
   }
   const Stage weights = add_stage({0, Pn}, [](const fntrs_locator_t* L) { return (uint64_t)L->k; });
   const Stage ahat = add_stage({0, Pn}, [](const fntrs_locator_t* L) { return 1ull << L->logm; });
+  // the logarithmic route: the first rank of every 256 positions goes up
+  // with the tables
+  const size_t conv_off = tab.size();
+  uint32_t conv_S = 0;
+  if (conv) {
+    const auto& z = Ls[0]->positions;
+    uint64_t sum = 0, q = 0;
+    for (uint32_t b = 0; b <= desc[0].n / 256; ++b) {
+      while (q < z.size() && z[q] < b * 256u) sum += z[q++];
+      tab.push_back((uint32_t)q);
+    }
+    conv_S = (uint32_t)(((sum % 65536u) * (65536u >> desc[0].logn)) & 0xFFFFu);
+  }
   // one transient allocation: descriptors | positions | tables | scratch
   const size_t desc_bytes = (P * sizeof(LocDesc) + 255) / 256 * 256;
   const size_t z_words = round_words(zall.size()), tab_words = round_words(tab.size());
@@ -627,7 +762,9 @@ static int build_locators(fntrs_ctx* c, std::vector<fntrs_locator_t*>& Ls, hipSt
   const bool small = P > 0 && Pn == P && std::all_of(Ls.begin(), Ls.end(), [](const fntrs_locator_t* L) {
     return L->k < L->n && L->n <= kLocSmallN && 2 * pad_pow2(L->k) <= L->n && (1u << L->logm) <= L->n;
   });
-  if (small) {
+  if (conv) {
+    if (int rc = conv_locator(c, Ls[0], desc[0], dtab + conv_off, conv_S, s)) return fail_free(rc);
+  } else if (small) {
     hipLaunchKernelGGL(k_locb_small, dim3(P), dim3(kLocSmallNT), 0, s, D, tw);
   } else {
     hipLaunchKernelGGL(k_locb_prep, dim3((prep.total + 255) / 256), dim3(256), 0, s, D, st_ptr(prep), P);
@@ -1054,6 +1191,8 @@ void fntrs_destroy(fntrs_ctx* c) {
   drop(c->capture_side);
   stage_release(c);
   workspace_release(c);
+  for (uint32_t* t : c->conv_tab)
+    if (t) (void)hipFree(t);
   if (c->tw) (void)hipFree(c->tw);
   delete c;
 }
@@ -1148,6 +1287,8 @@ int fntrs_locator_export(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t* A, ui
   std::lock_guard<std::mutex> lk(c->mu);
   if (c->device == FNTRS_HOST_ONLY) return fail(c, FNTRS_E_DEVICE, "host-only context");
   DeviceGuard g(c->device);
+  if (A)
+    if (int rc = locator_coeffs(c, L, nullptr)) return rc;
   HIP_TRY(c, hipEventSynchronize(L->ready));
   if (A) HIP_TRY(c, hipMemcpy(A, L->A, (L->k + 1) * 4ull, hipMemcpyDeviceToHost));
   if (w) HIP_TRY(c, hipMemcpy(w, L->w, L->k * 4ull, hipMemcpyDeviceToHost));

@@ -63,6 +63,10 @@ struct fntrs_locator_s {
   size_t bytes = 0;                  // this locator's share of the slab
   uint32_t *pos = nullptr, *wfull = nullptr, *ridx = nullptr, *ahat_br = nullptr, *ahat_s = nullptr;
   uint32_t *A = nullptr, *w = nullptr, *ahat = nullptr;
+  // logarithmic route: A at the n-th roots, and whether the coefficients A
+  // still have to be taken from them (on first use: export, direct decoding)
+  uint32_t* Avals = nullptr;
+  mutable bool coeffs_pending = false;
   hipEvent_t ready = nullptr;        // the slab's event
   // direct (quadratic) decoders: the inverse of the received rows of the
   // generator, and the systematic decoder's matrix and row tables
@@ -80,6 +84,7 @@ struct fntrs_ctx {
   uint32_t* tw = nullptr;            // tw[e] = 3^e mod p, e < 65536
   uint32_t* twi = nullptr;           // twi[e] = 3^-e mod p
   uint32_t* noalloc_scratch = nullptr;   // device address of the no-allocation encoder's scratch
+  uint32_t* conv_tab[17] = {};       // per log2 n: FNT_n of the 16 bit planes of log(r_n^d - 1), [n][16]
   size_t lds_max = 65536;
   fntrs::CtCfg enc_cfg[16] = {};     // kernel configuration per log2 transform size
   fntrs::CtCfg dec_cfg[16] = {};
@@ -260,6 +265,10 @@ inline bool encode_fourstep(const fntrs_ctx* c, int logK, int logN) {
 // k <= kDirectMaxK and transform length N <= kDirectMaxN.
 constexpr uint32_t kDirectMaxK = 1024, kDirectMaxN = 16384;
 bool direct_fits(uint32_t N, uint32_t k);
+// The coefficients of A for a locator of the logarithmic route, computed on
+// `s` after the locator's build the first time they are needed; the
+// locator's ready event then covers them.
+int locator_coeffs(fntrs_ctx* c, const fntrs_locator_t* L, hipStream_t s);
 int direct_encode(fntrs_ctx* c, uint32_t N, uint32_t rows, uint32_t k, uint32_t lanes, const uint32_t* src,
                   size_t ld_src, size_t stride_src, uint32_t* dst, size_t ld_dst, size_t stride_dst, uint32_t batch,
                   hipStream_t s);

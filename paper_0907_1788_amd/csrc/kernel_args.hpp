@@ -88,6 +88,22 @@ struct LocDesc {
   int logn, logk, logm;
 };
 
+// Last pass of the logarithmic locator of one large pattern (k_conv_finish).
+struct ConvFinishArgs {
+  const uint32_t* Q;      // forward FNT_n of the 16 products, [n][16]
+  const uint32_t* ind;    // indicator of R
+  const uint32_t* ridx;   // rank of each received position
+  const uint32_t* tw;     // 3^e, e < 65536
+  uint32_t* w;            // state: 1/A'(x_z) by rank
+  uint32_t* wfull;        // state: decoder weight per position
+  uint32_t* ahat;         // state: FNT_M(A mod x^k), natural
+  uint32_t* ahat_br;      // state: the same / M, bit-reversed
+  uint32_t* ahat_s;       // state: the same / M, natural
+  uint32_t* vals;         // A(x_j) for every j (0 on R)
+  uint32_t S, kr;
+  int logn, logm;
+};
+
 // Direct (quadratic) methods: Y[b][yrow(r)][l] = sum_j M(r, j) X[b][xrow(j)][l]
 // mod p, r < R, j < K, l < lanes.  M(r, j) is M[r*ldm + j], or (M null)
 // r_N^(pw(r) j) from the table 3^e, with pw(r) = pw[r] (or r when pw is

@@ -534,6 +534,103 @@ __global__ void k_loc_combine(const uint32_t* __restrict__ F, const uint32_t* __
   out[m] = m >= d ? fadd(v, fadd(a[m - d], b[m - d])) : v;
 }
 
+// ---------------------------------------------------------------- logarithms
+// Steps 1-3 of Sec. II-B for one large pattern without the product tree.
+// With x_z = r^z (r = r_n = 3^e, e = 65536/n) and R the k received
+// positions, every value the decoder needs is a product of differences of
+// points, and r^j - r^z = r^z (r^(j-z) - 1).  Taking discrete logarithms to
+// base 3 (mod 65536, the order of the multiplicative group),
+//   log A(x_j)   = S + C[j]            for j not in R,
+//   log A'(x_z)  = S - e z + C[z]      for z in R (the factor z' = z left out),
+// with S = e sum_{z in R} z and C[j] = sum_{z in R} l((j - z) mod n), where
+// l(d) = log(r^d - 1) for d != 0 and l(0) = 0.  C is one cyclic convolution
+// of the indicator of R with l.  It is exact over GF(65537) bit plane by bit
+// plane: plane b of C counts the z in R whose l(j - z) has bit b set, at most
+// k < 65537, so C mod 2^16 = sum_b 2^b count_b.  The tables FNT_n(plane_b(l))
+// are fixed per n; a pattern costs the transform of its indicator, a product
+// with the 16 planes, their 16 transforms back (a forward FNT read at negated
+// indices, times n^-1) and one pass over the n positions.  From the values:
+//   w_z = 1/A'(x_z),  the decoder weight -w_z x_z^(-1),
+//   FNT_M(A mod x^k) at q = A(x_(q n/M)) - r_M^(q k)   (A monic of degree k, M <= n),
+//   and the coefficients of A by one more transform of its n values (deg A = k < n).
+
+// Indicator of R and the per-position tables: ind[j] = 1 for a received
+// position j (rank q in the ascending list zin: pos[q] = j, ridx[j] = q),
+// else 0.  Workgroup b covers positions [256 b, 256 b + 256), whose ranks
+// are [bstart[b], bstart[b+1]) (from the host, which holds the positions).
+__global__ void __launch_bounds__(256) k_conv_mark(const uint32_t* __restrict__ zin, const uint32_t* __restrict__ bstart,
+                                                   uint32_t* __restrict__ ind, uint32_t* __restrict__ pos,
+                                                   uint32_t* __restrict__ ridx) {
+  __shared__ uint32_t rank1[256];   // rank + 1 of the position, 0: erased
+  const uint32_t t = threadIdx.x, j0 = blockIdx.x * 256u;
+  rank1[t] = 0u;
+  const uint32_t q0 = bstart[blockIdx.x], q1 = bstart[blockIdx.x + 1];
+  __syncthreads();
+  if (q0 + t < q1) rank1[zin[q0 + t] - j0] = q0 + t + 1u;
+  __syncthreads();
+  const uint32_t v = rank1[t], j = j0 + t;
+  ind[j] = v ? 1u : 0u;
+  if (v) {
+    pos[v - 1u] = j;
+    ridx[j] = v - 1u;
+  }
+}
+
+// P[j][b] = F[j] T[j][b] for the 16 bit planes (four per thread).
+__global__ void k_conv_mul(const uint32_t* __restrict__ F, const uint32_t* __restrict__ T, uint32_t* __restrict__ P,
+                           uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;   // (j, quarter)
+  if (i >= 4 * n) return;
+  const uint32_t f = F[i >> 2];
+  const u32x4 t = *(const FNTRS_GLOBAL u32x4*)gptr(T + 4 * (size_t)i);
+  *(FNTRS_GLOBAL u32x4*)gptr(P + 4 * (size_t)i) = u32x4{fmul(f, t.x), fmul(f, t.y), fmul(f, t.z), fmul(f, t.w)};
+}
+
+// One thread per position j: C[j] from the 16 counts, then A(x_j) or the
+// weights of j, and FNT_M(A mod x^k) where j is a multiple of n/M.
+__global__ void k_conv_finish(ConvFinishArgs a) {
+  const uint32_t n = 1u << a.logn, j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const uint32_t e = 65536u >> a.logn;
+  const uint32_t ninv = 65537u - e;   // n^-1 = -2^(16 - logn)
+  const u32x4* q = (const u32x4*)(a.Q + (size_t)((n - j) & (n - 1)) * 16);
+  uint32_t C = 0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const u32x4 c = *(const FNTRS_GLOBAL u32x4*)gptr(q + v);
+    C += (fmul(c.x, ninv) << (4 * v)) + (fmul(c.y, ninv) << (4 * v + 1)) + (fmul(c.z, ninv) << (4 * v + 2)) +
+         (fmul(c.w, ninv) << (4 * v + 3));
+  }
+  uint32_t val = 0;
+  if (a.ind[j]) {
+    const uint32_t lg = (a.S - e * j + C) & 0xFFFFu;                         // log A'(x_j)
+    a.w[a.ridx[j]] = a.tw[(65536u - lg) & 0xFFFFu];                         // 1/A'(x_j)
+    a.wfull[j] = a.tw[(32768u - lg - e * j) & 0xFFFFu];                     // -x_j^(-1)/A'(x_j)
+  } else {
+    a.wfull[j] = 0u;
+    val = a.tw[(a.S + C) & 0xFFFFu];                                        // A(x_j)
+  }
+  a.vals[j] = val;
+  const int sh = a.logn - a.logm;   // n/M = 2^sh
+  if ((j & ((1u << sh) - 1)) == 0) {
+    const uint32_t m = j >> sh, M = 1u << a.logm;
+    const uint32_t u = fsub(val, a.tw[((m * a.kr) & (M - 1)) << (16 - a.logm)]);   // minus r_M^(m k)
+    const uint32_t v = fmul(u, 65537u - (65536u >> a.logm));
+    a.ahat[m] = u;
+    a.ahat_br[bitrev(m, a.logm)] = v;
+    a.ahat_s[m] = v;
+  }
+}
+
+// Coefficients of A from the forward FNT_n G of its n values: a_i = G[-i] / n,
+// i < k, and the leading 1.
+__global__ void k_conv_coef(const uint32_t* __restrict__ G, uint32_t* __restrict__ A, uint32_t kr, int logn) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > kr) return;
+  const uint32_t n = 1u << logn;
+  A[i] = i == kr ? 1u : fmul(G[(n - i) & (n - 1)], 65537u - (65536u >> logn));
+}
+
 // n = 1 (and k = 1): encoding and decoding both copy the single symbol.
 __global__ void k_copy_rows(const uint32_t* __restrict__ src, uint64_t stride_src, uint32_t* __restrict__ dst,
                             uint64_t stride_dst, uint32_t lanes, uint32_t batch, const uint32_t* __restrict__ scale) {

@@ -437,6 +437,59 @@ std::function<void(Op&)> kernel_model(const std::string& name, dim3 grid, void**
       touch(x, (uintptr_t)xp, (size_t)count * 4, true, "x");
     };
   }
+  if (fn == "k_conv_mark") {   // workgroup b: positions [256 b, 256 b + 256)
+    const uint32_t* zin = *(const uint32_t* const*)args[0];
+    const uint32_t* bstart = *(const uint32_t* const*)args[1];
+    uint32_t* ind = *(uint32_t* const*)args[2];
+    uint32_t* pos = *(uint32_t* const*)args[3];
+    uint32_t* ridx = *(uint32_t* const*)args[4];
+    return [=](Op& x) {
+      const size_t n = (size_t)g * 256;
+      touch(x, (uintptr_t)bstart, ((size_t)g + 1) * 4, false, "bstart");
+      const uint32_t kr = bstart[g];   // the host table: every rank below n
+      touch(x, (uintptr_t)zin, (size_t)kr * 4, false, "zin");
+      touch(x, (uintptr_t)ind, n * 4, true, "ind");
+      touch(x, (uintptr_t)pos, (size_t)kr * 4, true, "pos");
+      touch(x, (uintptr_t)ridx, n * 4, true, "ridx");
+    };
+  }
+  if (fn == "k_conv_mul") {
+    const uint32_t* F = *(const uint32_t* const*)args[0];
+    const uint32_t* T = *(const uint32_t* const*)args[1];
+    uint32_t* P = *(uint32_t* const*)args[2];
+    const uint32_t n = *(const uint32_t*)args[3];
+    return [=](Op& x) {
+      touch(x, (uintptr_t)F, (size_t)n * 4, false, "F");
+      touch(x, (uintptr_t)T, (size_t)n * 64, false, "T");
+      touch(x, (uintptr_t)P, (size_t)n * 64, true, "P");
+    };
+  }
+  if (fn == "k_conv_finish") {
+    const fntrs::ConvFinishArgs a = *(const fntrs::ConvFinishArgs*)args[0];
+    return [=](Op& x) {
+      const size_t n = (size_t)1 << a.logn, M = (size_t)1 << a.logm;
+      touch(x, (uintptr_t)a.Q, n * 64, false, "Q");
+      touch(x, (uintptr_t)a.ind, n * 4, false, "ind");
+      touch(x, (uintptr_t)a.ridx, n * 4, false, "ridx");
+      touch(x, (uintptr_t)a.tw, 65536 * 4, false, "tw");
+      touch(x, (uintptr_t)a.w, (size_t)a.kr * 4, true, "w");
+      touch(x, (uintptr_t)a.wfull, n * 4, true, "wfull");
+      touch(x, (uintptr_t)a.ahat, M * 4, true, "ahat");
+      touch(x, (uintptr_t)a.ahat_br, M * 4, true, "ahat_br");
+      touch(x, (uintptr_t)a.ahat_s, M * 4, true, "ahat_s");
+      touch(x, (uintptr_t)a.vals, n * 4, true, "vals");
+    };
+  }
+  if (fn == "k_conv_coef") {
+    const uint32_t* G = *(const uint32_t* const*)args[0];
+    uint32_t* A = *(uint32_t* const*)args[1];
+    const uint32_t kr = *(const uint32_t*)args[2];
+    const int logn = *(const int*)args[3];
+    return [=](Op& x) {
+      touch(x, (uintptr_t)G, ((size_t)1 << logn) * 4, false, "G");
+      touch(x, (uintptr_t)A, ((size_t)kr + 1) * 4, true, "A");
+    };
+  }
   if (fn == "k_loc_combine") {
     const uint32_t* F = *(const uint32_t* const*)args[0];
     const uint32_t* a = *(const uint32_t* const*)args[1];

@@ -162,6 +162,24 @@ def scenario(name, fake, torch, fntrs):
         ctx.decode(loc, b, out, fntrs.FNTRS_RECV_FULL, stream=s2)
         fake.fakehip_drain()
         loc.release()
+    elif name == "large_locator_ok":
+        # one large pattern (the logarithmic route: a table built on first
+        # use, transforms through scratch) on s1, decoded on s2, twice
+        # (its coefficients are taken on first use: by the export, or by
+        # the direct decoder on s2)
+        N = 16384
+        for rep, K in enumerate((4096, 1024)):
+            z = np.arange(rep, N, 3, dtype=np.uint32)[:K]
+            loc = ctx.locator(N, K, z, stream=s1)
+            recv = torch.empty((1, N, 32))
+            out = torch.empty((1, K, 32))
+            ctx.decode(loc, recv, out, fntrs.FNTRS_RECV_FULL, stream=s2)
+            if rep == 0:
+                loc.export()
+            else:
+                ctx.decode(loc, recv, out, fntrs.FNTRS_RECV_FULL | fntrs.FNTRS_DIRECT, stream=s2)
+            fake.fakehip_drain()
+            loc.release()
     elif name == "direct_ok":
         # the direct methods' matrices are built on one stream and used on another
         z = np.arange(1, n, 2, dtype=np.uint32)[:k]

@@ -103,10 +103,10 @@ def test_encode_worked_example(ctx):
 @pytest.mark.parametrize("n,k,seed", [(2, 1, 1), (8, 4, 2), (64, 32, 3), (128, 64, 4), (512, 256, 5),
                                       (512, 128, 6), (1024, 64, 7), (4096, 1024, 8), (8192, 4096, 9),
                                       (16, 3, 10), (512, 100, 11), (2048, 1000, 12), (8192, 2500, 13),
-                                      # one pattern with a tree of 2^14 / 2^15 points: the top level
-                                      # and the evaluations run on the four-step kernels
+                                      # one pattern of 2^14 positions or more: the logarithmic route
                                       (32768, 16384, 14), (65536, 32768, 15), (65536, 20000, 16),
-                                      (65536, 9000, 17)])
+                                      (65536, 9000, 17), (16384, 1, 31), (16384, 4096, 32),
+                                      (65536, 2048, 33), (32768, 3000, 34), (65536, 1, 36)])
 def test_locator_state_matches_oracle(ctx, n, k, seed):
     say("locator", n, k, seed)
     z = synth.received_positions(seed, n, k)
@@ -147,6 +147,35 @@ def test_short_code_locator_matches_staged(n, k, seed):
             assert np.array_equal(gpu_decode(c, loc, e[:, z, :]), src.astype(np.int64))
             assert np.array_equal(gpu_decode(c, loc, e, fntrs.FNTRS_RECV_FULL), src.astype(np.int64))
         for x in (a, b, big):
+            x.release()
+    finally:
+        torch.cuda.synchronize()
+        ca.close()
+        cb.close()
+
+
+@pytest.mark.parametrize("n,k,seed", [(65536, 32768, 41), (32768, 12000, 42), (16384, 5000, 43), (20000, 4096, 44)])
+def test_large_locator_matches_tree(n, k, seed):
+    """A pattern of 2^14 positions or more built alone takes the logarithmic
+    route; in a batch with a second pattern it runs the product tree.  Both
+    give the same state (w and Ahat included, which the oracle comparison
+    skips at large k) and decode the same."""
+    say("large locator, logarithms vs tree", n, k, seed)
+    z = synth.received_positions(seed, n, k)
+    zl = synth.received_positions(seed + 1, 4096, 2048)
+    ca, cb = fntrs.Context(0), fntrs.Context(0)   # separate caches
+    try:
+        a = ca.locator(n, k, z)
+        b, other = cb.locators([(n, k, z), (4096, 2048, zl)])
+        for x, y in zip(a.export(), b.export()):
+            assert np.array_equal(x, y)
+        # round trip (the oracle's encoder is too slow at these sizes; both
+        # directions are compared with it elsewhere)
+        src = synth.source(seed, 1, k, 5)
+        e = gpu_encode(ca, src, n)
+        for c, loc in ((ca, a), (cb, b)):
+            assert np.array_equal(gpu_decode(c, loc, e[:, z, :]), src.astype(np.int64))
+        for x in (a, b, other):
             x.release()
     finally:
         torch.cuda.synchronize()

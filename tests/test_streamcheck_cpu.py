@@ -53,6 +53,7 @@ def run(fake, *args):
     ("encode_chain_ok", None),
     ("decode_other_stream_ok", None),
     ("direct_ok", None),
+    ("large_locator_ok", None),
     ("encode_chain_race", "race:"),
     ("out_of_bounds", "out of bounds:"),
     ("use_after_free", "use after free:"),
