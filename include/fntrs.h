@@ -164,6 +164,15 @@ int fntrs_encode_noalloc(fntrs_ctx* ctx, uint32_t n, uint32_t k, uint32_t lanes,
  *   A(x) = prod_{i<k} (x - r_n^(z_i)) by a product tree of FNT products,
  *   A'(x), its values at the received points by FNT_n, their inverses,
  *   and the FNT of size 2k of the low coefficients of A.
+ * A pattern of 2^14 positions or more built alone (this call, or a batch of
+ * one) takes the same quantities from discrete logarithms instead: one
+ * cyclic convolution of the received-position indicator with
+ * log(r_n^d - 1), exact over GF(65537) bit plane by bit plane, gives
+ * log A(x_j) and log A'(x_z) at every point, hence the weights and the
+ * transform of A mod x^k; the coefficients of A are then taken on first
+ * use (fntrs_locator_export, the direct decoder).  The first such pattern
+ * of a given n builds a table of 16 n words, kept with the context (the
+ * call synchronises `stream` once for it).
  * A pattern already in the context's cache is returned without rebuilding.
  * *out receives a reference that must be given back with
  * fntrs_locator_release.  Any 1 <= k <= n (k = n is allowed: no erasure); a
