@@ -164,7 +164,7 @@ int fntrs_encode_noalloc(fntrs_ctx* ctx, uint32_t n, uint32_t k, uint32_t lanes,
  *   A(x) = prod_{i<k} (x - r_n^(z_i)) by a product tree of FNT products,
  *   A'(x), its values at the received points by FNT_n, their inverses,
  *   and the FNT of size 2k of the low coefficients of A.
- * A pattern of 2^14 positions or more built alone (this call, or a batch of
+ * A pattern of 2^12 positions or more built alone (this call, or a batch of
  * one) takes the same quantities from discrete logarithms instead: one
  * cyclic convolution of the received-position indicator with
  * log(r_n^d - 1), exact over GF(65537) bit plane by bit plane, gives

@@ -433,7 +433,15 @@ int top_level_fourstep(fntrs_ctx* c, const LocDesc& d, int lev, uint32_t half, u
 // Logarithmic locator (k_conv_*) for one pattern of n >= 2^kConvMinLog
 // positions: a fixed number of launches whatever k, where the product tree
 // takes one dependent launch per level, each with few workgroups near the top.
-constexpr int kConvMinLog = 14;
+constexpr int kConvMinLog = 12;
+
+// FNT_n of `lanes` vectors stored [n][lanes] (k = n): the four-step kernels
+// from 2^14 points (scr: kFnOneScratchWords), the encoder below.
+int conv_fnt(fntrs_ctx* c, uint32_t n, uint32_t lanes, const uint32_t* src, uint32_t* dst, uint32_t* scr,
+             hipStream_t s) {
+  if (n >= (1u << kFourStepMinLog)) return fnt_lanes(c, n, n, lanes, src, dst, scr, s);
+  return encode_run(c, n, n, lanes, src, lanes, (size_t)n * lanes, dst, lanes, (size_t)n * lanes, 1, 0, s);
+}
 
 // dlog[x] = log_3 x for x in [1, 65536] (3 generates GF(65537)*).
 const std::vector<uint16_t>& dlog_table() {
@@ -471,7 +479,7 @@ int conv_table(fntrs_ctx* c, int logn, uint32_t* scr, hipStream_t s) {
   int rc = FNTRS_OK;
   if (hipMemcpyAsync(tmp, planes.data(), bytes, hipMemcpyHostToDevice, s) != hipSuccess)
     rc = fail(c, FNTRS_E_DEVICE, "log planes upload failed");
-  if (!rc) rc = fnt_lanes(c, n, n, 16, tmp, T, scr, s);
+  if (!rc) rc = conv_fnt(c, n, 16, tmp, T, scr, s);
   if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = fail(c, FNTRS_E_DEVICE, "log table transform failed");
   (void)hipFree(tmp);
   if (rc) {
@@ -490,9 +498,10 @@ int conv_table(fntrs_ctx* c, int logn, uint32_t* scr, hipStream_t s) {
 int conv_locator(fntrs_ctx* c, fntrs_locator_t* L, const LocDesc& d, const uint32_t* bstart, uint32_t S,
                  hipStream_t s) {
   const uint32_t n = d.n;
-  const size_t wn = n;   // n >= 2^14: every part stays 256-byte aligned
+  const size_t wn = n;   // n >= 2^12: every part stays 256-byte aligned
+  const size_t fsw = n >= (1u << kFourStepMinLog) ? kFnOneScratchWords : 0;
   Scratch sc;
-  if (int rc = scratch_acquire(c, (2 * wn + 32 * wn + kFnOneScratchWords) * 4, s, sc)) return rc;
+  if (int rc = scratch_acquire(c, (2 * wn + 32 * wn + fsw) * 4, s, sc)) return rc;
   uint32_t* ind = reinterpret_cast<uint32_t*>(sc.p);
   uint32_t* F = ind + wn;
   uint32_t* P = F + wn;
@@ -502,12 +511,12 @@ int conv_locator(fntrs_ctx* c, fntrs_locator_t* L, const LocDesc& d, const uint3
   const uint32_t blocks = n / 256;
   if (!rc) {
     hipLaunchKernelGGL(k_conv_mark, dim3(blocks), dim3(256), 0, s, d.zin, bstart, ind, d.pos, d.ridx);
-    rc = fnt_lanes(c, n, n, 1, ind, F, fs, s);
+    rc = conv_fnt(c, n, 1, ind, F, fs, s);
   }
   if (!rc) {
     hipLaunchKernelGGL(k_conv_mul, dim3(4 * blocks), dim3(256), 0, s, (const uint32_t*)F,
                        (const uint32_t*)c->conv_tab[d.logn], P, n);
-    rc = fnt_lanes(c, n, n, 16, P, Q, fs, s);
+    rc = conv_fnt(c, n, 16, P, Q, fs, s);
   }
   if (!rc) {
     ConvFinishArgs a{Q, ind, d.ridx, c->tw, d.w, d.wfull, d.ahat, d.ahat_br, d.ahat_s, L->Avals, S, d.kr, d.logn,
@@ -525,12 +534,13 @@ int conv_locator(fntrs_ctx* c, fntrs_locator_t* L, const LocDesc& d, const uint3
 int locator_coeffs(fntrs_ctx* c, const fntrs_locator_t* L, hipStream_t s) {
   if (!L->coeffs_pending) return FNTRS_OK;
   const uint32_t n = L->n;
+  const size_t fsw = n >= (1u << kFourStepMinLog) ? kFnOneScratchWords : 0;
   Scratch sc;
-  if (int rc = scratch_acquire(c, ((size_t)n + kFnOneScratchWords) * 4, s, sc)) return rc;
+  if (int rc = scratch_acquire(c, ((size_t)n + fsw) * 4, s, sc)) return rc;
   uint32_t* G = reinterpret_cast<uint32_t*>(sc.p);
   int rc = FNTRS_OK;
   if (hipStreamWaitEvent(s, L->ready, 0) != hipSuccess) rc = fail(c, FNTRS_E_DEVICE, "stream wait failed");
-  if (!rc) rc = fnt_lanes(c, n, n, 1, L->Avals, G, G + n, s);   // A = FNT_n of its values at negated indices / n
+  if (!rc) rc = conv_fnt(c, n, 1, L->Avals, G, G + n, s);   // A = FNT_n of its values at negated indices / n
   if (!rc) {
     hipLaunchKernelGGL(k_conv_coef, dim3((L->k + 256) / 256), dim3(256), 0, s, (const uint32_t*)G, L->A, L->k, L->logn);
     if (hipGetLastError() != hipSuccess) rc = fail(c, FNTRS_E_DEVICE, "locator coefficients kernel failed");
