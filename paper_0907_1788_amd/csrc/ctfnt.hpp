@@ -24,6 +24,8 @@
 // fold(fold(v)) lies in [-1, 65536] and an unsigned min maps -1 to 65536,
 // which gives the canonical residue stored to global memory.
 #pragma once
+#include <type_traits>
+
 #include "field.hpp"
 
 namespace fntrs {
@@ -210,10 +212,13 @@ struct TwLds {
 };
 
 // ---------------------------------------------------------------- butterflies
-template <int B, int V, int S0, bool INV, class TW>
+// DIT stages S0 + I0 .. S0 + B - 1 of an item (stages below I0 already
+// applied by its loader).
+template <int B, int V, int S0, bool INV, int I0 = 0, class TW>
 __device__ __forceinline__ void dit_stages(int32_t (&x)[1 << B][V], uint32_t jp, const TW& tws) {
+  static_assert(I0 >= 0 && I0 <= B, "stages to skip");
 #pragma unroll
-  for (int i = 0; i < B; ++i) {
+  for (int i = I0; i < B; ++i) {
     const int lg = S0 + i + 1;
 #pragma unroll
     for (int cc = 0; cc < (1 << i); ++cc) {
@@ -300,10 +305,22 @@ __host__ __device__ constexpr int dif_top(int L, int BM, int p) {
 // Loaders / storers are objects with a member template
 //   item<B, H>(base, g, x)  that moves the 2^B positions base + c*H of lane
 // group g between their home (global memory or the LDS tile) and registers.
+// A first-pass loader may declare kSkip: the number of leading DIT stages
+// its items arrive with already applied.
+template <class T, class = void>
+struct loader_skip {
+  static constexpr int value = 0;
+};
+template <class T>
+struct loader_skip<T, std::void_t<decltype(T::kSkip)>> {
+  static constexpr int value = T::kSkip;
+};
+
 template <int L, int BM, int P, int V, int G, bool INV, class TW, class Ld, class St>
 __device__ __forceinline__ void dit_pass(const TW& tw, Ld& ld, St& st) {
   constexpr int B = plan_b(L, BM, P);
   constexpr int S0 = dit_s0(L, BM, P);
+  constexpr int I0 = P == 0 ? loader_skip<Ld>::value : 0;
   constexpr uint32_t H = 1u << S0;
   constexpr uint32_t ITEMS = (1u << (L - B)) * G;
   for (uint32_t q = threadIdx.x; q < ITEMS; q += blockDim.x) {
@@ -312,7 +329,7 @@ __device__ __forceinline__ void dit_pass(const TW& tw, Ld& ld, St& st) {
     const uint32_t base = blk * (H << B) + jp;
     int32_t x[1 << B][V];
     ld.template item<B, H>(base, g, x);
-    dit_stages<B, V, S0, INV>(x, jp, tw);
+    dit_stages<B, V, S0, INV, I0>(x, jp, tw);
     st.template item<B, H>(base, g, x);
   }
 }

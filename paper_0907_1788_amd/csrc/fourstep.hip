@@ -120,7 +120,11 @@ hipError_t fourstep_encode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   a.tstride_in = T;
   a.out = sa; a.ld_out = T; a.tstride_out = rows * T; a.stride_out = base.tiles * rows * T;
   a.subs = a.n >> 8;
-  FNTRS_TRY(launch(fs::k4_enc1, fs::lds_with_tables<8>(), base.tiles * a.subs * batch, a, s));
+  // zero-padded source: k <= n/4 or n/2 lets the first pass skip its first stages
+  const uint32_t grid1 = base.tiles * a.subs * batch;
+  if (4ull * base.k <= base.n) FNTRS_TRY(launch(fs::k4_enc1<2>, fs::lds_with_tables<8>(), grid1, a, s));
+  else if (2ull * base.k <= base.n) FNTRS_TRY(launch(fs::k4_enc1<1>, fs::lds_with_tables<8>(), grid1, a, s));
+  else FNTRS_TRY(launch(fs::k4_enc1<0>, fs::lds_with_tables<8>(), grid1, a, s));
   FourStepArgs b = base;
   b.in = sa; b.ld_in = T; b.tstride_in = rows * T; b.stride_in = base.tiles * rows * T;
   b.tstride_out = T;

@@ -112,8 +112,15 @@ enum LoadKind { kScratch = 0, kZeros = 1, kWeighted = 2 };
 // rounds -- the row descriptors (which may themselves be reads), then the
 // rows, then the weights -- so each round waits once for the
 // whole item (zero rows of kZeros excepted).
-template <int L, int KIND, class RowFn>
+// REP > 0 (kZeros): every input index i >= 2^(L-REP) is a zero row, i.e.
+// every position p with a nonzero low REP bits.  The first REP DIT stages
+// then only copy: each group of 2^REP positions ends up holding its first
+// value (the lower element of every pair is zero before its stage).  The
+// loader makes those copies and the pass starts at stage REP (kSkip).
+template <int L, int KIND, class RowFn, int REP = 0>
 struct GLoad {
+  static_assert(REP == 0 || KIND == kZeros, "only zero rows can be skipped");
+  static constexpr int kSkip = REP;
   const uint32_t* base;   // block base + lane tile
   uint64_t ld;
   uint32_t lane0, lanes;
@@ -149,6 +156,15 @@ struct GLoad {
 #pragma unroll
       for (int v = 0; v < kV; ++v)
         if constexpr (KIND == kWeighted) x[c][v] = ct::mulw(x[c][v], w[c]);
+    }
+    if constexpr (REP > 0) {
+      static_assert(REP <= B, "the first pass covers the copied stages");
+      constexpr int mask = (1 << REP) - 1;
+#pragma unroll
+      for (int c = 0; c < (1 << B); ++c)
+        if (c & mask)
+#pragma unroll
+          for (int v = 0; v < kV; ++v) x[c][v] = x[c & ~mask][v];
     }
   }
   template <int B, uint32_t H>
@@ -393,7 +409,9 @@ __global__ void __launch_bounds__(kNT) k4_dec4(FourStepArgs a) {
 
 // Encoder as one FNT_n of the zero-padded source, n = N1 * 256.  Pass A:
 // rows i1 + N1 i2 (zero from k on), forward, times w_n^(i1 m2) -> scratch
-// row i1*256 + m2.
+// row i1*256 + m2.  R: k <= n / 2^R, so rows with i2 >= 2^(8-R) are zero
+// and the first R stages only copy (GLoad REP).
+template <int R>
 __global__ void __launch_bounds__(kNT) k4_enc1(FourStepArgs a) {
   using Gm = Geo<8>;
   extern __shared__ uint32_t lds[];
@@ -410,8 +428,8 @@ __global__ void __launch_bounds__(kNT) k4_enc1(FourStepArgs a) {
     w = t_tw[m2];
     return (uint64_t)i1 * 256u + m2;
   };
-  GLoad<8, kZeros, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.tile * a.tstride_in, a.ld_in, wk.lane0,
-                                      a.lanes, a.vec != 0, rowf};
+  GLoad<8, kZeros, decltype(rowf), R> l0{a.in + wk.blk * a.stride_in + wk.tile * a.tstride_in, a.ld_in, wk.lane0,
+                                         a.lanes, a.vec != 0, rowf};
   ct::LdsLoad<kV, Gm::G> lm{lds};
   ct::LdsStore<kV, Gm::G, false> sm{lds};
   GStore<8, false, true, decltype(destf)> sl{a.out + wk.blk * a.stride_out + wk.tile * a.tstride_out, a.ld_out, wk.lane0, a.lanes,

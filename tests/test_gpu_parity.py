@@ -69,6 +69,8 @@ ENC_CASES = [
     (8192, 8192, 3, 1), (16384, 2048, 4, 1), (32768, 32768, 2, 1),
     # four-step FNT_n of the zero-padded source (K >= 2^14)
     (16384, 16384, 5, 1), (32768, 9000, 37, 1), (32768, 16384, 3, 2), (65536, 20000, 2, 1),
+    # k <= n/4: the first pass starts after two copy-only stages
+    (65536, 16384, 3, 1), (65536, 10000, 2, 2),
 ]
 
 
