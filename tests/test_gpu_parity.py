@@ -415,6 +415,36 @@ def test_max_length_config(ctx, kind):
     loc.release()
 
 
+def test_rate_half_full_size_sampled_lanes(ctx):
+    """k = 4096, n = 8192, 2048 lanes x 64 blocks, each direction one call as
+    the benchmark makes it: every symbol of 32 lanes (16 at each end of the
+    lane range, in the first and the last block) equals the oracle's, and
+    every lane of every block decodes back to its source."""
+    say("rate 1/2 full size, 32 lanes all symbols")
+    n, k, lanes, blocks = 8192, 4096, 2048, 64
+    b0, b1 = synth.residues(8500, (k, lanes)), synth.residues(8501, (k, lanes))
+    d0, d1 = dev(b0), dev(b1)
+    src = torch.empty((blocks, k, lanes), dtype=torch.int32, device="cuda")
+    for b in range(blocks):
+        src[b] = d0 if b % 2 == 0 else d1
+    e = torch.empty((blocks, n, lanes), dtype=torch.int32, device="cuda")
+    ctx.encode(src, e, n)
+    torch.cuda.synchronize()
+    for blk, ref in ((0, b0), (blocks - 1, b1)):
+        for sel in (slice(0, 16), slice(lanes - 16, lanes)):
+            got = host(e[blk, :, sel])
+            assert np.array_equal(got, codec.encode(ref[:, sel], n)), (blk, sel)
+    z = synth.received_positions(8502, n, k)
+    loc = ctx.locator(n, k, z)
+    recv = e[:, torch.from_numpy(z.astype(np.int64)).to("cuda"), :].contiguous()
+    del e
+    out = torch.full((blocks, k, lanes), -7, dtype=torch.int32, device="cuda")
+    ctx.decode(loc, recv, out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, src)
+    loc.release()
+
+
 @pytest.mark.parametrize("k", [16384, 65536, 2048])
 def test_max_length_other_rates(ctx, k):
     say("max-length rate", k)

@@ -336,6 +336,22 @@ def test_step5_series_is_taylor_expansion():
         assert S[j] == ref
 
 
+def test_step5_series_long_count_is_taylor_expansion():
+    """The same term-by-term definition past the oracle's 512-row blocks
+    (count 1300: blocks 0-511, 512-1023 and a ragged 1024-1299)."""
+    n, k, count = 2048, 7, 1300
+    z = synth.received_positions(33, n, k)
+    x = codec.eval_points(n, z)
+    nv = synth.residues(34, (k,)).astype(np.int64)
+    S = codec.step5_series(n, z, nv, count)
+    xinv = [field.inverse(int(xi)) for xi in x]
+    for j in (0, 1, 511, 512, 513, 1023, 1024, 1299):
+        ref = 0
+        for i in range(k):
+            ref = (ref - int(nv[i]) * pow(xinv[i], j + 1, P)) % P
+        assert S[j] == ref
+
+
 def test_locator_ahat_definition():
     n, k = 64, 16
     z = synth.received_positions(41, n, k)
