@@ -732,6 +732,23 @@ static int build_locators(fntrs_ctx* c, std::vector<fntrs_locator_t*>& Ls, hipSt
     }
     conv_S = (uint32_t)(((sum % 65536u) * (65536u >> desc[0].logn)) & 0xFFFFu);
   }
+  // short codes: one workgroup per pattern runs every step (its LDS holds a
+  // tree of n/2 points and an M-point transform, M <= n)
+  const bool small = P > 0 && Pn == P && std::all_of(Ls.begin(), Ls.end(), [](const fntrs_locator_t* L) {
+    return L->k < L->n && L->n <= kLocSmallN && 2 * pad_pow2(L->k) <= L->n && (1u << L->logm) <= L->n;
+  });
+  if (small && P == 1 && Ls[0]->k <= kLocSmallMaxK) {
+    // one short pattern: descriptor and positions by value, nothing uploaded
+    LocSmallOne one{};
+    one.d = desc[0];
+    std::copy(Ls[0]->positions.begin(), Ls[0]->positions.end(), one.z);
+    hipLaunchKernelGGL(k_locb_small1, dim3(1), dim3(kLocSmallNT), 0, s, one, (const uint32_t*)c->tw);
+    if (hipError_t le = hipGetLastError(); le != hipSuccess)
+      return fail(c, FNTRS_E_DEVICE, "locator kernel: %s", hipGetErrorString(le));
+    if (hipEventRecord(slab->ready, s) != hipSuccess) return fail(c, FNTRS_E_DEVICE, "event record failed");
+    c->used += Ls[0]->bytes;
+    return FNTRS_OK;
+  }
   // one transient allocation: descriptors | positions | tables | scratch
   const size_t desc_bytes = (P * sizeof(LocDesc) + 255) / 256 * 256;
   const size_t z_words = round_words(zall.size()), tab_words = round_words(tab.size());
@@ -767,11 +784,6 @@ static int build_locators(fntrs_ctx* c, std::vector<fntrs_locator_t*>& Ls, hipSt
   auto launch_err = [&]() { return hipGetLastError(); };
   auto st_ptr = [&](const Stage& st) { return dtab + st.start_off; };
   const uint32_t* tw = c->tw;
-  // short codes: one workgroup per pattern runs every step (its LDS holds a
-  // tree of n/2 points and an M-point transform, M <= n)
-  const bool small = P > 0 && Pn == P && std::all_of(Ls.begin(), Ls.end(), [](const fntrs_locator_t* L) {
-    return L->k < L->n && L->n <= kLocSmallN && 2 * pad_pow2(L->k) <= L->n && (1u << L->logm) <= L->n;
-  });
   if (conv) {
     if (int rc = conv_locator(c, Ls[0], desc[0], dtab + conv_off, conv_S, s)) return fail_free(rc);
   } else if (small) {

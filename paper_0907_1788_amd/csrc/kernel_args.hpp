@@ -88,6 +88,14 @@ struct LocDesc {
   int logn, logk, logm;
 };
 
+// One short-code pattern passed whole as a kernel argument (k_locb_small1):
+// its descriptor and its received positions (n <= 1024 gives k <= 512).
+constexpr uint32_t kLocSmallMaxK = 512;
+struct LocSmallOne {
+  LocDesc d;
+  uint32_t z[kLocSmallMaxK];
+};
+
 // Last pass of the logarithmic locator of one large pattern (k_conv_finish).
 struct ConvFinishArgs {
   const uint32_t* Q;      // forward FNT_n of the 16 products, [n][16]

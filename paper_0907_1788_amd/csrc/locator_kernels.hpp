@@ -292,23 +292,24 @@ __global__ void k_locb_ahat(const LocDesc* __restrict__ D, const uint32_t* __res
 constexpr uint32_t kLocSmallN = 1024;
 constexpr int kLocSmallNT = 512;
 
-__global__ void __launch_bounds__(kLocSmallNT) k_locb_small(const LocDesc* __restrict__ D,
-                                                            const uint32_t* __restrict__ tw) {
+// zin: the pattern's received positions (a global pointer, or the array of
+// a by-value argument).
+template <class Z>
+__device__ __forceinline__ void locb_small(const LocDesc& d, const Z& zin, const uint32_t* __restrict__ tw) {
   __shared__ uint32_t tree[2][kLocSmallN / 2];
   __shared__ uint32_t spec[kLocSmallN];   // A', then the transform of A
   __shared__ uint32_t vals[kLocSmallN];   // A' at the n-th roots
   __shared__ uint32_t buf[kLocSmallN / 2];
-  const LocDesc& d = D[blockIdx.x];
   const uint32_t n = d.n, K = d.k, kr = d.kr;
   const uint32_t t = threadIdx.x, nt = blockDim.x;
   // positions into the state; an erased position must read weight 0
   for (uint32_t j = t; j < n; j += nt) d.wfull[j] = 0u;
-  for (uint32_t j = t; j < kr; j += nt) d.pos[j] = d.zin[j];
+  for (uint32_t j = t; j < kr; j += nt) d.pos[j] = zin[j];
   // step 1: the tree of the K linear factors (x - x_i); the points past the
   // received ones are roots at 0, so the root holds A(x) x^(K - kr).  Round
   // h pairs monic degree-h polynomials a = x^h + a_lo, b = x^h + b_lo into
   // a b = x^(2h) + x^h (a_lo + b_lo) + a_lo b_lo, one coefficient a thread.
-  for (uint32_t j = t; j < K; j += nt) tree[0][j] = j < kr ? fsub(0u, point_of(tw, d.zin[j], d.logn)) : 0u;
+  for (uint32_t j = t; j < K; j += nt) tree[0][j] = j < kr ? fsub(0u, point_of(tw, zin[j], d.logn)) : 0u;
   __syncthreads();
   int cur = 0;
   for (uint32_t h = 1; h < K; h <<= 1) {
@@ -361,7 +362,7 @@ __global__ void __launch_bounds__(kLocSmallNT) k_locb_small(const LocDesc* __res
   // step 4: w_i = 1/A'(x_i), and the decoder weight -w_i x_i^(-1) (sign and
   // index shift of step 5) and row i at position z_i
   for (uint32_t q = t; q < kr; q += nt) {
-    const uint32_t z = d.zin[q];
+    const uint32_t z = zin[q];
     const uint32_t wi = finv(vals[z]);
     const uint32_t xinv = tw[(65536u - ((z << (16 - d.logn)) & 0xFFFFu)) & 0xFFFFu];
     d.w[q] = wi;
@@ -383,6 +384,18 @@ __global__ void __launch_bounds__(kLocSmallNT) k_locb_small(const LocDesc* __res
     d.ahat_br[bitrev(q, logm)] = v;
     d.ahat_s[q] = v;
   }
+}
+
+__global__ void __launch_bounds__(kLocSmallNT) k_locb_small(const LocDesc* __restrict__ D,
+                                                            const uint32_t* __restrict__ tw) {
+  const LocDesc& d = D[blockIdx.x];
+  locb_small(d, d.zin, tw);
+}
+
+// One pattern whose descriptor and positions come by value: no upload, and
+// no wait for one, in front of the kernel.
+__global__ void __launch_bounds__(kLocSmallNT) k_locb_small1(LocSmallOne a, const uint32_t* __restrict__ tw) {
+  locb_small(a.d, a.z, tw);
 }
 
 // ---------------------------------------------------------------- large

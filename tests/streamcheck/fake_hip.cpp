@@ -349,7 +349,7 @@ void model_fourstep(Op& x, const std::string& base, const FourStepArgs& a, uint6
 
 void model_locdesc(Op& x, const LocDesc& d) {
   const size_t n = d.n, kr = d.kr, kt = d.k, M = kr < n ? (size_t)1 << d.logm : 0;
-  touch(x, (uintptr_t)d.zin, kr * 4, false, "zin");
+  if (d.zin) touch(x, (uintptr_t)d.zin, kr * 4, false, "zin");   // null: positions passed by value
   struct {
     const void* p;
     size_t words;
@@ -416,6 +416,14 @@ std::function<void(Op&)> kernel_model(const std::string& name, dim3 grid, void**
   if (fn.rfind("k4_", 0) == 0) {
     const FourStepArgs a = *(const FourStepArgs*)args[0];
     return [fn, a, g](Op& x) { model_fourstep(x, fn, a, g); };
+  }
+  if (fn == "k_locb_small1") {   // one pattern, descriptor and positions by value
+    const fntrs::LocSmallOne a = *(const fntrs::LocSmallOne*)args[0];
+    const uint32_t* tw = *(const uint32_t* const*)args[1];
+    return [a, tw](Op& x) {
+      model_locdesc(x, a.d);
+      touch(x, (uintptr_t)tw, 65536 * 4, false, "tw");
+    };
   }
   if (fn == "k_locb_small") {
     const LocDesc* D = *(const LocDesc* const*)args[0];
