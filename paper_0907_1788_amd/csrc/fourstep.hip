@@ -68,11 +68,14 @@ hipError_t fourstep_decode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   const int LB1 = base.logn - 8;
   const uint64_t T = fs::kT;
   // scratch of `rows` rows, tile-major
+  // (the flags of a buffer used with `rows` rows follow its 2-byte values)
   auto scr_in = [&](FourStepArgs& f, const uint32_t* p, uint64_t rows) {
     f.in = p; f.ld_in = T; f.tstride_in = rows * T; f.stride_in = tiles * rows * T;
+    f.foff_in = 2 * (uint64_t)batch * f.stride_in;
   };
   auto scr_out = [&](FourStepArgs& f, uint32_t* p, uint64_t rows) {
     f.out = p; f.ld_out = T; f.tstride_out = rows * T; f.stride_out = tiles * rows * T;
+    f.foff_out = 2 * (uint64_t)batch * f.stride_out;
   };
   FourStepArgs user = base;   // the caller's buffers are row-major
   user.tstride_in = T;
@@ -119,6 +122,7 @@ hipError_t fourstep_encode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   FourStepArgs a = base;
   a.tstride_in = T;
   a.out = sa; a.ld_out = T; a.tstride_out = rows * T; a.stride_out = base.tiles * rows * T;
+  a.foff_out = 2 * (uint64_t)batch * a.stride_out;   // the flags follow the 2-byte values
   a.subs = a.n >> 8;
   // zero-padded source: k <= n/4 or n/2 lets the first pass skip its first stages
   const uint32_t grid1 = base.tiles * a.subs * batch;
@@ -127,6 +131,7 @@ hipError_t fourstep_encode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   else FNTRS_TRY(launch(fs::k4_enc1<0>, fs::lds_with_tables<8>(), grid1, a, s));
   FourStepArgs b = base;
   b.in = sa; b.ld_in = T; b.tstride_in = rows * T; b.stride_in = base.tiles * rows * T;
+  b.foff_in = 2 * (uint64_t)batch * b.stride_in;
   b.tstride_out = T;
   b.subs = 256;
   switch (base.logn) {

@@ -76,25 +76,26 @@ __device__ __forceinline__ void zero_item(int32_t (&x)[V]) {
 
 // Scratch rows move as whole vectors of kV lanes: every lane tile of a
 // scratch buffer is complete (the first kernel writes its padding lanes,
-// which it reads as zero), vectors are kV-aligned, and scratch values stay
-// in the lazy range (|v| < 2^17) instead of being made canonical.
-__device__ __forceinline__ void scratch_get(const uint32_t* p, int32_t (&x)[kV]) {
-  if constexpr (kV == 2) {
-    const u32x2 t = *(const FNTRS_GLOBAL u32x2*)gptr(p);
-    x[0] = (int32_t)t.x; x[1] = (int32_t)t.y;
-  } else {
-#pragma unroll
-    for (int v = 0; v < kV; ++v) x[v] = (int32_t)gptr(p)[v];
-  }
+// which it reads as zero) and vectors are kV-aligned.  They hold canonical
+// residues in 17 bits: the low 16 bits of a thread's two lanes share one
+// word at element index e (byte 2e of the buffer), and their bit 16 (set
+// only for 65536) one byte at foff + e/2, so a buffer of E elements moves
+// 2.5 E bytes, not 4 E.
+static_assert(kV == 2, "scratch packs the two lanes of a thread");
+__device__ __forceinline__ void scratch_get(const uint32_t* org, uint64_t foff, const uint32_t* p,
+                                            int32_t (&x)[kV]) {
+  const uint64_t e = (uint64_t)(p - org);
+  const uint32_t t = *(const FNTRS_GLOBAL uint32_t*)gptr((const uint32_t*)((const uint16_t*)org + e));
+  const uint32_t f = *(const FNTRS_GLOBAL uint8_t*)gptr((const uint8_t*)org + foff + (e >> 1));
+  x[0] = (int32_t)((t & 0xFFFFu) | ((f & 1u) << 16));
+  x[1] = (int32_t)((t >> 16) | ((f & 2u) << 15));
 }
-__device__ __forceinline__ void scratch_put(uint32_t* p, const int32_t (&x)[kV]) {
-  if constexpr (kV == 2) {
-    const u32x2 t = {(uint32_t)x[0], (uint32_t)x[1]};
-    *(FNTRS_GLOBAL u32x2*)gptr(p) = t;
-  } else {
-#pragma unroll
-    for (int v = 0; v < kV; ++v) gptr(p)[v] = (uint32_t)x[v];
-  }
+// y: lazy values (|y| < 2^23), stored canonical.
+__device__ __forceinline__ void scratch_put(const uint32_t* org, uint64_t foff, uint32_t* p, const int32_t (&y)[kV]) {
+  const uint64_t e = (uint64_t)(p - org);
+  const uint32_t c0 = ct::canon(y[0]), c1 = ct::canon(y[1]);
+  *(FNTRS_GLOBAL uint32_t*)gptr((uint32_t*)((uint16_t*)org + e)) = (c0 & 0xFFFFu) | (c1 << 16);
+  *(FNTRS_GLOBAL uint8_t*)gptr((uint8_t*)org + foff + (e >> 1)) = (uint8_t)((c0 >> 16) | ((c1 >> 16) << 1));
 }
 
 // Where a loader's rows come from and what it does to them:
@@ -126,6 +127,8 @@ struct GLoad {
   uint32_t lane0, lanes;
   bool vec;
   RowFn rowf;
+  const uint32_t* org = nullptr;   // kScratch: the buffer's origin and the
+  uint64_t foff = 0;               // byte offset of its flags
   template <int B, bool WHOLE>
   __device__ __forceinline__ void rows(uint32_t ib, uint32_t g, int32_t (&x)[1 << B][kV]) {
     uint64_t r[1 << B];
@@ -139,7 +142,7 @@ struct GLoad {
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c) {
       if constexpr (KIND == kScratch) {
-        scratch_get(base + r[c] * kT + g * kV, x[c]);
+        scratch_get(org, foff, base + r[c] * kT + g * kV, x[c]);
       } else if constexpr (KIND == kZeros) {
         // zero rows (the encoder's padding: the top rows of every
         // sub-transform, a whole wave at a time) issue no read
@@ -190,6 +193,8 @@ struct GStore {
   uint32_t lane0, lanes;
   bool vec;
   DestFn destf;
+  const uint32_t* org = nullptr;   // SCRATCH: the buffer's origin and the
+  uint64_t foff = 0;               // byte offset of its flags
   template <int B, uint32_t H, bool WHOLE>
   __device__ __forceinline__ void rows(uint32_t pb, uint32_t g, int32_t (&x)[1 << B][kV]) {
     uint64_t r[1 << B];
@@ -206,7 +211,7 @@ struct GStore {
         int32_t y[kV];
 #pragma unroll
         for (int v = 0; v < kV; ++v) y[v] = ct::mulw(x[c][v], w[c]);
-        scratch_put(base + r[c] * kT + g * kV, y);
+        scratch_put(org, foff, base + r[c] * kT + g * kV, y);
       } else {
         if (r[c] == ~0ull) continue;
         ct::store_lanes<kV, WHOLE>(const_cast<uint32_t*>(rowp(base, ld, r[c], g)), lane0 + g * kV, lanes, x[c]);
@@ -266,7 +271,7 @@ __global__ void __launch_bounds__(kNT) k4_dec1(FourStepArgs a) {
   ct::LdsLoad<kV, Gm::G> lm{lds};
   ct::LdsStore<kV, Gm::G, false> sm{lds};
   GStore<LA, false, true, decltype(destf)> sl{a.out + wk.blk * a.stride_out + wk.tile * a.tstride_out, a.ld_out, wk.lane0, a.lanes,
-                                        a.vec != 0, destf};
+                                        a.vec != 0, destf, a.out, a.foff_out};
   using TW = typename Gm::TwType;
   const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
   ct::dit<LA, Gm::BM, kV, Gm::G, true>(tws, l0, lm, sm, sl);
@@ -311,13 +316,13 @@ __global__ void __launch_bounds__(kNT) k4_dec2(FourStepArgs a) {
     return (uint64_t)m2 * (1u << LB2) + mp;
   };
   GLoad<LB1, kScratch, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.tile * a.tstride_in, a.ld_in, wk.lane0, a.lanes, a.vec != 0,
-                                rowf};
+                                rowf, a.in, a.foff_in};
   ct::LdsLoad<kV, Gm::G> ll{lds};
   ct::LdsStore<kV, Gm::G, false> sl{lds};
   ct::LdsStore<kV, Gm::G, true> slf{lds};
   MaskStore<Gm::G> ms{lds, m2, a.k};
   GStore<LB2, true, true, decltype(destf)> sg{a.out + wk.blk * a.stride_out + wk.tile * a.tstride_out, a.ld_out, wk.lane0, a.lanes,
-                                        a.vec != 0, destf};
+                                        a.vec != 0, destf, a.out, a.foff_out};
   using TW = typename Gm::TwType;
   const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
   ct::dit<LB1, Gm::BM, kV, Gm::G, true>(tws, l0, ll, sl, ms);
@@ -366,13 +371,13 @@ __global__ void __launch_bounds__(kNT) k4_dec3(FourStepArgs a) {
     return (uint64_t)m2p * 256u + m2pp;
   };
   GLoad<8, kScratch, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.tile * a.tstride_in, a.ld_in, wk.lane0,
-                                        a.lanes, a.vec != 0, rowf};
+                                        a.lanes, a.vec != 0, rowf, a.in, a.foff_in};
   ct::LdsLoad<kV, Gm::G> ll{lds};
   ct::LdsStore<kV, Gm::G, false> sl{lds};
   ct::LdsStore<kV, Gm::G, true> slf{lds};
   AhatStore<Gm::G> ah{lds, t_ah};
   GStore<8, true, true, decltype(destf)> sg{a.out + wk.blk * a.stride_out + wk.tile * a.tstride_out, a.ld_out, wk.lane0, a.lanes,
-                                      a.vec != 0, destf};
+                                      a.vec != 0, destf, a.out, a.foff_out};
   using TW = typename Gm::TwType;
   const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
   ct::dit<8, Gm::BM, kV, Gm::G, false>(tws, l0, ll, sl, ah);
@@ -397,7 +402,7 @@ __global__ void __launch_bounds__(kNT) k4_dec4(FourStepArgs a) {
     return m < a.k ? (uint64_t)m : ~0ull;
   };
   GLoad<LB, kScratch, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.tile * a.tstride_in, a.ld_in, wk.lane0,
-                                         a.lanes, a.vec != 0, rowf};
+                                         a.lanes, a.vec != 0, rowf, a.in, a.foff_in};
   ct::LdsLoad<kV, Gm::G> ll{lds};
   ct::LdsStore<kV, Gm::G, false> sl{lds};
   GStore<LB, false, false, decltype(destf)> sg{a.out + wk.blk * a.stride_out + wk.tile * a.tstride_out, a.ld_out, wk.lane0, a.lanes,
@@ -433,7 +438,7 @@ __global__ void __launch_bounds__(kNT) k4_enc1(FourStepArgs a) {
   ct::LdsLoad<kV, Gm::G> lm{lds};
   ct::LdsStore<kV, Gm::G, false> sm{lds};
   GStore<8, false, true, decltype(destf)> sl{a.out + wk.blk * a.stride_out + wk.tile * a.tstride_out, a.ld_out, wk.lane0, a.lanes,
-                                       a.vec != 0, destf};
+                                       a.vec != 0, destf, a.out, a.foff_out};
   using TW = typename Gm::TwType;
   const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
   ct::dit<8, Gm::BM, kV, Gm::G, false>(tws, l0, lm, sm, sl);
@@ -457,7 +462,7 @@ __global__ void __launch_bounds__(kNT) k4_enc2(FourStepArgs a) {
     return (a.rows_out && r >= a.rows_out) ? ~0ull : (uint64_t)r;
   };
   GLoad<LB, kScratch, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.tile * a.tstride_in, a.ld_in, wk.lane0,
-                                         a.lanes, a.vec != 0, rowf};
+                                         a.lanes, a.vec != 0, rowf, a.in, a.foff_in};
   ct::LdsLoad<kV, Gm::G> lm{lds};
   ct::LdsStore<kV, Gm::G, false> sm{lds};
   GStore<LB, false, false, decltype(destf)> sl{a.out + wk.blk * a.stride_out + wk.tile * a.tstride_out, a.ld_out, wk.lane0, a.lanes,

@@ -64,6 +64,7 @@ struct FourStepArgs {
   uint32_t full, tiles, subs, vec;   // subs: sub-transforms per block
   uint32_t rows_out;                 // encoder: only rows < rows_out of out are written (0: all n)
   uint64_t tstride_in, tstride_out;  // elements between lane tiles (set by the four-step launchers)
+  uint64_t foff_in, foff_out;        // scratch in / out: byte offset of its bit-16 flags (four-step launchers)
 };
 
 // One erasure pattern of a locator batch: where its positions come from,
