@@ -76,8 +76,10 @@ void lds_attr_once(const void* fn, size_t bytes) {
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-int upload_async(fntrs_ctx* c, void* dst, const void* src, size_t bytes, hipStream_t s) {
-  if (bytes == 0) return FNTRS_OK;
+// A pinned staging slot of at least `bytes`, idle (its last use complete);
+// the caller fills it, enqueues what reads it, then records slot->ev on that
+// stream and sets slot->pending.
+int stage_slot(fntrs_ctx* c, size_t bytes, fntrs_ctx::StageSlot*& out) {
   constexpr size_t kMaxSlots = 32;
   fntrs_ctx::StageSlot* slot = nullptr;
   for (auto& q : c->stage) {   // an idle slot that is large enough
@@ -105,6 +107,14 @@ int upload_async(fntrs_ctx* c, void* dst, const void* src, size_t bytes, hipStre
       slot->bytes = sz;
     }
   }
+  out = slot;
+  return FNTRS_OK;
+}
+
+int upload_async(fntrs_ctx* c, void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return FNTRS_OK;
+  fntrs_ctx::StageSlot* slot = nullptr;
+  if (int rc = stage_slot(c, bytes, slot)) return rc;
   std::memcpy(slot->p, src, bytes);
   HIP_TRY(c, hipMemcpyAsync(dst, slot->p, bytes, hipMemcpyHostToDevice, s));
   HIP_TRY(c, hipEventRecord(slot->ev, s));
@@ -719,18 +729,34 @@ static int build_locators(fntrs_ctx* c, std::vector<fntrs_locator_t*>& Ls, hipSt
   }
   const Stage weights = add_stage({0, Pn}, [](const fntrs_locator_t* L) { return (uint64_t)L->k; });
   const Stage ahat = add_stage({0, Pn}, [](const fntrs_locator_t* L) { return 1ull << L->logm; });
-  // the logarithmic route: the first rank of every 256 positions goes up
-  // with the tables
-  const size_t conv_off = tab.size();
-  uint32_t conv_S = 0;
   if (conv) {
+    // the logarithmic route: the mark kernel reads the first rank of every
+    // 256 positions and the positions straight from pinned host memory, so
+    // no copy to the device goes ahead of it
     const auto& z = Ls[0]->positions;
+    const size_t nb = desc[0].n / 256 + 1;
+    fntrs_ctx::StageSlot* slot = nullptr;
+    if (int rc = stage_slot(c, (nb + z.size()) * 4, slot)) return rc;
+    uint32_t* h = static_cast<uint32_t*>(slot->p);
     uint64_t sum = 0, q = 0;
-    for (uint32_t b = 0; b <= desc[0].n / 256; ++b) {
+    for (uint32_t b = 0; b < nb; ++b) {
       while (q < z.size() && z[q] < b * 256u) sum += z[q++];
-      tab.push_back((uint32_t)q);
+      h[b] = (uint32_t)q;
     }
-    conv_S = (uint32_t)(((sum % 65536u) * (65536u >> desc[0].logn)) & 0xFFFFu);
+    std::copy(z.begin(), z.end(), h + nb);
+    const uint32_t S = (uint32_t)(((sum % 65536u) * (65536u >> desc[0].logn)) & 0xFFFFu);
+    void* dp = nullptr;
+    if (hipHostGetDevicePointer(&dp, slot->p, 0) != hipSuccess)
+      return fail(c, FNTRS_E_DEVICE, "no device address for the staged positions");
+    LocDesc d = desc[0];
+    d.zin = static_cast<const uint32_t*>(dp) + nb;
+    int rc = conv_locator(c, Ls[0], d, static_cast<const uint32_t*>(dp), S, s);
+    if (hipEventRecord(slot->ev, s) != hipSuccess && !rc) rc = fail(c, FNTRS_E_DEVICE, "event record failed");
+    slot->pending = true;
+    if (rc) return rc;
+    if (hipEventRecord(slab->ready, s) != hipSuccess) return fail(c, FNTRS_E_DEVICE, "event record failed");
+    c->used += Ls[0]->bytes;
+    return FNTRS_OK;
   }
   // short codes: one workgroup per pattern runs every step (its LDS holds a
   // tree of n/2 points and an M-point transform, M <= n)
@@ -784,9 +810,7 @@ static int build_locators(fntrs_ctx* c, std::vector<fntrs_locator_t*>& Ls, hipSt
   auto launch_err = [&]() { return hipGetLastError(); };
   auto st_ptr = [&](const Stage& st) { return dtab + st.start_off; };
   const uint32_t* tw = c->tw;
-  if (conv) {
-    if (int rc = conv_locator(c, Ls[0], desc[0], dtab + conv_off, conv_S, s)) return fail_free(rc);
-  } else if (small) {
+  if (small) {
     hipLaunchKernelGGL(k_locb_small, dim3(P), dim3(kLocSmallNT), 0, s, D, tw);
   } else {
     hipLaunchKernelGGL(k_locb_prep, dim3((prep.total + 255) / 256), dim3(256), 0, s, D, st_ptr(prep), P);

@@ -451,11 +451,24 @@ std::function<void(Op&)> kernel_model(const std::string& name, dim3 grid, void**
     uint32_t* ind = *(uint32_t* const*)args[2];
     uint32_t* pos = *(uint32_t* const*)args[3];
     uint32_t* ridx = *(uint32_t* const*)args[4];
+    // tables read from pinned host memory: the bytes as of the launch
+    auto pinned_copy = [](const void* p, size_t bytes) {
+      Alloc* a = find_alloc((uintptr_t)p);
+      std::shared_ptr<std::vector<uint8_t>> v;
+      if (a && a->kind == 2 && (uintptr_t)p + bytes <= a->hi)
+        v = std::make_shared<std::vector<uint8_t>>((const uint8_t*)p, (const uint8_t*)p + bytes);
+      return v;
+    };
+    const auto sb = pinned_copy(bstart, ((size_t)g + 1) * 4);
+    const auto sz = sb ? pinned_copy(zin, (size_t)bstart[g] * 4) : nullptr;
     return [=](Op& x) {
       const size_t n = (size_t)g * 256;
       touch(x, (uintptr_t)bstart, ((size_t)g + 1) * 4, false, "bstart");
       const uint32_t kr = bstart[g];   // the host table: every rank below n
       touch(x, (uintptr_t)zin, (size_t)kr * 4, false, "zin");
+      if ((sb && std::memcmp(sb->data(), bstart, sb->size()) != 0) ||
+          (sz && std::memcmp(sz->data(), zin, sz->size()) != 0))
+        error("pinned staging overwritten by the host before its kernel ran (" + x.what + ")");
       touch(x, (uintptr_t)ind, n * 4, true, "ind");
       touch(x, (uintptr_t)pos, (size_t)kr * 4, true, "pos");
       touch(x, (uintptr_t)ridx, n * 4, true, "ridx");
@@ -845,6 +858,14 @@ hipError_t hipHostMalloc(void** p, size_t bytes, unsigned int) {
   a.kind = 2;
   S().allocs[a.lo] = a;
   *p = q;
+  return hipSuccess;
+}
+// Pinned host memory is read by kernels at its own address.
+hipError_t hipHostGetDevicePointer(void** d, void* h, unsigned int) {
+  std::lock_guard<std::mutex> lk(S().mu);
+  Alloc* a = find_alloc((uintptr_t)h);
+  if (!d || !a || a->kind != 2) return hipErrorInvalidValue;
+  *d = h;
   return hipSuccess;
 }
 hipError_t hipHostFree(void* p) {
