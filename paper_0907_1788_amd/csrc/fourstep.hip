@@ -69,9 +69,13 @@ hipError_t fourstep_decode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   const uint64_t T = fs::kT;
   // scratch of `rows` rows, tile-major
   // (the flags of a buffer used with `rows` rows follow its 2-byte values)
-  auto scr_in = [&](FourStepArgs& f, const uint32_t* p, uint64_t rows) {
+  // sub_fast: work items go sub-transform first (fs::work_of), for the
+  // kernels that read scratch and write scratch (K2, K3); K4 writes the
+  // caller's rows and keeps the tile-first order.
+  auto scr_in = [&](FourStepArgs& f, const uint32_t* p, uint64_t rows, bool sub_fast) {
     f.in = p; f.ld_in = T; f.tstride_in = rows * T; f.stride_in = tiles * rows * T;
     f.foff_in = 2 * (uint64_t)batch * f.stride_in;
+    f.sub_fast = sub_fast ? 1u : 0u;
   };
   auto scr_out = [&](FourStepArgs& f, uint32_t* p, uint64_t rows) {
     f.out = p; f.ld_out = T; f.tstride_out = rows * T; f.stride_out = tiles * rows * T;
@@ -88,7 +92,7 @@ hipError_t fourstep_decode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   if (base.k == base.n) {
     // erasure-free: the inverse transform's pass B writes the source
     FourStepArgs b = user;
-    scr_in(b, sa, base.n);
+    scr_in(b, sa, base.n, false);
     b.subs = 256;
     b.M = base.n;
     return dec4_any(LB1, b, tiles * b.subs * batch, s);
@@ -96,19 +100,19 @@ hipError_t fourstep_decode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   const int LB2 = base.logm - 8;
   // K2: sa -> sb (M rows)
   FourStepArgs b = user;
-  scr_in(b, sa, base.n);
+  scr_in(b, sa, base.n, true);
   scr_out(b, sb, base.M);
   b.subs = 256;
   FNTRS_TRY(dec2_any(LB1, LB2, b, tiles * b.subs * batch, s));
   // K3: sb -> sa (M rows)
   FourStepArgs c = user;
-  scr_in(c, sb, base.M);
+  scr_in(c, sb, base.M, true);
   scr_out(c, sa, base.M);
   c.subs = base.M >> 8;
   FNTRS_TRY(launch(fs::k4_dec3, fs::lds_with_tables<8>(), tiles * c.subs * batch, c, s));
   // K4: sa -> dst
   FourStepArgs d = user;
-  scr_in(d, sa, base.M);
+  scr_in(d, sa, base.M, false);
   d.subs = 256;
   return dec4_any(LB2, d, tiles * d.subs * batch, s);
 }
@@ -132,6 +136,9 @@ hipError_t fourstep_encode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   FourStepArgs b = base;
   b.in = sa; b.ld_in = T; b.tstride_in = rows * T; b.stride_in = base.tiles * rows * T;
   b.foff_in = 2 * (uint64_t)batch * b.stride_in;
+  // sub-transform first when the output's row segments are whole 128-byte
+  // lines (no two lane tiles share one)
+  b.sub_fast = (base.ld_out % T == 0 && base.stride_out % T == 0 && (uintptr_t)base.out % (4 * T) == 0) ? 1u : 0u;
   b.tstride_out = T;
   b.subs = 256;
   switch (base.logn) {

@@ -46,7 +46,14 @@ using Geo = ct::Geo<L, kT, kNT, kV>;
 // rows of one tile lie in one contiguous region of rows*128 bytes instead of
 // being spread over the whole buffer at a stride of ld*4 bytes.
 
-// Decodes blockIdx into (lane tile, sub-transform, block).
+// Decodes blockIdx into (lane tile, sub-transform, block).  Consecutive
+// work items of one XCD run together and share its L2.  Items are ordered
+// lane tile first where neighbouring tiles share cache lines (row segments of
+// a row-major buffer whose lane count is not a multiple of the tile), else
+// sub-transform first (sub_fast): neighbouring sub-transforms share the lines
+// of a packed scratch buffer they read, whose 128-byte lines hold the 64-byte
+// value segments of two neighbouring rows and the 16-byte flag segments of
+// eight, rows that belong to neighbouring sub-transforms of one tile.
 struct Work {
   uint32_t tile, sub;
   uint64_t blk;
@@ -55,10 +62,17 @@ struct Work {
 __device__ __forceinline__ Work work_of(const FourStepArgs& a) {
   const uint32_t bid = ct::xcd_remap(blockIdx.x, gridDim.x);
   Work w;
-  w.tile = bid % a.tiles;
-  const uint32_t r = bid / a.tiles;
-  w.sub = r % a.subs;
-  w.blk = r / a.subs;
+  if (a.sub_fast) {
+    w.sub = bid % a.subs;
+    const uint32_t r = bid / a.subs;
+    w.tile = r % a.tiles;
+    w.blk = r / a.tiles;
+  } else {
+    w.tile = bid % a.tiles;
+    const uint32_t r = bid / a.tiles;
+    w.sub = r % a.subs;
+    w.blk = r / a.subs;
+  }
   w.lane0 = w.tile * kT;
   return w;
 }

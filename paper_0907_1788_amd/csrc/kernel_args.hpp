@@ -65,6 +65,7 @@ struct FourStepArgs {
   uint32_t rows_out;                 // encoder: only rows < rows_out of out are written (0: all n)
   uint64_t tstride_in, tstride_out;  // elements between lane tiles (set by the four-step launchers)
   uint64_t foff_in, foff_out;        // scratch in / out: byte offset of its bit-16 flags (four-step launchers)
+  uint32_t sub_fast;                 // work items ordered sub-transform first (see fs::work_of)
 };
 
 // One erasure pattern of a locator batch: where its positions come from,
