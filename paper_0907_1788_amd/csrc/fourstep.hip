@@ -7,6 +7,12 @@ namespace fntrs {
 
 namespace {
 
+uint32_t ilog2_u64(uint64_t v) {
+  uint32_t l = 0;
+  while ((v >> l) > 1) ++l;
+  return l;
+}
+
 template <class K>
 hipError_t launch(K kernel, size_t lds, uint32_t blocks, const FourStepArgs& a, hipStream_t s) {
   lds_attr_once((const void*)kernel, lds);
@@ -19,6 +25,21 @@ hipError_t launch(K kernel, size_t lds, uint32_t blocks, const FourStepArgs& a, 
     hipError_t e_ = (x);                \
     if (e_ != hipSuccess) return e_;    \
   } while (0)
+
+// Zeroes the given escape bitmaps (byte ranges of whole 16-byte vectors).
+hipError_t clear_bitmaps(const FsClearArgs& c, hipStream_t s) {
+  const uint64_t words = c.words[0] + c.words[1] + c.words[2];
+  const uint32_t blocks = (uint32_t)std::min<uint64_t>(1024, (words / 4 + 255) / 256 + 1);
+  hipLaunchKernelGGL(fs::k_fs_clear, dim3(blocks), dim3(256), 0, s, c);
+  return hipGetLastError();
+}
+
+// Byte offsets of the escape bitmaps in a scratch buffer of batch*rows*lds_
+// words (4 bytes per element): the 2-byte values and flag bytes of a use take
+// the first 2.5 bytes per element, the bitmaps (rows*tiles/8 bytes per block
+// each) start at 3 bytes per element.
+uint64_t bitmap_at(uint32_t batch, uint64_t rows, uint64_t lds_) { return 3 * (uint64_t)batch * rows * lds_; }
+uint64_t bitmap_bytes(uint32_t batch, uint32_t tiles, uint64_t rows) { return (uint64_t)batch * tiles * rows / 8; }
 
 template <int LB>
 hipError_t dec4(const FourStepArgs& a, uint32_t blocks, hipStream_t s) {
@@ -72,27 +93,46 @@ hipError_t fourstep_decode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   // sub_fast: work items go sub-transform first (fs::work_of), for the
   // kernels that read scratch and write scratch (K2, K3); K4 writes the
   // caller's rows and keeps the tile-first order.
-  auto scr_in = [&](FourStepArgs& f, const uint32_t* p, uint64_t rows, bool sub_fast) {
+  auto scr_in = [&](FourStepArgs& f, const uint32_t* p, uint64_t rows, uint64_t boff, bool sub_fast) {
     f.in = p; f.ld_in = T; f.tstride_in = rows * T; f.stride_in = tiles * rows * T;
     f.foff_in = 2 * (uint64_t)batch * f.stride_in;
+    f.boff_in = boff; f.rlog_in = ilog2_u64(rows);
     f.sub_fast = sub_fast ? 1u : 0u;
   };
-  auto scr_out = [&](FourStepArgs& f, uint32_t* p, uint64_t rows) {
+  // slog: log2 of the writer's row split (rows i*S + m)
+  auto scr_out = [&](FourStepArgs& f, uint32_t* p, uint64_t rows, uint64_t boff, uint32_t slog) {
     f.out = p; f.ld_out = T; f.tstride_out = rows * T; f.stride_out = tiles * rows * T;
     f.foff_out = 2 * (uint64_t)batch * f.stride_out;
+    f.boff_out = boff; f.rlog_out = ilog2_u64(rows); f.slog_out = slog;
   };
+  const uint64_t n = base.n, M = base.M;
+  // bitmaps: K1's rows and K3's rows in sa, K2's rows in sb
+  const uint64_t bA1 = bitmap_at(batch, n, lds_), bA2 = bA1 + bitmap_bytes(batch, tiles, n);
+  const uint64_t bB = bitmap_at(batch, M, lds_);
+  {
+    FsClearArgs cl{};
+    cl.p[0] = (uint32_t*)((uint8_t*)sa + bA1);
+    cl.words[0] = bitmap_bytes(batch, tiles, n) / 4;
+    if (base.k != base.n) {
+      cl.p[1] = (uint32_t*)((uint8_t*)sa + bA2);
+      cl.words[1] = bitmap_bytes(batch, tiles, M) / 4;
+      cl.p[2] = (uint32_t*)((uint8_t*)sb + bB);
+      cl.words[2] = bitmap_bytes(batch, tiles, M) / 4;
+    }
+    FNTRS_TRY(clear_bitmaps(cl, s));
+  }
   FourStepArgs user = base;   // the caller's buffers are row-major
   user.tstride_in = T;
   user.tstride_out = T;
   // K1: recv -> sa (n rows)
   FourStepArgs a = user;
-  scr_out(a, sa, a.n);
+  scr_out(a, sa, n, bA1, 8);
   a.subs = a.n >> 8;
   FNTRS_TRY(launch(fs::k4_dec1<8>, fs::lds_with_tables<8>(), tiles * a.subs * batch, a, s));
   if (base.k == base.n) {
     // erasure-free: the inverse transform's pass B writes the source
     FourStepArgs b = user;
-    scr_in(b, sa, base.n, false);
+    scr_in(b, sa, n, bA1, false);
     b.subs = 256;
     b.M = base.n;
     return dec4_any(LB1, b, tiles * b.subs * batch, s);
@@ -100,19 +140,19 @@ hipError_t fourstep_decode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   const int LB2 = base.logm - 8;
   // K2: sa -> sb (M rows)
   FourStepArgs b = user;
-  scr_in(b, sa, base.n, true);
-  scr_out(b, sb, base.M);
+  scr_in(b, sa, n, bA1, true);
+  scr_out(b, sb, M, bB, base.logm - 8);
   b.subs = 256;
   FNTRS_TRY(dec2_any(LB1, LB2, b, tiles * b.subs * batch, s));
   // K3: sb -> sa (M rows)
   FourStepArgs c = user;
-  scr_in(c, sb, base.M, true);
-  scr_out(c, sa, base.M);
+  scr_in(c, sb, M, bB, true);
+  scr_out(c, sa, M, bA2, 8);
   c.subs = base.M >> 8;
   FNTRS_TRY(launch(fs::k4_dec3, fs::lds_with_tables<8>(), tiles * c.subs * batch, c, s));
   // K4: sa -> dst
   FourStepArgs d = user;
-  scr_in(d, sa, base.M, false);
+  scr_in(d, sa, M, bA2, false);
   d.subs = 256;
   return dec4_any(LB2, d, tiles * d.subs * batch, s);
 }
@@ -127,6 +167,14 @@ hipError_t fourstep_encode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   a.tstride_in = T;
   a.out = sa; a.ld_out = T; a.tstride_out = rows * T; a.stride_out = base.tiles * rows * T;
   a.foff_out = 2 * (uint64_t)batch * a.stride_out;   // the flags follow the 2-byte values
+  const uint64_t bA = bitmap_at(batch, rows, lds_);
+  a.boff_out = bA; a.rlog_out = base.logn; a.slog_out = 8;
+  {
+    FsClearArgs cl{};
+    cl.p[0] = (uint32_t*)((uint8_t*)sa + bA);
+    cl.words[0] = bitmap_bytes(batch, base.tiles, rows) / 4;
+    FNTRS_TRY(clear_bitmaps(cl, s));
+  }
   a.subs = a.n >> 8;
   // zero-padded source: k <= n/4 or n/2 lets the first pass skip its first stages
   const uint32_t grid1 = base.tiles * a.subs * batch;
@@ -136,6 +184,7 @@ hipError_t fourstep_encode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   FourStepArgs b = base;
   b.in = sa; b.ld_in = T; b.tstride_in = rows * T; b.stride_in = base.tiles * rows * T;
   b.foff_in = 2 * (uint64_t)batch * b.stride_in;
+  b.boff_in = bA; b.rlog_in = base.logn;
   // sub-transform first when the output's row segments are whole 128-byte
   // lines (no two lane tiles share one)
   b.sub_fast = (base.ld_out % T == 0 && base.stride_out % T == 0 && (uintptr_t)base.out % (4 * T) == 0) ? 1u : 0u;

@@ -92,24 +92,42 @@ __device__ __forceinline__ void zero_item(int32_t (&x)[V]) {
 // scratch buffer is complete (the first kernel writes its padding lanes,
 // which it reads as zero) and vectors are kV-aligned.  They hold canonical
 // residues in 17 bits: the low 16 bits of a thread's two lanes share one
-// word at element index e (byte 2e of the buffer), and their bit 16 (set
-// only for 65536) one byte at foff + e/2, so a buffer of E elements moves
-// 2.5 E bytes, not 4 E.
+// word at element index e (byte 2e of the buffer).  Bit 16 is set only for
+// 65536, about once in 2^16 elements, so it is stored by exception: where a
+// lane of a row of a tile holds 65536, the row's 16 threads store one byte
+// each at foff + e/2 (bit 0: first lane, bit 1: second) and the row's bit is
+// set in an escape bitmap at boff.  That bitmap is cleared before the writer
+// runs and ordered by reader: a writer's rows are i*S + m and row i*S + m is
+// bit m*(R/S) + i of its tile's R bits, so the R/S rows one reading
+// sub-transform m takes are R/S consecutive bits.  A reader whose bits are
+// all clear (most of them) reads no flag byte.
 static_assert(kV == 2, "scratch packs the two lanes of a thread");
-__device__ __forceinline__ void scratch_get(const uint32_t* org, uint64_t foff, const uint32_t* p,
-                                            int32_t (&x)[kV]) {
+__device__ __forceinline__ void scratch_get(const uint32_t* org, const uint32_t* p, int32_t (&x)[kV]) {
   const uint64_t e = (uint64_t)(p - org);
   const uint32_t t = *(const FNTRS_GLOBAL uint32_t*)gptr((const uint32_t*)((const uint16_t*)org + e));
-  const uint32_t f = *(const FNTRS_GLOBAL uint8_t*)gptr((const uint8_t*)org + foff + (e >> 1));
-  x[0] = (int32_t)((t & 0xFFFFu) | ((f & 1u) << 16));
-  x[1] = (int32_t)((t >> 16) | ((f & 2u) << 15));
+  x[0] = (int32_t)(t & 0xFFFFu);
+  x[1] = (int32_t)(t >> 16);
 }
-// y: lazy values (|y| < 2^23), stored canonical.
-__device__ __forceinline__ void scratch_put(const uint32_t* org, uint64_t foff, uint32_t* p, const int32_t (&y)[kV]) {
+__device__ __forceinline__ void scratch_fix(const uint32_t* org, uint64_t foff, const uint32_t* p, int32_t (&x)[kV]) {
+  const uint64_t e = (uint64_t)(p - org);
+  const uint32_t f = *(const FNTRS_GLOBAL uint8_t*)gptr((const uint8_t*)org + foff + (e >> 1));
+  x[0] |= (int32_t)((f & 1u) << 16);
+  x[1] |= (int32_t)((f & 2u) << 15);
+}
+// y: lazy values (|y| < 2^23), stored canonical; bit: the row's bit in the
+// escape bitmap (uint32 words at bmap).  Called by all 16 threads of a row
+// (lanes 16j .. 16j+15 of a wave) together.
+__device__ __forceinline__ void scratch_put(const uint32_t* org, uint64_t foff, uint32_t* bmap, uint64_t bit,
+                                            uint32_t* p, const int32_t (&y)[kV]) {
   const uint64_t e = (uint64_t)(p - org);
   const uint32_t c0 = ct::canon(y[0]), c1 = ct::canon(y[1]);
   *(FNTRS_GLOBAL uint32_t*)gptr((uint32_t*)((uint16_t*)org + e)) = (c0 & 0xFFFFu) | (c1 << 16);
-  *(FNTRS_GLOBAL uint8_t*)gptr((uint8_t*)org + foff + (e >> 1)) = (uint8_t)((c0 >> 16) | ((c1 >> 16) << 1));
+  const uint32_t f = (c0 >> 16) | ((c1 >> 16) << 1);
+  const uint64_t any = __ballot(f != 0);
+  if ((any >> (threadIdx.x & 48u)) & 0xFFFFu) {
+    *(FNTRS_GLOBAL uint8_t*)gptr((uint8_t*)org + foff + (e >> 1)) = (uint8_t)f;
+    if ((threadIdx.x & 15u) == 0) atomicOr(bmap + (bit >> 5), 1u << (bit & 31u));
+  }
 }
 
 // Where a loader's rows come from and what it does to them:
@@ -143,6 +161,22 @@ struct GLoad {
   RowFn rowf;
   const uint32_t* org = nullptr;   // kScratch: the buffer's origin and the
   uint64_t foff = 0;               // byte offset of its flags
+  // kScratch: whether a row of this sub-transform holds 65536, and the word
+  // of the escape bitmap where its 2^L bits start
+  bool esc = false;
+  const uint32_t* bm = nullptr;
+  uint64_t w0 = 0;
+  // Reads the escape bits of sub-transform `sub` of tile (blk, tile) of a
+  // buffer of 2^rlog rows per tile.  Uniform, before any store of the kernel.
+  __device__ __forceinline__ void escapes(const FourStepArgs& a, const Work& wk) {
+    static_assert(L >= 5, "a sub-transform's escape bits are whole words");
+    bm = (const uint32_t*)((const uint8_t*)org + a.boff_in);
+    w0 = (((wk.blk * a.tiles + wk.tile) << a.rlog_in) + ((uint64_t)wk.sub << L)) >> 5;
+    uint32_t any = 0;
+#pragma unroll
+    for (int j = 0; j < (1 << (L - 5)); ++j) any |= gptr(bm)[w0 + j];
+    esc = any != 0;
+  }
   template <int B, bool WHOLE>
   __device__ __forceinline__ void rows(uint32_t ib, uint32_t g, int32_t (&x)[1 << B][kV]) {
     uint64_t r[1 << B];
@@ -156,7 +190,7 @@ struct GLoad {
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c) {
       if constexpr (KIND == kScratch) {
-        scratch_get(org, foff, base + r[c] * kT + g * kV, x[c]);
+        scratch_get(org, base + r[c] * kT + g * kV, x[c]);
       } else if constexpr (KIND == kZeros) {
         // zero rows (the encoder's padding: the top rows of every
         // sub-transform, a whole wave at a time) issue no read
@@ -166,6 +200,18 @@ struct GLoad {
           for (int v = 0; v < kV; ++v) x[c][v] = 0;
       } else {
         ct::load_lanes<kV, WHOLE>(rowp(base, ld, r[c], g), lane0 + g * kV, lanes, x[c]);
+      }
+    }
+    if constexpr (KIND == kScratch) {
+      if (esc) {   // uniform: a row of this sub-transform holds 65536
+#pragma unroll
+        for (int c = 0; c < (1 << B); ++c) {
+          const uint32_t i = ib | (bitrev((uint32_t)c, B) << (L - B));
+          if ((gptr(bm)[w0 + (i >> 5)] >> (i & 31u)) & 1u) {
+            uint32_t unused;   // the row again: r[] need not live past the loads
+            scratch_fix(org, foff, base + rowf(i, unused) * kT + g * kV, x[c]);
+          }
+        }
       }
     }
 #pragma unroll
@@ -209,6 +255,15 @@ struct GStore {
   DestFn destf;
   const uint32_t* org = nullptr;   // SCRATCH: the buffer's origin and the
   uint64_t foff = 0;               // byte offset of its flags
+  uint32_t* bmap = nullptr;        // SCRATCH: escape bitmap words
+  uint64_t bbit = 0;               // first bit of this tile
+  uint32_t slog = 0, qlog = 0;     // log2 S and log2 R/S
+  __device__ __forceinline__ void escapes(const FourStepArgs& a, const Work& wk) {
+    bmap = (uint32_t*)((uint8_t*)a.out + a.boff_out);
+    bbit = (wk.blk * a.tiles + wk.tile) << a.rlog_out;
+    slog = a.slog_out;
+    qlog = a.rlog_out - a.slog_out;
+  }
   template <int B, uint32_t H, bool WHOLE>
   __device__ __forceinline__ void rows(uint32_t pb, uint32_t g, int32_t (&x)[1 << B][kV]) {
     uint64_t r[1 << B];
@@ -225,7 +280,8 @@ struct GStore {
         int32_t y[kV];
 #pragma unroll
         for (int v = 0; v < kV; ++v) y[v] = ct::mulw(x[c][v], w[c]);
-        scratch_put(org, foff, base + r[c] * kT + g * kV, y);
+        const uint64_t bit = bbit + ((r[c] & ((1u << slog) - 1)) << qlog) + (r[c] >> slog);
+        scratch_put(org, foff, bmap, bit, base + r[c] * kT + g * kV, y);
       } else {
         if (r[c] == ~0ull) continue;
         ct::store_lanes<kV, WHOLE>(const_cast<uint32_t*>(rowp(base, ld, r[c], g)), lane0 + g * kV, lanes, x[c]);
@@ -265,16 +321,25 @@ __global__ void __launch_bounds__(kNT) k4_dec1(FourStepArgs a) {
   extern __shared__ uint32_t lds[];
   const Work wk = work_of(a);
   const uint32_t i1 = wk.sub, N1 = a.n >> LA;
-  // the weights and rows are read where the first pass needs them (a table
-  // would put a barrier between two global reads); the twiddles of the
-  // last pass come from a table read after the first barrier
+  // the weights, rows and last-pass twiddles of the 256 inputs go to LDS
+  // tables first, one word per thread, so the first pass's lane groups do
+  // not each read them again from global memory
   uint32_t* t_tw = lds + Gm::LDS_BYTES / 4;   // w_n^-(i1 m2)
-  for (uint32_t t = threadIdx.x; t < (1u << LA); t += kNT) t_tw[t] = tw4(a, true, i1 * t, a.logn);
-  auto rowf = [&](uint32_t i2, uint32_t& w) -> uint64_t {
-    const uint32_t z = i1 + N1 * i2;
-    w = gptr(a.wfull)[z];   // 0: erased (the row read is then discarded)
+  static_assert((3u << LA) <= kTabWords, "three tables of 2^LA words");
+  uint32_t* t_w = t_tw + (1u << LA);           // weight of input i2
+  uint32_t* t_r = t_w + (1u << LA);            // its row (0 where erased)
+  for (uint32_t t = threadIdx.x; t < (1u << LA); t += kNT) {
+    const uint32_t z = i1 + N1 * t;
+    const uint32_t w = gptr(a.wfull)[z];
     const uint32_t r = a.full ? z : gptr(a.ridx)[z];
-    return w ? (uint64_t)r : 0;
+    t_tw[t] = tw4(a, true, i1 * t, a.logn);
+    t_w[t] = w;
+    t_r[t] = w ? r : 0;
+  }
+  __syncthreads();
+  auto rowf = [&](uint32_t i2, uint32_t& w) -> uint64_t {
+    w = t_w[i2];   // 0: erased (the row read is then discarded)
+    return (uint64_t)t_r[i2];
   };
   auto destf = [&](uint32_t m2, uint32_t& w) -> uint64_t {
     w = t_tw[m2];
@@ -286,6 +351,7 @@ __global__ void __launch_bounds__(kNT) k4_dec1(FourStepArgs a) {
   ct::LdsStore<kV, Gm::G, false> sm{lds};
   GStore<LA, false, true, decltype(destf)> sl{a.out + wk.blk * a.stride_out + wk.tile * a.tstride_out, a.ld_out, wk.lane0, a.lanes,
                                         a.vec != 0, destf, a.out, a.foff_out};
+  sl.escapes(a, wk);
   using TW = typename Gm::TwType;
   const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
   ct::dit<LA, Gm::BM, kV, Gm::G, true>(tws, l0, lm, sm, sl);
@@ -331,12 +397,14 @@ __global__ void __launch_bounds__(kNT) k4_dec2(FourStepArgs a) {
   };
   GLoad<LB1, kScratch, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.tile * a.tstride_in, a.ld_in, wk.lane0, a.lanes, a.vec != 0,
                                 rowf, a.in, a.foff_in};
+  l0.escapes(a, wk);
   ct::LdsLoad<kV, Gm::G> ll{lds};
   ct::LdsStore<kV, Gm::G, false> sl{lds};
   ct::LdsStore<kV, Gm::G, true> slf{lds};
   MaskStore<Gm::G> ms{lds, m2, a.k};
   GStore<LB2, true, true, decltype(destf)> sg{a.out + wk.blk * a.stride_out + wk.tile * a.tstride_out, a.ld_out, wk.lane0, a.lanes,
                                         a.vec != 0, destf, a.out, a.foff_out};
+  sg.escapes(a, wk);
   using TW = typename Gm::TwType;
   const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
   ct::dit<LB1, Gm::BM, kV, Gm::G, true>(tws, l0, ll, sl, ms);
@@ -386,12 +454,14 @@ __global__ void __launch_bounds__(kNT) k4_dec3(FourStepArgs a) {
   };
   GLoad<8, kScratch, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.tile * a.tstride_in, a.ld_in, wk.lane0,
                                         a.lanes, a.vec != 0, rowf, a.in, a.foff_in};
+  l0.escapes(a, wk);
   ct::LdsLoad<kV, Gm::G> ll{lds};
   ct::LdsStore<kV, Gm::G, false> sl{lds};
   ct::LdsStore<kV, Gm::G, true> slf{lds};
   AhatStore<Gm::G> ah{lds, t_ah};
   GStore<8, true, true, decltype(destf)> sg{a.out + wk.blk * a.stride_out + wk.tile * a.tstride_out, a.ld_out, wk.lane0, a.lanes,
                                       a.vec != 0, destf, a.out, a.foff_out};
+  sg.escapes(a, wk);
   using TW = typename Gm::TwType;
   const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
   ct::dit<8, Gm::BM, kV, Gm::G, false>(tws, l0, ll, sl, ah);
@@ -417,6 +487,7 @@ __global__ void __launch_bounds__(kNT) k4_dec4(FourStepArgs a) {
   };
   GLoad<LB, kScratch, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.tile * a.tstride_in, a.ld_in, wk.lane0,
                                          a.lanes, a.vec != 0, rowf, a.in, a.foff_in};
+  l0.escapes(a, wk);
   ct::LdsLoad<kV, Gm::G> ll{lds};
   ct::LdsStore<kV, Gm::G, false> sl{lds};
   GStore<LB, false, false, decltype(destf)> sg{a.out + wk.blk * a.stride_out + wk.tile * a.tstride_out, a.ld_out, wk.lane0, a.lanes,
@@ -453,6 +524,7 @@ __global__ void __launch_bounds__(kNT) k4_enc1(FourStepArgs a) {
   ct::LdsStore<kV, Gm::G, false> sm{lds};
   GStore<8, false, true, decltype(destf)> sl{a.out + wk.blk * a.stride_out + wk.tile * a.tstride_out, a.ld_out, wk.lane0, a.lanes,
                                        a.vec != 0, destf, a.out, a.foff_out};
+  sl.escapes(a, wk);
   using TW = typename Gm::TwType;
   const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
   ct::dit<8, Gm::BM, kV, Gm::G, false>(tws, l0, lm, sm, sl);
@@ -477,6 +549,7 @@ __global__ void __launch_bounds__(kNT) k4_enc2(FourStepArgs a) {
   };
   GLoad<LB, kScratch, decltype(rowf)> l0{a.in + wk.blk * a.stride_in + wk.tile * a.tstride_in, a.ld_in, wk.lane0,
                                          a.lanes, a.vec != 0, rowf, a.in, a.foff_in};
+  l0.escapes(a, wk);
   ct::LdsLoad<kV, Gm::G> lm{lds};
   ct::LdsStore<kV, Gm::G, false> sm{lds};
   GStore<LB, false, false, decltype(destf)> sl{a.out + wk.blk * a.stride_out + wk.tile * a.tstride_out, a.ld_out, wk.lane0, a.lanes,
@@ -484,6 +557,18 @@ __global__ void __launch_bounds__(kNT) k4_enc2(FourStepArgs a) {
   using TW = typename Gm::TwType;
   const TW tws = ct::make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
   ct::dit<LB, Gm::BM, kV, Gm::G, false>(tws, l0, lm, sm, sl);
+}
+
+// Clears the escape bitmaps of a call (up to three ranges of whole 16-byte
+// vectors) before their writers run.
+__global__ void __launch_bounds__(256) k_fs_clear(FsClearArgs c) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    uint4* q = reinterpret_cast<uint4*>(c.p[j]);
+    const uint64_t nv = c.words[j] / 4;
+    for (uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x; t < nv; t += (uint64_t)gridDim.x * 256)
+      q[t] = make_uint4(0, 0, 0, 0);
+  }
 }
 
 }  // namespace fs

@@ -66,6 +66,19 @@ struct FourStepArgs {
   uint64_t tstride_in, tstride_out;  // elements between lane tiles (set by the four-step launchers)
   uint64_t foff_in, foff_out;        // scratch in / out: byte offset of its bit-16 flags (four-step launchers)
   uint32_t sub_fast;                 // work items ordered sub-transform first (see fs::work_of)
+  // scratch in / out: byte offset of the escape bitmap (one bit per row of a
+  // lane tile, set where a lane holds 65536; see fs::scratch_put), log2 of
+  // the rows per tile, and (out) log2 of the writer's row split S: its rows
+  // are i*S + m, and row i*S + m has bit m*(R/S) + i of its tile's R bits
+  uint64_t boff_in, boff_out;
+  uint32_t rlog_in, rlog_out, slog_out;
+};
+
+// Escape bitmaps a four-step call clears before its kernels run: up to
+// three ranges of whole 16-byte vectors.
+struct FsClearArgs {
+  uint32_t* p[3];
+  uint64_t words[3];   // multiples of 4
 };
 
 // One erasure pattern of a locator batch: where its positions come from,

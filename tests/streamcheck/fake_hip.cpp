@@ -208,6 +208,7 @@ void touch(Op& x, uintptr_t lo, size_t bytes, bool write, const char* what) {
   for (const Record& r : a->rec) {
     if (r.hi <= lo || r.lo >= hi) continue;
     if (!(r.write || write)) continue;
+    if (r.stream == x.stream && r.seq == x.seq) continue;   // this operation's own earlier access
     if (!hb(x, r.stream, r.seq))
       error(std::string("race: ") + where + (write ? " writes " : " reads ") + "[" + hexs(lo) + ", " + hexs(hi) +
             ") against " + (r.write ? "a write" : "a read") + " by " + r.what + " that is not ordered before it");
@@ -344,6 +345,11 @@ void model_fourstep(Op& x, const std::string& base, const FourStepArgs& a, uint6
   };
   touch(x, (uintptr_t)a.in, span(a.stride_in, a.tstride_in, rin, a.ld_in) * 4, false, "in");
   touch(x, (uintptr_t)a.out, span(a.stride_out, a.tstride_out, rout, a.ld_out) * 4, true, "out");
+  // a tile-major scratch buffer's escape bitmap: one bit per row of a tile
+  if (a.tstride_in != T)
+    touch(x, (uintptr_t)a.in + a.boff_in, (size_t)batch * a.tiles * (a.tstride_in / T) / 8, false, "escape bits in");
+  if (a.tstride_out != T)
+    touch(x, (uintptr_t)a.out + a.boff_out, (size_t)batch * a.tiles * (a.tstride_out / T) / 8, true, "escape bits out");
   model_tw(x, a.tw, a.twi);
 }
 
@@ -411,6 +417,16 @@ std::function<void(Op&)> kernel_model(const std::string& name, dim3 grid, void**
         return;
       }
       model_table(x, t, [&](const DecodeArgs& a, uint64_t items) { model_decode(x, a, items, D); });
+    };
+  }
+  if (fn == "k_fs_clear") {   // zeroes up to three ranges of 16-byte vectors
+    const fntrs::FsClearArgs c = *(const fntrs::FsClearArgs*)args[0];
+    return [c](Op& x) {
+      for (int j = 0; j < 3; ++j)
+        if (c.words[j]) {
+          if (c.words[j] % 4 || (uintptr_t)c.p[j] % 16) error(x.what + ": clear range is not whole 16-byte vectors");
+          touch(x, (uintptr_t)c.p[j], c.words[j] * 4, true, "escape bits");
+        }
     };
   }
   if (fn.rfind("k4_", 0) == 0) {
