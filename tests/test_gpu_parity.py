@@ -386,6 +386,35 @@ def test_extreme_inputs(ctx, n, k):
 
 
 # ------------------------------------------------------------------ n = 65536 (four-step path)
+@pytest.mark.parametrize("n,lanes", [(16384, 40), (32768, 136), (65536, 100), (65536, 40)])
+def test_fourstep_escape_rows(ctx, n, lanes):
+    """Scratch rows full of 65536, the one residue whose bit 16 the four-step
+    kernels store by exception: a source that is 65536 in row 0 only makes
+    every row of the first pass's sub-transform 0 equal 65536, so every
+    reader of the second pass meets an escaped row.  The codeword of such a
+    source is that constant on every row.  Two blocks and several lane tiles
+    (the last ragged) with different lanes set check that escapes land on
+    their own block, tile and lane."""
+    say("four-step escape rows", n, lanes)
+    k = n // 4
+    src = np.zeros((2, k, lanes), dtype=np.uint32)
+    src[0, 0, [0, 3, 17, lanes - 1]] = 65536
+    src[1, 0, 33:39] = 65536
+    src[1, 0, 5] = 7
+    out = gpu_encode(ctx, src, n)
+    for b in range(2):
+        assert np.array_equal(out[b], np.broadcast_to(src[b, 0].astype(np.int64), (n, lanes))), b
+    rows = np.arange(0, n, 997)
+    assert np.array_equal(out[1][rows], codec.encode(src[1], n, rows=rows))
+    # decoding that codeword returns the source (its scratch rows hold
+    # whatever the erasures make of it, the round trip holds regardless)
+    z = synth.received_positions(n + 11, n, k)
+    recv = out[:, z.astype(np.int64)].astype(np.uint32)
+    loc = ctx.locator(n, k, z)
+    assert np.array_equal(gpu_decode(ctx, loc, recv), src.astype(np.int64))
+    loc.release()
+
+
 @pytest.mark.parametrize("k,lanes", [(40000, 33), (65536, 8)])
 def test_encode_max_length_fourstep(ctx, k, lanes):
     say("encode four-step", 65536, k, lanes)
