@@ -90,14 +90,14 @@ hipError_t fourstep_decode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   const uint64_t T = fs::kT;
   // scratch of `rows` rows, tile-major
   // (the flags of a buffer used with `rows` rows follow its 2-byte values)
-  // sub_fast: work items go sub-transform first (fs::work_of), for the
-  // kernels that read scratch and write scratch (K2, K3); K4 writes the
-  // caller's rows and keeps the tile-first order.
-  auto scr_in = [&](FourStepArgs& f, const uint32_t* p, uint64_t rows, uint64_t boff, bool sub_fast) {
+  // order (fs::work_of): sub-transform first for the kernels that read
+  // scratch and write scratch (K2, K3), pairs of sub-transforms then tiles
+  // for K4, which writes the caller's rows.
+  auto scr_in = [&](FourStepArgs& f, const uint32_t* p, uint64_t rows, uint64_t boff, uint32_t order) {
     f.in = p; f.ld_in = T; f.tstride_in = rows * T; f.stride_in = tiles * rows * T;
     f.foff_in = 2 * (uint64_t)batch * f.stride_in;
     f.boff_in = boff; f.rlog_in = ilog2_u64(rows);
-    f.sub_fast = sub_fast ? 1u : 0u;
+    f.order = order;
   };
   // slog: log2 of the writer's row split (rows i*S + m)
   auto scr_out = [&](FourStepArgs& f, uint32_t* p, uint64_t rows, uint64_t boff, uint32_t slog) {
@@ -132,7 +132,7 @@ hipError_t fourstep_decode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   if (base.k == base.n) {
     // erasure-free: the inverse transform's pass B writes the source
     FourStepArgs b = user;
-    scr_in(b, sa, n, bA1, false);
+    scr_in(b, sa, n, bA1, 2);
     b.subs = 256;
     b.M = base.n;
     return dec4_any(LB1, b, tiles * b.subs * batch, s);
@@ -140,19 +140,19 @@ hipError_t fourstep_decode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   const int LB2 = base.logm - 8;
   // K2: sa -> sb (M rows)
   FourStepArgs b = user;
-  scr_in(b, sa, n, bA1, true);
+  scr_in(b, sa, n, bA1, 1);
   scr_out(b, sb, M, bB, base.logm - 8);
   b.subs = 256;
   FNTRS_TRY(dec2_any(LB1, LB2, b, tiles * b.subs * batch, s));
   // K3: sb -> sa (M rows)
   FourStepArgs c = user;
-  scr_in(c, sb, M, bB, true);
+  scr_in(c, sb, M, bB, 1);
   scr_out(c, sa, M, bA2, 8);
   c.subs = base.M >> 8;
   FNTRS_TRY(launch(fs::k4_dec3, fs::lds_with_tables<8>(), tiles * c.subs * batch, c, s));
   // K4: sa -> dst
   FourStepArgs d = user;
-  scr_in(d, sa, M, bA2, false);
+  scr_in(d, sa, M, bA2, 2);
   d.subs = 256;
   return dec4_any(LB2, d, tiles * d.subs * batch, s);
 }
@@ -185,9 +185,9 @@ hipError_t fourstep_encode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   b.in = sa; b.ld_in = T; b.tstride_in = rows * T; b.stride_in = base.tiles * rows * T;
   b.foff_in = 2 * (uint64_t)batch * b.stride_in;
   b.boff_in = bA; b.rlog_in = base.logn;
-  // sub-transform first when the output's row segments are whole 128-byte
-  // lines (no two lane tiles share one)
-  b.sub_fast = (base.ld_out % T == 0 && base.stride_out % T == 0 && (uintptr_t)base.out % (4 * T) == 0) ? 1u : 0u;
+  // pairs of sub-transforms, then tiles: reads the scratch lines whole and
+  // keeps neighbouring tiles of the output rows together
+  b.order = 2;
   b.tstride_out = T;
   b.subs = 256;
   switch (base.logn) {

@@ -47,13 +47,14 @@ using Geo = ct::Geo<L, kT, kNT, kV>;
 // being spread over the whole buffer at a stride of ld*4 bytes.
 
 // Decodes blockIdx into (lane tile, sub-transform, block).  Consecutive
-// work items of one XCD run together and share its L2.  Items are ordered
-// lane tile first where neighbouring tiles share cache lines (row segments of
-// a row-major buffer whose lane count is not a multiple of the tile), else
-// sub-transform first (sub_fast): neighbouring sub-transforms share the lines
-// of a packed scratch buffer they read, whose 128-byte lines hold the 64-byte
-// value segments of two neighbouring rows and the 16-byte flag segments of
-// eight, rows that belong to neighbouring sub-transforms of one tile.
+// work items of one XCD run together and share its L2, so the order decides
+// which workgroups share cache lines while they are in flight:
+//   0  lane tile first: neighbouring tiles share the lines of a row-major
+//      buffer whose lane count is not a multiple of the tile;
+//   1  sub-transform first: neighbouring sub-transforms share the 128-byte
+//      lines of the scratch rows they read (two 64-byte rows of one tile);
+//   2  pairs of sub-transforms, then tiles: both, for kernels that read
+//      scratch and write row-major rows.
 struct Work {
   uint32_t tile, sub;
   uint64_t blk;
@@ -62,11 +63,17 @@ struct Work {
 __device__ __forceinline__ Work work_of(const FourStepArgs& a) {
   const uint32_t bid = ct::xcd_remap(blockIdx.x, gridDim.x);
   Work w;
-  if (a.sub_fast) {
+  if (a.order == 1) {
     w.sub = bid % a.subs;
     const uint32_t r = bid / a.subs;
     w.tile = r % a.tiles;
     w.blk = r / a.tiles;
+  } else if (a.order == 2) {   // subs is even
+    const uint32_t rest = bid >> 1, half = a.subs >> 1;
+    w.tile = rest % a.tiles;
+    const uint32_t r = rest / a.tiles;
+    w.sub = ((r % half) << 1) | (bid & 1u);
+    w.blk = r / half;
   } else {
     w.tile = bid % a.tiles;
     const uint32_t r = bid / a.tiles;

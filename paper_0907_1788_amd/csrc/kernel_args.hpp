@@ -65,7 +65,8 @@ struct FourStepArgs {
   uint32_t rows_out;                 // encoder: only rows < rows_out of out are written (0: all n)
   uint64_t tstride_in, tstride_out;  // elements between lane tiles (set by the four-step launchers)
   uint64_t foff_in, foff_out;        // scratch in / out: byte offset of its bit-16 flags (four-step launchers)
-  uint32_t sub_fast;                 // work items ordered sub-transform first (see fs::work_of)
+  uint32_t order;                    // work item order (fs::work_of): 0 tile first, 1 sub-transform
+                                     // first, 2 sub-transform pairs, then tiles
   // scratch in / out: byte offset of the escape bitmap (one bit per row of a
   // lane tile, set where a lane holds 65536; see fs::scratch_put), log2 of
   // the rows per tile, and (out) log2 of the writer's row split S: its rows
