@@ -29,7 +29,8 @@ hipError_t launch(K kernel, size_t lds, uint32_t blocks, const FourStepArgs& a, 
 // Zeroes the given escape bitmaps (byte ranges of whole 16-byte vectors).
 hipError_t clear_bitmaps(const FsClearArgs& c, hipStream_t s) {
   const uint64_t words = c.words[0] + c.words[1] + c.words[2];
-  const uint32_t blocks = (uint32_t)std::min<uint64_t>(1024, (words / 4 + 255) / 256 + 1);
+  const uint64_t items = std::max<uint64_t>(words / 4, c.wr ? c.n / 4 : 0);
+  const uint32_t blocks = (uint32_t)std::min<uint64_t>(1024, (items + 255) / 256 + 1);
   hipLaunchKernelGGL(fs::k_fs_clear, dim3(blocks), dim3(256), 0, s, c);
   return hipGetLastError();
 }
@@ -109,10 +110,14 @@ hipError_t fourstep_decode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   // bitmaps: K1's rows and K3's rows in sa, K2's rows in sb
   const uint64_t bA1 = bitmap_at(batch, n, lds_), bA2 = bA1 + bitmap_bytes(batch, tiles, n);
   const uint64_t bB = bitmap_at(batch, M, lds_);
+  const uint64_t bWR = 7 * (uint64_t)batch * n * lds_ / 2;   // 3.5 bytes per element: 8 n bytes
   {
     FsClearArgs cl{};
     cl.p[0] = (uint32_t*)((uint8_t*)sa + bA1);
     cl.words[0] = bitmap_bytes(batch, tiles, n) / 4;
+    // K1's weights and rows by sub-transform, beyond the bitmaps
+    cl.wr = (uint32_t*)((uint8_t*)sa + bWR);
+    cl.wfull = base.wfull; cl.ridx = base.ridx; cl.n = base.n; cl.full = base.full;
     if (base.k != base.n) {
       cl.p[1] = (uint32_t*)((uint8_t*)sa + bA2);
       cl.words[1] = bitmap_bytes(batch, tiles, M) / 4;
@@ -127,6 +132,7 @@ hipError_t fourstep_decode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   // K1: recv -> sa (n rows)
   FourStepArgs a = user;
   scr_out(a, sa, n, bA1, 8);
+  a.wr = (const uint32_t*)((const uint8_t*)sa + bWR);
   a.subs = a.n >> 8;
   FNTRS_TRY(launch(fs::k4_dec1<8>, fs::lds_with_tables<8>(), tiles * a.subs * batch, a, s));
   if (base.k == base.n) {

@@ -327,7 +327,7 @@ __global__ void __launch_bounds__(kNT) k4_dec1(FourStepArgs a) {
   using Gm = Geo<LA>;
   extern __shared__ uint32_t lds[];
   const Work wk = work_of(a);
-  const uint32_t i1 = wk.sub, N1 = a.n >> LA;
+  const uint32_t i1 = wk.sub;
   // the weights, rows and last-pass twiddles of the 256 inputs go to LDS
   // tables first, one word per thread, so the first pass's lane groups do
   // not each read them again from global memory
@@ -336,12 +336,10 @@ __global__ void __launch_bounds__(kNT) k4_dec1(FourStepArgs a) {
   uint32_t* t_w = t_tw + (1u << LA);           // weight of input i2
   uint32_t* t_r = t_w + (1u << LA);            // its row (0 where erased)
   for (uint32_t t = threadIdx.x; t < (1u << LA); t += kNT) {
-    const uint32_t z = i1 + N1 * t;
-    const uint32_t w = gptr(a.wfull)[z];
-    const uint32_t r = a.full ? z : gptr(a.ridx)[z];
+    const u32x2 wr = *(const FNTRS_GLOBAL u32x2*)gptr(a.wr + 2 * (((uint64_t)i1 << LA) + t));
     t_tw[t] = tw4(a, true, i1 * t, a.logn);
-    t_w[t] = w;
-    t_r[t] = w ? r : 0;
+    t_w[t] = wr.x;
+    t_r[t] = wr.y;
   }
   __syncthreads();
   auto rowf = [&](uint32_t i2, uint32_t& w) -> uint64_t {
@@ -568,6 +566,9 @@ __global__ void __launch_bounds__(kNT) k4_enc2(FourStepArgs a) {
 
 // Clears the escape bitmaps of a call (up to three ranges of whole 16-byte
 // vectors) before their writers run.
+// The decoder's launch also lays out K1's weights and rows by sub-transform,
+// so that each K1 workgroup reads its 256 pairs from one contiguous 2 KiB
+// range instead of 512 words 4*n/256 bytes apart.
 __global__ void __launch_bounds__(256) k_fs_clear(FsClearArgs c) {
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
@@ -575,6 +576,16 @@ __global__ void __launch_bounds__(256) k_fs_clear(FsClearArgs c) {
     const uint64_t nv = c.words[j] / 4;
     for (uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x; t < nv; t += (uint64_t)gridDim.x * 256)
       q[t] = make_uint4(0, 0, 0, 0);
+  }
+  if (c.wr) {
+    const uint32_t N1 = c.n >> 8;
+    for (uint32_t t = blockIdx.x * 256 + threadIdx.x; t < c.n; t += gridDim.x * 256) {
+      const uint32_t i1 = t >> 8, i2 = t & 255u, z = i1 + N1 * i2;
+      const uint32_t w = gptr(c.wfull)[z];
+      const uint32_t r = c.full ? z : gptr(c.ridx)[z];
+      const u32x2 v = {w, w ? r : 0u};
+      *(FNTRS_GLOBAL u32x2*)gptr(c.wr + 2 * (uint64_t)t) = v;
+    }
   }
 }
 

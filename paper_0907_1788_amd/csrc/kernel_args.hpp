@@ -73,6 +73,7 @@ struct FourStepArgs {
   // are i*S + m, and row i*S + m has bit m*(R/S) + i of its tile's R bits
   uint64_t boff_in, boff_out;
   uint32_t rlog_in, rlog_out, slog_out;
+  const uint32_t* wr;                // decoder K1: weights and rows by sub-transform (FsClearArgs::wr)
 };
 
 // Escape bitmaps a four-step call clears before its kernels run: up to
@@ -80,6 +81,13 @@ struct FourStepArgs {
 struct FsClearArgs {
   uint32_t* p[3];
   uint64_t words[3];   // multiples of 4
+  // decoder: the weight and row of input i2 of K1's sub-transform i1 (the
+  // position z = i1 + (n/256) i2), as word pairs at wr[2 (256 i1 + i2)]
+  // (null: none); the row is 0 where the weight is 0
+  uint32_t* wr;
+  const uint32_t* wfull;
+  const uint32_t* ridx;
+  uint32_t n, full;
 };
 
 // One erasure pattern of a locator batch: where its positions come from,

@@ -321,8 +321,7 @@ void model_fourstep(Op& x, const std::string& base, const FourStepArgs& a, uint6
   else if (base == "k4_dec1") {
     rin = a.full ? a.n : a.k;
     rout = a.n;
-    touch(x, (uintptr_t)a.wfull, (size_t)a.n * 4, false, "wfull");
-    if (!a.full) touch(x, (uintptr_t)a.ridx, (size_t)a.n * 4, false, "ridx");
+    touch(x, (uintptr_t)a.wr, (size_t)a.n * 8, false, "weights and rows by sub-transform");
   } else if (base == "k4_dec2") { rin = a.n; rout = a.M; }
   else if (base == "k4_dec3") {
     rin = a.M;
@@ -427,6 +426,12 @@ std::function<void(Op&)> kernel_model(const std::string& name, dim3 grid, void**
           if (c.words[j] % 4 || (uintptr_t)c.p[j] % 16) error(x.what + ": clear range is not whole 16-byte vectors");
           touch(x, (uintptr_t)c.p[j], c.words[j] * 4, true, "escape bits");
         }
+      if (c.wr) {
+        if ((uintptr_t)c.wr % 8) error(x.what + ": weight and row pairs are not 8-byte aligned");
+        touch(x, (uintptr_t)c.wfull, (size_t)c.n * 4, false, "wfull");
+        if (!c.full) touch(x, (uintptr_t)c.ridx, (size_t)c.n * 4, false, "ridx");
+        touch(x, (uintptr_t)c.wr, (size_t)c.n * 8, true, "weights and rows by sub-transform");
+      }
     };
   }
   if (fn.rfind("k4_", 0) == 0) {
