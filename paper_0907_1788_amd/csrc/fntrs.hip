@@ -1200,10 +1200,23 @@ int fntrs_create(int device, size_t cap, fntrs_ctx** out) {
   uint64_t x = 1;
   for (int e = 0; e < 65536; ++e) { h[e] = (uint32_t)x; x = x * 3 % 65537; }
   for (int e = 0; e < 65536; ++e) h[65536 + e] = h[(65536 - e) & 0xFFFF];
-  if (hipMalloc((void**)&c->tw, 2 * 65536 * 4) != hipSuccess) { delete c; return FNTRS_E_NOMEM; }
+  // the four-step split twiddles (split_tw_offset): w_N^(+-i t) by [i][t]
+  h.resize(2 * 65536 + kSplitTwWords);
+  for (int logN = kSplitTwMinLog; logN <= 16; ++logN) {
+    const uint32_t N = 1u << logN, N2 = N >> 8, sh = 16 - logN;
+    for (int b = 0; b < 2; ++b)
+      for (int inv = 0; inv < 2; ++inv) {
+        uint32_t* t = h.data() + split_tw_offset(logN, b != 0, inv != 0);
+        const uint32_t rows = b ? 256 : N2, cols = b ? N2 : 256;
+        for (uint32_t i = 0; i < rows; ++i)
+          for (uint32_t j = 0; j < cols; ++j) t[i * cols + j] = h[(inv ? 65536 : 0) + (((i * j) & (N - 1)) << sh)];
+      }
+  }
+  const size_t tw_bytes = h.size() * 4;
+  if (hipMalloc((void**)&c->tw, tw_bytes) != hipSuccess) { delete c; return FNTRS_E_NOMEM; }
   c->twi = c->tw + 65536;
-  c->used += 2 * 65536 * 4;
-  if (hipMemcpy(c->tw, h.data(), 2 * 65536 * 4, hipMemcpyHostToDevice) != hipSuccess) {
+  c->used += tw_bytes;
+  if (hipMemcpy(c->tw, h.data(), tw_bytes, hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipFree(c->tw);
     delete c;
     return FNTRS_E_DEVICE;

@@ -29,7 +29,7 @@ hipError_t launch(K kernel, size_t lds, uint32_t blocks, const FourStepArgs& a, 
 // Zeroes the given escape bitmaps (byte ranges of whole 16-byte vectors).
 hipError_t clear_bitmaps(const FsClearArgs& c, hipStream_t s) {
   const uint64_t words = c.words[0] + c.words[1] + c.words[2];
-  const uint64_t items = std::max<uint64_t>(words / 4, c.wr ? c.n / 4 : 0);
+  const uint64_t items = std::max<uint64_t>(words / 4, c.wr ? c.n / 4 : 0);   // c.M <= c.n
   const uint32_t blocks = (uint32_t)std::min<uint64_t>(1024, (items + 255) / 256 + 1);
   hipLaunchKernelGGL(fs::k_fs_clear, dim3(blocks), dim3(256), 0, s, c);
   return hipGetLastError();
@@ -86,6 +86,7 @@ hipError_t fourstep_decode(const FourStepArgs& base, uint32_t batch, uint32_t* s
                            hipStream_t s) {
   const uint32_t tiles = base.tiles;
   if (base.logn < 14 || base.logn > 16) return hipErrorInvalidValue;
+  if (base.k != base.n && (base.logm < kSplitTwMinLog || base.logm > base.logn)) return hipErrorInvalidValue;
   if (lds_ != (uint64_t)tiles * fs::kT) return hipErrorInvalidValue;
   const int LB1 = base.logn - 8;
   const uint64_t T = fs::kT;
@@ -111,6 +112,7 @@ hipError_t fourstep_decode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   const uint64_t bA1 = bitmap_at(batch, n, lds_), bA2 = bA1 + bitmap_bytes(batch, tiles, n);
   const uint64_t bB = bitmap_at(batch, M, lds_);
   const uint64_t bWR = 7 * (uint64_t)batch * n * lds_ / 2;   // 3.5 bytes per element: 8 n bytes
+  const uint64_t bAH = bWR + 8 * n;                            // then K3's Â layout, 4 M bytes
   {
     FsClearArgs cl{};
     cl.p[0] = (uint32_t*)((uint8_t*)sa + bA1);
@@ -119,6 +121,8 @@ hipError_t fourstep_decode(const FourStepArgs& base, uint32_t batch, uint32_t* s
     cl.wr = (uint32_t*)((uint8_t*)sa + bWR);
     cl.wfull = base.wfull; cl.ridx = base.ridx; cl.n = base.n; cl.full = base.full;
     if (base.k != base.n) {
+      cl.ahat_t = (uint32_t*)((uint8_t*)sa + bAH);
+      cl.ahat = base.ahat; cl.M = base.M;
       cl.p[1] = (uint32_t*)((uint8_t*)sa + bA2);
       cl.words[1] = bitmap_bytes(batch, tiles, M) / 4;
       cl.p[2] = (uint32_t*)((uint8_t*)sb + bB);
@@ -133,6 +137,7 @@ hipError_t fourstep_decode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   FourStepArgs a = user;
   scr_out(a, sa, n, bA1, 8);
   a.wr = (const uint32_t*)((const uint8_t*)sa + bWR);
+  a.twsplit = base.tw + split_tw_offset(base.logn, false, true);
   a.subs = a.n >> 8;
   FNTRS_TRY(launch(fs::k4_dec1<8>, fs::lds_with_tables<8>(), tiles * a.subs * batch, a, s));
   if (base.k == base.n) {
@@ -148,12 +153,15 @@ hipError_t fourstep_decode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   FourStepArgs b = user;
   scr_in(b, sa, n, bA1, 1);
   scr_out(b, sb, M, bB, base.logm - 8);
+  b.twsplit = base.tw + split_tw_offset(base.logm, true, false);
   b.subs = 256;
   FNTRS_TRY(dec2_any(LB1, LB2, b, tiles * b.subs * batch, s));
   // K3: sb -> sa (M rows)
   FourStepArgs c = user;
   scr_in(c, sb, M, bB, 1);
   scr_out(c, sa, M, bA2, 8);
+  c.twsplit = base.tw + split_tw_offset(base.logm, false, true);
+  c.ahat_t = (const uint32_t*)((const uint8_t*)sa + bAH);
   c.subs = base.M >> 8;
   FNTRS_TRY(launch(fs::k4_dec3, fs::lds_with_tables<8>(), tiles * c.subs * batch, c, s));
   // K4: sa -> dst
@@ -175,6 +183,7 @@ hipError_t fourstep_encode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   a.foff_out = 2 * (uint64_t)batch * a.stride_out;   // the flags follow the 2-byte values
   const uint64_t bA = bitmap_at(batch, rows, lds_);
   a.boff_out = bA; a.rlog_out = base.logn; a.slog_out = 8;
+  a.twsplit = base.tw + split_tw_offset(base.logn, false, false);
   {
     FsClearArgs cl{};
     cl.p[0] = (uint32_t*)((uint8_t*)sa + bA);

@@ -302,13 +302,6 @@ struct GStore {
   }
 };
 
-// Twiddle of the four-step split: w_N^(e) for a forward / inverse root of
-// order N = 2^logN, e taken mod N.
-__device__ __forceinline__ uint32_t tw4(const FourStepArgs& a, bool inv, uint32_t e, int logN) {
-  const uint32_t idx = (e & ((1u << logN) - 1)) << (16 - logN);
-  return inv ? gptr(a.twi)[idx] : gptr(a.tw)[idx];
-}
-
 // Per-workgroup tables of the per-row factors of a tile (decoder weights and
 // rows, split twiddles, the locator's transform): each word is read from
 // global memory once per workgroup, one word per thread, into LDS behind the
@@ -337,7 +330,7 @@ __global__ void __launch_bounds__(kNT) k4_dec1(FourStepArgs a) {
   uint32_t* t_r = t_w + (1u << LA);            // its row (0 where erased)
   for (uint32_t t = threadIdx.x; t < (1u << LA); t += kNT) {
     const u32x2 wr = *(const FNTRS_GLOBAL u32x2*)gptr(a.wr + 2 * (((uint64_t)i1 << LA) + t));
-    t_tw[t] = tw4(a, true, i1 * t, a.logn);
+    t_tw[t] = gptr(a.twsplit)[((uint64_t)i1 << LA) + t];
     t_w[t] = wr.x;
     t_r[t] = wr.y;
   }
@@ -391,7 +384,7 @@ __global__ void __launch_bounds__(kNT) k4_dec2(FourStepArgs a) {
   const Work wk = work_of(a);
   const uint32_t m2 = wk.sub;
   uint32_t* t_tw = lds + Gm::LDS_BYTES / 4;   // w_M^(m2 mp), read after the first barrier
-  for (uint32_t t = threadIdx.x; t < (1u << LB2); t += kNT) t_tw[t] = tw4(a, false, m2 * t, a.logm);
+  for (uint32_t t = threadIdx.x; t < (1u << LB2); t += kNT) t_tw[t] = gptr(a.twsplit)[(m2 << LB2) + t];
   auto rowf = [&](uint32_t i1, uint32_t& w) -> uint64_t {
     w = 0;
     return (uint64_t)i1 * 256u + m2;
@@ -446,8 +439,8 @@ __global__ void __launch_bounds__(kNT) k4_dec3(FourStepArgs a) {
   uint32_t* t_ah = lds + Gm::LDS_BYTES / 4;   // read after the first barrier
   uint32_t* t_tw = t_ah + 256;                // w_M^-(m2' m2'')
   for (uint32_t t = threadIdx.x; t < 256u; t += kNT) {
-    t_ah[t] = gptr(a.ahat)[m2p + rows2 * t];
-    t_tw[t] = tw4(a, true, m2p * t, a.logm);
+    t_ah[t] = gptr(a.ahat_t)[(m2p << 8) + t];
+    t_tw[t] = gptr(a.twsplit)[(m2p << 8) + t];
   }
   auto rowf = [&](uint32_t i1p, uint32_t& w) -> uint64_t {
     w = 0;
@@ -513,7 +506,7 @@ __global__ void __launch_bounds__(kNT) k4_enc1(FourStepArgs a) {
   const Work wk = work_of(a);
   const uint32_t i1 = wk.sub, N1 = a.n >> 8;
   uint32_t* t_tw = lds + Gm::LDS_BYTES / 4;   // w_n^(i1 m2), read after the first barrier
-  for (uint32_t t = threadIdx.x; t < 256u; t += kNT) t_tw[t] = tw4(a, false, i1 * t, a.logn);
+  for (uint32_t t = threadIdx.x; t < 256u; t += kNT) t_tw[t] = gptr(a.twsplit)[(i1 << 8) + t];
   auto rowf = [&](uint32_t i2, uint32_t& w) -> uint64_t {
     w = 0;
     const uint32_t j = i1 + N1 * i2;
@@ -586,6 +579,11 @@ __global__ void __launch_bounds__(256) k_fs_clear(FsClearArgs c) {
       const u32x2 v = {w, w ? r : 0u};
       *(FNTRS_GLOBAL u32x2*)gptr(c.wr + 2 * (uint64_t)t) = v;
     }
+  }
+  if (c.ahat_t) {
+    const uint32_t rows2 = c.M >> 8;
+    for (uint32_t t = blockIdx.x * 256 + threadIdx.x; t < c.M; t += gridDim.x * 256)
+      gptr(c.ahat_t)[t] = gptr(c.ahat)[(t >> 8) + rows2 * (t & 255u)];
   }
 }
 

@@ -82,7 +82,8 @@ struct fntrs_ctx {
   int num_cu = 256;
   size_t cap = fntrs::kDefaultCap, used = 0;
   uint32_t* tw = nullptr;            // tw[e] = 3^e mod p, e < 65536
-  uint32_t* twi = nullptr;           // twi[e] = 3^-e mod p
+  uint32_t* twi = nullptr;           // twi[e] = 3^-e mod p (tw + 65536; the four-step split
+                                     // twiddles follow, see split_tw_offset)
   uint32_t* noalloc_scratch = nullptr;   // device address of the no-allocation encoder's scratch
   uint32_t* conv_tab[17] = {};       // per log2 n: FNT_n of the 16 bit planes of log(r_n^d - 1), [n][16]
   size_t lds_max = 65536;

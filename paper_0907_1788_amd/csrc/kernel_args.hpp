@@ -74,6 +74,8 @@ struct FourStepArgs {
   uint64_t boff_in, boff_out;
   uint32_t rlog_in, rlog_out, slog_out;
   const uint32_t* wr;                // decoder K1: weights and rows by sub-transform (FsClearArgs::wr)
+  const uint32_t* twsplit;           // this kernel's split twiddles by [sub-transform][index]
+  const uint32_t* ahat_t;            // decoder K3: the locator's transform by [sub-transform][index]
 };
 
 // Escape bitmaps a four-step call clears before its kernels run: up to
@@ -88,6 +90,11 @@ struct FsClearArgs {
   const uint32_t* wfull;
   const uint32_t* ridx;
   uint32_t n, full;
+  // decoder: ahat (natural order, M words) laid out for K3 as
+  // ahat_t[256 m2' + j] = ahat[m2' + (M/256) j] (null: none)
+  uint32_t* ahat_t;
+  const uint32_t* ahat;
+  uint32_t M;
 };
 
 // One erasure pattern of a locator batch: where its positions come from,

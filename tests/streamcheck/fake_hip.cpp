@@ -326,7 +326,7 @@ void model_fourstep(Op& x, const std::string& base, const FourStepArgs& a, uint6
   else if (base == "k4_dec3") {
     rin = a.M;
     rout = a.M;
-    touch(x, (uintptr_t)a.ahat, (size_t)a.M * 4, false, "ahat");
+    touch(x, (uintptr_t)a.ahat_t, (size_t)a.M * 4, false, "ahat by sub-transform");
   } else if (base == "k4_dec4") { rin = a.M; rout = a.k; }
   else {
     error("no model of four-step kernel " + base);
@@ -350,6 +350,12 @@ void model_fourstep(Op& x, const std::string& base, const FourStepArgs& a, uint6
   if (a.tstride_out != T)
     touch(x, (uintptr_t)a.out + a.boff_out, (size_t)batch * a.tiles * (a.tstride_out / T) / 8, true, "escape bits out");
   model_tw(x, a.tw, a.twi);
+  // split twiddles of the kernels that have them: a table of n (K1, encoder
+  // pass A) or M (K2, K3) words
+  if (base == "k4_dec1" || base == "k4_enc1")
+    touch(x, (uintptr_t)a.twsplit, (size_t)a.n * 4, false, "split twiddles");
+  if (base == "k4_dec2" || base == "k4_dec3")
+    touch(x, (uintptr_t)a.twsplit, (size_t)a.M * 4, false, "split twiddles");
 }
 
 void model_locdesc(Op& x, const LocDesc& d) {
@@ -431,6 +437,10 @@ std::function<void(Op&)> kernel_model(const std::string& name, dim3 grid, void**
         touch(x, (uintptr_t)c.wfull, (size_t)c.n * 4, false, "wfull");
         if (!c.full) touch(x, (uintptr_t)c.ridx, (size_t)c.n * 4, false, "ridx");
         touch(x, (uintptr_t)c.wr, (size_t)c.n * 8, true, "weights and rows by sub-transform");
+      }
+      if (c.ahat_t) {
+        touch(x, (uintptr_t)c.ahat, (size_t)c.M * 4, false, "ahat");
+        touch(x, (uintptr_t)c.ahat_t, (size_t)c.M * 4, true, "ahat by sub-transform");
       }
     };
   }
