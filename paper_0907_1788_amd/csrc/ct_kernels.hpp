@@ -77,13 +77,16 @@ struct Geo {
   using TwType = typename std::conditional<TW_LDS, TwLds<L, LO, TOP>, TwGlobal>::type;
 };
 
-template <int L, int LO, int TOP>
+// STRIDED: fill the LDS tables from tw itself (TwLds::fill_strided).
+template <bool STRIDED = false, int L, int LO, int TOP>
 __device__ __forceinline__ TwLds<L, LO, TOP> make_tw(const TwLds<L, LO, TOP>*, uint32_t* lds_tab, const uint32_t* tw,
                                                       const uint32_t*) {
   TwLds<L, LO, TOP> t{lds_tab};
-  t.fill(lds_tab, tw);
+  if constexpr (STRIDED) t.fill_strided(lds_tab, tw);
+  else t.fill(lds_tab, tw);
   return t;
 }
+template <bool STRIDED = false>
 __device__ __forceinline__ TwGlobal make_tw(const TwGlobal*, uint32_t*, const uint32_t* tw, const uint32_t* twi) {
   return TwGlobal{tw, twi};
 }
@@ -339,7 +342,9 @@ __global__ void __launch_bounds__(NT) k_enc_cos(EncodeArgs a) {
   using Gm = Geo<LK, TT, NT, VV>;
   using TW = typename Gm::TwType;
   extern __shared__ uint32_t lds[];
-  const TW tws = make_tw((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
+  // the kernel holds a tile's source across its cosets at the edge of its
+  // register budget: the strided fill keeps it from spilling
+  const TW tws = make_tw<true>((const TW*)nullptr, lds + Gm::TILE_BYTES / 4, a.tw, a.twi);
   enc_cos_item<LK, TT, NT, VV>(a, xcd_remap(blockIdx.x, gridDim.x), lds, tws);
 }
 

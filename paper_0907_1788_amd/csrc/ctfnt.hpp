@@ -202,8 +202,18 @@ struct TwLds {
     const uint32_t u = j << (L - lg);
     return tab[off(TOP + 1) + (inverse ? (1u << (L - 1)) - u : u)];
   }
-  // fills the tables from the global table tw[e] = 3^e: omega_(2^lg)^j = 3^(j 2^(16-lg))
+  // fills the tables from the context's stage tables (kStageTwBase after
+  // tw[e] = 3^e): omega_(2^lg)^j = 3^(j 2^(16-lg))
   __device__ __forceinline__ void fill(uint32_t* t, const uint32_t* __restrict__ tw) const {
+    const uint32_t* st = tw + kStageTwBase;
+    for (int lg = LO; lg <= TOP; ++lg)
+      for (uint32_t j = threadIdx.x; j <= (1u << (lg - 1)); j += blockDim.x) t[off(lg) + j] = gptr(st)[stage_tw_offset(lg) + j];
+    if (TOP < L)
+      for (uint32_t u = threadIdx.x; u <= (1u << (L - 1)); u += blockDim.x) t[off(TOP + 1) + u] = gptr(st)[stage_tw_offset(L) + u];
+  }
+  // the same from tw itself (strided reads): for a kernel at the edge of its
+  // register budget, where the other form's addressing costs a spill
+  __device__ __forceinline__ void fill_strided(uint32_t* t, const uint32_t* __restrict__ tw) const {
     for (int lg = LO; lg <= TOP; ++lg)
       for (uint32_t j = threadIdx.x; j <= (1u << (lg - 1)); j += blockDim.x) t[off(lg) + j] = gptr(tw)[j << (16 - lg)];
     if (TOP < L)

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "kernel_args.hpp"
+
 namespace fntrs {
 
 // Global-memory views of generic pointers.  A pointer that reaches a kernel

@@ -1200,8 +1200,11 @@ int fntrs_create(int device, size_t cap, fntrs_ctx** out) {
   uint64_t x = 1;
   for (int e = 0; e < 65536; ++e) { h[e] = (uint32_t)x; x = x * 3 % 65537; }
   for (int e = 0; e < 65536; ++e) h[65536 + e] = h[(65536 - e) & 0xFFFF];
-  // the four-step split twiddles (split_tw_offset): w_N^(+-i t) by [i][t]
-  h.resize(2 * 65536 + kSplitTwWords);
+  // the stage tables (stage_tw_offset), then the four-step split twiddles
+  // (split_tw_offset): w_N^(+-i t) by [i][t]
+  h.resize(kStageTwBase + kStageTwWords + kSplitTwWords);
+  for (int lg = 1; lg <= 16; ++lg)
+    for (uint32_t j = 0; j <= (1u << (lg - 1)); ++j) h[kStageTwBase + stage_tw_offset(lg) + j] = h[j << (16 - lg)];
   for (int logN = kSplitTwMinLog; logN <= 16; ++logN) {
     const uint32_t N = 1u << logN, N2 = N >> 8, sh = 16 - logN;
     for (int b = 0; b < 2; ++b)

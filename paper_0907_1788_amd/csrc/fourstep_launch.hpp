@@ -20,14 +20,15 @@ constexpr int kFourStepMinLog = 14;
 
 // Split twiddles of the four-step passes, laid out so that a workgroup reads
 // its factors from one contiguous range.  The context's twiddle allocation
-// holds tw (3^e), twi (3^-e), then for each N = 2^13 .. 2^16 (n, and the
+// holds tw (3^e), twi (3^-e), the stage tables (field.hpp), then for each
+// N = 2^13 .. 2^16 (n, and the
 // decoder's product length M >= n/2) four tables of N words: w_N^(i t) and
 // w_N^-(i t) by [i < N/256][t < 256] (layout A), then the same by
 // [i < 256][t < N/256] (layout B); w_N = 3^(65536/N).
 constexpr int kSplitTwMinLog = kFourStepMinLog - 1;
 constexpr size_t kSplitTwWords = 4 * ((size_t(1) << 17) - (size_t(1) << kSplitTwMinLog));
 __host__ __device__ constexpr size_t split_tw_offset(int logN, bool layout_b, bool inv) {
-  return 2 * size_t(65536) + 4 * ((size_t(1) << logN) - (size_t(1) << kSplitTwMinLog)) +
+  return kStageTwBase + kStageTwWords + 4 * ((size_t(1) << logN) - (size_t(1) << kSplitTwMinLog)) +
          (size_t(2 * (layout_b ? 1 : 0) + (inv ? 1 : 0)) << logN);
 }
 

@@ -78,6 +78,16 @@ struct FourStepArgs {
   const uint32_t* ahat_t;            // decoder K3: the locator's transform by [sub-transform][index]
 };
 
+// Layout of the context's twiddle allocation, in words from its start:
+// tw[e] = 3^e (e < 65536), then twi[e] = 3^-e, then the tables of every
+// transform stage, omega_(2^lg)^j = 3^(j 2^(16-lg)) for j <= 2^(lg-1) and
+// lg = 1..16 one after another (a workgroup fills its LDS stage tables from
+// consecutive words instead of words 2^(16-lg) apart), then the four-step
+// split twiddles (split_tw_offset).
+constexpr size_t kStageTwBase = 2 * size_t(65536);
+constexpr uint32_t stage_tw_offset(int lg) { return ((1u << (lg - 1)) - 1) + (lg - 1); }
+constexpr size_t kStageTwWords = stage_tw_offset(17);
+
 // Escape bitmaps a four-step call clears before its kernels run: up to
 // three ranges of whole 16-byte vectors.
 struct FsClearArgs {

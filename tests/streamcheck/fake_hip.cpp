@@ -259,6 +259,7 @@ std::vector<int> template_ints(const std::string& name) {
 void model_tw(Op& x, const uint32_t* tw, const uint32_t* twi) {
   touch(x, (uintptr_t)tw, 65536 * 4, false, "tw");
   touch(x, (uintptr_t)twi, 65536 * 4, false, "twi");
+  touch(x, (uintptr_t)(tw + fntrs::kStageTwBase), fntrs::kStageTwWords * 4, false, "stage twiddles");
 }
 
 void model_encode(Op& x, const EncodeArgs& a, uint64_t items, uint64_t per_block) {
