@@ -447,8 +447,18 @@ struct DecLoad {
   uint64_t ld;
   uint32_t lane0, lanes, row0;
   bool full, vec;
+  const uint32_t* wrb;   // DecodeArgs::wrb
   template <int B>
   __device__ __forceinline__ void consts(uint32_t base, uint32_t (&wv)[1 << B], uint32_t (&rv)[1 << B]) {
+    if (wrb) {   // uniform: the pairs of positions bitrev(base + c) lie together
+#pragma unroll
+      for (int c = 0; c < (1 << B); ++c) {
+        const u32x2 q = *(const FNTRS_GLOBAL u32x2*)gptr(wrb + 2 * (base + c));
+        wv[c] = q.x;
+        rv[c] = q.x ? q.y : row0;
+      }
+      return;
+    }
     const uint32_t zb = bitrev(base, L);
 #pragma unroll
     for (int c = 0; c < (1 << B); ++c) {
@@ -601,7 +611,7 @@ __device__ __forceinline__ void dec_item(const DecodeArgs& a, uint32_t item, uin
   const uint64_t blk = item / a.tiles;
   const uint32_t lane0 = tile * T;
   DecLoad<LN, V> lg{a.recv + blk * a.stride_recv + lane0, a.wfull, a.ridx, a.ld_recv, lane0, a.lanes,
-                    a.row0, a.full != 0, a.vec != 0};
+                    a.row0, a.full != 0, a.vec != 0, a.wrb};
   LdsLoad<V, G> ll{lds};
   LdsStore<V, G, false> sl{lds};
   SourceStore<V> sg{a.dst + blk * a.stride_dst + lane0, a.ld_dst, a.k, lane0, a.lanes, a.vec != 0};
@@ -673,7 +683,7 @@ __device__ __forceinline__ DecLoad<LN, Geo<LN, TT, NT, VV>::V> dec_loader(const 
   const uint32_t lane0 = (item % a.tiles) * T;
   const uint64_t blk = item / a.tiles;
   return {a.recv + blk * a.stride_recv + lane0, a.wfull, a.ridx, a.ld_recv, lane0, a.lanes, a.row0,
-          a.full != 0, a.vec != 0};
+          a.full != 0, a.vec != 0, a.wrb};
 }
 
 // Persistent decoder: a grid of resident size walks the work items (numbered

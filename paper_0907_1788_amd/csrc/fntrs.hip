@@ -404,6 +404,9 @@ bool eval_ct(int L, uint32_t grid, const LocDesc* D, const uint32_t* start, uint
 // transform of the lane-tile kernels runs in one or two.
 // `scr` holds n * kFourStepTile words (kFnOneScratchWords covers any n).
 constexpr size_t kFnOneScratchWords = size_t(65536) * kFourStepTile;
+// Lanes (times blocks) from which a single decode call lays out its first
+// pass's (weight, row) pairs (k_dec_pairs) before the transform kernel.
+constexpr uint64_t kDecPairsMinLanes = 4096;
 int fnt_lanes(fntrs_ctx* c, uint32_t n, uint32_t k, uint32_t lanes, const uint32_t* src, uint32_t* dst, uint32_t* scr,
               hipStream_t s) {
   FourStepArgs f{};
@@ -1110,6 +1113,22 @@ int fntrs::decode_run(fntrs_ctx* c, const fntrs_locator_t* L, uint32_t lanes, bo
   a.tiles = (lanes + cfg.T - 1) / cfg.T;
   const uint64_t blocks = (uint64_t)a.tiles * batch;
   if (blocks > 0x7fffffffull) return fail(c, FNTRS_E_INVAL, "grid too large");
+  // A large call reads the (weight, row) pairs of its first pass from one
+  // table in that pass's order (k_dec_pairs) instead of two tables at
+  // bit-reversed positions: a wave's reads then share cache lines.
+  if ((uint64_t)lanes * batch >= kDecPairsMinLanes && n >= 2 && n == (1u << L->logn)) {
+    Scratch sc;
+    if (int rc = scratch_acquire(c, (size_t)n * 8, s, sc)) return rc;
+    uint32_t* wrb = reinterpret_cast<uint32_t*>(sc.p);
+    hipLaunchKernelGGL(k_dec_pairs, dim3(std::min<uint32_t>(1024, (n + 255) / 256)), dim3(256), 0, s, L->wfull, L->ridx,
+                       wrb, n, (int)L->logn, a.full);
+    hipError_t e = hipGetLastError();
+    a.wrb = wrb;
+    if (e == hipSuccess) e = launch_ct_decode(c, L->logn, cfg, D, a, blocks, s);
+    scratch_release(c, sc, s);
+    HIP_TRY(c, e);
+    return FNTRS_OK;
+  }
   HIP_TRY(c, launch_ct_decode(c, L->logn, cfg, D, a, blocks, s));
   return FNTRS_OK;
 }

@@ -36,6 +36,10 @@ struct DecodeArgs {
   uint32_t full;            // recv holds n rows indexed by position
   uint32_t tiles, vec;
   uint32_t row0;            // a received row of recv: erased positions read it and discard the value
+  // optional: (weight, row) of position bitrev(p) at wrb[2p], p < n, the
+  // order the first pass reads them in (row 0 where the weight is 0); null:
+  // the first pass reads wfull and ridx
+  const uint32_t* wrb;
 };
 
 // Work table of the batched path: the jobs of one class (one transform size,

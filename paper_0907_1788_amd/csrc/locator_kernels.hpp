@@ -644,6 +644,20 @@ __global__ void k_conv_coef(const uint32_t* __restrict__ G, uint32_t* __restrict
   A[i] = i == kr ? 1u : fmul(G[(n - i) & (n - 1)], 65537u - (65536u >> logn));
 }
 
+// The decoder's (weight, row) pairs in the order its first pass reads them:
+// wrb[2p] = wfull[z], wrb[2p+1] = its row (z for a full recv, else ridx[z];
+// 0 where the weight is 0), z = bitrev(p) over logn bits.
+__global__ void __launch_bounds__(256) k_dec_pairs(const uint32_t* __restrict__ wfull, const uint32_t* __restrict__ ridx,
+                                                   uint32_t* __restrict__ wrb, uint32_t n, int logn, uint32_t full) {
+  for (uint32_t p = blockIdx.x * 256 + threadIdx.x; p < n; p += gridDim.x * 256) {
+    const uint32_t z = __brev(p) >> (32 - logn);
+    const uint32_t w = gptr(wfull)[z];
+    const uint32_t r = w ? (full ? z : gptr(ridx)[z]) : 0u;
+    const u32x2 v = {w, r};
+    *(FNTRS_GLOBAL u32x2*)gptr(wrb + 2 * (uint64_t)p) = v;
+  }
+}
+
 // n = 1 (and k = 1): encoding and decoding both copy the single symbol.
 __global__ void k_copy_rows(const uint32_t* __restrict__ src, uint64_t stride_src, uint32_t* __restrict__ dst,
                             uint64_t stride_dst, uint32_t lanes, uint32_t batch, const uint32_t* __restrict__ scale) {

@@ -283,8 +283,12 @@ void model_decode(Op& x, const DecodeArgs& a, uint64_t items, int D) {
   const uint32_t rows = a.full ? a.n : a.k;
   touch(x, (uintptr_t)a.recv, span_words(batch, a.stride_recv, rows, a.ld_recv, a.lanes) * 4, false, "recv");
   touch(x, (uintptr_t)a.dst, span_words(batch, a.stride_dst, a.k, a.ld_dst, a.lanes) * 4, true, "dst");
-  touch(x, (uintptr_t)a.wfull, (size_t)a.n * 4, false, "wfull");
-  if (!a.full && D >= 0) touch(x, (uintptr_t)a.ridx, (size_t)a.n * 4, false, "ridx");
+  if (a.wrb) {
+    touch(x, (uintptr_t)a.wrb, (size_t)a.n * 8, false, "first-pass pairs");
+  } else {
+    touch(x, (uintptr_t)a.wfull, (size_t)a.n * 4, false, "wfull");
+    if (!a.full && D >= 0) touch(x, (uintptr_t)a.ridx, (size_t)a.n * 4, false, "ridx");
+  }
   if (D >= 0) touch(x, (uintptr_t)a.ahat_br, (size_t)(a.n >> D) * 4, false, "ahat_br");
   model_tw(x, a.tw, a.twi);
 }
@@ -423,6 +427,18 @@ std::function<void(Op&)> kernel_model(const std::string& name, dim3 grid, void**
         return;
       }
       model_table(x, t, [&](const DecodeArgs& a, uint64_t items) { model_decode(x, a, items, D); });
+    };
+  }
+  if (fn == "k_dec_pairs") {   // (wfull, ridx, wrb, n, logn, full)
+    const uint32_t* wf = *(const uint32_t* const*)args[0];
+    const uint32_t* ri = *(const uint32_t* const*)args[1];
+    uint32_t* wrb = *(uint32_t* const*)args[2];
+    const uint32_t n = *(const uint32_t*)args[3];
+    const uint32_t full = *(const uint32_t*)args[5];
+    return [wf, ri, wrb, n, full](Op& x) {
+      touch(x, (uintptr_t)wf, (size_t)n * 4, false, "wfull");
+      if (!full) touch(x, (uintptr_t)ri, (size_t)n * 4, false, "ridx");
+      touch(x, (uintptr_t)wrb, (size_t)n * 8, true, "first-pass pairs");
     };
   }
   if (fn == "k_fs_clear") {   // zeroes up to three ranges of 16-byte vectors
