@@ -26,19 +26,22 @@ hipError_t launch(K kernel, size_t lds, uint32_t blocks, const FourStepArgs& a, 
     if (e_ != hipSuccess) return e_;    \
   } while (0)
 
-// Zeroes the given escape bitmaps (byte ranges of whole 16-byte vectors).
-hipError_t clear_bitmaps(const FsClearArgs& c, hipStream_t s) {
+// The call's first launch (fs::k_fs_prep): zeroes the escape bitmaps and lays
+// out the decoder's tables.
+hipError_t prepare_call(const FsPrepArgs& c, hipStream_t s) {
   const uint64_t words = c.words[0] + c.words[1] + c.words[2];
   const uint64_t items = std::max<uint64_t>(words / 4, c.wr ? c.n / 4 : 0);   // c.M <= c.n
   const uint32_t blocks = (uint32_t)std::min<uint64_t>(1024, (items + 255) / 256 + 1);
-  hipLaunchKernelGGL(fs::k_fs_clear, dim3(blocks), dim3(256), 0, s, c);
+  hipLaunchKernelGGL(fs::k_fs_prep, dim3(blocks), dim3(256), 0, s, c);
   return hipGetLastError();
 }
 
 // Byte offsets of the escape bitmaps in a scratch buffer of batch*rows*lds_
 // words (4 bytes per element): the 2-byte values and flag bytes of a use take
 // the first 2.5 bytes per element, the bitmaps (rows*tiles/8 bytes per block
-// each) start at 3 bytes per element.
+// each) start at 3 bytes per element.  The decoder's first buffer (n rows)
+// then holds, from 3.5 bytes per element, K1's (weight, row) pairs (8n bytes)
+// and K3's layout of the locator's transform (4M bytes).
 uint64_t bitmap_at(uint32_t batch, uint64_t rows, uint64_t lds_) { return 3 * (uint64_t)batch * rows * lds_; }
 uint64_t bitmap_bytes(uint32_t batch, uint32_t tiles, uint64_t rows) { return (uint64_t)batch * tiles * rows / 8; }
 
@@ -114,7 +117,7 @@ hipError_t fourstep_decode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   const uint64_t bWR = 7 * (uint64_t)batch * n * lds_ / 2;   // 3.5 bytes per element: 8 n bytes
   const uint64_t bAH = bWR + 8 * n;                            // then K3's Â layout, 4 M bytes
   {
-    FsClearArgs cl{};
+    FsPrepArgs cl{};
     cl.p[0] = (uint32_t*)((uint8_t*)sa + bA1);
     cl.words[0] = bitmap_bytes(batch, tiles, n) / 4;
     // K1's weights and rows by sub-transform, beyond the bitmaps
@@ -128,7 +131,7 @@ hipError_t fourstep_decode(const FourStepArgs& base, uint32_t batch, uint32_t* s
       cl.p[2] = (uint32_t*)((uint8_t*)sb + bB);
       cl.words[2] = bitmap_bytes(batch, tiles, M) / 4;
     }
-    FNTRS_TRY(clear_bitmaps(cl, s));
+    FNTRS_TRY(prepare_call(cl, s));
   }
   FourStepArgs user = base;   // the caller's buffers are row-major
   user.tstride_in = T;
@@ -185,10 +188,10 @@ hipError_t fourstep_encode(const FourStepArgs& base, uint32_t batch, uint32_t* s
   a.boff_out = bA; a.rlog_out = base.logn; a.slog_out = 8;
   a.twsplit = base.tw + split_tw_offset(base.logn, false, false);
   {
-    FsClearArgs cl{};
+    FsPrepArgs cl{};
     cl.p[0] = (uint32_t*)((uint8_t*)sa + bA);
     cl.words[0] = bitmap_bytes(batch, base.tiles, rows) / 4;
-    FNTRS_TRY(clear_bitmaps(cl, s));
+    FNTRS_TRY(prepare_call(cl, s));
   }
   a.subs = a.n >> 8;
   // zero-padded source: k <= n/4 or n/2 lets the first pass skip its first stages

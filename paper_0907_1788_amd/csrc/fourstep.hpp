@@ -557,12 +557,12 @@ __global__ void __launch_bounds__(kNT) k4_enc2(FourStepArgs a) {
   ct::dit<LB, Gm::BM, kV, Gm::G, false>(tws, l0, lm, sm, sl);
 }
 
-// Clears the escape bitmaps of a call (up to three ranges of whole 16-byte
-// vectors) before their writers run.
+// First launch of a four-step call: clears the escape bitmaps of the call
+// (up to three ranges of whole 16-byte vectors) before their writers run.
 // The decoder's launch also lays out K1's weights and rows by sub-transform,
 // so that each K1 workgroup reads its 256 pairs from one contiguous 2 KiB
 // range instead of 512 words 4*n/256 bytes apart.
-__global__ void __launch_bounds__(256) k_fs_clear(FsClearArgs c) {
+__global__ void __launch_bounds__(256) k_fs_prep(FsPrepArgs c) {
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     uint4* q = reinterpret_cast<uint4*>(c.p[j]);

@@ -77,7 +77,7 @@ struct FourStepArgs {
   // are i*S + m, and row i*S + m has bit m*(R/S) + i of its tile's R bits
   uint64_t boff_in, boff_out;
   uint32_t rlog_in, rlog_out, slog_out;
-  const uint32_t* wr;                // decoder K1: weights and rows by sub-transform (FsClearArgs::wr)
+  const uint32_t* wr;                // decoder K1: weights and rows by sub-transform (FsPrepArgs::wr)
   const uint32_t* twsplit;           // this kernel's split twiddles by [sub-transform][index]
   const uint32_t* ahat_t;            // decoder K3: the locator's transform by [sub-transform][index]
 };
@@ -92,9 +92,10 @@ constexpr size_t kStageTwBase = 2 * size_t(65536);
 constexpr uint32_t stage_tw_offset(int lg) { return ((1u << (lg - 1)) - 1) + (lg - 1); }
 constexpr size_t kStageTwWords = stage_tw_offset(17);
 
-// Escape bitmaps a four-step call clears before its kernels run: up to
-// three ranges of whole 16-byte vectors.
-struct FsClearArgs {
+// The first launch of a four-step call: the escape bitmaps it clears before
+// the call's kernels run (up to three ranges of whole 16-byte vectors) and,
+// for the decoder, the tables it lays out for K1 and K3.
+struct FsPrepArgs {
   uint32_t* p[3];
   uint64_t words[3];   // multiples of 4
   // decoder: the weight and row of input i2 of K1's sub-transform i1 (the

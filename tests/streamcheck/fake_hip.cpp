@@ -441,8 +441,8 @@ std::function<void(Op&)> kernel_model(const std::string& name, dim3 grid, void**
       touch(x, (uintptr_t)wrb, (size_t)n * 8, true, "first-pass pairs");
     };
   }
-  if (fn == "k_fs_clear") {   // zeroes up to three ranges of 16-byte vectors
-    const fntrs::FsClearArgs c = *(const fntrs::FsClearArgs*)args[0];
+  if (fn == "k_fs_prep") {   // zeroes up to three ranges of 16-byte vectors
+    const fntrs::FsPrepArgs c = *(const fntrs::FsPrepArgs*)args[0];
     return [c](Op& x) {
       for (int j = 0; j < 3; ++j)
         if (c.words[j]) {
